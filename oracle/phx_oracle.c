@@ -1,0 +1,733 @@
+/*
+ * Photon Monte Carlo oracle -- TEST INFRASTRUCTURE ONLY (see phx_oracle.h).
+ *
+ * Plain double-precision C, compiled with -O2 -ffp-contract=off -fno-fast-math.  Each function
+ * names the passage of the PhoSim paper (Peterson et al., ApJS 2015) it follows.  Where the paper
+ * is silent or garbled, the reading taken is stated at the function.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), keyed per photon so that any
+ * photon can be recomputed alone.  key = (seed, source), counter = (photon_lo, photon_hi, block,
+ * stream).  Block/word map of stream 0:
+ *   block 0: pupil radius, pupil angle, time, wavelength
+ *   block 1: wavelength blur within an SED bin, Sersic angle, silicon conversion length, (spare)
+ *   blocks 2..5: coating roulette for surfaces 4(b-2) .. 4(b-2)+3
+ *   block 6: diffusion Box-Muller pair, (spare, spare)
+ * Stream 1, block t: Sersic Gamma sampler trial t (normal pair words 0-1, acceptance word 2).
+ *
+ * Parity pins (tests/test_oracle_*.py): Philox vs an independent implementation (rocRAND, compiled
+ * on the host); uniform conversion exhaustive bounds; pupil density; Sersic radius median and
+ * Gamma law; paraboloid focus; ellipsoid foci; Cassegrain focus; Snell invariants and the tilted
+ * plate shift; Sellmeier and silicon index values; Rajkanan absorption against published silicon
+ * data (order of magnitude); Zernike orthonormality; screen deflection closed forms; coating
+ * roulette binomial; conversion depth exponential law; diffusion normal law; photometry integral.
+ */
+#include "phx_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TWO_PI 6.283185307179586476925286766559
+#define HC_EV_M 1.2398419843320026e-6 /* h c / e (eV m), SI-exact constants */
+#define K_B_EV 8.617333262e-5         /* Boltzmann constant (eV/K) */
+#define NEWTON_TOL 1e-12              /* m: |delta l| at convergence (paper: 0.01 um) */
+#define NEWTON_MAX 16
+
+/* ------------------------------------------------------------------------------------------ */
+/* Philox4x32-10 from its published definition: 10 rounds of
+ *   (L0, R0, L1, R1) -> (hi(M1*L1) ^ R0 ^ k0, lo(M1*L1), hi(M0*L0) ^ R1 ^ k1, lo(M0*L0))
+ * with the counter words read as (L0, R0, L1, R1) = (c0, c1, c2, c3), multipliers
+ * M0 = 0xD2511F53, M1 = 0xCD9E8D57 and the key bumped by the Weyl constants
+ * (0x9E3779B9, 0xBB67AE85) between rounds. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* u = (w + 1/2) 2^-32: exact in double, strictly inside (0, 1). */
+double orc_u01(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+static void draw(const orc_scene* sc, int32_t src, uint64_t photon, uint32_t block,
+                 uint32_t stream, double u[4]) {
+    uint32_t ctr[4] = {(uint32_t)photon, (uint32_t)(photon >> 32), block, stream};
+    uint32_t key[2] = {sc->seed, (uint32_t)src};
+    uint32_t w[4];
+    orc_philox(ctr, key, w);
+    for (int i = 0; i < 4; ++i) u[i] = orc_u01(w[i]);
+}
+
+static void note_margin(double* m, double v) {
+    v = fabs(v);
+    if (v < *m) *m = v;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Materials.                                                                                 */
+
+/* Sellmeier equation (section 2.4.1), lambda in micrometres inside the formula. */
+double orc_sellmeier(const orc_scene* sc, double lambda_m) {
+    double l2 = (lambda_m * 1e6) * (lambda_m * 1e6);
+    double s = 1.0;
+    for (int i = 0; i < 3; ++i) s += sc->glass_b[i] * l2 / (l2 - sc->glass_c[i]);
+    return sqrt(s);
+}
+
+/* Silicon index n = 3.36 + 0.211 E + 2.79 exp((E - 3.30)/0.398), E in eV (section 2.4.1). */
+double orc_n_silicon(double lambda_m) {
+    double e = HC_EV_M / lambda_m;
+    return 3.36 + 0.211 * e + 2.79 * exp((e - 3.30) / 0.398);
+}
+
+/* Rajkanan absorption coefficient (section 2.4.2), cm^-1.  Reading: the printed "C_i A_i" is
+ * C_i A_j (phonon i, indirect gap j), and each squared term contributes only where its base is
+ * positive (photon energy above the phonon-assisted threshold); the direct term only above E_gd. */
+double orc_rajkanan(double lambda_m, double T) {
+    const double beta = 7.021e-4, gam = 1108.0;
+    const double eg0[2] = {1.1557, 2.5}, egd0 = 3.2;
+    const double ep[2] = {1.827e-2, 5.773e-2};
+    const double C[2] = {5.5, 4.0};
+    const double A[2] = {3.231e2, 7.237e3};
+    const double Ad = 1.052e6;
+    double e = HC_EV_M / lambda_m;
+    double shift = beta * T * T / (T + gam);
+    double alpha = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        double absorb = exp(ep[i] / (K_B_EV * T)) - 1.0;
+        double emit = 1.0 - exp(-ep[i] / (K_B_EV * T));
+        for (int j = 0; j < 2; ++j) {
+            double eg = eg0[j] - shift;
+            double a = e - eg + ep[i];
+            double b = e - eg - ep[i];
+            double term = 0.0;
+            if (a > 0.0) term += a * a / absorb;
+            if (b > 0.0) term += b * b / emit;
+            alpha += C[i] * A[j] * term;
+        }
+    }
+    double egd = egd0 - shift;
+    if (e > egd) alpha += Ad * sqrt(e - egd);
+    return alpha;
+}
+
+static double medium_index(const orc_scene* sc, int medium, double lambda_m) {
+    if (medium == ORC_GLASS) return orc_sellmeier(sc, lambda_m);
+    if (medium == ORC_SILICON) return orc_n_silicon(lambda_m);
+    return 1.0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Surfaces (section 2.4.1): conic + polynomial asphere, plus Zernike deformation on M1.        */
+
+/* Noll-indexed Zernike polynomials j = 4..15, RMS-normalised on the unit disk, in Cartesian form
+ * (u, v) = (x, y)/R.  Reading of "Zernike expansion up to 5th order" (section 2.4.1): Noll 1976
+ * ordering; the perturbation vector carries Z4..Z15. */
+double orc_zernike(int j, double u, double v) {
+    double r2 = u * u + v * v;
+    switch (j) {
+    case 1: return 1.0;
+    case 2: return 2.0 * u;
+    case 3: return 2.0 * v;
+    case 4: return sqrt(3.0) * (2.0 * r2 - 1.0);
+    case 5: return sqrt(6.0) * (2.0 * u * v);
+    case 6: return sqrt(6.0) * (u * u - v * v);
+    case 7: return sqrt(8.0) * (3.0 * r2 - 2.0) * v;
+    case 8: return sqrt(8.0) * (3.0 * r2 - 2.0) * u;
+    case 9: return sqrt(8.0) * (3.0 * u * u * v - v * v * v);
+    case 10: return sqrt(8.0) * (u * u * u - 3.0 * u * v * v);
+    case 11: return sqrt(5.0) * (6.0 * r2 * r2 - 6.0 * r2 + 1.0);
+    case 12: return sqrt(10.0) * (4.0 * r2 - 3.0) * (u * u - v * v);
+    case 13: return sqrt(10.0) * (4.0 * r2 - 3.0) * (2.0 * u * v);
+    case 14: return sqrt(10.0) * (u * u * u * u - 6.0 * u * u * v * v + v * v * v * v);
+    case 15: return sqrt(10.0) * (4.0 * u * u * u * v - 4.0 * u * v * v * v);
+    default: return 0.0;
+    }
+}
+
+/* Partial derivatives of orc_zernike with respect to u and v. */
+void orc_zernike_grad(int j, double u, double v, double* du, double* dv) {
+    double r2 = u * u + v * v;
+    double a = 0.0, b = 0.0;
+    switch (j) {
+    case 2: a = 2.0; break;
+    case 3: b = 2.0; break;
+    case 4: a = sqrt(3.0) * 4.0 * u; b = sqrt(3.0) * 4.0 * v; break;
+    case 5: a = sqrt(6.0) * 2.0 * v; b = sqrt(6.0) * 2.0 * u; break;
+    case 6: a = sqrt(6.0) * 2.0 * u; b = -sqrt(6.0) * 2.0 * v; break;
+    case 7: a = sqrt(8.0) * 6.0 * u * v; b = sqrt(8.0) * (3.0 * u * u + 9.0 * v * v - 2.0); break;
+    case 8: a = sqrt(8.0) * (9.0 * u * u + 3.0 * v * v - 2.0); b = sqrt(8.0) * 6.0 * u * v; break;
+    case 9: a = sqrt(8.0) * 6.0 * u * v; b = sqrt(8.0) * (3.0 * u * u - 3.0 * v * v); break;
+    case 10: a = sqrt(8.0) * (3.0 * u * u - 3.0 * v * v); b = -sqrt(8.0) * 6.0 * u * v; break;
+    case 11: a = sqrt(5.0) * (24.0 * r2 - 12.0) * u; b = sqrt(5.0) * (24.0 * r2 - 12.0) * v; break;
+    case 12:
+        a = sqrt(10.0) * (8.0 * u * (u * u - v * v) + (4.0 * r2 - 3.0) * 2.0 * u);
+        b = sqrt(10.0) * (8.0 * v * (u * u - v * v) - (4.0 * r2 - 3.0) * 2.0 * v);
+        break;
+    case 13:
+        a = sqrt(10.0) * (16.0 * u * u * v + (4.0 * r2 - 3.0) * 2.0 * v);
+        b = sqrt(10.0) * (16.0 * u * v * v + (4.0 * r2 - 3.0) * 2.0 * u);
+        break;
+    case 14: a = sqrt(10.0) * (4.0 * u * u * u - 12.0 * u * v * v); b = sqrt(10.0) * (4.0 * v * v * v - 12.0 * u * u * v); break;
+    case 15: a = sqrt(10.0) * (12.0 * u * u * v - 4.0 * v * v * v); b = sqrt(10.0) * (4.0 * u * u * u - 12.0 * u * v * v); break;
+    default: break;
+    }
+    *du = a;
+    *dv = b;
+}
+
+/* Surface sag S(x, y) in the element frame and its gradient (sx, sy); returns NAN outside the
+ * conic's domain. */
+double orc_sag(const orc_scene* sc, int k, double x, double y, double* sx, double* sy) {
+    const orc_surface* s = &sc->surf[k];
+    double r2 = x * x + y * y;
+    double arg = 1.0 - (1.0 + s->kappa) * s->c * s->c * r2;
+    if (arg < 0.0) return NAN;
+    double root = sqrt(arg);
+    double sag = s->c * r2 / (1.0 + root);
+    double dsdr_over_r = s->c / root;
+    double r = sqrt(r2);
+    for (int i = 3; i <= 10; ++i) {
+        double a = s->alpha[i - 3];
+        if (a == 0.0) continue;
+        sag += a * pow(r, (double)i);
+        dsdr_over_r += (double)i * a * pow(r, (double)(i - 2));
+    }
+    double gx = x * dsdr_over_r, gy = y * dsdr_over_r;
+    if (k == 0 && sc->zernike_r > 0.0) {
+        double R = sc->zernike_r;
+        for (int j = 4; j <= 15; ++j) {
+            double amp = sc->theta[10 + (j - 4)];
+            if (amp == 0.0) continue;
+            double du, dv;
+            sag += amp * orc_zernike(j, x / R, y / R);
+            orc_zernike_grad(j, x / R, y / R, &du, &dv);
+            gx += amp * du / R;
+            gy += amp * dv / R;
+        }
+    }
+    if (sx) *sx = gx;
+    if (sy) *sy = gy;
+    return sag;
+}
+
+/* Ray-surface intersection (section 2.4.2).  The paper starts from a parabolic approximation and
+ * iterates l <- l0 + delta/n_z to 0.01 um.  Reading: the result is the root of
+ * f(l) = q_z + l d_z - S(q_x + l d_x, q_y + l d_y) nearest the vertex sheet; this oracle takes the
+ * exact conic root as the start (the root of the conic part, continuous as the quadratic
+ * coefficient vanishes) and runs Newton on f to |delta l| <= 1e-12 m.  Returns 0 on success,
+ * ORC_MISSED or ORC_NONCONV. */
+int orc_intersect(const orc_scene* sc, int k, const double q[3], const double d[3], double* l_out,
+                  int* iters) {
+    const orc_surface* s = &sc->surf[k];
+    double ck = 1.0 + s->kappa;
+    double A = s->c * (d[0] * d[0] + d[1] * d[1] + ck * d[2] * d[2]);
+    double B = s->c * (q[0] * d[0] + q[1] * d[1] + ck * q[2] * d[2]) - d[2];
+    double C = s->c * (q[0] * q[0] + q[1] * q[1] + ck * q[2] * q[2]) - 2.0 * q[2];
+    double disc = B * B - A * C;
+    *iters = 0;
+    if (disc < 0.0) return ORC_MISSED;
+    double den = B + (B >= 0.0 ? sqrt(disc) : -sqrt(disc));
+    if (den == 0.0) return ORC_MISSED;
+    double l = -C / den;
+    for (int it = 1; it <= NEWTON_MAX; ++it) {
+        double x = q[0] + l * d[0], y = q[1] + l * d[1], z = q[2] + l * d[2];
+        double sx, sy;
+        double S = orc_sag(sc, k, x, y, &sx, &sy);
+        if (isnan(S)) return ORC_MISSED;
+        double f = z - S;
+        double fp = d[2] - (sx * d[0] + sy * d[1]);
+        if (fp == 0.0) return ORC_NONCONV;
+        double dl = f / fp;
+        l -= dl;
+        *iters = it;
+        if (fabs(dl) <= NEWTON_TOL) {
+            *l_out = l;
+            return 0;
+        }
+    }
+    return ORC_NONCONV;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Coatings (section 2.4.2): transmission probability against incidence angle and wavelength,
+ * bilinear on the uniform (s = sin^2 theta, lambda) grid of the input table, clamped at its edges. */
+double orc_coating(const orc_scene* sc, int coat, double s, double lambda_m) {
+    const float* t = sc->coat + (size_t)coat * sc->n_s * sc->n_lam;
+    double fs = s / (sc->s_max / (double)(sc->n_s - 1));
+    double fl = (lambda_m - sc->lam0) / sc->dlam;
+    if (fs < 0.0) fs = 0.0;
+    if (fs > (double)(sc->n_s - 1)) fs = (double)(sc->n_s - 1);
+    if (fl < 0.0) fl = 0.0;
+    if (fl > (double)(sc->n_lam - 1)) fl = (double)(sc->n_lam - 1);
+    int is = (int)floor(fs), il = (int)floor(fl);
+    if (is > sc->n_s - 2) is = sc->n_s - 2;
+    if (il > sc->n_lam - 2) il = sc->n_lam - 2;
+    double a = fs - is, b = fl - il;
+    double t00 = t[(size_t)is * sc->n_lam + il], t01 = t[(size_t)is * sc->n_lam + il + 1];
+    double t10 = t[(size_t)(is + 1) * sc->n_lam + il], t11 = t[(size_t)(is + 1) * sc->n_lam + il + 1];
+    return (1.0 - a) * ((1.0 - b) * t00 + b * t01) + a * ((1.0 - b) * t10 + b * t11);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Atmosphere (sections 2.3.1-2.3.2).                                                          */
+
+static int64_t wrap(int64_t i, int64_t n) {
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Phase-gradient screens: the refractive kick is the gradient of the phase (section 2.3.2); with
+ * screens holding optical path W (m) the kick is grad W.  Reading: centred differences on the
+ * periodic grid, in single precision, g_x[j][i] = (W[j][i+1] - W[j][i-1]) * (1/(2p)). */
+static void derive_gradients(orc_scene* sc) {
+    int64_t N = sc->screen_n;
+    for (int l = 0; l < sc->n_layers; ++l)
+        for (int s = 0; s < sc->n_scales; ++s) {
+            const float* w = sc->opd + ((size_t)l * sc->n_scales + s) * N * N;
+            float* g = sc->grad + ((size_t)l * sc->n_scales + s) * N * N * 2;
+            float inv2p = (float)(1.0 / (2.0 * sc->pix[s]));
+            for (int64_t j = 0; j < N; ++j)
+                for (int64_t i = 0; i < N; ++i) {
+                    float dx = w[j * N + wrap(i + 1, N)] - w[j * N + wrap(i - 1, N)];
+                    float dy = w[wrap(j + 1, N) * N + i] - w[wrap(j - 1, N) * N + i];
+                    g[(j * N + i) * 2 + 0] = dx * inv2p;
+                    g[(j * N + i) * 2 + 1] = dy * inv2p;
+                }
+        }
+}
+
+/* Bilinear interpolation of one gradient screen at screen-pixel coordinates. */
+static void screen_lookup(const orc_scene* sc, int l, int s, double xs, double ys, double* gx,
+                          double* gy) {
+    int64_t N = sc->screen_n;
+    const float* g = sc->grad + ((size_t)l * sc->n_scales + s) * N * N * 2;
+    double fx = floor(xs), fy = floor(ys);
+    double a = xs - fx, b = ys - fy;
+    int64_t i0 = wrap((int64_t)fx, N), j0 = wrap((int64_t)fy, N);
+    int64_t i1 = wrap(i0 + 1, N), j1 = wrap(j0 + 1, N);
+    for (int c = 0; c < 2; ++c) {
+        double v00 = g[(j0 * N + i0) * 2 + c], v10 = g[(j0 * N + i1) * 2 + c];
+        double v01 = g[(j1 * N + i0) * 2 + c], v11 = g[(j1 * N + i1) * 2 + c];
+        double v = (1.0 - b) * ((1.0 - a) * v00 + a * v10) + b * ((1.0 - a) * v01 + a * v11);
+        if (c == 0) *gx = v; else *gy = v;
+    }
+}
+
+void orc_screen_gradient(const orc_scene* sc, int layer, int scale, double x, double y,
+                         double* gx, double* gy) {
+    screen_lookup(sc, layer, scale, x / sc->pix[scale], y / sc->pix[scale], gx, gy);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Rigid-body misalignments (section 2.4.1: decenter (2), defocus, Euler rotations).  Reading:
+ * rotation R = R_x(t_x) R_y(t_y) about the group's pivot, then translation (dx, dy, dz); a point q in
+ * a surface's nominal frame maps to global g = R q + t with t = P + R (v - P) + d, v the vertex. */
+static void prepare_transforms(orc_scene* sc) {
+    for (int k = 0; k < sc->n_surf; ++k) {
+        const orc_surface* s = &sc->surf[k];
+        double dx = 0, dy = 0, dz = 0, tx = 0, ty = 0;
+        const double* P = sc->pivot[0];
+        if (s->group == 1 || s->group == 2) {
+            const double* th = sc->theta + 5 * (s->group - 1);
+            dx = th[0]; dy = th[1]; tx = th[2]; ty = th[3]; dz = th[4];
+            P = sc->pivot[s->group];
+        }
+        double cx = cos(tx), sxn = sin(tx), cy = cos(ty), syn = sin(ty);
+        double Rx[3][3] = {{1, 0, 0}, {0, cx, -sxn}, {0, sxn, cx}};
+        double Ry[3][3] = {{cy, 0, syn}, {0, 1, 0}, {-syn, 0, cy}};
+        double R[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                R[i][j] = 0.0;
+                for (int m = 0; m < 3; ++m) R[i][j] += Rx[i][m] * Ry[m][j];
+            }
+        double v[3] = {0.0, 0.0, s->z};
+        double vp[3] = {v[0] - P[0], v[1] - P[1], v[2] - P[2]};
+        double d[3] = {dx, dy, dz};
+        for (int i = 0; i < 3; ++i) {
+            sc->trans[k][i] = P[i] + (R[i][0] * vp[0] + R[i][1] * vp[1] + R[i][2] * vp[2]) + d[i];
+            for (int j = 0; j < 3; ++j) sc->rot[k][i][j] = R[i][j];
+        }
+    }
+}
+
+static void to_local(const orc_scene* sc, int k, const double p[3], const double n[3], double q[3],
+                     double d[3]) {
+    double r[3] = {p[0] - sc->trans[k][0], p[1] - sc->trans[k][1], p[2] - sc->trans[k][2]};
+    for (int i = 0; i < 3; ++i) {
+        q[i] = sc->rot[k][0][i] * r[0] + sc->rot[k][1][i] * r[1] + sc->rot[k][2][i] * r[2];
+        d[i] = sc->rot[k][0][i] * n[0] + sc->rot[k][1][i] * n[1] + sc->rot[k][2][i] * n[2];
+    }
+}
+
+static void to_global(const orc_scene* sc, int k, const double q[3], const double d[3], double p[3],
+                      double n[3]) {
+    for (int i = 0; i < 3; ++i) {
+        p[i] = sc->rot[k][i][0] * q[0] + sc->rot[k][i][1] * q[1] + sc->rot[k][i][2] * q[2] +
+               sc->trans[k][i];
+        n[i] = sc->rot[k][i][0] * d[0] + sc->rot[k][i][1] * d[1] + sc->rot[k][i][2] * d[2];
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* SED cumulative distributions (section 2.2): bin probability = f_lambda x bin width / photon
+ * energy at the bin centre, accumulated in order, normalised so that CDF[K] = 1 exactly. */
+static void build_cdfs(orc_scene* sc) {
+    int K = sc->sed_k;
+    for (int s = 0; s < sc->n_sed; ++s) {
+        double* cdf = sc->sed_cdf + (size_t)s * (K + 1);
+        const double* f = sc->sed_flux + (size_t)s * K;
+        cdf[0] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double lo = sc->sed_edges[k], hi = sc->sed_edges[k + 1];
+            cdf[k + 1] = cdf[k] + f[k] * (hi - lo) * (0.5 * (lo + hi));
+        }
+        double total = cdf[K];
+        for (int k = 1; k < K; ++k) cdf[k] = cdf[k] / total;
+        cdf[K] = 1.0;
+    }
+}
+
+int orc_prepare(orc_scene* sc) {
+    sc->grad = NULL;
+    sc->sed_cdf = NULL;
+    if (sc->n_layers > 0 && sc->opd) {
+        size_t n = (size_t)sc->n_layers * sc->n_scales * sc->screen_n * sc->screen_n * 2;
+        sc->grad = (float*)malloc(n * sizeof(float));
+        if (!sc->grad) return -1;
+        derive_gradients(sc);
+    }
+    if (sc->n_sed > 0) {
+        sc->sed_cdf = (double*)malloc((size_t)sc->n_sed * (sc->sed_k + 1) * sizeof(double));
+        if (!sc->sed_cdf) return -1;
+        build_cdfs(sc);
+    }
+    prepare_transforms(sc);
+    return 0;
+}
+
+void orc_release(orc_scene* sc) {
+    free(sc->grad);
+    free(sc->sed_cdf);
+    sc->grad = NULL;
+    sc->sed_cdf = NULL;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Sersic radius (section 2.2.1).  With I(r) = I0 exp(-b_n (r/r0)^(1/n)) the radial density is
+ * proportional to r I(r); the substitution G = b_n (r/r0)^(1/n) makes G ~ Gamma(2n, 1), so
+ * r/r0 = (G/b_n)^n.  Gamma(a >= 1) by Marsaglia & Tsang (2000); a < 1 by Gamma(a+1) U^(1/a).
+ * Reading: the paper does not name a sampler.  Trial t draws from stream 1, block t. */
+static int gamma_sample(uint32_t seed, int32_t src, uint64_t photon, double shape, double* out,
+                        double* margin) {
+    orc_scene tmp;
+    tmp.seed = seed;
+    double dummy = 1e300;
+    if (!margin) margin = &dummy;
+    double a = shape < 1.0 ? shape + 1.0 : shape;
+    double dd = a - 1.0 / 3.0, cc = 1.0 / sqrt(9.0 * dd);
+    for (uint32_t t = 0; t < 64; ++t) {
+        double u[4];
+        draw(&tmp, src, photon, t, 1, u);
+        double x = sqrt(-2.0 * log(u[0])) * cos(TWO_PI * u[1]);
+        double v = 1.0 + cc * x;
+        note_margin(margin, v);
+        if (v <= 0.0) continue;
+        v = v * v * v;
+        double x2 = x * x;
+        double t1 = 1.0 - 0.0331 * x2 * x2;
+        note_margin(margin, u[2] - t1);
+        int accept = u[2] < t1;
+        if (!accept) {
+            double t2 = 0.5 * x2 + dd * (1.0 - v + log(v));
+            note_margin(margin, log(u[2]) - t2);
+            accept = log(u[2]) < t2;
+        }
+        if (accept) {
+            double g = dd * v;
+            if (shape < 1.0) g *= pow(u[3], 1.0 / shape);
+            *out = g;
+            return (int)t;
+        }
+    }
+    *out = shape; /* 64 rejections in a row: deterministic fallback to the mean */
+    return -1;
+}
+
+int orc_gamma(uint32_t seed, int32_t src, uint64_t photon, double shape, double* out) {
+    return gamma_sample(seed, src, photon, shape, out, NULL);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* The per-photon trace.                                                                       */
+
+static void set_event(orc_event* ev, int status, int surface, const double p[3]) {
+    ev->status = status;
+    ev->surface = surface;
+    ev->x = p[0]; ev->y = p[1]; ev->z = p[2];
+}
+
+static void renormalise(double n[3]) {
+    double m = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    n[0] /= m; n[1] /= m; n[2] /= m;
+}
+
+static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t* image,
+                      orc_event* ev) {
+    const orc_source* src = &sc->src[si];
+    double margin = 1e300;
+    double u0[4], u1[4];
+    draw(sc, si, photon, 0, 0, u0);
+    draw(sc, si, photon, 1, 0, u1);
+    memset(ev, 0, sizeof(*ev));
+    ev->photon = photon;
+    ev->source = si;
+    ev->pix_i = ev->pix_j = -1;
+
+    /* Direction from the source (section 2.2): tangent coordinates as n_x, n_y,
+     * n_z = -sqrt(1 - n_x^2 - n_y^2). */
+    double n[3] = {src->xi, src->eta, -sqrt(1.0 - src->xi * src->xi - src->eta * src->eta)};
+    if (src->kind == 1) {
+        /* Ellipsoidal Sersic (section 2.2.1): distance a r/r0 and b r/r0 along the axes at a
+         * uniform angle, rotated by the position angle, applied paraxially to n_x, n_y. */
+        double g;
+        gamma_sample(sc->seed, si, photon, 2.0 * src->sersic_n, &g, &margin);
+        double rr = pow(g / src->sersic_bn, src->sersic_n);
+        double psi = TWO_PI * u1[1];
+        double dmaj = src->sersic_a * rr * cos(psi), dmin = src->sersic_b * rr * sin(psi);
+        double cp = cos(src->sersic_pa), sp = sin(src->sersic_pa);
+        n[0] += dmaj * cp - dmin * sp;
+        n[1] += dmaj * sp + dmin * cp;
+        renormalise(n);
+    }
+    /* Time stamp t = t0 + t_e u (section 2.2), t0 = 0. */
+    double t = sc->exposure * u0[2];
+    /* Wavelength (section 2.2): top-hat flat in photon number, or the SED's photon CDF with a
+     * uniform blur across the chosen bin; then (1 + z). */
+    double lam;
+    if (src->sed < 0) {
+        lam = src->lam_lo + u0[3] * (src->lam_hi - src->lam_lo);
+    } else {
+        const double* cdf = sc->sed_cdf + (size_t)src->sed * (sc->sed_k + 1);
+        int k = 0;
+        while (k < sc->sed_k - 1 && !(cdf[k + 1] > u0[3])) ++k;
+        note_margin(&margin, u0[3] - cdf[k]);
+        note_margin(&margin, u0[3] - cdf[k + 1]);
+        lam = sc->sed_edges[k] + u1[0] * (sc->sed_edges[k + 1] - sc->sed_edges[k]);
+    }
+    lam = lam * (1.0 + src->redshift);
+    ev->lambda = lam;
+
+    /* Pupil (section 2.2): r = sqrt(u (r_o^2 - r_i^2) + r_i^2), phi = 2 pi v on the (slightly
+     * enlarged) annulus of the first mirror, z from its nominal surface. */
+    double ro = sc->pupil_r_out + sc->pupil_margin;
+    double ri = sc->pupil_r_in - sc->pupil_margin;
+    if (ri < 0.0) ri = 0.0;
+    double r = sqrt(u0[0] * (ro * ro - ri * ri) + ri * ri);
+    double phi = TWO_PI * u0[1];
+    double p[3] = {r * cos(phi), r * sin(phi), 0.0};
+    ev->t = t;
+    ev->px = p[0];
+    ev->py = p[1];
+    {
+        /* nominal sag of the first surface: conic + asphere only */
+        const orc_surface* s0 = &sc->surf[0];
+        double r2 = p[0] * p[0] + p[1] * p[1];
+        double arg = 1.0 - (1.0 + s0->kappa) * s0->c * s0->c * r2;
+        double z = s0->z + (arg >= 0.0 ? s0->c * r2 / (1.0 + sqrt(arg)) : 0.0);
+        for (int i = 3; i <= 10; ++i)
+            if (s0->alpha[i - 3] != 0.0) z += s0->alpha[i - 3] * pow(sqrt(r2), (double)i);
+        p[2] = z;
+    }
+
+    if ((sc->physics & ORC_ATMOSPHERE) && sc->n_layers > 0) {
+        /* Up to the highest layer along the ray (reading of the top-of-atmosphere move: the ray
+         * is moved up, l = (h - z)/n_z), then down through the layers (section 2.3.1:
+         * x <- x + n l, l = (h_i - h_{i+1})/(-n_z)), deflecting by the screen gradients at the
+         * wind-shifted position (section 2.3.1 frozen flow; section 2.3.2 kick = grad of phase)
+         * scaled by (lambda/lambda_ref)^(-1/5) (section 2.3.2). */
+        double scale = pow(lam / sc->lambda_ref, -0.2);
+        for (int i = sc->n_layers - 1; i >= 0; --i) {
+            double h = sc->height[i];
+            double l = (h - p[2]) / n[2];
+            p[0] += n[0] * l;
+            p[1] += n[1] * l;
+            p[2] = h;
+            double gx = 0.0, gy = 0.0;
+            for (int s = 0; s < sc->n_scales; ++s) {
+                double ax, ay;
+                double xs = (p[0] - sc->wind[i][0] * t) / sc->pix[s];
+                double ys = (p[1] - sc->wind[i][1] * t) / sc->pix[s];
+                screen_lookup(sc, i, s, xs, ys, &ax, &ay);
+                gx += ax;
+                gy += ay;
+            }
+            n[0] += scale * gx;
+            n[1] += scale * gy;
+            renormalise(n);
+        }
+    }
+    /* Back along the ray to the start plane above every optic. */
+    {
+        double l = (sc->z_start - p[2]) / n[2];
+        p[0] += n[0] * l;
+        p[1] += n[1] * l;
+        p[2] = sc->z_start;
+    }
+    /* Central obscuration (shadow of the secondary; section 2.4.1 obscuring structure). */
+    if (sc->obsc_r > 0.0) {
+        double l = (sc->obsc_z - p[2]) / n[2];
+        double x = p[0] + n[0] * l, y = p[1] + n[1] * l;
+        double rr = sqrt(x * x + y * y);
+        note_margin(&margin, (rr - sc->obsc_r) / sc->obsc_r);
+        if (rr < sc->obsc_r) {
+            double q[3] = {x, y, sc->obsc_z};
+            set_event(ev, ORC_OBSCURED, -1, q);
+            ev->margin = margin;
+            return;
+        }
+    }
+
+    double n_cur = 1.0;
+    double ucoat[4];
+    int coat_block = -1;
+    for (int k = 0; k < sc->n_surf; ++k) {
+        const orc_surface* s = &sc->surf[k];
+        double q[3], d[3];
+        to_local(sc, k, p, n, q, d);
+        double l;
+        int it;
+        int st = orc_intersect(sc, k, q, d, &l, &it);
+        ev->newton += it;
+        if (st == 0 && !(l > 0.0)) st = ORC_MISSED;
+        if (st != 0) {
+            set_event(ev, st, k, q);
+            ev->margin = margin;
+            return;
+        }
+        q[0] += d[0] * l; q[1] += d[1] * l; q[2] += d[2] * l;
+        /* clear aperture (paper Table 1: outer and inner radii) */
+        double rq = sqrt(q[0] * q[0] + q[1] * q[1]);
+        if (s->r_in > 0.0) note_margin(&margin, (rq - s->r_in) / s->r_in);
+        note_margin(&margin, (rq - s->r_out) / s->r_out);
+        if (rq < s->r_in || rq > s->r_out) {
+            set_event(ev, ORC_VIGNETTED, k, q);
+            ev->margin = margin;
+            return;
+        }
+        /* surface normal from the analytic sag gradient */
+        double gx, gy;
+        orc_sag(sc, k, q[0], q[1], &gx, &gy);
+        double N[3] = {-gx, -gy, 1.0};
+        renormalise(N);
+        double dn = d[0] * N[0] + d[1] * N[1] + d[2] * N[2];
+        if (dn > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; dn = -dn; }
+        double cosi = -dn;
+        /* coating roulette (section 2.4.2): survive with probability T(angle, lambda) */
+        if ((sc->physics & ORC_COATINGS) && s->coating >= 0) {
+            int blk = 2 + k / 4;
+            if (blk != coat_block) { draw(sc, si, photon, (uint32_t)blk, 0, ucoat); coat_block = blk; }
+            double uk = ucoat[k % 4];
+            double T = orc_coating(sc, s->coating, 1.0 - cosi * cosi, lam);
+            note_margin(&margin, uk - T);
+            if (!(uk < T)) {
+                set_event(ev, ORC_ABSORBED, k, q);
+                ev->margin = margin;
+                return;
+            }
+        }
+        int is_det = (s->kind == ORC_DETECTOR);
+        if (s->kind == ORC_MIRROR) {
+            /* reflection across the normal (section 2.4.2) */
+            for (int i = 0; i < 3; ++i) d[i] = d[i] - 2.0 * dn * N[i];
+        } else if (!is_det || (sc->physics & ORC_SILICON_PHYS)) {
+            /* refraction by the vector form of Snell's law (section 2.4.2), indices from the
+             * Sellmeier / silicon formulas (section 2.4.1); vacuum elsewhere */
+            double n2 = medium_index(sc, s->medium, lam);
+            double mu = n_cur / n2;
+            double kk = 1.0 - mu * mu * (1.0 - cosi * cosi);
+            note_margin(&margin, kk);
+            if (kk < 0.0) {
+                set_event(ev, ORC_TIR, k, q);
+                ev->margin = margin;
+                return;
+            }
+            double f = mu * cosi - sqrt(kk);
+            for (int i = 0; i < 3; ++i) d[i] = mu * d[i] + f * N[i];
+            n_cur = n2;
+        }
+        if (is_det) {
+            ev->x = q[0]; ev->y = q[1]; ev->z = q[2];
+            double xc = q[0], yc = q[1];
+            if (sc->physics & ORC_SILICON_PHYS) {
+                /* conversion length = mean free path x Exp(1) (section 2.4.2) */
+                double alpha = orc_rajkanan(lam, sc->temp_k) * 100.0; /* m^-1 */
+                double L = alpha > 0.0 ? -log(u1[2]) / alpha : INFINITY;
+                double depth = L * fabs(d[2]);
+                note_margin(&margin, (depth - sc->t_si) / sc->t_si);
+                if (!(depth <= sc->t_si)) {
+                    set_event(ev, ORC_ESCAPED, k, q);
+                    ev->margin = margin;
+                    return;
+                }
+                xc = q[0] + d[0] * L;
+                yc = q[1] + d[1] * L;
+                if (sc->physics & ORC_DIFFUSION) {
+                    /* Gaussian diffusion with sigma proportional to the drift distance
+                     * (section 2.4.3 simplified: sigma = sigma_max (t_Si - depth)/t_Si) */
+                    double ud[4];
+                    draw(sc, si, photon, 6, 0, ud);
+                    double sigma = sc->sigma_max * (sc->t_si - depth) / sc->t_si;
+                    double rad = sqrt(-2.0 * log(ud[0]));
+                    xc += sigma * rad * cos(TWO_PI * ud[1]);
+                    yc += sigma * rad * sin(TWO_PI * ud[1]);
+                }
+            }
+            ev->xe = xc;
+            ev->ye = yc;
+            /* pixel quantisation (section 2.4.3, last step) */
+            double fx = (xc - sc->chip_x0) / sc->pixel, fy = (yc - sc->chip_y0) / sc->pixel;
+            double ix = floor(fx), iy = floor(fy);
+            note_margin(&margin, fx - ix);
+            note_margin(&margin, 1.0 - (fx - ix));
+            note_margin(&margin, fy - iy);
+            note_margin(&margin, 1.0 - (fy - iy));
+            ev->status = ORC_OFF_CHIP;
+            ev->surface = k;
+            if (ix >= 0.0 && ix < (double)sc->nx && iy >= 0.0 && iy < (double)sc->ny) {
+                ev->status = ORC_DETECTED;
+                ev->pix_i = (int32_t)ix;
+                ev->pix_j = (int32_t)iy;
+                if (image) image[(size_t)ev->pix_j * sc->nx + ev->pix_i] += 1u;
+            }
+            ev->margin = margin;
+            return;
+        }
+        to_global(sc, k, q, d, p, n);
+    }
+    /* ran out of surfaces without a detector */
+    set_event(ev, ORC_MISSED, sc->n_surf, p);
+    ev->margin = margin;
+}
+
+int orc_trace(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count, uint32_t* image,
+              orc_event* events) {
+    if (src < 0 || src >= sc->n_src) return -1;
+    orc_event tmp;
+    for (uint64_t i = 0; i < count; ++i) {
+        orc_event* ev = events ? &events[i] : &tmp;
+        trace_one(sc, src, begin + i, image, ev);
+    }
+    return 0;
+}
