@@ -1,0 +1,239 @@
+/*
+ * phx -- photon Monte Carlo trace on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the per-photon trace of the photon Monte Carlo image simulator described by
+ * Peterson et al., "Simulation of Astronomical Images from Optical Survey Telescopes using a
+ * Comprehensive Photon Monte Carlo Approach" (ApJS 218:14, 2015):
+ *
+ *   sky photon sampling                                    (section 2.2, 2.2.1)
+ *   -> frozen-flow phase-screen deflection, layer by layer (sections 2.3.1, 2.3.2)
+ *   -> conic + polynomial-asphere surfaces: Newton intersection, reflection, refraction with
+ *      Sellmeier / silicon indices, coating-transmission roulette  (sections 2.4.1, 2.4.2)
+ *   -> silicon conversion at an exponentially distributed depth, charge diffusion, pixel binning
+ *                                                          (sections 2.4.2, 2.4.3)
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: PHX_OK (0) or a negative phx_status.  On error the context's message
+ *     (phx_last_error) says what was wrong; nothing is enqueued.  Errors never abort the process.
+ *   - Pointers named *_host are host memory, read during the call only.  Pointers named *_dev are
+ *     device memory on the context's GPU, owned by the caller; the library never frees them.
+ *     Output buffers are accumulated into, never cleared.
+ *   - Work is enqueued asynchronously on the given HIP stream (NULL = the legacy default stream);
+ *     caller-owned device buffers must stay valid until that stream has completed the work.
+ *   - A context belongs to one device and must not be used from two threads at once.
+ *   - Per-photon anomalies (no intersection, Newton non-convergence, total internal reflection)
+ *     are outcomes counted in the statistics buffer, not errors.
+ *
+ * Units: metres, seconds, radians.  Global frame: z towards the sky, photons arrive travelling
+ * towards -z, the first surface's vertex at the origin.
+ */
+#ifndef PHX_H
+#define PHX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t phx_status;
+enum {
+    PHX_OK = 0,
+    PHX_ERR_INVALID = -1,   /* bad argument: null pointer, size, NaN, out-of-range value */
+    PHX_ERR_STATE = -2,     /* a required load (prescription, sources, screens) is missing */
+    PHX_ERR_HIP = -3,       /* a HIP runtime call failed; message holds hipGetErrorString */
+    PHX_ERR_NOMEM = -4,     /* device or host allocation failed */
+    PHX_ERR_CAPACITY = -5   /* an output buffer is too small for the request */
+};
+
+#define PHX_MAX_SURF 16
+#define PHX_MAX_LAYERS 8
+#define PHX_MAX_SCALES 4
+#define PHX_N_THETA 22
+#define PHX_N_STATUS 10
+
+/* Surface kinds and media (section 2.4.1: mirrors have one surface, lenses two; the detector
+ * is an optical surface like a lens surface). */
+enum { PHX_MIRROR = 0, PHX_REFRACT = 1, PHX_DETECTOR = 2 };
+enum { PHX_VACUUM = 0, PHX_GLASS = 1, PHX_SILICON = 2 };
+
+/* Photon fates.  The statistics buffer counts them per (status, surface). */
+enum {
+    PHX_DETECTED = 0,   /* converted in silicon and binned on the chip            */
+    PHX_OFF_CHIP = 1,   /* reached the focal plane outside the chip's pixels      */
+    PHX_VIGNETTED = 2,  /* outside a surface's clear aperture                      */
+    PHX_ABSORBED = 3,   /* lost to a coating (transmission roulette)               */
+    PHX_MISSED = 4,     /* ray does not meet the surface                           */
+    PHX_NONCONV = 5,    /* intersection iteration did not converge                 */
+    PHX_TIR = 6,        /* total internal reflection at a refracting surface       */
+    PHX_ESCAPED = 7,    /* crossed the silicon without converting                  */
+    PHX_OBSCURED = 8,   /* blocked by the central obscuration                      */
+    PHX_CULLED = 9      /* removed before tracing by the transmission pre-roll     */
+};
+
+/* Physics and execution flags (phx_trace_args.flags). */
+enum {
+    PHX_F_ATMOSPHERE = 1u << 0, /* screen deflections (needs phx_load_screens)             */
+    PHX_F_COATINGS = 1u << 1,   /* coating roulette (needs phx_load_coatings)              */
+    PHX_F_SILICON = 1u << 2,    /* refraction into silicon, conversion depth, escape       */
+    PHX_F_DIFFUSION = 1u << 3,  /* Gaussian charge diffusion                               */
+    PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
+                                   worst-case transmission of any coated surface (section 3.2,
+                                   dynamic transmission optimisation); images and moments are
+                                   unchanged, culled photons are counted as PHX_CULLED */
+    PHX_F_EVENTS = 1u << 9,     /* write per-photon records for sampled photons            */
+    PHX_F_MOMENTS = 1u << 10    /* accumulate per-source moments of converted photons      */
+};
+
+typedef struct phx_ctx_s* phx_ctx;
+
+/* One optical surface (section 2.4.1 surface equation; paper Table 1 rows "optic type",
+ * "radius of curvature", "position", "outer/inner radius", "conic constant", "aspheric
+ * coefficients", "medium"):
+ *   z = z_vertex + c r^2 / (1 + sqrt(1 - (1 + kappa) c^2 r^2)) + sum_{i=3..10} alpha[i-3] r^i.
+ * medium is the medium the photon enters at this surface; coating is a table index or -1;
+ * group is the rigid-body perturbation group (0 none, 1 = theta[0..4], 2 = theta[5..9]). */
+typedef struct {
+    int32_t kind, medium, coating, group;
+    double z_vertex, curvature, conic;
+    double alpha[8];
+    double r_inner, r_outer;
+} phx_surface;
+
+/* Optical prescription + focal plane (paper Table 1).  Surfaces are in travel order; the last
+ * one must be the detector.  The chip is a rectangular device of nx x ny square pixels whose
+ * pixel (0,0) starts at (chip_x0, chip_y0) in the detector's frame (section 2.4.1). */
+typedef struct {
+    int32_t n_surfaces, nx, ny, pad;
+    phx_surface surf[PHX_MAX_SURF];
+    double pupil_r_inner, pupil_r_outer;  /* sampling annulus on the first surface (section 2.2) */
+    double z_start;                       /* plane above every optic where the optics trace starts */
+    double obscuration_z, obscuration_r;  /* central obscuration disk (r = 0: none) */
+    double sellmeier_b[3], sellmeier_c[3];/* glass: n^2 = 1 + sum B l^2/(l^2 - C), l in um */
+    double chip_x0, chip_y0, pixel;
+    double si_thickness, si_temperature, sigma_max; /* silicon (sections 2.4.2-2.4.3) */
+    double group_pivot[3][3];             /* rotation pivots of perturbation groups 0..2 */
+} phx_prescription;
+
+/* Turbulence layers (section 2.3.1): heights above the first surface's vertex, wind vectors,
+ * screen pixel sizes per nested scale (coarse to fine), screen side, reference wavelength of
+ * the (lambda/lambda_ref)^(-1/5) kick scaling (section 2.3.2). */
+typedef struct {
+    int32_t n_layers, n_scales, screen_n, pad;
+    double height[PHX_MAX_LAYERS];
+    double wind[PHX_MAX_LAYERS][2];
+    double pixel[PHX_MAX_SCALES];
+    double lambda_ref;
+} phx_atmosphere;
+
+/* A source (section 2.2): nominal direction n_x = xi, n_y = eta, n_z = -sqrt(1-xi^2-eta^2).
+ * kind 0 point, 1 ellipsoidal Sersic (section 2.2.1: index n, b_n, semi-axis scales a >= b in
+ * radians, position angle).  sed = -1: photon spectrum flat on [lambda_lo, lambda_hi]; sed >= 0:
+ * row of the tabulated SEDs.  Wavelengths are multiplied by (1 + redshift). */
+typedef struct {
+    double xi, eta;
+    int32_t kind, sed;
+    double lambda_lo, lambda_hi, redshift;
+    double sersic_n, sersic_bn, sersic_a, sersic_b, sersic_pa;
+    uint64_t n_photons;
+} phx_source;
+
+/* Per-photon record written for sampled photons (PHX_F_EVENTS). */
+typedef struct {
+    uint64_t photon;
+    int32_t source, status, surface, pix_i, pix_j, newton;
+    double x, y, z;    /* last position, in the frame of the deciding surface (detector frame
+                          for photons that reached the detector)                             */
+    double xe, ye;     /* electron position in the detector frame (after diffusion)         */
+    double lambda;
+} phx_event;
+
+/* Statistics buffer layout (uint64): counts[status][surface + 1] for status < PHX_N_STATUS and
+ * surface in -1..PHX_MAX_SURF-1 (column 0 = before any surface), followed by PHX_STAT_NEWTON
+ * (total Newton iterations) and PHX_STAT_TRACED (photons traced past the pre-roll). */
+#define PHX_STAT_COLS (PHX_MAX_SURF + 1)
+#define PHX_STAT_NEWTON (PHX_N_STATUS * PHX_STAT_COLS)
+#define PHX_STAT_TRACED (PHX_STAT_NEWTON + 1)
+#define PHX_STATS_LEN (PHX_STAT_TRACED + 1)
+
+/* Moments buffer layout (double): per source, [n, sum x, sum y, sum x^2, sum y^2, sum xy] of
+ * electron positions of photons that converted in silicon (status DETECTED or OFF_CHIP). */
+#define PHX_MOMENT_LEN 6
+
+typedef struct {
+    uint32_t seed;          /* Philox key word 0 (key word 1 = source index)                  */
+    uint32_t flags;         /* PHX_F_* */
+    int32_t src_begin;      /* sources [src_begin, src_end) of the loaded catalogue           */
+    int32_t src_end;
+    uint64_t photon_begin;  /* first photon index traced for every source                      */
+    uint64_t photon_count;  /* photons per source; 0 = each source's n_photons                 */
+    double exposure;        /* t_e (section 2.2 time stamp t = t_e u)                          */
+    double pupil_margin;    /* annulus enlargement (section 2.2: slightly larger aperture)      */
+    uint32_t* image_dev;    /* [ny][nx], accumulated (+1 per detected photon); required        */
+    uint64_t* stats_dev;    /* [PHX_STATS_LEN], accumulated; may be NULL                        */
+    double* moments_dev;    /* [n_sources][PHX_MOMENT_LEN], accumulated; NULL unless MOMENTS   */
+    phx_event* events_dev;  /* NULL unless EVENTS                                               */
+    uint64_t event_stride;  /* photon g of the launch (sources concatenated in order, photons
+                               in index order) is recorded at slot g / stride iff g % stride == 0 */
+    uint64_t event_capacity;/* slots available; PHX_ERR_CAPACITY if too small                   */
+} phx_trace_args;
+
+/* Library version string (static storage). */
+const char* phx_version(void);
+
+/* Create a context on HIP device `device`.  *out receives the handle.  Allocates the context's
+ * small device tables.  Errors: PHX_ERR_INVALID (null out, bad device), PHX_ERR_HIP. */
+phx_status phx_create(int32_t device, phx_ctx* out);
+
+/* Free the context and every device buffer it owns.  NULL is ignored.  Synchronises the device. */
+void phx_destroy(phx_ctx ctx);
+
+/* Message of the last failed call on ctx (context-owned, valid until the next call). */
+const char* phx_last_error(phx_ctx ctx);
+
+/* Load the optical prescription (section 2.4.1, paper Table 1), copied from host memory.
+ * Validates surface count (1..PHX_MAX_SURF, last = detector), finite values, apertures,
+ * chip size.  Keeps the current perturbation.  Errors: PHX_ERR_INVALID. */
+phx_status phx_load_prescription(phx_ctx ctx, const phx_prescription* p_host);
+
+/* Set the misalignment/deformation vector (section 2.4.1: decenter, defocus and rotations per
+ * rigid group; Zernike deformation of the first surface):
+ *   theta[0..4]  group 1: dx, dy, tilt_x, tilt_y, dz      theta[5..9] group 2: same
+ *   theta[10..21] Noll Z4..Z15 amplitudes (m) on surface 0, normalised to its outer radius.
+ * A group is rotated by R = R_x(tilt_x) R_y(tilt_y) about its pivot, then translated.
+ * n must be PHX_N_THETA.  Takes effect for work enqueued afterwards.  Errors: PHX_ERR_INVALID. */
+phx_status phx_set_perturbation(phx_ctx ctx, const double* theta_host, int32_t n);
+
+/* Load coating tables (section 2.4.2 transmission probability vs angle and wavelength):
+ * float32 [n_coat][n_s][n_lambda], transmission on a uniform grid of s = sin^2(incidence angle)
+ * from 0 to s_max and wavelength lambda0 + k dlambda.  Copied to device memory.
+ * Errors: PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
+phx_status phx_load_coatings(phx_ctx ctx, const float* tables_host, int32_t n_coat, int32_t n_s,
+                             int32_t n_lambda, double s_max, double lambda0, double dlambda);
+
+/* Load turbulence screens (sections 2.3.1-2.3.2).  opd_dev: float32 [L][S][N][N] optical path
+ * (m), row j along y, column i along x, periodic; read only by work enqueued on `stream` during
+ * this call.  The context derives and owns the gradient screens (centred differences).
+ * Errors: PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
+phx_status phx_load_screens(phx_ctx ctx, const phx_atmosphere* atm_host, const float* opd_dev,
+                            int64_t n_floats, void* stream);
+
+/* Load the source catalogue (section 2.2) and tabulated SEDs (f_lambda per wavelength bin on the
+ * shared grid sed_edges_host[0..sed_k]; flux_host [n_sed][sed_k]).  Both copied; the context
+ * builds each SED's photon cumulative distribution (section 2.2: flux / photon energy x bin
+ * width).  n_sed may be 0.  Errors: PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
+phx_status phx_load_sources(phx_ctx ctx, const phx_source* src_host, int32_t n_src,
+                            const double* sed_edges_host, const double* sed_flux_host,
+                            int32_t n_sed, int32_t sed_k);
+
+/* Trace photons: for every source s in [src_begin, src_end), photons photon_begin ..
+ * photon_begin + count - 1, each keyed by Philox4x32-10 (key = (seed, s), counter = (photon
+ * index, block, stream)), so any photon's history is reproducible independently of the launch.
+ * Enqueued on `stream`.  Errors: PHX_ERR_INVALID, PHX_ERR_STATE, PHX_ERR_CAPACITY, PHX_ERR_HIP. */
+phx_status phx_trace(phx_ctx ctx, const phx_trace_args* args, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,538 @@
+// C ABI of the photon trace library (declarations and contracts in include/phx.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "phx_internal.h"
+
+using phx::DevParams;
+using phx::DevSource;
+using phx::DevSurface;
+
+struct phx_ctx_s {
+    int device = 0;
+    int n_cu = 256;
+    std::string err;
+    bool have_presc = false, have_src = false, have_coat = false, have_screens = false;
+    phx_prescription presc{};
+    double theta[PHX_N_THETA] = {0};
+    DevParams host{};          // host image of the device parameter block
+    DevParams* dparams = nullptr;
+    bool dirty = true;
+    float* d_coat = nullptr;
+    float* d_coat_max = nullptr;
+    float2* d_grad = nullptr;
+    size_t grad_elems = 0;
+    DevSource* d_src = nullptr;
+    std::vector<phx_source> src;
+    double* d_cdf = nullptr;
+    double* d_edges = nullptr;
+    uint64_t* d_prefix = nullptr;
+    size_t prefix_cap = 0;
+};
+
+namespace {
+
+phx_status fail(phx_ctx c, phx_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+phx_status hip_fail(phx_ctx c, hipError_t e, const char* what) {
+    return fail(c, PHX_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_all(const double* v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+template <class T>
+void free_dev(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+// Rigid-body transforms of the surfaces from the perturbation vector.  A group's elements are
+// rotated by R = R_x(tx) R_y(ty) about the group's pivot P and translated by (dx, dy, dz): an
+// element-frame point q maps to g = R q + t with t = P + R (v - P) + d, v = (0, 0, z_vertex).
+void build_surfaces(phx_ctx c) {
+    const phx_prescription& p = c->presc;
+    DevParams& H = c->host;
+    H.n_surf = p.n_surfaces;
+    for (int k = 0; k < p.n_surfaces; ++k) {
+        const phx_surface& s = p.surf[k];
+        DevSurface& d = H.surf[k];
+        std::memset(&d, 0, sizeof(d));
+        d.kind = s.kind;
+        d.medium = s.medium;
+        d.coating = s.coating;
+        d.c = s.curvature;
+        d.kappa1 = 1.0 + s.conic;
+        d.asphere = 0;
+        for (int i = 0; i < 8; ++i) {
+            d.alpha[i] = s.alpha[i];
+            if (s.alpha[i] != 0.0) d.asphere = 1;
+        }
+        d.r_in = s.r_inner;
+        d.r_out = s.r_outer;
+        double dx = 0, dy = 0, dz = 0, tx = 0, ty = 0;
+        const double* P = p.group_pivot[0];
+        if (s.group == 1 || s.group == 2) {
+            const double* th = c->theta + 5 * (s.group - 1);
+            dx = th[0]; dy = th[1]; tx = th[2]; ty = th[3]; dz = th[4];
+            P = p.group_pivot[s.group];
+        }
+        d.moved = (dx != 0 || dy != 0 || dz != 0 || tx != 0 || ty != 0) ? 1 : 0;
+        const double cx = std::cos(tx), sx = std::sin(tx), cy = std::cos(ty), sy = std::sin(ty);
+        // R_x(tx) R_y(ty)
+        const double R[9] = {cy, 0.0, sy, sx * sy, cx, -sx * cy, -cx * sy, sx, cx * cy};
+        const double v[3] = {0.0, 0.0, s.z_vertex};
+        const double dd[3] = {dx, dy, dz};
+        for (int i = 0; i < 3; ++i) {
+            const double rv = R[3 * i] * (v[0] - P[0]) + R[3 * i + 1] * (v[1] - P[1]) +
+                              R[3 * i + 2] * (v[2] - P[2]);
+            d.t[i] = d.moved ? P[i] + rv + dd[i] : v[i];
+        }
+        for (int i = 0; i < 9; ++i) d.R[i] = R[i];
+    }
+    // Zernike deformation of surface 0
+    bool any = false;
+    for (int j = 0; j < phx::kNZern; ++j) {
+        H.zern[j] = c->theta[10 + j];
+        any |= H.zern[j] != 0.0;
+    }
+    H.surf[0].zernike = any ? 1 : 0;
+    H.zern_inv_r = 1.0 / p.surf[0].r_outer;
+}
+
+phx_status set_device(phx_ctx c) {
+    const hipError_t e = hipSetDevice(c->device);
+    return e == hipSuccess ? PHX_OK : hip_fail(c, e, "hipSetDevice");
+}
+
+phx_status upload_params(phx_ctx c, hipStream_t stream) {
+    if (!c->dirty) return PHX_OK;
+    hipError_t e = hipMemcpyAsync(c->dparams, &c->host, sizeof(DevParams), hipMemcpyHostToDevice,
+                                  stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync(params)");
+    // the host image may change before the copy runs: wait for it
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    c->dirty = false;
+    return PHX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* phx_version(void) { return "phx 0.1 (gfx950)"; }
+
+phx_status phx_create(int32_t device, phx_ctx* out) {
+    if (!out) return PHX_ERR_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PHX_ERR_INVALID;
+    phx_ctx c = new (std::nothrow) phx_ctx_s();
+    if (!c) return PHX_ERR_NOMEM;
+    c->device = device;
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, device);
+        if (e == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dparams, sizeof(DevParams));
+    if (e != hipSuccess) {
+        delete c;
+        return PHX_ERR_HIP;
+    }
+    *out = c;
+    return PHX_OK;
+}
+
+void phx_destroy(phx_ctx c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_dev(c->dparams);
+    free_dev(c->d_coat);
+    free_dev(c->d_coat_max);
+    free_dev(c->d_grad);
+    free_dev(c->d_src);
+    free_dev(c->d_cdf);
+    free_dev(c->d_edges);
+    free_dev(c->d_prefix);
+    delete c;
+}
+
+const char* phx_last_error(phx_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+phx_status phx_load_prescription(phx_ctx c, const phx_prescription* p) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!p) return fail(c, PHX_ERR_INVALID, "null prescription");
+    if (p->n_surfaces < 1 || p->n_surfaces > PHX_MAX_SURF)
+        return fail(c, PHX_ERR_INVALID, "n_surfaces %d outside 1..%d", p->n_surfaces, PHX_MAX_SURF);
+    if (p->surf[p->n_surfaces - 1].kind != PHX_DETECTOR)
+        return fail(c, PHX_ERR_INVALID, "the last surface must be the detector");
+    for (int k = 0; k < p->n_surfaces; ++k) {
+        const phx_surface& s = p->surf[k];
+        if (s.kind < PHX_MIRROR || s.kind > PHX_DETECTOR)
+            return fail(c, PHX_ERR_INVALID, "surface %d: bad kind %d", k, s.kind);
+        if (s.kind == PHX_DETECTOR && k != p->n_surfaces - 1)
+            return fail(c, PHX_ERR_INVALID, "surface %d: detector before the last surface", k);
+        if (s.medium < PHX_VACUUM || s.medium > PHX_SILICON)
+            return fail(c, PHX_ERR_INVALID, "surface %d: bad medium %d", k, s.medium);
+        if (s.group < 0 || s.group > 2)
+            return fail(c, PHX_ERR_INVALID, "surface %d: bad group %d", k, s.group);
+        const double v[4] = {s.z_vertex, s.curvature, s.conic, s.r_inner};
+        if (!finite_all(v, 4) || !finite_all(s.alpha, 8) || !std::isfinite(s.r_outer) ||
+            !(s.r_outer > 0.0) || s.r_inner < 0.0 || s.r_inner >= s.r_outer)
+            return fail(c, PHX_ERR_INVALID, "surface %d: non-finite value or bad aperture", k);
+    }
+    if (p->nx <= 0 || p->ny <= 0 || (int64_t)p->nx * p->ny > (int64_t)1 << 31)
+        return fail(c, PHX_ERR_INVALID, "chip %d x %d out of range", p->nx, p->ny);
+    const double g[] = {p->pupil_r_inner, p->pupil_r_outer, p->z_start, p->obscuration_z,
+                        p->obscuration_r, p->chip_x0, p->chip_y0, p->pixel, p->si_thickness,
+                        p->si_temperature, p->sigma_max};
+    if (!finite_all(g, sizeof(g) / sizeof(g[0])) || !(p->pixel > 0) || !(p->si_thickness > 0) ||
+        !(p->si_temperature > 0) || p->sigma_max < 0 || !(p->pupil_r_outer > p->pupil_r_inner) ||
+        p->pupil_r_inner < 0)
+        return fail(c, PHX_ERR_INVALID, "bad pupil, chip or silicon parameters");
+    if (!finite_all(p->sellmeier_b, 3) || !finite_all(p->sellmeier_c, 3) ||
+        !finite_all(&p->group_pivot[0][0], 9))
+        return fail(c, PHX_ERR_INVALID, "non-finite Sellmeier coefficients or pivots");
+    c->presc = *p;
+    DevParams& H = c->host;
+    H.nx = p->nx;
+    H.ny = p->ny;
+    H.pupil_r_in = p->pupil_r_inner;
+    H.pupil_r_out = p->pupil_r_outer;
+    H.z_start = p->z_start;
+    H.obsc_z = p->obscuration_z;
+    H.obsc_r = p->obscuration_r;
+    for (int i = 0; i < 3; ++i) {
+        H.sell_b[i] = p->sellmeier_b[i];
+        H.sell_c[i] = p->sellmeier_c[i];
+    }
+    H.has_glass = 0;
+    for (int k = 0; k < p->n_surfaces; ++k) H.has_glass |= p->surf[k].medium == PHX_GLASS;
+    H.chip_x0 = p->chip_x0;
+    H.chip_y0 = p->chip_y0;
+    H.pixel = p->pixel;
+    H.t_si = p->si_thickness;
+    H.sigma_max = p->sigma_max;
+    // Rajkanan temperature-dependent constants (section 2.4.2)
+    const double T = p->si_temperature, kB = 8.617333262e-5;
+    const double shift = 7.021e-4 * T * T / (T + 1108.0);
+    H.eg[0] = 1.1557 - shift;
+    H.eg[1] = 2.5 - shift;
+    H.egd = 3.2 - shift;
+    const double ep[2] = {1.827e-2, 5.773e-2};
+    for (int i = 0; i < 2; ++i) {
+        H.absorb[i] = std::exp(ep[i] / (kB * T)) - 1.0;
+        H.emit[i] = 1.0 - std::exp(-ep[i] / (kB * T));
+    }
+    build_surfaces(c);
+    c->have_presc = true;
+    c->dirty = true;
+    return PHX_OK;
+}
+
+phx_status phx_set_perturbation(phx_ctx c, const double* theta, int32_t n) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!theta || n != PHX_N_THETA)
+        return fail(c, PHX_ERR_INVALID, "perturbation needs %d values", PHX_N_THETA);
+    if (!finite_all(theta, PHX_N_THETA)) return fail(c, PHX_ERR_INVALID, "non-finite theta");
+    std::memcpy(c->theta, theta, sizeof(c->theta));
+    if (c->have_presc) build_surfaces(c);
+    c->dirty = true;
+    return PHX_OK;
+}
+
+phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t n_s,
+                             int32_t n_lam, double s_max, double lam0, double dlam) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!t || n_coat <= 0 || n_s < 2 || n_lam < 2 || !(s_max > 0) || !(dlam > 0) ||
+        !std::isfinite(lam0) || !std::isfinite(s_max) || !std::isfinite(dlam))
+        return fail(c, PHX_ERR_INVALID, "bad coating table description");
+    const size_t n = (size_t)n_coat * n_s * n_lam;
+    std::vector<float> mx((size_t)n_coat * n_lam, 0.0f);
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(t[i]) || t[i] < 0.0f || t[i] > 1.0f)
+            return fail(c, PHX_ERR_INVALID, "coating value %zu not in [0, 1]", i);
+    for (int k = 0; k < n_coat; ++k)
+        for (int s = 0; s < n_s; ++s)
+            for (int l = 0; l < n_lam; ++l) {
+                float v = t[((size_t)k * n_s + s) * n_lam + l];
+                float& m = mx[(size_t)k * n_lam + l];
+                if (v > m) m = v;
+            }
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    free_dev(c->d_coat);
+    free_dev(c->d_coat_max);
+    hipError_t e = hipMalloc((void**)&c->d_coat, n * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_coat_max, mx.size() * sizeof(float));
+    if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "coating tables: %s", hipGetErrorString(e));
+    e = hipMemcpy(c->d_coat, t, n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_coat_max, mx.data(), mx.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(coatings)");
+    DevParams& H = c->host;
+    H.n_coat = n_coat;
+    H.n_s = n_s;
+    H.n_lam = n_lam;
+    H.s_step = s_max / (double)(n_s - 1);
+    H.lam0 = lam0;
+    H.dlam = dlam;
+    H.coat = c->d_coat;
+    H.coat_max = c->d_coat_max;
+    c->have_coat = true;
+    c->dirty = true;
+    return PHX_OK;
+}
+
+phx_status phx_load_screens(phx_ctx c, const phx_atmosphere* a, const float* opd, int64_t n_floats,
+                            void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!a || !opd) return fail(c, PHX_ERR_INVALID, "null atmosphere or screen pointer");
+    if (a->n_layers < 1 || a->n_layers > PHX_MAX_LAYERS || a->n_scales < 1 ||
+        a->n_scales > PHX_MAX_SCALES)
+        return fail(c, PHX_ERR_INVALID, "layers %d / scales %d out of range", a->n_layers,
+                    a->n_scales);
+    const int N = a->screen_n;
+    if (N < 4 || (N & (N - 1)) != 0)
+        return fail(c, PHX_ERR_INVALID, "screen side %d must be a power of two >= 4", N);
+    const int64_t want = (int64_t)a->n_layers * a->n_scales * N * N;
+    if (n_floats != want)
+        return fail(c, PHX_ERR_INVALID, "screen buffer has %lld floats, expected %lld",
+                    (long long)n_floats, (long long)want);
+    for (int i = 0; i < a->n_layers; ++i) {
+        const double v[3] = {a->height[i], a->wind[i][0], a->wind[i][1]};
+        if (!finite_all(v, 3)) return fail(c, PHX_ERR_INVALID, "layer %d not finite", i);
+        if (i > 0 && !(a->height[i] > a->height[i - 1]))
+            return fail(c, PHX_ERR_INVALID, "layer heights must increase");
+    }
+    for (int s = 0; s < a->n_scales; ++s)
+        if (!(a->pixel[s] > 0) || !std::isfinite(a->pixel[s]))
+            return fail(c, PHX_ERR_INVALID, "scale %d pixel not positive", s);
+    if (!(a->lambda_ref > 0)) return fail(c, PHX_ERR_INVALID, "lambda_ref not positive");
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    if ((size_t)want != c->grad_elems) {
+        free_dev(c->d_grad);
+        c->grad_elems = 0;
+        hipError_t e = hipMalloc((void**)&c->d_grad, (size_t)want * sizeof(float2));
+        if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "gradient screens: %s",
+                                         hipGetErrorString(e));
+        c->grad_elems = (size_t)want;
+    }
+    hipError_t e = phx::launch_gradients(opd, c->d_grad, a->n_layers, a->n_scales, N, a->pixel, st);
+    if (e != hipSuccess) return hip_fail(c, e, "gradient kernel");
+    DevParams& H = c->host;
+    H.n_layers = a->n_layers;
+    H.n_scales = a->n_scales;
+    H.screen_n = N;
+    for (int i = 0; i < a->n_layers; ++i) {
+        H.height[i] = a->height[i];
+        H.wind[i][0] = a->wind[i][0];
+        H.wind[i][1] = a->wind[i][1];
+    }
+    for (int s = 0; s < a->n_scales; ++s) H.inv_pix[s] = 1.0 / a->pixel[s];
+    H.lambda_ref = a->lambda_ref;
+    H.grad = c->d_grad;
+    c->have_screens = true;
+    c->dirty = true;
+    return PHX_OK;
+}
+
+phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, const double* edges,
+                            const double* flux, int32_t n_sed, int32_t sed_k) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!src || n_src <= 0) return fail(c, PHX_ERR_INVALID, "no sources");
+    if (n_sed < 0 || (n_sed > 0 && (!edges || !flux || sed_k < 1)))
+        return fail(c, PHX_ERR_INVALID, "bad SED table");
+    std::vector<DevSource> ds(n_src);
+    for (int i = 0; i < n_src; ++i) {
+        const phx_source& s = src[i];
+        const double v[] = {s.xi, s.eta, s.lambda_lo, s.lambda_hi, s.redshift, s.sersic_n,
+                            s.sersic_bn, s.sersic_a, s.sersic_b, s.sersic_pa};
+        if (!finite_all(v, sizeof(v) / sizeof(v[0])))
+            return fail(c, PHX_ERR_INVALID, "source %d: non-finite field", i);
+        if (!(s.xi * s.xi + s.eta * s.eta < 1.0))
+            return fail(c, PHX_ERR_INVALID, "source %d: direction outside the unit disk", i);
+        if (s.kind != 0 && s.kind != 1) return fail(c, PHX_ERR_INVALID, "source %d: kind", i);
+        if (s.kind == 1 && !(s.sersic_n > 0 && s.sersic_bn > 0 && s.sersic_a >= 0 && s.sersic_b >= 0))
+            return fail(c, PHX_ERR_INVALID, "source %d: Sersic parameters", i);
+        if (s.sed >= n_sed || s.sed < -1) return fail(c, PHX_ERR_INVALID, "source %d: sed index", i);
+        if (s.sed < 0 && !(s.lambda_lo > 0 && s.lambda_hi >= s.lambda_lo))
+            return fail(c, PHX_ERR_INVALID, "source %d: wavelength band", i);
+        if (!(s.redshift > -1.0)) return fail(c, PHX_ERR_INVALID, "source %d: redshift", i);
+        DevSource& d = ds[i];
+        d.xi = s.xi;
+        d.eta = s.eta;
+        d.nz = -std::sqrt(1.0 - s.xi * s.xi - s.eta * s.eta);
+        d.lambda_lo = s.lambda_lo;
+        d.lambda_span = s.lambda_hi - s.lambda_lo;
+        d.redshift1 = 1.0 + s.redshift;
+        d.sersic_n = s.sersic_n;
+        d.sersic_bn = s.sersic_bn;
+        d.sersic_a = s.sersic_a;
+        d.sersic_b = s.sersic_b;
+        d.cos_pa = std::cos(s.sersic_pa);
+        d.sin_pa = std::sin(s.sersic_pa);
+        d.kind = s.kind;
+        d.sed = s.sed;
+        d.n_photons = s.n_photons;
+    }
+    // SED photon CDFs (section 2.2): bin weight = f_lambda x width x centre wavelength (flux over
+    // photon energy), accumulated in order and normalised; CDF[K] = 1 exactly.
+    std::vector<double> cdf;
+    if (n_sed > 0) {
+        for (int k = 0; k < sed_k; ++k)
+            if (!(edges[k + 1] > edges[k]) || !(edges[k] > 0))
+                return fail(c, PHX_ERR_INVALID, "SED edges must be positive and increasing");
+        cdf.assign((size_t)n_sed * (sed_k + 1), 0.0);
+        for (int s = 0; s < n_sed; ++s) {
+            double* C = cdf.data() + (size_t)s * (sed_k + 1);
+            const double* f = flux + (size_t)s * sed_k;
+            C[0] = 0.0;
+            for (int k = 0; k < sed_k; ++k) {
+                if (!(f[k] >= 0) || !std::isfinite(f[k]))
+                    return fail(c, PHX_ERR_INVALID, "SED %d bin %d negative or not finite", s, k);
+                const double lo = edges[k], hi = edges[k + 1];
+                C[k + 1] = C[k] + f[k] * (hi - lo) * (0.5 * (lo + hi));
+            }
+            const double total = C[sed_k];
+            if (!(total > 0)) return fail(c, PHX_ERR_INVALID, "SED %d is zero", s);
+            for (int k = 1; k < sed_k; ++k) C[k] = C[k] / total;
+            C[sed_k] = 1.0;
+        }
+    }
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    free_dev(c->d_src);
+    free_dev(c->d_cdf);
+    free_dev(c->d_edges);
+    hipError_t e = hipMalloc((void**)&c->d_src, ds.size() * sizeof(DevSource));
+    if (e == hipSuccess && n_sed > 0) e = hipMalloc((void**)&c->d_cdf, cdf.size() * sizeof(double));
+    if (e == hipSuccess && n_sed > 0)
+        e = hipMalloc((void**)&c->d_edges, (size_t)(sed_k + 1) * sizeof(double));
+    if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "sources: %s", hipGetErrorString(e));
+    e = hipMemcpy(c->d_src, ds.data(), ds.size() * sizeof(DevSource), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_sed > 0)
+        e = hipMemcpy(c->d_cdf, cdf.data(), cdf.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_sed > 0)
+        e = hipMemcpy(c->d_edges, edges, (size_t)(sed_k + 1) * sizeof(double),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(sources)");
+    c->src.assign(src, src + n_src);
+    DevParams& H = c->host;
+    H.src = c->d_src;
+    H.sed_cdf = c->d_cdf;
+    H.sed_edges = c->d_edges;
+    H.sed_k = n_sed > 0 ? sed_k : 0;
+    c->have_src = true;
+    c->dirty = true;
+    return PHX_OK;
+}
+
+phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!a) return fail(c, PHX_ERR_INVALID, "null trace arguments");
+    if (!c->have_presc || !c->have_src)
+        return fail(c, PHX_ERR_STATE, "load a prescription and sources first");
+    if ((a->flags & PHX_F_ATMOSPHERE) && !c->have_screens)
+        return fail(c, PHX_ERR_STATE, "PHX_F_ATMOSPHERE without loaded screens");
+    if ((a->flags & PHX_F_COATINGS) && !c->have_coat) {
+        bool coated = false;
+        for (int k = 0; k < c->presc.n_surfaces; ++k) coated |= c->presc.surf[k].coating >= 0;
+        if (coated) return fail(c, PHX_ERR_STATE, "PHX_F_COATINGS without loaded coatings");
+    }
+    for (int k = 0; k < c->presc.n_surfaces; ++k)
+        if (c->presc.surf[k].coating >= (c->have_coat ? c->host.n_coat : 0) &&
+            (a->flags & PHX_F_COATINGS))
+            return fail(c, PHX_ERR_INVALID, "surface %d uses coating %d beyond the loaded tables",
+                        k, c->presc.surf[k].coating);
+    const int n_src_all = (int)c->src.size();
+    if (a->src_begin < 0 || a->src_end > n_src_all || a->src_begin >= a->src_end)
+        return fail(c, PHX_ERR_INVALID, "source range [%d, %d) outside [0, %d)", a->src_begin,
+                    a->src_end, n_src_all);
+    if (!a->image_dev) return fail(c, PHX_ERR_INVALID, "null image");
+    if ((a->flags & PHX_F_MOMENTS) && !a->moments_dev)
+        return fail(c, PHX_ERR_INVALID, "PHX_F_MOMENTS without a moments buffer");
+    if (!std::isfinite(a->exposure) || a->exposure < 0 || !std::isfinite(a->pupil_margin) ||
+        a->pupil_margin < 0)
+        return fail(c, PHX_ERR_INVALID, "bad exposure or pupil margin");
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    phx::Launch L{};
+    L.seed = a->seed;
+    L.flags = a->flags;
+    L.src_begin = a->src_begin;
+    L.n_src = a->src_end - a->src_begin;
+    L.photon_begin = a->photon_begin;
+    L.exposure = a->exposure;
+    L.pupil_margin = a->pupil_margin;
+    L.image = a->image_dev;
+    L.stats = (unsigned long long*)a->stats_dev;
+    L.moments = a->moments_dev;
+    L.events = a->events_dev;
+    L.event_stride = a->event_stride;
+    if (a->photon_count > 0) {
+        L.uniform_count = a->photon_count;
+        if (a->photon_count > UINT64_MAX / (uint64_t)L.n_src)
+            return fail(c, PHX_ERR_INVALID, "photon total overflows");
+        L.total = a->photon_count * (uint64_t)L.n_src;
+    } else {
+        std::vector<uint64_t> pre(L.n_src + 1, 0);
+        for (int s = 0; s < L.n_src; ++s) {
+            const uint64_t n = c->src[a->src_begin + s].n_photons;
+            if (pre[s] > UINT64_MAX - n) return fail(c, PHX_ERR_INVALID, "photon total overflows");
+            pre[s + 1] = pre[s] + n;
+        }
+        L.total = pre[L.n_src];
+        if ((size_t)(L.n_src + 1) > c->prefix_cap) {
+            free_dev(c->d_prefix);
+            c->prefix_cap = 0;
+            hipError_t e = hipMalloc((void**)&c->d_prefix, (L.n_src + 1) * sizeof(uint64_t));
+            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "prefix table");
+            c->prefix_cap = L.n_src + 1;
+        }
+        // synchronous so that the host vector can go away
+        hipError_t e = hipStreamSynchronize(st);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_prefix, pre.data(), pre.size() * sizeof(uint64_t),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(c, e, "prefix upload");
+        L.prefix = c->d_prefix;
+    }
+    if (a->photon_begin > UINT64_MAX - (L.total ? L.total : 0))
+        return fail(c, PHX_ERR_INVALID, "photon index overflows");
+    if (a->flags & PHX_F_EVENTS) {
+        if (!a->events_dev || a->event_stride == 0)
+            return fail(c, PHX_ERR_INVALID, "PHX_F_EVENTS needs events_dev and event_stride > 0");
+        const uint64_t need = (L.total + a->event_stride - 1) / a->event_stride;
+        if (need > a->event_capacity)
+            return fail(c, PHX_ERR_CAPACITY, "events need %llu slots, capacity %llu",
+                        (unsigned long long)need, (unsigned long long)a->event_capacity);
+    }
+    phx_status r = upload_params(c, st);
+    if (r != PHX_OK) return r;
+    hipError_t e = phx::launch_trace(c->dparams, L, c->n_cu, st);
+    if (e != hipSuccess) return hip_fail(c, e, "trace kernel launch");
+    return PHX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal layout shared by the host API (phx_api.cpp) and the HIP kernels (phx_trace.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/phx.h"
+
+namespace phx {
+
+constexpr int kNZern = 12;  // Noll Z4..Z15
+
+// One surface as the kernels read it.  The element frame maps to the global frame by
+// g = R q + t (R row-major); `moved` = 0 means R = identity and t = (0, 0, z_vertex).
+struct DevSurface {
+    int32_t kind, medium, coating, moved;
+    int32_t asphere, zernike, pad0, pad1;
+    double R[9];
+    double t[3];
+    double c, kappa1;      // curvature, 1 + kappa
+    double alpha[8];       // alpha_3 .. alpha_10
+    double r_in, r_out;
+};
+
+struct DevSource {
+    double xi, eta, nz;
+    double lambda_lo, lambda_span, redshift1;
+    double sersic_n, sersic_bn, sersic_a, sersic_b, cos_pa, sin_pa;
+    int32_t kind, sed;
+    uint64_t n_photons;
+};
+
+// Everything the trace kernel reads that does not change between launches with the same loads.
+struct DevParams {
+    int32_t n_surf, nx, ny, n_layers;
+    int32_t n_scales, screen_n, n_coat, n_s;
+    int32_t n_lam, sed_k, has_glass, pad;
+    DevSurface surf[PHX_MAX_SURF];
+    double zern[kNZern];
+    double zern_inv_r;
+    double pupil_r_in, pupil_r_out;
+    double z_start, obsc_z, obsc_r;
+    double sell_b[3], sell_c[3];
+    double chip_x0, chip_y0, pixel;
+    double t_si, sigma_max;
+    // Rajkanan constants at the device temperature (section 2.4.2)
+    double eg[2], egd, absorb[2], emit[2];
+    // coatings: uniform grid in s = sin^2(theta) and wavelength
+    double s_step, lam0, dlam;
+    const float* coat;       // [n_coat][n_s][n_lam]
+    const float* coat_max;   // [n_coat][n_lam]: max over s of each wavelength column
+    // atmosphere
+    double height[PHX_MAX_LAYERS];
+    double wind[PHX_MAX_LAYERS][2];
+    double inv_pix[PHX_MAX_SCALES];
+    double lambda_ref;
+    const float2* grad;      // [L][S][N][N]
+    // sources
+    const DevSource* src;
+    const double* sed_cdf;   // [n_sed][sed_k + 1]
+    const double* sed_edges; // [sed_k + 1]
+};
+
+// Per-launch arguments.
+struct Launch {
+    uint32_t seed, flags;
+    int32_t src_begin, n_src;      // sources [src_begin, src_begin + n_src)
+    uint64_t photon_begin;
+    uint64_t uniform_count;        // > 0: every source traces this many photons
+    const uint64_t* prefix;        // else: exclusive prefix of per-source counts [n_src + 1]
+    uint64_t total;
+    double exposure, pupil_margin;
+    uint32_t* image;
+    unsigned long long* stats;
+    double* moments;
+    phx_event* events;
+    uint64_t event_stride;
+};
+
+hipError_t launch_trace(const DevParams* dparams, const Launch& L, int n_cu, hipStream_t stream);
+hipError_t launch_gradients(const float* opd, float2* grad, int n_layers, int n_scales, int n,
+                            const double* pixel, hipStream_t stream);
+
+}  // namespace phx

@@ -1,0 +1,294 @@
+"""Python binding of the C-ABI photon trace library (libphx.so, declared in include/phx.h).
+
+Argument marshalling only: every step of the trace runs in the library's HIP kernels.  PyTorch
+provides device memory and the stream.  Importing this module loads the library and fails
+loudly if it has not been built (``python -m paper_1504_06570_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphx.so")
+
+MAX_SURF, MAX_LAYERS, MAX_SCALES, N_THETA, N_STATUS = 16, 8, 4, 22, 10
+STAT_COLS = MAX_SURF + 1
+STAT_NEWTON = N_STATUS * STAT_COLS
+STAT_TRACED = STAT_NEWTON + 1
+STATS_LEN = STAT_TRACED + 1
+MOMENT_LEN = 6
+
+F_ATMOSPHERE, F_COATINGS, F_SILICON, F_DIFFUSION = 1, 2, 4, 8
+F_CULL, F_EVENTS, F_MOMENTS = 1 << 8, 1 << 9, 1 << 10
+STATUS = ["DETECTED", "OFF_CHIP", "VIGNETTED", "ABSORBED", "MISSED", "NONCONV", "TIR", "ESCAPED",
+          "OBSCURED", "CULLED"]
+DETECTED, OFF_CHIP, VIGNETTED, ABSORBED, MISSED, NONCONV, TIR, ESCAPED, OBSCURED, CULLED = range(10)
+
+
+class PhxError(RuntimeError):
+    pass
+
+
+class Surface(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("medium", C.c_int32), ("coating", C.c_int32),
+                ("group", C.c_int32), ("z_vertex", C.c_double), ("curvature", C.c_double),
+                ("conic", C.c_double), ("alpha", C.c_double * 8), ("r_inner", C.c_double),
+                ("r_outer", C.c_double)]
+
+
+class Prescription(C.Structure):
+    _fields_ = [("n_surfaces", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("pad", C.c_int32),
+                ("surf", Surface * MAX_SURF), ("pupil_r_inner", C.c_double),
+                ("pupil_r_outer", C.c_double), ("z_start", C.c_double),
+                ("obscuration_z", C.c_double), ("obscuration_r", C.c_double),
+                ("sellmeier_b", C.c_double * 3), ("sellmeier_c", C.c_double * 3),
+                ("chip_x0", C.c_double), ("chip_y0", C.c_double), ("pixel", C.c_double),
+                ("si_thickness", C.c_double), ("si_temperature", C.c_double),
+                ("sigma_max", C.c_double), ("group_pivot", (C.c_double * 3) * 3)]
+
+
+class Atmosphere(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("n_scales", C.c_int32), ("screen_n", C.c_int32),
+                ("pad", C.c_int32), ("height", C.c_double * MAX_LAYERS),
+                ("wind", (C.c_double * 2) * MAX_LAYERS), ("pixel", C.c_double * MAX_SCALES),
+                ("lambda_ref", C.c_double)]
+
+
+class Source(C.Structure):
+    _fields_ = [("xi", C.c_double), ("eta", C.c_double), ("kind", C.c_int32), ("sed", C.c_int32),
+                ("lambda_lo", C.c_double), ("lambda_hi", C.c_double), ("redshift", C.c_double),
+                ("sersic_n", C.c_double), ("sersic_bn", C.c_double), ("sersic_a", C.c_double),
+                ("sersic_b", C.c_double), ("sersic_pa", C.c_double), ("n_photons", C.c_uint64)]
+
+
+class TraceArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint32), ("flags", C.c_uint32), ("src_begin", C.c_int32),
+                ("src_end", C.c_int32), ("photon_begin", C.c_uint64), ("photon_count", C.c_uint64),
+                ("exposure", C.c_double), ("pupil_margin", C.c_double),
+                ("image_dev", C.c_void_p), ("stats_dev", C.c_void_p), ("moments_dev", C.c_void_p),
+                ("events_dev", C.c_void_p), ("event_stride", C.c_uint64),
+                ("event_capacity", C.c_uint64)]
+
+
+EVENT_DTYPE = np.dtype([("photon", np.uint64), ("source", np.int32), ("status", np.int32),
+                        ("surface", np.int32), ("pix_i", np.int32), ("pix_j", np.int32),
+                        ("newton", np.int32), ("x", np.float64), ("y", np.float64),
+                        ("z", np.float64), ("xe", np.float64), ("ye", np.float64),
+                        ("lam", np.float64)])
+assert EVENT_DTYPE.itemsize == 80
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PhxError(f"{LIB_PATH} is missing: build it with python -m paper_1504_06570_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.phx_version.restype = C.c_char_p
+        L.phx_create.argtypes = [C.c_int32, C.POINTER(C.c_void_p)]
+        L.phx_destroy.argtypes = [C.c_void_p]
+        L.phx_destroy.restype = None
+        L.phx_last_error.argtypes = [C.c_void_p]
+        L.phx_last_error.restype = C.c_char_p
+        L.phx_load_prescription.argtypes = [C.c_void_p, C.POINTER(Prescription)]
+        L.phx_set_perturbation.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32]
+        L.phx_load_coatings.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                        C.c_double, C.c_double, C.c_double]
+        L.phx_load_screens.argtypes = [C.c_void_p, C.POINTER(Atmosphere), C.c_void_p, C.c_int64,
+                                       C.c_void_p]
+        L.phx_load_sources.argtypes = [C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p,
+                                       C.c_void_p, C.c_int32, C.c_int32]
+        L.phx_trace.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
+        for f in ("phx_create", "phx_load_prescription", "phx_set_perturbation",
+                  "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace"):
+            getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def prescription_struct(p) -> Prescription:
+    P = Prescription()
+    P.n_surfaces = len(p.surfaces)
+    if P.n_surfaces > MAX_SURF:
+        raise PhxError("too many surfaces")
+    P.nx, P.ny = p.chip.nx, p.chip.ny
+    for k, s in enumerate(p.surfaces):
+        o = P.surf[k]
+        o.kind, o.medium, o.coating, o.group = s.kind, s.medium, s.coating, s.group
+        o.z_vertex, o.curvature, o.conic = s.z, s.curvature, s.conic
+        for i in range(8):
+            o.alpha[i] = s.alpha[i]
+        o.r_inner, o.r_outer = s.r_in, s.r_out
+    P.pupil_r_inner, P.pupil_r_outer, P.z_start = p.pupil_r_in, p.pupil_r_out, p.z_start
+    P.obscuration_z, P.obscuration_r = p.obscuration_z, p.obscuration_r
+    for i in range(3):
+        P.sellmeier_b[i] = p.glass_b[i]
+        P.sellmeier_c[i] = p.glass_c_um2[i]
+    P.chip_x0, P.chip_y0, P.pixel = p.chip.x0, p.chip.y0, p.chip.pixel
+    P.si_thickness, P.si_temperature, P.sigma_max = (p.silicon.thickness, p.silicon.temperature,
+                                                     p.silicon.sigma_max)
+    for g in range(3):
+        for i in range(3):
+            P.group_pivot[g][i] = p.group_pivot[g][i]
+    return P
+
+
+def sources_struct(S):
+    arr = (Source * len(S))()
+    for i in range(len(S)):
+        a = arr[i]
+        a.xi, a.eta = float(S.xi[i]), float(S.eta[i])
+        a.kind, a.sed = int(S.kind[i]), int(S.sed[i])
+        a.lambda_lo, a.lambda_hi, a.redshift = float(S.lam_lo[i]), float(S.lam_hi[i]), float(S.redshift[i])
+        a.sersic_n, a.sersic_bn = float(S.sersic_n[i]), float(S.sersic_bn[i])
+        a.sersic_a, a.sersic_b, a.sersic_pa = float(S.sersic_a[i]), float(S.sersic_b[i]), float(S.sersic_pa[i])
+        a.n_photons = int(S.n_photons[i])
+    return arr
+
+
+class Tracer:
+    """A library context on one GPU with a scene (paper_1504_06570_amd.scene) loaded."""
+
+    def __init__(self, scene, device: int = 0):
+        import torch
+        from .scene import coatings as coat_mod
+        self.L = lib()
+        self.scene = scene
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        rc = self.L.phx_create(device, C.byref(h))
+        if rc != 0:
+            raise PhxError(f"phx_create failed ({rc})")
+        self.ctx = h
+        self._check(self.L.phx_load_prescription(self.ctx, C.byref(prescription_struct(scene.prescription))))
+        self.set_perturbation(scene.perturbation)
+        if scene.coatings is not None:
+            ct = np.ascontiguousarray(scene.coatings, np.float32)
+            self._check(self.L.phx_load_coatings(self.ctx, ct.ctypes.data, ct.shape[0], ct.shape[1],
+                                                 ct.shape[2], coat_mod.S_MAX, coat_mod.LAM0,
+                                                 coat_mod.DLAM))
+        if scene.atmosphere is not None:
+            self.load_screens(scene.atmosphere)
+        self.load_sources(scene.sources, scene.sed)
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = self.L.phx_last_error(self.ctx).decode()
+            raise PhxError(f"phx error {rc}: {msg}")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.phx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_perturbation(self, theta):
+        th = np.ascontiguousarray(theta, np.float64)
+        self._check(self.L.phx_set_perturbation(self.ctx, th.ctypes.data_as(C.POINTER(C.c_double)),
+                                                th.shape[0]))
+
+    def load_screens(self, atm):
+        import torch
+        A = Atmosphere()
+        A.n_layers, A.n_scales, A.screen_n = atm.n_layers, atm.n_scales, atm.n
+        for i in range(atm.n_layers):
+            A.height[i] = atm.heights[i]
+            A.wind[i][0], A.wind[i][1] = atm.wind[i]
+        for s in range(atm.n_scales):
+            A.pixel[s] = atm.pixels[s]
+        A.lambda_ref = atm.lambda_ref
+        opd = torch.from_numpy(np.ascontiguousarray(atm.opd, np.float32)).to(self.device)
+        self._check(self.L.phx_load_screens(self.ctx, C.byref(A), opd.data_ptr(), opd.numel(),
+                                            _stream_handle()))
+        torch.cuda.current_stream().synchronize()
+        del opd
+
+    def load_sources(self, S, sed=None):
+        arr = sources_struct(S)
+        if sed is not None:
+            e = np.ascontiguousarray(sed.lam_edges, np.float64)
+            f = np.ascontiguousarray(sed.flux, np.float64)
+            self._check(self.L.phx_load_sources(self.ctx, arr, len(S), e.ctypes.data, f.ctypes.data,
+                                                f.shape[0], f.shape[1]))
+        else:
+            self._check(self.L.phx_load_sources(self.ctx, arr, len(S), None, None, 0, 0))
+        self.n_sources = len(S)
+
+    def new_image(self):
+        import torch
+        p = self.scene.prescription
+        return torch.zeros((p.chip.ny, p.chip.nx), dtype=torch.int32, device=self.device)
+
+    def trace(self, image=None, *, flags=None, seed=None, src_begin=0, src_end=None,
+              photon_begin=0, photon_count=0, stats=None, moments=None, event_stride=0,
+              events=None, stream=None, exposure=None):
+        """Enqueue one trace.  Returns (image, stats, moments, events) tensors (events raw bytes)."""
+        import torch
+        sc = self.scene
+        if image is None:
+            image = self.new_image()
+        if flags is None:
+            flags = int(sc.physics)
+        if event_stride:
+            flags |= F_EVENTS
+        if moments is not None:
+            flags |= F_MOMENTS
+        src_end = self.n_sources if src_end is None else src_end
+        a = TraceArgs()
+        a.seed = int(sc.seed if seed is None else seed) & 0xFFFFFFFF
+        a.flags = flags
+        a.src_begin, a.src_end = src_begin, src_end
+        a.photon_begin, a.photon_count = int(photon_begin), int(photon_count)
+        a.exposure = float(sc.exposure if exposure is None else exposure)
+        a.pupil_margin = float(sc.pupil_margin)
+        assert image.dtype == torch.int32 and image.is_contiguous()
+        a.image_dev = image.data_ptr()
+        a.stats_dev = stats.data_ptr() if stats is not None else None
+        a.moments_dev = moments.data_ptr() if moments is not None else None
+        if event_stride:
+            if photon_count:
+                total = photon_count * (src_end - src_begin)
+            else:
+                total = int(sc.sources.n_photons[src_begin:src_end].sum())
+            cap = (total + event_stride - 1) // event_stride
+            if events is None:
+                events = torch.zeros(cap * EVENT_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+            a.events_dev = events.data_ptr()
+            a.event_stride = event_stride
+            a.event_capacity = events.numel() // EVENT_DTYPE.itemsize
+        self._check(self.L.phx_trace(self.ctx, C.byref(a), _stream_handle(stream)))
+        return image, stats, moments, events
+
+    def new_stats(self):
+        import torch
+        return torch.zeros(STATS_LEN, dtype=torch.int64, device=self.device)
+
+    def new_moments(self):
+        import torch
+        return torch.zeros((self.n_sources, MOMENT_LEN), dtype=torch.float64, device=self.device)
+
+
+def events_to_numpy(events) -> np.ndarray:
+    return events.cpu().numpy().view(EVENT_DTYPE)
+
+
+def stats_table(stats) -> np.ndarray:
+    s = stats.cpu().numpy() if hasattr(stats, "cpu") else np.asarray(stats)
+    return s[:STAT_NEWTON].reshape(N_STATUS, STAT_COLS)

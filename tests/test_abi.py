@@ -1,0 +1,69 @@
+"""The C-ABI library loads on the CPU and exports every function include/phx.h declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "phx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(phx_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("phx_create", "phx_destroy", "phx_load_prescription", "phx_load_screens",
+              "phx_load_sources", "phx_trace", "phx_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1504_06570_amd import phx as P
+    L = P.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+        assert isinstance(getattr(L, n), ctypes._CFuncPtr)
+    assert P.lib().phx_version().startswith(b"phx")
+
+
+def test_struct_sizes_match_header_layout():
+    """The binding's ctypes structs have the header's sizes (checked against a host compile)."""
+    import subprocess
+    import tempfile
+    from paper_1504_06570_amd import phx as P
+    src = r"""
+#include <stdio.h>
+#include "phx.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(phx_surface), sizeof(phx_prescription),
+         sizeof(phx_atmosphere), sizeof(phx_source), sizeof(phx_event), sizeof(phx_trace_args),
+         offsetof(phx_trace_args, image_dev));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        exe = os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
+        got = [int(x) for x in subprocess.check_output([exe], text=True).split()]
+    want = [ctypes.sizeof(P.Surface), ctypes.sizeof(P.Prescription), ctypes.sizeof(P.Atmosphere),
+            ctypes.sizeof(P.Source), P.EVENT_DTYPE.itemsize, ctypes.sizeof(P.TraceArgs),
+            P.TraceArgs.image_dev.offset]
+    assert got == want
+
+
+def test_create_without_gpu_is_an_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1504_06570_amd import phx as P
+    h = ctypes.c_void_p()
+    assert P.lib().phx_create(0, ctypes.byref(h)) == -1
+    assert P.lib().phx_trace(None, None, None) == -1
+    assert P.lib().phx_last_error(None) == b"null context"
