@@ -1,0 +1,224 @@
+"""Benchmark: photons/s of the full atmosphere + optics + sensor photon trace on one MI355X.
+
+Workload (one step): one star at a random field position, 1e9 photons, seven frozen-flow von
+Karman layers (2048^2 screens at 1 m / 10 cm / 1 cm), the generated three-mirror telescope +
+camera with coatings, 100 um silicon with diffusion, a 4096^2 chip centred on the star.  Inputs
+are synthetic and resident on the GPU before timing; the image accumulates across steps.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photons/s (atm+optics+sensor) on 1 MI355X vs oracle; adjoint/forward cost ratio"
+PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1504_06570_amd", "csrc", "phx_trace.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "trace_kernel_full_1e9_pmc.json")
+
+# Algorithmic FP64 operation counts of the trace stages (add/sub/mul/div/sqrt/transcendental = 1,
+# fused multiply-add = 2), counted from the algorithm as written ("Roofline").
+FLOPS_GENERATE = 12          # uniform conversions, wavelength
+FLOPS_CULL_PER_COAT = 6      # pre-roll test per coated surface
+FLOPS_SOURCE = 45            # direction, time, pupil sample and sag
+FLOPS_LAYER = 112            # propagate, 3 scales x bilinear gradient pair, kick, renormalise
+FLOPS_SURFACE = 80           # transform, conic root, clip, normal, coating, reflect/refract
+FLOPS_NEWTON = 70            # one Newton step: point, sag + gradient with asphere terms
+FLOPS_SILICON = 65           # index, absorption, conversion, diffusion, pixel
+
+
+def algorithmic_flops(stats, n_generated, n_layers, n_surf, n_coated, culled_flag):
+    """FP64 operations the trace performs for this launch's photon fates (stats buffer)."""
+    import numpy as np
+    from paper_1504_06570_amd import phx
+    tab = phx.stats_table(stats).astype(np.float64)
+    traced = float(stats[phx.STAT_TRACED])
+    newton = float(stats[phx.STAT_NEWTON])
+    # photons that reached surface k = photons whose fate was decided at surface >= k
+    decided_at = tab.sum(axis=0)          # by column (surface + 1)
+    reach = [decided_at[k + 1:].sum() for k in range(n_surf)]
+    silicon = tab[[phx.DETECTED, phx.OFF_CHIP, phx.ESCAPED], n_surf].sum()
+    f = n_generated * FLOPS_GENERATE
+    if culled_flag:
+        f += n_generated * FLOPS_CULL_PER_COAT * n_coated
+    f += traced * (FLOPS_SOURCE + n_layers * FLOPS_LAYER)
+    f += sum(reach) * FLOPS_SURFACE + newton * FLOPS_NEWTON + silicon * FLOPS_SILICON
+    return f
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in (KERNEL_SRC, os.path.join(ROOT, "paper_1504_06570_amd", "csrc", "phx_internal.h")):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(n_launch_photons):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if
+    it is missing or was taken on a different kernel source."""
+    try:
+        d = json.load(open(PMC_SUMMARY))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash() or d.get("photons") != n_launch_photons:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scene, n_photons, threads):
+    import numpy as np
+    import oracle as O
+    orc = O.Oracle(scene)
+    img = np.zeros(orc.image_shape, np.uint32)
+    counts = np.array([n_photons], np.uint64)
+    t0 = time.perf_counter()
+    orc.trace_sources(counts=counts, image=img, events=False, threads=threads)
+    dt = time.perf_counter() - t0
+    return n_photons / dt, dt
+
+
+def copy_probe():
+    """A plain 1 GiB device copy, for calibrating the HBM byte counters."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": a.numel() * 4}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--photons", type=float, default=1e9)
+    ap.add_argument("--no-cull", action="store_true", help="time without the pre-roll only")
+    ap.add_argument("--cpu-sample", type=float, default=3e6)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the run without the pre-roll")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    import numpy as np
+    import torch
+    from paper_1504_06570_amd import phx
+    from paper_1504_06570_amd.scene import configs as C
+
+    n_ph = int(args.photons)
+    t_setup = time.perf_counter()
+    scene = C.full()
+    scene.sources.n_photons[:] = n_ph
+    tr = phx.Tracer(scene)
+    print(f"# setup {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+    base = int(scene.physics)
+    flags = base if args.no_cull else base | phx.F_CULL
+    n_surf = len(scene.prescription.surfaces)
+    n_coated = sum(1 for s in scene.prescription.surfaces if s.coating >= 0)
+    img = tr.new_image()
+    stats = tr.new_stats()
+    for _ in range(args.warmup):
+        tr.trace(img, flags=flags, stats=stats)
+    torch.cuda.synchronize()
+    stats.zero_()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        tr.trace(img, flags=flags, stats=stats)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = n_ph / (ms * 1e-3)
+    st = stats.cpu().numpy()
+    print(f"# timed {args.steps} steps: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    flops = algorithmic_flops(st, n_ph * args.steps, scene.atmosphere.n_layers, n_surf, n_coated,
+                              not args.no_cull) / args.steps
+    achieved = flops / (ms * 1e-3) / 1e12
+    tab = phx.stats_table(st) / args.steps
+    detected = float(tab[phx.DETECTED].sum())
+
+    extra = {}
+    if not args.no_cull and not args.no_compare:
+        # the same step without the pre-roll (every photon traced until its fate)
+        nc_img = tr.new_image()
+        tr.trace(nc_img, flags=base)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        tr.trace(nc_img, flags=base)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        nc_ms = e0.elapsed_time(e1)
+        extra["value_without_preroll"] = n_ph / (nc_ms * 1e-3)
+        extra["ms_per_step_without_preroll"] = nc_ms
+
+    cpu = None
+    if not args.skip_cpu:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        n_cpu = int(args.cpu_sample)
+        rate, dt = cpu_baseline(scene, n_cpu, threads)
+        cpu = {"value": rate, "unit": "photons/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n_cpu:.0e} photons of the same star, full physics, no pre-roll, "
+                         f"{dt:.1f} s on {threads} host threads"}
+        print(f"# cpu oracle {rate:.3e} photons/s ({dt:.1f}s)", file=sys.stderr, flush=True)
+
+    traffic = traffic_from_profiles(n_ph)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "photons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "full single-source trace: 1 star, 1e9 photons/step, 7 frozen-flow von "
+                        "Karman layers (3 x 2048^2 screens each), TMA+camera, coatings, silicon, "
+                        "diffusion, 4096^2 chip",
+            "photons_per_step": n_ph,
+            "preroll_cull": not args.no_cull,
+            "detected_per_step": detected,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": traffic,
+        },
+        "cpu_baseline": cpu,
+        "adjoint_forward_ratio": None,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

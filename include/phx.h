@@ -103,7 +103,8 @@ typedef struct {
 
 /* Optical prescription + focal plane (paper Table 1).  Surfaces are in travel order; the last
  * one must be the detector.  The chip is a rectangular device of nx x ny square pixels whose
- * pixel (0,0) starts at (chip_x0, chip_y0) in the detector's frame (section 2.4.1). */
+ * pixel (0,0) starts at (chip_x0, chip_y0) in the detector's frame (section 2.4.1); nx, ny are at
+ * most 32767. */
 typedef struct {
     int32_t n_surfaces, nx, ny, pad;
     phx_surface surf[PHX_MAX_SURF];

@@ -1,6 +1,7 @@
 // C ABI of the photon trace library (declarations and contracts in include/phx.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -26,14 +27,20 @@ struct phx_ctx_s {
     bool dirty = true;
     float* d_coat = nullptr;
     float* d_coat_max = nullptr;
-    float2* d_grad = nullptr;
+    float4* d_grad = nullptr;
     size_t grad_elems = 0;
     DevSource* d_src = nullptr;
     std::vector<phx_source> src;
+    std::vector<float> coat_max;   // host copy of the per-wavelength worst-case transmission
     double* d_cdf = nullptr;
     double* d_edges = nullptr;
     uint64_t* d_prefix = nullptr;
     size_t prefix_cap = 0;
+    uint32_t* d_survivors = nullptr;     // pre-roll survivors of one chunk
+    unsigned int* d_counts = nullptr;    // survivor count per chunk
+    uint64_t counts_cap = 0;
+    double* d_state = nullptr;           // start-plane state of one chunk [7][ws_chunk]
+    uint64_t ws_chunk = 0;
 };
 
 namespace {
@@ -83,10 +90,14 @@ void build_surfaces(phx_ctx c) {
         d.asphere = 0;
         for (int i = 0; i < 8; ++i) {
             d.alpha[i] = s.alpha[i];
-            if (s.alpha[i] != 0.0) d.asphere = 1;
+            if (s.alpha[i] != 0.0) d.asphere = (i & 1) ? 1 : 2;   // alpha[i] is alpha_{i+3}
         }
+        for (int i = 0; i < 8; i += 2)
+            if (s.alpha[i] != 0.0) d.asphere = 2;                  // an odd power is present
         d.r_in = s.r_inner;
         d.r_out = s.r_outer;
+        d.r_in2 = s.r_inner * s.r_inner;
+        d.r_out2 = s.r_outer * s.r_outer;
         double dx = 0, dy = 0, dz = 0, tx = 0, ty = 0;
         const double* P = p.group_pivot[0];
         if (s.group == 1 || s.group == 2) {
@@ -107,14 +118,54 @@ void build_surfaces(phx_ctx c) {
         }
         for (int i = 0; i < 9; ++i) d.R[i] = R[i];
     }
-    // Zernike deformation of surface 0
+    // Zernike deformation of surface 0 (Noll Z4..Z15, amplitudes theta[10..21]) expanded into the
+    // monomials u^a v^b of degree <= 4, ordered as the kernel's zernike_poly expects.
+    enum { C00, C10, C01, C20, C11, C02, C30, C21, C12, C03, C40, C31, C22, C13, C04 };
+    const double* a = c->theta + 10;
+    const double s3 = std::sqrt(3.0), s5 = std::sqrt(5.0), s6 = std::sqrt(6.0);
+    const double s8 = std::sqrt(8.0), s10 = std::sqrt(10.0);
+    double z[phx::kNZernPoly] = {0};
+    z[C00] += -s3 * a[0];  z[C20] += 2 * s3 * a[0];  z[C02] += 2 * s3 * a[0];           // Z4
+    z[C11] += 2 * s6 * a[1];                                                             // Z5
+    z[C20] += s6 * a[2];   z[C02] += -s6 * a[2];                                         // Z6
+    z[C21] += 3 * s8 * a[3]; z[C03] += 3 * s8 * a[3]; z[C01] += -2 * s8 * a[3];         // Z7
+    z[C30] += 3 * s8 * a[4]; z[C12] += 3 * s8 * a[4]; z[C10] += -2 * s8 * a[4];         // Z8
+    z[C21] += 3 * s8 * a[5]; z[C03] += -s8 * a[5];                                      // Z9
+    z[C30] += s8 * a[6];   z[C12] += -3 * s8 * a[6];                                     // Z10
+    z[C40] += 6 * s5 * a[7]; z[C22] += 12 * s5 * a[7]; z[C04] += 6 * s5 * a[7];         // Z11
+    z[C20] += -6 * s5 * a[7]; z[C02] += -6 * s5 * a[7]; z[C00] += s5 * a[7];
+    z[C40] += 4 * s10 * a[8]; z[C04] += -4 * s10 * a[8];                                // Z12
+    z[C20] += -3 * s10 * a[8]; z[C02] += 3 * s10 * a[8];
+    z[C31] += 8 * s10 * a[9]; z[C13] += 8 * s10 * a[9]; z[C11] += -6 * s10 * a[9];     // Z13
+    z[C40] += s10 * a[10]; z[C22] += -6 * s10 * a[10]; z[C04] += s10 * a[10];         // Z14
+    z[C31] += 4 * s10 * a[11]; z[C13] += -4 * s10 * a[11];                             // Z15
     bool any = false;
-    for (int j = 0; j < phx::kNZern; ++j) {
-        H.zern[j] = c->theta[10 + j];
-        any |= H.zern[j] != 0.0;
-    }
+    for (int j = 0; j < phx::kNZern; ++j) any |= a[j] != 0.0;
+    for (int j = 0; j < phx::kNZernPoly; ++j) H.zern[j] = z[j];
     H.surf[0].zernike = any ? 1 : 0;
     H.zern_inv_r = 1.0 / p.surf[0].r_outer;
+}
+
+// Pre-roll order: coated surfaces sorted by the mean (over wavelength) of their coating's
+// worst-case transmission, most selective first; ties keep the surface order.
+void build_cull_order(phx_ctx c) {
+    DevParams& H = c->host;
+    H.n_cull = 0;
+    if (!c->have_presc || !c->have_coat) return;
+    std::vector<std::pair<double, int>> v;
+    for (int k = 0; k < c->presc.n_surfaces; ++k) {
+        const int co = c->presc.surf[k].coating;
+        if (co < 0 || co >= H.n_coat) continue;
+        double m = 0.0;
+        for (int l = 0; l < H.n_lam; ++l) m += c->coat_max[(size_t)co * H.n_lam + l];
+        v.push_back({m / H.n_lam, k});
+    }
+    std::stable_sort(v.begin(), v.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+                         return a.first < b.first;
+                     });
+    for (size_t i = 0; i < v.size(); ++i) H.cull_order[i] = v[i].second;
+    H.n_cull = (int)v.size();
 }
 
 phx_status set_device(phx_ctx c) {
@@ -175,6 +226,9 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_cdf);
     free_dev(c->d_edges);
     free_dev(c->d_prefix);
+    free_dev(c->d_survivors);
+    free_dev(c->d_counts);
+    free_dev(c->d_state);
     delete c;
 }
 
@@ -202,7 +256,7 @@ phx_status phx_load_prescription(phx_ctx c, const phx_prescription* p) {
             !(s.r_outer > 0.0) || s.r_inner < 0.0 || s.r_inner >= s.r_outer)
             return fail(c, PHX_ERR_INVALID, "surface %d: non-finite value or bad aperture", k);
     }
-    if (p->nx <= 0 || p->ny <= 0 || (int64_t)p->nx * p->ny > (int64_t)1 << 31)
+    if (p->nx <= 0 || p->ny <= 0 || p->nx > 32767 || p->ny > 32767)
         return fail(c, PHX_ERR_INVALID, "chip %d x %d out of range", p->nx, p->ny);
     const double g[] = {p->pupil_r_inner, p->pupil_r_outer, p->z_start, p->obscuration_z,
                         p->obscuration_r, p->chip_x0, p->chip_y0, p->pixel, p->si_thickness,
@@ -247,6 +301,7 @@ phx_status phx_load_prescription(phx_ctx c, const phx_prescription* p) {
     }
     build_surfaces(c);
     c->have_presc = true;
+    build_cull_order(c);
     c->dirty = true;
     return PHX_OK;
 }
@@ -294,12 +349,14 @@ phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t 
     H.n_coat = n_coat;
     H.n_s = n_s;
     H.n_lam = n_lam;
-    H.s_step = s_max / (double)(n_s - 1);
+    H.inv_s_step = (double)(n_s - 1) / s_max;
     H.lam0 = lam0;
-    H.dlam = dlam;
+    H.inv_dlam = 1.0 / dlam;
     H.coat = c->d_coat;
     H.coat_max = c->d_coat_max;
+    c->coat_max = mx;
     c->have_coat = true;
+    build_cull_order(c);
     c->dirty = true;
     return PHX_OK;
 }
@@ -334,7 +391,7 @@ phx_status phx_load_screens(phx_ctx c, const phx_atmosphere* a, const float* opd
     if ((size_t)want != c->grad_elems) {
         free_dev(c->d_grad);
         c->grad_elems = 0;
-        hipError_t e = hipMalloc((void**)&c->d_grad, (size_t)want * sizeof(float2));
+        hipError_t e = hipMalloc((void**)&c->d_grad, (size_t)want * 2 * sizeof(float4));
         if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "gradient screens: %s",
                                          hipGetErrorString(e));
         c->grad_elems = (size_t)want;
@@ -490,6 +547,9 @@ phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
     L.moments = a->moments_dev;
     L.events = a->events_dev;
     L.event_stride = a->event_stride;
+    L.any_sersic = 0;
+    for (int s = a->src_begin; s < a->src_end; ++s) L.any_sersic |= c->src[s].kind == 1;
+    L.any_zernike = c->host.surf[0].zernike;
     if (a->photon_count > 0) {
         L.uniform_count = a->photon_count;
         if (a->photon_count > UINT64_MAX / (uint64_t)L.n_src)
@@ -528,9 +588,37 @@ phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
             return fail(c, PHX_ERR_CAPACITY, "events need %llu slots, capacity %llu",
                         (unsigned long long)need, (unsigned long long)a->event_capacity);
     }
+    // Workspace: chunk = min(kChunk, total rounded up to a power of two), allocated once and grown
+    uint64_t chunk = 1024;
+    while (chunk < L.total && chunk < phx::kChunk) chunk <<= 1;
+    if (chunk > c->ws_chunk) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        free_dev(c->d_survivors);
+        free_dev(c->d_state);
+        c->ws_chunk = 0;
+        e = hipMalloc((void**)&c->d_survivors, chunk * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, 7 * chunk * sizeof(double));
+        if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "trace workspace: %s",
+                                         hipGetErrorString(e));
+        c->ws_chunk = chunk;
+    }
+    chunk = c->ws_chunk;
+    const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
+    if (n_chunks > c->counts_cap) {
+        // the previous counters may still be in use by enqueued work
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        free_dev(c->d_counts);
+        c->counts_cap = 0;
+        e = hipMalloc((void**)&c->d_counts, n_chunks * sizeof(unsigned int));
+        if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "chunk counters");
+        c->counts_cap = n_chunks;
+    }
+    const phx::Workspace W{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk};
     phx_status r = upload_params(c, st);
     if (r != PHX_OK) return r;
-    hipError_t e = phx::launch_trace(c->dparams, L, c->n_cu, st);
+    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, st);
     if (e != hipSuccess) return hip_fail(c, e, "trace kernel launch");
     return PHX_OK;
 }

@@ -8,17 +8,19 @@
 namespace phx {
 
 constexpr int kNZern = 12;  // Noll Z4..Z15
+constexpr int kNZernPoly = 15;  // monomials u^a v^b, a + b <= 4
 
 // One surface as the kernels read it.  The element frame maps to the global frame by
 // g = R q + t (R row-major); `moved` = 0 means R = identity and t = (0, 0, z_vertex).
 struct DevSurface {
     int32_t kind, medium, coating, moved;
-    int32_t asphere, zernike, pad0, pad1;
+    int32_t asphere, zernike, pad0, pad1;  // asphere: 0 none, 1 even terms only, 2 general
     double R[9];
     double t[3];
     double c, kappa1;      // curvature, 1 + kappa
     double alpha[8];       // alpha_3 .. alpha_10
     double r_in, r_out;
+    double r_in2, r_out2;  // squared aperture radii
 };
 
 struct DevSource {
@@ -35,7 +37,7 @@ struct DevParams {
     int32_t n_scales, screen_n, n_coat, n_s;
     int32_t n_lam, sed_k, has_glass, pad;
     DevSurface surf[PHX_MAX_SURF];
-    double zern[kNZern];
+    double zern[kNZernPoly];   // Zernike deformation of surface 0 as monomial coefficients
     double zern_inv_r;
     double pupil_r_in, pupil_r_out;
     double z_start, obsc_z, obsc_r;
@@ -45,7 +47,9 @@ struct DevParams {
     // Rajkanan constants at the device temperature (section 2.4.2)
     double eg[2], egd, absorb[2], emit[2];
     // coatings: uniform grid in s = sin^2(theta) and wavelength
-    double s_step, lam0, dlam;
+    double inv_s_step, lam0, inv_dlam;
+    int32_t cull_order[PHX_MAX_SURF]; // coated surfaces, most selective coating first
+    int32_t n_cull;
     const float* coat;       // [n_coat][n_s][n_lam]
     const float* coat_max;   // [n_coat][n_lam]: max over s of each wavelength column
     // atmosphere
@@ -53,7 +57,9 @@ struct DevParams {
     double wind[PHX_MAX_LAYERS][2];
     double inv_pix[PHX_MAX_SCALES];
     double lambda_ref;
-    const float2* grad;      // [L][S][N][N]
+    const float4* grad;      // [L][S][N][N][2]: per cell (i, j) the gradients (g_x, g_y) at
+                             // (i, j), (i+1, j) then (i, j+1), (i+1, j+1): one 32-byte record
+                             // holds a bilinear footprint
     // sources
     const DevSource* src;
     const double* sed_cdf;   // [n_sed][sed_k + 1]
@@ -74,10 +80,25 @@ struct Launch {
     double* moments;
     phx_event* events;
     uint64_t event_stride;
+    int32_t any_sersic;            // an extended source is in the range
+    int32_t any_zernike;           // the first surface carries a Zernike deformation
 };
 
-hipError_t launch_trace(const DevParams* dparams, const Launch& L, int n_cu, hipStream_t stream);
-hipError_t launch_gradients(const float* opd, float2* grad, int n_layers, int n_scales, int n,
+// Scratch of the staged trace: the launch's photon range is processed in chunks; per chunk the
+// pre-roll survivors (offsets within the chunk), a survivor counter, and the start-plane state
+// of every traced photon (7 doubles each, structure of arrays).
+constexpr uint64_t kChunk = 1ull << 26;
+struct Workspace {
+    uint32_t* survivors;       // [chunk]
+    unsigned int* counts;      // [n_chunks]
+    uint64_t n_chunks;
+    double* state;             // [7][chunk]; null = run the fused single kernel
+    uint64_t chunk;
+};
+
+hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
+                        hipStream_t stream);
+hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, hipStream_t stream);
 
 }  // namespace phx

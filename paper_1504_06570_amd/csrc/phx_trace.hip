@@ -45,6 +45,27 @@ __device__ __forceinline__ double u01(uint32_t w) {
     return fma((double)w, 2.3283064365386963e-10, 1.1641532182693481e-10);
 }
 
+// Reciprocal and reciprocal square root for well-scaled operands (no zeros, infinities or
+// denormals): the hardware estimate refined by two Newton steps, about 1 ulp; used for the
+// continuous geometry (decisions that quantise, like the pixel index, keep IEEE division).
+__device__ __forceinline__ double rcp_fast(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_fast(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+// sqrt(x) for x >= 0 via the reciprocal square root (0 maps to 0).
+__device__ __forceinline__ double sqrt_fast(double x) { return x > 0.0 ? x * rsq_fast(x) : 0.0; }
+
 struct Rng {
     uint32_t k0, k1, lo, hi;
     __device__ uint4 block(uint32_t b, uint32_t stream = 0) const {
@@ -91,62 +112,48 @@ __device__ __forceinline__ double absorption(const DevParams& P, double lam) {
 // ---------------------------------------------------------------------------------------------
 // Surfaces.
 
-// Noll Z4..Z15 on the unit disk and their gradients; z[] are the amplitudes.
-__device__ void zernike_sum(const double* z, double u, double v, double& s, double& du,
-                            double& dv) {
-    const double r2 = u * u + v * v;
-    const double s3 = 1.7320508075688772, s6 = 2.449489742783178, s8 = 2.8284271247461903;
-    const double s5 = 2.23606797749979, s10 = 3.1622776601683795;
-    const double uu = u * u, vv = v * v;
-    s = 0.0; du = 0.0; dv = 0.0;
-    // Z4
-    s += z[0] * s3 * (2.0 * r2 - 1.0);  du += z[0] * s3 * 4.0 * u;  dv += z[0] * s3 * 4.0 * v;
-    // Z5, Z6
-    s += z[1] * s6 * 2.0 * u * v;       du += z[1] * s6 * 2.0 * v;  dv += z[1] * s6 * 2.0 * u;
-    s += z[2] * s6 * (uu - vv);         du += z[2] * s6 * 2.0 * u;  dv -= z[2] * s6 * 2.0 * v;
-    // Z7, Z8
-    s += z[3] * s8 * (3.0 * r2 - 2.0) * v;
-    du += z[3] * s8 * 6.0 * u * v;      dv += z[3] * s8 * (3.0 * uu + 9.0 * vv - 2.0);
-    s += z[4] * s8 * (3.0 * r2 - 2.0) * u;
-    du += z[4] * s8 * (9.0 * uu + 3.0 * vv - 2.0);  dv += z[4] * s8 * 6.0 * u * v;
-    // Z9, Z10
-    s += z[5] * s8 * (3.0 * uu * v - vv * v);
-    du += z[5] * s8 * 6.0 * u * v;      dv += z[5] * s8 * (3.0 * uu - 3.0 * vv);
-    s += z[6] * s8 * (uu * u - 3.0 * u * vv);
-    du += z[6] * s8 * (3.0 * uu - 3.0 * vv);  dv -= z[6] * s8 * 6.0 * u * v;
-    // Z11
-    s += z[7] * s5 * (6.0 * r2 * r2 - 6.0 * r2 + 1.0);
-    du += z[7] * s5 * (24.0 * r2 - 12.0) * u;  dv += z[7] * s5 * (24.0 * r2 - 12.0) * v;
-    // Z12, Z13
-    const double w = 4.0 * r2 - 3.0;
-    s += z[8] * s10 * w * (uu - vv);
-    du += z[8] * s10 * (8.0 * u * (uu - vv) + 2.0 * w * u);
-    dv += z[8] * s10 * (8.0 * v * (uu - vv) - 2.0 * w * v);
-    s += z[9] * s10 * w * 2.0 * u * v;
-    du += z[9] * s10 * (16.0 * uu * v + 2.0 * w * v);
-    dv += z[9] * s10 * (16.0 * u * vv + 2.0 * w * u);
-    // Z14, Z15
-    s += z[10] * s10 * (uu * uu - 6.0 * uu * vv + vv * vv);
-    du += z[10] * s10 * (4.0 * uu * u - 12.0 * u * vv);
-    dv += z[10] * s10 * (4.0 * vv * v - 12.0 * uu * v);
-    s += z[11] * s10 * (4.0 * uu * u * v - 4.0 * u * vv * v);
-    du += z[11] * s10 * (12.0 * uu * v - 4.0 * vv * v);
-    dv += z[11] * s10 * (4.0 * uu * u - 12.0 * u * vv);
+// Zernike deformation as a bivariate polynomial of degree 4 in (u, v) = (x, y)/R: the host
+// expands the Noll Z4..Z15 amplitudes into monomial coefficients c[] ordered (0,0) (1,0) (0,1)
+// (2,0) (1,1) (0,2) (3,0) (2,1) (1,2) (0,3) (4,0) (3,1) (2,2) (1,3) (0,4).  Returns the value and
+// the partial derivatives in u and v (Horner in u within each power of v).
+__device__ __forceinline__ void zernike_poly(const double* c, double u, double v, double& s,
+                                             double& du, double& dv) {
+    const double p0 = c[0] + u * (c[1] + u * (c[3] + u * (c[6] + u * c[10])));
+    const double p1 = c[2] + u * (c[4] + u * (c[7] + u * c[11]));
+    const double p2 = c[5] + u * (c[8] + u * c[12]);
+    const double p3 = c[9] + u * c[13];
+    const double p4 = c[14];
+    s = p0 + v * (p1 + v * (p2 + v * (p3 + v * p4)));
+    const double q0 = c[1] + u * (2.0 * c[3] + u * (3.0 * c[6] + u * 4.0 * c[10]));
+    const double q1 = c[4] + u * (2.0 * c[7] + u * 3.0 * c[11]);
+    const double q2 = c[8] + u * 2.0 * c[12];
+    const double q3 = c[13];
+    du = q0 + v * (q1 + v * (q2 + v * q3));
+    dv = p1 + v * (2.0 * p2 + v * (3.0 * p3 + v * 4.0 * p4));
 }
 
 // Sag S(x, y) and g with (dS/dx, dS/dy) = (x g, y g) + zernike gradient.  Returns false outside
 // the conic's domain.
+template <bool ZERN>
 __device__ __forceinline__ bool sag(const DevParams& P, const DevSurface& s, double x, double y,
                                     double& S, double& gx, double& gy) {
     const double r2 = x * x + y * y;
     const double arg = 1.0 - s.kappa1 * s.c * s.c * r2;
     if (arg < 0.0) return false;
-    const double root = sqrt(arg);
-    S = s.c * r2 / (1.0 + root);
-    double g = s.c / root;
-    if (s.asphere) {
-        const double r = sqrt(r2);
-        // sum alpha_i r^i and sum i alpha_i r^(i-2), i = 3..10
+    // conic: S = c r^2 / (1 + root), dS/dr / r = c / root, root = sqrt(arg); one reciprocal
+    // square root and one reciprocal
+    const double inv_root = rsq_fast(arg);
+    const double root = arg * inv_root;
+    S = s.c * r2 * rcp_fast(1.0 + root);
+    double g = s.c * inv_root;
+    if (s.asphere == 1) {
+        // even terms only: Horner in r^2
+        const double* a = s.alpha;
+        S += r2 * r2 * (a[1] + r2 * (a[3] + r2 * (a[5] + r2 * a[7])));
+        g += r2 * (4.0 * a[1] + r2 * (6.0 * a[3] + r2 * (8.0 * a[5] + r2 * 10.0 * a[7])));
+    } else if (s.asphere == 2) {
+        // general: sum alpha_i r^i and sum i alpha_i r^(i-2), i = 3..10
+        const double r = sqrt_fast(r2);
         double pw = r;          // r^(i-2) for i = 3
         double acc_s = 0.0, acc_g = 0.0;
 #pragma unroll
@@ -161,9 +168,9 @@ __device__ __forceinline__ bool sag(const DevParams& P, const DevSurface& s, dou
     }
     gx = x * g;
     gy = y * g;
-    if (s.zernike) {
+    if (ZERN && s.zernike) {
         double zs, zu, zv;
-        zernike_sum(P.zern, x * P.zern_inv_r, y * P.zern_inv_r, zs, zu, zv);
+        zernike_poly(P.zern, x * P.zern_inv_r, y * P.zern_inv_r, zs, zu, zv);
         S += zs;
         gx += zu * P.zern_inv_r;
         gy += zv * P.zern_inv_r;
@@ -174,6 +181,7 @@ __device__ __forceinline__ bool sag(const DevParams& P, const DevSurface& s, dou
 // Intersection of the ray q + l d with the surface: exact conic root, then Newton on
 // f(l) = q_z + l d_z - S(q_x + l d_x, q_y + l d_y).  Returns 0 or a status; gx, gy receive the
 // sag gradient at the last evaluation.
+template <bool ZERN>
 __device__ int intersect(const DevParams& P, const DevSurface& s, const double q[3],
                          const double d[3], double& l, double& gx, double& gy, int& iters) {
     const double A = s.c * (d[0] * d[0] + d[1] * d[1] + s.kappa1 * d[2] * d[2]);
@@ -181,17 +189,18 @@ __device__ int intersect(const DevParams& P, const DevSurface& s, const double q
     const double C = s.c * (q[0] * q[0] + q[1] * q[1] + s.kappa1 * q[2] * q[2]) - 2.0 * q[2];
     const double disc = B * B - A * C;
     if (disc < 0.0) return PHX_MISSED;
-    const double sq = sqrt(disc);
+    const double sq = sqrt_fast(disc);
     const double den = B >= 0.0 ? B + sq : B - sq;
     if (den == 0.0) return PHX_MISSED;
-    l = -C / den;
+    l = -C * rcp_fast(den);
+#pragma unroll 1
     for (int it = 1; it <= kNewtonMax; ++it) {
         const double x = q[0] + l * d[0], y = q[1] + l * d[1], z = q[2] + l * d[2];
         double S;
-        if (!sag(P, s, x, y, S, gx, gy)) return PHX_MISSED;
+        if (!sag<ZERN>(P, s, x, y, S, gx, gy)) return PHX_MISSED;
         const double fp = d[2] - (gx * d[0] + gy * d[1]);
         if (fp == 0.0) return PHX_NONCONV;
-        const double dl = (z - S) / fp;
+        const double dl = (z - S) * rcp_fast(fp);
         l -= dl;
         iters += 1;
         if (fabs(dl) <= kNewtonTol) return 0;
@@ -199,43 +208,51 @@ __device__ int intersect(const DevParams& P, const DevSurface& s, const double q
     return PHX_NONCONV;
 }
 
-__device__ __forceinline__ double coating(const DevParams& P, int c, double s, double lam) {
-    const float* t = P.coat + (size_t)c * P.n_s * P.n_lam;
-    double fs = s / P.s_step;
-    double fl = (lam - P.lam0) / P.dlam;
-    fs = fmin(fmax(fs, 0.0), (double)(P.n_s - 1));
+// Position of a wavelength on the coating tables' uniform wavelength axis (clamped at the ends):
+// column il and weight b of column il + 1.  Computed once per photon.
+struct LamCol {
+    int il;
+    double b;
+};
+__device__ __forceinline__ LamCol lambda_column(const DevParams& P, double lam) {
+    double fl = (lam - P.lam0) * P.inv_dlam;
     fl = fmin(fmax(fl, 0.0), (double)(P.n_lam - 1));
-    int is = min((int)floor(fs), P.n_s - 2);
-    int il = min((int)floor(fl), P.n_lam - 2);
-    const double a = fs - is, b = fl - il;
-    const float* r0 = t + (size_t)is * P.n_lam + il;
+    const int il = min((int)floor(fl), P.n_lam - 2);
+    return LamCol{il, fl - il};
+}
+
+// Coating transmission (section 2.4.2): bilinear in s = sin^2(incidence) and wavelength.
+__device__ __forceinline__ double coating(const DevParams& P, int c, double s, const LamCol& lc) {
+    double fs = s * P.inv_s_step;
+    fs = fmin(fmax(fs, 0.0), (double)(P.n_s - 1));
+    const int is = min((int)floor(fs), P.n_s - 2);
+    const double a = fs - is, b = lc.b;
+    const float* r0 = P.coat + ((size_t)c * P.n_s + is) * P.n_lam + lc.il;
     const float* r1 = r0 + P.n_lam;
     return (1.0 - a) * ((1.0 - b) * (double)r0[0] + b * (double)r0[1]) +
            a * ((1.0 - b) * (double)r1[0] + b * (double)r1[1]);
 }
 
-// Upper bound of a coating's transmission over all angles at wavelength lam (pre-roll).
-__device__ __forceinline__ double coating_max(const DevParams& P, int c, double lam) {
-    double fl = (lam - P.lam0) / P.dlam;
-    fl = fmin(fmax(fl, 0.0), (double)(P.n_lam - 1));
-    const int il = min((int)floor(fl), P.n_lam - 2);
-    const float* m = P.coat_max + (size_t)c * P.n_lam + il;
+// Upper bound of a coating's transmission over all angles at the photon's wavelength (pre-roll).
+__device__ __forceinline__ double coating_max(const DevParams& P, int c, const LamCol& lc) {
+    const float* m = P.coat_max + (size_t)c * P.n_lam + lc.il;
     return fmax((double)m[0], (double)m[1]);
 }
 
-__device__ __forceinline__ void screen_tap(const float2* g, int64_t N, double xs, double ys,
+// Bilinear interpolation of one gradient screen at screen-pixel coordinates (xs, ys): one
+// 32-byte record per cell holds the four corner gradients.
+__device__ __forceinline__ void screen_tap(const float4* g, int64_t N, double xs, double ys,
                                            double& ax, double& ay) {
     const double fx = floor(xs), fy = floor(ys);
     const double a = xs - fx, b = ys - fy;
     const int64_t m = N - 1;
     const int64_t i0 = (int64_t)fx & m, j0 = (int64_t)fy & m;
-    const int64_t i1 = (i0 + 1) & m, j1 = (j0 + 1) & m;
-    const float2 v00 = g[j0 * N + i0], v10 = g[j0 * N + i1];
-    const float2 v01 = g[j1 * N + i0], v11 = g[j1 * N + i1];
-    ax = (1.0 - b) * ((1.0 - a) * (double)v00.x + a * (double)v10.x) +
-         b * ((1.0 - a) * (double)v01.x + a * (double)v11.x);
-    ay = (1.0 - b) * ((1.0 - a) * (double)v00.y + a * (double)v10.y) +
-         b * ((1.0 - a) * (double)v01.y + a * (double)v11.y);
+    const float4* rec = g + 2 * (j0 * N + i0);
+    const float4 lo = rec[0], hi = rec[1];   // (i,j) (i+1,j) | (i,j+1) (i+1,j+1)
+    ax = (1.0 - b) * ((1.0 - a) * (double)lo.x + a * (double)lo.z) +
+         b * ((1.0 - a) * (double)hi.x + a * (double)hi.z);
+    ay = (1.0 - b) * ((1.0 - a) * (double)lo.y + a * (double)lo.w) +
+         b * ((1.0 - a) * (double)hi.y + a * (double)hi.w);
 }
 
 __device__ __forceinline__ void normalise(double n[3]) {
@@ -247,10 +264,11 @@ __device__ __forceinline__ void normalise(double n[3]) {
 __device__ double gamma_sample(const Rng& rng, double shape) {
     const double a = shape < 1.0 ? shape + 1.0 : shape;
     const double dd = a - 1.0 / 3.0, cc = 1.0 / sqrt(9.0 * dd);
+#pragma unroll 1
     for (uint32_t t = 0; t < 64; ++t) {
         const uint4 w = rng.block(t, 1);
         const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z);
-        const double x = sqrt(-2.0 * log(u0)) * cos(kTwoPi * u1);
+        const double x = sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
         double v = 1.0 + cc * x;
         if (v <= 0.0) continue;
         v = v * v * v;
@@ -259,11 +277,59 @@ __device__ double gamma_sample(const Rng& rng, double shape) {
         if (!accept) accept = log(u2) < 0.5 * x2 + dd * (1.0 - v + log(v));
         if (accept) {
             double g = dd * v;
-            if (shape < 1.0) g *= pow(u01(w.w), 1.0 / shape);
+            if (shape < 1.0) g *= exp(log(u01(w.w)) / shape);
             return g;
         }
     }
     return shape;
+}
+
+// Wavelength (section 2.2): flat photon spectrum, or the SED's photon CDF (first bin k with
+// CDF[k+1] > u) blurred uniformly across the bin; then (1 + z).
+__device__ __forceinline__ double wavelength(const DevParams& P, const DevSource& src,
+                                             const uint4& w0, const uint4& w1) {
+    double lam;
+    if (src.sed < 0) {
+        lam = src.lambda_lo + u01(w0.w) * src.lambda_span;
+    } else {
+        const double* cdf = P.sed_cdf + (size_t)src.sed * (P.sed_k + 1);
+        const double u = u01(w0.w);
+        int lo = 0, hi = P.sed_k - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cdf[mid + 1] > u) hi = mid; else lo = mid + 1;
+        }
+        lam = P.sed_edges[lo] + u01(w1.x) * (P.sed_edges[lo + 1] - P.sed_edges[lo]);
+    }
+    return lam * src.redshift1;
+}
+
+// Pre-roll test (section 3.2): true when a coated surface's roulette draw exceeds the largest
+// transmission that coating has at this wavelength for any angle, so the photon cannot survive.
+__device__ bool preroll_culls(const DevParams& P, const Launch& L, int si, uint64_t idx,
+                              double& lam) {
+    const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+    const uint4 w0 = rng.block(0);
+    const DevSource& src = P.src[si];
+    uint4 w1 = make_uint4(0, 0, 0, 0);
+    if (src.sed >= 0) w1 = rng.block(1);
+    lam = wavelength(P, src, w0, w1);
+    if (!((L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS))) return false;
+    // coated surfaces in order of decreasing selectivity, so most culled photons need one test
+    const LamCol lc = lambda_column(P, lam);
+    int blk = -1;
+    uint4 w = make_uint4(0, 0, 0, 0);
+    for (int j = 0; j < P.n_cull; ++j) {
+        const int k = P.cull_order[j];
+        if (2 + (k >> 2) != blk) {
+            blk = 2 + (k >> 2);
+            w = rng.block(blk);
+        }
+        const int m = k & 3;
+        const uint32_t wk = m == 0 ? w.x : (m == 1 ? w.y : (m == 2 ? w.z : w.w));
+        if (u01(wk) > coating_max(P, P.surf[k].coating, lc) + 1e-12) return true;
+    }
+    return false;
 }
 
 struct Outcome {
@@ -273,60 +339,29 @@ struct Outcome {
 };
 
 // The whole per-photon path.  `culled` photons return PHX_CULLED without being traced.
-__device__ Outcome trace_photon(const DevParams& P, const Launch& L, int si, uint64_t idx) {
+// Photon state at the start plane above the optics.
+struct Front {
+    double p[3], n[3], lam;
+};
+
+// Sky sampling (sections 2.2, 2.2.1) and the atmosphere (sections 2.3.1-2.3.2), ending on the
+// start plane above every optic.
+template <bool SERSIC>
+__device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64_t idx, Front& f) {
     const DevSource& src = P.src[si];
-    Outcome o;
-    o.status = PHX_MISSED; o.surface = -1; o.newton = 0; o.pix_i = -1; o.pix_j = -1;
-    o.x = o.y = o.z = o.xe = o.ye = 0.0;
     const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
     const uint4 w0 = rng.block(0);
-    const uint4 w1 = rng.block(1);
-
-    // wavelength (section 2.2): flat photon spectrum or tabulated SED CDF + blur in the bin
-    double lam;
-    if (src.sed < 0) {
-        lam = src.lambda_lo + u01(w0.w) * src.lambda_span;
-    } else {
-        const double* cdf = P.sed_cdf + (size_t)src.sed * (P.sed_k + 1);
-        const double u = u01(w0.w);
-        int lo = 0, hi = P.sed_k - 1;   // smallest k in [0, K-1] with cdf[k+1] > u
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (cdf[mid + 1] > u) hi = mid; else lo = mid + 1;
-        }
-        lam = P.sed_edges[lo] + u01(w1.x) * (P.sed_edges[lo + 1] - P.sed_edges[lo]);
-    }
-    lam = lam * src.redshift1;
-    o.lam = lam;
-
-    // pre-roll (section 3.2): a photon whose roulette draw exceeds the worst-case transmission of
-    // a coated surface cannot be detected
-    if ((L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS)) {
-        for (int b = 0; b * 4 < P.n_surf; ++b) {
-            bool any = false;
-            for (int k = 4 * b; k < min(4 * b + 4, P.n_surf); ++k) any |= P.surf[k].coating >= 0;
-            if (!any) continue;
-            const uint4 w = rng.block(2 + b);
-            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-            for (int k = 4 * b; k < min(4 * b + 4, P.n_surf); ++k) {
-                const int c = P.surf[k].coating;
-                if (c < 0) continue;
-                if (u01(ws[k & 3]) > coating_max(P, c, lam) + 1e-12) {
-                    o.status = PHX_CULLED;
-                    o.surface = -1;
-                    return o;
-                }
-            }
-        }
-    }
+    uint4 w1 = make_uint4(0, 0, 0, 0);
+    if (src.sed >= 0 || (SERSIC && src.kind == 1)) w1 = rng.block(1);
+    const double lam = wavelength(P, src, w0, w1);
 
     // direction (section 2.2) and extended-source perturbation (section 2.2.1)
     double n[3] = {src.xi, src.eta, src.nz};
-    if (src.kind == 1) {
+    if (SERSIC && src.kind == 1) {
         const double g = gamma_sample(rng, 2.0 * src.sersic_n);
-        const double rr = pow(g / src.sersic_bn, src.sersic_n);
+        const double rr = exp(src.sersic_n * log(g / src.sersic_bn));
         double sp, cp;
-        sincos(kTwoPi * u01(w1.y), &sp, &cp);
+        sincospi(2.0 * u01(w1.y), &sp, &cp);
         const double dmaj = src.sersic_a * rr * cp, dmin = src.sersic_b * rr * sp;
         n[0] += dmaj * src.cos_pa - dmin * src.sin_pa;
         n[1] += dmaj * src.sin_pa + dmin * src.cos_pa;
@@ -341,7 +376,7 @@ __device__ Outcome trace_photon(const DevParams& P, const Launch& L, int si, uin
         const double ri = fmax(P.pupil_r_in - L.pupil_margin, 0.0);
         const double r = sqrt(u01(w0.x) * (ro * ro - ri * ri) + ri * ri);
         double sphi, cphi;
-        sincos(kTwoPi * u01(w0.y), &sphi, &cphi);
+        sincospi(2.0 * u01(w0.y), &sphi, &cphi);
         p[0] = r * cphi;
         p[1] = r * sphi;
         const DevSurface& s0 = P.surf[0];
@@ -361,8 +396,9 @@ __device__ Outcome trace_photon(const DevParams& P, const Launch& L, int si, uin
     // atmosphere (sections 2.3.1-2.3.2): move up to the highest layer, then down layer by layer,
     // deflecting by the wind-shifted screen gradients scaled by (lambda/lambda_ref)^(-1/5)
     if ((L.flags & PHX_F_ATMOSPHERE) && P.n_layers > 0) {
-        const double kick = pow(lam / P.lambda_ref, -0.2);
+        const double kick = exp(-0.2 * log(lam / P.lambda_ref));
         const int64_t N = P.screen_n;
+#pragma unroll 1
         for (int i = P.n_layers - 1; i >= 0; --i) {
             const double h = P.height[i];
             const double l = (h - p[2]) / n[2];
@@ -372,8 +408,9 @@ __device__ Outcome trace_photon(const DevParams& P, const Launch& L, int si, uin
             const double sx = p[0] - P.wind[i][0] * t;
             const double sy = p[1] - P.wind[i][1] * t;
             double gx = 0.0, gy = 0.0;
+#pragma unroll 1
             for (int s = 0; s < P.n_scales; ++s) {
-                const float2* g = P.grad + ((size_t)(i * P.n_scales + s)) * N * N;
+                const float4* g = P.grad + ((size_t)(i * P.n_scales + s)) * N * N * 2;
                 double ax, ay;
                 screen_tap(g, N, sx * P.inv_pix[s], sy * P.inv_pix[s], ax, ay);
                 gx += ax;
@@ -390,132 +427,206 @@ __device__ Outcome trace_photon(const DevParams& P, const Launch& L, int si, uin
         p[1] += n[1] * l;
         p[2] = P.z_start;
     }
+    f.p[0] = p[0]; f.p[1] = p[1]; f.p[2] = p[2];
+    f.n[0] = n[0]; f.n[1] = n[1]; f.n[2] = n[2];
+    f.lam = lam;
+}
+
+// Silicon (sections 2.4.2-2.4.3): conversion after a path of mean free path x Exp(1) along the
+// refracted direction d; escape if deeper than the silicon; Gaussian diffusion with sigma
+// proportional to the drift distance to the collecting surface.  Moves (xc, yc) from the landing
+// point to the electron position; returns true if the photon escapes.  Kept out of line: it runs
+// once per photon and inlining it raises the register count of the whole optics loop.
+__device__ __noinline__ bool sensor_stage(const DevParams& P, const Launch& L, const Rng& rng,
+                                          double lam, const double* d, double& xc, double& yc) {
+    if (L.flags & PHX_F_SILICON) {
+        const double alpha = absorption(P, lam);
+        const double L_conv = alpha > 0.0 ? -log(u01(rng.block(1).z)) / alpha : INFINITY;
+        const double depth = L_conv * fabs(d[2]);
+        if (!(depth <= P.t_si)) return true;
+        xc += d[0] * L_conv;
+        yc += d[1] * L_conv;
+        if (L.flags & PHX_F_DIFFUSION) {
+            const uint4 wd = rng.block(6);
+            const double sigma = P.sigma_max * (P.t_si - depth) / P.t_si;
+            const double rad = sqrt(-2.0 * log(u01(wd.x)));
+            double sa, ca;
+            sincospi(2.0 * u01(wd.y), &sa, &ca);
+            xc += sigma * rad * ca;
+            yc += sigma * rad * sa;
+        }
+    }
+    return false;
+}
+
+// Central obscuration, the surfaces (sections 2.4.1-2.4.2), silicon (sections 2.4.2-2.4.3) and
+// the pixel, from the start-plane state.
+struct Hit {
+    double q[3], d[3], N[3];
+    double dn;
+};
+
+// Transform into surface k's frame, intersect, clip to the clear aperture, take the normal and
+// play the coating roulette (sections 2.4.1-2.4.2).  Returns 0 to continue or the photon's fate.
+template <bool ZERN>
+__device__ __forceinline__ int hit_surface(const DevParams& P, const Launch& L, const Rng& rng,
+                                           int k, const double p[3], const double n[3],
+                                           const LamCol& lc, uint4& wc, int& wc_block, Hit& h,
+                                           int& newton) {
+    const DevSurface& s = P.surf[k];
+    if (s.moved) {
+        const double r0 = p[0] - s.t[0], r1 = p[1] - s.t[1], r2 = p[2] - s.t[2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            h.q[i] = s.R[i] * r0 + s.R[3 + i] * r1 + s.R[6 + i] * r2;
+            h.d[i] = s.R[i] * n[0] + s.R[3 + i] * n[1] + s.R[6 + i] * n[2];
+        }
+    } else {
+        h.q[0] = p[0]; h.q[1] = p[1]; h.q[2] = p[2] - s.t[2];
+        h.d[0] = n[0]; h.d[1] = n[1]; h.d[2] = n[2];
+    }
+    double l, gx = 0.0, gy = 0.0;
+    int st = intersect<ZERN>(P, s, h.q, h.d, l, gx, gy, newton);
+    if (st == 0 && !(l > 0.0)) st = PHX_MISSED;
+    if (st != 0) return st;
+    h.q[0] += h.d[0] * l; h.q[1] += h.d[1] * l; h.q[2] += h.d[2] * l;
+    const double rq2 = h.q[0] * h.q[0] + h.q[1] * h.q[1];
+    if (rq2 < s.r_in2 || rq2 > s.r_out2) return PHX_VIGNETTED;
+    const double inv = rsq_fast(gx * gx + gy * gy + 1.0);
+    h.N[0] = -gx * inv; h.N[1] = -gy * inv; h.N[2] = inv;
+    h.dn = h.d[0] * h.N[0] + h.d[1] * h.N[1] + h.d[2] * h.N[2];
+    if (h.dn > 0.0) { h.N[0] = -h.N[0]; h.N[1] = -h.N[1]; h.N[2] = -h.N[2]; h.dn = -h.dn; }
+    if ((L.flags & PHX_F_COATINGS) && s.coating >= 0) {
+        const int blk = 2 + (k >> 2);
+        if (blk != wc_block) { wc = rng.block(blk); wc_block = blk; }
+        const int j = k & 3;
+        const uint32_t w = j == 0 ? wc.x : (j == 1 ? wc.y : (j == 2 ? wc.z : wc.w));
+        const double T = coating(P, s.coating, 1.0 - h.dn * h.dn, lc);
+        if (!(u01(w) < T)) return PHX_ABSORBED;
+    }
+    return 0;
+}
+
+// Refraction by the vector form of Snell's law (section 2.4.2); false on total internal
+// reflection.
+__device__ __forceinline__ bool refract(Hit& h, double mu) {
+    const double cosi = -h.dn;
+    const double kk = 1.0 - mu * mu * (1.0 - cosi * cosi);
+    if (kk < 0.0) return false;
+    const double f = mu * cosi - sqrt_fast(kk);
+    h.d[0] = mu * h.d[0] + f * h.N[0];
+    h.d[1] = mu * h.d[1] + f * h.N[1];
+    h.d[2] = mu * h.d[2] + f * h.N[2];
+    return true;
+}
+
+// Central obscuration, the surfaces (sections 2.4.1-2.4.2), silicon (sections 2.4.2-2.4.3) and
+// the pixel, from the start-plane state.
+template <bool ZERN>
+__device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint64_t idx,
+                               const Front& f) {
+    Outcome o;
+    o.status = PHX_MISSED; o.surface = -1; o.newton = 0; o.pix_i = -1; o.pix_j = -1;
+    o.x = o.y = o.z = o.xe = o.ye = 0.0;
+    const double lam = f.lam;
+    o.lam = lam;
+    const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+    double p[3] = {f.p[0], f.p[1], f.p[2]};
+    double n[3] = {f.n[0], f.n[1], f.n[2]};
     if (P.obsc_r > 0.0) {
         const double l = (P.obsc_z - p[2]) / n[2];
         const double x = p[0] + n[0] * l, y = p[1] + n[1] * l;
         if (sqrt(x * x + y * y) < P.obsc_r) {
             o.status = PHX_OBSCURED;
-            o.surface = -1;
             o.x = x; o.y = y; o.z = P.obsc_z;
             return o;
         }
     }
-
     const double n_glass = P.has_glass ? sellmeier(P, lam) : 1.0;
+    const LamCol lc = (L.flags & PHX_F_COATINGS) && P.n_lam > 1 ? lambda_column(P, lam)
+                                                               : LamCol{0, 0.0};
     double n_cur = 1.0;
     uint4 wc = make_uint4(0, 0, 0, 0);
     int wc_block = -1;
-    for (int k = 0; k < P.n_surf; ++k) {
+    Hit h;
+    const int kdet = P.n_surf - 1;
+#pragma unroll 1
+    for (int k = 0; k < kdet; ++k) {
         const DevSurface& s = P.surf[k];
-        double q[3], d[3];
-        if (s.moved) {
-            const double r0 = p[0] - s.t[0], r1 = p[1] - s.t[1], r2 = p[2] - s.t[2];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                q[i] = s.R[i] * r0 + s.R[3 + i] * r1 + s.R[6 + i] * r2;
-                d[i] = s.R[i] * n[0] + s.R[3 + i] * n[1] + s.R[6 + i] * n[2];
+        int st = hit_surface<ZERN>(P, L, rng, k, p, n, lc, wc, wc_block, h, o.newton);
+        if (st == 0) {
+            if (s.kind == PHX_MIRROR) {
+                // reflection across the normal (section 2.4.2)
+                h.d[0] -= 2.0 * h.dn * h.N[0];
+                h.d[1] -= 2.0 * h.dn * h.N[1];
+                h.d[2] -= 2.0 * h.dn * h.N[2];
+            } else {
+                const double n2 = s.medium == PHX_GLASS ? n_glass : 1.0;
+                if (refract(h, n_cur / n2)) n_cur = n2; else st = PHX_TIR;
             }
-        } else {
-            q[0] = p[0]; q[1] = p[1]; q[2] = p[2] - s.t[2];
-            d[0] = n[0]; d[1] = n[1]; d[2] = n[2];
         }
-        double l, gx = 0.0, gy = 0.0;
-        int st = intersect(P, s, q, d, l, gx, gy, o.newton);
-        if (st == 0 && !(l > 0.0)) st = PHX_MISSED;
         if (st != 0) {
-            o.status = st; o.surface = k; o.x = q[0]; o.y = q[1]; o.z = q[2];
-            return o;
-        }
-        q[0] += d[0] * l; q[1] += d[1] * l; q[2] += d[2] * l;
-        const double rq = sqrt(q[0] * q[0] + q[1] * q[1]);
-        if (rq < s.r_in || rq > s.r_out) {
-            o.status = PHX_VIGNETTED; o.surface = k; o.x = q[0]; o.y = q[1]; o.z = q[2];
-            return o;
-        }
-        double N[3] = {-gx, -gy, 1.0};
-        normalise(N);
-        double dn = d[0] * N[0] + d[1] * N[1] + d[2] * N[2];
-        if (dn > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; dn = -dn; }
-        const double cosi = -dn;
-        if ((L.flags & PHX_F_COATINGS) && s.coating >= 0) {
-            const int blk = 2 + (k >> 2);
-            if (blk != wc_block) { wc = rng.block(blk); wc_block = blk; }
-            const uint32_t ws[4] = {wc.x, wc.y, wc.z, wc.w};
-            const double T = coating(P, s.coating, 1.0 - cosi * cosi, lam);
-            if (!(u01(ws[k & 3]) < T)) {
-                o.status = PHX_ABSORBED; o.surface = k; o.x = q[0]; o.y = q[1]; o.z = q[2];
-                return o;
-            }
-        }
-        const bool det = s.kind == PHX_DETECTOR;
-        if (s.kind == PHX_MIRROR) {
-            d[0] -= 2.0 * dn * N[0]; d[1] -= 2.0 * dn * N[1]; d[2] -= 2.0 * dn * N[2];
-        } else if (!det || (L.flags & PHX_F_SILICON)) {
-            const double n2 = s.medium == PHX_GLASS ? n_glass
-                            : (s.medium == PHX_SILICON ? n_silicon(lam) : 1.0);
-            const double mu = n_cur / n2;
-            const double kk = 1.0 - mu * mu * (1.0 - cosi * cosi);
-            if (kk < 0.0) {
-                o.status = PHX_TIR; o.surface = k; o.x = q[0]; o.y = q[1]; o.z = q[2];
-                return o;
-            }
-            const double f = mu * cosi - sqrt(kk);
-            d[0] = mu * d[0] + f * N[0]; d[1] = mu * d[1] + f * N[1]; d[2] = mu * d[2] + f * N[2];
-            n_cur = n2;
-        }
-        if (det) {
-            o.x = q[0]; o.y = q[1]; o.z = q[2]; o.surface = k;
-            double xc = q[0], yc = q[1];
-            if (L.flags & PHX_F_SILICON) {
-                // conversion length = mean free path x Exp(1) (section 2.4.2)
-                const double alpha = absorption(P, lam);
-                const double L_conv = alpha > 0.0 ? -log(u01(w1.z)) / alpha : INFINITY;
-                const double depth = L_conv * fabs(d[2]);
-                if (!(depth <= P.t_si)) {
-                    o.status = PHX_ESCAPED;
-                    return o;
-                }
-                xc += d[0] * L_conv;
-                yc += d[1] * L_conv;
-                if (L.flags & PHX_F_DIFFUSION) {
-                    const uint4 wd = rng.block(6);
-                    const double sigma = P.sigma_max * (P.t_si - depth) / P.t_si;
-                    const double rad = sqrt(-2.0 * log(u01(wd.x)));
-                    double sa, ca;
-                    sincos(kTwoPi * u01(wd.y), &sa, &ca);
-                    xc += sigma * rad * ca;
-                    yc += sigma * rad * sa;
-                }
-            }
-            o.xe = xc; o.ye = yc;
-            const double fx = (xc - P.chip_x0) / P.pixel, fy = (yc - P.chip_y0) / P.pixel;
-            const double ix = floor(fx), iy = floor(fy);
-            o.status = PHX_OFF_CHIP;
-            if (ix >= 0.0 && ix < (double)P.nx && iy >= 0.0 && iy < (double)P.ny) {
-                o.status = PHX_DETECTED;
-                o.pix_i = (int)ix;
-                o.pix_j = (int)iy;
-            }
+            o.status = st; o.surface = k; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
             return o;
         }
         if (s.moved) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                p[i] = s.R[3 * i] * q[0] + s.R[3 * i + 1] * q[1] + s.R[3 * i + 2] * q[2] + s.t[i];
-                n[i] = s.R[3 * i] * d[0] + s.R[3 * i + 1] * d[1] + s.R[3 * i + 2] * d[2];
+                p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] + s.t[i];
+                n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
             }
         } else {
-            p[0] = q[0]; p[1] = q[1]; p[2] = q[2] + s.t[2];
-            n[0] = d[0]; n[1] = d[1]; n[2] = d[2];
+            p[0] = h.q[0]; p[1] = h.q[1]; p[2] = h.q[2] + s.t[2];
+            n[0] = h.d[0]; n[1] = h.d[1]; n[2] = h.d[2];
         }
     }
-    o.status = PHX_MISSED;
-    o.surface = P.n_surf;
+    // the detector surface: refraction into silicon, conversion, diffusion, pixel
+    int st = hit_surface<ZERN>(P, L, rng, kdet, p, n, lc, wc, wc_block, h, o.newton);
+    if (st == 0 && (L.flags & PHX_F_SILICON) && !refract(h, n_cur / n_silicon(lam))) st = PHX_TIR;
+    o.surface = kdet;
+    o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+    if (st != 0) {
+        o.status = st;
+        return o;
+    }
+    double xc = h.q[0], yc = h.q[1];
+    if (sensor_stage(P, L, rng, lam, h.d, xc, yc)) {
+        o.status = PHX_ESCAPED;
+        return o;
+    }
+    o.xe = xc; o.ye = yc;
+    // pixel quantisation (section 2.4.3)
+    const double fx = (xc - P.chip_x0) / P.pixel, fy = (yc - P.chip_y0) / P.pixel;
+    const double ix = floor(fx), iy = floor(fy);
+    o.status = PHX_OFF_CHIP;
+    if (ix >= 0.0 && ix < (double)P.nx && iy >= 0.0 && iy < (double)P.ny) {
+        o.status = PHX_DETECTED;
+        o.pix_i = (int)ix;
+        o.pix_j = (int)iy;
+    }
     return o;
 }
 
+// The whole per-photon path (optionally with the pre-roll test first).
+__device__ Outcome trace_photon(const DevParams& P, const Launch& L, int si, uint64_t idx,
+                               bool preroll = true) {
+    if (preroll && (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS)) {
+        double lam;
+        if (preroll_culls(P, L, si, idx, lam)) {
+            Outcome o;
+            o.status = PHX_CULLED; o.surface = -1; o.newton = 0; o.pix_i = o.pix_j = -1;
+            o.x = o.y = o.z = o.xe = o.ye = 0.0;
+            o.lam = lam;
+            return o;
+        }
+    }
+    Front f;
+    photon_front<true>(P, L, si, idx, f);
+    return photon_back<true>(P, L, si, idx, f);
+}
+
 // Wavefront-aggregated increment: lanes with the same pixel elect one leader that adds the
-// group's count.
+// group's count.  Every lane of the wavefront must call it.
 __device__ __forceinline__ void bin_photon(uint32_t* image, int pix, bool active) {
     uint64_t pending = __ballot(active);
     const int lane = __lane_id();
@@ -528,60 +639,62 @@ __device__ __forceinline__ void bin_photon(uint32_t* image, int pix, bool active
     }
 }
 
-__global__ __launch_bounds__(kBlock) void trace_kernel(const DevParams* __restrict__ Pg,
-                                                       const Launch L) {
-    __shared__ uint32_t s_stats[PHX_STATS_LEN];
+// Flattened launch index g -> (source, photon index).
+__device__ __forceinline__ void decode(const Launch& L, uint64_t g, int& si, uint64_t& idx) {
+    int s;
+    uint64_t local;
+    if (L.n_src == 1) {
+        s = 0;
+        local = g;
+    } else if (L.uniform_count) {
+        s = (int)(g / L.uniform_count);
+        local = g - (uint64_t)s * L.uniform_count;
+    } else {
+        int lo = 0, hi = L.n_src - 1;   // largest s with prefix[s] <= g
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.prefix[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        s = lo;
+        local = g - L.prefix[s];
+    }
+    si = L.src_begin + s;
+    idx = L.photon_begin + local;
+}
+
+__device__ __forceinline__ void write_event(const Launch& L, uint64_t g, int si, uint64_t idx,
+                                            const Outcome& o) {
+    phx_event& e = L.events[g / L.event_stride];
+    e.photon = idx; e.source = si; e.status = o.status; e.surface = o.surface;
+    e.pix_i = o.pix_i; e.pix_j = o.pix_j; e.newton = o.newton;
+    e.x = o.x; e.y = o.y; e.z = o.z; e.xe = o.xe; e.ye = o.ye; e.lambda = o.lam;
+}
+
+// Book-keeping of one traced photon: LDS status counter, moments, event record; returns the
+// pixel to bin (-1 for none).
+__device__ __forceinline__ int account(const DevParams& P, const Launch& L, uint32_t* s_stats,
+                                       uint64_t g, int si, uint64_t idx, const Outcome& o) {
+    atomicAdd(&s_stats[o.status * PHX_STAT_COLS + min(o.surface + 1, PHX_STAT_COLS - 1)], 1u);
+    if ((L.flags & PHX_F_MOMENTS) && o.status <= PHX_OFF_CHIP) {
+        double* m = L.moments + (size_t)si * PHX_MOMENT_LEN;
+        atomicAdd(m + 0, 1.0);
+        atomicAdd(m + 1, o.xe);
+        atomicAdd(m + 2, o.ye);
+        atomicAdd(m + 3, o.xe * o.xe);
+        atomicAdd(m + 4, o.ye * o.ye);
+        atomicAdd(m + 5, o.xe * o.ye);
+    }
+    if ((L.flags & PHX_F_EVENTS) && (g % L.event_stride) == 0) write_event(L, g, si, idx, o);
+    return o.status == PHX_DETECTED ? o.pix_j * P.nx + o.pix_i : -1;
+}
+
+__device__ __forceinline__ void stats_init(uint32_t* s_stats) {
     for (int i = threadIdx.x; i < PHX_STATS_LEN; i += blockDim.x) s_stats[i] = 0;
     __syncthreads();
-    const DevParams& P = *Pg;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // every lane of a wavefront runs the same number of iterations (bin_photon uses ballots)
-    const uint64_t n_iter = (L.total + stride - 1) / stride;
-    uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t newton = 0, traced = 0;
-    for (uint64_t it = 0; it < n_iter; ++it, g += stride) {
-        const bool valid = g < L.total;
-        int pix = -1;
-        if (valid) {
-            int s;
-            uint64_t local;
-            if (L.uniform_count) {
-                s = (int)(g / L.uniform_count);
-                local = g - (uint64_t)s * L.uniform_count;
-            } else {
-                int lo = 0, hi = L.n_src - 1;   // largest s with prefix[s] <= g
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (L.prefix[mid] <= g) lo = mid; else hi = mid - 1;
-                }
-                s = lo;
-                local = g - L.prefix[s];
-            }
-            const int si = L.src_begin + s;
-            const uint64_t idx = L.photon_begin + local;
-            const Outcome o = trace_photon(P, L, si, idx);
-            atomicAdd(&s_stats[o.status * PHX_STAT_COLS + min(o.surface + 1, PHX_STAT_COLS - 1)], 1u);
-            newton += o.newton;
-            traced += o.status != PHX_CULLED;
-            if (o.status == PHX_DETECTED) pix = o.pix_j * P.nx + o.pix_i;
-            if ((L.flags & PHX_F_MOMENTS) && o.status <= PHX_OFF_CHIP) {
-                double* m = L.moments + (size_t)si * PHX_MOMENT_LEN;
-                atomicAdd(m + 0, 1.0);
-                atomicAdd(m + 1, o.xe);
-                atomicAdd(m + 2, o.ye);
-                atomicAdd(m + 3, o.xe * o.xe);
-                atomicAdd(m + 4, o.ye * o.ye);
-                atomicAdd(m + 5, o.xe * o.ye);
-            }
-            if ((L.flags & PHX_F_EVENTS) && (g % L.event_stride) == 0) {
-                phx_event& e = L.events[g / L.event_stride];
-                e.photon = idx; e.source = si; e.status = o.status; e.surface = o.surface;
-                e.pix_i = o.pix_i; e.pix_j = o.pix_j; e.newton = o.newton;
-                e.x = o.x; e.y = o.y; e.z = o.z; e.xe = o.xe; e.ye = o.ye; e.lambda = o.lam;
-            }
-        }
-        bin_photon(L.image, pix, pix >= 0);
-    }
+}
+
+__device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, uint32_t newton,
+                                            uint32_t traced) {
     atomicAdd(&s_stats[PHX_STAT_NEWTON], newton);
     atomicAdd(&s_stats[PHX_STAT_TRACED], traced);
     __syncthreads();
@@ -591,9 +704,211 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(const DevParams* __restri
     }
 }
 
+// Every photon of [begin, begin + len) traced in place (no pre-roll compaction).
+__global__ __launch_bounds__(kBlock) void trace_kernel(const DevParams* __restrict__ Pg,
+                                                       const Launch L, uint64_t begin,
+                                                       uint64_t len) {
+    __shared__ uint32_t s_stats[PHX_STATS_LEN];
+    stats_init(s_stats);
+    const DevParams& P = *Pg;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_iter = (len + stride - 1) / stride;   // uniform across the wavefront
+    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t newton = 0, traced = 0;
+    for (uint64_t it = 0; it < n_iter; ++it, r += stride) {
+        int pix = -1;
+        if (r < len) {
+            const uint64_t g = begin + r;
+            int si;
+            uint64_t idx;
+            decode(L, g, si, idx);
+            const Outcome o = trace_photon(P, L, si, idx);
+            newton += o.newton;
+            traced += o.status != PHX_CULLED;
+            pix = account(P, L, s_stats, g, si, idx, o);
+        }
+        bin_photon(L.image, pix, pix >= 0);
+    }
+    stats_flush(L, s_stats, newton, traced);
+}
+
+// Pre-roll (section 3.2, dynamic transmission optimisation): draw each photon's wavelength and
+// coating roulette numbers; photons whose draw exceeds the worst-case transmission of a coated
+// surface cannot be detected and are counted as culled.  Survivors (offsets in the chunk) are
+// staged in LDS and appended to the chunk's survivor list with one device-wide atomic per flush.
+constexpr int kQueue = 4096;
+__global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __restrict__ Pg,
+                                                          const Launch L, uint64_t begin,
+                                                          uint64_t len, uint32_t* __restrict__ surv,
+                                                          unsigned int* __restrict__ count) {
+    __shared__ uint32_t s_stats[PHX_STATS_LEN];
+    __shared__ uint32_t s_q[kQueue];
+    __shared__ unsigned int s_qn, s_base;
+    if (threadIdx.x == 0) s_qn = 0;
+    stats_init(s_stats);
+    const DevParams& P = *Pg;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_iter = (len + stride - 1) / stride;   // the same for every thread
+    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = __lane_id();
+    for (uint64_t it = 0; it < n_iter; ++it, r += stride) {
+        bool keep = false;
+        if (r < len) {
+            const uint64_t g = begin + r;
+            int si;
+            uint64_t idx;
+            decode(L, g, si, idx);
+            double lam;
+            keep = !preroll_culls(P, L, si, idx, lam);
+            if (!keep) {
+                Outcome o;
+                o.status = PHX_CULLED; o.surface = -1; o.newton = 0; o.pix_i = o.pix_j = -1;
+                o.x = o.y = o.z = o.xe = o.ye = 0.0;
+                o.lam = lam;
+                account(P, L, s_stats, g, si, idx, o);
+            }
+        }
+        const uint64_t mask = __ballot(keep);
+        if (mask) {
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            unsigned int base = 0;
+            if (lane == leader) base = atomicAdd(&s_qn, (unsigned int)__popcll(mask));
+            base = __shfl(base, leader);
+            if (keep) s_q[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)r;
+        }
+        __syncthreads();
+        const unsigned int qn = s_qn;
+        if (qn > (unsigned int)(kQueue - kBlock) || it + 1 == n_iter) {
+            __syncthreads();
+            if (threadIdx.x == 0) s_base = atomicAdd(count, qn);
+            __syncthreads();
+            const unsigned int base = s_base;
+            for (unsigned int i = threadIdx.x; i < qn; i += blockDim.x) surv[base + i] = s_q[i];
+            __syncthreads();
+            if (threadIdx.x == 0) s_qn = 0;
+            __syncthreads();
+        }
+    }
+    stats_flush(L, s_stats, 0u, 0u);
+}
+
+// Front half of the trace for the chunk's photons (the survivor list, or every photon when
+// surv is null): sky sampling and the atmosphere, leaving the start-plane state in SoA arrays
+// st[0..6][i] = p_x, p_y, p_z, n_x, n_y, n_z, lambda.
+template <bool SERSIC>
+__global__ __launch_bounds__(kBlock) void front_kernel(const DevParams* __restrict__ Pg,
+                                                       const Launch L, uint64_t begin,
+                                                       const uint32_t* __restrict__ surv,
+                                                       const unsigned int* __restrict__ count,
+                                                       uint64_t n_all, double* __restrict__ st,
+                                                       uint64_t st_stride) {
+    const DevParams& P = *Pg;
+    const uint64_t n = surv ? (uint64_t)*count : n_all;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const uint64_t g = begin + (surv ? (uint64_t)surv[r] : r);
+        int si;
+        uint64_t idx;
+        decode(L, g, si, idx);
+        Front f;
+        photon_front<SERSIC>(P, L, si, idx, f);
+        st[0 * st_stride + r] = f.p[0];
+        st[1 * st_stride + r] = f.p[1];
+        st[2 * st_stride + r] = f.p[2];
+        st[3 * st_stride + r] = f.n[0];
+        st[4 * st_stride + r] = f.n[1];
+        st[5 * st_stride + r] = f.n[2];
+        st[6 * st_stride + r] = f.lam;
+    }
+}
+
+// Back half: optics, silicon, pixel and book-keeping, from the start-plane state.
+// Pixel counts go through a per-workgroup LDS window of kWin x kWin pixels placed at the first
+// detected pixel the workgroup sees (a star's image core), flushed to the image once at the end;
+// pixels outside the window take wavefront-aggregated global atomics.
+constexpr int kWin = 64;
+template <bool ZERN>
+__global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restrict__ Pg,
+                                                      const Launch L, uint64_t begin,
+                                                      const uint32_t* __restrict__ surv,
+                                                      const unsigned int* __restrict__ count,
+                                                      uint64_t n_all, const double* __restrict__ st,
+                                                      uint64_t st_stride) {
+    __shared__ uint32_t s_stats[PHX_STATS_LEN];
+    __shared__ uint32_t s_win[kWin * kWin];
+    __shared__ int s_org;   // window origin: (i0 << 16) | j0, or -1 before the first detection
+    for (int i = threadIdx.x; i < kWin * kWin; i += blockDim.x) s_win[i] = 0;
+    if (threadIdx.x == 0) s_org = -1;
+    stats_init(s_stats);
+    const DevParams& P = *Pg;
+    const uint64_t n = surv ? (uint64_t)*count : n_all;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n_iter = (n + stride - 1) / stride;      // the same for every thread
+    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t newton = 0, traced = 0;
+    for (uint64_t it = 0; it < n_iter; ++it, r += stride) {
+        int pix = -1;
+        if (r < n) {
+            const uint64_t g = begin + (surv ? (uint64_t)surv[r] : r);
+            int si;
+            uint64_t idx;
+            decode(L, g, si, idx);
+            Front f;
+            f.p[0] = st[0 * st_stride + r];
+            f.p[1] = st[1 * st_stride + r];
+            f.p[2] = st[2 * st_stride + r];
+            f.n[0] = st[3 * st_stride + r];
+            f.n[1] = st[4 * st_stride + r];
+            f.n[2] = st[5 * st_stride + r];
+            f.lam = st[6 * st_stride + r];
+            const Outcome o = photon_back<ZERN>(P, L, si, idx, f);
+            newton += o.newton;
+            traced += 1;
+            if (account(P, L, s_stats, g, si, idx, o) >= 0) {
+                int org = s_org;
+                if (org < 0) {
+                    const int want = (max(o.pix_i - kWin / 2, 0) << 16) | max(o.pix_j - kWin / 2, 0);
+                    const int prev = atomicCAS(&s_org, -1, want);
+                    org = prev < 0 ? want : prev;
+                }
+                const int wi = o.pix_i - (org >> 16), wj = o.pix_j - (org & 0xffff);
+                if (wi >= 0 && wi < kWin && wj >= 0 && wj < kWin)
+                    atomicAdd(&s_win[wj * kWin + wi], 1u);
+                else
+                    pix = o.pix_j * P.nx + o.pix_i;
+            }
+        }
+        bin_photon(L.image, pix, pix >= 0);
+    }
+    stats_flush(L, s_stats, newton, traced);   // ends with a barrier
+    const int org = s_org;
+    if (org >= 0) {
+        const int i0 = org >> 16, j0 = org & 0xffff;
+        for (int k = threadIdx.x; k < kWin * kWin; k += blockDim.x) {
+            const uint32_t c = s_win[k];
+            const int i = i0 + (k % kWin), j = j0 + (k / kWin);
+            if (c && i < P.nx && j < P.ny) atomicAdd(&L.image[(size_t)j * P.nx + i], c);
+        }
+    }
+}
+
+__global__ void fill_u32(unsigned int* p, uint64_t n, unsigned int v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // Centred-difference gradients of periodic OPD screens (the refractive kick of section 2.3.2 is
-// the phase gradient), single precision: g_x = (W[j][i+1] - W[j][i-1]) * (1/(2p)).
-__global__ void gradient_kernel(const float* __restrict__ opd, float2* __restrict__ grad, int n,
+// the phase gradient), single precision: g_x = (W[j][i+1] - W[j][i-1]) * (1/(2p)), likewise g_y.
+// Thread (plane, j, i) writes the cell record: gradients at (i, j), (i+1, j), (i, j+1), (i+1, j+1).
+__device__ __forceinline__ float2 grad_at(const float* w, int n, int i, int j, float f) {
+    const int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
+    const int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
+    const float dx = w[(int64_t)j * n + ip] - w[(int64_t)j * n + im];
+    const float dy = w[(int64_t)jp * n + i] - w[(int64_t)jm * n + i];
+    return make_float2(dx * f, dy * f);
+}
+
+__global__ void gradient_kernel(const float* __restrict__ opd, float4* __restrict__ grad, int n,
                                 int n_scales, const float* inv2p, int64_t total) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= total) return;
@@ -603,25 +918,69 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float2* __restric
     const int j = (int)(r / n), i = (int)(r - (int64_t)j * n);
     const float* w = opd + plane * nn;
     const float f = inv2p[plane % n_scales];
-    const int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
-    const int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
-    const float dx = w[(int64_t)j * n + ip] - w[(int64_t)j * n + im];
-    const float dy = w[(int64_t)jp * n + i] - w[(int64_t)jm * n + i];
-    grad[id] = make_float2(dx * f, dy * f);
+    const int i1 = i + 1 == n ? 0 : i + 1, j1 = j + 1 == n ? 0 : j + 1;
+    const float2 g00 = grad_at(w, n, i, j, f), g10 = grad_at(w, n, i1, j, f);
+    const float2 g01 = grad_at(w, n, i, j1, f), g11 = grad_at(w, n, i1, j1, f);
+    grad[2 * id] = make_float4(g00.x, g00.y, g10.x, g10.y);
+    grad[2 * id + 1] = make_float4(g01.x, g01.y, g11.x, g11.y);
 }
 
 }  // namespace
 
-hipError_t launch_trace(const DevParams* dparams, const Launch& L, int n_cu, hipStream_t stream) {
+hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
+                        hipStream_t stream) {
     if (L.total == 0) return hipSuccess;
-    const uint64_t want = (L.total + kBlock - 1) / kBlock;
-    const uint64_t cap = (uint64_t)n_cu * 8;
-    const int grid = (int)(want < cap ? want : cap);
-    hipLaunchKernelGGL(trace_kernel, dim3(grid), dim3(kBlock), 0, stream, dparams, L);
+    const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
+    if (!W.state) {
+        // small launches without a workspace: one fused kernel
+        const uint64_t want = (L.total + kBlock - 1) / kBlock;
+        const uint64_t cap = (uint64_t)n_cu * 8;
+        const int grid = (int)(want < cap ? want : cap);
+        hipLaunchKernelGGL(trace_kernel, dim3(grid), dim3(kBlock), 0, stream, dparams, L,
+                           (uint64_t)0, L.total);
+        return hipGetLastError();
+    }
+    const uint64_t chunk = W.chunk;
+    const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
+    if (preroll) {
+        if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(fill_u32, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256), 0,
+                           stream, W.counts, n_chunks, 0u);
+    }
+    for (uint64_t c = 0; c < n_chunks; ++c) {
+        const uint64_t begin = c * chunk;
+        const uint64_t len = L.total - begin < chunk ? L.total - begin : chunk;
+        const uint32_t* surv = nullptr;
+        const unsigned int* cnt = nullptr;
+        if (preroll) {
+            const uint64_t want = (len + kBlock - 1) / kBlock;
+            const uint64_t cap = (uint64_t)n_cu * 8;
+            const int ggrid = (int)(want < cap ? want : cap);
+            hipLaunchKernelGGL(generate_kernel, dim3(ggrid), dim3(kBlock), 0, stream, dparams, L,
+                               begin, len, W.survivors, W.counts + c);
+            surv = W.survivors;
+            cnt = W.counts + c;
+        }
+        const uint64_t want = (len + kBlock - 1) / kBlock;
+        const uint64_t fcap = (uint64_t)n_cu * 32, bcap = (uint64_t)n_cu * 4;
+        const dim3 fg((unsigned)(want < fcap ? want : fcap)), bg((unsigned)(want < bcap ? want : bcap));
+        if (L.any_sersic)
+            hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
+                               surv, cnt, len, W.state, chunk);
+        else
+            hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
+                               surv, cnt, len, W.state, chunk);
+        if (L.any_zernike)
+            hipLaunchKernelGGL(back_kernel<true>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
+                               surv, cnt, len, (const double*)W.state, chunk);
+        else
+            hipLaunchKernelGGL(back_kernel<false>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
+                               surv, cnt, len, (const double*)W.state, chunk);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_gradients(const float* opd, float2* grad, int n_layers, int n_scales, int n,
+hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, hipStream_t stream) {
     // inverse 2p per scale, rounded to float once (the same value for every texel)
     float h_inv2p[PHX_MAX_SCALES];

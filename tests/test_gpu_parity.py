@@ -136,3 +136,24 @@ def test_error_paths(phx):
     bad.prescription.surfaces[0].r_out = float("nan")
     with pytest.raises(phx.PhxError):
         phx.Tracer(bad)
+
+
+def test_preroll_events_consistent(phx):
+    """With the pre-roll on, every photon it removes is one that the full trace does not detect,
+    and every other photon has exactly the record it has without the pre-roll."""
+    import torch
+    s = C.full(scale=2e-4, screen_n=128)
+    tr = phx.Tracer(s)
+    _, _, _, ea = tr.trace(event_stride=1)
+    _, _, _, eb = tr.trace(event_stride=1, flags=int(s.physics) | phx.F_CULL)
+    torch.cuda.synchronize()
+    a, b = phx.events_to_numpy(ea), phx.events_to_numpy(eb)
+    assert np.array_equal(a["photon"], b["photon"])
+    culled = b["status"] == phx.CULLED
+    assert culled.mean() > 0.5
+    assert not np.isin(a["status"][culled], [phx.DETECTED, phx.OFF_CHIP]).any()
+    keep = ~culled
+    for f in ("status", "surface", "pix_i", "pix_j"):
+        assert np.array_equal(a[f][keep], b[f][keep]), f
+    for f in ("x", "y", "xe", "ye", "lam"):
+        assert np.array_equal(a[f][keep], b[f][keep]), f
