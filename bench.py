@@ -27,32 +27,27 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "trace_kernel_full_1e9_pmc.json")
 
 # Algorithmic FP64 operation counts of the trace stages (add/sub/mul/div/sqrt/transcendental = 1,
 # fused multiply-add = 2), counted from the algorithm as written ("Roofline").
-FLOPS_GENERATE = 12          # uniform conversions, wavelength
-FLOPS_CULL_PER_COAT = 6      # pre-roll test per coated surface
-FLOPS_SOURCE = 45            # direction, time, pupil sample and sag
-FLOPS_LAYER = 112            # propagate, 3 scales x bilinear gradient pair, kick, renormalise
+# Algorithmic bytes of the sky+atmosphere stage per traced photon: per layer and scale one
+# bilinear footprint of four (g_x, g_y) float pairs, plus the 7-double start-plane state written.
 FLOPS_SURFACE = 80           # transform, conic root, clip, normal, coating, reflect/refract
 FLOPS_NEWTON = 70            # one Newton step: point, sag + gradient with asphere terms
 FLOPS_SILICON = 65           # index, absorption, conversion, diffusion, pixel
+STATE_BYTES = 7 * 8
 
 
-def algorithmic_flops(stats, n_generated, n_layers, n_surf, n_coated, culled_flag):
-    """FP64 operations the trace performs for this launch's photon fates (stats buffer)."""
+def front_bytes_per_photon(n_layers, n_scales):
+    return n_layers * n_scales * 4 * 8 + STATE_BYTES
+
+
+def back_flops(stats, n_surf):
+    """FP64 operations of the optics + silicon stage for this launch's traced photons."""
     import numpy as np
     from paper_1504_06570_amd import phx
     tab = phx.stats_table(stats).astype(np.float64)
-    traced = float(stats[phx.STAT_TRACED])
-    newton = float(stats[phx.STAT_NEWTON])
-    # photons that reached surface k = photons whose fate was decided at surface >= k
-    decided_at = tab.sum(axis=0)          # by column (surface + 1)
-    reach = [decided_at[k + 1:].sum() for k in range(n_surf)]
+    decided_at = tab.sum(axis=0)
+    reach = sum(decided_at[k + 1:].sum() for k in range(n_surf))
     silicon = tab[[phx.DETECTED, phx.OFF_CHIP, phx.ESCAPED], n_surf].sum()
-    f = n_generated * FLOPS_GENERATE
-    if culled_flag:
-        f += n_generated * FLOPS_CULL_PER_COAT * n_coated
-    f += traced * (FLOPS_SOURCE + n_layers * FLOPS_LAYER)
-    f += sum(reach) * FLOPS_SURFACE + newton * FLOPS_NEWTON + silicon * FLOPS_SILICON
-    return f
+    return reach * FLOPS_SURFACE + float(stats[phx.STAT_NEWTON]) * FLOPS_NEWTON + silicon * FLOPS_SILICON
 
 
 def kernel_hash():
@@ -62,16 +57,16 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(n_launch_photons):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if
-    it is missing or was taken on a different kernel source."""
+def traffic_from_profiles(n_launch_photons, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None if it is missing or was taken on a different kernel source."""
     try:
         d = json.load(open(PMC_SUMMARY))
     except (OSError, ValueError):
         return None
     if d.get("kernel_hash") != kernel_hash() or d.get("photons") != n_launch_photons:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_launch", {}).get(kernel)
 
 
 def cpu_baseline(scene, n_photons, threads):
@@ -104,7 +99,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--photons", type=float, default=1e9)
     ap.add_argument("--no-cull", action="store_true", help="time without the pre-roll only")
-    ap.add_argument("--cpu-sample", type=float, default=3e6)
+    ap.add_argument("--cpu-sample", type=float, default=8e7)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
@@ -141,22 +136,36 @@ def main():
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    tr.set_timing(True)   # HIP events around every kernel of the timed steps
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
         tr.trace(img, flags=flags, stats=stats)
     ev1.record(stream)
     torch.cuda.synchronize()
+    kt = tr.get_timing()
+    tr.set_timing(False)
     ms = ev0.elapsed_time(ev1) / args.steps
     value = n_ph / (ms * 1e-3)
     st = stats.cpu().numpy()
-    print(f"# timed {args.steps} steps: {ms:.2f} ms/step", file=sys.stderr, flush=True)
-    flops = algorithmic_flops(st, n_ph * args.steps, scene.atmosphere.n_layers, n_surf, n_coated,
-                              not args.no_cull) / args.steps
-    achieved = flops / (ms * 1e-3) / 1e12
+    print(f"# timed {args.steps} steps: {ms:.2f} ms/step; kernels {kt}", file=sys.stderr, flush=True)
     tab = phx.stats_table(st) / args.steps
     detected = float(tab[phx.DETECTED].sum())
-
+    traced = float(st[phx.STAT_TRACED])
+    chunks = max(kt["chunks"], 1.0)
+    atm = scene.atmosphere
+    # per-launch (one chunk's kernel) figures of each stage
+    kinds = {
+        "front": dict(ms=kt["front"] / chunks, bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS,
+                      work=traced * front_bytes_per_photon(atm.n_layers, atm.n_scales) / chunks,
+                      scale=1e-9),
+        "back": dict(ms=kt["back"] / chunks, bound="alu", unit="TFLOP/s", peak=PEAK_FP64_TFLOPS,
+                     work=back_flops(st, n_surf) / chunks, scale=1e-12),
+    }
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    d = kinds[dom]
+    achieved = d["work"] / (d["ms"] * 1e-3) * d["scale"]
+    stage_ms = {k: kt[k] / args.steps for k in ("generate", "front", "back")}
     extra = {}
     if not args.no_cull and not args.no_compare:
         # the same step without the pre-roll (every photon traced until its fate)
@@ -183,7 +192,7 @@ def main():
                          f"{dt:.1f} s on {threads} host threads"}
         print(f"# cpu oracle {rate:.3e} photons/s ({dt:.1f}s)", file=sys.stderr, flush=True)
 
-    traffic = traffic_from_profiles(n_ph)
+    traffic = traffic_from_profiles(n_ph, f"{dom}_kernel")
     out = {
         "metric": METRIC,
         "value": value,
@@ -206,13 +215,16 @@ def main():
             "detected_per_step": detected,
         },
         "roofline": {
-            "bound": "alu",
+            "bound": d["bound"],
             "achieved": achieved,
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
+            "peak": d["peak"],
+            "unit": d["unit"],
+            "frac": achieved / d["peak"],
             "traffic": traffic,
+            "kernel": f"{dom}_kernel",
+            "launch_ms": d["ms"],
         },
+        "stage_ms_per_step": stage_ms,
         "cpu_baseline": cpu,
         "adjoint_forward_ratio": None,
     }

@@ -41,7 +41,35 @@ struct phx_ctx_s {
     uint64_t counts_cap = 0;
     double* d_state = nullptr;           // start-plane state of one chunk [7][ws_chunk]
     uint64_t ws_chunk = 0;
+    // kernel timing (phx_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_pairs;   // kind, (start, stop)
+    size_t ev_used = 0;
+    long pending_start[3] = {-1, -1, -1};
+    double timing_ms[3] = {0, 0, 0};
+    double timing_chunks = 0;
 };
+
+namespace {
+void timing_record(void* self, int kind, int edge, hipStream_t stream) {
+    phx_ctx c = (phx_ctx)self;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->ev_pool.push_back(e);
+    }
+    const size_t i = c->ev_used++;
+    if (hipEventRecord(c->ev_pool[i], stream) != hipSuccess) return;
+    if (edge == 0) {
+        c->pending_start[kind] = (long)i;
+    } else if (c->pending_start[kind] >= 0) {
+        c->ev_pairs.push_back({kind, {(size_t)c->pending_start[kind], i}});
+        c->pending_start[kind] = -1;
+        if (kind == 2) c->timing_chunks += 1;
+    }
+}
+}  // namespace
 
 namespace {
 
@@ -229,6 +257,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_survivors);
     free_dev(c->d_counts);
     free_dev(c->d_state);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -618,8 +647,43 @@ phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
     const phx::Workspace W{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk};
     phx_status r = upload_params(c, st);
     if (r != PHX_OK) return r;
-    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, st);
+    phx::Timing T;
+    T.on = c->timing;
+    T.record = timing_record;
+    T.self = c;
+    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, st, T);
     if (e != hipSuccess) return hip_fail(c, e, "trace kernel launch");
+    return PHX_OK;
+}
+
+phx_status phx_set_timing(phx_ctx c, int32_t on) {
+    if (!c) return PHX_ERR_INVALID;
+    c->timing = on != 0;
+    c->ev_pairs.clear();
+    c->ev_used = 0;
+    for (int k = 0; k < 3; ++k) {
+        c->pending_start[k] = -1;
+        c->timing_ms[k] = 0.0;
+    }
+    c->timing_chunks = 0;
+    return PHX_OK;
+}
+
+phx_status phx_get_timing(phx_ctx c, double* out, int32_t n) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!out || n < 1) return fail(c, PHX_ERR_INVALID, "null or empty output");
+    for (const auto& pr : c->ev_pairs) {
+        hipError_t e = hipEventSynchronize(c->ev_pool[pr.second.second]);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, c->ev_pool[pr.second.first], c->ev_pool[pr.second.second]);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+        c->timing_ms[pr.first] += ms;
+    }
+    c->ev_pairs.clear();
+    c->ev_used = 0;
+    const double v[4] = {c->timing_ms[0], c->timing_ms[1], c->timing_ms[2], c->timing_chunks};
+    for (int i = 0; i < n && i < 4; ++i) out[i] = v[i];
     return PHX_OK;
 }
 

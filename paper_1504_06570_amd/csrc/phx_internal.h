@@ -96,8 +96,16 @@ struct Workspace {
     uint64_t chunk;
 };
 
+// Optional per-kernel timing: events recorded before/after each kernel launch.
+struct Timing {
+    bool on = false;
+    // event pairs per kernel kind (0 generate, 1 front, 2 back), appended per chunk
+    void (*record)(void* self, int kind, int edge, hipStream_t stream) = nullptr;
+    void* self = nullptr;
+};
+
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                        hipStream_t stream);
+                        hipStream_t stream, const Timing& T);
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, hipStream_t stream);
 

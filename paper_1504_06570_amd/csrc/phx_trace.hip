@@ -928,7 +928,10 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
 }  // namespace
 
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                        hipStream_t stream) {
+                        hipStream_t stream, const Timing& T) {
+    auto mark = [&](int kind, int edge) {
+        if (T.on) T.record(T.self, kind, edge, stream);
+    };
     if (L.total == 0) return hipSuccess;
     const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
     if (!W.state) {
@@ -956,26 +959,32 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
             const uint64_t want = (len + kBlock - 1) / kBlock;
             const uint64_t cap = (uint64_t)n_cu * 8;
             const int ggrid = (int)(want < cap ? want : cap);
+            mark(0, 0);
             hipLaunchKernelGGL(generate_kernel, dim3(ggrid), dim3(kBlock), 0, stream, dparams, L,
                                begin, len, W.survivors, W.counts + c);
+            mark(0, 1);
             surv = W.survivors;
             cnt = W.counts + c;
         }
         const uint64_t want = (len + kBlock - 1) / kBlock;
         const uint64_t fcap = (uint64_t)n_cu * 32, bcap = (uint64_t)n_cu * 4;
         const dim3 fg((unsigned)(want < fcap ? want : fcap)), bg((unsigned)(want < bcap ? want : bcap));
+        mark(1, 0);
         if (L.any_sersic)
             hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
                                surv, cnt, len, W.state, chunk);
         else
             hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
                                surv, cnt, len, W.state, chunk);
+        mark(1, 1);
+        mark(2, 0);
         if (L.any_zernike)
             hipLaunchKernelGGL(back_kernel<true>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
                                surv, cnt, len, (const double*)W.state, chunk);
         else
             hipLaunchKernelGGL(back_kernel<false>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
                                surv, cnt, len, (const double*)W.state, chunk);
+        mark(2, 1);
     }
     return hipGetLastError();
 }

@@ -105,8 +105,11 @@ def lib():
         L.phx_load_sources.argtypes = [C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p,
                                        C.c_void_p, C.c_int32, C.c_int32]
         L.phx_trace.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
+        L.phx_set_timing.argtypes = [C.c_void_p, C.c_int32]
+        L.phx_get_timing.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32]
         for f in ("phx_create", "phx_load_prescription", "phx_set_perturbation",
-                  "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace"):
+                  "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace",
+                  "phx_set_timing", "phx_get_timing"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -275,6 +278,16 @@ class Tracer:
             a.event_capacity = events.numel() // EVENT_DTYPE.itemsize
         self._check(self.L.phx_trace(self.ctx, C.byref(a), _stream_handle(stream)))
         return image, stats, moments, events
+
+    def set_timing(self, on: bool):
+        self._check(self.L.phx_set_timing(self.ctx, 1 if on else 0))
+
+    def get_timing(self):
+        """Accumulated kernel milliseconds since timing was switched on:
+        dict(generate, front, back, chunks)."""
+        out = (C.c_double * 4)()
+        self._check(self.L.phx_get_timing(self.ctx, out, 4))
+        return dict(generate=out[0], front=out[1], back=out[2], chunks=out[3])
 
     def new_stats(self):
         import torch
