@@ -234,6 +234,36 @@ phx_status phx_load_sources(phx_ctx ctx, const phx_source* src_host, int32_t n_s
  * Enqueued on `stream`.  Errors: PHX_ERR_INVALID, PHX_ERR_STATE, PHX_ERR_CAPACITY, PHX_ERR_HIP. */
 phx_status phx_trace(phx_ctx ctx, const phx_trace_args* args, void* stream);
 
+/* Launch shape of phx_trace / phx_trace_batched.  chunk_log2: photons per chunk = 2^chunk_log2
+ * (16..27; the context keeps a survivor list and a 56-byte state per photon of one chunk);
+ * *_blocks_per_cu: workgroups of 256 lanes per compute unit for the pre-roll, sky+atmosphere and
+ * optics kernels (1..64); dynamic_tiles: 0 = static grid-stride, 1 = the sky and optics kernels
+ * claim tiles of 2048 photons from a device counter.  Defaults: 26, 8, 32, 4, 0. */
+typedef struct {
+    int32_t chunk_log2;
+    int32_t generate_blocks_per_cu, front_blocks_per_cu, back_blocks_per_cu;
+    int32_t dynamic_tiles;
+} phx_launch_config;
+
+phx_status phx_set_launch_config(phx_ctx ctx, const phx_launch_config* cfg_host);
+phx_status phx_get_launch_config(phx_ctx ctx, phx_launch_config* cfg_host);
+
+/* Batched trace (the many-source schedule): the same photons and results as phx_trace with the
+ * same arguments, but the whole launch -- every chunk's pre-roll, sky and optics kernels over the
+ * concatenated photon ranges of all sources in [src_begin, src_end) -- is captured once into a HIP
+ * graph (keyed by the arguments and launch shape) and replayed with a single graph launch on
+ * `stream`.  The first call with a new key prepares (uploads tables, may synchronise `stream`)
+ * and captures on a context-owned stream; later calls only launch the graph.  Errors as phx_trace. */
+phx_status phx_trace_batched(phx_ctx ctx, const phx_trace_args* args, void* stream);
+
+/* Autotuner: times phx_trace_batched on `sample` for candidate launch shapes (coordinate descent
+ * over back, front and pre-roll workgroups per CU, the schedule and the chunk size), writing into
+ * context-owned scratch outputs (the sample's output pointers are ignored), sets the fastest
+ * shape on the context and returns it in *best_host (may be NULL).  Synchronises `stream`.
+ * Errors as phx_trace, plus PHX_ERR_NOMEM. */
+phx_status phx_autotune(phx_ctx ctx, const phx_trace_args* sample, void* stream,
+                        phx_launch_config* best_host);
+
 /* Kernel timing for profiling.  While on, phx_trace brackets each kernel it launches with HIP
  * events on the trace stream; phx_get_timing waits for them and returns the accumulated
  * milliseconds per kernel kind since timing was switched on:

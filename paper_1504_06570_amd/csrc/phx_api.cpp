@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -49,6 +50,20 @@ struct phx_ctx_s {
     long pending_start[3] = {-1, -1, -1};
     double timing_ms[3] = {0, 0, 0};
     double timing_chunks = 0;
+    // launch shape, prefix-table cache, captured graphs (phx_trace_batched)
+    phx::LaunchConfig cfg;
+    int chunk_log2 = 26;
+    uint64_t* d_tiles = nullptr;
+    bool prefix_valid = false;
+    int prefix_begin = 0, prefix_end = 0;
+    uint64_t src_version = 0, prefix_version = 0;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, hipGraphExec_t> graphs;
+    float autotune_ms = 0.0f;
+    void graphs_clear() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
 };
 
 namespace {
@@ -257,6 +272,9 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_survivors);
     free_dev(c->d_counts);
     free_dev(c->d_state);
+    free_dev(c->d_tiles);
+    c->graphs_clear();
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -524,6 +542,8 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(sources)");
     c->src.assign(src, src + n_src);
+    c->src_version += 1;
+    c->graphs_clear();
     DevParams& H = c->host;
     H.src = c->d_src;
     H.sed_cdf = c->d_cdf;
@@ -534,23 +554,28 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
     return PHX_OK;
 }
 
-phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
-    if (!c) return PHX_ERR_INVALID;
+}  // extern "C"
+
+namespace {
+
+// Validation, uploads and workspace for a trace; fills the launch description.  May synchronise
+// `st` (new prefix table, growing workspace, changed parameter block).
+phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Launch& L,
+                   phx::Workspace& W) {
     if (!a) return fail(c, PHX_ERR_INVALID, "null trace arguments");
     if (!c->have_presc || !c->have_src)
         return fail(c, PHX_ERR_STATE, "load a prescription and sources first");
     if ((a->flags & PHX_F_ATMOSPHERE) && !c->have_screens)
         return fail(c, PHX_ERR_STATE, "PHX_F_ATMOSPHERE without loaded screens");
-    if ((a->flags & PHX_F_COATINGS) && !c->have_coat) {
-        bool coated = false;
-        for (int k = 0; k < c->presc.n_surfaces; ++k) coated |= c->presc.surf[k].coating >= 0;
-        if (coated) return fail(c, PHX_ERR_STATE, "PHX_F_COATINGS without loaded coatings");
-    }
-    for (int k = 0; k < c->presc.n_surfaces; ++k)
-        if (c->presc.surf[k].coating >= (c->have_coat ? c->host.n_coat : 0) &&
-            (a->flags & PHX_F_COATINGS))
-            return fail(c, PHX_ERR_INVALID, "surface %d uses coating %d beyond the loaded tables",
-                        k, c->presc.surf[k].coating);
+    if (a->flags & PHX_F_COATINGS)
+        for (int k = 0; k < c->presc.n_surfaces; ++k) {
+            const int co = c->presc.surf[k].coating;
+            if (co >= 0 && !c->have_coat)
+                return fail(c, PHX_ERR_STATE, "PHX_F_COATINGS without loaded coatings");
+            if (co >= 0 && co >= c->host.n_coat)
+                return fail(c, PHX_ERR_INVALID, "surface %d uses coating %d beyond the tables", k,
+                            co);
+        }
     const int n_src_all = (int)c->src.size();
     if (a->src_begin < 0 || a->src_end > n_src_all || a->src_begin >= a->src_end)
         return fail(c, PHX_ERR_INVALID, "source range [%d, %d) outside [0, %d)", a->src_begin,
@@ -562,8 +587,7 @@ phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
         a->pupil_margin < 0)
         return fail(c, PHX_ERR_INVALID, "bad exposure or pupil margin");
     if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
-    hipStream_t st = (hipStream_t)stream;
-    phx::Launch L{};
+    L = phx::Launch{};
     L.seed = a->seed;
     L.flags = a->flags;
     L.src_begin = a->src_begin;
@@ -592,19 +616,30 @@ phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
             pre[s + 1] = pre[s] + n;
         }
         L.total = pre[L.n_src];
-        if ((size_t)(L.n_src + 1) > c->prefix_cap) {
-            free_dev(c->d_prefix);
-            c->prefix_cap = 0;
-            hipError_t e = hipMalloc((void**)&c->d_prefix, (L.n_src + 1) * sizeof(uint64_t));
-            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "prefix table");
-            c->prefix_cap = L.n_src + 1;
+        const bool same = c->prefix_valid && c->prefix_begin == a->src_begin &&
+                          c->prefix_end == a->src_end && c->prefix_version == c->src_version;
+        if (!same) {
+            if ((size_t)(L.n_src + 1) > c->prefix_cap) {
+                hipError_t e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+                free_dev(c->d_prefix);
+                c->prefix_cap = 0;
+                e = hipMalloc((void**)&c->d_prefix, (L.n_src + 1) * sizeof(uint64_t));
+                if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "prefix table");
+                c->prefix_cap = L.n_src + 1;
+            }
+            // enqueued work may still read the previous table; the host vector must outlive
+            // the copy: both are handled by doing it synchronously after the stream drains
+            hipError_t e = hipStreamSynchronize(st);
+            if (e == hipSuccess)
+                e = hipMemcpy(c->d_prefix, pre.data(), pre.size() * sizeof(uint64_t),
+                              hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(c, e, "prefix upload");
+            c->prefix_valid = true;
+            c->prefix_begin = a->src_begin;
+            c->prefix_end = a->src_end;
+            c->prefix_version = c->src_version;
         }
-        // synchronous so that the host vector can go away
-        hipError_t e = hipStreamSynchronize(st);
-        if (e == hipSuccess)
-            e = hipMemcpy(c->d_prefix, pre.data(), pre.size() * sizeof(uint64_t),
-                          hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(c, e, "prefix upload");
         L.prefix = c->d_prefix;
     }
     if (a->photon_begin > UINT64_MAX - (L.total ? L.total : 0))
@@ -617,42 +652,222 @@ phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
             return fail(c, PHX_ERR_CAPACITY, "events need %llu slots, capacity %llu",
                         (unsigned long long)need, (unsigned long long)a->event_capacity);
     }
-    // Workspace: chunk = min(kChunk, total rounded up to a power of two), allocated once and grown
+    // Workspace: chunk = min(2^chunk_log2, total rounded up to a power of two); grows only
+    const uint64_t max_chunk = 1ull << c->chunk_log2;
     uint64_t chunk = 1024;
-    while (chunk < L.total && chunk < phx::kChunk) chunk <<= 1;
+    while (chunk < L.total && chunk < max_chunk) chunk <<= 1;
     if (chunk > c->ws_chunk) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
         free_dev(c->d_survivors);
         free_dev(c->d_state);
         c->ws_chunk = 0;
+        c->graphs_clear();
         e = hipMalloc((void**)&c->d_survivors, chunk * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, 7 * chunk * sizeof(double));
         if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "trace workspace: %s",
                                          hipGetErrorString(e));
         c->ws_chunk = chunk;
     }
-    chunk = c->ws_chunk;
+    chunk = std::min<uint64_t>(c->ws_chunk, max_chunk);
     const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
     if (n_chunks > c->counts_cap) {
-        // the previous counters may still be in use by enqueued work
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
         free_dev(c->d_counts);
+        free_dev(c->d_tiles);
         c->counts_cap = 0;
+        c->graphs_clear();
         e = hipMalloc((void**)&c->d_counts, n_chunks * sizeof(unsigned int));
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_tiles, 2 * n_chunks * sizeof(uint64_t));
         if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "chunk counters");
         c->counts_cap = n_chunks;
     }
-    const phx::Workspace W{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk};
-    phx_status r = upload_params(c, st);
-    if (r != PHX_OK) return r;
+    W = phx::Workspace{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk,
+                       (unsigned long long*)c->d_tiles};
+    return upload_params(c, st);
+}
+
+phx_status enqueue(phx_ctx c, const phx::Launch& L, const phx::Workspace& W, hipStream_t st,
+                   bool timed) {
     phx::Timing T;
-    T.on = c->timing;
+    T.on = timed && c->timing;
     T.record = timing_record;
     T.self = c;
-    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, st, T);
+    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, c->cfg, st, T);
     if (e != hipSuccess) return hip_fail(c, e, "trace kernel launch");
+    return PHX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    phx::Launch L;
+    phx::Workspace W;
+    phx_status r = prepare(c, a, st, L, W);
+    if (r != PHX_OK) return r;
+    return enqueue(c, L, W, st, true);
+}
+
+phx_status phx_trace_batched(phx_ctx c, const phx_trace_args* a, void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    phx::Launch L;
+    phx::Workspace W;
+    phx_status r = prepare(c, a, st, L, W);
+    if (r != PHX_OK) return r;
+    // graph key: the launch description, the workspace and the launch shape
+    std::string key((const char*)&L, sizeof(L));
+    key.append((const char*)&W, sizeof(W));
+    key.append((const char*)&c->cfg, sizeof(c->cfg));
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        if (c->graphs.size() >= 32) c->graphs_clear();
+        if (!c->cap_stream) {
+            hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreate");
+        }
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+        phx_status q = enqueue(c, L, W, c->cap_stream, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->cap_stream, &g);
+        if (q != PHX_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return q;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        it = c->graphs.emplace(key, x).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, st);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    return PHX_OK;
+}
+
+phx_status phx_set_launch_config(phx_ctx c, const phx_launch_config* cfg) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!cfg) return fail(c, PHX_ERR_INVALID, "null launch config");
+    if (cfg->chunk_log2 < 16 || cfg->chunk_log2 > 27 || cfg->generate_blocks_per_cu < 1 ||
+        cfg->generate_blocks_per_cu > 64 || cfg->front_blocks_per_cu < 1 ||
+        cfg->front_blocks_per_cu > 64 || cfg->back_blocks_per_cu < 1 ||
+        cfg->back_blocks_per_cu > 64 || (cfg->dynamic_tiles != 0 && cfg->dynamic_tiles != 1))
+        return fail(c, PHX_ERR_INVALID, "launch config out of range");
+    c->chunk_log2 = cfg->chunk_log2;
+    c->cfg.generate_per_cu = cfg->generate_blocks_per_cu;
+    c->cfg.front_per_cu = cfg->front_blocks_per_cu;
+    c->cfg.back_per_cu = cfg->back_blocks_per_cu;
+    c->cfg.dynamic = cfg->dynamic_tiles;
+    return PHX_OK;
+}
+
+phx_status phx_get_launch_config(phx_ctx c, phx_launch_config* cfg) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!cfg) return fail(c, PHX_ERR_INVALID, "null launch config");
+    cfg->chunk_log2 = c->chunk_log2;
+    cfg->generate_blocks_per_cu = c->cfg.generate_per_cu;
+    cfg->front_blocks_per_cu = c->cfg.front_per_cu;
+    cfg->back_blocks_per_cu = c->cfg.back_per_cu;
+    cfg->dynamic_tiles = c->cfg.dynamic;
+    return PHX_OK;
+}
+
+phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
+                        phx_launch_config* best) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!sample) return fail(c, PHX_ERR_INVALID, "null sample");
+    if (!c->have_presc) return fail(c, PHX_ERR_STATE, "load a prescription first");
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    // scratch outputs
+    uint32_t* img = nullptr;
+    unsigned long long* stats = nullptr;
+    double* mom = nullptr;
+    const size_t npix = (size_t)c->presc.nx * c->presc.ny;
+    hipError_t e = hipMalloc((void**)&img, npix * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&stats, PHX_STATS_LEN * sizeof(uint64_t));
+    if (e == hipSuccess && (sample->flags & PHX_F_MOMENTS))
+        e = hipMalloc((void**)&mom, c->src.size() * PHX_MOMENT_LEN * sizeof(double));
+    if (e != hipSuccess) {
+        free_dev(img);
+        free_dev(stats);
+        free_dev(mom);
+        return fail(c, PHX_ERR_NOMEM, "autotune scratch");
+    }
+    phx_trace_args a = *sample;
+    a.flags &= ~(uint32_t)PHX_F_EVENTS;
+    a.image_dev = img;
+    a.stats_dev = (uint64_t*)stats;
+    a.moments_dev = mom;
+    a.events_dev = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    phx_launch_config cur;
+    phx_get_launch_config(c, &cur);
+    phx_status status = PHX_OK;
+    auto measure = [&](const phx_launch_config& k, float& ms_out) -> phx_status {
+        phx_status r = phx_set_launch_config(c, &k);
+        if (r != PHX_OK) return r;
+        r = phx_trace_batched(c, &a, st);   // warm-up (prepares and captures)
+        if (r != PHX_OK) return r;
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(e0, st);
+            r = phx_trace_batched(c, &a, st);
+            if (r != PHX_OK) return r;
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(c, PHX_ERR_HIP, "sync");
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best_ms = std::min(best_ms, ms);
+        }
+        ms_out = best_ms;
+        return PHX_OK;
+    };
+    float cur_ms = 0.0f;
+    status = measure(cur, cur_ms);
+    // coordinate descent, one pass per knob
+    const int backs[] = {2, 3, 4, 6, 8};
+    const int fronts[] = {8, 16, 32, 48};
+    const int gens[] = {4, 8, 16};
+    const int chunks[] = {24, 25, 26};
+    for (int knob = 0; knob < 5 && status == PHX_OK; ++knob) {
+        std::vector<phx_launch_config> cand;
+        if (knob == 0) for (int v : backs) { auto k = cur; k.back_blocks_per_cu = v; cand.push_back(k); }
+        if (knob == 1) for (int v : fronts) { auto k = cur; k.front_blocks_per_cu = v; cand.push_back(k); }
+        if (knob == 2) for (int v : gens) { auto k = cur; k.generate_blocks_per_cu = v; cand.push_back(k); }
+        if (knob == 3) for (int v = 0; v < 2; ++v) { auto k = cur; k.dynamic_tiles = v; cand.push_back(k); }
+        if (knob == 4) for (int v : chunks) { auto k = cur; k.chunk_log2 = v; cand.push_back(k); }
+        for (const auto& k : cand) {
+            if (std::memcmp(&k, &cur, sizeof(k)) == 0) continue;
+            float ms = 0.0f;
+            status = measure(k, ms);
+            if (status != PHX_OK) break;
+            if (ms < cur_ms) {
+                cur_ms = ms;
+                cur = k;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    free_dev(img);
+    free_dev(stats);
+    free_dev(mom);
+    c->graphs_clear();
+    if (status != PHX_OK) return status;
+    phx_set_launch_config(c, &cur);
+    c->autotune_ms = cur_ms;
+    if (best) *best = cur;
     return PHX_OK;
 }
 

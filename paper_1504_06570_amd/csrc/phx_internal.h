@@ -94,7 +94,19 @@ struct Workspace {
     uint64_t n_chunks;
     double* state;             // [7][chunk]; null = run the fused single kernel
     uint64_t chunk;
+    unsigned long long* tiles; // [n_chunks][2] tile counters of the dynamic schedule
 };
+
+// Launch shape (tunable): workgroups per compute unit of each stage, and the schedule of the
+// sky and optics stages (static grid-stride, or tiles of kTileIters x 256 photons taken from a
+// device counter).
+struct LaunchConfig {
+    int generate_per_cu = 8;
+    int front_per_cu = 32;
+    int back_per_cu = 4;
+    int dynamic = 0;
+};
+constexpr int kTileIters = 8;
 
 // Optional per-kernel timing: events recorded before/after each kernel launch.
 struct Timing {
@@ -105,7 +117,7 @@ struct Timing {
 };
 
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                        hipStream_t stream, const Timing& T);
+                        const LaunchConfig& cfg, hipStream_t stream, const Timing& T);
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, hipStream_t stream);
 

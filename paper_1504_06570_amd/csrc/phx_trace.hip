@@ -20,7 +20,6 @@
 namespace phx {
 namespace {
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kHcEvM = 1.2398419843320026e-6;  // h c / e in eV m
 constexpr double kNewtonTol = 1e-12;             // m
 constexpr int kNewtonMax = 16;
@@ -792,6 +791,32 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
     stats_flush(L, s_stats, 0u, 0u);
 }
 
+// Block-uniform work distribution over [0, n): static (tile = block, block + grid, ...) or
+// dynamic (tiles of kTileIters x blockDim elements claimed from a device counter).
+struct Tiles {
+    unsigned long long* ctr;   // null: static
+    uint64_t tile, sub, n;
+    __device__ bool next(unsigned long long* s_tile) {
+        if (!ctr) {
+            if (sub) tile += gridDim.x;
+            sub = 1;
+            return tile * blockDim.x < n;
+        }
+        if (sub == 0 || sub == kTileIters) {
+            __syncthreads();
+            if (threadIdx.x == 0) *s_tile = atomicAdd(ctr, 1ull);
+            __syncthreads();
+            tile = *s_tile * kTileIters;
+            sub = 0;
+        } else {
+            tile += 1;
+        }
+        sub += 1;
+        return tile * blockDim.x < n;
+    }
+    __device__ uint64_t index() const { return tile * blockDim.x + threadIdx.x; }
+};
+
 // Front half of the trace for the chunk's photons (the survivor list, or every photon when
 // surv is null): sky sampling and the atmosphere, leaving the start-plane state in SoA arrays
 // st[0..6][i] = p_x, p_y, p_z, n_x, n_y, n_z, lambda.
@@ -801,11 +826,15 @@ __global__ __launch_bounds__(kBlock) void front_kernel(const DevParams* __restri
                                                        const uint32_t* __restrict__ surv,
                                                        const unsigned int* __restrict__ count,
                                                        uint64_t n_all, double* __restrict__ st,
-                                                       uint64_t st_stride) {
+                                                       uint64_t st_stride,
+                                                       unsigned long long* tile_ctr) {
+    __shared__ unsigned long long s_tile;
     const DevParams& P = *Pg;
     const uint64_t n = surv ? (uint64_t)*count : n_all;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    Tiles T{tile_ctr, blockIdx.x, 0, n};
+    while (T.next(&s_tile)) {
+        const uint64_t r = T.index();
+        if (r >= n) continue;
         const uint64_t g = begin + (surv ? (uint64_t)surv[r] : r);
         int si;
         uint64_t idx;
@@ -833,20 +862,21 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
                                                       const uint32_t* __restrict__ surv,
                                                       const unsigned int* __restrict__ count,
                                                       uint64_t n_all, const double* __restrict__ st,
-                                                      uint64_t st_stride) {
+                                                      uint64_t st_stride,
+                                                      unsigned long long* tile_ctr) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
     __shared__ uint32_t s_win[kWin * kWin];
+    __shared__ unsigned long long s_tile;
     __shared__ int s_org;   // window origin: (i0 << 16) | j0, or -1 before the first detection
     for (int i = threadIdx.x; i < kWin * kWin; i += blockDim.x) s_win[i] = 0;
     if (threadIdx.x == 0) s_org = -1;
     stats_init(s_stats);
     const DevParams& P = *Pg;
     const uint64_t n = surv ? (uint64_t)*count : n_all;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t n_iter = (n + stride - 1) / stride;      // the same for every thread
-    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Tiles T{tile_ctr, blockIdx.x, 0, n};
     uint32_t newton = 0, traced = 0;
-    for (uint64_t it = 0; it < n_iter; ++it, r += stride) {
+    while (T.next(&s_tile)) {   // block-uniform: every lane takes part in bin_photon's ballots
+        const uint64_t r = T.index();
         int pix = -1;
         if (r < n) {
             const uint64_t g = begin + (surv ? (uint64_t)surv[r] : r);
@@ -928,7 +958,7 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
 }  // namespace
 
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                        hipStream_t stream, const Timing& T) {
+                        const LaunchConfig& cfg, hipStream_t stream, const Timing& T) {
     auto mark = [&](int kind, int edge) {
         if (T.on) T.record(T.self, kind, edge, stream);
     };
@@ -945,11 +975,13 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
     }
     const uint64_t chunk = W.chunk;
     const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
-    if (preroll) {
-        if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
+    if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
+    if (preroll)
         hipLaunchKernelGGL(fill_u32, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256), 0,
                            stream, W.counts, n_chunks, 0u);
-    }
+    if (cfg.dynamic)
+        hipLaunchKernelGGL(fill_u32, dim3((unsigned)((4 * n_chunks + 255) / 256)), dim3(256), 0,
+                           stream, (unsigned int*)W.tiles, 4 * n_chunks, 0u);
     for (uint64_t c = 0; c < n_chunks; ++c) {
         const uint64_t begin = c * chunk;
         const uint64_t len = L.total - begin < chunk ? L.total - begin : chunk;
@@ -957,7 +989,7 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
         const unsigned int* cnt = nullptr;
         if (preroll) {
             const uint64_t want = (len + kBlock - 1) / kBlock;
-            const uint64_t cap = (uint64_t)n_cu * 8;
+            const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
             const int ggrid = (int)(want < cap ? want : cap);
             mark(0, 0);
             hipLaunchKernelGGL(generate_kernel, dim3(ggrid), dim3(kBlock), 0, stream, dparams, L,
@@ -967,23 +999,26 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
             cnt = W.counts + c;
         }
         const uint64_t want = (len + kBlock - 1) / kBlock;
-        const uint64_t fcap = (uint64_t)n_cu * 32, bcap = (uint64_t)n_cu * 4;
+        const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
+        const uint64_t bcap = (uint64_t)n_cu * cfg.back_per_cu;
+        unsigned long long* ft = cfg.dynamic ? W.tiles + 2 * c : nullptr;
+        unsigned long long* bt = cfg.dynamic ? W.tiles + 2 * c + 1 : nullptr;
         const dim3 fg((unsigned)(want < fcap ? want : fcap)), bg((unsigned)(want < bcap ? want : bcap));
         mark(1, 0);
         if (L.any_sersic)
             hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, W.state, chunk);
+                               surv, cnt, len, W.state, chunk, ft);
         else
             hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, W.state, chunk);
+                               surv, cnt, len, W.state, chunk, ft);
         mark(1, 1);
         mark(2, 0);
         if (L.any_zernike)
             hipLaunchKernelGGL(back_kernel<true>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, (const double*)W.state, chunk);
+                               surv, cnt, len, (const double*)W.state, chunk, bt);
         else
             hipLaunchKernelGGL(back_kernel<false>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, (const double*)W.state, chunk);
+                               surv, cnt, len, (const double*)W.state, chunk, bt);
         mark(2, 1);
     }
     return hipGetLastError();

@@ -74,6 +74,15 @@ class TraceArgs(C.Structure):
                 ("event_capacity", C.c_uint64)]
 
 
+class LaunchConfig(C.Structure):
+    _fields_ = [("chunk_log2", C.c_int32), ("generate_blocks_per_cu", C.c_int32),
+                ("front_blocks_per_cu", C.c_int32), ("back_blocks_per_cu", C.c_int32),
+                ("dynamic_tiles", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 EVENT_DTYPE = np.dtype([("photon", np.uint64), ("source", np.int32), ("status", np.int32),
                         ("surface", np.int32), ("pix_i", np.int32), ("pix_j", np.int32),
                         ("newton", np.int32), ("x", np.float64), ("y", np.float64),
@@ -107,9 +116,15 @@ def lib():
         L.phx_trace.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
         L.phx_set_timing.argtypes = [C.c_void_p, C.c_int32]
         L.phx_get_timing.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32]
+        L.phx_set_launch_config.argtypes = [C.c_void_p, C.POINTER(LaunchConfig)]
+        L.phx_get_launch_config.argtypes = [C.c_void_p, C.POINTER(LaunchConfig)]
+        L.phx_trace_batched.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
+        L.phx_autotune.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p,
+                                   C.POINTER(LaunchConfig)]
         for f in ("phx_create", "phx_load_prescription", "phx_set_perturbation",
                   "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace",
-                  "phx_set_timing", "phx_get_timing"):
+                  "phx_set_timing", "phx_get_timing", "phx_set_launch_config",
+                  "phx_get_launch_config", "phx_trace_batched", "phx_autotune"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -239,10 +254,8 @@ class Tracer:
         p = self.scene.prescription
         return torch.zeros((p.chip.ny, p.chip.nx), dtype=torch.int32, device=self.device)
 
-    def trace(self, image=None, *, flags=None, seed=None, src_begin=0, src_end=None,
-              photon_begin=0, photon_count=0, stats=None, moments=None, event_stride=0,
-              events=None, stream=None, exposure=None):
-        """Enqueue one trace.  Returns (image, stats, moments, events) tensors (events raw bytes)."""
+    def _args(self, image, flags, seed, src_begin, src_end, photon_begin, photon_count, stats,
+              moments, event_stride, events, exposure):
         import torch
         sc = self.scene
         if image is None:
@@ -276,8 +289,44 @@ class Tracer:
             a.events_dev = events.data_ptr()
             a.event_stride = event_stride
             a.event_capacity = events.numel() // EVENT_DTYPE.itemsize
-        self._check(self.L.phx_trace(self.ctx, C.byref(a), _stream_handle(stream)))
+        return a, image, events
+
+    def trace(self, image=None, *, flags=None, seed=None, src_begin=0, src_end=None,
+              photon_begin=0, photon_count=0, stats=None, moments=None, event_stride=0,
+              events=None, stream=None, exposure=None, batched=False):
+        """Enqueue one trace of sources [src_begin, src_end).  `batched` replays a captured graph
+        of the whole launch (phx_trace_batched).  Returns (image, stats, moments, events)
+        tensors (events as raw bytes)."""
+        a, image, events = self._args(image, flags, seed, src_begin, src_end, photon_begin,
+                                      photon_count, stats, moments, event_stride, events, exposure)
+        fn = self.L.phx_trace_batched if batched else self.L.phx_trace
+        self._check(fn(self.ctx, C.byref(a), _stream_handle(stream)))
         return image, stats, moments, events
+
+    def launch_config(self) -> dict:
+        cfg = LaunchConfig()
+        self._check(self.L.phx_get_launch_config(self.ctx, C.byref(cfg)))
+        return cfg.as_dict()
+
+    def set_launch_config(self, **kw):
+        """Change the launch shape; unspecified fields keep their value."""
+        cfg = LaunchConfig()
+        self._check(self.L.phx_get_launch_config(self.ctx, C.byref(cfg)))
+        for k, v in kw.items():
+            if k not in cfg.as_dict():
+                raise KeyError(k)
+            setattr(cfg, k, int(v))
+        self._check(self.L.phx_set_launch_config(self.ctx, C.byref(cfg)))
+
+    def autotune(self, *, flags=None, seed=None, src_begin=0, src_end=None, photon_count=0,
+                 stream=None) -> dict:
+        """Pick the launch shape that traces this sample fastest (the sample's outputs go to
+        scratch buffers) and keep it; returns the chosen configuration."""
+        a, _, _ = self._args(self.new_image(), flags, seed, src_begin, src_end, 0, photon_count,
+                             None, None, 0, None, None)
+        cfg = LaunchConfig()
+        self._check(self.L.phx_autotune(self.ctx, C.byref(a), _stream_handle(stream), C.byref(cfg)))
+        return cfg.as_dict()
 
     def set_timing(self, on: bool):
         self._check(self.L.phx_set_timing(self.ctx, 1 if on else 0))

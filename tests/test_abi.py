@@ -40,9 +40,9 @@ def test_struct_sizes_match_header_layout():
 #include <stdio.h>
 #include "phx.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(phx_surface), sizeof(phx_prescription),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phx_surface), sizeof(phx_prescription),
          sizeof(phx_atmosphere), sizeof(phx_source), sizeof(phx_event), sizeof(phx_trace_args),
-         offsetof(phx_trace_args, image_dev));
+         offsetof(phx_trace_args, image_dev), sizeof(phx_launch_config));
   return 0;
 }
 """
@@ -54,7 +54,7 @@ int main(void) {
         got = [int(x) for x in subprocess.check_output([exe], text=True).split()]
     want = [ctypes.sizeof(P.Surface), ctypes.sizeof(P.Prescription), ctypes.sizeof(P.Atmosphere),
             ctypes.sizeof(P.Source), P.EVENT_DTYPE.itemsize, ctypes.sizeof(P.TraceArgs),
-            P.TraceArgs.image_dev.offset]
+            P.TraceArgs.image_dev.offset, ctypes.sizeof(P.LaunchConfig)]
     assert got == want
 
 
@@ -67,3 +67,5 @@ def test_create_without_gpu_is_an_error():
     assert P.lib().phx_create(0, ctypes.byref(h)) == -1
     assert P.lib().phx_trace(None, None, None) == -1
     assert P.lib().phx_last_error(None) == b"null context"
+    assert P.lib().phx_trace_batched(None, None, None) == -1
+    assert P.lib().phx_autotune(None, None, None, None) == -1
