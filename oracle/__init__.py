@@ -121,6 +121,9 @@ def lib():
             L.orc_gamma.argtypes = [C.c_uint32, C.c_int32, C.c_uint64, C.c_double,
                                     C.POINTER(C.c_double)]
             L.orc_gamma.restype = C.c_int
+            L.orc_jacobian.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_uint64,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32)]
             _lib = L
     return _lib
 
@@ -281,6 +284,34 @@ class Oracle:
         if events:
             return np.concatenate(out) if out else np.zeros(0, EVENT_DTYPE)
         return None
+
+    def jacobian(self, src: int, begin: int, count: int, h, threads: int = 1):
+        """d(xe, ye)/d(theta) of photons [begin, begin + count) of one source: Richardson-
+        extrapolated central differences with steps h (22 absolute values), every decision held
+        fixed.  Returns (jac [count, 2, 22], frozen [count] bool)."""
+        h = np.ascontiguousarray(h, np.float64)
+        assert h.shape == (N_THETA,) and np.all(h > 0)
+        jac = np.zeros((count, 2, N_THETA), np.float64)
+        frozen = np.zeros(count, np.int32)
+        hp = h.ctypes.data_as(C.POINTER(C.c_double))
+
+        def run(a, b):
+            rc = lib().orc_jacobian(C.byref(self.sc), src, begin + a, b - a, hp,
+                                    jac[a:b].ctypes.data_as(C.POINTER(C.c_double)),
+                                    frozen[a:b].ctypes.data_as(C.POINTER(C.c_int32)))
+            assert rc == 0
+
+        if threads <= 1 or count < 2 * threads:
+            run(0, count)
+        else:
+            cuts = np.linspace(0, count, threads + 1).astype(int)
+            ths = [threading.Thread(target=run, args=(cuts[w], cuts[w + 1]))
+                   for w in range(threads)]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+        return jac, frozen.astype(bool)
 
     # primitives -----------------------------------------------------------------------------
     def sag(self, k, x, y):

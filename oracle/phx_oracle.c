@@ -731,3 +731,57 @@ int orc_trace(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count, 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Derivative of each photon's electron position (xe, ye) with respect to the 22 perturbation
+ * parameters.  The paper has no derivative; this is the plain limit definition of one: central
+ * differences f'(t) ~ D(h) = (f(t + h) - f(t - h)) / 2h, taken at h and h/2 and combined by one
+ * Richardson step (4 D(h/2) - D(h)) / 3, whose error is O(h^4).  The photon keeps its random
+ * numbers (they are keyed by photon index), and every discrete decision is held fixed: a photon
+ * counts only if it is converted (DETECTED or OFF_CHIP) in the nominal trace and in all four
+ * perturbed traces of every parameter, with the same deciding surface.  frozen[i] = 1 for such
+ * photons and 0 otherwise (their rows are zero).  jac is [count][2][22]. */
+int orc_jacobian(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count,
+                 const double* h, double* jac, int32_t* frozen) {
+    if (src < 0 || src >= sc->n_src) return -1;
+    orc_scene w = *sc;
+    static const double off[4] = {1.0, -1.0, 0.5, -0.5};
+    for (uint64_t i = 0; i < count; ++i) {
+        double* J = jac + i * 2 * ORC_N_THETA;
+        memset(J, 0, 2 * ORC_N_THETA * sizeof(double));
+        frozen[i] = 0;
+        orc_event e0;
+        trace_one(sc, src, begin + i, NULL, &e0);
+        if (e0.status != ORC_DETECTED && e0.status != ORC_OFF_CHIP) continue;
+        int ok = 1;
+        for (int j = 0; j < ORC_N_THETA && ok; ++j) {
+            double f[4][2];
+            for (int m = 0; m < 4; ++m) {
+                memcpy(w.theta, sc->theta, sizeof(w.theta));
+                w.theta[j] += off[m] * h[j];
+                prepare_transforms(&w);
+                orc_event e;
+                trace_one(&w, src, begin + i, NULL, &e);
+                if ((e.status != ORC_DETECTED && e.status != ORC_OFF_CHIP) ||
+                    e.surface != e0.surface) {
+                    ok = 0;
+                    break;
+                }
+                f[m][0] = e.xe;
+                f[m][1] = e.ye;
+            }
+            if (!ok) break;
+            for (int c = 0; c < 2; ++c) {
+                double d1 = (f[0][c] - f[1][c]) / (2.0 * h[j]);
+                double d2 = (f[2][c] - f[3][c]) / h[j];
+                J[c * ORC_N_THETA + j] = (4.0 * d2 - d1) / 3.0;
+            }
+        }
+        if (!ok) {
+            memset(J, 0, 2 * ORC_N_THETA * sizeof(double));
+            continue;
+        }
+        frozen[i] = 1;
+    }
+    return 0;
+}

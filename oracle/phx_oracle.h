@@ -98,6 +98,10 @@ void orc_release(orc_scene* sc);
 /* Trace photons [begin, begin+count) of source `src`; events may be NULL; image may be NULL. */
 int  orc_trace(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count,
                uint32_t* image, orc_event* events);
+/* d(xe, ye)/d(theta) of photons [begin, begin+count) by Richardson-extrapolated central
+ * differences with frozen decisions; jac [count][2][22], frozen [count]. */
+int  orc_jacobian(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count,
+                  const double* h, double* jac, int32_t* frozen);
 /* Primitives exported for the pin tests. */
 void   orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_u01(uint32_t w);

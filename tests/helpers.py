@@ -81,3 +81,36 @@ def plate_scene(thickness, tilt, lam=600e-9, n_photons=200):
     th[7] = tilt  # camera tx
     s.perturbation = th
     return s
+
+
+def fold_scene(D=2.0, delta=0.3, r0=0.5, n_photons=300, physics=0, lam=600e-9):
+    """Flat mirror at z = 0 (perturbation group 1, the surface that also carries the Zernike
+    terms) reflecting vertical light up to a flat detector at z = D (group 2, pivot a height
+    `delta` above its vertex).  At zero perturbation the landing point is the pupil sample, and
+    the first derivatives of the landing point have closed forms."""
+    m = Op.Surface("FLAT", Op.MIRROR, 0.0, 0.0, 0.0, (0.0,) * 8, 0.0, r0, Op.VACUUM, -1, 1)
+    det = Op.Surface("DET", Op.DETECTOR, D, 0.0, 0.0, (0.0,) * 8, 0.0, 2.0, Op.SILICON, -1, 2)
+    chip = Op.Chip(0.0, 0.0, pixel=1e-3, nx=1000, ny=1000)
+    p = Op.Prescription("fold", [m, det], chip, pupil_r_in=0.0, pupil_r_out=0.9 * r0,
+                        z_start=D + 1.0, obscuration_z=0.0, obscuration_r=0.0,
+                        group_pivot=((0.0, 0.0, 0.0), (0.0, 0.0, 0.1), (0.0, 0.0, D + delta)))
+    src = point_sources([0.0], [0.0], n_photons, lam, lam)
+    return C.Scene("fold", p, src, physics=physics, seed=14)
+
+
+def noll_zernike(j, u, v):
+    """Noll-indexed Zernike polynomial from its radial/azimuthal definition (Noll 1976)."""
+    from math import factorial
+    nm = {4: (2, 0), 5: (2, -2), 6: (2, 2), 7: (3, -1), 8: (3, 1), 9: (3, -3), 10: (3, 3),
+          11: (4, 0), 12: (4, 2), 13: (4, -2), 14: (4, 4), 15: (4, -4)}
+    n, m = nm[j]
+    rho = np.hypot(u, v)
+    phi = np.arctan2(v, u)
+    ma = abs(m)
+    R = sum((-1) ** k * factorial(n - k) / (factorial(k) * factorial((n + ma) // 2 - k) *
+                                             factorial((n - ma) // 2 - k)) * rho ** (n - 2 * k)
+            for k in range((n - ma) // 2 + 1))
+    if m == 0:
+        return np.sqrt(n + 1) * R
+    ang = np.cos(ma * phi) if m > 0 else np.sin(ma * phi)
+    return np.sqrt(2 * (n + 1)) * R * ang
