@@ -158,9 +158,17 @@ typedef struct {
 #define PHX_STAT_TRACED (PHX_STAT_NEWTON + 1)
 #define PHX_STATS_LEN (PHX_STAT_TRACED + 1)
 
-/* Moments buffer layout (double): per source, [n, sum x, sum y, sum x^2, sum y^2, sum xy] of
- * electron positions of photons that converted in silicon (status DETECTED or OFF_CHIP). */
-#define PHX_MOMENT_LEN 6
+/* Moments buffer layout (uint64 words): per source PHX_MOMENT_WORDS words holding exact sums
+ * over the photons that converted in silicon (status DETECTED or OFF_CHIP) of their electron
+ * position (x, y) in the detector frame, quantised to X = round(x * 2^PHX_MOMENT_Q_LOG2),
+ * Y likewise (round half to even; requires |x|, |y| < 1 m):
+ *   word 0        n (number of converted photons), word 1 zero,
+ *   words 2-3     sum X      words 4-5   sum Y      words 6-7   sum X^2
+ *   words 8-9     sum Y^2    words 10-11 sum X Y
+ * each sum a two's-complement 128-bit integer, low word first.  Integer addition is exact and
+ * associative, so the words do not depend on launch shape, batching or execution order. */
+#define PHX_MOMENT_WORDS 12
+#define PHX_MOMENT_Q_LOG2 44
 
 typedef struct {
     uint32_t seed;          /* Philox key word 0 (key word 1 = source index)                  */
@@ -173,7 +181,7 @@ typedef struct {
     double pupil_margin;    /* annulus enlargement (section 2.2: slightly larger aperture)      */
     uint32_t* image_dev;    /* [ny][nx], accumulated (+1 per detected photon); required        */
     uint64_t* stats_dev;    /* [PHX_STATS_LEN], accumulated; may be NULL                        */
-    double* moments_dev;    /* [n_sources][PHX_MOMENT_LEN], accumulated; NULL unless MOMENTS   */
+    uint64_t* moments_dev;  /* [n_sources][PHX_MOMENT_WORDS], accumulated; NULL unless MOMENTS */
     phx_event* events_dev;  /* NULL unless EVENTS                                               */
     uint64_t event_stride;  /* photon g of the launch (sources concatenated in order, photons
                                in index order) is recorded at slot g / stride iff g % stride == 0 */
@@ -263,6 +271,28 @@ phx_status phx_trace_batched(phx_ctx ctx, const phx_trace_args* args, void* stre
  * Errors as phx_trace, plus PHX_ERR_NOMEM. */
 phx_status phx_autotune(phx_ctx ctx, const phx_trace_args* sample, void* stream,
                         phx_launch_config* best_host);
+
+/* Adjoint trace: the gradient of a weighted sum of per-source moments with respect to the
+ * PHX_N_THETA perturbation parameters (section 2.4.1 misalignments: group 1 and group 2 shift
+ * x, y, tilt x, y, piston; then the primary's Zernike Z4..Z15 amplitudes, section 2.4.1 surface
+ * perturbations), as the pathwise derivative of the electron positions with every discrete
+ * decision held at its forward value.  `args` names the same photons as the forward trace (its
+ * output pointers are ignored; the pre-roll is switched on with coatings: it removes no
+ * converted photon).  Only converted photons (DETECTED or OFF_CHIP) contribute, photon i of
+ * source s with cotangents
+ *     xbar = g[0] + g[2] (x_i - g[5]) + g[4] (y_i - g[6])
+ *     ybar = g[1] + g[3] (y_i - g[6]) + g[4] (x_i - g[5]),  g = seed_dev + 8 (s - src_begin)
+ * (for mean and central second moments: g = (dL/dmx, dL/dmy, 2 dL/dIxx, 2 dL/dIyy, dL/dIxy) / n
+ * and (mx, my) the source's mean position).  seed_dev: device [src_end - src_begin][8] doubles.
+ * grad_dev: device [PHX_N_THETA] doubles, overwritten with sum_i xbar_i dx_i/dtheta +
+ * ybar_i dy_i/dtheta; the sum is taken in a fixed order for a fixed launch shape.  jac_dev:
+ * optional device [slots][2][PHX_N_THETA] doubles; photon g of the launch (indexed as events)
+ * with g % jac_stride == 0 gets its own (dx/dtheta, dy/dtheta), zero if not converted.
+ * Enqueued on `stream`; may synchronise it to grow the context's tape.  Errors: as phx_trace,
+ * PHX_ERR_CAPACITY if jac_capacity < ceil(total / jac_stride). */
+phx_status phx_adjoint(phx_ctx ctx, const phx_trace_args* args, const double* seed_dev,
+                       double* grad_dev, double* jac_dev, uint64_t jac_stride,
+                       uint64_t jac_capacity, void* stream);
 
 /* Kernel timing for profiling.  While on, phx_trace brackets each kernel it launches with HIP
  * events on the trace stream; phx_get_timing waits for them and returns the accumulated

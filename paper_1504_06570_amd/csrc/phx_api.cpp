@@ -60,6 +60,13 @@ struct phx_ctx_s {
     hipStream_t cap_stream = nullptr;
     std::map<std::string, hipGraphExec_t> graphs;
     float autotune_ms = 0.0f;
+    // adjoint workspace
+    int adj_per_cu = 2;
+    double* d_tape = nullptr;
+    uint64_t tape_cap = 0;
+    double* d_partial = nullptr;
+    uint64_t rows_cap = 0;
+    double* d_colsum = nullptr;
     void graphs_clear() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
@@ -139,6 +146,8 @@ void build_surfaces(phx_ctx c) {
             if (s.alpha[i] != 0.0) d.asphere = 2;                  // an odd power is present
         d.r_in = s.r_inner;
         d.r_out = s.r_outer;
+        d.z_vertex = s.z_vertex;
+        d.group = (s.group == 1 || s.group == 2) ? s.group : 0;
         d.r_in2 = s.r_inner * s.r_inner;
         d.r_out2 = s.r_outer * s.r_outer;
         double dx = 0, dy = 0, dz = 0, tx = 0, ty = 0;
@@ -161,27 +170,49 @@ void build_surfaces(phx_ctx c) {
         }
         for (int i = 0; i < 9; ++i) d.R[i] = R[i];
     }
+    // medium in front of each surface, in travel order (mirrors keep it, lenses set it)
+    bool glass = false;
+    for (int k = 0; k < p.n_surfaces; ++k) {
+        H.surf[k].glass_in = glass ? 1 : 0;
+        if (p.surf[k].kind == PHX_REFRACT) glass = p.surf[k].medium == PHX_GLASS;
+    }
+    for (int g = 0; g < 3; ++g) {
+        double tx = 0.0, ty = 0.0;
+        if (g > 0) {
+            tx = c->theta[5 * (g - 1) + 2];
+            ty = c->theta[5 * (g - 1) + 3];
+        }
+        H.group_cs[g][0] = std::cos(tx);
+        H.group_cs[g][1] = std::sin(tx);
+        H.group_cs[g][2] = std::cos(ty);
+        H.group_cs[g][3] = std::sin(ty);
+        for (int i = 0; i < 3; ++i) H.group_pivot[g][i] = p.group_pivot[g][i];
+    }
     // Zernike deformation of surface 0 (Noll Z4..Z15, amplitudes theta[10..21]) expanded into the
     // monomials u^a v^b of degree <= 4, ordered as the kernel's zernike_poly expects.
     enum { C00, C10, C01, C20, C11, C02, C30, C21, C12, C03, C40, C31, C22, C13, C04 };
-    const double* a = c->theta + 10;
     const double s3 = std::sqrt(3.0), s5 = std::sqrt(5.0), s6 = std::sqrt(6.0);
     const double s8 = std::sqrt(8.0), s10 = std::sqrt(10.0);
+    double (*B)[phx::kNZernPoly] = H.zern_basis;
+    std::memset(H.zern_basis, 0, sizeof(H.zern_basis));
+    B[0][C00] = -s3;  B[0][C20] = 2 * s3;  B[0][C02] = 2 * s3;                    // Z4
+    B[1][C11] = 2 * s6;                                                          // Z5
+    B[2][C20] = s6;   B[2][C02] = -s6;                                            // Z6
+    B[3][C21] = 3 * s8; B[3][C03] = 3 * s8; B[3][C01] = -2 * s8;                  // Z7
+    B[4][C30] = 3 * s8; B[4][C12] = 3 * s8; B[4][C10] = -2 * s8;                  // Z8
+    B[5][C21] = 3 * s8; B[5][C03] = -s8;                                         // Z9
+    B[6][C30] = s8;   B[6][C12] = -3 * s8;                                        // Z10
+    B[7][C40] = 6 * s5; B[7][C22] = 12 * s5; B[7][C04] = 6 * s5;                  // Z11
+    B[7][C20] = -6 * s5; B[7][C02] = -6 * s5; B[7][C00] = s5;
+    B[8][C40] = 4 * s10; B[8][C04] = -4 * s10;                                   // Z12
+    B[8][C20] = -3 * s10; B[8][C02] = 3 * s10;
+    B[9][C31] = 8 * s10; B[9][C13] = 8 * s10; B[9][C11] = -6 * s10;              // Z13
+    B[10][C40] = s10; B[10][C22] = -6 * s10; B[10][C04] = s10;                   // Z14
+    B[11][C31] = 4 * s10; B[11][C13] = -4 * s10;                                 // Z15
+    const double* a = c->theta + 10;
     double z[phx::kNZernPoly] = {0};
-    z[C00] += -s3 * a[0];  z[C20] += 2 * s3 * a[0];  z[C02] += 2 * s3 * a[0];           // Z4
-    z[C11] += 2 * s6 * a[1];                                                             // Z5
-    z[C20] += s6 * a[2];   z[C02] += -s6 * a[2];                                         // Z6
-    z[C21] += 3 * s8 * a[3]; z[C03] += 3 * s8 * a[3]; z[C01] += -2 * s8 * a[3];         // Z7
-    z[C30] += 3 * s8 * a[4]; z[C12] += 3 * s8 * a[4]; z[C10] += -2 * s8 * a[4];         // Z8
-    z[C21] += 3 * s8 * a[5]; z[C03] += -s8 * a[5];                                      // Z9
-    z[C30] += s8 * a[6];   z[C12] += -3 * s8 * a[6];                                     // Z10
-    z[C40] += 6 * s5 * a[7]; z[C22] += 12 * s5 * a[7]; z[C04] += 6 * s5 * a[7];         // Z11
-    z[C20] += -6 * s5 * a[7]; z[C02] += -6 * s5 * a[7]; z[C00] += s5 * a[7];
-    z[C40] += 4 * s10 * a[8]; z[C04] += -4 * s10 * a[8];                                // Z12
-    z[C20] += -3 * s10 * a[8]; z[C02] += 3 * s10 * a[8];
-    z[C31] += 8 * s10 * a[9]; z[C13] += 8 * s10 * a[9]; z[C11] += -6 * s10 * a[9];     // Z13
-    z[C40] += s10 * a[10]; z[C22] += -6 * s10 * a[10]; z[C04] += s10 * a[10];         // Z14
-    z[C31] += 4 * s10 * a[11]; z[C13] += -4 * s10 * a[11];                             // Z15
+    for (int j = 0; j < phx::kNZern; ++j)
+        for (int m = 0; m < phx::kNZernPoly; ++m) z[m] += B[j][m] * a[j];
     bool any = false;
     for (int j = 0; j < phx::kNZern; ++j) any |= a[j] != 0.0;
     for (int j = 0; j < phx::kNZernPoly; ++j) H.zern[j] = z[j];
@@ -273,6 +304,9 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_counts);
     free_dev(c->d_state);
     free_dev(c->d_tiles);
+    free_dev(c->d_tape);
+    free_dev(c->d_partial);
+    free_dev(c->d_colsum);
     c->graphs_clear();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -561,7 +595,7 @@ namespace {
 // Validation, uploads and workspace for a trace; fills the launch description.  May synchronise
 // `st` (new prefix table, growing workspace, changed parameter block).
 phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Launch& L,
-                   phx::Workspace& W) {
+                   phx::Workspace& W, bool need_image = true) {
     if (!a) return fail(c, PHX_ERR_INVALID, "null trace arguments");
     if (!c->have_presc || !c->have_src)
         return fail(c, PHX_ERR_STATE, "load a prescription and sources first");
@@ -580,9 +614,11 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     if (a->src_begin < 0 || a->src_end > n_src_all || a->src_begin >= a->src_end)
         return fail(c, PHX_ERR_INVALID, "source range [%d, %d) outside [0, %d)", a->src_begin,
                     a->src_end, n_src_all);
-    if (!a->image_dev) return fail(c, PHX_ERR_INVALID, "null image");
-    if ((a->flags & PHX_F_MOMENTS) && !a->moments_dev)
+    if (need_image && !a->image_dev) return fail(c, PHX_ERR_INVALID, "null image");
+    if (need_image && (a->flags & PHX_F_MOMENTS) && !a->moments_dev)
         return fail(c, PHX_ERR_INVALID, "PHX_F_MOMENTS without a moments buffer");
+    if ((a->flags & PHX_F_MOMENTS) && c->presc.surf[c->presc.n_surfaces - 1].r_outer > 0.5)
+        return fail(c, PHX_ERR_INVALID, "PHX_F_MOMENTS needs a detector radius <= 0.5 m");
     if (!std::isfinite(a->exposure) || a->exposure < 0 || !std::isfinite(a->pupil_margin) ||
         a->pupil_margin < 0)
         return fail(c, PHX_ERR_INVALID, "bad exposure or pupil margin");
@@ -597,7 +633,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     L.pupil_margin = a->pupil_margin;
     L.image = a->image_dev;
     L.stats = (unsigned long long*)a->stats_dev;
-    L.moments = a->moments_dev;
+    L.moments = (unsigned long long*)a->moments_dev;
     L.events = a->events_dev;
     L.event_stride = a->event_stride;
     L.any_sersic = 0;
@@ -644,7 +680,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     }
     if (a->photon_begin > UINT64_MAX - (L.total ? L.total : 0))
         return fail(c, PHX_ERR_INVALID, "photon index overflows");
-    if (a->flags & PHX_F_EVENTS) {
+    if (need_image && (a->flags & PHX_F_EVENTS)) {
         if (!a->events_dev || a->event_stride == 0)
             return fail(c, PHX_ERR_INVALID, "PHX_F_EVENTS needs events_dev and event_stride > 0");
         const uint64_t need = (L.total + a->event_stride - 1) / a->event_stride;
@@ -752,6 +788,79 @@ phx_status phx_trace_batched(phx_ctx c, const phx_trace_args* a, void* stream) {
     return PHX_OK;
 }
 
+phx_status phx_adjoint(phx_ctx c, const phx_trace_args* a, const double* seed_dev,
+                       double* grad_dev, double* jac_dev, uint64_t jac_stride,
+                       uint64_t jac_capacity, void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!a) return fail(c, PHX_ERR_INVALID, "null trace arguments");
+    if (!seed_dev || !grad_dev) return fail(c, PHX_ERR_INVALID, "null seed or gradient buffer");
+    hipStream_t st = (hipStream_t)stream;
+    phx_trace_args b = *a;
+    // outputs of the forward trace are not produced; the pre-roll changes no converted photon
+    b.flags &= ~(uint32_t)(PHX_F_EVENTS | PHX_F_MOMENTS);
+    if (b.flags & PHX_F_COATINGS) b.flags |= PHX_F_CULL;
+    b.image_dev = nullptr;
+    b.stats_dev = nullptr;
+    b.moments_dev = nullptr;
+    b.events_dev = nullptr;
+    phx::Launch L;
+    phx::Workspace W;
+    phx_status r = prepare(c, &b, st, L, W, false);
+    if (r != PHX_OK) return r;
+    if (jac_dev) {
+        if (jac_stride == 0) return fail(c, PHX_ERR_INVALID, "jacobian stride 0");
+        const uint64_t need = (L.total + jac_stride - 1) / jac_stride;
+        if (need > jac_capacity)
+            return fail(c, PHX_ERR_CAPACITY, "jacobian needs %llu slots, capacity %llu",
+                        (unsigned long long)need, (unsigned long long)jac_capacity);
+    }
+    // Adjoint workspace: tape for every thread of one launch, one partial row per workgroup
+    const uint64_t grid = (uint64_t)c->n_cu * c->adj_per_cu;
+    const uint64_t threads = grid * phx::kThreads;
+    const uint64_t n_chunks = L.total ? (L.total + W.chunk - 1) / W.chunk : 0;
+    const uint64_t tape_need = (uint64_t)c->presc.n_surfaces * phx::kTapeFields * threads;
+    const uint64_t rows_need = std::max<uint64_t>(n_chunks * grid, 1);
+    if (tape_need > c->tape_cap || rows_need > c->rows_cap || !c->d_colsum) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        if (tape_need > c->tape_cap) {
+            free_dev(c->d_tape);
+            c->tape_cap = 0;
+            e = hipMalloc((void**)&c->d_tape, tape_need * sizeof(double));
+            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "adjoint tape");
+            c->tape_cap = tape_need;
+        }
+        if (rows_need > c->rows_cap) {
+            free_dev(c->d_partial);
+            c->rows_cap = 0;
+            e = hipMalloc((void**)&c->d_partial, rows_need * phx::kAdj * sizeof(double));
+            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "adjoint partial sums");
+            c->rows_cap = rows_need;
+        }
+        if (!c->d_colsum) {
+            e = hipMalloc((void**)&c->d_colsum, phx::kAdj * sizeof(double));
+            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "adjoint column sums");
+        }
+    }
+    phx::Adjoint A;
+    A.seed = seed_dev;
+    A.partial = c->d_partial;
+    A.tape = c->d_tape;
+    A.tape_stride = threads;
+    A.jac = jac_dev;
+    A.jac_stride = jac_dev ? jac_stride : 1;
+    A.jac_cap = jac_capacity;
+    A.per_cu = c->adj_per_cu;
+    phx::Timing T;
+    T.on = c->timing;
+    T.record = timing_record;
+    T.self = c;
+    hipError_t e = phx::launch_adjoint(c->dparams, L, W, c->n_cu, c->cfg, A, c->d_colsum, grad_dev,
+                                       st, T);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint kernel launch");
+    return PHX_OK;
+}
+
 phx_status phx_set_launch_config(phx_ctx c, const phx_launch_config* cfg) {
     if (!c) return PHX_ERR_INVALID;
     if (!cfg) return fail(c, PHX_ERR_INVALID, "null launch config");
@@ -789,12 +898,12 @@ phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     // scratch outputs
     uint32_t* img = nullptr;
     unsigned long long* stats = nullptr;
-    double* mom = nullptr;
+    uint64_t* mom = nullptr;
     const size_t npix = (size_t)c->presc.nx * c->presc.ny;
     hipError_t e = hipMalloc((void**)&img, npix * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&stats, PHX_STATS_LEN * sizeof(uint64_t));
     if (e == hipSuccess && (sample->flags & PHX_F_MOMENTS))
-        e = hipMalloc((void**)&mom, c->src.size() * PHX_MOMENT_LEN * sizeof(double));
+        e = hipMalloc((void**)&mom, c->src.size() * PHX_MOMENT_WORDS * sizeof(uint64_t));
     if (e != hipSuccess) {
         free_dev(img);
         free_dev(stats);

@@ -14,13 +14,16 @@ constexpr int kNZernPoly = 15;  // monomials u^a v^b, a + b <= 4
 // g = R q + t (R row-major); `moved` = 0 means R = identity and t = (0, 0, z_vertex).
 struct DevSurface {
     int32_t kind, medium, coating, moved;
-    int32_t asphere, zernike, pad0, pad1;  // asphere: 0 none, 1 even terms only, 2 general
+    int32_t asphere, zernike;              // asphere: 0 none, 1 even terms only, 2 general
+    int32_t group;                         // rigid-body perturbation group (0 = fixed)
+    int32_t glass_in;                      // the ray arrives through glass (else vacuum)
     double R[9];
     double t[3];
     double c, kappa1;      // curvature, 1 + kappa
     double alpha[8];       // alpha_3 .. alpha_10
     double r_in, r_out;
     double r_in2, r_out2;  // squared aperture radii
+    double z_vertex;       // nominal vertex height (the group transform acts about a pivot)
 };
 
 struct DevSource {
@@ -39,6 +42,9 @@ struct DevParams {
     DevSurface surf[PHX_MAX_SURF];
     double zern[kNZernPoly];   // Zernike deformation of surface 0 as monomial coefficients
     double zern_inv_r;
+    double zern_basis[kNZern][kNZernPoly];  // Noll Z4..Z15 as monomial coefficients
+    double group_pivot[3][3];
+    double group_cs[3][4];     // cos t_x, sin t_x, cos t_y, sin t_y of each group's rotation
     double pupil_r_in, pupil_r_out;
     double z_start, obsc_z, obsc_r;
     double sell_b[3], sell_c[3];
@@ -77,7 +83,7 @@ struct Launch {
     double exposure, pupil_margin;
     uint32_t* image;
     unsigned long long* stats;
-    double* moments;
+    unsigned long long* moments;
     phx_event* events;
     uint64_t event_stride;
     int32_t any_sersic;            // an extended source is in the range
@@ -92,7 +98,7 @@ struct Workspace {
     uint32_t* survivors;       // [chunk]
     unsigned int* counts;      // [n_chunks]
     uint64_t n_chunks;
-    double* state;             // [7][chunk]; null = run the fused single kernel
+    double* state;             // [7][chunk]
     uint64_t chunk;
     unsigned long long* tiles; // [n_chunks][2] tile counters of the dynamic schedule
 };
@@ -107,6 +113,7 @@ struct LaunchConfig {
     int dynamic = 0;
 };
 constexpr int kTileIters = 8;
+constexpr int kThreads = 256;   // workgroup size of every trace kernel
 
 // Optional per-kernel timing: events recorded before/after each kernel launch.
 struct Timing {
@@ -118,6 +125,24 @@ struct Timing {
 
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
                         const LaunchConfig& cfg, hipStream_t stream, const Timing& T);
+// Adjoint of the per-source moments (pathwise derivative, decisions frozen).  Per-lane
+// accumulators: the ten rigid-body parameters, then the fifteen monomial coefficients of the
+// primary's deformation (mapped to Zernike amplitudes by the final reduction).
+constexpr int kAdj = 10 + kNZernPoly;
+constexpr int kTapeFields = 7;   // per surface: hit point (3), incoming direction (3), path length
+struct Adjoint {
+    const double* seed;      // [n_src][8]: gx, gy, gxx, gyy, gxy, mean x, mean y, unused
+    double* partial;         // [rows][kAdj], one row per (chunk, workgroup)
+    double* tape;            // [n_surf * kTapeFields][tape_stride]
+    uint64_t tape_stride;    // threads of one adjoint launch
+    double* jac;             // optional [slots][2][PHX_N_THETA]
+    uint64_t jac_stride, jac_cap;
+    int per_cu;              // workgroups per compute unit of the adjoint kernel
+};
+
+hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
+                          const LaunchConfig& cfg, const Adjoint& A, double* colsum, double* grad,
+                          hipStream_t stream, const Timing& T);
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, hipStream_t stream);
 

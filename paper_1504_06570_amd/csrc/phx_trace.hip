@@ -23,7 +23,7 @@ namespace {
 constexpr double kHcEvM = 1.2398419843320026e-6;  // h c / e in eV m
 constexpr double kNewtonTol = 1e-12;             // m
 constexpr int kNewtonMax = 16;
-constexpr int kBlock = 256;
+constexpr int kBlock = kThreads;
 
 // ---------------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11).
@@ -462,12 +462,12 @@ __device__ __noinline__ bool sensor_stage(const DevParams& P, const Launch& L, c
 // the pixel, from the start-plane state.
 struct Hit {
     double q[3], d[3], N[3];
-    double dn;
+    double dn, l;
 };
 
 // Transform into surface k's frame, intersect, clip to the clear aperture, take the normal and
 // play the coating roulette (sections 2.4.1-2.4.2).  Returns 0 to continue or the photon's fate.
-template <bool ZERN>
+template <bool ZERN, bool TAPE = false>
 __device__ __forceinline__ int hit_surface(const DevParams& P, const Launch& L, const Rng& rng,
                                            int k, const double p[3], const double n[3],
                                            const LamCol& lc, uint4& wc, int& wc_block, Hit& h,
@@ -488,6 +488,7 @@ __device__ __forceinline__ int hit_surface(const DevParams& P, const Launch& L, 
     int st = intersect<ZERN>(P, s, h.q, h.d, l, gx, gy, newton);
     if (st == 0 && !(l > 0.0)) st = PHX_MISSED;
     if (st != 0) return st;
+    if (TAPE) h.l = l;
     h.q[0] += h.d[0] * l; h.q[1] += h.d[1] * l; h.q[2] += h.d[2] * l;
     const double rq2 = h.q[0] * h.q[0] + h.q[1] * h.q[1];
     if (rq2 < s.r_in2 || rq2 > s.r_out2) return PHX_VIGNETTED;
@@ -519,11 +520,21 @@ __device__ __forceinline__ bool refract(Hit& h, double mu) {
     return true;
 }
 
+// Tape of one surface passage for the adjoint: hit point and incoming direction in the
+// element frame, and the path length from the previous surface, at tp[(k * kTapeFields + i) * ts].
+__device__ __forceinline__ void tape_put(double* tp, uint64_t ts, int k, const Hit& h) {
+    double* t = tp + (uint64_t)k * kTapeFields * ts;
+    t[0] = h.q[0]; t[ts] = h.q[1]; t[2 * ts] = h.q[2];
+    t[3 * ts] = h.d[0]; t[4 * ts] = h.d[1]; t[5 * ts] = h.d[2];
+    t[6 * ts] = h.l;
+}
+
 // Central obscuration, the surfaces (sections 2.4.1-2.4.2), silicon (sections 2.4.2-2.4.3) and
-// the pixel, from the start-plane state.
-template <bool ZERN>
+// the pixel, from the start-plane state.  With TAPE, every surface passage is recorded for the
+// adjoint sweep.
+template <bool ZERN, bool TAPE = false>
 __device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint64_t idx,
-                               const Front& f) {
+                               const Front& f, double* tp = nullptr, uint64_t ts = 0) {
     Outcome o;
     o.status = PHX_MISSED; o.surface = -1; o.newton = 0; o.pix_i = -1; o.pix_j = -1;
     o.x = o.y = o.z = o.xe = o.ye = 0.0;
@@ -552,8 +563,9 @@ __device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint
 #pragma unroll 1
     for (int k = 0; k < kdet; ++k) {
         const DevSurface& s = P.surf[k];
-        int st = hit_surface<ZERN>(P, L, rng, k, p, n, lc, wc, wc_block, h, o.newton);
+        int st = hit_surface<ZERN, TAPE>(P, L, rng, k, p, n, lc, wc, wc_block, h, o.newton);
         if (st == 0) {
+            if (TAPE) tape_put(tp, ts, k, h);
             if (s.kind == PHX_MIRROR) {
                 // reflection across the normal (section 2.4.2)
                 h.d[0] -= 2.0 * h.dn * h.N[0];
@@ -580,7 +592,8 @@ __device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint
         }
     }
     // the detector surface: refraction into silicon, conversion, diffusion, pixel
-    int st = hit_surface<ZERN>(P, L, rng, kdet, p, n, lc, wc, wc_block, h, o.newton);
+    int st = hit_surface<ZERN, TAPE>(P, L, rng, kdet, p, n, lc, wc, wc_block, h, o.newton);
+    if (TAPE && st == 0) tape_put(tp, ts, kdet, h);
     if (st == 0 && (L.flags & PHX_F_SILICON) && !refract(h, n_cur / n_silicon(lam))) st = PHX_TIR;
     o.surface = kdet;
     o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
@@ -604,24 +617,6 @@ __device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint
         o.pix_j = (int)iy;
     }
     return o;
-}
-
-// The whole per-photon path (optionally with the pre-roll test first).
-__device__ Outcome trace_photon(const DevParams& P, const Launch& L, int si, uint64_t idx,
-                               bool preroll = true) {
-    if (preroll && (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS)) {
-        double lam;
-        if (preroll_culls(P, L, si, idx, lam)) {
-            Outcome o;
-            o.status = PHX_CULLED; o.surface = -1; o.newton = 0; o.pix_i = o.pix_j = -1;
-            o.x = o.y = o.z = o.xe = o.ye = 0.0;
-            o.lam = lam;
-            return o;
-        }
-    }
-    Front f;
-    photon_front<true>(P, L, si, idx, f);
-    return photon_back<true>(P, L, si, idx, f);
 }
 
 // Wavefront-aggregated increment: lanes with the same pixel elect one leader that adds the
@@ -669,22 +664,62 @@ __device__ __forceinline__ void write_event(const Launch& L, uint64_t g, int si,
     e.x = o.x; e.y = o.y; e.z = o.z; e.xe = o.xe; e.ye = o.ye; e.lambda = o.lam;
 }
 
-// Book-keeping of one traced photon: LDS status counter, moments, event record; returns the
-// pixel to bin (-1 for none).
+// Book-keeping of one traced photon: LDS status counter and event record; returns the pixel to
+// bin (-1 for none).
 __device__ __forceinline__ int account(const DevParams& P, const Launch& L, uint32_t* s_stats,
                                        uint64_t g, int si, uint64_t idx, const Outcome& o) {
     atomicAdd(&s_stats[o.status * PHX_STAT_COLS + min(o.surface + 1, PHX_STAT_COLS - 1)], 1u);
-    if ((L.flags & PHX_F_MOMENTS) && o.status <= PHX_OFF_CHIP) {
-        double* m = L.moments + (size_t)si * PHX_MOMENT_LEN;
-        atomicAdd(m + 0, 1.0);
-        atomicAdd(m + 1, o.xe);
-        atomicAdd(m + 2, o.ye);
-        atomicAdd(m + 3, o.xe * o.xe);
-        atomicAdd(m + 4, o.ye * o.ye);
-        atomicAdd(m + 5, o.xe * o.ye);
-    }
     if ((L.flags & PHX_F_EVENTS) && (g % L.event_stride) == 0) write_event(L, g, si, idx, o);
     return o.status == PHX_DETECTED ? o.pix_j * P.nx + o.pix_i : -1;
+}
+
+// Exact per-source moments of converted photons.  Positions are quantised to 2^-44 m and the
+// sums (count, X, Y, X^2, Y^2, XY) are accumulated as 128-bit integers, so the result is
+// independent of the order in which photons arrive.  Lanes of the wavefront that hold the same
+// source are summed with cross-lane shuffles first; the group's leader then adds the sums with
+// one pair of 64-bit atomics per 128-bit word (the low word's carry goes into the high word).
+// Every lane of the wavefront must call it.
+__device__ __forceinline__ void wave_sum128(unsigned __int128& v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const uint64_t lo = __shfl_xor((unsigned long long)(uint64_t)v, m);
+        const uint64_t hi = __shfl_xor((unsigned long long)(uint64_t)(v >> 64), m);
+        v += ((unsigned __int128)hi << 64) | lo;
+    }
+}
+
+__device__ __forceinline__ void atomic_add128(unsigned long long* w, unsigned __int128 v) {
+    const unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
+    const unsigned long long old = atomicAdd(w, lo);
+    const unsigned long long carry = old + lo < old ? 1ull : 0ull;
+    if (hi + carry) atomicAdd(w + 1, hi + carry);
+}
+
+__device__ void add_moments(const Launch& L, int si, double xe, double ye, bool active) {
+    uint64_t pending = __ballot(active);
+    const int lane = __lane_id();
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int key = __shfl(si, leader);
+        const bool mine = active && si == key;
+        const uint64_t same = __ballot(mine);
+        pending &= ~same;
+        const double q = 17592186044416.0;   // 2^PHX_MOMENT_Q_LOG2
+        const long long X = mine ? __double2ll_rn(xe * q) : 0;
+        const long long Y = mine ? __double2ll_rn(ye * q) : 0;
+        unsigned __int128 v[5] = {(unsigned __int128)(__int128)X, (unsigned __int128)(__int128)Y,
+                                  (unsigned __int128)((__int128)X * X),
+                                  (unsigned __int128)((__int128)Y * Y),
+                                  (unsigned __int128)((__int128)X * Y)};
+#pragma unroll
+        for (int i = 0; i < 5; ++i) wave_sum128(v[i]);
+        if (lane == leader) {
+            unsigned long long* w = L.moments + (size_t)key * PHX_MOMENT_WORDS;
+            atomicAdd(w, (unsigned long long)__popcll(same));
+#pragma unroll
+            for (int i = 0; i < 5; ++i) atomic_add128(w + 2 + 2 * i, v[i]);
+        }
+    }
 }
 
 __device__ __forceinline__ void stats_init(uint32_t* s_stats) {
@@ -701,34 +736,6 @@ __device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, 
         for (int i = threadIdx.x; i < PHX_STATS_LEN; i += blockDim.x)
             if (s_stats[i]) atomicAdd(&L.stats[i], (unsigned long long)s_stats[i]);
     }
-}
-
-// Every photon of [begin, begin + len) traced in place (no pre-roll compaction).
-__global__ __launch_bounds__(kBlock) void trace_kernel(const DevParams* __restrict__ Pg,
-                                                       const Launch L, uint64_t begin,
-                                                       uint64_t len) {
-    __shared__ uint32_t s_stats[PHX_STATS_LEN];
-    stats_init(s_stats);
-    const DevParams& P = *Pg;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t n_iter = (len + stride - 1) / stride;   // uniform across the wavefront
-    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t newton = 0, traced = 0;
-    for (uint64_t it = 0; it < n_iter; ++it, r += stride) {
-        int pix = -1;
-        if (r < len) {
-            const uint64_t g = begin + r;
-            int si;
-            uint64_t idx;
-            decode(L, g, si, idx);
-            const Outcome o = trace_photon(P, L, si, idx);
-            newton += o.newton;
-            traced += o.status != PHX_CULLED;
-            pix = account(P, L, s_stats, g, si, idx, o);
-        }
-        bin_photon(L.image, pix, pix >= 0);
-    }
-    stats_flush(L, s_stats, newton, traced);
 }
 
 // Pre-roll (section 3.2, dynamic transmission optimisation): draw each photon's wavelength and
@@ -875,9 +882,12 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
     const uint64_t n = surv ? (uint64_t)*count : n_all;
     Tiles T{tile_ctr, blockIdx.x, 0, n};
     uint32_t newton = 0, traced = 0;
-    while (T.next(&s_tile)) {   // block-uniform: every lane takes part in bin_photon's ballots
+    while (T.next(&s_tile)) {   // block-uniform: every lane takes part in the wavefront ballots
         const uint64_t r = T.index();
         int pix = -1;
+        int m_si = 0;
+        double m_x = 0.0, m_y = 0.0;
+        bool m_on = false;
         if (r < n) {
             const uint64_t g = begin + (surv ? (uint64_t)surv[r] : r);
             int si;
@@ -894,6 +904,8 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
             const Outcome o = photon_back<ZERN>(P, L, si, idx, f);
             newton += o.newton;
             traced += 1;
+            m_si = si; m_x = o.xe; m_y = o.ye;
+            m_on = (L.flags & PHX_F_MOMENTS) && o.status <= PHX_OFF_CHIP;
             if (account(P, L, s_stats, g, si, idx, o) >= 0) {
                 int org = s_org;
                 if (org < 0) {
@@ -909,6 +921,7 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
             }
         }
         bin_photon(L.image, pix, pix >= 0);
+        if (L.flags & PHX_F_MOMENTS) add_moments(L, m_si, m_x, m_y, m_on);
     }
     stats_flush(L, s_stats, newton, traced);   // ends with a barrier
     const int org = s_org;
@@ -920,6 +933,415 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
             if (c && i < P.nx && j < P.ny) atomicAdd(&L.image[(size_t)j * P.nx + i], c);
         }
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint trace: pathwise derivative of per-source moments with respect to the rigid-body
+// parameters of the two perturbation groups and the Zernike amplitudes of the primary, with
+// every discrete decision (pupil, coatings, apertures, conversion, escape) held at its forward
+// value.  Each converted photon is traced again with a tape of its surface passages, then swept
+// from the electron position back to the primary: the intersection by the implicit-function
+// rule (the path length solves q_z + l d_z = S(q_x + l d_x, q_y + l d_y)), the normal through
+// the sag Hessian, reflection and Snell refraction through their Jacobians, and each group
+// transform g = R q + t with t = pivot + R (vertex - pivot) + shift.
+
+// Monomials u^a v^b of the Zernike expansion (order of zernike_poly).
+__device__ constexpr int kMonoA[kNZernPoly] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
+__device__ constexpr int kMonoB[kNZernPoly] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4};
+
+__device__ __forceinline__ double ipow(const double* pw, int e) { return e > 0 ? pw[e] : 1.0; }
+
+// Sag slopes and Hessian in the element frame at (x, y).
+template <bool ZERN>
+__device__ __forceinline__ void sag_hessian(const DevParams& P, const DevSurface& s, int k,
+                                            double x, double y, double& Sx, double& Sy,
+                                            double& Hxx, double& Hxy, double& Hyy) {
+    const double r2 = x * x + y * y;
+    const double arg = fmax(1.0 - s.kappa1 * s.c * s.c * r2, 0.0);
+    const double root = sqrt(arg);
+    const double iroot = root > 0.0 ? 1.0 / root : 0.0;
+    double g = s.c * iroot;                                       // dS/dr / r
+    double gp = 0.5 * s.c * s.kappa1 * s.c * s.c * iroot * iroot * iroot;   // dg / d(r^2)
+    if (s.asphere == 1) {
+        const double* a = s.alpha;
+        g += r2 * (4.0 * a[1] + r2 * (6.0 * a[3] + r2 * (8.0 * a[5] + r2 * 10.0 * a[7])));
+        gp += 4.0 * a[1] + r2 * (12.0 * a[3] + r2 * (24.0 * a[5] + r2 * 40.0 * a[7]));
+    } else if (s.asphere == 2) {
+        const double r = sqrt(r2);
+        const double ir = r > 0.0 ? 1.0 / r : 0.0;
+        double pw = r;   // r^(i-2)
+        for (int i = 3; i <= 10; ++i) {
+            const double a = s.alpha[i - 3];
+            g += (double)i * a * pw;
+            gp += 0.5 * (double)(i * (i - 2)) * a * pw * ir * ir;   // i (i-2) a r^(i-4) / 2
+            pw *= r;
+        }
+    }
+    Sx = x * g;
+    Sy = y * g;
+    Hxx = g + 2.0 * x * x * gp;
+    Hxy = 2.0 * x * y * gp;
+    Hyy = g + 2.0 * y * y * gp;
+    if (ZERN && k == 0 && s.zernike) {
+        const double ir = P.zern_inv_r;
+        const double u = x * ir, v = y * ir;
+        double pu[5], pv[5];
+        pu[0] = pv[0] = 1.0;
+        for (int e = 1; e < 5; ++e) { pu[e] = pu[e - 1] * u; pv[e] = pv[e - 1] * v; }
+        double zu = 0, zv = 0, zuu = 0, zuv = 0, zvv = 0;
+#pragma unroll
+        for (int m = 0; m < kNZernPoly; ++m) {
+            const int a = kMonoA[m], b = kMonoB[m];
+            const double c = P.zern[m];
+            if (a >= 1) zu += c * a * ipow(pu, a - 1) * pv[b];
+            if (b >= 1) zv += c * b * pu[a] * ipow(pv, b - 1);
+            if (a >= 2) zuu += c * a * (a - 1) * ipow(pu, a - 2) * pv[b];
+            if (a >= 1 && b >= 1) zuv += c * a * b * ipow(pu, a - 1) * ipow(pv, b - 1);
+            if (b >= 2) zvv += c * b * (b - 1) * pu[a] * ipow(pv, b - 2);
+        }
+        Sx += zu * ir;
+        Sy += zv * ir;
+        Hxx += zuu * ir * ir;
+        Hxy += zuv * ir * ir;
+        Hyy += zvv * ir * ir;
+    }
+}
+
+__device__ __forceinline__ void group_rotation_derivs(const DevParams& P, int g, double dRx[9],
+                                                      double dRy[9]) {
+    const double cx = P.group_cs[g][0], sx = P.group_cs[g][1];
+    const double cy = P.group_cs[g][2], sy = P.group_cs[g][3];
+    // R = R_x(t_x) R_y(t_y) = [[cy, 0, sy], [sx sy, cx, -sx cy], [-cx sy, sx, cx cy]]
+    dRx[0] = 0.0;      dRx[1] = 0.0; dRx[2] = 0.0;
+    dRx[3] = cx * sy;  dRx[4] = -sx; dRx[5] = -cx * cy;
+    dRx[6] = sx * sy;  dRx[7] = cx;  dRx[8] = -sx * cy;
+    dRy[0] = -sy;      dRy[1] = 0.0; dRy[2] = cy;
+    dRy[3] = sx * cy;  dRy[4] = 0.0; dRy[5] = sx * sy;
+    dRy[6] = -cx * cy; dRy[7] = 0.0; dRy[8] = -cx * sy;
+}
+
+// The sweep for NC cotangent columns at once: seeds (xb, yb) of the electron position, results
+// added to acc[c][0..kAdj).
+template <bool ZERN, int NC>
+__device__ void adjoint_sweep(const DevParams& P, const Launch& L, const Rng& rng, double lam,
+                              const double* tp, uint64_t ts, const double* xb, const double* yb,
+                              double (*acc)[kAdj]) {
+    const int kdet = P.n_surf - 1;
+    const double n_glass = P.has_glass ? sellmeier(P, lam) : 1.0;
+    double pb[NC][3], nb[NC][3];   // global-frame cotangents of the ray leaving surface k
+#pragma unroll 1
+    for (int k = kdet; k >= 0; --k) {
+        const DevSurface& s = P.surf[k];
+        const double* t = tp + (uint64_t)k * kTapeFields * ts;
+        const double q1[3] = {t[0], t[ts], t[2 * ts]};
+        const double d0[3] = {t[3 * ts], t[4 * ts], t[5 * ts]};
+        const double l = t[6 * ts];
+        double Sx, Sy, Hxx, Hxy, Hyy;
+        sag_hessian<ZERN>(P, s, k, q1[0], q1[1], Sx, Sy, Hxx, Hxy, Hyy);
+        const double inv = 1.0 / sqrt(Sx * Sx + Sy * Sy + 1.0);
+        const double Nr[3] = {-Sx * inv, -Sy * inv, inv};
+        const double dnr = d0[0] * Nr[0] + d0[1] * Nr[1] + d0[2] * Nr[2];
+        const double sg = dnr > 0.0 ? -1.0 : 1.0;
+        const double N[3] = {sg * Nr[0], sg * Nr[1], sg * Nr[2]};
+        const double dn = sg * dnr;
+        const double n_in = s.glass_in ? n_glass : 1.0;
+        // 0: no outgoing direction, 1: reflection, 2: refraction
+        int mode;
+        double mu = 1.0;
+        if (k == kdet) {
+            mode = (L.flags & PHX_F_SILICON) ? 2 : 0;
+            mu = n_in / n_silicon(lam);
+        } else if (s.kind == PHX_MIRROR) {
+            mode = 1;
+        } else {
+            mode = 2;
+            mu = n_in / (s.medium == PHX_GLASS ? n_glass : 1.0);
+        }
+        double d1[3] = {d0[0], d0[1], d0[2]};
+        double f = 0.0, fpr = 0.0;
+        if (mode == 1) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) d1[i] = d0[i] - 2.0 * dn * N[i];
+        } else if (mode == 2) {
+            const double cosi = -dn;
+            const double kk = 1.0 - mu * mu * (1.0 - cosi * cosi);
+            const double w = sqrt(fmax(kk, 0.0));
+            f = mu * cosi - w;
+            fpr = mu - (w > 0.0 ? mu * mu * cosi / w : 0.0);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) d1[i] = mu * d0[i] + f * N[i];
+        }
+        double qb[NC][3], db[NC][3];
+        double Rb[NC][9], tb[NC][3];
+        const bool grp = s.group != 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Rb[c][i] = 0.0;
+            tb[c][0] = tb[c][1] = tb[c][2] = 0.0;
+        }
+        if (k == kdet) {
+            // electron position from the landing point (sections 2.4.2-2.4.3)
+            double Lc = 0.0, kz = 0.0, ca = 0.0, sa = 0.0;
+            if (L.flags & PHX_F_SILICON) {
+                Lc = -log(u01(rng.block(1).z)) / absorption(P, lam);
+                if (L.flags & PHX_F_DIFFUSION) {
+                    const uint4 wd = rng.block(6);
+                    const double rad = sqrt(-2.0 * log(u01(wd.x)));
+                    sincospi(2.0 * u01(wd.y), &sa, &ca);
+                    ca *= rad;
+                    sa *= rad;
+                    kz = -P.sigma_max * Lc * (d1[2] >= 0.0 ? 1.0 : -1.0) / P.t_si;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                qb[c][0] = xb[c]; qb[c][1] = yb[c]; qb[c][2] = 0.0;
+                db[c][0] = Lc * xb[c]; db[c][1] = Lc * yb[c];
+                db[c][2] = kz * (ca * xb[c] + sa * yb[c]);
+            }
+        } else {
+            // leaving surface k: p' = R q1 + t, n' = R d1
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    qb[c][j] = s.R[j] * pb[c][0] + s.R[3 + j] * pb[c][1] + s.R[6 + j] * pb[c][2];
+                    db[c][j] = s.R[j] * nb[c][0] + s.R[3 + j] * nb[c][1] + s.R[6 + j] * nb[c][2];
+                }
+                if (grp) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+                            Rb[c][3 * i + j] += pb[c][i] * q1[j] + nb[c][i] * d1[j];
+                        tb[c][i] += pb[c][i];
+                    }
+                }
+            }
+        }
+        const double mv[3] = {-Sx, -Sy, 1.0};
+        const double fpn = d0[2] - Sx * d0[0] - Sy * d0[1];
+        double mono[kNZernPoly], mu_[kNZernPoly], mv_[kNZernPoly];
+        if (k == 0) {
+            const double ir = P.zern_inv_r;
+            const double u = q1[0] * ir, v = q1[1] * ir;
+            double pu[5], pv[5];
+            pu[0] = pv[0] = 1.0;
+            for (int e = 1; e < 5; ++e) { pu[e] = pu[e - 1] * u; pv[e] = pv[e - 1] * v; }
+#pragma unroll
+            for (int m = 0; m < kNZernPoly; ++m) {
+                const int a = kMonoA[m], b = kMonoB[m];
+                mono[m] = pu[a] * pv[b];
+                mu_[m] = a >= 1 ? a * ipow(pu, a - 1) * pv[b] * ir : 0.0;
+                mv_[m] = b >= 1 ? b * pu[a] * ipow(pv, b - 1) * ir : 0.0;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            // reflection / refraction: cotangents of the incoming direction and of the normal
+            double d0b[3] = {0.0, 0.0, 0.0}, Nb[3] = {0.0, 0.0, 0.0};
+            const double tN = N[0] * db[c][0] + N[1] * db[c][1] + N[2] * db[c][2];
+            if (mode == 1) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    d0b[i] = db[c][i] - 2.0 * tN * N[i];
+                    Nb[i] = -2.0 * (dn * db[c][i] + tN * d0[i]);
+                }
+            } else if (mode == 2) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    d0b[i] = mu * db[c][i] - tN * fpr * N[i];
+                    Nb[i] = f * db[c][i] - tN * fpr * d0[i];
+                }
+            }
+            // N = sg (-Sx, -Sy, 1) / sqrt(Sx^2 + Sy^2 + 1)
+            const double nn = sg * (Nb[0] * Nr[0] + Nb[1] * Nr[1] + Nb[2] * Nr[2]);
+            const double Sxb = -sg * Nb[0] * inv - nn * Sx * inv * inv;
+            const double Syb = -sg * Nb[1] * inv - nn * Sy * inv * inv;
+            double qc[3] = {qb[c][0] + Sxb * Hxx + Syb * Hxy, qb[c][1] + Sxb * Hxy + Syb * Hyy,
+                            qb[c][2]};
+            // intersection: q1 = q0 + l d0 with F(l) = q1_z - S(q1_x, q1_y) = 0
+            const double lb = qc[0] * d0[0] + qc[1] * d0[1] + qc[2] * d0[2];
+            const double coef = -lb / fpn;
+            double q0b[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                q0b[i] = qc[i] + coef * mv[i];
+                d0b[i] += l * qc[i] + coef * l * mv[i];
+            }
+            if (k == 0) {
+#pragma unroll
+                for (int m = 0; m < kNZernPoly; ++m)
+                    acc[c][10 + m] += Sxb * mu_[m] + Syb * mv_[m] - coef * mono[m];
+            }
+            // entering surface k: q0 = R^T (p - t), d0 = R^T n
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                pb[c][i] = s.R[3 * i] * q0b[0] + s.R[3 * i + 1] * q0b[1] + s.R[3 * i + 2] * q0b[2];
+                nb[c][i] = s.R[3 * i] * d0b[0] + s.R[3 * i + 1] * d0b[1] + s.R[3 * i + 2] * d0b[2];
+            }
+            if (grp) {
+                const double q0[3] = {q1[0] - l * d0[0], q1[1] - l * d0[1], q1[2] - l * d0[2]};
+                double pt[3], nw[3];   // p - t = R q0 and n = R d0 (global frame)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    pt[i] = s.R[3 * i] * q0[0] + s.R[3 * i + 1] * q0[1] + s.R[3 * i + 2] * q0[2];
+                    nw[i] = s.R[3 * i] * d0[0] + s.R[3 * i + 1] * d0[1] + s.R[3 * i + 2] * d0[2];
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Rb[c][3 * i + j] += pt[i] * q0b[j] + nw[i] * d0b[j];
+                    tb[c][i] -= pb[c][i];
+                }
+                // t = pivot + R (vertex - pivot) + shift
+                const double* Pv = P.group_pivot[s.group];
+                const double vp[3] = {-Pv[0], -Pv[1], s.z_vertex - Pv[2]};
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Rb[c][3 * i + j] += tb[c][i] * vp[j];
+                double dRx[9], dRy[9];
+                group_rotation_derivs(P, s.group, dRx, dRy);
+                double gx = 0.0, gy = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    gx += Rb[c][i] * dRx[i];
+                    gy += Rb[c][i] * dRy[i];
+                }
+                const int b = 5 * (s.group - 1);
+                acc[c][b + 0] += tb[c][0];
+                acc[c][b + 1] += tb[c][1];
+                acc[c][b + 2] += gx;
+                acc[c][b + 3] += gy;
+                acc[c][b + 4] += tb[c][2];
+            }
+        }
+    }
+}
+
+// Wavefront then workgroup sum of the per-lane accumulators in a fixed order; thread 0..kAdj-1
+// write the workgroup's row.
+__device__ void block_sum_rows(double* acc, double* row) {
+    __shared__ double s_part[kBlock / 64][kAdj];
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+#pragma unroll
+    for (int j = 0; j < kAdj; ++j) {
+        double v = acc[j];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+        if (lane == 0) s_part[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kAdj) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v += s_part[w][threadIdx.x];
+        row[threadIdx.x] = v;
+    }
+}
+
+template <bool ZERN, bool JAC>
+__global__ __launch_bounds__(kBlock) void adjoint_kernel(const DevParams* __restrict__ Pg,
+                                                         const Launch L, uint64_t begin,
+                                                         const uint32_t* __restrict__ surv,
+                                                         const unsigned int* __restrict__ count,
+                                                         uint64_t n_all,
+                                                         const double* __restrict__ st,
+                                                         uint64_t st_stride, const Adjoint A,
+                                                         uint64_t row0) {
+    const DevParams& P = *Pg;
+    const uint64_t n = surv ? (uint64_t)*count : n_all;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double* tp = A.tape + tid;
+    const uint64_t ts = A.tape_stride;
+    double acc[1][kAdj];
+#pragma unroll
+    for (int j = 0; j < kAdj; ++j) acc[0][j] = 0.0;
+    for (uint64_t r = tid; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t g = begin + (surv ? (uint64_t)surv[r] : r);
+        int si;
+        uint64_t idx;
+        decode(L, g, si, idx);
+        Front f;
+        f.p[0] = st[0 * st_stride + r];
+        f.p[1] = st[1 * st_stride + r];
+        f.p[2] = st[2 * st_stride + r];
+        f.n[0] = st[3 * st_stride + r];
+        f.n[1] = st[4 * st_stride + r];
+        f.n[2] = st[5 * st_stride + r];
+        f.lam = st[6 * st_stride + r];
+        const Outcome o = photon_back<ZERN, true>(P, L, si, idx, f, tp, ts);
+        const bool conv = o.status <= PHX_OFF_CHIP;
+        const bool sampled = JAC && A.jac && (g % A.jac_stride) == 0;
+        if (!conv) {
+            if (sampled) {
+                double* J = A.jac + (g / A.jac_stride) * 2 * PHX_N_THETA;
+                for (int j = 0; j < 2 * PHX_N_THETA; ++j) J[j] = 0.0;
+            }
+            continue;
+        }
+        const double* sd = A.seed + (size_t)(si - L.src_begin) * 8;
+        const double dx = o.xe - sd[5], dy = o.ye - sd[6];
+        const double sxb = sd[0] + sd[2] * dx + sd[4] * dy;
+        const double syb = sd[1] + sd[3] * dy + sd[4] * dx;
+        const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+        if (!JAC) {
+            adjoint_sweep<ZERN, 1>(P, L, rng, o.lam, tp, ts, &sxb, &syb, acc);
+        } else {
+            double jl[2][kAdj];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int j = 0; j < kAdj; ++j) jl[c][j] = 0.0;
+            const double xs[2] = {1.0, 0.0}, ys[2] = {0.0, 1.0};
+            adjoint_sweep<ZERN, 2>(P, L, rng, o.lam, tp, ts, xs, ys, jl);
+#pragma unroll
+            for (int j = 0; j < kAdj; ++j) acc[0][j] += sxb * jl[0][j] + syb * jl[1][j];
+            if (sampled) {
+                double* J = A.jac + (g / A.jac_stride) * 2 * PHX_N_THETA;
+                for (int c = 0; c < 2; ++c) {
+                    for (int j = 0; j < 10; ++j) J[c * PHX_N_THETA + j] = jl[c][j];
+                    for (int z = 0; z < kNZern; ++z) {
+                        double v = 0.0;
+                        for (int m = 0; m < kNZernPoly; ++m) v += P.zern_basis[z][m] * jl[c][10 + m];
+                        J[c * PHX_N_THETA + 10 + z] = v;
+                    }
+                }
+            }
+        }
+    }
+    block_sum_rows(acc[0], A.partial + (row0 + blockIdx.x) * kAdj);
+}
+
+// Column sums of the partial rows (fixed order: each thread a strided share, then a tree).
+__global__ __launch_bounds__(256) void adjoint_columns(const double* __restrict__ partial,
+                                                       uint64_t rows, double* __restrict__ colsum) {
+    __shared__ double s[256];
+    const int j = blockIdx.x;
+    double v = 0.0;
+    for (uint64_t r = threadIdx.x; r < rows; r += blockDim.x) v += partial[r * kAdj + j];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) colsum[j] = s[0];
+}
+
+// Rigid-body columns as they are; monomial columns mapped to the Zernike amplitudes.
+__global__ void adjoint_finish(const DevParams* __restrict__ Pg, const double* __restrict__ colsum,
+                               double* __restrict__ grad) {
+    const int j = threadIdx.x;
+    if (j >= PHX_N_THETA) return;
+    if (j < 10) {
+        grad[j] = colsum[j];
+        return;
+    }
+    double v = 0.0;
+    for (int m = 0; m < kNZernPoly; ++m) v += Pg->zern_basis[j - 10][m] * colsum[10 + m];
+    grad[j] = v;
 }
 
 __global__ void fill_u32(unsigned int* p, uint64_t n, unsigned int v) {
@@ -964,15 +1386,7 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
     };
     if (L.total == 0) return hipSuccess;
     const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
-    if (!W.state) {
-        // small launches without a workspace: one fused kernel
-        const uint64_t want = (L.total + kBlock - 1) / kBlock;
-        const uint64_t cap = (uint64_t)n_cu * 8;
-        const int grid = (int)(want < cap ? want : cap);
-        hipLaunchKernelGGL(trace_kernel, dim3(grid), dim3(kBlock), 0, stream, dparams, L,
-                           (uint64_t)0, L.total);
-        return hipGetLastError();
-    }
+    if (!W.state || !W.survivors || !W.counts) return hipErrorInvalidValue;
     const uint64_t chunk = W.chunk;
     const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
     if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
@@ -1021,6 +1435,80 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
                                surv, cnt, len, (const double*)W.state, chunk, bt);
         mark(2, 1);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
+                          const LaunchConfig& cfg, const Adjoint& A, double* colsum, double* grad,
+                          hipStream_t stream, const Timing& T) {
+    auto mark = [&](int kind, int edge) {
+        if (T.on) T.record(T.self, kind, edge, stream);
+    };
+    if (!W.state || !W.survivors || !W.counts) return hipErrorInvalidValue;
+    const uint64_t grid = (uint64_t)n_cu * A.per_cu;
+    if (grid * kBlock > A.tape_stride) return hipErrorInvalidValue;
+    const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
+    const uint64_t chunk = W.chunk;
+    const uint64_t n_chunks = L.total ? (L.total + chunk - 1) / chunk : 0;
+    if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
+    if (preroll && n_chunks)
+        hipLaunchKernelGGL(fill_u32, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256), 0,
+                           stream, W.counts, n_chunks, 0u);
+    const bool jac = A.jac != nullptr;
+    for (uint64_t c = 0; c < n_chunks; ++c) {
+        const uint64_t begin = c * chunk;
+        const uint64_t len = L.total - begin < chunk ? L.total - begin : chunk;
+        const uint32_t* surv = nullptr;
+        const unsigned int* cnt = nullptr;
+        const uint64_t want = (len + kBlock - 1) / kBlock;
+        if (preroll) {
+            const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
+            mark(0, 0);
+            hipLaunchKernelGGL(generate_kernel, dim3((unsigned)(want < cap ? want : cap)),
+                               dim3(kBlock), 0, stream, dparams, L, begin, len, W.survivors,
+                               W.counts + c);
+            mark(0, 1);
+            surv = W.survivors;
+            cnt = W.counts + c;
+        }
+        const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
+        const dim3 fg((unsigned)(want < fcap ? want : fcap));
+        mark(1, 0);
+        if (L.any_sersic)
+            hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
+                               surv, cnt, len, W.state, chunk, (unsigned long long*)nullptr);
+        else
+            hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
+                               surv, cnt, len, W.state, chunk, (unsigned long long*)nullptr);
+        mark(1, 1);
+        mark(2, 0);
+        const uint64_t row0 = c * grid;
+        const dim3 ag((unsigned)grid);
+        if (L.any_zernike) {
+            if (jac)
+                hipLaunchKernelGGL((adjoint_kernel<true, true>), ag, dim3(kBlock), 0, stream,
+                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
+                                   chunk, A, row0);
+            else
+                hipLaunchKernelGGL((adjoint_kernel<true, false>), ag, dim3(kBlock), 0, stream,
+                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
+                                   chunk, A, row0);
+        } else {
+            if (jac)
+                hipLaunchKernelGGL((adjoint_kernel<false, true>), ag, dim3(kBlock), 0, stream,
+                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
+                                   chunk, A, row0);
+            else
+                hipLaunchKernelGGL((adjoint_kernel<false, false>), ag, dim3(kBlock), 0, stream,
+                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
+                                   chunk, A, row0);
+        }
+        mark(2, 1);
+    }
+    const uint64_t rows = n_chunks * grid;
+    hipLaunchKernelGGL(adjoint_columns, dim3(kAdj), dim3(256), 0, stream, A.partial, rows, colsum);
+    hipLaunchKernelGGL(adjoint_finish, dim3(1), dim3(64), 0, stream, dparams,
+                       (const double*)colsum, grad);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ STAT_COLS = MAX_SURF + 1
 STAT_NEWTON = N_STATUS * STAT_COLS
 STAT_TRACED = STAT_NEWTON + 1
 STATS_LEN = STAT_TRACED + 1
-MOMENT_LEN = 6
+MOMENT_WORDS, MOMENT_Q_LOG2 = 12, 44
 
 F_ATMOSPHERE, F_COATINGS, F_SILICON, F_DIFFUSION = 1, 2, 4, 8
 F_CULL, F_EVENTS, F_MOMENTS = 1 << 8, 1 << 9, 1 << 10
@@ -343,8 +343,56 @@ class Tracer:
         return torch.zeros(STATS_LEN, dtype=torch.int64, device=self.device)
 
     def new_moments(self):
+        """Zeroed moment words [n_sources][MOMENT_WORDS] (uint64 held in int64)."""
         import torch
-        return torch.zeros((self.n_sources, MOMENT_LEN), dtype=torch.float64, device=self.device)
+        return torch.zeros((self.n_sources, MOMENT_WORDS), dtype=torch.int64, device=self.device)
+
+
+def moment_sums(words):
+    """Moment words [n][MOMENT_WORDS] -> per source the exact integers (n, SX, SY, SXX, SYY, SXY)
+    (positions in units of 2^-MOMENT_Q_LOG2 m), as Python ints."""
+    if hasattr(words, "cpu"):
+        words = words.cpu().numpy()
+    w = np.ascontiguousarray(words).view(np.uint64).reshape(-1, MOMENT_WORDS)
+    out = []
+    for row in w:
+        vals = [int(row[0])]
+        for i in range(5):
+            v = (int(row[3 + 2 * i]) << 64) | int(row[2 + 2 * i])
+            vals.append(v - (1 << 128) if v >> 127 else v)
+        out.append(tuple(vals))
+    return out
+
+
+def moments_from_sums(sums) -> np.ndarray:
+    """Per source (n, mean x, mean y, Ixx, Iyy, Ixy) in metres and square metres, the central
+    second moments (1/n) sum (x - mean)^2 etc.  Evaluated exactly in rational arithmetic from
+    the integer sums and rounded once, so no cancellation is lost; n = 0 gives a zero row."""
+    from fractions import Fraction
+    q = 1 << MOMENT_Q_LOG2
+    out = np.zeros((len(sums), 6))
+    for i, (n, sx, sy, sxx, syy, sxy) in enumerate(sums):
+        if n == 0:
+            continue
+        out[i] = (n, float(Fraction(sx, n * q)), float(Fraction(sy, n * q)),
+                  float(Fraction(n * sxx - sx * sx, n * n * q * q)),
+                  float(Fraction(n * syy - sy * sy, n * n * q * q)),
+                  float(Fraction(n * sxy - sx * sy, n * n * q * q)))
+    return out
+
+
+def moments(words) -> np.ndarray:
+    """Moment words -> per source (n, mean x, mean y, Ixx, Iyy, Ixy)."""
+    return moments_from_sums(moment_sums(words))
+
+
+def quantised_sums(xe, ye):
+    """The exact integer sums the library accumulates, for positions given on the host."""
+    q = float(1 << MOMENT_Q_LOG2)
+    X = [int(v) for v in np.rint(np.asarray(xe, np.float64) * q)]
+    Y = [int(v) for v in np.rint(np.asarray(ye, np.float64) * q)]
+    return (len(X), sum(X), sum(Y), sum(a * a for a in X), sum(b * b for b in Y),
+            sum(a * b for a, b in zip(X, Y)))
 
 
 def events_to_numpy(events) -> np.ndarray:

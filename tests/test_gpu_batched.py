@@ -110,17 +110,17 @@ def test_autotune_picks_a_valid_shape_and_keeps_results(phx, scene):
 
 
 def test_batched_moments_match_per_source(phx, scene):
-    """Per-source moment sums (atomic FP64, order-dependent rounding) agree to 1e-9 relative."""
+    """Per-source moment words are exact integer sums: a batched launch reproduces the
+    per-source launches bit for bit."""
     import torch
     tr = phx.Tracer(scene)
     m_ref = tr.new_moments()
-    for s in range(0, len(scene.sources), 97):
+    rows = list(range(0, len(scene.sources), 97))
+    for s in rows:
         tr.trace(moments=m_ref, src_begin=s, src_end=s + 1)
     m = tr.new_moments()
     tr.trace(moments=m, batched=True)
     torch.cuda.synchronize()
-    rows = np.arange(0, len(scene.sources), 97)
-    a, b = m.cpu().numpy()[rows], m_ref.cpu().numpy()[rows]
-    assert np.array_equal(a[:, 0], b[:, 0])          # detected counts
-    np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-18)
+    assert torch.equal(m[rows], m_ref[rows])
+    assert int(m[:, 0].sum()) > 0
     tr.close()
