@@ -67,6 +67,8 @@ struct phx_ctx_s {
     double* d_partial = nullptr;
     uint64_t rows_cap = 0;
     double* d_colsum = nullptr;
+    uint64_t* d_bits = nullptr;
+    unsigned int* d_bsum = nullptr;
     void graphs_clear() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
@@ -307,6 +309,8 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_tape);
     free_dev(c->d_partial);
     free_dev(c->d_colsum);
+    free_dev(c->d_bits);
+    free_dev(c->d_bsum);
     c->graphs_clear();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -697,10 +701,15 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
         free_dev(c->d_survivors);
         free_dev(c->d_state);
+        free_dev(c->d_bits);
+        free_dev(c->d_bsum);
         c->ws_chunk = 0;
         c->graphs_clear();
         e = hipMalloc((void**)&c->d_survivors, chunk * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, 7 * chunk * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_bits, (chunk + 63) / 64 * sizeof(uint64_t));
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&c->d_bsum, phx::compact_groups(chunk) * sizeof(unsigned int));
         if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "trace workspace: %s",
                                          hipGetErrorString(e));
         c->ws_chunk = chunk;
@@ -720,7 +729,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         c->counts_cap = n_chunks;
     }
     W = phx::Workspace{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk,
-                       (unsigned long long*)c->d_tiles};
+                       (unsigned long long*)c->d_tiles, (unsigned long long*)c->d_bits,
+                       c->d_bsum};
     return upload_params(c, st);
 }
 

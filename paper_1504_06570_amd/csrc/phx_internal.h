@@ -91,8 +91,9 @@ struct Launch {
 };
 
 // Scratch of the staged trace: the launch's photon range is processed in chunks; per chunk the
-// pre-roll survivors (offsets within the chunk), a survivor counter, and the start-plane state
-// of every traced photon (7 doubles each, structure of arrays).
+// pre-roll survivor bitmap, the survivors (offsets within the chunk, in photon order), a
+// survivor counter, and the start-plane state of every traced photon (7 doubles each,
+// structure of arrays).
 constexpr uint64_t kChunk = 1ull << 26;
 struct Workspace {
     uint32_t* survivors;       // [chunk]
@@ -101,7 +102,12 @@ struct Workspace {
     double* state;             // [7][chunk]
     uint64_t chunk;
     unsigned long long* tiles; // [n_chunks][2] tile counters of the dynamic schedule
+    unsigned long long* bits;  // [chunk / 64] survivor bitmap
+    unsigned int* bsum;        // [compact_groups(chunk)] survivors per compaction workgroup
 };
+// Workgroups of the ordered compaction for a chunk of n photons (64 photons per bitmap word,
+// 4096 words per workgroup).
+inline uint64_t compact_groups(uint64_t n) { return ((n + 63) / 64 + 4095) / 4096; }
 
 // Launch shape (tunable): workgroups per compute unit of each stage, and the schedule of the
 // sky and optics stages (static grid-stride, or tiles of kTileIters x 256 photons taken from a

@@ -740,17 +740,15 @@ __device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, 
 
 // Pre-roll (section 3.2, dynamic transmission optimisation): draw each photon's wavelength and
 // coating roulette numbers; photons whose draw exceeds the worst-case transmission of a coated
-// surface cannot be detected and are counted as culled.  Survivors (offsets in the chunk) are
-// staged in LDS and appended to the chunk's survivor list with one device-wide atomic per flush.
-constexpr int kQueue = 4096;
+// surface cannot be detected and are counted as culled.  Each wavefront writes the survivor
+// mask of its 64 consecutive photons as one bitmap word (no atomics); an ordered compaction
+// (compact_count, compact_scatter) then lists the survivors in photon order, so every later
+// stage sees the same photon in the same slot on every run.
 __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __restrict__ Pg,
                                                           const Launch L, uint64_t begin,
-                                                          uint64_t len, uint32_t* __restrict__ surv,
-                                                          unsigned int* __restrict__ count) {
+                                                          uint64_t len,
+                                                          unsigned long long* __restrict__ bits) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
-    __shared__ uint32_t s_q[kQueue];
-    __shared__ unsigned int s_qn, s_base;
-    if (threadIdx.x == 0) s_qn = 0;
     stats_init(s_stats);
     const DevParams& P = *Pg;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -775,27 +773,83 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
             }
         }
         const uint64_t mask = __ballot(keep);
-        if (mask) {
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            unsigned int base = 0;
-            if (lane == leader) base = atomicAdd(&s_qn, (unsigned int)__popcll(mask));
-            base = __shfl(base, leader);
-            if (keep) s_q[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)r;
-        }
-        __syncthreads();
-        const unsigned int qn = s_qn;
-        if (qn > (unsigned int)(kQueue - kBlock) || it + 1 == n_iter) {
-            __syncthreads();
-            if (threadIdx.x == 0) s_base = atomicAdd(count, qn);
-            __syncthreads();
-            const unsigned int base = s_base;
-            for (unsigned int i = threadIdx.x; i < qn; i += blockDim.x) surv[base + i] = s_q[i];
-            __syncthreads();
-            if (threadIdx.x == 0) s_qn = 0;
-            __syncthreads();
-        }
+        // r - lane is a multiple of 64: block and grid strides are multiples of the wavefront
+        if (lane == 0 && r < len) bits[r >> 6] = (unsigned long long)mask;
     }
     stats_flush(L, s_stats, 0u, 0u);
+}
+
+// Ordered compaction of the survivor bitmap: kCompactWords words per workgroup.
+constexpr int kWordsPerThread = 16;
+constexpr uint64_t kCompactWords = (uint64_t)kBlock * kWordsPerThread;
+
+__device__ __forceinline__ unsigned int block_sum_u32(unsigned int v, unsigned int* s_tmp) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    if (__lane_id() == 0) s_tmp[threadIdx.x / 64] = v;
+    __syncthreads();
+    unsigned int t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += s_tmp[w];
+    __syncthreads();
+    return t;
+}
+
+// Survivors per workgroup range of the bitmap.
+__global__ __launch_bounds__(kBlock) void compact_count(const unsigned long long* __restrict__ bits,
+                                                        uint64_t n_words,
+                                                        unsigned int* __restrict__ bsum) {
+    __shared__ unsigned int s_tmp[kBlock / 64];
+    const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWords;
+    unsigned int c = 0;
+    for (int i = 0; i < kWordsPerThread; ++i) {
+        const uint64_t w = w0 + (uint64_t)i * kBlock + threadIdx.x;
+        if (w < n_words) c += __popcll(bits[w]);
+    }
+    const unsigned int t = block_sum_u32(c, s_tmp);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
+}
+
+// Survivor offsets in photon order; the last workgroup stores the total in *count.
+__global__ __launch_bounds__(kBlock) void compact_scatter(const unsigned long long* __restrict__ bits,
+                                                          uint64_t n_words,
+                                                          const unsigned int* __restrict__ bsum,
+                                                          uint32_t* __restrict__ surv,
+                                                          unsigned int* __restrict__ count) {
+    __shared__ unsigned int s_tmp[kBlock / 64];
+    __shared__ unsigned int s_scan[kBlock];
+    // survivors before this workgroup's range
+    unsigned int pre = 0;
+    for (unsigned int b = threadIdx.x; b < blockIdx.x; b += blockDim.x) pre += bsum[b];
+    const unsigned int base = block_sum_u32(pre, s_tmp);
+    // this thread's words: a contiguous run, so that offsets follow photon order
+    const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWords + (uint64_t)threadIdx.x * kWordsPerThread;
+    unsigned long long wv[kWordsPerThread];
+    unsigned int c = 0;
+#pragma unroll
+    for (int i = 0; i < kWordsPerThread; ++i) {
+        wv[i] = w0 + i < n_words ? bits[w0 + i] : 0ull;
+        c += __popcll(wv[i]);
+    }
+    // inclusive scan of the per-thread counts (Hillis-Steele over the workgroup)
+    s_scan[threadIdx.x] = c;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+        const unsigned int v = threadIdx.x >= (unsigned)d ? s_scan[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s_scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned int o = base + s_scan[threadIdx.x] - c;
+#pragma unroll
+    for (int i = 0; i < kWordsPerThread; ++i) {
+        unsigned long long m = wv[i];
+        while (m) {
+            const int bit = __ffsll(m) - 1;
+            surv[o++] = (uint32_t)((w0 + i) * 64 + bit);
+            m &= m - 1;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) *count = base + s_scan[kBlock - 1];
 }
 
 // Block-uniform work distribution over [0, n): static (tile = block, block + grid, ...) or
@@ -1379,6 +1433,23 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
 
 }  // namespace
 
+// Pre-roll of one chunk: survivor bitmap, then the ordered survivor list and its count.
+static void launch_preroll(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
+                           const LaunchConfig& cfg, uint64_t begin, uint64_t len, uint64_t c,
+                           hipStream_t stream) {
+    const uint64_t want = (len + kBlock - 1) / kBlock;
+    const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
+    hipLaunchKernelGGL(generate_kernel, dim3((unsigned)(want < cap ? want : cap)), dim3(kBlock), 0,
+                       stream, dparams, L, begin, len, W.bits);
+    const uint64_t n_words = (len + 63) / 64;
+    const unsigned nb = (unsigned)((n_words + kCompactWords - 1) / kCompactWords);
+    hipLaunchKernelGGL(compact_count, dim3(nb), dim3(kBlock), 0, stream,
+                       (const unsigned long long*)W.bits, n_words, W.bsum);
+    hipLaunchKernelGGL(compact_scatter, dim3(nb), dim3(kBlock), 0, stream,
+                       (const unsigned long long*)W.bits, n_words, (const unsigned int*)W.bsum,
+                       W.survivors, W.counts + c);
+}
+
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
                         const LaunchConfig& cfg, hipStream_t stream, const Timing& T) {
     auto mark = [&](int kind, int edge) {
@@ -1386,13 +1457,10 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
     };
     if (L.total == 0) return hipSuccess;
     const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
-    if (!W.state || !W.survivors || !W.counts) return hipErrorInvalidValue;
+    if (!W.state || !W.survivors || !W.counts || !W.bits || !W.bsum) return hipErrorInvalidValue;
     const uint64_t chunk = W.chunk;
     const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
     if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
-    if (preroll)
-        hipLaunchKernelGGL(fill_u32, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256), 0,
-                           stream, W.counts, n_chunks, 0u);
     if (cfg.dynamic)
         hipLaunchKernelGGL(fill_u32, dim3((unsigned)((4 * n_chunks + 255) / 256)), dim3(256), 0,
                            stream, (unsigned int*)W.tiles, 4 * n_chunks, 0u);
@@ -1402,12 +1470,8 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
         const uint32_t* surv = nullptr;
         const unsigned int* cnt = nullptr;
         if (preroll) {
-            const uint64_t want = (len + kBlock - 1) / kBlock;
-            const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
-            const int ggrid = (int)(want < cap ? want : cap);
             mark(0, 0);
-            hipLaunchKernelGGL(generate_kernel, dim3(ggrid), dim3(kBlock), 0, stream, dparams, L,
-                               begin, len, W.survivors, W.counts + c);
+            launch_preroll(dparams, L, W, n_cu, cfg, begin, len, c, stream);
             mark(0, 1);
             surv = W.survivors;
             cnt = W.counts + c;
@@ -1444,16 +1508,13 @@ hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Works
     auto mark = [&](int kind, int edge) {
         if (T.on) T.record(T.self, kind, edge, stream);
     };
-    if (!W.state || !W.survivors || !W.counts) return hipErrorInvalidValue;
+    if (!W.state || !W.survivors || !W.counts || !W.bits || !W.bsum) return hipErrorInvalidValue;
     const uint64_t grid = (uint64_t)n_cu * A.per_cu;
     if (grid * kBlock > A.tape_stride) return hipErrorInvalidValue;
     const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
     const uint64_t chunk = W.chunk;
     const uint64_t n_chunks = L.total ? (L.total + chunk - 1) / chunk : 0;
     if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
-    if (preroll && n_chunks)
-        hipLaunchKernelGGL(fill_u32, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256), 0,
-                           stream, W.counts, n_chunks, 0u);
     const bool jac = A.jac != nullptr;
     for (uint64_t c = 0; c < n_chunks; ++c) {
         const uint64_t begin = c * chunk;
@@ -1462,11 +1523,8 @@ hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Works
         const unsigned int* cnt = nullptr;
         const uint64_t want = (len + kBlock - 1) / kBlock;
         if (preroll) {
-            const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
             mark(0, 0);
-            hipLaunchKernelGGL(generate_kernel, dim3((unsigned)(want < cap ? want : cap)),
-                               dim3(kBlock), 0, stream, dparams, L, begin, len, W.survivors,
-                               W.counts + c);
+            launch_preroll(dparams, L, W, n_cu, cfg, begin, len, c, stream);
             mark(0, 1);
             surv = W.survivors;
             cnt = W.counts + c;

@@ -121,10 +121,12 @@ def lib():
         L.phx_trace_batched.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
         L.phx_autotune.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p,
                                    C.POINTER(LaunchConfig)]
+        L.phx_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p]
         for f in ("phx_create", "phx_load_prescription", "phx_set_perturbation",
                   "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace",
                   "phx_set_timing", "phx_get_timing", "phx_set_launch_config",
-                  "phx_get_launch_config", "phx_trace_batched", "phx_autotune"):
+                  "phx_get_launch_config", "phx_trace_batched", "phx_autotune", "phx_adjoint"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -255,10 +257,10 @@ class Tracer:
         return torch.zeros((p.chip.ny, p.chip.nx), dtype=torch.int32, device=self.device)
 
     def _args(self, image, flags, seed, src_begin, src_end, photon_begin, photon_count, stats,
-              moments, event_stride, events, exposure):
+              moments, event_stride, events, exposure, adjoint_only=False):
         import torch
         sc = self.scene
-        if image is None:
+        if image is None and not adjoint_only:
             image = self.new_image()
         if flags is None:
             flags = int(sc.physics)
@@ -274,8 +276,9 @@ class Tracer:
         a.photon_begin, a.photon_count = int(photon_begin), int(photon_count)
         a.exposure = float(sc.exposure if exposure is None else exposure)
         a.pupil_margin = float(sc.pupil_margin)
-        assert image.dtype == torch.int32 and image.is_contiguous()
-        a.image_dev = image.data_ptr()
+        if image is not None:
+            assert image.dtype == torch.int32 and image.is_contiguous()
+            a.image_dev = image.data_ptr()
         a.stats_dev = stats.data_ptr() if stats is not None else None
         a.moments_dev = moments.data_ptr() if moments is not None else None
         if event_stride:
@@ -302,6 +305,35 @@ class Tracer:
         fn = self.L.phx_trace_batched if batched else self.L.phx_trace
         self._check(fn(self.ctx, C.byref(a), _stream_handle(stream)))
         return image, stats, moments, events
+
+    def adjoint(self, seeds, *, flags=None, seed=None, src_begin=0, src_end=None, photon_begin=0,
+                photon_count=0, jac_stride=0, grad=None, stream=None):
+        """Gradient of sum_i (xbar_i x_i + ybar_i y_i) over converted photons with respect to the
+        22 perturbation parameters (phx_adjoint).  seeds: float64 device tensor [n, 8] for the
+        sources [src_begin, src_end) (see adjoint_seeds).  With jac_stride > 0 also returns the
+        per-photon Jacobians [slots, 2, 22] of every jac_stride-th photon of the launch."""
+        import torch
+        src_end = self.n_sources if src_end is None else src_end
+        seeds = seeds.to(device=self.device, dtype=torch.float64).contiguous()
+        if seeds.shape != (src_end - src_begin, 8):
+            raise PhxError(f"seeds must be [{src_end - src_begin}, 8], got {tuple(seeds.shape)}")
+        a, _, _ = self._args(None, flags, seed, src_begin, src_end, photon_begin, photon_count,
+                             None, None, 0, None, None, adjoint_only=True)
+        if grad is None:
+            grad = torch.zeros(N_THETA, dtype=torch.float64, device=self.device)
+        jac = None
+        jp, cap = None, 0
+        if jac_stride:
+            if photon_count:
+                total = photon_count * (src_end - src_begin)
+            else:
+                total = int(self.scene.sources.n_photons[src_begin:src_end].sum())
+            cap = (total + jac_stride - 1) // jac_stride
+            jac = torch.zeros((cap, 2, N_THETA), dtype=torch.float64, device=self.device)
+            jp = jac.data_ptr()
+        self._check(self.L.phx_adjoint(self.ctx, C.byref(a), seeds.data_ptr(), grad.data_ptr(), jp,
+                                       int(jac_stride), int(cap), _stream_handle(stream)))
+        return (grad, jac) if jac_stride else grad
 
     def launch_config(self) -> dict:
         cfg = LaunchConfig()
@@ -393,6 +425,27 @@ def quantised_sums(xe, ye):
     Y = [int(v) for v in np.rint(np.asarray(ye, np.float64) * q)]
     return (len(X), sum(X), sum(Y), sum(a * a for a in X), sum(b * b for b in Y),
             sum(a * b for a, b in zip(X, Y)))
+
+
+def adjoint_seeds(mom, gout) -> np.ndarray:
+    """Per-source cotangent coefficients for phx_adjoint from the forward moments
+    mom [n, 6] = (n, mean x, mean y, Ixx, Iyy, Ixy) and the loss gradient gout [n, 5] with
+    respect to (mean x, mean y, Ixx, Iyy, Ixy): d mean/d x_i = 1/n, d Ixx/d x_i = 2 (x_i - mean)/n,
+    d Ixy/d x_i = (y_i - mean y)/n.  Sources without converted photons get zero rows."""
+    mom = np.asarray(mom, np.float64)
+    g = np.asarray(gout, np.float64)
+    out = np.zeros((len(mom), 8))
+    n = mom[:, 0]
+    ok = n > 0
+    inv = np.where(ok, 1.0 / np.where(ok, n, 1.0), 0.0)
+    out[:, 0] = g[:, 0] * inv
+    out[:, 1] = g[:, 1] * inv
+    out[:, 2] = 2.0 * g[:, 2] * inv
+    out[:, 3] = 2.0 * g[:, 3] * inv
+    out[:, 4] = g[:, 4] * inv
+    out[:, 5] = mom[:, 1]
+    out[:, 6] = mom[:, 2]
+    return out
 
 
 def events_to_numpy(events) -> np.ndarray:
