@@ -81,6 +81,127 @@ def cpu_baseline(scene, n_photons, threads):
     return n_photons / dt, dt
 
 
+def batched_leg(steps, per_source_steps=1):
+    """Many uneven sources: one graph-replayed launch over all of them (launch shape picked by
+    the autotuner) against one plain launch per source, on the same GPU and the same photons."""
+    import numpy as np
+    import torch
+    from paper_1504_06570_amd import phx
+    from paper_1504_06570_amd.scene import configs as C
+    t0 = time.perf_counter()
+    scene = C.batched()
+    tr = phx.Tracer(scene)
+    print(f"# batched setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    flags = int(scene.physics) | phx.F_CULL
+    counts = scene.sources.n_photons.astype(np.int64)
+    total = int(counts.sum())
+    t0 = time.perf_counter()
+    best = tr.autotune(flags=flags)
+    t_tune = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # untimed first passes of both forms into fresh images: they must be identical
+    one_b = tr.new_image()
+    tr.trace(one_b, flags=flags, batched=True)
+    one_p = tr.new_image()
+    for s in range(len(counts)):
+        tr.trace(one_p, flags=flags, src_begin=s, src_end=s + 1, photon_count=int(counts[s]))
+    torch.cuda.synchronize()
+    same = bool(torch.equal(one_b, one_p))
+    del one_p
+    img = tr.new_image()
+    e0.record(stream)
+    for _ in range(steps):
+        tr.trace(img, flags=flags, batched=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(per_source_steps):
+        for s in range(len(counts)):
+            tr.trace(img, flags=flags, src_begin=s, src_end=s + 1, photon_count=int(counts[s]))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1) / per_source_steps
+    same = same and bool(torch.equal(img, one_b * (steps + per_source_steps)))
+    tr.close()
+    print(f"# batched {ms_b:.2f} ms, per-source {ms_p:.2f} ms, tune {t_tune:.1f}s {best}",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": f"{len(counts)} sources (80% stars, 20% Sersic), power-law counts slope -1.5 "
+                    f"on [10, 1e7], blackbody SEDs, full atmosphere + optics + sensor",
+        "photons_per_step": total,
+        "value": total / (ms_b * 1e-3),
+        "ms_per_step": ms_b,
+        "per_source_value": total / (ms_p * 1e-3),
+        "per_source_ms_per_step": ms_p,
+        "speedup_vs_per_source": ms_p / ms_b,
+        "images_identical": same,
+        "launch_config": best,
+        "autotune_s": t_tune,
+    }
+
+
+def gradient_leg(steps):
+    """Fixed-seed gradients of per-source centroids and second moments with respect to the 22
+    optics parameters: 25 stars on a 5 x 5 grid, 1e7 photons each, full atmosphere + optics +
+    sensor.  Times the forward trace with moments and the adjoint trace of the same photons."""
+    import numpy as np
+    import torch
+    from paper_1504_06570_amd import phx
+    from paper_1504_06570_amd.scene import configs as C
+    t0 = time.perf_counter()
+    scene = C.gradients()
+    tr = phx.Tracer(scene)
+    theta = np.random.default_rng(5).uniform(-1, 1, C.N_PERTURB) * C.PERTURB_RANGE
+    tr.set_perturbation(theta)
+    print(f"# gradient setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    flags = int(scene.physics) | phx.F_CULL
+    total = int(scene.sources.n_photons.sum())
+    stream = torch.cuda.current_stream()
+    img = tr.new_image()
+    m = tr.new_moments()
+    tr.trace(img, flags=flags, moments=m)
+    torch.cuda.synchronize()
+    mom = phx.moments(m)
+    gout = np.random.default_rng(6).standard_normal((len(mom), 5))
+    seeds = torch.from_numpy(phx.adjoint_seeds(mom, gout)).cuda()
+    grad = tr.adjoint(seeds, flags=flags)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        m.zero_()
+        tr.trace(img, flags=flags, moments=m)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1) / steps
+    tr.set_timing(True)
+    e0.record(stream)
+    for _ in range(steps):
+        tr.adjoint(seeds, flags=flags, grad=grad)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_a = e0.elapsed_time(e1) / steps
+    kt = tr.get_timing()
+    tr.set_timing(False)
+    tr.close()
+    print(f"# forward {ms_f:.2f} ms, adjoint {ms_a:.2f} ms, kernels {kt}", file=sys.stderr,
+          flush=True)
+    return {
+        "workload": "25 stars on a 5x5 field grid, 1e7 photons each, full atmosphere + optics + "
+                    "sensor, perturbed optics; gradients of per-source centroid and second "
+                    "moments with respect to 22 parameters",
+        "photons_per_step": total,
+        "forward_ms": ms_f,
+        "adjoint_ms": ms_a,
+        "adjoint_forward_ratio": ms_a / ms_f,
+        "forward_photons_per_s": total / (ms_f * 1e-3),
+        "adjoint_photons_per_s": total / (ms_a * 1e-3),
+        "adjoint_stage_ms": {k: kt[k] / steps for k in ("generate", "front", "back")},
+    }
+
+
 def copy_probe():
     """A plain 1 GiB device copy, for calibrating the HBM byte counters."""
     import torch
@@ -104,6 +225,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the run without the pre-roll")
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-source batched leg")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -192,6 +315,13 @@ def main():
                          f"{dt:.1f} s on {threads} host threads"}
         print(f"# cpu oracle {rate:.3e} photons/s ({dt:.1f}s)", file=sys.stderr, flush=True)
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(max(args.steps, 1))
+    gradient = None
+    if not args.no_gradient:
+        gradient = gradient_leg(max(args.steps, 1))
+
     traffic = traffic_from_profiles(n_ph, f"{dom}_kernel")
     out = {
         "metric": METRIC,
@@ -226,7 +356,9 @@ def main():
         },
         "stage_ms_per_step": stage_ms,
         "cpu_baseline": cpu,
-        "adjoint_forward_ratio": None,
+        "batched": batched,
+        "gradient": gradient,
+        "adjoint_forward_ratio": gradient["adjoint_forward_ratio"] if gradient else None,
     }
     out.update(extra)
     print(json.dumps(out), flush=True)

@@ -69,6 +69,8 @@ struct phx_ctx_s {
     double* d_colsum = nullptr;
     uint64_t* d_bits = nullptr;
     unsigned int* d_bsum = nullptr;
+    uint8_t* d_key = nullptr;
+    unsigned int* d_hist = nullptr;
     void graphs_clear() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
@@ -311,6 +313,8 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_colsum);
     free_dev(c->d_bits);
     free_dev(c->d_bsum);
+    free_dev(c->d_key);
+    free_dev(c->d_hist);
     c->graphs_clear();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -703,6 +707,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         free_dev(c->d_state);
         free_dev(c->d_bits);
         free_dev(c->d_bsum);
+        free_dev(c->d_key);
+        free_dev(c->d_hist);
         c->ws_chunk = 0;
         c->graphs_clear();
         e = hipMalloc((void**)&c->d_survivors, chunk * sizeof(uint32_t));
@@ -710,6 +716,10 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_bits, (chunk + 63) / 64 * sizeof(uint64_t));
         if (e == hipSuccess)
             e = hipMalloc((void**)&c->d_bsum, phx::compact_groups(chunk) * sizeof(unsigned int));
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_key, chunk);
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&c->d_hist, 2 * phx::compact_groups(chunk) *
+                                                  phx::kTimeBucketsMax * sizeof(unsigned int));
         if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "trace workspace: %s",
                                          hipGetErrorString(e));
         c->ws_chunk = chunk;
@@ -730,7 +740,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     }
     W = phx::Workspace{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk,
                        (unsigned long long*)c->d_tiles, (unsigned long long*)c->d_bits,
-                       c->d_bsum};
+                       c->d_bsum, c->d_key, c->d_hist};
     return upload_params(c, st);
 }
 

@@ -104,7 +104,10 @@ struct Workspace {
     unsigned long long* tiles; // [n_chunks][2] tile counters of the dynamic schedule
     unsigned long long* bits;  // [chunk / 64] survivor bitmap
     unsigned int* bsum;        // [compact_groups(chunk)] survivors per compaction workgroup
+    uint8_t* key;              // [chunk] time bucket of each survivor
+    unsigned int* hist;        // [2][compact_groups(chunk)][kTimeBucketsMax] counts, offsets
 };
+constexpr int kTimeBucketsMax = 64;
 // Workgroups of the ordered compaction for a chunk of n photons (64 photons per bitmap word,
 // 4096 words per workgroup).
 inline uint64_t compact_groups(uint64_t n) { return ((n + 63) / 64 + 4095) / 4096; }

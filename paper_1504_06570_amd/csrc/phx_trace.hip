@@ -24,15 +24,21 @@ constexpr double kHcEvM = 1.2398419843320026e-6;  // h c / e in eV m
 constexpr double kNewtonTol = 1e-12;             // m
 constexpr int kNewtonMax = 16;
 constexpr int kBlock = kThreads;
+constexpr int kTimeBuckets = kTimeBucketsMax;   // time buckets of the survivor sort
+static_assert(kTimeBuckets <= 256, "bucket ids are stored in one byte");
 
 // ---------------------------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11).
+// Philox4x32-10 (Salmon et al., SC'11).  Each round's two 32x32 -> 64-bit products come from one
+// v_mad_u64_u32 each, and each three-way xor from one v_bitop3 (truth table 0x96).
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96),
+                       (uint32_t)p1,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96),
+                       (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -306,9 +312,10 @@ __device__ __forceinline__ double wavelength(const DevParams& P, const DevSource
 // Pre-roll test (section 3.2): true when a coated surface's roulette draw exceeds the largest
 // transmission that coating has at this wavelength for any angle, so the photon cannot survive.
 __device__ bool preroll_culls(const DevParams& P, const Launch& L, int si, uint64_t idx,
-                              double& lam) {
+                              double& lam, uint32_t& w_time) {
     const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
     const uint4 w0 = rng.block(0);
+    w_time = w0.z;
     const DevSource& src = P.src[si];
     uint4 w1 = make_uint4(0, 0, 0, 0);
     if (src.sed >= 0) w1 = rng.block(1);
@@ -747,7 +754,8 @@ __device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, 
 __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __restrict__ Pg,
                                                           const Launch L, uint64_t begin,
                                                           uint64_t len,
-                                                          unsigned long long* __restrict__ bits) {
+                                                          unsigned long long* __restrict__ bits,
+                                                          uint8_t* __restrict__ key) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
     stats_init(s_stats);
     const DevParams& P = *Pg;
@@ -763,7 +771,10 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
             uint64_t idx;
             decode(L, g, si, idx);
             double lam;
-            keep = !preroll_culls(P, L, si, idx, lam);
+            uint32_t wt;
+            keep = !preroll_culls(P, L, si, idx, lam, wt);
+            // time bucket of a survivor (the time stamp is t_e u01(wt))
+            if (keep && key) key[r] = (uint8_t)min((int)(u01(wt) * kTimeBuckets), kTimeBuckets - 1);
             if (!keep) {
                 Outcome o;
                 o.status = PHX_CULLED; o.surface = -1; o.newton = 0; o.pix_i = o.pix_j = -1;
@@ -850,6 +861,99 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const unsigned long lo
         }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) *count = base + s_scan[kBlock - 1];
+}
+
+// Time-bucketed compaction (with the atmosphere): a stable counting sort of the survivors by
+// time bucket, so that photons traced together see the same wind-shifted stretch of every phase
+// screen and share its cache lines.  Within a bucket survivors keep photon order; the result is
+// the same on every run.
+__global__ __launch_bounds__(kBlock) void bucket_count(const unsigned long long* __restrict__ bits,
+                                                       const uint8_t* __restrict__ key,
+                                                       uint64_t n_words,
+                                                       unsigned int* __restrict__ hist) {
+    __shared__ unsigned int s_h[kTimeBuckets];
+    if (threadIdx.x < kTimeBuckets) s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWords;
+    for (int i = 0; i < kWordsPerThread; ++i) {
+        const uint64_t w = w0 + (uint64_t)i * kBlock + threadIdx.x;
+        if (w >= n_words) continue;
+        unsigned long long m = bits[w];
+        while (m) {
+            const int bit = __ffsll(m) - 1;
+            atomicAdd(&s_h[key[w * 64 + bit]], 1u);
+            m &= m - 1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kTimeBuckets) hist[(uint64_t)blockIdx.x * kTimeBuckets + threadIdx.x] = s_h[threadIdx.x];
+}
+
+// Start offset of every (workgroup, bucket) in bucket-major order; one workgroup.
+__global__ __launch_bounds__(kBlock) void bucket_scan(const unsigned int* __restrict__ hist,
+                                                      unsigned int n_groups,
+                                                      unsigned int* __restrict__ off,
+                                                      unsigned int* __restrict__ count) {
+    __shared__ unsigned int s_tot[kTimeBuckets];
+    const unsigned int b = threadIdx.x;
+    if (b < kTimeBuckets) {
+        unsigned int run = 0;
+        for (unsigned int g = 0; g < n_groups; ++g) {
+            const unsigned int v = hist[(uint64_t)g * kTimeBuckets + b];
+            off[(uint64_t)g * kTimeBuckets + b] = run;
+            run += v;
+        }
+        s_tot[b] = run;
+    }
+    __syncthreads();
+    if (b < kTimeBuckets) {
+        unsigned int base = 0;
+        for (unsigned int c = 0; c < b; ++c) base += s_tot[c];
+        for (unsigned int g = 0; g < n_groups; ++g) off[(uint64_t)g * kTimeBuckets + b] += base;
+        if (b == kTimeBuckets - 1) *count = base + s_tot[b];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void bucket_scatter(const unsigned long long* __restrict__ bits,
+                                                         const uint8_t* __restrict__ key,
+                                                         uint64_t n_words,
+                                                         const unsigned int* __restrict__ off,
+                                                         uint32_t* __restrict__ surv) {
+    __shared__ unsigned int s_c[kTimeBuckets][kBlock];   // per bucket, per thread: count, then slot
+    const int t = threadIdx.x;
+    for (int b = 0; b < kTimeBuckets; ++b) s_c[b][t] = 0;
+    const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWords + (uint64_t)t * kWordsPerThread;
+    for (int i = 0; i < kWordsPerThread; ++i) {
+        if (w0 + i >= n_words) break;
+        unsigned long long m = bits[w0 + i];
+        while (m) {
+            const int bit = __ffsll(m) - 1;
+            s_c[key[(w0 + i) * 64 + bit]][t] += 1;
+            m &= m - 1;
+        }
+    }
+    __syncthreads();
+    if (t < kTimeBuckets) {   // exclusive scan of bucket t over the threads, in thread order
+        unsigned int run = 0;
+        for (int u = 0; u < kBlock; ++u) {
+            const unsigned int v = s_c[t][u];
+            s_c[t][u] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const unsigned int* o = off + (uint64_t)blockIdx.x * kTimeBuckets;
+    for (int i = 0; i < kWordsPerThread; ++i) {
+        if (w0 + i >= n_words) break;
+        unsigned long long m = bits[w0 + i];
+        while (m) {
+            const int bit = __ffsll(m) - 1;
+            const int b = key[(w0 + i) * 64 + bit];
+            surv[o[b] + s_c[b][t]] = (uint32_t)((w0 + i) * 64 + bit);
+            s_c[b][t] += 1;
+            m &= m - 1;
+        }
+    }
 }
 
 // Block-uniform work distribution over [0, n): static (tile = block, block + grid, ...) or
@@ -1433,16 +1537,29 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
 
 }  // namespace
 
-// Pre-roll of one chunk: survivor bitmap, then the ordered survivor list and its count.
+// Pre-roll of one chunk: survivor bitmap, then the survivor list (in photon order, or sorted by
+// time bucket when the atmosphere is on) and its count.
 static void launch_preroll(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
                            const LaunchConfig& cfg, uint64_t begin, uint64_t len, uint64_t c,
                            hipStream_t stream) {
+    const bool sort = (L.flags & PHX_F_ATMOSPHERE) && W.key && W.hist;
     const uint64_t want = (len + kBlock - 1) / kBlock;
     const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
     hipLaunchKernelGGL(generate_kernel, dim3((unsigned)(want < cap ? want : cap)), dim3(kBlock), 0,
-                       stream, dparams, L, begin, len, W.bits);
+                       stream, dparams, L, begin, len, W.bits, sort ? W.key : (uint8_t*)nullptr);
     const uint64_t n_words = (len + 63) / 64;
     const unsigned nb = (unsigned)((n_words + kCompactWords - 1) / kCompactWords);
+    if (sort) {
+        hipLaunchKernelGGL(bucket_count, dim3(nb), dim3(kBlock), 0, stream,
+                           (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words, W.hist);
+        hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(kBlock), 0, stream,
+                           (const unsigned int*)W.hist, nb, W.hist + (uint64_t)nb * kTimeBuckets,
+                           W.counts + c);
+        hipLaunchKernelGGL(bucket_scatter, dim3(nb), dim3(kBlock), 0, stream,
+                           (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words,
+                           (const unsigned int*)(W.hist + (uint64_t)nb * kTimeBuckets), W.survivors);
+        return;
+    }
     hipLaunchKernelGGL(compact_count, dim3(nb), dim3(kBlock), 0, stream,
                        (const unsigned long long*)W.bits, n_words, W.bsum);
     hipLaunchKernelGGL(compact_scatter, dim3(nb), dim3(kBlock), 0, stream,
