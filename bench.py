@@ -343,6 +343,8 @@ def main():
             "photons_per_step": n_ph,
             "preroll_cull": not args.no_cull,
             "detected_per_step": detected,
+            "traced_per_step": traced / args.steps,
+            "newton_per_traced": float(st[phx.STAT_NEWTON]) / max(traced, 1.0),
         },
         "roofline": {
             "bound": d["bound"],

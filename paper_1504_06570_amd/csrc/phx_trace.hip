@@ -198,6 +198,17 @@ __device__ int intersect(const DevParams& P, const DevSurface& s, const double q
     const double den = B >= 0.0 ? B + sq : B - sq;
     if (den == 0.0) return PHX_MISSED;
     l = -C * rcp_fast(den);
+    if (s.asphere == 0 && !(ZERN && s.zernike)) {
+        // a plain conic: the root is the intersection (a Newton update would be rounding-sized,
+        // far below the tolerance); only the slope at the hit point is needed
+        const double x = q[0] + l * d[0], y = q[1] + l * d[1];
+        const double arg = 1.0 - s.kappa1 * s.c * s.c * (x * x + y * y);
+        if (arg < 0.0) return PHX_MISSED;
+        const double g = s.c * rsq_fast(arg);
+        gx = x * g;
+        gy = y * g;
+        return 0;
+    }
 #pragma unroll 1
     for (int it = 1; it <= kNewtonMax; ++it) {
         const double x = q[0] + l * d[0], y = q[1] + l * d[1], z = q[2] + l * d[2];
@@ -309,23 +320,27 @@ __device__ __forceinline__ double wavelength(const DevParams& P, const DevSource
     return lam * src.redshift1;
 }
 
-// Pre-roll test (section 3.2): true when a coated surface's roulette draw exceeds the largest
-// transmission that coating has at this wavelength for any angle, so the photon cannot survive.
-__device__ bool preroll_culls(const DevParams& P, const Launch& L, int si, uint64_t idx,
-                              double& lam, uint32_t& w_time) {
-    const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+// Pre-roll test (section 3.2): a photon is culled when a coated surface's roulette draw exceeds
+// the largest transmission that coating has at this wavelength for any angle, so it cannot
+// survive.  The coated surfaces are tested in order of decreasing selectivity; tests j0..j1-1
+// of that order.  preroll_draw gives the wavelength (and the time word) from the photon's first
+// Philox blocks.
+__device__ __forceinline__ double preroll_draw(const DevParams& P, const Rng& rng, int si,
+                                               uint32_t& w_time) {
     const uint4 w0 = rng.block(0);
     w_time = w0.z;
     const DevSource& src = P.src[si];
     uint4 w1 = make_uint4(0, 0, 0, 0);
     if (src.sed >= 0) w1 = rng.block(1);
-    lam = wavelength(P, src, w0, w1);
-    if (!((L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS))) return false;
-    // coated surfaces in order of decreasing selectivity, so most culled photons need one test
+    return wavelength(P, src, w0, w1);
+}
+
+__device__ __forceinline__ bool preroll_tests(const DevParams& P, const Rng& rng, double lam,
+                                              int j0, int j1) {
     const LamCol lc = lambda_column(P, lam);
     int blk = -1;
     uint4 w = make_uint4(0, 0, 0, 0);
-    for (int j = 0; j < P.n_cull; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const int k = P.cull_order[j];
         if (2 + (k >> 2) != blk) {
             blk = 2 + (k >> 2);
@@ -671,13 +686,29 @@ __device__ __forceinline__ void write_event(const Launch& L, uint64_t g, int si,
     e.x = o.x; e.y = o.y; e.z = o.z; e.xe = o.xe; e.ye = o.ye; e.lambda = o.lam;
 }
 
-// Book-keeping of one traced photon: LDS status counter and event record; returns the pixel to
-// bin (-1 for none).
-__device__ __forceinline__ int account(const DevParams& P, const Launch& L, uint32_t* s_stats,
-                                       uint64_t g, int si, uint64_t idx, const Outcome& o) {
-    atomicAdd(&s_stats[o.status * PHX_STAT_COLS + min(o.surface + 1, PHX_STAT_COLS - 1)], 1u);
+// Book-keeping of one traced photon: event record; returns the pixel to bin (-1 for none).
+__device__ __forceinline__ int account(const DevParams& P, const Launch& L, uint64_t g, int si,
+                                       uint64_t idx, const Outcome& o) {
     if ((L.flags & PHX_F_EVENTS) && (g % L.event_stride) == 0) write_event(L, g, si, idx, o);
     return o.status == PHX_DETECTED ? o.pix_j * P.nx + o.pix_i : -1;
+}
+
+__device__ __forceinline__ int stat_slot(const Outcome& o) {
+    return o.status * PHX_STAT_COLS + min(o.surface + 1, PHX_STAT_COLS - 1);
+}
+
+// Wavefront-aggregated status count: lanes with the same (status, surface) slot add their count
+// with one LDS atomic.  Every lane of the wavefront must call it.
+__device__ __forceinline__ void count_stat(uint32_t* s_stats, int slot, bool active) {
+    uint64_t pending = __ballot(active);
+    const int lane = __lane_id();
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int key = __shfl(slot, leader);
+        const uint64_t same = __ballot(active && slot == key);
+        if (lane == leader) atomicAdd(&s_stats[key], (uint32_t)__popcll(same));
+        pending &= ~same;
+    }
 }
 
 // Exact per-source moments of converted photons.  Positions are quantised to 2^-44 m and the
@@ -745,47 +776,106 @@ __device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, 
     }
 }
 
-// Pre-roll (section 3.2, dynamic transmission optimisation): draw each photon's wavelength and
-// coating roulette numbers; photons whose draw exceeds the worst-case transmission of a coated
-// surface cannot be detected and are counted as culled.  Each wavefront writes the survivor
-// mask of its 64 consecutive photons as one bitmap word (no atomics); an ordered compaction
-// (compact_count, compact_scatter) then lists the survivors in photon order, so every later
-// stage sees the same photon in the same slot on every run.
+// Pre-roll (section 3.2, dynamic transmission optimisation).  Each workgroup takes contiguous
+// ranges of kGenRange photons.  Stage one draws every photon's wavelength and applies the most
+// selective coating test; its survivors are queued in LDS and stage two applies the remaining
+// tests to them densely, so the many photons that fail the first test cost one test.  The
+// survivors' bits are set in an LDS copy of the range's bitmap words, written out once (the
+// bitmap does not depend on the order of the queue), with each survivor's time bucket when
+// requested.  An ordered compaction then lists the survivors.
+constexpr int kGenIters = 16;
+constexpr int kGenRange = kBlock * kGenIters;   // photons per range (64 bitmap words)
+
+__device__ __forceinline__ void culled_event(const Launch& L, uint64_t g, int si, uint64_t idx,
+                                             double lam) {
+    if ((L.flags & PHX_F_EVENTS) && (g % L.event_stride) == 0) {
+        Outcome o;
+        o.status = PHX_CULLED; o.surface = -1; o.newton = 0; o.pix_i = o.pix_j = -1;
+        o.x = o.y = o.z = o.xe = o.ye = 0.0;
+        o.lam = lam;
+        write_event(L, g, si, idx, o);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __restrict__ Pg,
                                                           const Launch L, uint64_t begin,
                                                           uint64_t len,
                                                           unsigned long long* __restrict__ bits,
                                                           uint8_t* __restrict__ key) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
+    __shared__ unsigned long long s_bits[kGenRange / 64];
+    __shared__ uint16_t s_q[kGenRange];
+    __shared__ unsigned int s_qn;
     stats_init(s_stats);
     const DevParams& P = *Pg;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t n_iter = (len + stride - 1) / stride;   // the same for every thread
-    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id();
-    for (uint64_t it = 0; it < n_iter; ++it, r += stride) {
-        bool keep = false;
-        if (r < len) {
-            const uint64_t g = begin + r;
-            int si;
-            uint64_t idx;
-            decode(L, g, si, idx);
-            double lam;
-            uint32_t wt;
-            keep = !preroll_culls(P, L, si, idx, lam, wt);
-            // time bucket of a survivor (the time stamp is t_e u01(wt))
-            if (keep && key) key[r] = (uint8_t)min((int)(u01(wt) * kTimeBuckets), kTimeBuckets - 1);
-            if (!keep) {
-                Outcome o;
-                o.status = PHX_CULLED; o.surface = -1; o.newton = 0; o.pix_i = o.pix_j = -1;
-                o.x = o.y = o.z = o.xe = o.ye = 0.0;
-                o.lam = lam;
-                account(P, L, s_stats, g, si, idx, o);
+    const int n_tests = P.n_cull;
+    const uint64_t n_ranges = (len + kGenRange - 1) / kGenRange;
+    for (uint64_t rg = blockIdx.x; rg < n_ranges; rg += gridDim.x) {   // workgroup-uniform
+        const uint64_t r0 = rg * kGenRange;
+        if (threadIdx.x < kGenRange / 64) s_bits[threadIdx.x] = 0ull;
+        if (threadIdx.x == 0) s_qn = 0;
+        __syncthreads();
+        // stage one: wavelength and the first test for every photon of the range
+        for (int it = 0; it < kGenIters; ++it) {
+            const int rr = it * kBlock + threadIdx.x;
+            const uint64_t r = r0 + rr;
+            bool pass = false, culled = false;
+            if (r < len) {
+                const uint64_t g = begin + r;
+                int si;
+                uint64_t idx;
+                decode(L, g, si, idx);
+                const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                uint32_t wt;
+                const double lam = preroll_draw(P, rng, si, wt);
+                culled = preroll_tests(P, rng, lam, 0, min(n_tests, 1));
+                pass = !culled;
+                if (culled) culled_event(L, g, si, idx, lam);
             }
+            const uint64_t pm = __ballot(pass), cm = __ballot(culled);
+            unsigned int base = 0;
+            if (lane == 0) {
+                if (pm) base = atomicAdd(&s_qn, (unsigned int)__popcll(pm));
+                if (cm) atomicAdd(&s_stats[PHX_CULLED * PHX_STAT_COLS], (uint32_t)__popcll(cm));
+            }
+            base = __shfl(base, 0);
+            if (pass) s_q[base + __popcll(pm & ((1ull << lane) - 1ull))] = (uint16_t)rr;
         }
-        const uint64_t mask = __ballot(keep);
-        // r - lane is a multiple of 64: block and grid strides are multiples of the wavefront
-        if (lane == 0 && r < len) bits[r >> 6] = (unsigned long long)mask;
+        __syncthreads();
+        // stage two: the remaining tests for the queued photons
+        const unsigned int qn = s_qn;
+        for (unsigned int q0 = 0; q0 < qn; q0 += kBlock) {
+            const unsigned int qi = q0 + threadIdx.x;
+            bool keep = false, culled = false;
+            if (qi < qn) {
+                const int rr = s_q[qi];
+                const uint64_t r = r0 + rr;
+                const uint64_t g = begin + r;
+                int si;
+                uint64_t idx;
+                decode(L, g, si, idx);
+                const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                uint32_t wt;
+                const double lam = preroll_draw(P, rng, si, wt);
+                culled = preroll_tests(P, rng, lam, 1, n_tests);
+                keep = !culled;
+                if (keep) {
+                    atomicOr(&s_bits[rr >> 6], 1ull << (rr & 63));
+                    // time bucket of a survivor (the time stamp is t_e u01(wt))
+                    if (key) key[r] = (uint8_t)min((int)(u01(wt) * kTimeBuckets), kTimeBuckets - 1);
+                } else {
+                    culled_event(L, g, si, idx, lam);
+                }
+            }
+            const uint64_t cm = __ballot(culled);
+            if (lane == 0 && cm)
+                atomicAdd(&s_stats[PHX_CULLED * PHX_STAT_COLS], (uint32_t)__popcll(cm));
+        }
+        __syncthreads();
+        if (threadIdx.x < kGenRange / 64 && r0 + (uint64_t)threadIdx.x * 64 < len)
+            bits[(r0 >> 6) + threadIdx.x] = s_bits[threadIdx.x];
+        __syncthreads();
     }
     stats_flush(L, s_stats, 0u, 0u);
 }
@@ -1043,7 +1133,7 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
     while (T.next(&s_tile)) {   // block-uniform: every lane takes part in the wavefront ballots
         const uint64_t r = T.index();
         int pix = -1;
-        int m_si = 0;
+        int m_si = 0, slot = 0;
         double m_x = 0.0, m_y = 0.0;
         bool m_on = false;
         if (r < n) {
@@ -1064,7 +1154,8 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
             traced += 1;
             m_si = si; m_x = o.xe; m_y = o.ye;
             m_on = (L.flags & PHX_F_MOMENTS) && o.status <= PHX_OFF_CHIP;
-            if (account(P, L, s_stats, g, si, idx, o) >= 0) {
+            slot = stat_slot(o);
+            if (account(P, L, g, si, idx, o) >= 0) {
                 int org = s_org;
                 if (org < 0) {
                     const int want = (max(o.pix_i - kWin / 2, 0) << 16) | max(o.pix_j - kWin / 2, 0);
@@ -1079,6 +1170,7 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
             }
         }
         bin_photon(L.image, pix, pix >= 0);
+        count_stat(s_stats, slot, r < n);
         if (L.flags & PHX_F_MOMENTS) add_moments(L, m_si, m_x, m_y, m_on);
     }
     stats_flush(L, s_stats, newton, traced);   // ends with a barrier
@@ -1543,7 +1635,7 @@ static void launch_preroll(const DevParams* dparams, const Launch& L, const Work
                            const LaunchConfig& cfg, uint64_t begin, uint64_t len, uint64_t c,
                            hipStream_t stream) {
     const bool sort = (L.flags & PHX_F_ATMOSPHERE) && W.key && W.hist;
-    const uint64_t want = (len + kBlock - 1) / kBlock;
+    const uint64_t want = (len + kGenRange - 1) / kGenRange;
     const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
     hipLaunchKernelGGL(generate_kernel, dim3((unsigned)(want < cap ? want : cap)), dim3(kBlock), 0,
                        stream, dparams, L, begin, len, W.bits, sort ? W.key : (uint8_t*)nullptr);
