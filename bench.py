@@ -227,6 +227,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the run without the pre-roll")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-source batched leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--only", choices=("batched", "gradient"), default=None,
+                    help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -234,6 +236,10 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.only:
+        leg = batched_leg if args.only == "batched" else gradient_leg
+        print(json.dumps(leg(max(args.steps, 1))), flush=True)
         return
     import numpy as np
     import torch

@@ -71,6 +71,7 @@ struct phx_ctx_s {
     unsigned int* d_bsum = nullptr;
     uint8_t* d_key = nullptr;
     unsigned int* d_hist = nullptr;
+    std::vector<phx::ChunkSpan> plan;
     void graphs_clear() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
@@ -725,7 +726,26 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         c->ws_chunk = chunk;
     }
     chunk = std::min<uint64_t>(c->ws_chunk, max_chunk);
-    const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
+    // Chunk plan.  With the atmosphere, a chunk that holds one source has its survivors sorted by
+    // time (screen locality); launches of big sources are cut at source boundaries for that,
+    // launches of many small sources are cut evenly and keep photon order.
+    c->plan.clear();
+    const bool atm = (a->flags & PHX_F_ATMOSPHERE) != 0;
+    const bool per_source = atm && L.n_src > 1 && L.total / (uint64_t)L.n_src >= chunk / 8;
+    if (per_source) {
+        uint64_t start = 0;
+        for (int s = 0; s < L.n_src; ++s) {
+            const uint64_t n_s = L.uniform_count ? L.uniform_count
+                                                 : c->src[a->src_begin + s].n_photons;
+            for (uint64_t o = 0; o < n_s; o += chunk)
+                c->plan.push_back({start + o, std::min(chunk, n_s - o), 1, 0});
+            start += n_s;
+        }
+    } else {
+        for (uint64_t b = 0; b < L.total; b += chunk)
+            c->plan.push_back({b, std::min(chunk, L.total - b), (atm && L.n_src == 1) ? 1 : 0, 0});
+    }
+    const uint64_t n_chunks = c->plan.size();
     if (n_chunks > c->counts_cap) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
@@ -740,7 +760,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     }
     W = phx::Workspace{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk,
                        (unsigned long long*)c->d_tiles, (unsigned long long*)c->d_bits,
-                       c->d_bsum, c->d_key, c->d_hist};
+                       c->d_bsum, c->d_key, c->d_hist, c->plan.data(), (uint64_t)c->plan.size()};
     return upload_params(c, st);
 }
 
@@ -837,7 +857,7 @@ phx_status phx_adjoint(phx_ctx c, const phx_trace_args* a, const double* seed_de
     // Adjoint workspace: tape for every thread of one launch, one partial row per workgroup
     const uint64_t grid = (uint64_t)c->n_cu * c->adj_per_cu;
     const uint64_t threads = grid * phx::kThreads;
-    const uint64_t n_chunks = L.total ? (L.total + W.chunk - 1) / W.chunk : 0;
+    const uint64_t n_chunks = W.n_plan;
     const uint64_t tape_need = (uint64_t)c->presc.n_surfaces * phx::kTapeFields * threads;
     const uint64_t rows_need = std::max<uint64_t>(n_chunks * grid, 1);
     if (tape_need > c->tape_cap || rows_need > c->rows_cap || !c->d_colsum) {

@@ -95,6 +95,12 @@ struct Launch {
 // survivor counter, and the start-plane state of every traced photon (7 doubles each,
 // structure of arrays).
 constexpr uint64_t kChunk = 1ull << 26;
+// One chunk of a launch: photons [begin, begin + len) of the flattened launch index, and whether
+// its pre-roll survivors are sorted by time bucket (chunks holding a single source).
+struct ChunkSpan {
+    uint64_t begin, len;
+    int32_t sort, pad;
+};
 struct Workspace {
     uint32_t* survivors;       // [chunk]
     unsigned int* counts;      // [n_chunks]
@@ -105,7 +111,9 @@ struct Workspace {
     unsigned long long* bits;  // [chunk / 64] survivor bitmap
     unsigned int* bsum;        // [compact_groups(chunk)] survivors per compaction workgroup
     uint8_t* key;              // [chunk] time bucket of each survivor
-    unsigned int* hist;        // [2][compact_groups(chunk)][kTimeBucketsMax] counts, offsets
+    unsigned int* hist;        // [compact_groups(chunk)][kTimeBucketsMax] survivors per bucket
+    const ChunkSpan* plan;     // host array: the launch's chunks in order
+    uint64_t n_plan;
 };
 constexpr int kTimeBucketsMax = 64;
 // Workgroups of the ordered compaction for a chunk of n photons (64 photons per bitmap word,

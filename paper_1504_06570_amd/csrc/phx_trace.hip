@@ -733,7 +733,31 @@ __device__ __forceinline__ void atomic_add128(unsigned long long* w, unsigned __
     if (hi + carry) atomicAdd(w + 1, hi + carry);
 }
 
-__device__ void add_moments(const Launch& L, int si, double xe, double ye, bool active) {
+// Moments of one source are first gathered in a per-workgroup LDS record (the first source the
+// workgroup meets, s_src); other sources, and the record at the end of the workgroup, go to the
+// global words.  Without it every wavefront of a one-source launch would add to the same twelve
+// global words.
+struct MomentCache {
+    unsigned long long w[PHX_MOMENT_WORDS];
+    int src;
+};
+
+__device__ __forceinline__ void moment_cache_init(MomentCache* mc) {
+    if (threadIdx.x < PHX_MOMENT_WORDS) mc->w[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) mc->src = -1;
+}
+
+// Called by one thread after the workgroup's last add_moments (and a barrier).
+__device__ __forceinline__ void moment_cache_flush(const Launch& L, MomentCache* mc) {
+    if (mc->src < 0) return;
+    unsigned long long* w = L.moments + (size_t)mc->src * PHX_MOMENT_WORDS;
+    atomicAdd(w, mc->w[0]);
+    for (int i = 0; i < 5; ++i)
+        atomic_add128(w + 2 + 2 * i, ((unsigned __int128)mc->w[3 + 2 * i] << 64) | mc->w[2 + 2 * i]);
+}
+
+__device__ void add_moments(const Launch& L, int si, double xe, double ye, bool active,
+                            MomentCache* mc) {
     uint64_t pending = __ballot(active);
     const int lane = __lane_id();
     while (pending) {
@@ -752,7 +776,13 @@ __device__ void add_moments(const Launch& L, int si, double xe, double ye, bool 
 #pragma unroll
         for (int i = 0; i < 5; ++i) wave_sum128(v[i]);
         if (lane == leader) {
-            unsigned long long* w = L.moments + (size_t)key * PHX_MOMENT_WORDS;
+            int cached = mc->src;
+            if (cached < 0) {
+                const int prev = atomicCAS(&mc->src, -1, key);
+                cached = prev < 0 ? key : prev;
+            }
+            unsigned long long* w = cached == key ? mc->w
+                                                  : L.moments + (size_t)key * PHX_MOMENT_WORDS;
             atomicAdd(w, (unsigned long long)__popcll(same));
 #pragma unroll
             for (int i = 0; i < 5; ++i) atomic_add128(w + 2 + 2 * i, v[i]);
@@ -979,38 +1009,46 @@ __global__ __launch_bounds__(kBlock) void bucket_count(const unsigned long long*
     if (threadIdx.x < kTimeBuckets) hist[(uint64_t)blockIdx.x * kTimeBuckets + threadIdx.x] = s_h[threadIdx.x];
 }
 
-// Start offset of every (workgroup, bucket) in bucket-major order; one workgroup.
-__global__ __launch_bounds__(kBlock) void bucket_scan(const unsigned int* __restrict__ hist,
-                                                      unsigned int n_groups,
-                                                      unsigned int* __restrict__ off,
-                                                      unsigned int* __restrict__ count) {
-    __shared__ unsigned int s_tot[kTimeBuckets];
-    const unsigned int b = threadIdx.x;
-    if (b < kTimeBuckets) {
-        unsigned int run = 0;
-        for (unsigned int g = 0; g < n_groups; ++g) {
-            const unsigned int v = hist[(uint64_t)g * kTimeBuckets + b];
-            off[(uint64_t)g * kTimeBuckets + b] = run;
-            run += v;
-        }
-        s_tot[b] = run;
-    }
-    __syncthreads();
-    if (b < kTimeBuckets) {
-        unsigned int base = 0;
-        for (unsigned int c = 0; c < b; ++c) base += s_tot[c];
-        for (unsigned int g = 0; g < n_groups; ++g) off[(uint64_t)g * kTimeBuckets + b] += base;
-        if (b == kTimeBuckets - 1) *count = base + s_tot[b];
-    }
-}
-
+// Each workgroup first derives where its survivors of every bucket start: the survivors of all
+// earlier buckets, plus those of its bucket in earlier workgroups (from the per-workgroup
+// histograms); the last workgroup stores the total in *count.
 __global__ __launch_bounds__(kBlock) void bucket_scatter(const unsigned long long* __restrict__ bits,
                                                          const uint8_t* __restrict__ key,
                                                          uint64_t n_words,
-                                                         const unsigned int* __restrict__ off,
-                                                         uint32_t* __restrict__ surv) {
+                                                         const unsigned int* __restrict__ hist,
+                                                         uint32_t* __restrict__ surv,
+                                                         unsigned int* __restrict__ count) {
     __shared__ unsigned int s_c[kTimeBuckets][kBlock];   // per bucket, per thread: count, then slot
+    __shared__ unsigned int s_tot[kBlock / kTimeBuckets][kTimeBuckets];
+    __shared__ unsigned int s_pre[kBlock / kTimeBuckets][kTimeBuckets];
+    __shared__ unsigned int s_off[kTimeBuckets];
     const int t = threadIdx.x;
+    {
+        constexpr int kParts = kBlock / kTimeBuckets;
+        const int b = t % kTimeBuckets, part = t / kTimeBuckets;
+        unsigned int tot = 0, pre = 0;
+        for (unsigned int g = part; g < gridDim.x; g += kParts) {
+            const unsigned int v = hist[(uint64_t)g * kTimeBuckets + b];
+            tot += v;
+            if (g < blockIdx.x) pre += v;
+        }
+        s_tot[part][b] = tot;
+        s_pre[part][b] = pre;
+        __syncthreads();
+        if (t < kTimeBuckets) {
+            unsigned int base = 0, mine = 0, all = 0;
+            for (int c = 0; c < kTimeBuckets; ++c) {
+                unsigned int tc = 0;
+                for (int q = 0; q < kParts; ++q) tc += s_tot[q][c];
+                if (c < t) base += tc;
+                all += tc;
+            }
+            for (int q = 0; q < kParts; ++q) mine += s_pre[q][t];
+            s_off[t] = base + mine;
+            if (blockIdx.x == gridDim.x - 1 && t == 0) *count = all;
+        }
+        __syncthreads();
+    }
     for (int b = 0; b < kTimeBuckets; ++b) s_c[b][t] = 0;
     const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWords + (uint64_t)t * kWordsPerThread;
     for (int i = 0; i < kWordsPerThread; ++i) {
@@ -1032,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter(const unsigned long lon
         }
     }
     __syncthreads();
-    const unsigned int* o = off + (uint64_t)blockIdx.x * kTimeBuckets;
+    const unsigned int* o = s_off;
     for (int i = 0; i < kWordsPerThread; ++i) {
         if (w0 + i >= n_words) break;
         unsigned long long m = bits[w0 + i];
@@ -1123,8 +1161,10 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
     __shared__ uint32_t s_win[kWin * kWin];
     __shared__ unsigned long long s_tile;
     __shared__ int s_org;   // window origin: (i0 << 16) | j0, or -1 before the first detection
+    __shared__ MomentCache s_mc;
     for (int i = threadIdx.x; i < kWin * kWin; i += blockDim.x) s_win[i] = 0;
     if (threadIdx.x == 0) s_org = -1;
+    moment_cache_init(&s_mc);
     stats_init(s_stats);
     const DevParams& P = *Pg;
     const uint64_t n = surv ? (uint64_t)*count : n_all;
@@ -1171,9 +1211,10 @@ __global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restric
         }
         bin_photon(L.image, pix, pix >= 0);
         count_stat(s_stats, slot, r < n);
-        if (L.flags & PHX_F_MOMENTS) add_moments(L, m_si, m_x, m_y, m_on);
+        if (L.flags & PHX_F_MOMENTS) add_moments(L, m_si, m_x, m_y, m_on, &s_mc);
     }
     stats_flush(L, s_stats, newton, traced);   // ends with a barrier
+    if (threadIdx.x == 0 && (L.flags & PHX_F_MOMENTS)) moment_cache_flush(L, &s_mc);
     const int org = s_org;
     if (org >= 0) {
         const int i0 = org >> 16, j0 = org & 0xffff;
@@ -1630,26 +1671,24 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
 }  // namespace
 
 // Pre-roll of one chunk: survivor bitmap, then the survivor list (in photon order, or sorted by
-// time bucket when the atmosphere is on) and its count.
+// time bucket) and its count.
 static void launch_preroll(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                           const LaunchConfig& cfg, uint64_t begin, uint64_t len, uint64_t c,
+                           const LaunchConfig& cfg, const ChunkSpan& sp, uint64_t c,
                            hipStream_t stream) {
-    const bool sort = (L.flags & PHX_F_ATMOSPHERE) && W.key && W.hist;
-    const uint64_t want = (len + kGenRange - 1) / kGenRange;
+    const bool sort = sp.sort && W.key && W.hist;
+    const uint64_t want = (sp.len + kGenRange - 1) / kGenRange;
     const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
     hipLaunchKernelGGL(generate_kernel, dim3((unsigned)(want < cap ? want : cap)), dim3(kBlock), 0,
-                       stream, dparams, L, begin, len, W.bits, sort ? W.key : (uint8_t*)nullptr);
-    const uint64_t n_words = (len + 63) / 64;
+                       stream, dparams, L, sp.begin, sp.len, W.bits,
+                       sort ? W.key : (uint8_t*)nullptr);
+    const uint64_t n_words = (sp.len + 63) / 64;
     const unsigned nb = (unsigned)((n_words + kCompactWords - 1) / kCompactWords);
     if (sort) {
         hipLaunchKernelGGL(bucket_count, dim3(nb), dim3(kBlock), 0, stream,
                            (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words, W.hist);
-        hipLaunchKernelGGL(bucket_scan, dim3(1), dim3(kBlock), 0, stream,
-                           (const unsigned int*)W.hist, nb, W.hist + (uint64_t)nb * kTimeBuckets,
-                           W.counts + c);
         hipLaunchKernelGGL(bucket_scatter, dim3(nb), dim3(kBlock), 0, stream,
                            (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words,
-                           (const unsigned int*)(W.hist + (uint64_t)nb * kTimeBuckets), W.survivors);
+                           (const unsigned int*)W.hist, W.survivors, W.counts + c);
         return;
     }
     hipLaunchKernelGGL(compact_count, dim3(nb), dim3(kBlock), 0, stream,
@@ -1668,19 +1707,20 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
     const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
     if (!W.state || !W.survivors || !W.counts || !W.bits || !W.bsum) return hipErrorInvalidValue;
     const uint64_t chunk = W.chunk;
-    const uint64_t n_chunks = (L.total + chunk - 1) / chunk;
-    if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
+    const uint64_t n_chunks = W.n_plan;
+    if (!W.plan || n_chunks > W.n_chunks) return hipErrorInvalidValue;
     if (cfg.dynamic)
         hipLaunchKernelGGL(fill_u32, dim3((unsigned)((4 * n_chunks + 255) / 256)), dim3(256), 0,
                            stream, (unsigned int*)W.tiles, 4 * n_chunks, 0u);
     for (uint64_t c = 0; c < n_chunks; ++c) {
-        const uint64_t begin = c * chunk;
-        const uint64_t len = L.total - begin < chunk ? L.total - begin : chunk;
+        const uint64_t begin = W.plan[c].begin;
+        const uint64_t len = W.plan[c].len;
+        if (len > chunk) return hipErrorInvalidValue;
         const uint32_t* surv = nullptr;
         const unsigned int* cnt = nullptr;
         if (preroll) {
             mark(0, 0);
-            launch_preroll(dparams, L, W, n_cu, cfg, begin, len, c, stream);
+            launch_preroll(dparams, L, W, n_cu, cfg, W.plan[c], c, stream);
             mark(0, 1);
             surv = W.survivors;
             cnt = W.counts + c;
@@ -1722,18 +1762,19 @@ hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Works
     if (grid * kBlock > A.tape_stride) return hipErrorInvalidValue;
     const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
     const uint64_t chunk = W.chunk;
-    const uint64_t n_chunks = L.total ? (L.total + chunk - 1) / chunk : 0;
-    if (n_chunks > W.n_chunks) return hipErrorInvalidValue;
+    const uint64_t n_chunks = W.n_plan;
+    if ((n_chunks && !W.plan) || n_chunks > W.n_chunks) return hipErrorInvalidValue;
     const bool jac = A.jac != nullptr;
     for (uint64_t c = 0; c < n_chunks; ++c) {
-        const uint64_t begin = c * chunk;
-        const uint64_t len = L.total - begin < chunk ? L.total - begin : chunk;
+        const uint64_t begin = W.plan[c].begin;
+        const uint64_t len = W.plan[c].len;
+        if (len > chunk) return hipErrorInvalidValue;
         const uint32_t* surv = nullptr;
         const unsigned int* cnt = nullptr;
         const uint64_t want = (len + kBlock - 1) / kBlock;
         if (preroll) {
             mark(0, 0);
-            launch_preroll(dparams, L, W, n_cu, cfg, begin, len, c, stream);
+            launch_preroll(dparams, L, W, n_cu, cfg, W.plan[c], c, stream);
             mark(0, 1);
             surv = W.survivors;
             cnt = W.counts + c;

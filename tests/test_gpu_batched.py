@@ -124,3 +124,19 @@ def test_batched_moments_match_per_source(phx, scene):
     assert torch.equal(m[rows], m_ref[rows])
     assert int(m[:, 0].sum()) > 0
     tr.close()
+
+
+def test_source_aligned_chunks_match(phx):
+    """Launches of a few big sources are cut at source boundaries and their survivors sorted by
+    time; images, statistics and moment words equal those of the evenly cut launch."""
+    import torch
+    s = C.gradients(scale=2e-4, screen_n=128)
+    tr = phx.Tracer(s)
+    kw = dict(src_begin=10, src_end=15, photon_count=20000, flags=int(s.physics) | phx.F_CULL)
+    ref, ref_st, ref_m, _ = tr.trace(stats=tr.new_stats(), moments=tr.new_moments(), **kw)
+    tr.set_launch_config(chunk_log2=16)      # chunk 65536: each source (20000) is >= chunk / 8
+    img, st, m, _ = tr.trace(stats=tr.new_stats(), moments=tr.new_moments(), **kw)
+    torch.cuda.synchronize()
+    assert int(ref.sum()) > 0 and int(ref_m[10:15, 0].min()) > 0
+    assert torch.equal(img, ref) and torch.equal(st, ref_st) and torch.equal(m, ref_m)
+    tr.close()
