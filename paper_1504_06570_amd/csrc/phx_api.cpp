@@ -58,6 +58,8 @@ struct phx_ctx_s {
     int prefix_begin = 0, prefix_end = 0;
     uint64_t src_version = 0, prefix_version = 0;
     hipStream_t cap_stream = nullptr;
+    hipStream_t aux_stream = nullptr;       // optics stage of the chunk pipeline
+    std::vector<hipEvent_t> pipe_ev;        // hand-off events of the chunk pipeline
     std::map<std::string, hipGraphExec_t> graphs;
     float autotune_ms = 0.0f;
     // adjoint workspace
@@ -318,6 +320,8 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_hist);
     c->graphs_clear();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+    for (hipEvent_t e : c->pipe_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -712,8 +716,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         free_dev(c->d_hist);
         c->ws_chunk = 0;
         c->graphs_clear();
-        e = hipMalloc((void**)&c->d_survivors, chunk * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, 7 * chunk * sizeof(double));
+        e = hipMalloc((void**)&c->d_survivors, 2 * chunk * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, 2 * 7 * chunk * sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_bits, (chunk + 63) / 64 * sizeof(uint64_t));
         if (e == hipSuccess)
             e = hipMalloc((void**)&c->d_bsum, phx::compact_groups(chunk) * sizeof(unsigned int));
@@ -760,17 +764,43 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     }
     W = phx::Workspace{c->d_survivors, c->d_counts, c->counts_cap, c->d_state, chunk,
                        (unsigned long long*)c->d_tiles, (unsigned long long*)c->d_bits,
-                       c->d_bsum, c->d_key, c->d_hist, c->plan.data(), (uint64_t)c->plan.size()};
+                       c->d_bsum, c->d_key, c->d_hist, c->plan.data(), (uint64_t)c->plan.size(),
+                       2};
+    if (c->cfg.pipeline) {
+        if (!c->aux_stream) {
+            hipError_t e = hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreate");
+        }
+        while (c->pipe_ev.size() < 2 * c->plan.size() + 1) {
+            hipEvent_t ev = nullptr;
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+            c->pipe_ev.push_back(ev);
+        }
+    }
     return upload_params(c, st);
 }
 
+phx::Pipe pipe_of(phx_ctx c) {
+    phx::Pipe p;
+    if (c->cfg.pipeline && c->aux_stream) {
+        p.aux = c->aux_stream;
+        p.ev = c->pipe_ev.data();
+        p.n_ev = c->pipe_ev.size();
+    }
+    return p;
+}
+
+// Eager launches (timed) may pipeline chunks over the context's streams; a launch being captured
+// into a graph stays on the capturing stream.
 phx_status enqueue(phx_ctx c, const phx::Launch& L, const phx::Workspace& W, hipStream_t st,
-                   bool timed) {
+                   bool eager) {
     phx::Timing T;
-    T.on = timed && c->timing;
+    T.on = eager && c->timing;
     T.record = timing_record;
     T.self = c;
-    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, c->cfg, st, T);
+    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, c->cfg, st,
+                                     eager ? pipe_of(c) : phx::Pipe{}, T);
     if (e != hipSuccess) return hip_fail(c, e, "trace kernel launch");
     return PHX_OK;
 }
@@ -797,9 +827,16 @@ phx_status phx_trace_batched(phx_ctx c, const phx_trace_args* a, void* stream) {
     phx_status r = prepare(c, a, st, L, W);
     if (r != PHX_OK) return r;
     // graph key: the launch description, the workspace and the launch shape
+    // (the launch description is value-initialised, so its padding is zero; the workspace
+    // fields are appended one by one)
     std::string key((const char*)&L, sizeof(L));
-    key.append((const char*)&W, sizeof(W));
-    key.append((const char*)&c->cfg, sizeof(c->cfg));
+    auto put = [&key](const void* p, size_t n) { key.append((const char*)p, n); };
+    const void* ptrs[] = {W.survivors, W.counts, W.state, W.tiles, W.bits, W.bsum, W.key, W.hist};
+    put(ptrs, sizeof(ptrs));
+    const uint64_t sizes[] = {W.n_chunks, W.chunk, W.n_plan, (uint64_t)W.buffers};
+    put(sizes, sizeof(sizes));
+    put(W.plan, W.n_plan * sizeof(phx::ChunkSpan));
+    put(&c->cfg, sizeof(c->cfg));
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         if (c->graphs.size() >= 32) c->graphs_clear();
@@ -896,7 +933,7 @@ phx_status phx_adjoint(phx_ctx c, const phx_trace_args* a, const double* seed_de
     T.record = timing_record;
     T.self = c;
     hipError_t e = phx::launch_adjoint(c->dparams, L, W, c->n_cu, c->cfg, A, c->d_colsum, grad_dev,
-                                       st, T);
+                                       st, pipe_of(c), T);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint kernel launch");
     return PHX_OK;
 }
@@ -907,13 +944,15 @@ phx_status phx_set_launch_config(phx_ctx c, const phx_launch_config* cfg) {
     if (cfg->chunk_log2 < 16 || cfg->chunk_log2 > 27 || cfg->generate_blocks_per_cu < 1 ||
         cfg->generate_blocks_per_cu > 64 || cfg->front_blocks_per_cu < 1 ||
         cfg->front_blocks_per_cu > 64 || cfg->back_blocks_per_cu < 1 ||
-        cfg->back_blocks_per_cu > 64 || (cfg->dynamic_tiles != 0 && cfg->dynamic_tiles != 1))
+        cfg->back_blocks_per_cu > 64 || (cfg->dynamic_tiles != 0 && cfg->dynamic_tiles != 1) ||
+        (cfg->pipeline != 0 && cfg->pipeline != 1))
         return fail(c, PHX_ERR_INVALID, "launch config out of range");
     c->chunk_log2 = cfg->chunk_log2;
     c->cfg.generate_per_cu = cfg->generate_blocks_per_cu;
     c->cfg.front_per_cu = cfg->front_blocks_per_cu;
     c->cfg.back_per_cu = cfg->back_blocks_per_cu;
     c->cfg.dynamic = cfg->dynamic_tiles;
+    c->cfg.pipeline = cfg->pipeline;
     return PHX_OK;
 }
 
@@ -925,6 +964,7 @@ phx_status phx_get_launch_config(phx_ctx c, phx_launch_config* cfg) {
     cfg->front_blocks_per_cu = c->cfg.front_per_cu;
     cfg->back_blocks_per_cu = c->cfg.back_per_cu;
     cfg->dynamic_tiles = c->cfg.dynamic;
+    cfg->pipeline = c->cfg.pipeline;
     return PHX_OK;
 }
 

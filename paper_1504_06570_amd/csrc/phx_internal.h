@@ -102,10 +102,10 @@ struct ChunkSpan {
     int32_t sort, pad;
 };
 struct Workspace {
-    uint32_t* survivors;       // [chunk]
+    uint32_t* survivors;       // [buffers][chunk]
     unsigned int* counts;      // [n_chunks]
     uint64_t n_chunks;
-    double* state;             // [7][chunk]
+    double* state;             // [buffers][7][chunk]
     uint64_t chunk;
     unsigned long long* tiles; // [n_chunks][2] tile counters of the dynamic schedule
     unsigned long long* bits;  // [chunk / 64] survivor bitmap
@@ -114,6 +114,14 @@ struct Workspace {
     unsigned int* hist;        // [compact_groups(chunk)][kTimeBucketsMax] survivors per bucket
     const ChunkSpan* plan;     // host array: the launch's chunks in order
     uint64_t n_plan;
+    int buffers;               // survivors and states hold this many chunks (1 or 2)
+};
+
+// Second stream and events for pipelining chunks (aux null: everything on the caller's stream).
+struct Pipe {
+    hipStream_t aux = nullptr;   // optics stage
+    hipEvent_t* ev = nullptr;    // at least 2 n_chunks + 1 events
+    uint64_t n_ev = 0;
 };
 constexpr int kTimeBucketsMax = 64;
 // Workgroups of the ordered compaction for a chunk of n photons (64 photons per bitmap word,
@@ -128,6 +136,7 @@ struct LaunchConfig {
     int front_per_cu = 32;
     int back_per_cu = 4;
     int dynamic = 0;
+    int pipeline = 1;
 };
 constexpr int kTileIters = 8;
 constexpr int kThreads = 256;   // workgroup size of every trace kernel
@@ -141,7 +150,8 @@ struct Timing {
 };
 
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                        const LaunchConfig& cfg, hipStream_t stream, const Timing& T);
+                        const LaunchConfig& cfg, hipStream_t stream, const Pipe& pipe,
+                        const Timing& T);
 // Adjoint of the per-source moments (pathwise derivative, decisions frozen).  Per-lane
 // accumulators: the ten rigid-body parameters, then the fifteen monomial coefficients of the
 // primary's deformation (mapped to Zernike amplitudes by the final reduction).
@@ -159,7 +169,7 @@ struct Adjoint {
 
 hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
                           const LaunchConfig& cfg, const Adjoint& A, double* colsum, double* grad,
-                          hipStream_t stream, const Timing& T);
+                          hipStream_t stream, const Pipe& pipe, const Timing& T);
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, hipStream_t stream);
 

@@ -1674,7 +1674,7 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
 // time bucket) and its count.
 static void launch_preroll(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
                            const LaunchConfig& cfg, const ChunkSpan& sp, uint64_t c,
-                           hipStream_t stream) {
+                           uint32_t* surv, hipStream_t stream) {
     const bool sort = sp.sort && W.key && W.hist;
     const uint64_t want = (sp.len + kGenRange - 1) / kGenRange;
     const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
@@ -1688,131 +1688,169 @@ static void launch_preroll(const DevParams* dparams, const Launch& L, const Work
                            (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words, W.hist);
         hipLaunchKernelGGL(bucket_scatter, dim3(nb), dim3(kBlock), 0, stream,
                            (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words,
-                           (const unsigned int*)W.hist, W.survivors, W.counts + c);
+                           (const unsigned int*)W.hist, surv, W.counts + c);
         return;
     }
     hipLaunchKernelGGL(compact_count, dim3(nb), dim3(kBlock), 0, stream,
                        (const unsigned long long*)W.bits, n_words, W.bsum);
     hipLaunchKernelGGL(compact_scatter, dim3(nb), dim3(kBlock), 0, stream,
                        (const unsigned long long*)W.bits, n_words, (const unsigned int*)W.bsum,
-                       W.survivors, W.counts + c);
+                       surv, W.counts + c);
 }
 
+// Chunks are pipelined over two streams when the pipe gives a second one: the pre-roll and sky
+// stage of chunk c run on `stream` while the optics stage of chunk c - 1 runs on pipe.aux, so the
+// bandwidth-bound sky stage and the arithmetic-bound optics stage share the compute units.
+// Survivor lists and states alternate between two buffers; events order the hand-offs (sky ->
+// optics, and buffer reuse), and the caller's stream waits for the last optics stage before
+// returning work to it.
+namespace {
+struct Stages {
+    const DevParams* dparams;
+    const Launch& L;
+    const Workspace& W;
+    int n_cu;
+    const LaunchConfig& cfg;
+    hipStream_t stream;
+    const Pipe& pipe;
+    const Timing& T;
+    bool piped() const { return pipe.aux && pipe.ev; }
+    hipEvent_t ev(int kind, uint64_t c) const { return pipe.ev[2 * c + kind]; }  // 0 sky, 1 optics
+    void mark(int kind, int edge, hipStream_t s) const {
+        if (T.on) T.record(T.self, kind, edge, s);
+    }
+    bool preroll() const { return (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS); }
+    uint32_t* surv_buf(uint64_t c) const { return W.survivors + (piped() ? c % 2 : 0) * W.chunk; }
+    double* state_buf(uint64_t c) const { return W.state + (piped() ? c % 2 : 0) * 7 * W.chunk; }
+
+    // pre-roll and sky stage of chunk c on `stream`
+    void front(uint64_t c, unsigned long long* ft) const {
+        const ChunkSpan& sp = W.plan[c];
+        if (piped() && c >= 2) (void)hipStreamWaitEvent(stream, ev(1, c - 2), 0);
+        const uint32_t* surv = nullptr;
+        const unsigned int* cnt = nullptr;
+        if (preroll()) {
+            mark(0, 0, stream);
+            launch_preroll(dparams, L, W, n_cu, cfg, sp, c, surv_buf(c), stream);
+            mark(0, 1, stream);
+            surv = surv_buf(c);
+            cnt = W.counts + c;
+        }
+        const uint64_t want = (sp.len + kBlock - 1) / kBlock;
+        const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
+        const dim3 fg((unsigned)(want < fcap ? want : fcap));
+        mark(1, 0, stream);
+        if (L.any_sersic)
+            hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L,
+                               sp.begin, surv, cnt, sp.len, state_buf(c), W.chunk, ft);
+        else
+            hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L,
+                               sp.begin, surv, cnt, sp.len, state_buf(c), W.chunk, ft);
+        mark(1, 1, stream);
+        if (piped()) (void)hipEventRecord(ev(0, c), stream);
+    }
+    // the optics stage's stream after waiting for the sky stage of chunk c
+    hipStream_t optics_begin(uint64_t c) const {
+        if (!piped()) return stream;
+        (void)hipStreamWaitEvent(pipe.aux, ev(0, c), 0);
+        return pipe.aux;
+    }
+    void optics_end(uint64_t c) const {
+        if (piped()) (void)hipEventRecord(ev(1, c), pipe.aux);
+    }
+    void fork(uint64_t n_chunks) const {
+        if (!piped()) return;
+        (void)hipEventRecord(pipe.ev[2 * n_chunks], stream);
+        (void)hipStreamWaitEvent(pipe.aux, pipe.ev[2 * n_chunks], 0);
+    }
+    void join(uint64_t n_chunks) const {
+        if (piped() && n_chunks) (void)hipStreamWaitEvent(stream, ev(1, n_chunks - 1), 0);
+    }
+    bool valid() const {
+        if (!W.state || !W.survivors || !W.counts || !W.bits || !W.bsum) return false;
+        if ((W.n_plan && !W.plan) || W.n_plan > W.n_chunks) return false;
+        if (piped() && (W.buffers < 2 || pipe.n_ev < 2 * W.n_plan + 1)) return false;
+        for (uint64_t c = 0; c < W.n_plan; ++c)
+            if (W.plan[c].len > W.chunk) return false;
+        return true;
+    }
+};
+}  // namespace
+
 hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                        const LaunchConfig& cfg, hipStream_t stream, const Timing& T) {
-    auto mark = [&](int kind, int edge) {
-        if (T.on) T.record(T.self, kind, edge, stream);
-    };
+                        const LaunchConfig& cfg, hipStream_t stream, const Pipe& pipe,
+                        const Timing& T) {
     if (L.total == 0) return hipSuccess;
-    const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
-    if (!W.state || !W.survivors || !W.counts || !W.bits || !W.bsum) return hipErrorInvalidValue;
-    const uint64_t chunk = W.chunk;
+    const Stages S{dparams, L, W, n_cu, cfg, stream, pipe, T};
+    if (!S.valid()) return hipErrorInvalidValue;
     const uint64_t n_chunks = W.n_plan;
-    if (!W.plan || n_chunks > W.n_chunks) return hipErrorInvalidValue;
     if (cfg.dynamic)
         hipLaunchKernelGGL(fill_u32, dim3((unsigned)((4 * n_chunks + 255) / 256)), dim3(256), 0,
                            stream, (unsigned int*)W.tiles, 4 * n_chunks, 0u);
+    S.fork(n_chunks);
     for (uint64_t c = 0; c < n_chunks; ++c) {
-        const uint64_t begin = W.plan[c].begin;
-        const uint64_t len = W.plan[c].len;
-        if (len > chunk) return hipErrorInvalidValue;
-        const uint32_t* surv = nullptr;
-        const unsigned int* cnt = nullptr;
-        if (preroll) {
-            mark(0, 0);
-            launch_preroll(dparams, L, W, n_cu, cfg, W.plan[c], c, stream);
-            mark(0, 1);
-            surv = W.survivors;
-            cnt = W.counts + c;
-        }
-        const uint64_t want = (len + kBlock - 1) / kBlock;
-        const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
+        S.front(c, cfg.dynamic ? W.tiles + 2 * c : nullptr);
+        const ChunkSpan& sp = W.plan[c];
+        const uint32_t* surv = S.preroll() ? S.surv_buf(c) : nullptr;
+        const unsigned int* cnt = S.preroll() ? W.counts + c : nullptr;
+        const uint64_t want = (sp.len + kBlock - 1) / kBlock;
         const uint64_t bcap = (uint64_t)n_cu * cfg.back_per_cu;
-        unsigned long long* ft = cfg.dynamic ? W.tiles + 2 * c : nullptr;
+        const dim3 bg((unsigned)(want < bcap ? want : bcap));
         unsigned long long* bt = cfg.dynamic ? W.tiles + 2 * c + 1 : nullptr;
-        const dim3 fg((unsigned)(want < fcap ? want : fcap)), bg((unsigned)(want < bcap ? want : bcap));
-        mark(1, 0);
-        if (L.any_sersic)
-            hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, W.state, chunk, ft);
-        else
-            hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, W.state, chunk, ft);
-        mark(1, 1);
-        mark(2, 0);
+        const hipStream_t bs = S.optics_begin(c);
+        S.mark(2, 0, bs);
         if (L.any_zernike)
-            hipLaunchKernelGGL(back_kernel<true>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, (const double*)W.state, chunk, bt);
+            hipLaunchKernelGGL(back_kernel<true>, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin,
+                               surv, cnt, sp.len, (const double*)S.state_buf(c), W.chunk, bt);
         else
-            hipLaunchKernelGGL(back_kernel<false>, bg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, (const double*)W.state, chunk, bt);
-        mark(2, 1);
+            hipLaunchKernelGGL(back_kernel<false>, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin,
+                               surv, cnt, sp.len, (const double*)S.state_buf(c), W.chunk, bt);
+        S.mark(2, 1, bs);
+        S.optics_end(c);
     }
+    S.join(n_chunks);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
                           const LaunchConfig& cfg, const Adjoint& A, double* colsum, double* grad,
-                          hipStream_t stream, const Timing& T) {
-    auto mark = [&](int kind, int edge) {
-        if (T.on) T.record(T.self, kind, edge, stream);
-    };
-    if (!W.state || !W.survivors || !W.counts || !W.bits || !W.bsum) return hipErrorInvalidValue;
+                          hipStream_t stream, const Pipe& pipe, const Timing& T) {
+    const Stages S{dparams, L, W, n_cu, cfg, stream, pipe, T};
+    if (!S.valid()) return hipErrorInvalidValue;
     const uint64_t grid = (uint64_t)n_cu * A.per_cu;
     if (grid * kBlock > A.tape_stride) return hipErrorInvalidValue;
-    const bool preroll = (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS);
-    const uint64_t chunk = W.chunk;
     const uint64_t n_chunks = W.n_plan;
-    if ((n_chunks && !W.plan) || n_chunks > W.n_chunks) return hipErrorInvalidValue;
     const bool jac = A.jac != nullptr;
+    S.fork(n_chunks);
     for (uint64_t c = 0; c < n_chunks; ++c) {
-        const uint64_t begin = W.plan[c].begin;
-        const uint64_t len = W.plan[c].len;
-        if (len > chunk) return hipErrorInvalidValue;
-        const uint32_t* surv = nullptr;
-        const unsigned int* cnt = nullptr;
-        const uint64_t want = (len + kBlock - 1) / kBlock;
-        if (preroll) {
-            mark(0, 0);
-            launch_preroll(dparams, L, W, n_cu, cfg, W.plan[c], c, stream);
-            mark(0, 1);
-            surv = W.survivors;
-            cnt = W.counts + c;
-        }
-        const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
-        const dim3 fg((unsigned)(want < fcap ? want : fcap));
-        mark(1, 0);
-        if (L.any_sersic)
-            hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, W.state, chunk, (unsigned long long*)nullptr);
-        else
-            hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L, begin,
-                               surv, cnt, len, W.state, chunk, (unsigned long long*)nullptr);
-        mark(1, 1);
-        mark(2, 0);
+        S.front(c, nullptr);
+        const ChunkSpan& sp = W.plan[c];
+        const uint32_t* surv = S.preroll() ? S.surv_buf(c) : nullptr;
+        const unsigned int* cnt = S.preroll() ? W.counts + c : nullptr;
+        const hipStream_t bs = S.optics_begin(c);
         const uint64_t row0 = c * grid;
         const dim3 ag((unsigned)grid);
+        const double* cst = S.state_buf(c);
+        S.mark(2, 0, bs);
         if (L.any_zernike) {
             if (jac)
-                hipLaunchKernelGGL((adjoint_kernel<true, true>), ag, dim3(kBlock), 0, stream,
-                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
-                                   chunk, A, row0);
+                hipLaunchKernelGGL((adjoint_kernel<true, true>), ag, dim3(kBlock), 0, bs, dparams,
+                                   L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
             else
-                hipLaunchKernelGGL((adjoint_kernel<true, false>), ag, dim3(kBlock), 0, stream,
-                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
-                                   chunk, A, row0);
+                hipLaunchKernelGGL((adjoint_kernel<true, false>), ag, dim3(kBlock), 0, bs, dparams,
+                                   L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
         } else {
             if (jac)
-                hipLaunchKernelGGL((adjoint_kernel<false, true>), ag, dim3(kBlock), 0, stream,
-                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
-                                   chunk, A, row0);
+                hipLaunchKernelGGL((adjoint_kernel<false, true>), ag, dim3(kBlock), 0, bs, dparams,
+                                   L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
             else
-                hipLaunchKernelGGL((adjoint_kernel<false, false>), ag, dim3(kBlock), 0, stream,
-                                   dparams, L, begin, surv, cnt, len, (const double*)W.state,
-                                   chunk, A, row0);
+                hipLaunchKernelGGL((adjoint_kernel<false, false>), ag, dim3(kBlock), 0, bs,
+                                   dparams, L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
         }
-        mark(2, 1);
+        S.mark(2, 1, bs);
+        S.optics_end(c);
     }
+    S.join(n_chunks);
     const uint64_t rows = n_chunks * grid;
     hipLaunchKernelGGL(adjoint_columns, dim3(kAdj), dim3(256), 0, stream, A.partial, rows, colsum);
     hipLaunchKernelGGL(adjoint_finish, dim3(1), dim3(64), 0, stream, dparams,

@@ -77,7 +77,7 @@ class TraceArgs(C.Structure):
 class LaunchConfig(C.Structure):
     _fields_ = [("chunk_log2", C.c_int32), ("generate_blocks_per_cu", C.c_int32),
                 ("front_blocks_per_cu", C.c_int32), ("back_blocks_per_cu", C.c_int32),
-                ("dynamic_tiles", C.c_int32)]
+                ("dynamic_tiles", C.c_int32), ("pipeline", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -136,14 +136,17 @@ def test_vjp_equals_sum_of_jacobians(phx):
 
 
 def test_adjoint_is_deterministic(phx):
+    """Repeats give the same bits, with the chunk pipeline on two streams or on one."""
     import torch
     s = C.gradients(scale=2e-4, screen_n=128)
     tr = phx.Tracer(s)
     seeds = torch.ones((len(s.sources), 8), dtype=torch.float64)
     a = tr.adjoint(seeds, photon_count=3000).clone()
-    b = tr.adjoint(seeds, photon_count=3000)
+    b = tr.adjoint(seeds, photon_count=3000).clone()
+    tr.set_launch_config(pipeline=0)
+    c = tr.adjoint(seeds, photon_count=3000).clone()
     torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    assert torch.equal(a, b) and torch.equal(a, c)
     tr.close()
 
 

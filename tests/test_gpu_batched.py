@@ -70,6 +70,8 @@ def test_graph_replays_match_eager(phx, scene):
     dict(chunk_log2=16, dynamic_tiles=1),
     dict(chunk_log2=17, generate_blocks_per_cu=1, front_blocks_per_cu=3, back_blocks_per_cu=1),
     dict(generate_blocks_per_cu=64, front_blocks_per_cu=64, back_blocks_per_cu=16),
+    dict(pipeline=0),
+    dict(pipeline=0, chunk_log2=16, dynamic_tiles=1),
 ])
 def test_launch_shapes_bin_the_same_photons(phx, scene, cfg):
     import torch
@@ -89,7 +91,7 @@ def test_launch_shapes_bin_the_same_photons(phx, scene, cfg):
 def test_launch_config_validation(phx, scene):
     tr = phx.Tracer(C.tiny())
     for bad in (dict(chunk_log2=15), dict(chunk_log2=28), dict(back_blocks_per_cu=0),
-                dict(front_blocks_per_cu=65), dict(dynamic_tiles=2)):
+                dict(front_blocks_per_cu=65), dict(dynamic_tiles=2), dict(pipeline=2)):
         with pytest.raises(phx.PhxError):
             tr.set_launch_config(**bad)
     tr.close()
