@@ -296,6 +296,26 @@ def main():
     achieved = d["work"] / (d["ms"] * 1e-3) * d["scale"]
     stage_ms = {k: kt[k] / args.steps for k in ("generate", "front", "back")}
     extra = {}
+    # The timed steps overlap each chunk's optics stage with the next chunk's sky stage, so the
+    # per-launch durations above include time shared with the other kernel.  One more step with
+    # the stages on a single stream gives each kernel's duration alone.
+    tr.set_launch_config(pipeline=0)
+    iso_stats = tr.new_stats()
+    tr.set_timing(True)
+    tr.trace(tr.new_image(), flags=flags, stats=iso_stats)
+    torch.cuda.synchronize()
+    kti = tr.get_timing()
+    tr.set_timing(False)
+    tr.set_launch_config(pipeline=1)
+    ci = max(kti["chunks"], 1.0)
+    iso = {}
+    for k, v in kinds.items():
+        ms_k = kti[k] / ci
+        a_k = v["work"] / (ms_k * 1e-3) * v["scale"]
+        iso[f"{k}_kernel"] = {"bound": v["bound"], "achieved": a_k, "peak": v["peak"],
+                              "unit": v["unit"], "frac": a_k / v["peak"], "launch_ms": ms_k}
+    extra["roofline_single_stream"] = iso
+    extra["stage_ms_single_stream"] = {k: kti[k] for k in ("generate", "front", "back")}
     if not args.no_cull and not args.no_compare:
         # the same step without the pre-roll (every photon traced until its fate)
         nc_img = tr.new_image()

@@ -571,3 +571,36 @@ def test_gradient_richardson_is_step_independent():
     assert both.sum() > 20
     scale = np.abs(a[both]).max(axis=(0, 1), keepdims=True)
     assert np.all(np.abs(a[both] - b[both]) <= 5e-6 * scale)
+
+
+def test_detected_fraction_matches_effective_area_integral():
+    """Photometry: with vertical light on a flat coated detector, the detected (converted)
+    fraction is the band average of T(0, lambda) (1 - exp(-alpha(lambda) t_Si)), the coating
+    transmission at normal incidence times the absorption probability in the silicon (the
+    effective-area integral over a flat photon spectrum), computed here by quadrature."""
+    from tests import helpers as H
+    from paper_1504_06570_amd.scene import coatings as CT
+    from paper_1504_06570_amd.scene.sources import point_sources
+    n = 200000
+    tables = CT.standard_tables()
+    s = H.flat_detector_scene(n_photons=n, physics=C.PHYS_COATINGS | C.PHYS_SILICON,
+                              coatings=tables, det_coating=CT.FILTER)
+    lo, hi = 480e-9, 1060e-9
+    s.sources = point_sources([0.0], [0.0], n, lo, hi)
+    orc = O.Oracle(s)
+    ev = orc.trace_sources(threads=8)
+    p_hat = np.mean(ev["status"] <= O.OFF_CHIP)
+    lam = np.linspace(lo, hi, 20001)
+    grid = CT.LAM0 + CT.DLAM * np.arange(CT.N_LAM)
+    T = np.interp(lam, grid, tables[CT.FILTER, 0, :].astype(np.float64))
+    t_si = s.prescription.silicon.thickness
+    temp = s.prescription.silicon.temperature
+    alpha = np.array([orc_alpha(l, temp) for l in lam]) * 100.0   # cm^-1 -> m^-1
+    f = T * (1.0 - np.exp(-alpha * t_si))
+    P = np.sum(0.5 * (f[1:] + f[:-1])) / (len(lam) - 1)
+    sigma = np.sqrt(P * (1 - P) / n)
+    assert abs(p_hat - P) < 4 * sigma, (p_hat, P, sigma)
+
+
+def orc_alpha(lam, temp):
+    return O.lib().orc_rajkanan(lam, temp)
