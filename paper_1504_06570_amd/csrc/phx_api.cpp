@@ -74,6 +74,8 @@ struct phx_ctx_s {
     uint8_t* d_key = nullptr;
     unsigned int* d_hist = nullptr;
     std::vector<phx::ChunkSpan> plan;
+    double sed_lo = 0.0;                    // lowest SED bin edge (m)
+    std::vector<double> grad_max;           // [layer][scale] largest gradient norm of a screen
     void graphs_clear() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
@@ -490,8 +492,25 @@ phx_status phx_load_screens(phx_ctx c, const phx_atmosphere* a, const float* opd
                                          hipGetErrorString(e));
         c->grad_elems = (size_t)want;
     }
-    hipError_t e = phx::launch_gradients(opd, c->d_grad, a->n_layers, a->n_scales, N, a->pixel, st);
+    const int planes = a->n_layers * a->n_scales;
+    unsigned int* d_gmax = nullptr;
+    hipError_t e = hipMalloc((void**)&d_gmax, planes * sizeof(unsigned int));
+    if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "screen maxima");
+    e = hipMemsetAsync(d_gmax, 0, planes * sizeof(unsigned int), st);
+    if (e == hipSuccess)
+        e = phx::launch_gradients(opd, c->d_grad, a->n_layers, a->n_scales, N, a->pixel, d_gmax, st);
+    std::vector<unsigned int> gm(planes, 0u);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = hipMemcpy(gm.data(), d_gmax, planes * sizeof(unsigned int), hipMemcpyDeviceToHost);
+    free_dev(d_gmax);
     if (e != hipSuccess) return hip_fail(c, e, "gradient kernel");
+    c->grad_max.assign(planes, 0.0);
+    for (int i = 0; i < planes; ++i) {
+        float f;
+        std::memcpy(&f, &gm[i], sizeof(f));
+        c->grad_max[i] = std::isfinite(f) ? (double)f : INFINITY;
+    }
     DevParams& H = c->host;
     H.n_layers = a->n_layers;
     H.n_scales = a->n_scales;
@@ -555,6 +574,7 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
         for (int k = 0; k < sed_k; ++k)
             if (!(edges[k + 1] > edges[k]) || !(edges[k] > 0))
                 return fail(c, PHX_ERR_INVALID, "SED edges must be positive and increasing");
+        c->sed_lo = edges[0];
         cdf.assign((size_t)n_sed * (sed_k + 1), 0.0);
         for (int s = 0; s < n_sed; ++s) {
             double* C = cdf.data() + (size_t)s * (sed_k + 1);
@@ -605,6 +625,50 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
 
 namespace {
 
+// Radii of the pupil annulus outside which a photon cannot reach the primary's clear aperture:
+// the aperture widened by a bound on the atmospheric displacement at the primary.  Each layer i
+// turns the ray by at most kick_max x (sum over scales of the screen's largest gradient norm; a
+// bilinear value never exceeds its corners), and the turn displaces the landing point by at most
+// that angle x (h_i + |z| of the primary) / min |n_z|; the sum over layers is taken with a factor
+// 1.1 for the second-order terms (renormalisation, the sag slope at the displaced point, each
+// below 1 %).
+void set_cull_radii(phx_ctx c, const phx_trace_args* a, phx::Launch& L) {
+    L.cull_r_lo = -INFINITY;
+    L.cull_r_hi = INFINITY;
+    const phx::DevSurface& s0 = c->host.surf[0];
+    if (s0.moved || c->presc.n_surfaces < 2) return;
+    double D = 1e-6;
+    if (a->flags & PHX_F_ATMOSPHERE) {
+        if (!c->have_screens || c->grad_max.empty()) return;
+        double lam_min = INFINITY, nz_min = 1.0;
+        for (int s = a->src_begin; s < a->src_end; ++s) {
+            const phx_source& q = c->src[s];
+            const double lo = (q.sed >= 0 ? c->sed_lo : q.lambda_lo) * (1.0 + q.redshift);
+            lam_min = std::min(lam_min, lo);
+            nz_min = std::min(nz_min, std::sqrt(std::max(0.0, 1.0 - q.xi * q.xi - q.eta * q.eta)));
+        }
+        if (!(lam_min > 0.0) || !(nz_min > 0.5)) return;
+        const double kick = std::pow(lam_min / c->host.lambda_ref, -0.2);
+        // |z| of the primary over the sampled annulus
+        const double R = s0.r_out + a->pupil_margin;
+        const double arg = std::max(0.0, 1.0 - s0.kappa1 * s0.c * s0.c * R * R);
+        double zmax = std::fabs(s0.t[2]) + std::fabs(s0.c) * R * R / (1.0 + std::sqrt(arg));
+        for (int i = 0; i < 8; ++i) zmax += std::fabs(s0.alpha[i]) * std::pow(R, i + 3);
+        for (int j = 0; j < phx::kNZern; ++j) zmax += 8.0 * std::fabs(c->theta[10 + j]);
+        double sum = 0.0;
+        const int S = c->host.n_scales;
+        for (int i = 0; i < c->host.n_layers; ++i) {
+            double g = 0.0;
+            for (int k = 0; k < S; ++k) g += c->grad_max[(size_t)i * S + k];
+            sum += kick * g * (std::fabs(c->host.height[i]) + zmax) / nz_min;
+        }
+        if (!std::isfinite(sum)) return;
+        D += 1.1 * sum;
+    }
+    L.cull_r_lo = s0.r_in - D;
+    L.cull_r_hi = s0.r_out + D;
+}
+
 // Validation, uploads and workspace for a trace; fills the launch description.  May synchronise
 // `st` (new prefix table, growing workspace, changed parameter block).
 phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Launch& L,
@@ -652,6 +716,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     L.any_sersic = 0;
     for (int s = a->src_begin; s < a->src_end; ++s) L.any_sersic |= c->src[s].kind == 1;
     L.any_zernike = c->host.surf[0].zernike;
+    set_cull_radii(c, a, L);
     if (a->photon_count > 0) {
         L.uniform_count = a->photon_count;
         if (a->photon_count > UINT64_MAX / (uint64_t)L.n_src)

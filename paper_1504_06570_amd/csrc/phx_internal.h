@@ -88,6 +88,9 @@ struct Launch {
     uint64_t event_stride;
     int32_t any_sersic;            // an extended source is in the range
     int32_t any_zernike;           // the first surface carries a Zernike deformation
+    // pre-roll geometric cull: a pupil sample at radius r < cull_r_lo or r > cull_r_hi cannot
+    // reach the primary's clear aperture (its atmospheric displacement is bounded)
+    double cull_r_lo, cull_r_hi;
 };
 
 // Scratch of the staged trace: the launch's photon range is processed in chunks; per chunk the
@@ -171,6 +174,6 @@ hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Works
                           const LaunchConfig& cfg, const Adjoint& A, double* colsum, double* grad,
                           hipStream_t stream, const Pipe& pipe, const Timing& T);
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
-                            const double* pixel, hipStream_t stream);
+                            const double* pixel, unsigned int* gmax, hipStream_t stream);
 
 }  // namespace phx

@@ -326,9 +326,10 @@ __device__ __forceinline__ double wavelength(const DevParams& P, const DevSource
 // of that order.  preroll_draw gives the wavelength (and the time word) from the photon's first
 // Philox blocks.
 __device__ __forceinline__ double preroll_draw(const DevParams& P, const Rng& rng, int si,
-                                               uint32_t& w_time) {
+                                               uint32_t& w_time, uint32_t& w_radius) {
     const uint4 w0 = rng.block(0);
     w_time = w0.z;
+    w_radius = w0.x;
     const DevSource& src = P.src[si];
     uint4 w1 = make_uint4(0, 0, 0, 0);
     if (src.sed >= 0) w1 = rng.block(1);
@@ -807,9 +808,12 @@ __device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, 
 }
 
 // Pre-roll (section 3.2, dynamic transmission optimisation).  Each workgroup takes contiguous
-// ranges of kGenRange photons.  Stage one draws every photon's wavelength and applies the most
-// selective coating test; its survivors are queued in LDS and stage two applies the remaining
-// tests to them densely, so the many photons that fail the first test cost one test.  The
+// ranges of kGenRange photons.  Stage one draws every photon's wavelength and pupil radius, drops
+// photons whose pupil sample cannot reach the primary's aperture (the annulus is sampled wider
+// than the aperture to leave room for atmospheric displacement, which the host bounds) and
+// applies the most selective coating test; its survivors are queued in LDS and stage two applies
+// the remaining tests to them densely, so the many photons that fail the first test cost one
+// test.  The
 // survivors' bits are set in an LDS copy of the range's bitmap words, written out once (the
 // bitmap does not depend on the order of the queue), with each survivor's time bucket when
 // requested.  An ordered compaction then lists the survivors.
@@ -857,9 +861,15 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 uint64_t idx;
                 decode(L, g, si, idx);
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
-                uint32_t wt;
-                const double lam = preroll_draw(P, rng, si, wt);
-                culled = preroll_tests(P, rng, lam, 0, min(n_tests, 1));
+                uint32_t wt, wr;
+                const double lam = preroll_draw(P, rng, si, wt, wr);
+                // pupil radius as the sky stage samples it: outside the reachable annulus the
+                // photon is vignetted at the primary whatever the atmosphere does
+                const double ro = P.pupil_r_out + L.pupil_margin;
+                const double ri = fmax(P.pupil_r_in - L.pupil_margin, 0.0);
+                const double rp = sqrt(u01(wr) * (ro * ro - ri * ri) + ri * ri);
+                culled = rp < L.cull_r_lo || rp > L.cull_r_hi ||
+                         preroll_tests(P, rng, lam, 0, min(n_tests, 1));
                 pass = !culled;
                 if (culled) culled_event(L, g, si, idx, lam);
             }
@@ -886,8 +896,8 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 uint64_t idx;
                 decode(L, g, si, idx);
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
-                uint32_t wt;
-                const double lam = preroll_draw(P, rng, si, wt);
+                uint32_t wt, wr;
+                const double lam = preroll_draw(P, rng, si, wt, wr);
                 culled = preroll_tests(P, rng, lam, 1, n_tests);
                 keep = !culled;
                 if (keep) {
@@ -1150,7 +1160,7 @@ __global__ __launch_bounds__(kBlock) void front_kernel(const DevParams* __restri
 // pixels outside the window take wavefront-aggregated global atomics.
 constexpr int kWin = 64;
 template <bool ZERN>
-__global__ __launch_bounds__(kBlock) void back_kernel(const DevParams* __restrict__ Pg,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void back_kernel(const DevParams* __restrict__ Pg,
                                                       const Launch L, uint64_t begin,
                                                       const uint32_t* __restrict__ surv,
                                                       const unsigned int* __restrict__ count,
@@ -1651,10 +1661,15 @@ __device__ __forceinline__ float2 grad_at(const float* w, int n, int i, int j, f
     return make_float2(dx * f, dy * f);
 }
 
+// Also records, per screen, the largest gradient norm of any cell (as float bits: the order of
+// non-negative floats is that of their bits), from which the host bounds how far the atmosphere
+// can displace a photon at the primary.
 __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restrict__ grad, int n,
-                                int n_scales, const float* inv2p, int64_t total) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= total) return;
+                                int n_scales, const float* inv2p, int64_t total,
+                                unsigned int* __restrict__ gmax) {
+    const int64_t id0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = id0 < total;
+    const int64_t id = live ? id0 : total - 1;
     const int64_t nn = (int64_t)n * n;
     const int64_t plane = id / nn;
     const int64_t r = id - plane * nn;
@@ -1664,8 +1679,20 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
     const int i1 = i + 1 == n ? 0 : i + 1, j1 = j + 1 == n ? 0 : j + 1;
     const float2 g00 = grad_at(w, n, i, j, f), g10 = grad_at(w, n, i1, j, f);
     const float2 g01 = grad_at(w, n, i, j1, f), g11 = grad_at(w, n, i1, j1, f);
-    grad[2 * id] = make_float4(g00.x, g00.y, g10.x, g10.y);
-    grad[2 * id + 1] = make_float4(g01.x, g01.y, g11.x, g11.y);
+    if (live) {
+        grad[2 * id] = make_float4(g00.x, g00.y, g10.x, g10.y);
+        grad[2 * id + 1] = make_float4(g01.x, g01.y, g11.x, g11.y);
+    }
+    if (!gmax) return;
+    float m = live ? sqrtf(g00.x * g00.x + g00.y * g00.y) : 0.0f;
+    const int p0 = __shfl((int)plane, 0);
+    if (__ballot((int)plane != p0) == 0) {   // the whole wavefront is on one screen
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if (__lane_id() == 0) atomicMax(&gmax[plane], __float_as_uint(m));
+    } else if (live) {
+        atomicMax(&gmax[plane], __float_as_uint(m));
+    }
 }
 
 }  // namespace
@@ -1859,7 +1886,7 @@ hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Works
 }
 
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
-                            const double* pixel, hipStream_t stream) {
+                            const double* pixel, unsigned int* gmax, hipStream_t stream) {
     // inverse 2p per scale, rounded to float once (the same value for every texel)
     float h_inv2p[PHX_MAX_SCALES];
     for (int s = 0; s < n_scales; ++s) h_inv2p[s] = (float)(1.0 / (2.0 * pixel[s]));
@@ -1872,7 +1899,7 @@ hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_
     const int block = 256;
     const int64_t grid = (total + block - 1) / block;
     hipLaunchKernelGGL(gradient_kernel, dim3((unsigned)grid), dim3(block), 0, stream, opd, grad, n,
-                       n_scales, d_inv2p, total);
+                       n_scales, d_inv2p, total, gmax);
     e = hipGetLastError();
     (void)hipFreeAsync(d_inv2p, stream);
     return e;

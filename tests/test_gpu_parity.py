@@ -176,3 +176,25 @@ def test_moments_equal_sums_over_events(phx):
         sel = conv & (e["source"] == si)
         assert got[si] == phx.quantised_sums(e["xe"][sel], e["ye"][sel]), si
     tr.close()
+
+
+def test_geometric_preroll_culls_only_primary_vignetting(phx):
+    """With the atmosphere the pupil annulus is sampled wider than the primary; the pre-roll drops
+    samples farther out than the bounded atmospheric displacement.  With coatings that never cull,
+    every photon it drops is vignetted at the primary in the full trace, and every other photon
+    keeps its record."""
+    import torch
+    s = C.full(scale=2e-4, screen_n=128)
+    s.coatings = np.ones_like(s.coatings)
+    tr = phx.Tracer(s)
+    _, _, _, ea = tr.trace(event_stride=1)
+    _, _, _, eb = tr.trace(event_stride=1, flags=int(s.physics) | phx.F_CULL)
+    torch.cuda.synchronize()
+    a, b = phx.events_to_numpy(ea), phx.events_to_numpy(eb)
+    culled = b["status"] == phx.CULLED
+    assert culled.mean() > 0.03
+    assert np.all(a["status"][culled] == phx.VIGNETTED) and np.all(a["surface"][culled] == 0)
+    keep = ~culled
+    for f in ("status", "surface", "pix_i", "pix_j", "x", "y", "xe", "ye"):
+        assert np.array_equal(a[f][keep], b[f][keep]), f
+    tr.close()
