@@ -96,7 +96,9 @@ def batched_leg(steps, per_source_steps=1):
     counts = scene.sources.n_photons.astype(np.int64)
     total = int(counts.sum())
     t0 = time.perf_counter()
+    tr.set_launch_config(pipeline=0)   # tune the graph-replayed launch
     best = tr.autotune(flags=flags)
+    tr.set_launch_config(pipeline=1)   # per-source launches below run eagerly
     t_tune = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -258,6 +260,10 @@ def main():
     n_coated = sum(1 for s in scene.prescription.surfaces if s.coating >= 0)
     img = tr.new_image()
     stats = tr.new_stats()
+    t_tune = time.perf_counter()
+    tuned = tr.autotune(flags=flags)   # eager launches pipelined over two streams
+    t_tune = time.perf_counter() - t_tune
+    print(f"# autotuned {tuned} in {t_tune:.1f}s", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         tr.trace(img, flags=flags, stats=stats)
     torch.cuda.synchronize()
@@ -368,6 +374,8 @@ def main():
                         "diffusion, 4096^2 chip",
             "photons_per_step": n_ph,
             "preroll_cull": not args.no_cull,
+            "launch_config": tuned,
+            "autotune_s": t_tune,
             "detected_per_step": detected,
             "traced_per_step": traced / args.steps,
             "newton_per_traced": float(st[phx.STAT_NEWTON]) / max(traced, 1.0),

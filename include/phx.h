@@ -269,11 +269,12 @@ phx_status phx_get_launch_config(phx_ctx ctx, phx_launch_config* cfg_host);
  * and captures on a context-owned stream; later calls only launch the graph.  Errors as phx_trace. */
 phx_status phx_trace_batched(phx_ctx ctx, const phx_trace_args* args, void* stream);
 
-/* Autotuner: times phx_trace_batched on `sample` for candidate launch shapes (coordinate descent
- * over back, front and pre-roll workgroups per CU, the schedule and the chunk size), writing into
- * context-owned scratch outputs (the sample's output pointers are ignored), sets the fastest
- * shape on the context and returns it in *best_host (may be NULL).  Synchronises `stream`.
- * Errors as phx_trace, plus PHX_ERR_NOMEM. */
+/* Autotuner: times `sample` for candidate launch shapes (coordinate descent over optics, sky and
+ * pre-roll workgroups per CU, the schedule and the chunk size; the pipeline setting is kept and
+ * selects what is timed: eager phx_trace launches when it is 1, phx_trace_batched graph replays
+ * when it is 0), writing into context-owned scratch outputs (the sample's output pointers are
+ * ignored), sets the fastest shape on the context and returns it in *best_host (may be NULL).
+ * Synchronises `stream`.  Errors as phx_trace, plus PHX_ERR_NOMEM. */
 phx_status phx_autotune(phx_ctx ctx, const phx_trace_args* sample, void* stream,
                         phx_launch_config* best_host);
 

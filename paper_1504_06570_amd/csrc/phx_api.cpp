@@ -836,7 +836,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
             hipError_t e = hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking);
             if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreate");
         }
-        while (c->pipe_ev.size() < 2 * c->plan.size() + 1) {
+        while (c->pipe_ev.size() < 3 * c->plan.size() + 1) {
             hipEvent_t ev = nullptr;
             hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
             if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
@@ -1067,15 +1067,19 @@ phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     phx_launch_config cur;
     phx_get_launch_config(c, &cur);
     phx_status status = PHX_OK;
+    // the path the shape is for: eager launches pipelined over two streams, or graph replays
+    auto launch = [&]() -> phx_status {
+        return c->cfg.pipeline ? phx_trace(c, &a, st) : phx_trace_batched(c, &a, st);
+    };
     auto measure = [&](const phx_launch_config& k, float& ms_out) -> phx_status {
         phx_status r = phx_set_launch_config(c, &k);
         if (r != PHX_OK) return r;
-        r = phx_trace_batched(c, &a, st);   // warm-up (prepares and captures)
+        r = launch();   // warm-up (prepares, and captures a graph)
         if (r != PHX_OK) return r;
         float best_ms = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, st);
-            r = phx_trace_batched(c, &a, st);
+            r = launch();
             if (r != PHX_OK) return r;
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) return fail(c, PHX_ERR_HIP, "sync");
@@ -1089,9 +1093,9 @@ phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     float cur_ms = 0.0f;
     status = measure(cur, cur_ms);
     // coordinate descent, one pass per knob
-    const int backs[] = {2, 3, 4, 6, 8};
-    const int fronts[] = {8, 16, 32, 48};
-    const int gens[] = {4, 8, 16};
+    const int backs[] = {2, 3, 4, 6, 8, 12};
+    const int fronts[] = {8, 16, 24, 32, 48, 64};
+    const int gens[] = {2, 4, 8, 16};
     const int chunks[] = {24, 25, 26};
     for (int knob = 0; knob < 5 && status == PHX_OK; ++knob) {
         std::vector<phx_launch_config> cand;

@@ -122,8 +122,8 @@ struct Workspace {
 
 // Second stream and events for pipelining chunks (aux null: everything on the caller's stream).
 struct Pipe {
-    hipStream_t aux = nullptr;   // optics stage
-    hipEvent_t* ev = nullptr;    // at least 2 n_chunks + 1 events
+    hipStream_t aux = nullptr;   // pre-roll and optics stages
+    hipEvent_t* ev = nullptr;    // at least 3 n_chunks + 1 events
     uint64_t n_ev = 0;
 };
 constexpr int kTimeBucketsMax = 64;

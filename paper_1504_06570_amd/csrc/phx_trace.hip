@@ -1725,12 +1725,14 @@ static void launch_preroll(const DevParams* dparams, const Launch& L, const Work
                        surv, W.counts + c);
 }
 
-// Chunks are pipelined over two streams when the pipe gives a second one: the pre-roll and sky
-// stage of chunk c run on `stream` while the optics stage of chunk c - 1 runs on pipe.aux, so the
-// bandwidth-bound sky stage and the arithmetic-bound optics stage share the compute units.
-// Survivor lists and states alternate between two buffers; events order the hand-offs (sky ->
-// optics, and buffer reuse), and the caller's stream waits for the last optics stage before
-// returning work to it.
+// Chunks are pipelined over two streams when the pipe gives a second one: the bandwidth-bound
+// sky stage runs on `stream` and the arithmetic-bound pre-roll and optics stage on pipe.aux, in
+// the order pre-roll(0), pre-roll(1), optics(0), pre-roll(2), optics(1), ..., so the two kinds
+// of work share the compute units.  Survivor lists and states alternate between two buffers;
+// events order the hand-offs (pre-roll -> sky -> optics, and state reuse), the host issues every
+// event record before the waits on it, and the caller's stream waits for the last optics stage
+// before returning work to it.  Without a second stream each chunk's stages run in order on
+// `stream`.
 namespace {
 struct Stages {
     const DevParams* dparams;
@@ -1742,26 +1744,34 @@ struct Stages {
     const Pipe& pipe;
     const Timing& T;
     bool piped() const { return pipe.aux && pipe.ev; }
-    hipEvent_t ev(int kind, uint64_t c) const { return pipe.ev[2 * c + kind]; }  // 0 sky, 1 optics
+    // events per chunk: 0 pre-roll done, 1 sky done, 2 optics done; then one fork event
+    hipEvent_t ev(int kind, uint64_t c) const { return pipe.ev[3 * c + kind]; }
     void mark(int kind, int edge, hipStream_t s) const {
         if (T.on) T.record(T.self, kind, edge, s);
     }
     bool preroll() const { return (L.flags & PHX_F_CULL) && (L.flags & PHX_F_COATINGS); }
+    hipStream_t arith() const { return piped() ? pipe.aux : stream; }
     uint32_t* surv_buf(uint64_t c) const { return W.survivors + (piped() ? c % 2 : 0) * W.chunk; }
     double* state_buf(uint64_t c) const { return W.state + (piped() ? c % 2 : 0) * 7 * W.chunk; }
+    const uint32_t* surv(uint64_t c) const { return preroll() ? surv_buf(c) : nullptr; }
+    const unsigned int* cnt(uint64_t c) const { return preroll() ? W.counts + c : nullptr; }
 
-    // pre-roll and sky stage of chunk c on `stream`
-    void front(uint64_t c, unsigned long long* ft) const {
-        const ChunkSpan& sp = W.plan[c];
-        if (piped() && c >= 2) (void)hipStreamWaitEvent(stream, ev(1, c - 2), 0);
-        const uint32_t* surv = nullptr;
-        const unsigned int* cnt = nullptr;
+    // pre-roll of chunk c (survivor list and count)
+    void pre(uint64_t c) const {
+        const hipStream_t s = arith();
         if (preroll()) {
-            mark(0, 0, stream);
-            launch_preroll(dparams, L, W, n_cu, cfg, sp, c, surv_buf(c), stream);
-            mark(0, 1, stream);
-            surv = surv_buf(c);
-            cnt = W.counts + c;
+            mark(0, 0, s);
+            launch_preroll(dparams, L, W, n_cu, cfg, W.plan[c], c, surv_buf(c), s);
+            mark(0, 1, s);
+        }
+        if (piped()) (void)hipEventRecord(ev(0, c), s);
+    }
+    // sky stage of chunk c on `stream`
+    void sky(uint64_t c, unsigned long long* ft) const {
+        const ChunkSpan& sp = W.plan[c];
+        if (piped()) {
+            (void)hipStreamWaitEvent(stream, ev(0, c), 0);
+            if (c >= 2) (void)hipStreamWaitEvent(stream, ev(2, c - 2), 0);
         }
         const uint64_t want = (sp.len + kBlock - 1) / kBlock;
         const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
@@ -1769,37 +1779,63 @@ struct Stages {
         mark(1, 0, stream);
         if (L.any_sersic)
             hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L,
-                               sp.begin, surv, cnt, sp.len, state_buf(c), W.chunk, ft);
+                               sp.begin, surv(c), cnt(c), sp.len, state_buf(c), W.chunk, ft);
         else
             hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L,
-                               sp.begin, surv, cnt, sp.len, state_buf(c), W.chunk, ft);
+                               sp.begin, surv(c), cnt(c), sp.len, state_buf(c), W.chunk, ft);
         mark(1, 1, stream);
-        if (piped()) (void)hipEventRecord(ev(0, c), stream);
+        if (piped()) (void)hipEventRecord(ev(1, c), stream);
     }
     // the optics stage's stream after waiting for the sky stage of chunk c
     hipStream_t optics_begin(uint64_t c) const {
-        if (!piped()) return stream;
-        (void)hipStreamWaitEvent(pipe.aux, ev(0, c), 0);
-        return pipe.aux;
+        if (piped()) (void)hipStreamWaitEvent(pipe.aux, ev(1, c), 0);
+        return arith();
     }
     void optics_end(uint64_t c) const {
-        if (piped()) (void)hipEventRecord(ev(1, c), pipe.aux);
+        if (piped()) (void)hipEventRecord(ev(2, c), pipe.aux);
     }
     void fork(uint64_t n_chunks) const {
         if (!piped()) return;
-        (void)hipEventRecord(pipe.ev[2 * n_chunks], stream);
-        (void)hipStreamWaitEvent(pipe.aux, pipe.ev[2 * n_chunks], 0);
+        (void)hipEventRecord(pipe.ev[3 * n_chunks], stream);
+        (void)hipStreamWaitEvent(pipe.aux, pipe.ev[3 * n_chunks], 0);
     }
     void join(uint64_t n_chunks) const {
-        if (piped() && n_chunks) (void)hipStreamWaitEvent(stream, ev(1, n_chunks - 1), 0);
+        if (piped() && n_chunks) (void)hipStreamWaitEvent(stream, ev(2, n_chunks - 1), 0);
     }
     bool valid() const {
         if (!W.state || !W.survivors || !W.counts || !W.bits || !W.bsum) return false;
         if ((W.n_plan && !W.plan) || W.n_plan > W.n_chunks) return false;
-        if (piped() && (W.buffers < 2 || pipe.n_ev < 2 * W.n_plan + 1)) return false;
+        if (piped() && (W.buffers < 2 || pipe.n_ev < 3 * W.n_plan + 1)) return false;
         for (uint64_t c = 0; c < W.n_plan; ++c)
             if (W.plan[c].len > W.chunk) return false;
         return true;
+    }
+    // Issue every chunk's stages; optics(c) is the caller's callback for the optics stage.
+    template <class Optics>
+    void run(uint64_t n_chunks, bool dynamic, Optics optics) const {
+        fork(n_chunks);
+        if (!piped()) {
+            for (uint64_t c = 0; c < n_chunks; ++c) {
+                pre(c);
+                sky(c, dynamic ? W.tiles + 2 * c : nullptr);
+                optics(c, optics_begin(c));
+                optics_end(c);
+            }
+            return;
+        }
+        for (uint64_t c = 0; c < n_chunks; ++c) {
+            pre(c);
+            sky(c, dynamic ? W.tiles + 2 * c : nullptr);
+            if (c >= 1) {
+                optics(c - 1, optics_begin(c - 1));
+                optics_end(c - 1);
+            }
+        }
+        if (n_chunks) {
+            optics(n_chunks - 1, optics_begin(n_chunks - 1));
+            optics_end(n_chunks - 1);
+        }
+        join(n_chunks);
     }
 };
 }  // namespace
@@ -1814,28 +1850,23 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
     if (cfg.dynamic)
         hipLaunchKernelGGL(fill_u32, dim3((unsigned)((4 * n_chunks + 255) / 256)), dim3(256), 0,
                            stream, (unsigned int*)W.tiles, 4 * n_chunks, 0u);
-    S.fork(n_chunks);
-    for (uint64_t c = 0; c < n_chunks; ++c) {
-        S.front(c, cfg.dynamic ? W.tiles + 2 * c : nullptr);
+    S.run(n_chunks, cfg.dynamic != 0, [&](uint64_t c, hipStream_t bs) {
         const ChunkSpan& sp = W.plan[c];
-        const uint32_t* surv = S.preroll() ? S.surv_buf(c) : nullptr;
-        const unsigned int* cnt = S.preroll() ? W.counts + c : nullptr;
         const uint64_t want = (sp.len + kBlock - 1) / kBlock;
         const uint64_t bcap = (uint64_t)n_cu * cfg.back_per_cu;
         const dim3 bg((unsigned)(want < bcap ? want : bcap));
         unsigned long long* bt = cfg.dynamic ? W.tiles + 2 * c + 1 : nullptr;
-        const hipStream_t bs = S.optics_begin(c);
         S.mark(2, 0, bs);
         if (L.any_zernike)
             hipLaunchKernelGGL(back_kernel<true>, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin,
-                               surv, cnt, sp.len, (const double*)S.state_buf(c), W.chunk, bt);
+                               S.surv(c), S.cnt(c), sp.len, (const double*)S.state_buf(c), W.chunk,
+                               bt);
         else
             hipLaunchKernelGGL(back_kernel<false>, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin,
-                               surv, cnt, sp.len, (const double*)S.state_buf(c), W.chunk, bt);
+                               S.surv(c), S.cnt(c), sp.len, (const double*)S.state_buf(c), W.chunk,
+                               bt);
         S.mark(2, 1, bs);
-        S.optics_end(c);
-    }
-    S.join(n_chunks);
+    });
     return hipGetLastError();
 }
 
@@ -1848,36 +1879,31 @@ hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Works
     if (grid * kBlock > A.tape_stride) return hipErrorInvalidValue;
     const uint64_t n_chunks = W.n_plan;
     const bool jac = A.jac != nullptr;
-    S.fork(n_chunks);
-    for (uint64_t c = 0; c < n_chunks; ++c) {
-        S.front(c, nullptr);
+    S.run(n_chunks, false, [&](uint64_t c, hipStream_t bs) {
         const ChunkSpan& sp = W.plan[c];
-        const uint32_t* surv = S.preroll() ? S.surv_buf(c) : nullptr;
-        const unsigned int* cnt = S.preroll() ? W.counts + c : nullptr;
-        const hipStream_t bs = S.optics_begin(c);
         const uint64_t row0 = c * grid;
         const dim3 ag((unsigned)grid);
         const double* cst = S.state_buf(c);
+        const uint32_t* sv = S.surv(c);
+        const unsigned int* cn = S.cnt(c);
         S.mark(2, 0, bs);
         if (L.any_zernike) {
             if (jac)
                 hipLaunchKernelGGL((adjoint_kernel<true, true>), ag, dim3(kBlock), 0, bs, dparams,
-                                   L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
+                                   L, sp.begin, sv, cn, sp.len, cst, W.chunk, A, row0);
             else
                 hipLaunchKernelGGL((adjoint_kernel<true, false>), ag, dim3(kBlock), 0, bs, dparams,
-                                   L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
+                                   L, sp.begin, sv, cn, sp.len, cst, W.chunk, A, row0);
         } else {
             if (jac)
                 hipLaunchKernelGGL((adjoint_kernel<false, true>), ag, dim3(kBlock), 0, bs, dparams,
-                                   L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
+                                   L, sp.begin, sv, cn, sp.len, cst, W.chunk, A, row0);
             else
                 hipLaunchKernelGGL((adjoint_kernel<false, false>), ag, dim3(kBlock), 0, bs,
-                                   dparams, L, sp.begin, surv, cnt, sp.len, cst, W.chunk, A, row0);
+                                   dparams, L, sp.begin, sv, cn, sp.len, cst, W.chunk, A, row0);
         }
         S.mark(2, 1, bs);
-        S.optics_end(c);
-    }
-    S.join(n_chunks);
+    });
     const uint64_t rows = n_chunks * grid;
     hipLaunchKernelGGL(adjoint_columns, dim3(kAdj), dim3(256), 0, stream, A.partial, rows, colsum);
     hipLaunchKernelGGL(adjoint_finish, dim3(1), dim3(64), 0, stream, dparams,
