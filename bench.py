@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the run without the pre-roll")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-source batched leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--only", choices=("batched", "gradient"), default=None,
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
@@ -261,7 +262,10 @@ def main():
     img = tr.new_image()
     stats = tr.new_stats()
     t_tune = time.perf_counter()
-    tuned = tr.autotune(flags=flags)   # eager launches pipelined over two streams
+    if args.no_autotune:
+        tuned = tr.launch_config()
+    else:
+        tuned = tr.autotune(flags=flags)   # eager launches pipelined over two streams
     t_tune = time.perf_counter() - t_tune
     print(f"# autotuned {tuned} in {t_tune:.1f}s", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
