@@ -81,7 +81,7 @@ def cpu_baseline(scene, n_photons, threads):
     return n_photons / dt, dt
 
 
-def batched_leg(steps, per_source_steps=1):
+def batched_leg(steps, per_source_steps=1, variant_slope=-1.1):
     """Many uneven sources: one graph-replayed launch over all of them (launch shape picked by
     the autotuner) against one plain launch per source, on the same GPU and the same photons."""
     import numpy as np
@@ -129,6 +129,27 @@ def batched_leg(steps, per_source_steps=1):
     tr.close()
     print(f"# batched {ms_b:.2f} ms, per-source {ms_p:.2f} ms, tune {t_tune:.1f}s {best}",
           file=sys.stderr, flush=True)
+    # the same catalogue with counts drawn from a shallower power law (slope -1.1), the photon
+    # total the configuration quotes (~3e9); batched launch only
+    variant = None
+    if variant_slope is not None:
+        sv = C.batched(slope=variant_slope)
+        tv = phx.Tracer(sv)
+        tot_v = int(sv.sources.n_photons.astype(np.int64).sum())
+        tv.set_launch_config(**{k: v for k, v in best.items()})
+        img_v = tv.new_image()
+        tv.trace(img_v, flags=flags, batched=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        tv.trace(img_v, flags=flags, batched=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_v = e0.elapsed_time(e1)
+        tv.close()
+        variant = {"slope": variant_slope, "photons_per_step": tot_v, "ms_per_step": ms_v,
+                   "value": tot_v / (ms_v * 1e-3)}
+        print(f"# batched slope {variant_slope}: {tot_v:.3e} photons, {ms_v:.1f} ms",
+              file=sys.stderr, flush=True)
     return {
         "workload": f"{len(counts)} sources (80% stars, 20% Sersic), power-law counts slope -1.5 "
                     f"on [10, 1e7], blackbody SEDs, full atmosphere + optics + sensor",
@@ -141,6 +162,7 @@ def batched_leg(steps, per_source_steps=1):
         "images_identical": same,
         "launch_config": best,
         "autotune_s": t_tune,
+        "variant": variant,
     }
 
 
