@@ -27,7 +27,7 @@ struct phx_ctx_s {
     DevParams* dparams = nullptr;
     bool dirty = true;
     float* d_coat = nullptr;
-    float* d_coat_max = nullptr;
+    int64_t* d_coat_thr = nullptr;
     float4* d_grad = nullptr;
     size_t grad_elems = 0;
     DevSource* d_src = nullptr;
@@ -229,6 +229,22 @@ void build_surfaces(phx_ctx c) {
     H.zern_inv_r = 1.0 / p.surf[0].r_outer;
 }
 
+// Largest 32-bit roulette word w whose uniform (w + 1/2) 2^-32 does not exceed r, or -1 when
+// none does: u01(w) > r  <=>  w > word_threshold(r), since u01 is increasing and exact.
+int64_t word_threshold(double r) {
+    const auto u = [](int64_t w) {
+        return std::fma((double)w, 2.3283064365386963e-10, 1.1641532182693481e-10);
+    };
+    const int64_t top = 0xFFFFFFFFll;
+    if (!(u(0) <= r)) return -1;
+    if (u(top) <= r) return top;
+    int64_t w = (int64_t)std::floor(r * 4294967296.0 - 0.5);
+    w = std::min(std::max(w, (int64_t)0), top);
+    while (w < top && u(w + 1) <= r) ++w;
+    while (w > 0 && u(w) > r) --w;
+    return w;
+}
+
 // Pre-roll order: coated surfaces sorted by the mean (over wavelength) of their coating's
 // worst-case transmission, most selective first; ties keep the surface order.
 void build_cull_order(phx_ctx c) {
@@ -303,7 +319,7 @@ void phx_destroy(phx_ctx c) {
     (void)hipDeviceSynchronize();
     free_dev(c->dparams);
     free_dev(c->d_coat);
-    free_dev(c->d_coat_max);
+    free_dev(c->d_coat_thr);
     free_dev(c->d_grad);
     free_dev(c->d_src);
     free_dev(c->d_cdf);
@@ -416,7 +432,7 @@ phx_status phx_set_perturbation(phx_ctx c, const double* theta, int32_t n) {
 phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t n_s,
                              int32_t n_lam, double s_max, double lam0, double dlam) {
     if (!c) return PHX_ERR_INVALID;
-    if (!t || n_coat <= 0 || n_s < 2 || n_lam < 2 || !(s_max > 0) || !(dlam > 0) ||
+    if (!t || n_coat <= 0 || n_s < 2 || n_lam < 2 || n_lam > 16384 || !(s_max > 0) || !(dlam > 0) ||
         !std::isfinite(lam0) || !std::isfinite(s_max) || !std::isfinite(dlam))
         return fail(c, PHX_ERR_INVALID, "bad coating table description");
     const size_t n = (size_t)n_coat * n_s * n_lam;
@@ -431,15 +447,25 @@ phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t 
                 float& m = mx[(size_t)k * n_lam + l];
                 if (v > m) m = v;
             }
+    // pre-roll thresholds per wavelength column pair (the test compares the roulette word)
+    std::vector<int64_t> thr(mx.size());
+    for (int k = 0; k < n_coat; ++k)
+        for (int l = 0; l < n_lam; ++l) {
+            const int l0 = std::min(l, n_lam - 2);
+            const double m = std::fmax((double)mx[(size_t)k * n_lam + l0],
+                                       (double)mx[(size_t)k * n_lam + l0 + 1]);
+            thr[(size_t)k * n_lam + l] = word_threshold(m + 1e-12);
+        }
     if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
     free_dev(c->d_coat);
-    free_dev(c->d_coat_max);
+    free_dev(c->d_coat_thr);
     hipError_t e = hipMalloc((void**)&c->d_coat, n * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->d_coat_max, mx.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_coat_thr, thr.size() * sizeof(int64_t));
     if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "coating tables: %s", hipGetErrorString(e));
     e = hipMemcpy(c->d_coat, t, n * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(c->d_coat_max, mx.data(), mx.size() * sizeof(float), hipMemcpyHostToDevice);
+        e = hipMemcpy(c->d_coat_thr, thr.data(), thr.size() * sizeof(int64_t),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(coatings)");
     DevParams& H = c->host;
     H.n_coat = n_coat;
@@ -449,7 +475,7 @@ phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t 
     H.lam0 = lam0;
     H.inv_dlam = 1.0 / dlam;
     H.coat = c->d_coat;
-    H.coat_max = c->d_coat_max;
+    H.coat_thr = c->d_coat_thr;
     c->coat_max = mx;
     c->have_coat = true;
     build_cull_order(c);
@@ -633,8 +659,8 @@ namespace {
 // 1.1 for the second-order terms (renormalisation, the sag slope at the displaced point, each
 // below 1 %).
 void set_cull_radii(phx_ctx c, const phx_trace_args* a, phx::Launch& L) {
-    L.cull_r_lo = -INFINITY;
-    L.cull_r_hi = INFINITY;
+    L.cull_r2_lo = -1.0;
+    L.cull_r2_hi = INFINITY;
     const phx::DevSurface& s0 = c->host.surf[0];
     if (s0.moved || c->presc.n_surfaces < 2) return;
     double D = 1e-6;
@@ -665,8 +691,9 @@ void set_cull_radii(phx_ctx c, const phx_trace_args* a, phx::Launch& L) {
         if (!std::isfinite(sum)) return;
         D += 1.1 * sum;
     }
-    L.cull_r_lo = s0.r_in - D;
-    L.cull_r_hi = s0.r_out + D;
+    const double lo = s0.r_in - D, hi = s0.r_out + D;
+    L.cull_r2_lo = lo > 0.0 ? lo * lo : -1.0;
+    L.cull_r2_hi = hi * hi;
 }
 
 // Validation, uploads and workspace for a trace; fills the launch description.  May synchronise
@@ -807,12 +834,13 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
             const uint64_t n_s = L.uniform_count ? L.uniform_count
                                                  : c->src[a->src_begin + s].n_photons;
             for (uint64_t o = 0; o < n_s; o += chunk)
-                c->plan.push_back({start + o, std::min(chunk, n_s - o), 1, 0});
+                c->plan.push_back({start + o, std::min(chunk, n_s - o), start, 1, s});
             start += n_s;
         }
     } else {
         for (uint64_t b = 0; b < L.total; b += chunk)
-            c->plan.push_back({b, std::min(chunk, L.total - b), (atm && L.n_src == 1) ? 1 : 0, 0});
+            c->plan.push_back({b, std::min(chunk, L.total - b), 0,
+                               (atm && L.n_src == 1) ? 1 : 0, L.n_src == 1 ? 0 : -1});
     }
     const uint64_t n_chunks = c->plan.size();
     if (n_chunks > c->counts_cap) {

@@ -57,7 +57,10 @@ struct DevParams {
     int32_t cull_order[PHX_MAX_SURF]; // coated surfaces, most selective coating first
     int32_t n_cull;
     const float* coat;       // [n_coat][n_s][n_lam]
-    const float* coat_max;   // [n_coat][n_lam]: max over s of each wavelength column
+    const int64_t* coat_thr; // [n_coat][n_lam]: pre-roll threshold of wavelength column pair
+                             // (il, il + 1): the largest roulette word w whose uniform
+                             // (w + 1/2) 2^-32 does not exceed the larger of the two columns'
+                             // maxima over s (plus 1e-12); -1 when every word exceeds it
     // atmosphere
     double height[PHX_MAX_LAYERS];
     double wind[PHX_MAX_LAYERS][2];
@@ -88,9 +91,10 @@ struct Launch {
     uint64_t event_stride;
     int32_t any_sersic;            // an extended source is in the range
     int32_t any_zernike;           // the first surface carries a Zernike deformation
-    // pre-roll geometric cull: a pupil sample at radius r < cull_r_lo or r > cull_r_hi cannot
+    // pre-roll geometric cull: a pupil sample at radius r with r^2 < cull_r2_lo or
+    // r^2 > cull_r2_hi cannot
     // reach the primary's clear aperture (its atmospheric displacement is bounded)
-    double cull_r_lo, cull_r_hi;
+    double cull_r2_lo, cull_r2_hi;
 };
 
 // Scratch of the staged trace: the launch's photon range is processed in chunks; per chunk the
@@ -99,10 +103,12 @@ struct Launch {
 // structure of arrays).
 constexpr uint64_t kChunk = 1ull << 26;
 // One chunk of a launch: photons [begin, begin + len) of the flattened launch index, and whether
-// its pre-roll survivors are sorted by time bucket (chunks holding a single source).
+// its pre-roll survivors are sorted by time bucket.  A chunk inside one source's range names it
+// (src: index relative to the launch's first source, first: the flattened index of that source's
+// first photon); src = -1 for a chunk that spans several sources.
 struct ChunkSpan {
-    uint64_t begin, len;
-    int32_t sort, pad;
+    uint64_t begin, len, first;
+    int32_t sort, src;
 };
 struct Workspace {
     uint32_t* survivors;       // [buffers][chunk]

@@ -25,7 +25,7 @@ constexpr double kNewtonTol = 1e-12;             // m
 constexpr int kNewtonMax = 16;
 constexpr int kBlock = kThreads;
 constexpr int kTimeBuckets = kTimeBucketsMax;   // time buckets of the survivor sort
-static_assert(kTimeBuckets <= 256, "bucket ids are stored in one byte");
+static_assert(kTimeBuckets <= 64, "bucket ids are stored in one byte and queued in six bits");
 
 // ---------------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11).  Each round's two 32x32 -> 64-bit products come from one
@@ -249,11 +249,6 @@ __device__ __forceinline__ double coating(const DevParams& P, int c, double s, c
            a * ((1.0 - b) * (double)r1[0] + b * (double)r1[1]);
 }
 
-// Upper bound of a coating's transmission over all angles at the photon's wavelength (pre-roll).
-__device__ __forceinline__ double coating_max(const DevParams& P, int c, const LamCol& lc) {
-    const float* m = P.coat_max + (size_t)c * P.n_lam + lc.il;
-    return fmax((double)m[0], (double)m[1]);
-}
 
 // Bilinear interpolation of one gradient screen at screen-pixel coordinates (xs, ys): one
 // 32-byte record per cell holds the four corner gradients.
@@ -336,9 +331,9 @@ __device__ __forceinline__ double preroll_draw(const DevParams& P, const Rng& rn
     return wavelength(P, src, w0, w1);
 }
 
-__device__ __forceinline__ bool preroll_tests(const DevParams& P, const Rng& rng, double lam,
-                                              int j0, int j1) {
-    const LamCol lc = lambda_column(P, lam);
+// Tests j0..j1-1 at wavelength column il.
+__device__ __forceinline__ bool preroll_tests(const DevParams& P, const Rng& rng, int il, int j0,
+                                              int j1) {
     int blk = -1;
     uint4 w = make_uint4(0, 0, 0, 0);
     for (int j = j0; j < j1; ++j) {
@@ -349,7 +344,7 @@ __device__ __forceinline__ bool preroll_tests(const DevParams& P, const Rng& rng
         }
         const int m = k & 3;
         const uint32_t wk = m == 0 ? w.x : (m == 1 ? w.y : (m == 2 ? w.z : w.w));
-        if (u01(wk) > coating_max(P, P.surf[k].coating, lc) + 1e-12) return true;
+        if ((int64_t)wk > P.coat_thr[(size_t)P.surf[k].coating * P.n_lam + il]) return true;
     }
     return false;
 }
@@ -423,7 +418,7 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
 #pragma unroll 1
         for (int i = P.n_layers - 1; i >= 0; --i) {
             const double h = P.height[i];
-            const double l = (h - p[2]) / n[2];
+            const double l = (h - p[2]) * rcp_fast(n[2]);
             p[0] += n[0] * l;
             p[1] += n[1] * l;
             p[2] = h;
@@ -440,11 +435,14 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
             }
             n[0] += kick * gx;
             n[1] += kick * gy;
-            normalise(n);
+            const double inv = rsq_fast(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            n[0] *= inv;
+            n[1] *= inv;
+            n[2] *= inv;
         }
     }
     {
-        const double l = (P.z_start - p[2]) / n[2];
+        const double l = (P.z_start - p[2]) * rcp_fast(n[2]);
         p[0] += n[0] * l;
         p[1] += n[1] * l;
         p[2] = P.z_start;
@@ -819,6 +817,7 @@ __device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, 
 // requested.  An ordered compaction then lists the survivors.
 constexpr int kGenIters = 16;
 constexpr int kGenRange = kBlock * kGenIters;   // photons per range (64 bitmap words)
+static_assert(kGenRange <= 4096, "range offsets are queued in twelve bits");
 
 __device__ __forceinline__ void culled_event(const Launch& L, uint64_t g, int si, uint64_t idx,
                                              double lam) {
@@ -831,14 +830,18 @@ __device__ __forceinline__ void culled_event(const Launch& L, uint64_t g, int si
     }
 }
 
+// ONE: every photon of the chunk belongs to source one_si, whose first photon has flattened
+// index `first` (the source index and the Philox key are then uniform over the workgroup).
+template <bool ONE>
 __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __restrict__ Pg,
                                                           const Launch L, uint64_t begin,
-                                                          uint64_t len,
+                                                          uint64_t len, int one_si,
+                                                          uint64_t first,
                                                           unsigned long long* __restrict__ bits,
                                                           uint8_t* __restrict__ key) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
     __shared__ unsigned long long s_bits[kGenRange / 64];
-    __shared__ uint16_t s_q[kGenRange];
+    __shared__ uint32_t s_q[kGenRange];   // queued photon: offset | time bucket << 12 | column << 18
     __shared__ unsigned int s_qn;
     stats_init(s_stats);
     const DevParams& P = *Pg;
@@ -855,23 +858,34 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
             const int rr = it * kBlock + threadIdx.x;
             const uint64_t r = r0 + rr;
             bool pass = false, culled = false;
+            uint32_t entry = 0;
             if (r < len) {
                 const uint64_t g = begin + r;
                 int si;
                 uint64_t idx;
-                decode(L, g, si, idx);
+                if constexpr (ONE) {
+                    si = one_si;
+                    idx = L.photon_begin + (g - first);
+                } else {
+                    decode(L, g, si, idx);
+                }
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
                 uint32_t wt, wr;
                 const double lam = preroll_draw(P, rng, si, wt, wr);
-                // pupil radius as the sky stage samples it: outside the reachable annulus the
-                // photon is vignetted at the primary whatever the atmosphere does
+                // squared pupil radius as the sky stage samples it: outside the reachable annulus
+                // the photon is vignetted at the primary whatever the atmosphere does (the bounds
+                // carry a margin far above the rounding of the square root)
                 const double ro = P.pupil_r_out + L.pupil_margin;
                 const double ri = fmax(P.pupil_r_in - L.pupil_margin, 0.0);
-                const double rp = sqrt(u01(wr) * (ro * ro - ri * ri) + ri * ri);
-                culled = rp < L.cull_r_lo || rp > L.cull_r_hi ||
-                         preroll_tests(P, rng, lam, 0, min(n_tests, 1));
+                const double rp2 = u01(wr) * (ro * ro - ri * ri) + ri * ri;
+                const int il = lambda_column(P, lam).il;
+                culled = rp2 < L.cull_r2_lo || rp2 > L.cull_r2_hi ||
+                         preroll_tests(P, rng, il, 0, min(n_tests, 1));
                 pass = !culled;
                 if (culled) culled_event(L, g, si, idx, lam);
+                // time bucket of a survivor (the time stamp is t_e u01(wt))
+                const int tb = min((int)(u01(wt) * kTimeBuckets), kTimeBuckets - 1);
+                entry = (uint32_t)rr | ((uint32_t)tb << 12) | ((uint32_t)il << 18);
             }
             const uint64_t pm = __ballot(pass), cm = __ballot(culled);
             unsigned int base = 0;
@@ -880,7 +894,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 if (cm) atomicAdd(&s_stats[PHX_CULLED * PHX_STAT_COLS], (uint32_t)__popcll(cm));
             }
             base = __shfl(base, 0);
-            if (pass) s_q[base + __popcll(pm & ((1ull << lane) - 1ull))] = (uint16_t)rr;
+            if (pass) s_q[base + __popcll(pm & ((1ull << lane) - 1ull))] = entry;
         }
         __syncthreads();
         // stage two: the remaining tests for the queued photons
@@ -889,23 +903,27 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
             const unsigned int qi = q0 + threadIdx.x;
             bool keep = false, culled = false;
             if (qi < qn) {
-                const int rr = s_q[qi];
+                const uint32_t entry = s_q[qi];
+                const int rr = (int)(entry & 0xfffu);
                 const uint64_t r = r0 + rr;
                 const uint64_t g = begin + r;
                 int si;
                 uint64_t idx;
-                decode(L, g, si, idx);
+                if constexpr (ONE) {
+                    si = one_si;
+                    idx = L.photon_begin + (g - first);
+                } else {
+                    decode(L, g, si, idx);
+                }
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
-                uint32_t wt, wr;
-                const double lam = preroll_draw(P, rng, si, wt, wr);
-                culled = preroll_tests(P, rng, lam, 1, n_tests);
+                culled = preroll_tests(P, rng, (int)(entry >> 18), 1, n_tests);
                 keep = !culled;
                 if (keep) {
                     atomicOr(&s_bits[rr >> 6], 1ull << (rr & 63));
-                    // time bucket of a survivor (the time stamp is t_e u01(wt))
-                    if (key) key[r] = (uint8_t)min((int)(u01(wt) * kTimeBuckets), kTimeBuckets - 1);
-                } else {
-                    culled_event(L, g, si, idx, lam);
+                    if (key) key[r] = (uint8_t)((entry >> 12) & 0x3fu);
+                } else if ((L.flags & PHX_F_EVENTS) && (g % L.event_stride) == 0) {
+                    uint32_t wt, wr;
+                    culled_event(L, g, si, idx, preroll_draw(P, rng, si, wt, wr));
                 }
             }
             const uint64_t cm = __ballot(culled);
@@ -1705,9 +1723,14 @@ static void launch_preroll(const DevParams* dparams, const Launch& L, const Work
     const bool sort = sp.sort && W.key && W.hist;
     const uint64_t want = (sp.len + kGenRange - 1) / kGenRange;
     const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
-    hipLaunchKernelGGL(generate_kernel, dim3((unsigned)(want < cap ? want : cap)), dim3(kBlock), 0,
-                       stream, dparams, L, sp.begin, sp.len, W.bits,
-                       sort ? W.key : (uint8_t*)nullptr);
+    const dim3 gg((unsigned)(want < cap ? want : cap));
+    uint8_t* key = sort ? W.key : (uint8_t*)nullptr;
+    if (sp.src >= 0)
+        hipLaunchKernelGGL(generate_kernel<true>, gg, dim3(kBlock), 0, stream, dparams, L,
+                           sp.begin, sp.len, L.src_begin + sp.src, sp.first, W.bits, key);
+    else
+        hipLaunchKernelGGL(generate_kernel<false>, gg, dim3(kBlock), 0, stream, dparams, L,
+                           sp.begin, sp.len, 0, (uint64_t)0, W.bits, key);
     const uint64_t n_words = (sp.len + 63) / 64;
     const unsigned nb = (unsigned)((n_words + kCompactWords - 1) / kCompactWords);
     if (sort) {
