@@ -218,7 +218,7 @@ phx_status phx_set_perturbation(phx_ctx ctx, const double* theta_host, int32_t n
 
 /* Load coating tables (section 2.4.2 transmission probability vs angle and wavelength):
  * float32 [n_coat][n_s][n_lambda], transmission on a uniform grid of s = sin^2(incidence angle)
- * from 0 to s_max and wavelength lambda0 + k dlambda (2 <= n_lambda <= 16384).  Copied to device
+ * from 0 to s_max and wavelength lambda0 + k dlambda (2 <= n_lambda <= 8192).  Copied to device
  * memory.
  * Errors: PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
 phx_status phx_load_coatings(phx_ctx ctx, const float* tables_host, int32_t n_coat, int32_t n_s,

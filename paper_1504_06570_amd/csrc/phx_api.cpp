@@ -28,6 +28,7 @@ struct phx_ctx_s {
     bool dirty = true;
     float* d_coat = nullptr;
     int64_t* d_coat_thr = nullptr;
+    uint32_t* d_esc_thr = nullptr;       // pre-roll escape filter per wavelength column
     float4* d_grad = nullptr;
     size_t grad_elems = 0;
     DevSource* d_src = nullptr;
@@ -229,6 +230,88 @@ void build_surfaces(phx_ctx c) {
     H.zern_inv_r = 1.0 / p.surf[0].r_outer;
 }
 
+phx_status set_device(phx_ctx c);
+
+// Host copies of the silicon and glass optics the pre-roll escape filter is built from (the
+// filter only needs to be approximately right: a low value skips culls, never adds one).
+double host_absorption(const DevParams& H, double lam) {
+    const double e = 1.2398419843320026e-6 / lam;
+    const double C[2] = {5.5, 4.0}, A[2] = {3.231e2, 7.237e3}, ep[2] = {1.827e-2, 5.773e-2};
+    double alpha = 0.0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const double a = e - H.eg[j] + ep[i], b = e - H.eg[j] - ep[i];
+            double term = 0.0;
+            if (a > 0.0) term += a * a / H.absorb[i];
+            if (b > 0.0) term += b * b / H.emit[i];
+            alpha += C[i] * A[j] * term;
+        }
+    if (e > H.egd) alpha += 1.052e6 * std::sqrt(e - H.egd);
+    return alpha * 100.0;
+}
+double host_n_silicon(double lam) {
+    const double e = 1.2398419843320026e-6 / lam;
+    return 3.36 + 0.211 * e + 2.79 * std::exp((e - 3.30) / 0.398);
+}
+double host_sellmeier(const DevParams& H, double lam) {
+    const double l2 = (lam * 1e6) * (lam * 1e6);
+    double s = 1.0;
+    for (int i = 0; i < 3; ++i) s += H.sell_b[i] * l2 / (l2 - H.sell_c[i]);
+    return std::sqrt(s);
+}
+
+// Pre-roll escape filter (section 3.2 with the silicon stage): a photon whose conversion distance
+// L = -ln(u) / alpha exceeds t_Si / cos_min, with cos_min the smallest cosine a ray refracted into
+// silicon can have, escapes whatever its path: u < E(lambda) = exp(-alpha t_Si / cos_min).  Per
+// wavelength column the table holds the first word whose uniform reaches 1.5 x max E over the
+// column (sampled; the first column also stands for every bluer wavelength, whose absorption is
+// stronger), so that words at or above it skip the exact test (0: the column never takes it); the
+// last column stands for every redder wavelength and always takes it.
+phx_status build_escape_table(phx_ctx c) {
+    DevParams& H = c->host;
+    H.esc_thr = nullptr;
+    H.esc_col0 = H.n_lam;
+    if (!c->have_presc || !c->have_coat) return PHX_OK;
+    // a flat silicon detector: the depth is measured along the surface normal
+    const phx_surface& det = c->presc.surf[c->presc.n_surfaces - 1];
+    if (det.medium != PHX_SILICON || det.curvature != 0.0) return PHX_OK;
+    for (int i = 0; i < 8; ++i)
+        if (det.alpha[i] != 0.0) return PHX_OK;
+    std::vector<uint32_t> t((size_t)H.n_lam, 0xFFFFFFFFu);
+    const double dlam = 1.0 / H.inv_dlam;
+    for (int il = 0; il + 2 < H.n_lam; ++il) {
+        double emax = 0.0;
+        for (int k = 0; k <= 32; ++k) {
+            const double lam = il == 0 ? H.lam0 * (0.5 + k / 64.0) + k / 32.0 * dlam
+                                       : H.lam0 + (il + k / 32.0) * dlam;
+            const double n_in = H.has_glass ? host_sellmeier(H, lam) : 1.0;
+            const double q = n_in / host_n_silicon(lam);
+            const double cmin = q < 1.0 ? std::sqrt(1.0 - q * q) : 0.0;
+            const double alpha = host_absorption(H, lam);
+            const double e = cmin > 0.0 ? std::exp(-alpha * H.t_si / cmin) : 0.0;
+            emax = std::max(emax, e);
+        }
+        // u01(w) < x  <=>  w < x 2^32 - 1/2: no word passes below ceil(x 2^32 - 1/2).  A column
+        // whose escape chance stays below 1e-3 skips the test: its Philox block would cost more
+        // than the culls save (skipping a cull never changes a result).
+        const double x = emax * 1.5;
+        const double w = std::ceil(x * 4294967296.0 - 0.5);
+        t[(size_t)il] = x < 1e-3 ? 0u : (w >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)w);
+    }
+    int col0 = H.n_lam;
+    for (int il = H.n_lam - 1; il >= 0; --il)
+        if (t[(size_t)il]) col0 = il;
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    free_dev(c->d_esc_thr);
+    hipError_t e = hipMalloc((void**)&c->d_esc_thr, t.size() * sizeof(uint32_t));
+    if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "escape table: %s", hipGetErrorString(e));
+    e = hipMemcpy(c->d_esc_thr, t.data(), t.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(escape table)");
+    H.esc_thr = c->d_esc_thr;
+    H.esc_col0 = col0;
+    return PHX_OK;
+}
+
 // Largest 32-bit roulette word w whose uniform (w + 1/2) 2^-32 does not exceed r, or -1 when
 // none does: u01(w) > r  <=>  w > word_threshold(r), since u01 is increasing and exact.
 int64_t word_threshold(double r) {
@@ -320,6 +403,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->dparams);
     free_dev(c->d_coat);
     free_dev(c->d_coat_thr);
+    free_dev(c->d_esc_thr);
     free_dev(c->d_grad);
     free_dev(c->d_src);
     free_dev(c->d_cdf);
@@ -415,7 +499,7 @@ phx_status phx_load_prescription(phx_ctx c, const phx_prescription* p) {
     c->have_presc = true;
     build_cull_order(c);
     c->dirty = true;
-    return PHX_OK;
+    return build_escape_table(c);
 }
 
 phx_status phx_set_perturbation(phx_ctx c, const double* theta, int32_t n) {
@@ -432,7 +516,7 @@ phx_status phx_set_perturbation(phx_ctx c, const double* theta, int32_t n) {
 phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t n_s,
                              int32_t n_lam, double s_max, double lam0, double dlam) {
     if (!c) return PHX_ERR_INVALID;
-    if (!t || n_coat <= 0 || n_s < 2 || n_lam < 2 || n_lam > 16384 || !(s_max > 0) || !(dlam > 0) ||
+    if (!t || n_coat <= 0 || n_s < 2 || n_lam < 2 || n_lam > 8192 || !(s_max > 0) || !(dlam > 0) ||
         !std::isfinite(lam0) || !std::isfinite(s_max) || !std::isfinite(dlam))
         return fail(c, PHX_ERR_INVALID, "bad coating table description");
     const size_t n = (size_t)n_coat * n_s * n_lam;
@@ -480,7 +564,7 @@ phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t 
     c->have_coat = true;
     build_cull_order(c);
     c->dirty = true;
-    return PHX_OK;
+    return build_escape_table(c);
 }
 
 phx_status phx_load_screens(phx_ctx c, const phx_atmosphere* a, const float* opd, int64_t n_floats,

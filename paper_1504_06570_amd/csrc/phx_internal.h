@@ -55,6 +55,11 @@ struct DevParams {
     // coatings: uniform grid in s = sin^2(theta) and wavelength
     double inv_s_step, lam0, inv_dlam;
     int32_t cull_order[PHX_MAX_SURF]; // coated surfaces, most selective coating first
+    // pre-roll escape test per wavelength column: a conversion word at or above esc_thr[il]
+    // cannot mean a certain escape (a quick filter; the exact test follows below it); null: off
+    const uint32_t* esc_thr;
+    int32_t esc_col0;          // first column whose esc_thr is not 0 (n_lam when none)
+    int32_t esc_pad;
     int32_t n_cull;
     const float* coat;       // [n_coat][n_s][n_lam]
     const int64_t* coat_thr; // [n_coat][n_lam]: pre-roll threshold of wavelength column pair

@@ -349,6 +349,22 @@ __device__ __forceinline__ bool preroll_tests(const DevParams& P, const Rng& rng
     return false;
 }
 
+// Pre-roll escape test (section 3.2 with the silicon stage): the photon converts deeper than the
+// silicon whatever its path, since its conversion distance (the silicon stage's draw) times the
+// smallest cosine a ray refracted into silicon can have exceeds the thickness.  The ray reaches
+// silicon from vacuum or glass, so sin(theta) in silicon is at most n_in / n_Si with n_in the
+// glass index when the optics hold glass; the relative margin 1e-12 covers the rounding of the
+// optics stage's refracted direction.  Kept out of line: it runs for few photons, and inlined it
+// raises the register count of the whole pre-roll.
+__device__ __noinline__ bool escape_certain(const DevParams& P, double lam, uint32_t w_conv) {
+    const double alpha = absorption(P, lam);
+    const double L_conv = alpha > 0.0 ? -log(u01(w_conv)) / alpha : INFINITY;
+    const double q = (P.has_glass ? sellmeier(P, lam) : 1.0) / n_silicon(lam);
+    if (!(q < 1.0)) return false;
+    const double cos_min = sqrt(1.0 - q * q);
+    return L_conv * cos_min * (1.0 - 1e-12) > P.t_si;
+}
+
 struct Outcome {
     int status, surface, newton;
     int pix_i, pix_j;
@@ -841,8 +857,9 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                                                           uint8_t* __restrict__ key) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
     __shared__ unsigned long long s_bits[kGenRange / 64];
-    __shared__ uint32_t s_q[kGenRange];   // queued photon: offset | time bucket << 12 | column << 18
-    __shared__ unsigned int s_qn;
+    // queued photon: offset | time bucket << 12 | wavelength column << 18 | escape test << 31
+    __shared__ uint32_t s_q[kGenRange];
+    __shared__ unsigned int s_qn, s_esc;
     stats_init(s_stats);
     const DevParams& P = *Pg;
     const int lane = __lane_id();
@@ -851,7 +868,10 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
     for (uint64_t rg = blockIdx.x; rg < n_ranges; rg += gridDim.x) {   // workgroup-uniform
         const uint64_t r0 = rg * kGenRange;
         if (threadIdx.x < kGenRange / 64) s_bits[threadIdx.x] = 0ull;
-        if (threadIdx.x == 0) s_qn = 0;
+        if (threadIdx.x == 0) {
+            s_qn = 0;
+            s_esc = 0;
+        }
         __syncthreads();
         // stage one: wavelength and the first test for every photon of the range
         for (int it = 0; it < kGenIters; ++it) {
@@ -916,8 +936,20 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                     decode(L, g, si, idx);
                 }
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
-                culled = preroll_tests(P, rng, (int)(entry >> 18), 1, n_tests);
-                keep = !culled;
+                const int il = (int)((entry >> 18) & 0x1fffu);
+                culled = preroll_tests(P, rng, il, 1, n_tests);
+                const uint32_t et = P.esc_thr && il >= P.esc_col0 ? P.esc_thr[il] : 0u;
+                bool later = false;
+                if (!culled && et && (L.flags & PHX_F_SILICON)) {
+                    // escape: a quick filter on the conversion word here; the exact test in
+                    // stage three, out of this loop's register budget
+                    later = rng.block(1).z < et;
+                    if (later) {
+                        s_q[qi] = entry | (1u << 31);
+                        s_esc = 1u;
+                    }
+                }
+                keep = !culled && !later;
                 if (keep) {
                     atomicOr(&s_bits[rr >> 6], 1ull << (rr & 63));
                     if (key) key[r] = (uint8_t)((entry >> 12) & 0x3fu);
@@ -929,6 +961,41 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
             const uint64_t cm = __ballot(culled);
             if (lane == 0 && cm)
                 atomicAdd(&s_stats[PHX_CULLED * PHX_STAT_COLS], (uint32_t)__popcll(cm));
+        }
+        // stage three: the exact escape test for the photons stage two flagged
+        __syncthreads();
+        if (s_esc) {
+            for (unsigned int q0 = 0; q0 < qn; q0 += kBlock) {
+                const unsigned int qi = q0 + threadIdx.x;
+                const uint32_t entry = qi < qn ? s_q[qi] : 0u;
+                bool culled = false;
+                if (entry >> 31) {
+                    const int rr = (int)(entry & 0xfffu);
+                    const uint64_t r = r0 + rr;
+                    const uint64_t g = begin + r;
+                    int si;
+                    uint64_t idx;
+                    if constexpr (ONE) {
+                        si = one_si;
+                        idx = L.photon_begin + (g - first);
+                    } else {
+                        decode(L, g, si, idx);
+                    }
+                    const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                    uint32_t wt, wr;
+                    const double lam = preroll_draw(P, rng, si, wt, wr);
+                    culled = escape_certain(P, lam, rng.block(1).z);
+                    if (!culled) {
+                        atomicOr(&s_bits[rr >> 6], 1ull << (rr & 63));
+                        if (key) key[r] = (uint8_t)((entry >> 12) & 0x3fu);
+                    } else {
+                        culled_event(L, g, si, idx, lam);
+                    }
+                }
+                const uint64_t cm = __ballot(culled);
+                if (lane == 0 && cm)
+                    atomicAdd(&s_stats[PHX_CULLED * PHX_STAT_COLS], (uint32_t)__popcll(cm));
+            }
         }
         __syncthreads();
         if (threadIdx.x < kGenRange / 64 && r0 + (uint64_t)threadIdx.x * 64 < len)

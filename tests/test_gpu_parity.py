@@ -181,8 +181,8 @@ def test_moments_equal_sums_over_events(phx):
 def test_geometric_preroll_culls_only_primary_vignetting(phx):
     """With the atmosphere the pupil annulus is sampled wider than the primary; the pre-roll drops
     samples farther out than the bounded atmospheric displacement.  With coatings that never cull,
-    every photon it drops is vignetted at the primary in the full trace, and every other photon
-    keeps its record."""
+    every photon it drops is vignetted at the primary in the full trace (or, for the red photons
+    the escape test removes, crosses the silicon), and every other photon keeps its record."""
     import torch
     s = C.full(scale=2e-4, screen_n=128)
     s.coatings = np.ones_like(s.coatings)
@@ -192,8 +192,37 @@ def test_geometric_preroll_culls_only_primary_vignetting(phx):
     torch.cuda.synchronize()
     a, b = phx.events_to_numpy(ea), phx.events_to_numpy(eb)
     culled = b["status"] == phx.CULLED
-    assert culled.mean() > 0.03
-    assert np.all(a["status"][culled] == phx.VIGNETTED) and np.all(a["surface"][culled] == 0)
+    prim = (a["status"] == phx.VIGNETTED) & (a["surface"] == 0)
+    assert (culled & prim).mean() > 0.03
+    assert np.all((prim | (a["status"] == phx.ESCAPED))[culled])
+    keep = ~culled
+    for f in ("status", "surface", "pix_i", "pix_j", "x", "y", "xe", "ye"):
+        assert np.array_equal(a[f][keep], b[f][keep]), f
+    tr.close()
+
+
+def test_escape_preroll_culls_only_certain_escapes(phx):
+    """Red photons with coatings that never cull: the pre-roll's escape test removes photons whose
+    conversion distance times the smallest refracted cosine exceeds the silicon thickness; none of
+    them converts in the full trace (those that reach the silicon escape it), and every other
+    photon keeps its record."""
+    import torch
+    s = C.telescope(scale=0.002)
+    s.coatings = np.ones_like(s.coatings)
+    s.sources.lam_lo[:] = 950e-9
+    s.sources.lam_hi[:] = 1080e-9
+    tr = phx.Tracer(s)
+    _, _, _, ea = tr.trace(event_stride=1)
+    img_b, _, _, eb = tr.trace(event_stride=1, flags=int(s.physics) | phx.F_CULL)
+    img_a, _, _, _ = tr.trace()
+    torch.cuda.synchronize()
+    assert torch.equal(img_a, img_b)
+    a, b = phx.events_to_numpy(ea), phx.events_to_numpy(eb)
+    culled = b["status"] == phx.CULLED
+    escaped = a["status"] == phx.ESCAPED
+    assert culled.sum() > 0.2 * escaped.sum() > 0
+    assert not np.isin(a["status"][culled], [phx.DETECTED, phx.OFF_CHIP]).any()
+    assert escaped[culled].mean() > 0.5, np.bincount(a["status"][culled])
     keep = ~culled
     for f in ("status", "surface", "pix_i", "pix_j", "x", "y", "xe", "ye"):
         assert np.array_equal(a[f][keep], b[f][keep]), f
