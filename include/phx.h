@@ -80,10 +80,13 @@ enum {
     PHX_F_DIFFUSION = 1u << 3,  /* Gaussian charge diffusion                               */
     PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
                                    worst-case transmission of any coated surface (section 3.2,
-                                   dynamic transmission optimisation), and pupil samples whose
+                                   dynamic transmission optimisation), pupil samples whose
                                    radius lies farther outside the primary's clear annulus than
-                                   the largest atmospheric displacement; images and moments are
-                                   unchanged, culled photons are counted as PHX_CULLED */
+                                   the largest atmospheric displacement, and (flat silicon
+                                   detector) photons whose conversion distance times the smallest
+                                   refracted cosine exceeds the silicon thickness; images and
+                                   moments are unchanged, culled photons are counted as
+                                   PHX_CULLED */
     PHX_F_EVENTS = 1u << 9,     /* write per-photon records for sampled photons            */
     PHX_F_MOMENTS = 1u << 10    /* accumulate per-source moments of converted photons      */
 };
