@@ -906,9 +906,9 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         c->ws_chunk = chunk;
     }
     chunk = std::min<uint64_t>(c->ws_chunk, max_chunk);
-    // Chunk plan.  With the atmosphere, a chunk that holds one source has its survivors sorted by
-    // time (screen locality); launches of big sources are cut at source boundaries for that,
-    // launches of many small sources are cut evenly and keep photon order.
+    // Chunk plan.  With the atmosphere every chunk has its survivors sorted by time (screen
+    // locality; a chunk of many sources keeps their order within a time bucket); launches of big
+    // sources are cut at source boundaries, launches of many small sources evenly.
     c->plan.clear();
     const bool atm = (a->flags & PHX_F_ATMOSPHERE) != 0;
     const bool per_source = atm && L.n_src > 1 && L.total / (uint64_t)L.n_src >= chunk / 8;
@@ -923,8 +923,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         }
     } else {
         for (uint64_t b = 0; b < L.total; b += chunk)
-            c->plan.push_back({b, std::min(chunk, L.total - b), 0,
-                               (atm && L.n_src == 1) ? 1 : 0, L.n_src == 1 ? 0 : -1});
+            c->plan.push_back({b, std::min(chunk, L.total - b), 0, atm ? 1 : 0,
+                               L.n_src == 1 ? 0 : -1});
     }
     const uint64_t n_chunks = c->plan.size();
     if (n_chunks > c->counts_cap) {
