@@ -237,7 +237,8 @@ phx_status phx_load_screens(phx_ctx ctx, const phx_atmosphere* atm_host, const f
 /* Load the source catalogue (section 2.2) and tabulated SEDs (f_lambda per wavelength bin on the
  * shared grid sed_edges_host[0..sed_k]; flux_host [n_sed][sed_k]).  Both copied; the context
  * builds each SED's photon cumulative distribution (section 2.2: flux / photon energy x bin
- * width).  n_sed may be 0.  Errors: PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
+ * width) and a search guide for it.  n_sed may be 0; 1 <= sed_k <= 65535.  Errors:
+ * PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
 phx_status phx_load_sources(phx_ctx ctx, const phx_source* src_host, int32_t n_src,
                             const double* sed_edges_host, const double* sed_flux_host,
                             int32_t n_sed, int32_t sed_k);

@@ -35,6 +35,7 @@ struct phx_ctx_s {
     std::vector<phx_source> src;
     std::vector<float> coat_max;   // host copy of the per-wavelength worst-case transmission
     double* d_cdf = nullptr;
+    uint16_t* d_guide = nullptr;          // SED search guide [n_sed][kSedGuide + 1]
     double* d_edges = nullptr;
     uint64_t* d_prefix = nullptr;
     size_t prefix_cap = 0;
@@ -407,6 +408,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_grad);
     free_dev(c->d_src);
     free_dev(c->d_cdf);
+    free_dev(c->d_guide);
     free_dev(c->d_edges);
     free_dev(c->d_prefix);
     free_dev(c->d_survivors);
@@ -642,7 +644,7 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
                             const double* flux, int32_t n_sed, int32_t sed_k) {
     if (!c) return PHX_ERR_INVALID;
     if (!src || n_src <= 0) return fail(c, PHX_ERR_INVALID, "no sources");
-    if (n_sed < 0 || (n_sed > 0 && (!edges || !flux || sed_k < 1)))
+    if (n_sed < 0 || (n_sed > 0 && (!edges || !flux || sed_k < 1 || sed_k > 65535)))
         return fail(c, PHX_ERR_INVALID, "bad SED table");
     std::vector<DevSource> ds(n_src);
     for (int i = 0; i < n_src; ++i) {
@@ -680,6 +682,7 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
     // SED photon CDFs (section 2.2): bin weight = f_lambda x width x centre wavelength (flux over
     // photon energy), accumulated in order and normalised; CDF[K] = 1 exactly.
     std::vector<double> cdf;
+    std::vector<uint16_t> guide;
     if (n_sed > 0) {
         for (int k = 0; k < sed_k; ++k)
             if (!(edges[k + 1] > edges[k]) || !(edges[k] > 0))
@@ -701,19 +704,39 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
             for (int k = 1; k < sed_k; ++k) C[k] = C[k] / total;
             C[sed_k] = 1.0;
         }
+        // search guide: the first bin k with CDF[k + 1] > j / kSedGuide (the same predicate as
+        // the device search, so the guided search returns the same bin)
+        guide.assign((size_t)n_sed * (phx::kSedGuide + 1), 0);
+        for (int s = 0; s < n_sed; ++s) {
+            const double* C = cdf.data() + (size_t)s * (sed_k + 1);
+            uint16_t* G = guide.data() + (size_t)s * (phx::kSedGuide + 1);
+            int k = 0;
+            for (int j = 0; j < phx::kSedGuide; ++j) {
+                const double u = (double)j / phx::kSedGuide;
+                while (k < sed_k - 1 && !(C[k + 1] > u)) ++k;
+                G[j] = (uint16_t)k;
+            }
+            G[phx::kSedGuide] = (uint16_t)(sed_k - 1);
+        }
     }
     if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
     free_dev(c->d_src);
     free_dev(c->d_cdf);
+    free_dev(c->d_guide);
     free_dev(c->d_edges);
     hipError_t e = hipMalloc((void**)&c->d_src, ds.size() * sizeof(DevSource));
     if (e == hipSuccess && n_sed > 0) e = hipMalloc((void**)&c->d_cdf, cdf.size() * sizeof(double));
+    if (e == hipSuccess && n_sed > 0)
+        e = hipMalloc((void**)&c->d_guide, guide.size() * sizeof(uint16_t));
     if (e == hipSuccess && n_sed > 0)
         e = hipMalloc((void**)&c->d_edges, (size_t)(sed_k + 1) * sizeof(double));
     if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "sources: %s", hipGetErrorString(e));
     e = hipMemcpy(c->d_src, ds.data(), ds.size() * sizeof(DevSource), hipMemcpyHostToDevice);
     if (e == hipSuccess && n_sed > 0)
         e = hipMemcpy(c->d_cdf, cdf.data(), cdf.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_sed > 0)
+        e = hipMemcpy(c->d_guide, guide.data(), guide.size() * sizeof(uint16_t),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess && n_sed > 0)
         e = hipMemcpy(c->d_edges, edges, (size_t)(sed_k + 1) * sizeof(double),
                       hipMemcpyHostToDevice);
@@ -724,6 +747,7 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
     DevParams& H = c->host;
     H.src = c->d_src;
     H.sed_cdf = c->d_cdf;
+    H.sed_guide = c->d_guide;
     H.sed_edges = c->d_edges;
     H.sed_k = n_sed > 0 ? sed_k : 0;
     c->have_src = true;

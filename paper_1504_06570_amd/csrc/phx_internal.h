@@ -8,6 +8,7 @@
 namespace phx {
 
 constexpr int kNZern = 12;  // Noll Z4..Z15
+constexpr int kSedGuide = 1024;   // guide entries per SED for the wavelength search
 constexpr int kNZernPoly = 15;  // monomials u^a v^b, a + b <= 4
 
 // One surface as the kernels read it.  The element frame maps to the global frame by
@@ -78,6 +79,8 @@ struct DevParams {
     const DevSource* src;
     const double* sed_cdf;   // [n_sed][sed_k + 1]
     const double* sed_edges; // [sed_k + 1]
+    const uint16_t* sed_guide; // [n_sed][kSedGuide + 1]: guide[j] = the first bin k with
+                               // CDF[k + 1] > j / kSedGuide (guide[kSedGuide] = sed_k - 1)
 };
 
 // Per-launch arguments.

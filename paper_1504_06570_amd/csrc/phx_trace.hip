@@ -296,7 +296,8 @@ __device__ double gamma_sample(const Rng& rng, double shape) {
 }
 
 // Wavelength (section 2.2): flat photon spectrum, or the SED's photon CDF (first bin k with
-// CDF[k+1] > u) blurred uniformly across the bin; then (1 + z).
+// CDF[k+1] > u, found by bisection between two entries of a guide table) blurred uniformly
+// across the bin; then (1 + z).
 __device__ __forceinline__ double wavelength(const DevParams& P, const DevSource& src,
                                              const uint4& w0, const uint4& w1) {
     double lam;
@@ -305,7 +306,10 @@ __device__ __forceinline__ double wavelength(const DevParams& P, const DevSource
     } else {
         const double* cdf = P.sed_cdf + (size_t)src.sed * (P.sed_k + 1);
         const double u = u01(w0.w);
-        int lo = 0, hi = P.sed_k - 1;
+        // the answer lies between the guide entries around u (u kSedGuide is exact)
+        const uint16_t* guide = P.sed_guide + (size_t)src.sed * (kSedGuide + 1);
+        const int j = min((int)(u * kSedGuide), kSedGuide - 1);
+        int lo = guide[j], hi = guide[j + 1];
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (cdf[mid + 1] > u) hi = mid; else lo = mid + 1;
