@@ -39,6 +39,9 @@ struct phx_ctx_s {
     double* d_edges = nullptr;
     uint64_t* d_prefix = nullptr;
     size_t prefix_cap = 0;
+    int32_t* d_src_guide = nullptr;       // photon-block -> source guide of the prefix table
+    size_t src_guide_cap = 0;
+    uint32_t guide_shift = 0;
     uint32_t* d_survivors = nullptr;     // pre-roll survivors of one chunk
     unsigned int* d_counts = nullptr;    // survivor count per chunk
     uint64_t counts_cap = 0;
@@ -411,6 +414,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_guide);
     free_dev(c->d_edges);
     free_dev(c->d_prefix);
+    free_dev(c->d_src_guide);
     free_dev(c->d_survivors);
     free_dev(c->d_counts);
     free_dev(c->d_state);
@@ -868,6 +872,33 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         const bool same = c->prefix_valid && c->prefix_begin == a->src_begin &&
                           c->prefix_end == a->src_end && c->prefix_version == c->src_version;
         if (!same) {
+            // source guide: blocks of 2^shift photons, about four per source
+            uint32_t shift = 0;
+            while (shift < 40 && (L.total >> (shift + 1)) >= 4 * (uint64_t)L.n_src) ++shift;
+            const uint64_t nb = L.total ? ((L.total - 1) >> shift) + 1 : 1;
+            std::vector<int32_t> guide(nb + 1);
+            int s = 0;
+            for (uint64_t b = 0; b < nb; ++b) {
+                const uint64_t g = b << shift;
+                while (s + 1 < L.n_src && pre[s + 1] <= g) ++s;
+                guide[b] = s;
+            }
+            guide[nb] = L.n_src - 1;
+            if (guide.size() > c->src_guide_cap) {
+                hipError_t e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+                free_dev(c->d_src_guide);
+                c->src_guide_cap = 0;
+                e = hipMalloc((void**)&c->d_src_guide, guide.size() * sizeof(int32_t));
+                if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "source guide");
+                c->src_guide_cap = guide.size();
+            }
+            hipError_t e = hipStreamSynchronize(st);
+            if (e == hipSuccess)
+                e = hipMemcpy(c->d_src_guide, guide.data(), guide.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(c, e, "source guide upload");
+            c->guide_shift = shift;
             if ((size_t)(L.n_src + 1) > c->prefix_cap) {
                 hipError_t e = hipStreamSynchronize(st);
                 if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
@@ -879,7 +910,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
             }
             // enqueued work may still read the previous table; the host vector must outlive
             // the copy: both are handled by doing it synchronously after the stream drains
-            hipError_t e = hipStreamSynchronize(st);
+            e = hipStreamSynchronize(st);
             if (e == hipSuccess)
                 e = hipMemcpy(c->d_prefix, pre.data(), pre.size() * sizeof(uint64_t),
                               hipMemcpyHostToDevice);
@@ -890,6 +921,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
             c->prefix_version = c->src_version;
         }
         L.prefix = c->d_prefix;
+        L.src_guide = c->d_src_guide;
+        L.guide_shift = c->guide_shift;
     }
     if (a->photon_begin > UINT64_MAX - (L.total ? L.total : 0))
         return fail(c, PHX_ERR_INVALID, "photon index overflows");

@@ -90,6 +90,9 @@ struct Launch {
     uint64_t photon_begin;
     uint64_t uniform_count;        // > 0: every source traces this many photons
     const uint64_t* prefix;        // else: exclusive prefix of per-source counts [n_src + 1]
+    const int32_t* src_guide;      // with prefix: src_guide[b] = the source holding flattened
+                                   // photon b << guide_shift ([blocks + 1], last = n_src - 1)
+    uint32_t guide_shift, guide_pad;
     uint64_t total;
     double exposure, pupil_margin;
     uint32_t* image;

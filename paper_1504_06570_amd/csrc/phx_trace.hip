@@ -685,7 +685,9 @@ __device__ __forceinline__ void decode(const Launch& L, uint64_t g, int& si, uin
         s = (int)(g / L.uniform_count);
         local = g - (uint64_t)s * L.uniform_count;
     } else {
-        int lo = 0, hi = L.n_src - 1;   // largest s with prefix[s] <= g
+        // largest s with prefix[s] <= g, between the sources of the guide blocks around g
+        const uint64_t b = g >> L.guide_shift;
+        int lo = L.src_guide[b], hi = L.src_guide[b + 1];
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (L.prefix[mid] <= g) lo = mid; else hi = mid - 1;
