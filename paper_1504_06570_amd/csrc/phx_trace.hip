@@ -21,7 +21,10 @@ namespace phx {
 namespace {
 
 constexpr double kHcEvM = 1.2398419843320026e-6;  // h c / e in eV m
-constexpr double kNewtonTol = 1e-12;             // m
+// Newton stops once a step is at most 1e-9 m: convergence is quadratic, so the root is then
+// within about (|f''| / 2|f'|) x (1e-9 m)^2, far below a picometre (the paper's criterion is
+// 0.01 um).
+constexpr double kNewtonTol = 1e-9;              // m
 constexpr int kNewtonMax = 16;
 constexpr int kBlock = kThreads;
 constexpr int kTimeBuckets = kTimeBucketsMax;   // time buckets of the survivor sort
