@@ -324,34 +324,44 @@ __device__ __forceinline__ double wavelength(const DevParams& P, const DevSource
 
 // Pre-roll test (section 3.2): a photon is culled when a coated surface's roulette draw exceeds
 // the largest transmission that coating has at this wavelength for any angle, so it cannot
-// survive.  The coated surfaces are tested in order of decreasing selectivity; tests j0..j1-1
-// of that order.  preroll_draw gives the wavelength (and the time word) from the photon's first
-// Philox blocks.
-__device__ __forceinline__ double preroll_draw(const DevParams& P, const Rng& rng, int si,
-                                               uint32_t& w_time, uint32_t& w_radius) {
+// survive.  The coated surfaces are tested in order of decreasing selectivity.  preroll_draw
+// gives the wavelength (and the time and radius words) from the photon's first Philox blocks.
+__device__ __forceinline__ double preroll_draw(const DevParams& P, const Rng& rng,
+                                               const DevSource& src, uint32_t& w_time,
+                                               uint32_t& w_radius) {
     const uint4 w0 = rng.block(0);
     w_time = w0.z;
     w_radius = w0.x;
-    const DevSource& src = P.src[si];
     uint4 w1 = make_uint4(0, 0, 0, 0);
     if (src.sed >= 0) w1 = rng.block(1);
     return wavelength(P, src, w0, w1);
 }
 
-// Tests j0..j1-1 at wavelength column il.
-__device__ __forceinline__ bool preroll_tests(const DevParams& P, const Rng& rng, int il, int j0,
-                                              int j1) {
+__device__ __forceinline__ uint32_t word_of(const uint4& w, int m) {
+    return m == 0 ? w.x : (m == 1 ? w.y : (m == 2 ? w.z : w.w));
+}
+
+// The first (most selective) test, at wavelength column il.
+__device__ __forceinline__ bool preroll_first(const DevParams& P, const Rng& rng, int il) {
+    const int k = P.cull_order[0];
+    const uint32_t wk = word_of(rng.block(2 + (k >> 2)), k & 3);
+    return (int64_t)wk > P.coat_thr[(size_t)P.surf[k].coating * P.n_lam + il];
+}
+
+// Tests 1..n_tests-1 in order, stopping at the first that culls; a roulette block is drawn when
+// the next test's surface needs a different one.
+__device__ __forceinline__ bool preroll_rest(const DevParams& P, const Rng& rng, int il,
+                                             int n_tests) {
     int blk = -1;
     uint4 w = make_uint4(0, 0, 0, 0);
-    for (int j = j0; j < j1; ++j) {
+    for (int j = 1; j < n_tests; ++j) {
         const int k = P.cull_order[j];
         if (2 + (k >> 2) != blk) {
             blk = 2 + (k >> 2);
             w = rng.block(blk);
         }
-        const int m = k & 3;
-        const uint32_t wk = m == 0 ? w.x : (m == 1 ? w.y : (m == 2 ? w.z : w.w));
-        if ((int64_t)wk > P.coat_thr[(size_t)P.surf[k].coating * P.n_lam + il]) return true;
+        if ((int64_t)word_of(w, k & 3) > P.coat_thr[(size_t)P.surf[k].coating * P.n_lam + il])
+            return true;
     }
     return false;
 }
@@ -873,6 +883,9 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
     const DevParams& P = *Pg;
     const int lane = __lane_id();
     const int n_tests = P.n_cull;
+    // the chunk's one source, read once (the other case reads each photon's source record)
+    DevSource one_src{};
+    if constexpr (ONE) one_src = P.src[one_si];
     const uint64_t n_ranges = (len + kGenRange - 1) / kGenRange;
     for (uint64_t rg = blockIdx.x; rg < n_ranges; rg += gridDim.x) {   // workgroup-uniform
         const uint64_t r0 = rg * kGenRange;
@@ -900,7 +913,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 }
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
                 uint32_t wt, wr;
-                const double lam = preroll_draw(P, rng, si, wt, wr);
+                const double lam = preroll_draw(P, rng, ONE ? one_src : P.src[si], wt, wr);
                 // squared pupil radius as the sky stage samples it: outside the reachable annulus
                 // the photon is vignetted at the primary whatever the atmosphere does (the bounds
                 // carry a margin far above the rounding of the square root)
@@ -909,7 +922,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 const double rp2 = u01(wr) * (ro * ro - ri * ri) + ri * ri;
                 const int il = lambda_column(P, lam).il;
                 culled = rp2 < L.cull_r2_lo || rp2 > L.cull_r2_hi ||
-                         preroll_tests(P, rng, il, 0, min(n_tests, 1));
+                         (n_tests > 0 && preroll_first(P, rng, il));
                 pass = !culled;
                 if (culled) culled_event(L, g, si, idx, lam);
                 // time bucket of a survivor (the time stamp is t_e u01(wt))
@@ -946,7 +959,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 }
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
                 const int il = (int)((entry >> 18) & 0x1fffu);
-                culled = preroll_tests(P, rng, il, 1, n_tests);
+                culled = preroll_rest(P, rng, il, n_tests);
                 const uint32_t et = P.esc_thr && il >= P.esc_col0 ? P.esc_thr[il] : 0u;
                 bool later = false;
                 if (!culled && et && (L.flags & PHX_F_SILICON)) {
@@ -964,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                     if (key) key[r] = (uint8_t)((entry >> 12) & 0x3fu);
                 } else if ((L.flags & PHX_F_EVENTS) && (g % L.event_stride) == 0) {
                     uint32_t wt, wr;
-                    culled_event(L, g, si, idx, preroll_draw(P, rng, si, wt, wr));
+                    culled_event(L, g, si, idx, preroll_draw(P, rng, ONE ? one_src : P.src[si], wt, wr));
                 }
             }
             const uint64_t cm = __ballot(culled);
@@ -992,7 +1005,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                     }
                     const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
                     uint32_t wt, wr;
-                    const double lam = preroll_draw(P, rng, si, wt, wr);
+                    const double lam = preroll_draw(P, rng, ONE ? one_src : P.src[si], wt, wr);
                     culled = escape_certain(P, lam, rng.block(1).z);
                     if (!culled) {
                         atomicOr(&s_bits[rr >> 6], 1ull << (rr & 63));
