@@ -583,41 +583,57 @@ __device__ __forceinline__ void tape_put(double* tp, uint64_t ts, int k, const H
     t[6 * ts] = h.l;
 }
 
-// Central obscuration, the surfaces (sections 2.4.1-2.4.2), silicon (sections 2.4.2-2.4.3) and
-// the pixel, from the start-plane state.  With TAPE, every surface passage is recorded for the
-// adjoint sweep.
-template <bool ZERN, bool TAPE = false>
-__device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint64_t idx,
-                               const Front& f, double* tp = nullptr, uint64_t ts = 0) {
-    Outcome o;
+// A photon between surfaces, in the global frame: position, direction and the index of the
+// medium it travels in.
+struct Ray {
+    double p[3], n[3], n_cur;
+};
+
+// Per-photon constants of the optics stage: the glass index and the coating tables' wavelength
+// column at the photon's wavelength.
+struct Optics {
+    double lam, n_glass;
+    LamCol lc;
+};
+__device__ __forceinline__ Optics optics_of(const DevParams& P, const Launch& L, double lam) {
+    Optics c;
+    c.lam = lam;
+    c.n_glass = P.has_glass ? sellmeier(P, lam) : 1.0;
+    c.lc = (L.flags & PHX_F_COATINGS) && P.n_lam > 1 ? lambda_column(P, lam) : LamCol{0, 0.0};
+    return c;
+}
+
+__device__ __forceinline__ void outcome_init(Outcome& o, double lam) {
     o.status = PHX_MISSED; o.surface = -1; o.newton = 0; o.pix_i = -1; o.pix_j = -1;
     o.x = o.y = o.z = o.xe = o.ye = 0.0;
-    const double lam = f.lam;
     o.lam = lam;
-    const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
-    double p[3] = {f.p[0], f.p[1], f.p[2]};
-    double n[3] = {f.n[0], f.n[1], f.n[2]};
-    if (P.obsc_r > 0.0) {
-        const double l = (P.obsc_z - p[2]) / n[2];
-        const double x = p[0] + n[0] * l, y = p[1] + n[1] * l;
-        if (sqrt(x * x + y * y) < P.obsc_r) {
-            o.status = PHX_OBSCURED;
-            o.x = x; o.y = y; o.z = P.obsc_z;
-            return o;
-        }
-    }
-    const double n_glass = P.has_glass ? sellmeier(P, lam) : 1.0;
-    const LamCol lc = (L.flags & PHX_F_COATINGS) && P.n_lam > 1 ? lambda_column(P, lam)
-                                                               : LamCol{0, 0.0};
-    double n_cur = 1.0;
-    uint4 wc = make_uint4(0, 0, 0, 0);
-    int wc_block = -1;
+}
+
+// Central obscuration (section 2.4.1): true, with the outcome filled, if the ray meets it.
+__device__ __forceinline__ bool obscured(const DevParams& P, const Ray& ray, Outcome& o) {
+    if (!(P.obsc_r > 0.0)) return false;
+    const double l = (P.obsc_z - ray.p[2]) / ray.n[2];
+    const double x = ray.p[0] + ray.n[0] * l, y = ray.p[1] + ray.n[1] * l;
+    if (!(sqrt(x * x + y * y) < P.obsc_r)) return false;
+    o.status = PHX_OBSCURED;
+    o.x = x; o.y = y; o.z = P.obsc_z;
+    return true;
+}
+
+// Surfaces k0..k1-1 before the detector (sections 2.4.1-2.4.2): returns true while the photon
+// lives, else fills the outcome.  wc / wc_block cache the roulette block of the last coated
+// surface (wc_block = -1: none).
+template <bool ZERN, bool TAPE = false>
+__device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch& L, const Rng& rng,
+                                               const Optics& oc, Ray& ray, int k0, int k1,
+                                               uint4& wc, int& wc_block, Outcome& o,
+                                               double* tp = nullptr, uint64_t ts = 0) {
     Hit h;
-    const int kdet = P.n_surf - 1;
 #pragma unroll 1
-    for (int k = 0; k < kdet; ++k) {
+    for (int k = k0; k < k1; ++k) {
         const DevSurface& s = P.surf[k];
-        int st = hit_surface<ZERN, TAPE>(P, L, rng, k, p, n, lc, wc, wc_block, h, o.newton);
+        int st = hit_surface<ZERN, TAPE>(P, L, rng, k, ray.p, ray.n, oc.lc, wc, wc_block, h,
+                                         o.newton);
         if (st == 0) {
             if (TAPE) tape_put(tp, ts, k, h);
             if (s.kind == PHX_MIRROR) {
@@ -626,39 +642,53 @@ __device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint
                 h.d[1] -= 2.0 * h.dn * h.N[1];
                 h.d[2] -= 2.0 * h.dn * h.N[2];
             } else {
-                const double n2 = s.medium == PHX_GLASS ? n_glass : 1.0;
-                if (refract(h, n_cur / n2)) n_cur = n2; else st = PHX_TIR;
+                const double n2 = s.medium == PHX_GLASS ? oc.n_glass : 1.0;
+                if (refract(h, ray.n_cur / n2)) ray.n_cur = n2; else st = PHX_TIR;
             }
         }
         if (st != 0) {
             o.status = st; o.surface = k; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
-            return o;
+            return false;
         }
         if (s.moved) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] + s.t[i];
-                n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
+                ray.p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] +
+                           s.t[i];
+                ray.n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
             }
         } else {
-            p[0] = h.q[0]; p[1] = h.q[1]; p[2] = h.q[2] + s.t[2];
-            n[0] = h.d[0]; n[1] = h.d[1]; n[2] = h.d[2];
+            ray.p[0] = h.q[0]; ray.p[1] = h.q[1]; ray.p[2] = h.q[2] + s.t[2];
+            ray.n[0] = h.d[0]; ray.n[1] = h.d[1]; ray.n[2] = h.d[2];
         }
     }
-    // the detector surface: refraction into silicon, conversion, diffusion, pixel
-    int st = hit_surface<ZERN, TAPE>(P, L, rng, kdet, p, n, lc, wc, wc_block, h, o.newton);
+    return true;
+}
+
+// The detector surface: refraction into silicon, conversion, diffusion and the pixel (sections
+// 2.4.2-2.4.3); fills the outcome.
+template <bool ZERN, bool TAPE = false>
+__device__ __forceinline__ void finish_detector(const DevParams& P, const Launch& L,
+                                                const Rng& rng, const Optics& oc, Ray& ray,
+                                                uint4& wc, int& wc_block, Outcome& o,
+                                                double* tp = nullptr, uint64_t ts = 0) {
+    const int kdet = P.n_surf - 1;
+    Hit h;
+    int st = hit_surface<ZERN, TAPE>(P, L, rng, kdet, ray.p, ray.n, oc.lc, wc, wc_block, h,
+                                     o.newton);
     if (TAPE && st == 0) tape_put(tp, ts, kdet, h);
-    if (st == 0 && (L.flags & PHX_F_SILICON) && !refract(h, n_cur / n_silicon(lam))) st = PHX_TIR;
+    if (st == 0 && (L.flags & PHX_F_SILICON) && !refract(h, ray.n_cur / n_silicon(oc.lam)))
+        st = PHX_TIR;
     o.surface = kdet;
     o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
     if (st != 0) {
         o.status = st;
-        return o;
+        return;
     }
     double xc = h.q[0], yc = h.q[1];
-    if (sensor_stage(P, L, rng, lam, h.d, xc, yc)) {
+    if (sensor_stage(P, L, rng, oc.lam, h.d, xc, yc)) {
         o.status = PHX_ESCAPED;
-        return o;
+        return;
     }
     o.xe = xc; o.ye = yc;
     // pixel quantisation (section 2.4.3)
@@ -670,6 +700,25 @@ __device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint
         o.pix_i = (int)ix;
         o.pix_j = (int)iy;
     }
+}
+
+// Central obscuration, the surfaces (sections 2.4.1-2.4.2), silicon (sections 2.4.2-2.4.3) and
+// the pixel, from the start-plane state.  With TAPE, every surface passage is recorded for the
+// adjoint sweep.
+template <bool ZERN, bool TAPE = false>
+__device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint64_t idx,
+                               const Front& f, double* tp = nullptr, uint64_t ts = 0) {
+    Outcome o;
+    outcome_init(o, f.lam);
+    const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+    Ray ray{{f.p[0], f.p[1], f.p[2]}, {f.n[0], f.n[1], f.n[2]}, 1.0};
+    if (obscured(P, ray, o)) return o;
+    const Optics oc = optics_of(P, L, f.lam);
+    uint4 wc = make_uint4(0, 0, 0, 0);
+    int wc_block = -1;
+    if (!trace_surfaces<ZERN, TAPE>(P, L, rng, oc, ray, 0, P.n_surf - 1, wc, wc_block, o, tp, ts))
+        return o;
+    finish_detector<ZERN, TAPE>(P, L, rng, oc, ray, wc, wc_block, o, tp, ts);
     return o;
 }
 
@@ -1261,74 +1310,166 @@ __global__ __launch_bounds__(kBlock) void front_kernel(const DevParams* __restri
     }
 }
 
-// Back half: optics, silicon, pixel and book-keeping, from the start-plane state.
-// Pixel counts go through a per-workgroup LDS window of kWin x kWin pixels placed at the first
-// detected pixel the workgroup sees (a star's image core), flushed to the image once at the end;
-// pixels outside the window take wavefront-aggregated global atomics.
-constexpr int kWin = 64;
+// Book-keeping of finished photons, one per lane where act (every lane of the wavefront calls
+// it): the event record, the pixel (through the workgroup's LDS window of win x win pixels placed
+// at the first detection, else a wavefront-aggregated global atomic), the status count and the
+// moment words.
+__device__ __forceinline__ void book(const DevParams& P, const Launch& L, bool act, uint64_t g,
+                                     int si, uint64_t idx, const Outcome& o, uint32_t* s_stats,
+                                     uint32_t* s_win, int win, int* s_org, MomentCache* s_mc) {
+    int pix = -1, slot = 0;
+    bool m_on = false;
+    if (act) {
+        m_on = (L.flags & PHX_F_MOMENTS) && o.status <= PHX_OFF_CHIP;
+        slot = stat_slot(o);
+        if (account(P, L, g, si, idx, o) >= 0) {
+            int org = *s_org;
+            if (org < 0) {
+                const int want = (max(o.pix_i - win / 2, 0) << 16) | max(o.pix_j - win / 2, 0);
+                const int prev = atomicCAS(s_org, -1, want);
+                org = prev < 0 ? want : prev;
+            }
+            const int wi = o.pix_i - (org >> 16), wj = o.pix_j - (org & 0xffff);
+            if (wi >= 0 && wi < win && wj >= 0 && wj < win)
+                atomicAdd(&s_win[wj * win + wi], 1u);
+            else
+                pix = o.pix_j * P.nx + o.pix_i;
+        }
+    }
+    bin_photon(L.image, pix, pix >= 0);
+    count_stat(s_stats, slot, act);
+    if (L.flags & PHX_F_MOMENTS) add_moments(L, si, o.xe, o.ye, m_on, s_mc);
+}
+
+// Back half, the optics stage with refill (sections 2.4.1-2.4.3), from the start-plane state:
+// each wavefront takes 64 photons at a time
+// through the central obscuration and the first surface, queues the survivors in LDS, and runs
+// the rest of the optics, the silicon and the pixel on 64 queued photons at a time, so lanes
+// whose photon was vignetted or absorbed at the first surface are refilled instead of idling
+// through the remaining surfaces.  Work units of 64 photons: static (unit w of the grid's
+// wavefronts, then every grid-size-th unit) or from a device counter.
+constexpr int kWin = 32;                  // LDS pixel window of the optics kernel
+constexpr int kQueue = 128;               // queued photons per wavefront (64 + 63 carried)
+constexpr int kWaves = kBlock / 64;
 template <bool ZERN>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void back_kernel(const DevParams* __restrict__ Pg,
-                                                      const Launch L, uint64_t begin,
-                                                      const uint32_t* __restrict__ surv,
-                                                      const unsigned int* __restrict__ count,
-                                                      uint64_t n_all, const double* __restrict__ st,
-                                                      uint64_t st_stride,
-                                                      unsigned long long* tile_ctr) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void back_kernel(
+        const DevParams* __restrict__ Pg, const Launch L, uint64_t begin,
+        const uint32_t* __restrict__ surv, const unsigned int* __restrict__ count, uint64_t n_all,
+        const double* __restrict__ st, uint64_t st_stride, unsigned long long* unit_ctr) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
     __shared__ uint32_t s_win[kWin * kWin];
-    __shared__ unsigned long long s_tile;
     __shared__ int s_org;   // window origin: (i0 << 16) | j0, or -1 before the first detection
     __shared__ MomentCache s_mc;
+    __shared__ double s_q[kWaves][7][kQueue];   // p, n (global frame) and wavelength
+    __shared__ uint32_t s_qr[kWaves][kQueue];   // position in the survivor list
+    __shared__ int32_t s_qk[kWaves][kQueue];    // Newton steps so far << 1 | travelling in glass
     for (int i = threadIdx.x; i < kWin * kWin; i += blockDim.x) s_win[i] = 0;
     if (threadIdx.x == 0) s_org = -1;
     moment_cache_init(&s_mc);
-    stats_init(s_stats);
+    stats_init(s_stats);   // ends with a barrier
     const DevParams& P = *Pg;
     const uint64_t n = surv ? (uint64_t)*count : n_all;
-    Tiles T{tile_ctr, blockIdx.x, 0, n};
+    const int wave = threadIdx.x >> 6, lane = __lane_id();
+    double (*q)[kQueue] = s_q[wave];
+    uint32_t* qr = s_qr[wave];
+    int32_t* qk = s_qk[wave];
+    const uint64_t n_units = (n + 63) / 64;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
+    uint64_t unit = (uint64_t)blockIdx.x * kWaves + wave;
+    if (unit_ctr) {
+        unsigned long long u = 0;
+        if (lane == 0) u = atomicAdd(unit_ctr, 1ull);
+        unit = __shfl(u, 0);
+    }
+    const int kdet = P.n_surf - 1;
+    const int k_first = kdet < 1 ? kdet : 1;   // surfaces of the first pass: [0, k_first)
+    int qn = 0;                                // queued photons (wavefront-uniform)
     uint32_t newton = 0, traced = 0;
-    while (T.next(&s_tile)) {   // block-uniform: every lane takes part in the wavefront ballots
-        const uint64_t r = T.index();
-        int pix = -1;
-        int m_si = 0, slot = 0;
-        double m_x = 0.0, m_y = 0.0;
-        bool m_on = false;
-        if (r < n) {
-            const uint64_t g = begin + (surv ? (uint64_t)surv[r] : r);
-            int si;
-            uint64_t idx;
-            decode(L, g, si, idx);
-            Front f;
-            f.p[0] = st[0 * st_stride + r];
-            f.p[1] = st[1 * st_stride + r];
-            f.p[2] = st[2 * st_stride + r];
-            f.n[0] = st[3 * st_stride + r];
-            f.n[1] = st[4 * st_stride + r];
-            f.n[2] = st[5 * st_stride + r];
-            f.lam = st[6 * st_stride + r];
-            const Outcome o = photon_back<ZERN>(P, L, si, idx, f);
-            newton += o.newton;
-            traced += 1;
-            m_si = si; m_x = o.xe; m_y = o.ye;
-            m_on = (L.flags & PHX_F_MOMENTS) && o.status <= PHX_OFF_CHIP;
-            slot = stat_slot(o);
-            if (account(P, L, g, si, idx, o) >= 0) {
-                int org = s_org;
-                if (org < 0) {
-                    const int want = (max(o.pix_i - kWin / 2, 0) << 16) | max(o.pix_j - kWin / 2, 0);
-                    const int prev = atomicCAS(&s_org, -1, want);
-                    org = prev < 0 ? want : prev;
-                }
-                const int wi = o.pix_i - (org >> 16), wj = o.pix_j - (org & 0xffff);
-                if (wi >= 0 && wi < kWin && wj >= 0 && wj < kWin)
-                    atomicAdd(&s_win[wj * kWin + wi], 1u);
-                else
-                    pix = o.pix_j * P.nx + o.pix_i;
+    for (;;) {
+        const bool more = unit < n_units;
+        if (qn >= 64 || (!more && qn > 0)) {
+            // second pass: up to 64 queued photons through the remaining surfaces
+            const int take = qn < 64 ? qn : 64;
+            const bool act = lane < take;
+            Outcome o;
+            outcome_init(o, 0.0);
+            uint64_t g = 0, idx = 0;
+            int si = 0;
+            if (act) {
+                const int e = qn - take + lane;
+                const uint32_t r = qr[e];
+                const int32_t kq = qk[e];
+                g = begin + (surv ? (uint64_t)surv[r] : (uint64_t)r);
+                decode(L, g, si, idx);
+                const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                const double lam = q[6][e];
+                outcome_init(o, lam);
+                o.newton = kq >> 1;
+                const Optics oc = optics_of(P, L, lam);
+                Ray ray{{q[0][e], q[1][e], q[2][e]}, {q[3][e], q[4][e], q[5][e]},
+                        (kq & 1) ? oc.n_glass : 1.0};
+                uint4 wc = make_uint4(0, 0, 0, 0);
+                int wc_block = -1;
+                if (trace_surfaces<ZERN>(P, L, rng, oc, ray, k_first, kdet, wc, wc_block, o))
+                    finish_detector<ZERN>(P, L, rng, oc, ray, wc, wc_block, o);
+                newton += o.newton;
             }
+            book(P, L, act, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
+            qn -= take;
+            __builtin_amdgcn_wave_barrier();
+            continue;
         }
-        bin_photon(L.image, pix, pix >= 0);
-        count_stat(s_stats, slot, r < n);
-        if (L.flags & PHX_F_MOMENTS) add_moments(L, m_si, m_x, m_y, m_on, &s_mc);
+        if (!more) break;
+        // first pass: the next 64 photons through the central obscuration and the first surface
+        const uint64_t r = unit * 64 + lane;
+        const bool valid = r < n;
+        bool alive = false;
+        Outcome o;
+        outcome_init(o, 0.0);
+        uint64_t g = 0, idx = 0;
+        int si = 0;
+        Ray ray{{0.0, 0.0, 0.0}, {0.0, 0.0, 1.0}, 1.0};
+        if (valid) {
+            g = begin + (surv ? (uint64_t)surv[r] : r);
+            decode(L, g, si, idx);
+            const double lam = st[6 * st_stride + r];
+            outcome_init(o, lam);
+            ray.p[0] = st[0 * st_stride + r];
+            ray.p[1] = st[1 * st_stride + r];
+            ray.p[2] = st[2 * st_stride + r];
+            ray.n[0] = st[3 * st_stride + r];
+            ray.n[1] = st[4 * st_stride + r];
+            ray.n[2] = st[5 * st_stride + r];
+            if (!obscured(P, ray, o)) {
+                const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                const Optics oc = optics_of(P, L, lam);
+                uint4 wc = make_uint4(0, 0, 0, 0);
+                int wc_block = -1;
+                alive = trace_surfaces<ZERN>(P, L, rng, oc, ray, 0, k_first, wc, wc_block, o);
+            }
+            traced += 1;
+        }
+        const uint64_t am = __ballot(alive);
+        if (alive) {
+            const int e = qn + __popcll(am & ((1ull << lane) - 1ull));
+            q[0][e] = ray.p[0]; q[1][e] = ray.p[1]; q[2][e] = ray.p[2];
+            q[3][e] = ray.n[0]; q[4][e] = ray.n[1]; q[5][e] = ray.n[2];
+            q[6][e] = o.lam;
+            qr[e] = (uint32_t)r;
+            qk[e] = (o.newton << 1) | (ray.n_cur != 1.0 ? 1 : 0);
+        }
+        qn += __popcll(am);
+        const bool done = valid && !alive;
+        if (done) newton += o.newton;
+        book(P, L, done, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
+        if (unit_ctr) {
+            unsigned long long u = 0;
+            if (lane == 0) u = atomicAdd(unit_ctr, 1ull);
+            unit = __shfl(u, 0);
+        } else {
+            unit += n_waves;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     stats_flush(L, s_stats, newton, traced);   // ends with a barrier
     if (threadIdx.x == 0 && (L.flags & PHX_F_MOMENTS)) moment_cache_flush(L, &s_mc);
