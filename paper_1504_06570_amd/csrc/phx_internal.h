@@ -152,9 +152,9 @@ inline uint64_t compact_groups(uint64_t n) { return ((n + 63) / 64 + 4095) / 409
 // sky and optics stages (static grid-stride, or tiles of kTileIters x 256 photons taken from a
 // device counter).
 struct LaunchConfig {
-    int generate_per_cu = 8;
-    int front_per_cu = 32;
-    int back_per_cu = 4;
+    int generate_per_cu = 16;
+    int front_per_cu = 64;
+    int back_per_cu = 3;
     int dynamic = 0;
     int pipeline = 1;
 };
