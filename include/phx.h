@@ -254,10 +254,9 @@ phx_status phx_trace(phx_ctx ctx, const phx_trace_args* args, void* stream);
  * *_blocks_per_cu: workgroups of 256 lanes per compute unit for the pre-roll, sky+atmosphere and
  * optics kernels (1..64); dynamic_tiles: 0 = static grid-stride, 1 = the sky kernel claims tiles of
  * 2048 photons and each optics wavefront units of 64 from device counters; pipeline: 1 = each
- * chunk's optics stage runs
- * on a context-owned second stream, overlapping the next chunk's pre-roll and sky stage (ordered
- * by events; the caller's stream waits for the last optics stage), 0 = everything on the caller's
- * stream.  Launches captured by phx_trace_batched always run on the capturing stream.
+ * chunk's pre-roll and optics stages run on a context-owned second stream, overlapping the sky
+ * stage of the chunk between them (ordered by events; the caller's stream waits for the last
+ * optics stage), 0 = everything on the caller's stream.  Launches captured by phx_trace_batched always run on the capturing stream.
  * Defaults: 26, 16, 64, 3, 0, 1. */
 typedef struct {
     int32_t chunk_log2;
