@@ -142,3 +142,29 @@ def test_source_aligned_chunks_match(phx):
     assert int(ref.sum()) > 0 and int(ref_m[10:15, 0].min()) > 0
     assert torch.equal(img, ref) and torch.equal(st, ref_st) and torch.equal(m, ref_m)
     tr.close()
+
+
+def test_zero_count_sources_and_events(phx):
+    """Sources without photons between others (the decode's guide must skip them), one launch
+    against per-source launches, with event records checked photon by photon."""
+    import torch
+    s = C.batched(scale=1e-2, screen_n=256, n_src=64)
+    counts = s.sources.n_photons.copy()
+    counts[1::3] = 0
+    counts[-1] = 0
+    s.sources.n_photons[:] = counts
+    tr = phx.Tracer(s)
+    ref = tr.new_image()
+    for k in range(len(s.sources)):
+        if counts[k]:
+            tr.trace(ref, src_begin=k, src_end=k + 1)
+    img, _, _, ev = tr.trace(event_stride=1)
+    torch.cuda.synchronize()
+    assert int(ref.sum()) > 0 and torch.equal(img, ref)
+    e = phx.events_to_numpy(ev)
+    assert len(e) == int(counts.sum())
+    expect = np.repeat(np.arange(len(counts)), counts.astype(np.int64))
+    assert np.array_equal(e["source"], expect)
+    first = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+    assert np.array_equal(e["photon"].astype(np.int64), np.arange(len(e)) - first[expect])
+    tr.close()
