@@ -964,11 +964,13 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
     }
     chunk = std::min<uint64_t>(c->ws_chunk, max_chunk);
     // Chunk plan.  With the atmosphere every chunk has its survivors sorted by time (screen
-    // locality; a chunk of many sources keeps their order within a time bucket); launches of big
-    // sources are cut at source boundaries, launches of many small sources evenly.
+    // locality; a chunk of many sources keeps their order within a time bucket); traces of big
+    // sources are cut at source boundaries, traces of many small sources and adjoints evenly.
     c->plan.clear();
     const bool atm = (a->flags & PHX_F_ATMOSPHERE) != 0;
-    const bool per_source = atm && L.n_src > 1 && L.total / (uint64_t)L.n_src >= chunk / 8;
+    // (the adjoint cuts evenly: its optics kernel is the heavy stage and wants few, full chunks)
+    const bool per_source = need_image && atm && L.n_src > 1 &&
+                            L.total / (uint64_t)L.n_src >= chunk / 8;
     if (per_source) {
         uint64_t start = 0;
         for (int s = 0; s < L.n_src; ++s) {
