@@ -227,3 +227,19 @@ def test_escape_preroll_culls_only_certain_escapes(phx):
     for f in ("status", "surface", "pix_i", "pix_j", "x", "y", "xe", "ye"):
         assert np.array_equal(a[f][keep], b[f][keep]), f
     tr.close()
+
+
+def test_photon_index_crossing_32_bits(phx):
+    """Photon indices around 2^32 (the Philox counter's high word turns over): GPU and oracle
+    agree photon by photon, with the pre-roll and the atmosphere on."""
+    s = C.full(scale=2e-4, screen_n=128)
+    begin = (1 << 32) - 3000
+    flags = int(s.physics) | phx.F_CULL
+    gev, gimg, oev, oimg, _ = run_both(phx, s, flags=flags, photon_count=6000, photon_begin=begin)
+    assert gev["photon"].min() == begin and gev["photon"].max() == begin + 5999
+    g, o = parity.match(gev, oev)
+    culled = g["status"] == phx.CULLED
+    assert 0 < culled.sum() < len(g)
+    rep = parity.compare(g[~culled], o[~culled])
+    assert rep["boundary_frac"] < 1e-5
+    assert not np.isin(o["status"][culled], [phx.DETECTED, phx.OFF_CHIP]).any()
