@@ -893,12 +893,14 @@ __device__ __forceinline__ void stats_flush(const Launch& L, uint32_t* s_stats, 
 // ranges of kGenRange photons.  Stage one draws every photon's wavelength and pupil radius, drops
 // photons whose pupil sample cannot reach the primary's aperture (the annulus is sampled wider
 // than the aperture to leave room for atmospheric displacement, which the host bounds) and
-// applies the most selective coating test; its survivors are queued in LDS and stage two applies
-// the remaining tests to them densely, so the many photons that fail the first test cost one
-// test.  The
-// survivors' bits are set in an LDS copy of the range's bitmap words, written out once (the
-// bitmap does not depend on the order of the queue), with each survivor's time bucket when
-// requested.  An ordered compaction then lists the survivors.
+// applies the most selective coating test; its survivors are queued in LDS (offset, time bucket,
+// wavelength column) and stage two applies the remaining tests to them densely, so the many
+// photons that fail the first test cost one test.  Stage two also flags the photons whose
+// conversion word passes the escape filter, and stage three (only when any is flagged) runs the
+// exact escape test on them out of the main loops' register budget.  The survivors' bits are set
+// in an LDS copy of the range's bitmap words, written out once (the bitmap does not depend on the
+// order of the queue), with each survivor's time bucket when requested.  An ordered compaction
+// or the time-bucket sort then lists the survivors.
 constexpr int kGenIters = 16;
 constexpr int kGenRange = kBlock * kGenIters;   // photons per range (64 bitmap words)
 static_assert(kGenRange <= 4096, "range offsets are queued in twelve bits");
