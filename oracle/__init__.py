@@ -20,8 +20,9 @@ CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
 
 MAX_SURF, MAX_LAYERS, MAX_SCALES, N_THETA = 16, 8, 4, 22
 STATUS = ["DETECTED", "OFF_CHIP", "VIGNETTED", "ABSORBED", "MISSED", "NONCONV", "TIR",
-          "ESCAPED", "OBSCURED"]
+          "ESCAPED", "OBSCURED", "CULLED", "EXTINCT", "DEAD"]
 DETECTED, OFF_CHIP, VIGNETTED, ABSORBED, MISSED, NONCONV, TIR, ESCAPED, OBSCURED = range(9)
+EXTINCT, DEAD = 10, 11
 
 
 def build() -> str:
@@ -45,6 +46,17 @@ class Source(C.Structure):
                 ("sersic_b", C.c_double), ("sersic_pa", C.c_double), ("n_photons", C.c_uint64)]
 
 
+class Extra(C.Structure):
+    _fields_ = [("zenith", C.c_double), ("zenith_pa", C.c_double), ("tau0", C.c_double),
+                ("gamma", C.c_double), ("pressure", C.c_double), ("water", C.c_double),
+                ("temperature", C.c_double), ("lam0", C.c_double), ("dome_sigma", C.c_double),
+                ("halo_f", C.c_double), ("halo_n", C.c_double), ("halo_r0", C.c_double),
+                ("halo_max", C.c_double), ("dead", C.c_double), ("vanes", C.c_int32),
+                ("pad", C.c_int32), ("vane_angle", C.c_double), ("vane_width", C.c_double),
+                ("vane_r_in", C.c_double), ("vane_r_out", C.c_double), ("vane_z_lo", C.c_double),
+                ("vane_z_hi", C.c_double)]
+
+
 class Scene(C.Structure):
     _fields_ = [
         ("n_surf", C.c_int32), ("physics", C.c_int32), ("surf", Surface * MAX_SURF),
@@ -65,6 +77,7 @@ class Scene(C.Structure):
         ("src", C.POINTER(Source)), ("sed_edges", C.POINTER(C.c_double)),
         ("sed_flux", C.POINTER(C.c_double)),
         ("seed", C.c_uint32), ("pad3", C.c_int32), ("exposure", C.c_double),
+        ("ex", Extra),
         ("grad", C.POINTER(C.c_float)), ("sed_cdf", C.POINTER(C.c_double)),
         ("rot", ((C.c_double * 3) * 3) * MAX_SURF), ("trans", (C.c_double * 3) * MAX_SURF),
     ]
@@ -121,6 +134,11 @@ def lib():
             L.orc_gamma.argtypes = [C.c_uint32, C.c_int32, C.c_uint64, C.c_double,
                                     C.POINTER(C.c_double)]
             L.orc_gamma.restype = C.c_int
+            L.orc_air_refractivity.argtypes = [C.c_double] * 4
+            L.orc_air_refractivity.restype = C.c_double
+            L.orc_halo_sample.argtypes = [C.c_uint32, C.c_int32, C.c_uint64, C.c_double,
+                                          C.c_double, C.POINTER(C.c_double)]
+            L.orc_halo_sample.restype = C.c_int
             L.orc_jacobian.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_uint64,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32)]
@@ -212,6 +230,11 @@ class Oracle:
             sc.sed_flux = f.ctypes.data_as(C.POINTER(C.c_double))
         sc.seed = int(scene.seed) & 0xFFFFFFFF
         sc.exposure = scene.exposure
+        x = getattr(scene, "extras", None)
+        if x is not None:
+            for name, _ in Extra._fields_:
+                if name != "pad":
+                    setattr(sc.ex, name, getattr(x, name))
         self.sc = sc
         self.scene = scene
         if L.orc_prepare(C.byref(sc)) != 0:
@@ -336,6 +359,19 @@ class Oracle:
         gx, gy = C.c_double(), C.c_double()
         lib().orc_screen_gradient(C.byref(self.sc), layer, scale, x, y, C.byref(gx), C.byref(gy))
         return gx.value, gy.value
+
+
+def air_refractivity(lam, pressure, temperature, water):
+    """n - 1 of air (the Filippenko formula); lam in metres, pressures in mmHg, T in deg C."""
+    return lib().orc_air_refractivity(lam, pressure, temperature, water)
+
+
+def halo_sample(seed, src, photon, n, x_max):
+    """(x, trial) of the halo sampler for one photon; trial = -1 when every trial was rejected."""
+    x = C.c_double()
+    t = lib().orc_halo_sample(int(seed) & 0xFFFFFFFF, int(src), int(photon), n, x_max,
+                              C.byref(x))
+    return x.value, t
 
 
 def image_from_events(ev, shape):

@@ -12,14 +12,21 @@
  *   block 1: wavelength blur within an SED bin, Sersic angle, silicon conversion length, (spare)
  *   blocks 2..5: coating roulette for surfaces 4(b-2) .. 4(b-2)+3
  *   block 6: diffusion Box-Muller pair, (spare, spare)
+ *   block 7: aerosol extinction, halo selection, halo azimuth, spider diffraction sign
+ *   block 8: dome-seeing Box-Muller pair, (spare, spare)
  * Stream 1, block t: Sersic Gamma sampler trial t (normal pair words 0-1, acceptance word 2).
+ * Stream 2, block t: micro-roughness halo trial t (proposal word 0, acceptance word 1).
  *
  * Parity pins (tests/test_oracle_*.py): Philox vs an independent implementation (rocRAND, compiled
  * on the host); uniform conversion exhaustive bounds; pupil density; Sersic radius median and
  * Gamma law; paraboloid focus; ellipsoid foci; Cassegrain focus; Snell invariants and the tilted
  * plate shift; Sellmeier and silicon index values; Rajkanan absorption against published silicon
  * data (order of magnitude); Zernike orthonormality; screen deflection closed forms; coating
- * roulette binomial; conversion depth exponential law; diffusion normal law; photometry integral.
+ * roulette binomial; conversion depth exponential law; diffusion normal law; photometry integral;
+ * air refractivity against standard-air values and its pressure, temperature and water laws;
+ * dispersion image shift; aerosol survival exp(-tau sec z); dome-seeing normal law; halo radius
+ * against the incomplete-beta CDF; spider shadow area and the lambda / (4 pi d) kick; dead-layer
+ * fraction 1 - exp(-alpha t).
  */
 #include "phx_oracle.h"
 
@@ -469,6 +476,157 @@ int orc_gamma(uint32_t seed, int32_t src, uint64_t photon, double shape, double*
     return gamma_sample(seed, src, photon, shape, out, NULL);
 }
 
+static void renormalise(double n[3]) {
+    double m = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    n[0] /= m; n[1] /= m; n[2] /= m;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Per-photon physics beyond the core path.                                                    */
+
+/* Refractivity n - 1 of air (section 2.3.2, the Filippenko formula): lambda in metres (the
+ * formula takes micrometres), pressure P and water-vapour pressure W in mmHg, temperature T in
+ * deg C.  Reading: the printed water term ends in a division by W, which would make the term grow
+ * without bound in dry air; it is taken as a product with W (humid air is less refractive).
+ * Pinned: the refractivity of dry air at 15 C, 760 mmHg near the sodium D line, the 0 C value,
+ * pressure scaling and the sign and size of the water term. */
+double orc_air_refractivity(double lambda_m, double P, double T, double W) {
+    double lam_um = lambda_m * 1e6;
+    double s2 = 1.0 / (lam_um * lam_um);
+    double dry = 64.328 + 29498.1 / (146.0 - s2) + 255.4 / (41.0 - s2);
+    double pt = P * (1.0 + (1.049 - 0.0157 * T) * 1e-6 * P) / (720.883 * (1.0 + 0.003661 * T));
+    double wet = (0.0624 - 0.000680 * s2) / (1.0 + 0.003661 * T) * W;
+    return 1e-6 * (dry * pt - wet);
+}
+
+/* Micro-roughness halo radius (section 2.4.2): the scattered light has surface brightness
+ * 1/(1 + (r/r0)^n) on the sky, so x = r/r0 has density proportional to x/(1 + x^n) (per unit x),
+ * here truncated at x_max (reading: the paper does not bound the angle; a bound keeps kicks
+ * physical).  Reading: the paper names no sampler.  Rejection from the proposal density
+ * proportional to x (1 + x^2)^(-n/2), whose CDF 1 - (1 + x^2)^(1 - n/2) inverts in closed form;
+ * the ratio (1 + x^2)^(n/2) / (1 + x^n) never exceeds its value 2^(n/2 - 1) at x = 1 (power-mean
+ * inequality, n >= 2), so a proposal x is kept when u < ratio / 2^(n/2 - 1).  Trial t reads stream
+ * 2, block t (proposal word 0, acceptance word 1); after 32 rejected trials the photon is not
+ * scattered (returns -1).  Requires 2 < n <= 6.  Pinned: Kolmogorov-Smirnov against the exact
+ * CDF (n = 4: (2/pi) atan(x^2); any n: the regularised incomplete beta I_s(2/n, 1 - 2/n) with
+ * s = x^n / (1 + x^n)). */
+static int halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, double x_max,
+                       double* x_out, double* margin) {
+    double dummy = 1e300;
+    if (!margin) margin = &dummy;
+    double e = 1.0 - 0.5 * n; /* < 0 */
+    double Fq = 1.0 - pow(1.0 + x_max * x_max, e);
+    double M = pow(2.0, 0.5 * n - 1.0);
+    for (uint32_t t = 0; t < 32; ++t) {
+        uint32_t ctr[4] = {(uint32_t)photon, (uint32_t)(photon >> 32), t, 2u};
+        uint32_t key[2] = {seed, (uint32_t)src};
+        uint32_t w[4];
+        orc_philox(ctr, key, w);
+        double v = orc_u01(w[0]), u = orc_u01(w[1]);
+        /* (1 + x^2)^e = 1 - v Fq */
+        double x = sqrt(pow(1.0 - v * Fq, 1.0 / e) - 1.0);
+        double ratio = pow(1.0 + x * x, 0.5 * n) / (1.0 + pow(x, n));
+        note_margin(margin, u - ratio / M);
+        if (u < ratio / M) {
+            *x_out = x;
+            return (int)t;
+        }
+    }
+    *x_out = 0.0;
+    return -1;
+}
+
+int orc_halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, double x_max,
+                    double* x_out) {
+    return halo_sample(seed, src, photon, n, x_max, x_out, NULL);
+}
+
+/* Spider (section 2.4.1: rectangular volumes; section 2.4.2: edge diffraction after Freniere et
+ * al.).  Vane k is the box u in [r_in, r_out], |v| <= w/2, z in [z_lo, z_hi] in the frame of the
+ * unit vectors u = (cos a_k, sin a_k, 0), v = (-sin a_k, cos a_k, 0), a_k = a_0 + 2 pi k / vanes.
+ * Returns 1 if the incoming ray meets a vane (q = the entry point).  Otherwise d is the smallest
+ * distance between the ray's line and a long edge of any vane (the four segments along u at
+ * v = +-w/2, z = z_lo or z_hi; for a segment, the distance of the line to its nearest point), the
+ * ray moves to the vanes' mid-height and turns by lambda / (4 pi d) across the nearest vane,
+ * along +v or -v by the sign word.  Readings: only the incoming pass is tested (as for the central
+ * obscuration); the deflection is perpendicular to the edge in the horizontal plane with a random
+ * sign (the spread of the uncertainty-principle picture), added to (n_x, n_y) with
+ * renormalisation like the other kicks; d is floored at lambda (the formula diverges at the
+ * edge).  Pinned: the shadowed fraction of a vertical beam against the vanes' exact area inside
+ * the annulus; the focal-plane offset against lambda / (4 pi d) for vertical rays. */
+static int spider(const orc_scene* sc, double p[3], double n[3], double lam, double u_sign,
+                  double q[3], double* margin) {
+    const orc_extra* x = &sc->ex;
+    double hw = 0.5 * x->vane_width;
+    double best = INFINITY, second = INFINITY, dk[8];
+    int best_k = -1;
+    for (int k = 0; k < x->vanes; ++k) {
+        dk[k] = INFINITY;
+        double a = x->vane_angle + TWO_PI * k / x->vanes;
+        double U[3] = {cos(a), sin(a), 0.0}, V[3] = {-sin(a), cos(a), 0.0};
+        /* ray in the vane frame */
+        double pu = p[0] * U[0] + p[1] * U[1], pv = p[0] * V[0] + p[1] * V[1], pz = p[2];
+        double nu = n[0] * U[0] + n[1] * U[1], nv = n[0] * V[0] + n[1] * V[1], nz = n[2];
+        double lo[3] = {x->vane_r_in, -hw, x->vane_z_lo}, hi[3] = {x->vane_r_out, hw, x->vane_z_hi};
+        double o[3] = {pu, pv, pz}, dd[3] = {nu, nv, nz};
+        double t0 = -INFINITY, t1 = INFINITY;
+        int inside = 1;
+        for (int i = 0; i < 3; ++i) {
+            if (dd[i] == 0.0) {
+                if (o[i] < lo[i] || o[i] > hi[i]) inside = 0;
+            } else {
+                double ta = (lo[i] - o[i]) / dd[i], tb = (hi[i] - o[i]) / dd[i];
+                if (ta > tb) { double tmp = ta; ta = tb; tb = tmp; }
+                if (ta > t0) t0 = ta;
+                if (tb < t1) t1 = tb;
+            }
+        }
+        if (inside && t0 <= t1 && t1 >= 0.0) {
+            if (t0 < 0.0) t0 = 0.0;
+            note_margin(margin, (t1 - t0) / (fabs(t0) + fabs(t1)));
+            for (int i = 0; i < 3; ++i) q[i] = p[i] + n[i] * t0;
+            return 1;
+        }
+        /* distance of the ray's line to the four long edges */
+        for (int e = 0; e < 4; ++e) {
+            double ve = (e & 1) ? hw : -hw, ze = (e & 2) ? x->vane_z_hi : x->vane_z_lo;
+            /* edge point E(s) = s U + ve V + ze z; w0 = E(0) - p */
+            double w0[3] = {ve * V[0] - p[0], ve * V[1] - p[1], ze - p[2]};
+            double b = U[0] * n[0] + U[1] * n[1];
+            double dw = U[0] * w0[0] + U[1] * w0[1];
+            double ew = n[0] * w0[0] + n[1] * w0[1] + n[2] * w0[2];
+            double s = (b * ew - dw) / (1.0 - b * b);
+            if (s < x->vane_r_in) s = x->vane_r_in;
+            if (s > x->vane_r_out) s = x->vane_r_out;
+            double r[3] = {w0[0] + s * U[0], w0[1] + s * U[1], w0[2]};
+            double rn = r[0] * n[0] + r[1] * n[1] + r[2] * n[2];
+            double c[3] = {r[0] - rn * n[0], r[1] - rn * n[1], r[2] - rn * n[2]};
+            double dist = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            if (dist < dk[k]) dk[k] = dist;
+        }
+    }
+    for (int k = 0; k < x->vanes; ++k)
+        if (dk[k] < best) { best = dk[k]; best_k = k; }
+    if (best_k < 0) return 0;
+    for (int k = 0; k < x->vanes; ++k)
+        if (k != best_k && dk[k] < second) second = dk[k];
+    note_margin(margin, best / x->vane_width);
+    if (second < INFINITY) note_margin(margin, (second - best) / best);
+    note_margin(margin, u_sign - 0.5);
+    double zm = 0.5 * (x->vane_z_lo + x->vane_z_hi);
+    double l = (zm - p[2]) / n[2];
+    p[0] += n[0] * l;
+    p[1] += n[1] * l;
+    p[2] = zm;
+    double a = x->vane_angle + TWO_PI * best_k / x->vanes;
+    double delta = lam / (2.0 * TWO_PI * (best > lam ? best : lam));
+    if (!(u_sign < 0.5)) delta = -delta;
+    n[0] += delta * -sin(a);
+    n[1] += delta * cos(a);
+    renormalise(n);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* The per-photon trace.                                                                       */
 
@@ -478,10 +636,6 @@ static void set_event(orc_event* ev, int status, int surface, const double p[3])
     ev->x = p[0]; ev->y = p[1]; ev->z = p[2];
 }
 
-static void renormalise(double n[3]) {
-    double m = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    n[0] /= m; n[1] /= m; n[2] /= m;
-}
 
 static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t* image,
                       orc_event* ev) {
@@ -528,6 +682,18 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
     }
     lam = lam * (1.0 + src->redshift);
     ev->lambda = lam;
+    const orc_extra* ex = &sc->ex;
+    if (sc->physics & ORC_DISPERSION) {
+        /* Atmospheric dispersion (section 2.3.2): refraction (n_air - 1) tan z toward the zenith,
+         * less that of the reference wavelength lam0, applied to (n_x, n_y) like the Sersic
+         * offset.  Reading: plane-parallel refraction R = (n - 1) tan z. */
+        double dR = (orc_air_refractivity(lam, ex->pressure, ex->temperature, ex->water) -
+                     orc_air_refractivity(ex->lam0, ex->pressure, ex->temperature, ex->water)) *
+                    tan(ex->zenith);
+        n[0] += dR * cos(ex->zenith_pa);
+        n[1] += dR * sin(ex->zenith_pa);
+        renormalise(n);
+    }
 
     /* Pupil (section 2.2): r = sqrt(u (r_o^2 - r_i^2) + r_i^2), phi = 2 pi v on the (slightly
      * enlarged) annulus of the first mirror, z from its nominal surface. */
@@ -584,6 +750,54 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         p[0] += n[0] * l;
         p[1] += n[1] * l;
         p[2] = sc->z_start;
+    }
+    double u7[4] = {0.5, 0.5, 0.5, 0.5};
+    if (sc->physics & (ORC_AEROSOL | ORC_HALO | ORC_SPIDER)) draw(sc, si, photon, 7, 0, u7);
+    if (sc->physics & ORC_AEROSOL) {
+        /* Aerosol opacity (section 2.3.2): tau = tau0 (lambda / 500 nm)^gamma at the zenith, times
+         * the airmass sec z along the path; the photon survives with probability exp(-tau).
+         * Reading: the printed destruction probability exp(-tau) is the survival probability. */
+        double tau = ex->tau0 * pow(lam / 500e-9, ex->gamma) / cos(ex->zenith);
+        double keep = exp(-tau);
+        note_margin(&margin, u7[0] - keep);
+        if (!(u7[0] < keep)) {
+            set_event(ev, ORC_EXTINCT, -1, p);
+            ev->margin = margin;
+            return;
+        }
+    }
+    if (sc->physics & ORC_DOME) {
+        /* Dome seeing (section 2.4.2): an isotropic Gaussian kick of the direction, standard
+         * deviation dome_sigma per axis (Box-Muller), at the entrance of the telescope. */
+        double ud[4];
+        draw(sc, si, photon, 8, 0, ud);
+        double rad = sqrt(-2.0 * log(ud[0]));
+        n[0] += ex->dome_sigma * rad * cos(TWO_PI * ud[1]);
+        n[1] += ex->dome_sigma * rad * sin(TWO_PI * ud[1]);
+        renormalise(n);
+    }
+    if (sc->physics & ORC_HALO) {
+        /* Micro-roughness halo (section 2.4.2): with probability f, a kick of angle r0 x
+         * (halo_sample) toward a uniform azimuth, at the start of the telescope. */
+        note_margin(&margin, u7[1] - ex->halo_f);
+        if (u7[1] < ex->halo_f) {
+            double xh;
+            if (halo_sample(sc->seed, si, photon, ex->halo_n, ex->halo_max / ex->halo_r0, &xh,
+                            &margin) >= 0) {
+                double r = ex->halo_r0 * xh;
+                n[0] += r * cos(TWO_PI * u7[2]);
+                n[1] += r * sin(TWO_PI * u7[2]);
+                renormalise(n);
+            }
+        }
+    }
+    if ((sc->physics & ORC_SPIDER) && ex->vanes > 0) {
+        double q[3];
+        if (spider(sc, p, n, lam, u7[3], q, &margin)) {
+            set_event(ev, ORC_OBSCURED, -1, q);
+            ev->margin = margin;
+            return;
+        }
     }
     /* Central obscuration (shadow of the secondary; section 2.4.1 obscuring structure). */
     if (sc->obsc_r > 0.0) {
@@ -680,6 +894,17 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
                     set_event(ev, ORC_ESCAPED, k, q);
                     ev->margin = margin;
                     return;
+                }
+                if (sc->physics & ORC_DEAD_LAYER) {
+                    /* field-free dead layer (section 2.4.2): electrons converted within `dead`
+                     * of the surface the light enters are removed.  Reading: the paper's "back
+                     * surface" of a back-illuminated device is the illuminated one. */
+                    note_margin(&margin, (depth - ex->dead) / sc->t_si);
+                    if (depth < ex->dead) {
+                        set_event(ev, ORC_DEAD, k, q);
+                        ev->margin = margin;
+                        return;
+                    }
                 }
                 xc = q[0] + d[0] * L;
                 yc = q[1] + d[1] * L;

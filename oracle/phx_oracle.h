@@ -22,10 +22,13 @@
 
 enum { ORC_MIRROR = 0, ORC_REFRACT = 1, ORC_DETECTOR = 2 };
 enum { ORC_VACUUM = 0, ORC_GLASS = 1, ORC_SILICON = 2 };
-enum { ORC_ATMOSPHERE = 1, ORC_COATINGS = 2, ORC_SILICON_PHYS = 4, ORC_DIFFUSION = 8 };
+enum { ORC_ATMOSPHERE = 1, ORC_COATINGS = 2, ORC_SILICON_PHYS = 4, ORC_DIFFUSION = 8,
+       ORC_AEROSOL = 16, ORC_DISPERSION = 32, ORC_DOME = 64, ORC_HALO = 128,
+       ORC_SPIDER = 2048, ORC_DEAD_LAYER = 4096 };
 enum {
     ORC_DETECTED = 0, ORC_OFF_CHIP = 1, ORC_VIGNETTED = 2, ORC_ABSORBED = 3, ORC_MISSED = 4,
-    ORC_NONCONV = 5, ORC_TIR = 6, ORC_ESCAPED = 7, ORC_OBSCURED = 8
+    ORC_NONCONV = 5, ORC_TIR = 6, ORC_ESCAPED = 7, ORC_OBSCURED = 8,
+    ORC_EXTINCT = 10, ORC_DEAD = 11
 };
 
 typedef struct {
@@ -42,6 +45,21 @@ typedef struct {
     double sersic_n, sersic_bn, sersic_a, sersic_b, sersic_pa;
     uint64_t n_photons;
 } orc_source;
+
+/* Per-photon physics beyond the core path (sections 2.3.2, 2.4.1, 2.4.2); angles in radians,
+ * lengths in metres.  Each part is used only when its physics bit is set. */
+typedef struct {
+    double zenith, zenith_pa;          /* zenith angle; refraction moves (n_x, n_y) along
+                                          (cos zenith_pa, sin zenith_pa)                     */
+    double tau0, gamma;                /* aerosol: tau = tau0 (lambda / 500 nm)^gamma        */
+    double pressure, water, temperature; /* mmHg, mmHg, deg C                                */
+    double lam0;                       /* wavelength whose refraction is taken out           */
+    double dome_sigma;                 /* dome seeing: Gaussian kick per axis                */
+    double halo_f, halo_n, halo_r0, halo_max; /* micro-roughness halo                        */
+    double dead;                       /* field-free layer at the silicon entrance surface   */
+    int32_t vanes, pad;                /* spider: vanes at vane_angle + 2 pi k / vanes       */
+    double vane_angle, vane_width, vane_r_in, vane_r_out, vane_z_lo, vane_z_hi;
+} orc_extra;
 
 typedef struct {
     /* optics */
@@ -76,6 +94,7 @@ typedef struct {
     uint32_t seed;
     int32_t pad3;
     double exposure;
+    orc_extra ex;
     /* derived by orc_prepare (owned by the oracle) */
     float* grad;        /* [L][S][N][N][2] */
     double* sed_cdf;    /* [n_sed][sed_k + 1] */
@@ -117,4 +136,7 @@ double orc_coating(const orc_scene* sc, int coat, double s, double lambda_m);
 void   orc_screen_gradient(const orc_scene* sc, int layer, int scale, double x, double y,
                            double* gx, double* gy);
 int    orc_gamma(uint32_t seed, int32_t src, uint64_t photon, double shape, double* out);
+double orc_air_refractivity(double lambda_m, double pressure, double temperature, double water);
+int    orc_halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, double x_max,
+                       double* x_out);
 #endif

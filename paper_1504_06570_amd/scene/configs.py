@@ -25,6 +25,7 @@ import numpy as np
 from . import coatings as _coat
 from .atmosphere import Atmosphere, make_atmosphere
 from .optics import Prescription, paraboloid, paraxial_image, tma_camera
+from .physics import Extras
 from .sources import (SEDTable, Sources, blackbody_table, point_sources, power_law_counts,
                       sersic_bn)
 
@@ -60,6 +61,7 @@ class Scene:
     pupil_margin: float = 0.0
     perturbation: np.ndarray = field(default_factory=lambda: np.zeros(N_PERTURB))
     meta: dict = field(default_factory=dict)
+    extras: Optional[Extras] = None               # parameters of the PHYS_EXTRA bits
 
 
 def _coated_tma(chip_center=(0.0, 0.0)):

@@ -1,0 +1,63 @@
+"""Parameters of the per-photon physics beyond the core path (setup inputs only).
+
+Defaults: aerosol tau0 = 0.02, Gamma = -1.28 and the micro-roughness halo (f, n, r0) =
+(0.135, 3.5, 0.1 deg) are the paper's values (sections 2.3.2 and 2.4.2).  The rest are synthetic
+site and hardware values: 30 deg zenith angle, a 2.7 km site (520 mmHg, 8 mmHg water, 12 C),
+dome seeing of 0.1 arcsec per axis, a halo truncated at 1 deg, a 50 nm field-free layer, and a
+four-vane spider holding the secondary of the three-mirror telescope.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+
+# Flag bits of the extra physics (the same bits as the library's PHX_F_* flags).
+PHYS_AEROSOL = 1 << 4
+PHYS_DISPERSION = 1 << 5
+PHYS_DOME = 1 << 6
+PHYS_HALO = 1 << 7
+PHYS_SPIDER = 1 << 11
+PHYS_DEAD_LAYER = 1 << 12
+PHYS_EXTRA = (PHYS_AEROSOL | PHYS_DISPERSION | PHYS_DOME | PHYS_HALO | PHYS_SPIDER |
+              PHYS_DEAD_LAYER)
+
+ARCSEC = math.radians(1.0 / 3600.0)
+
+
+@dataclass
+class Extras:
+    zenith: float = math.radians(30.0)
+    zenith_pa: float = math.radians(60.0)
+    tau0: float = 0.02
+    gamma: float = -1.28
+    pressure: float = 520.0          # mmHg
+    water: float = 8.0               # mmHg
+    temperature: float = 12.0        # deg C
+    lam0: float = 600e-9             # refraction of this wavelength is taken out (m)
+    dome_sigma: float = 0.1 * ARCSEC
+    halo_f: float = 0.135
+    halo_n: float = 3.5
+    halo_r0: float = math.radians(0.1)
+    halo_max: float = math.radians(1.0)
+    dead: float = 50e-9              # m
+    vanes: int = 4
+    vane_angle: float = math.radians(45.0)
+    vane_width: float = 0.03
+    vane_r_in: float = 1.6
+    vane_r_out: float = 4.4
+    vane_z_lo: float = 6.45
+    vane_z_hi: float = 6.95
+
+    def replace(self, **kw) -> "Extras":
+        return replace(self, **kw)
+
+
+def tma_extras() -> Extras:
+    """Extras for the three-mirror telescope (spider between the secondary and the start plane)."""
+    return Extras()
+
+
+def paraboloid_extras(focal: float = 10.0) -> Extras:
+    """Extras for the 1 m paraboloid: a four-vane spider 0.5 m below the start plane."""
+    return Extras(vane_width=0.01, vane_r_in=0.0, vane_r_out=0.6,
+                  vane_z_lo=focal + 0.5, vane_z_hi=focal + 0.6, vane_angle=0.0)
