@@ -51,7 +51,7 @@ enum {
 #define PHX_MAX_LAYERS 8
 #define PHX_MAX_SCALES 4
 #define PHX_N_THETA 22
-#define PHX_N_STATUS 10
+#define PHX_N_STATUS 12
 
 /* Surface kinds and media (section 2.4.1: mirrors have one surface, lenses two; the detector
  * is an optical surface like a lens surface). */
@@ -69,7 +69,9 @@ enum {
     PHX_TIR = 6,        /* total internal reflection at a refracting surface       */
     PHX_ESCAPED = 7,    /* crossed the silicon without converting                  */
     PHX_OBSCURED = 8,   /* blocked by the central obscuration                      */
-    PHX_CULLED = 9      /* removed before tracing by the transmission pre-roll     */
+    PHX_CULLED = 9,     /* removed before tracing by the transmission pre-roll     */
+    PHX_EXTINCT = 10,   /* destroyed by aerosol opacity (PHX_F_AEROSOL)            */
+    PHX_DEAD = 11       /* converted in the field-free dead layer (PHX_F_DEAD_LAYER) */
 };
 
 /* Physics and execution flags (phx_trace_args.flags). */
@@ -78,6 +80,15 @@ enum {
     PHX_F_COATINGS = 1u << 1,   /* coating roulette (needs phx_load_coatings)              */
     PHX_F_SILICON = 1u << 2,    /* refraction into silicon, conversion depth, escape       */
     PHX_F_DIFFUSION = 1u << 3,  /* Gaussian charge diffusion                               */
+    /* Per-photon physics beyond the core path; each needs phx_load_physics.  With PHX_F_DOME,
+       PHX_F_HALO or PHX_F_SPIDER the pre-roll keeps every pupil sample (the kicks at the
+       telescope entrance have no bound on the displacement at the primary). */
+    PHX_F_AEROSOL = 1u << 4,    /* aerosol extinction (section 2.3.2)                      */
+    PHX_F_DISPERSION = 1u << 5, /* atmospheric dispersion (section 2.3.2)                  */
+    PHX_F_DOME = 1u << 6,       /* dome seeing (section 2.4.2)                             */
+    PHX_F_HALO = 1u << 7,       /* micro-roughness halo (section 2.4.2)                    */
+    PHX_F_SPIDER = 1u << 11,    /* spider shadow and edge diffraction (2.4.1-2.4.2)        */
+    PHX_F_DEAD_LAYER = 1u << 12,/* field-free dead layer (section 2.4.2; needs SILICON)    */
     PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
                                    worst-case transmission of any coated surface (section 3.2,
                                    dynamic transmission optimisation), pupil samples whose
@@ -144,6 +155,42 @@ typedef struct {
     double sersic_n, sersic_bn, sersic_a, sersic_b, sersic_pa;
     uint64_t n_photons;
 } phx_source;
+
+/* Parameters of the per-photon physics beyond the core path.  Angles in radians, lengths in
+ * metres, all in the global frame of the prescription.  Random numbers: Philox block 7 (aerosol,
+ * halo selection, halo azimuth, spider sign), block 8 (dome-seeing normal pair), stream 2 block t
+ * (halo rejection trial t).
+ *  - Aerosol (section 2.3.2): a photon survives with probability exp(-tau sec z),
+ *    tau = tau0 (lambda / 500 nm)^gamma; else PHX_EXTINCT at the start plane.
+ *  - Dispersion (section 2.3.2): the source direction moves by (R(lambda) - R(lambda0)) along
+ *    (cos zenith_pa, sin zenith_pa) in (n_x, n_y), R = (n_air - 1) tan z with the Filippenko
+ *    index of air at pressure, water-vapour pressure (mmHg) and temperature (deg C), the water
+ *    term taken as a product with W.
+ *  - Dome seeing (section 2.4.2): a normal kick of standard deviation dome_sigma per axis added
+ *    to (n_x, n_y) on the start plane.
+ *  - Halo (section 2.4.2): with probability halo_fraction, a kick of angle r0 x toward a uniform
+ *    azimuth, x with density proportional to x / (1 + x^n) on [0, halo_max / r0]
+ *    (2 < n <= 6), drawn by rejection (at most 32 trials, then no kick).
+ *  - Spider (section 2.4.1 rectangular volumes, 2.4.2 edge diffraction): spider_vanes boxes
+ *    (at most 8), vane k along azimuth spider_angle + 2 pi k / spider_vanes, spanning radii
+ *    [r_inner, r_outer], width spider_width across and heights [z_low, z_high] (z_high at most
+ *    the start plane).  A ray that meets a box is PHX_OBSCURED; any other turns, at the vanes'
+ *    mid-height, by lambda / (4 pi max(d, lambda)) across the nearest vane (sign from its random
+ *    word), d = the closest distance between the ray and a long edge of a vane.
+ *  - Dead layer (section 2.4.2): an electron converted less than dead_layer below the surface the
+ *    light enters is removed (PHX_DEAD). */
+typedef struct {
+    double zenith_angle, zenith_pa;
+    double aerosol_tau0, aerosol_gamma;
+    double air_pressure, air_water, air_temperature;
+    double dispersion_lambda0;
+    double dome_sigma;
+    double halo_fraction, halo_index, halo_r0, halo_max;
+    double dead_layer;
+    int32_t spider_vanes, pad;
+    double spider_angle, spider_width, spider_r_inner, spider_r_outer;
+    double spider_z_low, spider_z_high;
+} phx_physics;
 
 /* Per-photon record written for sampled photons (PHX_F_EVENTS). */
 typedef struct {
@@ -242,6 +289,15 @@ phx_status phx_load_screens(phx_ctx ctx, const phx_atmosphere* atm_host, const f
 phx_status phx_load_sources(phx_ctx ctx, const phx_source* src_host, int32_t n_src,
                             const double* sed_edges_host, const double* sed_flux_host,
                             int32_t n_sed, int32_t sed_k);
+
+/* Load the parameters of the per-photon physics beyond the core path (the PHX_F_AEROSOL ..
+ * PHX_F_DEAD_LAYER flags; a trace with one of them set before this call fails with
+ * PHX_ERR_STATE).  Copied.  Validates 0 <= zenith_angle < pi/2, tau0 >= 0, pressures >= 0,
+ * temperature > -273.15, lambda0 > 0.16 um, dome_sigma >= 0, 0 <= halo_fraction <= 1,
+ * 2 < halo_index <= 6, 0 < halo_r0, 0 < halo_max < pi/2, dead_layer >= 0, 0 <= spider_vanes <= 8
+ * and (with vanes) width > 0, r_inner < r_outer, z_low < z_high <= the prescription's start
+ * plane (load the prescription first).  Errors: PHX_ERR_INVALID, PHX_ERR_STATE. */
+phx_status phx_load_physics(phx_ctx ctx, const phx_physics* physics_host);
 
 /* Trace photons: for every source s in [src_begin, src_end), photons photon_begin ..
  * photon_begin + count - 1, each keyed by Philox4x32-10 (key = (seed, s), counter = (photon

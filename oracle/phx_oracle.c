@@ -544,7 +544,7 @@ int orc_halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, doubl
 /* Spider (section 2.4.1: rectangular volumes; section 2.4.2: edge diffraction after Freniere et
  * al.).  Vane k is the box u in [r_in, r_out], |v| <= w/2, z in [z_lo, z_hi] in the frame of the
  * unit vectors u = (cos a_k, sin a_k, 0), v = (-sin a_k, cos a_k, 0), a_k = a_0 + 2 pi k / vanes.
- * Returns 1 if the incoming ray meets a vane (q = the entry point).  Otherwise d is the smallest
+ * Returns 1 if the incoming ray meets a vane (q = the first entry point along the ray).  Otherwise d is the smallest
  * distance between the ray's line and a long edge of any vane (the four segments along u at
  * v = +-w/2, z = z_lo or z_hi; for a segment, the distance of the line to its nearest point), the
  * ray moves to the vanes' mid-height and turns by lambda / (4 pi d) across the nearest vane,
@@ -558,7 +558,7 @@ static int spider(const orc_scene* sc, double p[3], double n[3], double lam, dou
                   double q[3], double* margin) {
     const orc_extra* x = &sc->ex;
     double hw = 0.5 * x->vane_width;
-    double best = INFINITY, second = INFINITY, dk[8];
+    double best = INFINITY, second = INFINITY, dk[8], t_hit = INFINITY;
     int best_k = -1;
     for (int k = 0; k < x->vanes; ++k) {
         dk[k] = INFINITY;
@@ -584,8 +584,8 @@ static int spider(const orc_scene* sc, double p[3], double n[3], double lam, dou
         if (inside && t0 <= t1 && t1 >= 0.0) {
             if (t0 < 0.0) t0 = 0.0;
             note_margin(margin, (t1 - t0) / (fabs(t0) + fabs(t1)));
-            for (int i = 0; i < 3; ++i) q[i] = p[i] + n[i] * t0;
-            return 1;
+            if (t0 < t_hit) t_hit = t0;
+            continue;
         }
         /* distance of the ray's line to the four long edges */
         for (int e = 0; e < 4; ++e) {
@@ -604,6 +604,10 @@ static int spider(const orc_scene* sc, double p[3], double n[3], double lam, dou
             double dist = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
             if (dist < dk[k]) dk[k] = dist;
         }
+    }
+    if (t_hit < INFINITY) {
+        for (int i = 0; i < 3; ++i) q[i] = p[i] + n[i] * t_hit;
+        return 1;
     }
     for (int k = 0; k < x->vanes; ++k)
         if (dk[k] < best) { best = dk[k]; best_k = k; }

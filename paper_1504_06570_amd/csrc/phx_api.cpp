@@ -21,6 +21,7 @@ struct phx_ctx_s {
     int n_cu = 256;
     std::string err;
     bool have_presc = false, have_src = false, have_coat = false, have_screens = false;
+    bool have_phys = false;
     phx_prescription presc{};
     double theta[PHX_N_THETA] = {0};
     DevParams host{};          // host image of the device parameter block
@@ -573,6 +574,79 @@ phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t 
     return build_escape_table(c);
 }
 
+phx_status phx_load_physics(phx_ctx c, const phx_physics* x) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!x) return fail(c, PHX_ERR_INVALID, "null physics parameters");
+    if (!c->have_presc) return fail(c, PHX_ERR_STATE, "load a prescription first");
+    const double half_pi = 0.5 * M_PI;
+    const double v[] = {x->zenith_angle, x->zenith_pa, x->aerosol_tau0, x->aerosol_gamma,
+                        x->air_pressure, x->air_water, x->air_temperature,
+                        x->dispersion_lambda0, x->dome_sigma, x->halo_fraction, x->halo_index,
+                        x->halo_r0, x->halo_max, x->dead_layer};
+    if (!finite_all(v, (int)(sizeof(v) / sizeof(v[0]))))
+        return fail(c, PHX_ERR_INVALID, "non-finite physics parameter");
+    if (!(x->zenith_angle >= 0.0 && x->zenith_angle < half_pi))
+        return fail(c, PHX_ERR_INVALID, "zenith angle outside [0, pi/2)");
+    if (!(x->aerosol_tau0 >= 0.0) || !(x->air_pressure >= 0.0) || !(x->air_water >= 0.0) ||
+        !(x->air_temperature > -273.15) || !(x->dispersion_lambda0 > 0.16e-6))
+        return fail(c, PHX_ERR_INVALID, "bad aerosol or air parameters");
+    if (!(x->dome_sigma >= 0.0) || !(x->halo_fraction >= 0.0 && x->halo_fraction <= 1.0) ||
+        !(x->halo_index > 2.0 && x->halo_index <= 6.0) || !(x->halo_r0 > 0.0) ||
+        !(x->halo_max > 0.0 && x->halo_max < half_pi) || !(x->dead_layer >= 0.0))
+        return fail(c, PHX_ERR_INVALID, "bad dome, halo or dead-layer parameters");
+    if (x->spider_vanes < 0 || x->spider_vanes > 8)
+        return fail(c, PHX_ERR_INVALID, "spider vanes %d outside 0..8", x->spider_vanes);
+    if (x->spider_vanes > 0) {
+        const double g[] = {x->spider_angle, x->spider_width, x->spider_r_inner,
+                            x->spider_r_outer, x->spider_z_low, x->spider_z_high};
+        if (!finite_all(g, 6) || !(x->spider_width > 0.0) ||
+            !(x->spider_r_inner < x->spider_r_outer) || !(x->spider_z_low < x->spider_z_high) ||
+            !(x->spider_z_high <= c->presc.z_start))
+            return fail(c, PHX_ERR_INVALID, "bad spider geometry");
+    }
+    phx::DevPhysics& X = c->host.ph;
+    X = phx::DevPhysics{};
+    X.airmass = 1.0 / std::cos(x->zenith_angle);
+    X.tau0 = x->aerosol_tau0;
+    X.gamma = x->aerosol_gamma;
+    // Filippenko index of air: factors of the dry bracket and of the water term
+    const double T = x->air_temperature, P = x->air_pressure;
+    X.disp_tanz = std::tan(x->zenith_angle);
+    X.disp_cx = std::cos(x->zenith_pa);
+    X.disp_cy = std::sin(x->zenith_pa);
+    X.disp_pt = P * (1.0 + (1.049 - 0.0157 * T) * 1e-6 * P) / (720.883 * (1.0 + 0.003661 * T));
+    X.disp_w = x->air_water / (1.0 + 0.003661 * T);
+    const double lu = x->dispersion_lambda0 * 1e6;
+    X.disp_s0 = 1.0 / (lu * lu);
+    X.disp_b0 = 64.328 + 29498.1 / (146.0 - X.disp_s0) + 255.4 / (41.0 - X.disp_s0);
+    X.dome_sigma = x->dome_sigma;
+    // halo: proposal density x (1 + x^2)^(-n/2) truncated at x_max, acceptance bound 2^(n/2 - 1)
+    const double n = x->halo_index, xmax = x->halo_max / x->halo_r0;
+    X.halo_f = x->halo_fraction;
+    X.halo_n = n;
+    X.halo_r0 = x->halo_r0;
+    X.halo_e = 1.0 - 0.5 * n;
+    X.halo_fq = 1.0 - std::pow(1.0 + xmax * xmax, X.halo_e);
+    X.halo_inv_m = std::pow(2.0, 1.0 - 0.5 * n);
+    X.dead = x->dead_layer;
+    X.vanes = x->spider_vanes;
+    for (int k = 0; k < x->spider_vanes; ++k) {
+        const double a = x->spider_angle + 2.0 * M_PI * k / x->spider_vanes;
+        X.vane_c[k] = std::cos(a);
+        X.vane_s[k] = std::sin(a);
+    }
+    X.vane_w = x->spider_width;
+    X.vane_hw = 0.5 * x->spider_width;
+    X.vane_r0 = x->spider_r_inner;
+    X.vane_r1 = x->spider_r_outer;
+    X.vane_z0 = x->spider_z_low;
+    X.vane_z1 = x->spider_z_high;
+    X.vane_zm = 0.5 * (x->spider_z_low + x->spider_z_high);
+    c->have_phys = true;
+    c->dirty = true;
+    return PHX_OK;
+}
+
 phx_status phx_load_screens(phx_ctx c, const phx_atmosphere* a, const float* opd, int64_t n_floats,
                             void* stream) {
     if (!c) return PHX_ERR_INVALID;
@@ -763,6 +837,9 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
 
 namespace {
 
+constexpr uint32_t kExtraFlags = PHX_F_AEROSOL | PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO |
+                                 PHX_F_SPIDER | PHX_F_DEAD_LAYER;
+
 // Radii of the pupil annulus outside which a photon cannot reach the primary's clear aperture:
 // the aperture widened by a bound on the atmospheric displacement at the primary.  Each layer i
 // turns the ray by at most kick_max x (sum over scales of the screen's largest gradient norm; a
@@ -773,6 +850,9 @@ namespace {
 void set_cull_radii(phx_ctx c, const phx_trace_args* a, phx::Launch& L) {
     L.cull_r2_lo = -1.0;
     L.cull_r2_hi = INFINITY;
+    // kicks at the telescope entrance (unbounded normal dome kick, halo, spider diffraction) move
+    // the landing point on the primary without a useful bound
+    if (a->flags & (PHX_F_DOME | PHX_F_HALO | PHX_F_SPIDER)) return;
     const phx::DevSurface& s0 = c->host.surf[0];
     if (s0.moved || c->presc.n_surfaces < 2) return;
     double D = 1e-6;
@@ -817,6 +897,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         return fail(c, PHX_ERR_STATE, "load a prescription and sources first");
     if ((a->flags & PHX_F_ATMOSPHERE) && !c->have_screens)
         return fail(c, PHX_ERR_STATE, "PHX_F_ATMOSPHERE without loaded screens");
+    if ((a->flags & kExtraFlags) && !c->have_phys)
+        return fail(c, PHX_ERR_STATE, "per-photon physics flags without phx_load_physics");
     if (a->flags & PHX_F_COATINGS)
         for (int k = 0; k < c->presc.n_surfaces; ++k) {
             const int co = c->presc.surf[k].coating;

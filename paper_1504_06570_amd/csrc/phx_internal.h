@@ -35,6 +35,22 @@ struct DevSource {
     uint64_t n_photons;
 };
 
+// Per-photon physics beyond the core path, as the kernels use it (derived from phx_physics).
+struct DevPhysics {
+    double airmass;                  // sec z
+    double tau0, gamma;              // aerosol tau = tau0 (lambda / 500 nm)^gamma
+    double disp_tanz, disp_cx, disp_cy;  // tan z and the direction of the shift in (n_x, n_y)
+    double disp_pt, disp_w;          // Filippenko pressure-temperature factor, water factor
+    double disp_b0, disp_s0;         // standard-air bracket and 1/lambda0^2 (um^-2) at lambda0
+    double dome_sigma;
+    double halo_f, halo_n, halo_r0;
+    double halo_e, halo_fq, halo_inv_m;  // 1 - n/2, proposal CDF at x_max, 2^(1 - n/2)
+    double dead;
+    int32_t vanes, pad;
+    double vane_c[8], vane_s[8];     // unit vector of each vane
+    double vane_hw, vane_r0, vane_r1, vane_z0, vane_z1, vane_zm, vane_w;
+};
+
 // Everything the trace kernel reads that does not change between launches with the same loads.
 struct DevParams {
     int32_t n_surf, nx, ny, n_layers;
@@ -81,6 +97,7 @@ struct DevParams {
     const double* sed_edges; // [sed_k + 1]
     const uint16_t* sed_guide; // [n_sed][kSedGuide + 1]: guide[j] = the first bin k with
                                // CDF[k + 1] > j / kSedGuide (guide[kSedGuide] = sed_k - 1)
+    DevPhysics ph;
 };
 
 // Per-launch arguments.
@@ -159,6 +176,10 @@ struct LaunchConfig {
     int pipeline = 1;
 };
 constexpr int kTileIters = 8;
+// Flags that select the sky and optics kernels carrying the per-photon physics beyond the core
+// path (the other instantiations hold none of its code).
+constexpr uint32_t kFrontExtra = PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO;
+constexpr uint32_t kBackExtra = PHX_F_AEROSOL | PHX_F_SPIDER;
 constexpr int kThreads = 256;   // workgroup size of every trace kernel
 
 // Optional per-kernel timing: events recorded before/after each kernel launch.

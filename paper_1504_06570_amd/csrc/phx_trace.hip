@@ -21,6 +21,7 @@ namespace phx {
 namespace {
 
 constexpr double kHcEvM = 1.2398419843320026e-6;  // h c / e in eV m
+constexpr double kPi = 3.141592653589793;
 // Newton stops once a step is at most 1e-9 m: convergence is quadratic, so the root is then
 // within about (|f''| / 2|f'|) x (1e-9 m)^2, far below a picometre (the paper's criterion is
 // 0.01 um).
@@ -382,6 +383,171 @@ __device__ __noinline__ bool escape_certain(const DevParams& P, double lam, uint
     return L_conv * cos_min * (1.0 - 1e-12) > P.t_si;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Per-photon physics beyond the core path.  Only the sky and optics kernel instantiations with
+// EXTRA = true contain this code (the launch picks them when one of its flags is set), so the
+// registers and occupancy of the other instantiations do not depend on it.
+
+__device__ __forceinline__ double3 unit3(double3 v) {
+    const double inv = 1.0 / sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+    return make_double3(v.x * inv, v.y * inv, v.z * inv);
+}
+
+// Atmospheric dispersion (section 2.3.2): the direction moves by R(lambda) - R(lambda0) along the
+// zenith direction in (n_x, n_y), R = (n_air - 1) tan z, n_air from the Filippenko formula with
+// its pressure-temperature and water factors precomputed; the difference of the dry brackets and
+// of the water terms is taken before scaling, so no 1 + 3e-4 is formed.
+__device__ __forceinline__ double3 disperse(const DevParams& P, double lam, double3 n) {
+    const DevPhysics& X = P.ph;
+    const double lu = lam * 1e6;
+    const double s = 1.0 / (lu * lu);
+    const double b = 64.328 + 29498.1 / (146.0 - s) + 255.4 / (41.0 - s);
+    const double dR =
+        1e-6 * (X.disp_pt * (b - X.disp_b0) + 0.000680 * X.disp_w * (s - X.disp_s0)) * X.disp_tanz;
+    n.x += dR * X.disp_cx;
+    n.y += dR * X.disp_cy;
+    return unit3(n);
+}
+
+// Dome seeing and the micro-roughness halo (section 2.4.2), kicks of the direction on the start
+// plane.  Dome: a normal kick of dome_sigma per axis (Box-Muller on block 8).  Halo: with
+// probability f (block 7, word y) an angle r0 x toward the azimuth of block 7 word z; x has
+// density proportional to x / (1 + x^n) on [0, x_max], drawn by rejection from the density
+// x (1 + x^2)^(-n/2), whose CDF 1 - (1 + x^2)^(1 - n/2) inverts in closed form, keeping a trial
+// when u < (1 + x^2)^(n/2) / (1 + x^n) / 2^(n/2 - 1) (the ratio's maximum, at x = 1); trial t
+// reads stream 2 block t (proposal x, acceptance y); after 32 rejections no kick.
+__device__ __forceinline__ double3 entrance_kicks(const DevParams& P, uint32_t flags, Rng rng,
+                                               double3 n) {
+    const DevPhysics& X = P.ph;
+    if (flags & PHX_F_DOME) {
+        const uint4 w = rng.block(8);
+        const double rad = sqrt(-2.0 * log(u01(w.x)));
+        double sa, ca;
+        sincospi(2.0 * u01(w.y), &sa, &ca);
+        n.x += X.dome_sigma * rad * ca;
+        n.y += X.dome_sigma * rad * sa;
+        n = unit3(n);
+    }
+    if (flags & PHX_F_HALO) {
+        const uint4 w7 = rng.block(7);
+        if (u01(w7.y) < X.halo_f) {
+            double x = -1.0;
+#pragma unroll 1
+            for (uint32_t t = 0; t < 32; ++t) {
+                const uint4 w = rng.block(t, 2);
+                const double xt = sqrt(exp(log(1.0 - u01(w.x) * X.halo_fq) / X.halo_e) - 1.0);
+                const double ratio =
+                    exp(0.5 * X.halo_n * log(1.0 + xt * xt)) / (1.0 + exp(X.halo_n * log(xt)));
+                if (u01(w.y) < ratio * X.halo_inv_m) {
+                    x = xt;
+                    break;
+                }
+            }
+            if (x >= 0.0) {
+                const double r = X.halo_r0 * x;
+                double sa, ca;
+                sincospi(2.0 * u01(w7.z), &sa, &ca);
+                n.x += r * ca;
+                n.y += r * sa;
+                n = unit3(n);
+            }
+        }
+    }
+    return n;
+}
+
+// Aerosol extinction (section 2.3.2) and the spider (sections 2.4.1-2.4.2) at the telescope
+// entrance.  status 0: the photon lives (a ray that passes the spider is moved to the vanes'
+// mid-height and turned); PHX_EXTINCT with p the start-plane point; PHX_OBSCURED with p the first
+// point along the ray inside a vane.
+struct Entry {
+    double3 p, n;
+    int status;
+};
+
+// One slab of the ray-box test: narrows [t0, t1] to the parameters where o + t d lies in [lo, hi].
+__device__ __forceinline__ void slab(double o, double d, double lo, double hi, double& t0,
+                                     double& t1, bool& inside) {
+    if (d == 0.0) {
+        if (o < lo || o > hi) inside = false;
+        return;
+    }
+    double ta = (lo - o) / d, tb = (hi - o) / d;
+    if (ta > tb) {
+        const double tmp = ta;
+        ta = tb;
+        tb = tmp;
+    }
+    t0 = fmax(t0, ta);
+    t1 = fmin(t1, tb);
+}
+
+// Aerosol: survival with probability exp(-tau sec z), tau = tau0 (lambda / 500 nm)^gamma (block 7
+// word x).  Spider: vane k is the box u in [r_in, r_out], |v| <= w/2, z in [z_lo, z_hi] along
+// u = (c_k, s_k, 0), v = (-s_k, c_k, 0).  A ray that passes every box turns by
+// lambda / (4 pi max(d, lambda)) along +v or -v of the nearest vane (block 7 word w), d = the
+// smallest distance between the ray's line and a vane's long edge (segment along u at v = +-w/2,
+// z = z_lo or z_hi: the closest point of the infinite edge line, clamped to the segment, then its
+// distance to the ray's line).
+__device__ __forceinline__ Entry entrance_extra(const DevParams& P, uint32_t flags, Rng rng,
+                                             double lam, double3 p, double3 n) {
+    const DevPhysics& X = P.ph;
+    const uint4 w7 = rng.block(7);
+    if (flags & PHX_F_AEROSOL) {
+        const double tau = X.tau0 * exp(X.gamma * log(lam / 500e-9)) * X.airmass;
+        if (!(u01(w7.x) < exp(-tau))) return Entry{p, n, PHX_EXTINCT};
+    }
+    if ((flags & PHX_F_SPIDER) && X.vanes > 0) {
+        double best = INFINITY, t_hit = INFINITY;
+        int bk = -1;
+#pragma unroll 1
+        for (int k = 0; k < X.vanes; ++k) {
+            const double c = X.vane_c[k], s = X.vane_s[k];
+            double t0 = -INFINITY, t1 = INFINITY;
+            bool inside = true;
+            slab(p.x * c + p.y * s, n.x * c + n.y * s, X.vane_r0, X.vane_r1, t0, t1, inside);
+            slab(-p.x * s + p.y * c, -n.x * s + n.y * c, -X.vane_hw, X.vane_hw, t0, t1, inside);
+            slab(p.z, n.z, X.vane_z0, X.vane_z1, t0, t1, inside);
+            if (inside && t0 <= t1 && t1 >= 0.0) {
+                t_hit = fmin(t_hit, fmax(t0, 0.0));
+                continue;
+            }
+            const double b = c * n.x + s * n.y;
+            const double inv = 1.0 / (1.0 - b * b);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double ve = (e & 1) ? X.vane_hw : -X.vane_hw;
+                const double ze = (e & 2) ? X.vane_z1 : X.vane_z0;
+                const double w0x = -ve * s - p.x, w0y = ve * c - p.y, w0z = ze - p.z;
+                const double dw = c * w0x + s * w0y;
+                const double ew = n.x * w0x + n.y * w0y + n.z * w0z;
+                const double sc = fmin(fmax((b * ew - dw) * inv, X.vane_r0), X.vane_r1);
+                const double rx = w0x + sc * c, ry = w0y + sc * s, rz = w0z;
+                const double rn = rx * n.x + ry * n.y + rz * n.z;
+                const double cx = rx - rn * n.x, cy = ry - rn * n.y, cz = rz - rn * n.z;
+                const double dist = sqrt(cx * cx + cy * cy + cz * cz);
+                if (dist < best) {
+                    best = dist;
+                    bk = k;
+                }
+            }
+        }
+        if (t_hit < INFINITY)
+            return Entry{make_double3(p.x + n.x * t_hit, p.y + n.y * t_hit, p.z + n.z * t_hit), n,
+                         PHX_OBSCURED};
+        if (bk >= 0) {
+            const double l = (X.vane_zm - p.z) / n.z;
+            p = make_double3(p.x + n.x * l, p.y + n.y * l, X.vane_zm);
+            double delta = lam / (4.0 * kPi * fmax(best, lam));
+            if (!(u01(w7.w) < 0.5)) delta = -delta;
+            n.x -= delta * X.vane_s[bk];
+            n.y += delta * X.vane_c[bk];
+            n = unit3(n);
+        }
+    }
+    return Entry{p, n, 0};
+}
+
 struct Outcome {
     int status, surface, newton;
     int pix_i, pix_j;
@@ -396,7 +562,7 @@ struct Front {
 
 // Sky sampling (sections 2.2, 2.2.1) and the atmosphere (sections 2.3.1-2.3.2), ending on the
 // start plane above every optic.
-template <bool SERSIC>
+template <bool SERSIC, bool EXTRA>
 __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64_t idx, Front& f) {
     const DevSource& src = P.src[si];
     const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
@@ -416,6 +582,10 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
         n[0] += dmaj * src.cos_pa - dmin * src.sin_pa;
         n[1] += dmaj * src.sin_pa + dmin * src.cos_pa;
         normalise(n);
+    }
+    if (EXTRA && (L.flags & PHX_F_DISPERSION)) {
+        const double3 m = disperse(P, lam, make_double3(n[0], n[1], n[2]));
+        n[0] = m.x; n[1] = m.y; n[2] = m.z;
     }
     const double t = L.exposure * u01(w0.z);
 
@@ -480,6 +650,10 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
         p[1] += n[1] * l;
         p[2] = P.z_start;
     }
+    if (EXTRA && (L.flags & (PHX_F_DOME | PHX_F_HALO))) {
+        const double3 m = entrance_kicks(P, L.flags, rng, make_double3(n[0], n[1], n[2]));
+        n[0] = m.x; n[1] = m.y; n[2] = m.z;
+    }
     f.p[0] = p[0]; f.p[1] = p[1]; f.p[2] = p[2];
     f.n[0] = n[0]; f.n[1] = n[1]; f.n[2] = n[2];
     f.lam = lam;
@@ -487,16 +661,19 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
 
 // Silicon (sections 2.4.2-2.4.3): conversion after a path of mean free path x Exp(1) along the
 // refracted direction d; escape if deeper than the silicon; Gaussian diffusion with sigma
-// proportional to the drift distance to the collecting surface.  Moves (xc, yc) from the landing
-// point to the electron position; returns true if the photon escapes.  Kept out of line: it runs
-// once per photon and inlining it raises the register count of the whole optics loop.
-__device__ __noinline__ bool sensor_stage(const DevParams& P, const Launch& L, const Rng& rng,
-                                          double lam, const double* d, double& xc, double& yc) {
+// proportional to the drift distance to the collecting surface.  With PHX_F_DEAD_LAYER an
+// electron converted less than `dead` below the entrance surface is removed (section 2.4.2
+// field-free layer).  Moves (xc, yc) from the landing point to the electron position; returns 0,
+// PHX_ESCAPED or PHX_DEAD.  Kept out of line: it runs once per photon and inlining it raises the
+// register count of the whole optics loop.
+__device__ __noinline__ int sensor_stage(const DevParams& P, const Launch& L, const Rng& rng,
+                                         double lam, const double* d, double& xc, double& yc) {
     if (L.flags & PHX_F_SILICON) {
         const double alpha = absorption(P, lam);
         const double L_conv = alpha > 0.0 ? -log(u01(rng.block(1).z)) / alpha : INFINITY;
         const double depth = L_conv * fabs(d[2]);
-        if (!(depth <= P.t_si)) return true;
+        if (!(depth <= P.t_si)) return PHX_ESCAPED;
+        if ((L.flags & PHX_F_DEAD_LAYER) && depth < P.ph.dead) return PHX_DEAD;
         xc += d[0] * L_conv;
         yc += d[1] * L_conv;
         if (L.flags & PHX_F_DIFFUSION) {
@@ -509,7 +686,7 @@ __device__ __noinline__ bool sensor_stage(const DevParams& P, const Launch& L, c
             yc += sigma * rad * sa;
         }
     }
-    return false;
+    return 0;
 }
 
 // Central obscuration, the surfaces (sections 2.4.1-2.4.2), silicon (sections 2.4.2-2.4.3) and
@@ -620,6 +797,26 @@ __device__ __forceinline__ bool obscured(const DevParams& P, const Ray& ray, Out
     return true;
 }
 
+// Before the first surface: aerosol extinction and the spider (when their flags are set), then
+// the central obscuration.  True while the photon lives, else the outcome is filled.
+template <bool EXTRA>
+__device__ __forceinline__ bool entrance(const DevParams& P, const Launch& L, const Rng& rng,
+                                         Ray& ray, Outcome& o) {
+    if (EXTRA && (L.flags & (PHX_F_AEROSOL | PHX_F_SPIDER))) {
+        const Entry e = entrance_extra(P, L.flags, rng, o.lam,
+                                       make_double3(ray.p[0], ray.p[1], ray.p[2]),
+                                       make_double3(ray.n[0], ray.n[1], ray.n[2]));
+        if (e.status != 0) {
+            o.status = e.status;
+            o.x = e.p.x; o.y = e.p.y; o.z = e.p.z;
+            return false;
+        }
+        ray.p[0] = e.p.x; ray.p[1] = e.p.y; ray.p[2] = e.p.z;
+        ray.n[0] = e.n.x; ray.n[1] = e.n.y; ray.n[2] = e.n.z;
+    }
+    return !obscured(P, ray, o);
+}
+
 // Surfaces k0..k1-1 before the detector (sections 2.4.1-2.4.2): returns true while the photon
 // lives, else fills the outcome.  wc / wc_block cache the roulette block of the last coated
 // surface (wc_block = -1: none).
@@ -686,8 +883,9 @@ __device__ __forceinline__ void finish_detector(const DevParams& P, const Launch
         return;
     }
     double xc = h.q[0], yc = h.q[1];
-    if (sensor_stage(P, L, rng, oc.lam, h.d, xc, yc)) {
-        o.status = PHX_ESCAPED;
+    const int ss = sensor_stage(P, L, rng, oc.lam, h.d, xc, yc);
+    if (ss != 0) {
+        o.status = ss;
         return;
     }
     o.xe = xc; o.ye = yc;
@@ -712,7 +910,7 @@ __device__ Outcome photon_back(const DevParams& P, const Launch& L, int si, uint
     outcome_init(o, f.lam);
     const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
     Ray ray{{f.p[0], f.p[1], f.p[2]}, {f.n[0], f.n[1], f.n[2]}, 1.0};
-    if (obscured(P, ray, o)) return o;
+    if (!entrance<true>(P, L, rng, ray, o)) return o;
     const Optics oc = optics_of(P, L, f.lam);
     uint4 wc = make_uint4(0, 0, 0, 0);
     int wc_block = -1;
@@ -1281,7 +1479,7 @@ struct Tiles {
 // Front half of the trace for the chunk's photons (the survivor list, or every photon when
 // surv is null): sky sampling and the atmosphere, leaving the start-plane state in SoA arrays
 // st[0..6][i] = p_x, p_y, p_z, n_x, n_y, n_z, lambda.
-template <bool SERSIC>
+template <bool SERSIC, bool EXTRA>
 __global__ __launch_bounds__(kBlock) void front_kernel(const DevParams* __restrict__ Pg,
                                                        const Launch L, uint64_t begin,
                                                        const uint32_t* __restrict__ surv,
@@ -1301,7 +1499,7 @@ __global__ __launch_bounds__(kBlock) void front_kernel(const DevParams* __restri
         uint64_t idx;
         decode(L, g, si, idx);
         Front f;
-        photon_front<SERSIC>(P, L, si, idx, f);
+        photon_front<SERSIC, EXTRA>(P, L, si, idx, f);
         st[0 * st_stride + r] = f.p[0];
         st[1 * st_stride + r] = f.p[1];
         st[2 * st_stride + r] = f.p[2];
@@ -1353,7 +1551,7 @@ __device__ __forceinline__ void book(const DevParams& P, const Launch& L, bool a
 constexpr int kWin = 32;                  // LDS pixel window of the optics kernel
 constexpr int kQueue = 128;               // queued photons per wavefront (64 + 63 carried)
 constexpr int kWaves = kBlock / 64;
-template <bool ZERN>
+template <bool ZERN, bool EXTRA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void back_kernel(
         const DevParams* __restrict__ Pg, const Launch L, uint64_t begin,
         const uint32_t* __restrict__ surv, const unsigned int* __restrict__ count, uint64_t n_all,
@@ -1442,8 +1640,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             ray.n[0] = st[3 * st_stride + r];
             ray.n[1] = st[4 * st_stride + r];
             ray.n[2] = st[5 * st_stride + r];
-            if (!obscured(P, ray, o)) {
-                const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+            const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+            if (entrance<EXTRA>(P, L, rng, ray, o)) {
                 const Optics oc = optics_of(P, L, lam);
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
@@ -2032,12 +2230,11 @@ struct Stages {
         const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
         const dim3 fg((unsigned)(want < fcap ? want : fcap));
         mark(1, 0, stream);
-        if (L.any_sersic)
-            hipLaunchKernelGGL(front_kernel<true>, fg, dim3(kBlock), 0, stream, dparams, L,
-                               sp.begin, surv(c), cnt(c), sp.len, state_buf(c), W.chunk, ft);
-        else
-            hipLaunchKernelGGL(front_kernel<false>, fg, dim3(kBlock), 0, stream, dparams, L,
-                               sp.begin, surv(c), cnt(c), sp.len, state_buf(c), W.chunk, ft);
+        const bool extra = (L.flags & kFrontExtra) != 0;
+        const auto fk = L.any_sersic ? (extra ? front_kernel<true, true> : front_kernel<true, false>)
+                                     : (extra ? front_kernel<false, true> : front_kernel<false, false>);
+        hipLaunchKernelGGL(fk, fg, dim3(kBlock), 0, stream, dparams, L, sp.begin, surv(c), cnt(c),
+                           sp.len, state_buf(c), W.chunk, ft);
         mark(1, 1, stream);
         if (piped()) (void)hipEventRecord(ev(1, c), stream);
     }
@@ -2112,14 +2309,11 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
         const dim3 bg((unsigned)(want < bcap ? want : bcap));
         unsigned long long* bt = cfg.dynamic ? W.tiles + 2 * c + 1 : nullptr;
         S.mark(2, 0, bs);
-        if (L.any_zernike)
-            hipLaunchKernelGGL(back_kernel<true>, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin,
-                               S.surv(c), S.cnt(c), sp.len, (const double*)S.state_buf(c), W.chunk,
-                               bt);
-        else
-            hipLaunchKernelGGL(back_kernel<false>, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin,
-                               S.surv(c), S.cnt(c), sp.len, (const double*)S.state_buf(c), W.chunk,
-                               bt);
+        const bool extra = (L.flags & kBackExtra) != 0;
+        const auto bk = L.any_zernike ? (extra ? back_kernel<true, true> : back_kernel<true, false>)
+                                      : (extra ? back_kernel<false, true> : back_kernel<false, false>);
+        hipLaunchKernelGGL(bk, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin, S.surv(c), S.cnt(c),
+                           sp.len, (const double*)S.state_buf(c), W.chunk, bt);
         S.mark(2, 1, bs);
     });
     return hipGetLastError();

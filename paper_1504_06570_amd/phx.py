@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libphx.so")
 
-MAX_SURF, MAX_LAYERS, MAX_SCALES, N_THETA, N_STATUS = 16, 8, 4, 22, 10
+MAX_SURF, MAX_LAYERS, MAX_SCALES, N_THETA, N_STATUS = 16, 8, 4, 22, 12
 STAT_COLS = MAX_SURF + 1
 STAT_NEWTON = N_STATUS * STAT_COLS
 STAT_TRACED = STAT_NEWTON + 1
@@ -24,9 +24,12 @@ MOMENT_WORDS, MOMENT_Q_LOG2 = 12, 44
 
 F_ATMOSPHERE, F_COATINGS, F_SILICON, F_DIFFUSION = 1, 2, 4, 8
 F_CULL, F_EVENTS, F_MOMENTS = 1 << 8, 1 << 9, 1 << 10
+F_AEROSOL, F_DISPERSION, F_DOME, F_HALO = 1 << 4, 1 << 5, 1 << 6, 1 << 7
+F_SPIDER, F_DEAD_LAYER = 1 << 11, 1 << 12
 STATUS = ["DETECTED", "OFF_CHIP", "VIGNETTED", "ABSORBED", "MISSED", "NONCONV", "TIR", "ESCAPED",
-          "OBSCURED", "CULLED"]
-DETECTED, OFF_CHIP, VIGNETTED, ABSORBED, MISSED, NONCONV, TIR, ESCAPED, OBSCURED, CULLED = range(10)
+          "OBSCURED", "CULLED", "EXTINCT", "DEAD"]
+(DETECTED, OFF_CHIP, VIGNETTED, ABSORBED, MISSED, NONCONV, TIR, ESCAPED, OBSCURED, CULLED,
+ EXTINCT, DEAD) = range(12)
 
 
 class PhxError(RuntimeError):
@@ -63,6 +66,34 @@ class Source(C.Structure):
                 ("lambda_lo", C.c_double), ("lambda_hi", C.c_double), ("redshift", C.c_double),
                 ("sersic_n", C.c_double), ("sersic_bn", C.c_double), ("sersic_a", C.c_double),
                 ("sersic_b", C.c_double), ("sersic_pa", C.c_double), ("n_photons", C.c_uint64)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("zenith_angle", C.c_double), ("zenith_pa", C.c_double),
+                ("aerosol_tau0", C.c_double), ("aerosol_gamma", C.c_double),
+                ("air_pressure", C.c_double), ("air_water", C.c_double),
+                ("air_temperature", C.c_double), ("dispersion_lambda0", C.c_double),
+                ("dome_sigma", C.c_double), ("halo_fraction", C.c_double),
+                ("halo_index", C.c_double), ("halo_r0", C.c_double), ("halo_max", C.c_double),
+                ("dead_layer", C.c_double), ("spider_vanes", C.c_int32), ("pad", C.c_int32),
+                ("spider_angle", C.c_double), ("spider_width", C.c_double),
+                ("spider_r_inner", C.c_double), ("spider_r_outer", C.c_double),
+                ("spider_z_low", C.c_double), ("spider_z_high", C.c_double)]
+
+
+def physics_struct(x) -> Physics:
+    """phx_physics from a scene's Extras (paper_1504_06570_amd.scene.physics)."""
+    P = Physics()
+    P.zenith_angle, P.zenith_pa = x.zenith, x.zenith_pa
+    P.aerosol_tau0, P.aerosol_gamma = x.tau0, x.gamma
+    P.air_pressure, P.air_water, P.air_temperature = x.pressure, x.water, x.temperature
+    P.dispersion_lambda0, P.dome_sigma = x.lam0, x.dome_sigma
+    P.halo_fraction, P.halo_index, P.halo_r0, P.halo_max = x.halo_f, x.halo_n, x.halo_r0, x.halo_max
+    P.dead_layer = x.dead
+    P.spider_vanes, P.spider_angle, P.spider_width = x.vanes, x.vane_angle, x.vane_width
+    P.spider_r_inner, P.spider_r_outer = x.vane_r_in, x.vane_r_out
+    P.spider_z_low, P.spider_z_high = x.vane_z_lo, x.vane_z_hi
+    return P
 
 
 class TraceArgs(C.Structure):
@@ -114,6 +145,7 @@ def lib():
         L.phx_load_sources.argtypes = [C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p,
                                        C.c_void_p, C.c_int32, C.c_int32]
         L.phx_trace.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
+        L.phx_load_physics.argtypes = [C.c_void_p, C.POINTER(Physics)]
         L.phx_set_timing.argtypes = [C.c_void_p, C.c_int32]
         L.phx_get_timing.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32]
         L.phx_set_launch_config.argtypes = [C.c_void_p, C.POINTER(LaunchConfig)]
@@ -201,6 +233,8 @@ class Tracer:
                                                  coat_mod.DLAM))
         if scene.atmosphere is not None:
             self.load_screens(scene.atmosphere)
+        if getattr(scene, "extras", None) is not None:
+            self.load_physics(scene.extras)
         self.load_sources(scene.sources, scene.sed)
 
     def _check(self, rc):
@@ -239,6 +273,9 @@ class Tracer:
                                             _stream_handle()))
         torch.cuda.current_stream().synchronize()
         del opd
+
+    def load_physics(self, extras):
+        self._check(self.L.phx_load_physics(self.ctx, C.byref(physics_struct(extras))))
 
     def load_sources(self, S, sed=None):
         arr = sources_struct(S)

@@ -103,6 +103,20 @@ def test_full_stack_matches_oracle(phx):
     assert n > 100
 
 
+def test_full_stack_with_extra_physics_matches_oracle(phx):
+    """Dispersion, dome seeing, the halo, the spider, aerosol extinction and the dead layer on top
+    of the full stack: none depends on the perturbation, so the photons' Jacobians still agree
+    with the oracle's central differences (and the same photons are removed on both sides)."""
+    from paper_1504_06570_amd.scene import physics as X
+    s = C.gradients(scale=1e-4, screen_n=128)
+    s.physics = int(s.physics) | X.PHYS_EXTRA
+    s.extras = X.tma_extras()
+    rng = np.random.default_rng(23)
+    s.perturbation = rng.uniform(-1, 1, C.N_PERTURB) * RANGE
+    n = compare_with_oracle(phx, s, 3000, sources=[0, 12, 24])
+    assert n > 100
+
+
 def test_vjp_equals_sum_of_jacobians(phx):
     """The reduced gradient equals sum_i xbar_i J_x,i + ybar_i J_y,i assembled on the host from
     the per-photon Jacobians (seeds, decode and fixed-order reductions)."""

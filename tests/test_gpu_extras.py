@@ -1,0 +1,137 @@
+"""GPU trace with the per-photon physics beyond the core path (aerosol, dispersion, dome seeing,
+micro-roughness halo, spider, dead layer) against the CPU oracle, photon by photon and pixel by
+pixel, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1504_06570_amd.scene import configs as C
+from paper_1504_06570_amd.scene import physics as X
+from tests import helpers as H
+from tests import parity
+from tests.test_gpu_parity import run_both
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def phx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_06570_amd import phx as P
+    return P
+
+
+def _tiny(flags, scale=0.2, **kw):
+    s = C.tiny(scale=scale)
+    s.physics = flags
+    s.extras = X.paraboloid_extras().replace(**kw)
+    return s
+
+
+@pytest.mark.parametrize("flag,kw", [
+    (X.PHYS_DISPERSION, dict(zenith=math.radians(50.0))),
+    (X.PHYS_AEROSOL, dict(tau0=0.3, zenith=math.radians(60.0))),
+    (X.PHYS_DOME, dict(dome_sigma=2e-6)),
+    (X.PHYS_HALO, dict(halo_max=math.radians(0.25))),
+    (X.PHYS_SPIDER, {}),
+])
+def test_each_effect_on_the_paraboloid(phx, flag, kw):
+    """One effect at a time on the 1 m paraboloid (a flat 320-1080 nm spectrum so dispersion and
+    the spider's lambda / (4 pi d) vary per photon): statuses, positions and pixels equal the
+    oracle's."""
+    s = _tiny(flag, **kw)
+    s.sources.lam_lo[:] = 320e-9
+    s.sources.lam_hi[:] = 1080e-9
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev)
+    assert rep["boundary_frac"] < 1e-4
+    assert parity.images_agree(gimg, oimg, gev, oev)
+    if flag == X.PHYS_AEROSOL:
+        assert (gev["status"] == phx.EXTINCT).mean() > 0.1
+    if flag == X.PHYS_SPIDER:
+        assert (gev["status"] == phx.OBSCURED).mean() > 0.01
+
+
+def test_dead_layer_on_the_flat_detector(phx):
+    """Blue photons on a flat silicon detector: the dead layer removes the same photons on both
+    sides (status DEAD), the rest convert at the same points."""
+    s = H.flat_detector_scene(n_photons=20000, lam=420e-9,
+                              physics=C.PHYS_SILICON | C.PHYS_DIFFUSION | X.PHYS_DEAD_LAYER)
+    s.extras = X.Extras(dead=100e-9, vanes=0)   # no spider above this detector's start plane
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev)
+    assert rep["boundary_frac"] < 1e-4
+    assert (gev["status"] == phx.DEAD).mean() > 0.1
+    assert parity.images_agree(gimg, oimg, gev, oev)
+
+
+def _full_extras(scale=2e-4, screen_n=256):
+    s = C.full(scale=scale, screen_n=screen_n)
+    s.physics = C.PHYS_ALL | X.PHYS_EXTRA
+    s.extras = X.tma_extras()
+    return s
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_full_stack_with_every_effect(phx, cull):
+    """Seven atmosphere layers, the three-mirror telescope with coatings, silicon, diffusion and
+    every extra effect on at once (the pre-roll on or off): photon-by-photon and pixel parity."""
+    s = _full_extras()
+    flags = int(s.physics) | (phx.F_CULL if cull else 0)
+    gev, gimg, oev, oimg, st = run_both(phx, s, flags=flags)
+    culled = gev["status"] == phx.CULLED
+    if cull:
+        assert culled.any()
+        # culled photons are the ones the oracle finds absorbed, escaped or otherwise lost
+        assert not np.isin(oev["status"][np.isin(oev["photon"], gev["photon"][culled])],
+                           [O.DETECTED, O.OFF_CHIP]).any()
+        keep = ~culled
+        gev = gev[keep]
+        oev = oev[np.isin(oev["photon"], gev["photon"])]
+    rep = parity.compare(gev, oev)
+    assert rep["boundary_frac"] < 1e-4
+    assert rep["detected"] > 500
+    assert parity.images_agree(gimg, oimg, gev, oev)
+    for status in (phx.EXTINCT, phx.DEAD, phx.OBSCURED):
+        assert (oev["status"] == status).any()
+
+
+def test_batched_graph_with_every_effect(phx):
+    """The captured-graph batched trace with every effect on equals the eager trace (Sersic
+    sources and blackbody SEDs in front), and both equal the oracle's image."""
+    import torch
+    s = C.batched(scale=2e-3, screen_n=128, n_src=200)
+    s.physics = C.PHYS_ALL | X.PHYS_EXTRA
+    s.extras = X.tma_extras()
+    tr = phx.Tracer(s)
+    a, _, _, _ = tr.trace()
+    b, _, _, _ = tr.trace(batched=True)
+    c, _, _, _ = tr.trace(batched=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(b, c)
+    tr.close()
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev)
+    assert rep["boundary_frac"] < 1e-4
+    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert np.array_equal(gimg, a.cpu().numpy().view(np.uint32))
+
+
+def test_physics_flags_need_parameters(phx):
+    """A trace with an extra-physics flag before phx_load_physics fails with PHX_ERR_STATE; bad
+    parameters are rejected with PHX_ERR_INVALID."""
+    s = C.tiny(scale=0.01)
+    tr = phx.Tracer(s)
+    with pytest.raises(phx.PhxError):
+        tr.trace(flags=phx.F_HALO)
+    for bad in (dict(halo_n=2.0), dict(zenith=math.radians(95.0)), dict(vanes=9),
+                dict(vane_z_hi=100.0), dict(halo_f=1.5)):
+        with pytest.raises(phx.PhxError):
+            tr.load_physics(X.paraboloid_extras().replace(**bad))
+    tr.load_physics(X.paraboloid_extras())
+    tr.trace(flags=phx.F_HALO)
+    tr.close()
