@@ -46,7 +46,7 @@ def back_flops(stats, n_surf):
     tab = phx.stats_table(stats).astype(np.float64)
     decided_at = tab.sum(axis=0)
     reach = sum(decided_at[k + 1:].sum() for k in range(n_surf))
-    silicon = tab[[phx.DETECTED, phx.OFF_CHIP, phx.ESCAPED], n_surf].sum()
+    silicon = tab[[phx.DETECTED, phx.OFF_CHIP, phx.ESCAPED, phx.DEAD], n_surf].sum()
     return reach * FLOPS_SURFACE + float(stats[phx.STAT_NEWTON]) * FLOPS_NEWTON + silicon * FLOPS_SILICON
 
 
@@ -226,6 +226,71 @@ def gradient_leg(steps):
     }
 
 
+def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
+    """The headline step with aerosol extinction, dispersion, dome seeing, the micro-roughness
+    halo, the spider and the dead layer switched on (their kernels' EXTRA instantiations): time
+    per step, its cost against the core step, and each kernel's duration on a single stream."""
+    import torch
+    from paper_1504_06570_amd import phx
+    from paper_1504_06570_amd.scene import physics as X
+    tr.load_physics(X.tma_extras())
+    fx = flags | X.PHYS_EXTRA
+    img = tr.new_image()
+    stats = tr.new_stats()
+    tr.trace(img, flags=fx)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    tr.set_timing(True)
+    e0.record(stream)
+    for _ in range(steps):
+        tr.trace(img, flags=fx, stats=stats)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kt = tr.get_timing()
+    tr.set_timing(False)
+    ms = e0.elapsed_time(e1) / steps
+    st = stats.cpu().numpy()
+    tab = phx.stats_table(st) / steps
+    traced = float(st[phx.STAT_TRACED]) / steps
+    # each kernel alone (single stream)
+    tr.set_launch_config(pipeline=0)
+    tr.set_timing(True)
+    tr.trace(tr.new_image(), flags=fx)
+    torch.cuda.synchronize()
+    kti = tr.get_timing()
+    tr.set_timing(False)
+    tr.set_launch_config(pipeline=1)
+    ci = max(kti["chunks"], 1.0)
+    atm = scene.atmosphere
+    f_ms = kti["front"] / ci
+    f_bytes = traced * front_bytes_per_photon(atm.n_layers, atm.n_scales) / ci
+    f_gbs = f_bytes / (f_ms * 1e-3) * 1e-9
+    print(f"# extra physics {ms:.2f} ms/step ({ms / core_ms:.2f}x core), kernels {kt}",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": "the headline star with aerosol extinction, dispersion, dome seeing, the "
+                    "micro-roughness halo, a four-vane spider and a 50 nm dead layer on "
+                    "(pre-roll on; its geometric cull is off with entrance kicks)",
+        "photons_per_step": n_ph,
+        "ms_per_step": ms,
+        "value": n_ph / (ms * 1e-3),
+        "cost_vs_core": ms / core_ms,
+        "traced_per_step": traced,
+        "detected_per_step": float(tab[phx.DETECTED].sum()),
+        "extinct_per_step": float(tab[phx.EXTINCT].sum()),
+        "dead_per_step": float(tab[phx.DEAD].sum()),
+        "obscured_per_step": float(tab[phx.OBSCURED].sum()),
+        "stage_ms_per_step": {k: kt[k] / steps for k in ("generate", "front", "back")},
+        "stage_ms_single_stream": {k: kti[k] for k in ("generate", "front", "back")},
+        "front_kernel_single_stream": {"bound": "hbm", "achieved": f_gbs, "peak": PEAK_HBM_GBS,
+                                       "unit": "GB/s", "frac": f_gbs / PEAK_HBM_GBS,
+                                       "launch_ms": f_ms},
+        "back_kernel_single_stream_ms": kti["back"] / ci,
+    }
+
+
 def copy_probe():
     """A plain 1 GiB device copy, for calibrating the HBM byte counters."""
     import torch
@@ -252,6 +317,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the many-source batched leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the leg with the per-photon physics beyond the core path")
     ap.add_argument("--only", choices=("batched", "gradient"), default=None,
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
@@ -362,6 +429,9 @@ def main():
         nc_ms = e0.elapsed_time(e1)
         extra["value_without_preroll"] = n_ph / (nc_ms * 1e-3)
         extra["ms_per_step_without_preroll"] = nc_ms
+
+    if not args.no_extras:
+        extra["extra_physics"] = extras_leg(tr, scene, flags, max(args.steps, 1), n_ph, ms)
 
     cpu = None
     if not args.skip_cpu:
