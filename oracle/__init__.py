@@ -54,7 +54,9 @@ class Extra(C.Structure):
                 ("halo_max", C.c_double), ("dead", C.c_double), ("vanes", C.c_int32),
                 ("pad", C.c_int32), ("vane_angle", C.c_double), ("vane_width", C.c_double),
                 ("vane_r_in", C.c_double), ("vane_r_out", C.c_double), ("vane_z_lo", C.c_double),
-                ("vane_z_hi", C.c_double)]
+                ("vane_z_hi", C.c_double), ("kick_r0", C.c_double), ("kick_L0", C.c_double),
+                ("kick_kappa_crit", C.c_double), ("kick_kappa_max", C.c_double),
+                ("kick_fraction", C.c_double * MAX_LAYERS)]
 
 
 class Scene(C.Structure):
@@ -139,6 +141,11 @@ def lib():
             L.orc_halo_sample.argtypes = [C.c_uint32, C.c_int32, C.c_uint64, C.c_double,
                                           C.c_double, C.POINTER(C.c_double)]
             L.orc_halo_sample.restype = C.c_int
+            L.orc_kick_variance.argtypes = [C.POINTER(Scene), C.c_int]
+            L.orc_kick_variance.restype = C.c_double
+            L.orc_second_kick.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_int,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
+            L.orc_second_kick.restype = C.c_int
             L.orc_jacobian.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_uint64,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32)]
@@ -233,7 +240,10 @@ class Oracle:
         x = getattr(scene, "extras", None)
         if x is not None:
             for name, _ in Extra._fields_:
-                if name != "pad":
+                if name == "kick_fraction":
+                    for i, f in enumerate(x.kick_fraction[:MAX_LAYERS]):
+                        sc.ex.kick_fraction[i] = f
+                elif name != "pad":
                     setattr(sc.ex, name, getattr(x, name))
         self.sc = sc
         self.scene = scene
@@ -348,6 +358,16 @@ class Oracle:
         l, it = C.c_double(), C.c_int()
         st = lib().orc_intersect(C.byref(self.sc), k, qa, da, C.byref(l), C.byref(it))
         return st, l.value, it.value
+
+    def kick_variance(self, layer):
+        return lib().orc_kick_variance(C.byref(self.sc), layer)
+
+    def second_kick(self, src, photon, layer):
+        """(kx, ky, K): the second kick (radians at the reference wavelength) of one photon at
+        one layer and its number of scatterings."""
+        kx, ky = C.c_double(), C.c_double()
+        K = lib().orc_second_kick(C.byref(self.sc), src, photon, layer, C.byref(kx), C.byref(ky))
+        return kx.value, ky.value, K
 
     def sellmeier(self, lam):
         return lib().orc_sellmeier(C.byref(self.sc), lam)

@@ -15,7 +15,9 @@
  *   block 7: aerosol extinction, halo selection, halo azimuth, spider diffraction sign
  *   block 8: dome-seeing Box-Muller pair, (spare, spare)
  * Stream 1, block t: Sersic Gamma sampler trial t (normal pair words 0-1, acceptance word 2).
+ *   blocks 9, 10: second-kick scattering count of layers 0-3, 4-7 (one word per layer)
  * Stream 2, block t: micro-roughness halo trial t (proposal word 0, acceptance word 1).
+ * Stream 3, block 8 i + j: scattering j of layer i's second kick (wavenumber word 0, azimuth 1).
  *
  * Parity pins (tests/test_oracle_*.py): Philox vs an independent implementation (rocRAND, compiled
  * on the host); uniform conversion exhaustive bounds; pupil density; Sersic radius median and
@@ -541,6 +543,76 @@ int orc_halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, doubl
     return halo_sample(seed, src, photon, n, x_max, x_out, NULL);
 }
 
+/* Second kick of the hybrid atmosphere (section 2.3.2): the modes of a layer above kappa_crit
+ * act through their long-exposure PSF_>, the Fourier transform of B_>(rho) = exp(-D(rho)/2) with
+ * D(rho) = 4 pi int_{kappa_crit} [1 - J0(kappa rho)] Phi(kappa) kappa dkappa.  Writing
+ * D = 2 (s2 - C(rho)), with C the correlation of the high-frequency phase (the transform of Phi
+ * restricted to kappa > kappa_crit) and s2 = C(0) its variance, gives
+ * B_> = exp(-s2) sum_k C^k / k!: PSF_> is a compound Poisson law, K ~ Poisson(s2) scatterings,
+ * each a deflection by lambda_ref kappa / (2 pi) toward a uniform azimuth with kappa drawn from
+ * the density proportional to Phi(kappa) kappa on [kappa_crit, kappa_max].  Phi is the paper's
+ * phase spectrum, 0.033 (2 pi) k^2 C_n^2 kappa^(-11/3), with the Fried parameter of the paper
+ * (k^2 int C_n^2 = r0^(-5/3) / 0.423), in the von Karman form of the screens
+ * (kappa^2 + kappa0^2)^(-11/6), kappa0 = 2 pi / L0, for the layer's share of the turbulence
+ * integral (r0_i^(-5/3) = fraction_i r0^(-5/3)).  Readings: kappa_max is the finest screen's
+ * Nyquist wavenumber (the paper's high-frequency screens end there; its integral to infinity would
+ * give kicks of radians); at most 8 scatterings per layer (probability of more < 1e-14 for
+ * s2 < 0.2); the kicks are scaled by (lambda / lambda_ref)^(-1/5) like the refractive ones.
+ * Pinned: the characteristic function of the sampled kick against exp(-D(rho)/2) from the
+ * paper's Bessel integral at several rho; the fraction of unkicked photons exp(-s2). */
+static double kick_A(const orc_extra* x, double kappa) {
+    double k0 = TWO_PI / x->kick_L0;
+    return pow(kappa * kappa + k0 * k0, -5.0 / 6.0);
+}
+
+double orc_kick_variance(const orc_scene* sc, int layer) {
+    const orc_extra* x = &sc->ex;
+    double c = 0.033 * TWO_PI / 0.423 * x->kick_fraction[layer] * pow(x->kick_r0, -5.0 / 3.0);
+    /* 2 pi int kappa Phi dkappa, int kappa (kappa^2 + k0^2)^(-11/6) = -(3/5) (.)^(-5/6) */
+    return TWO_PI * c * 0.6 * (kick_A(x, x->kick_kappa_crit) - kick_A(x, x->kick_kappa_max));
+}
+
+static int second_kick(const orc_scene* sc, int32_t si, uint64_t photon, int layer, double* kx,
+                       double* ky, double* margin) {
+    const orc_extra* x = &sc->ex;
+    double u[4];
+    draw(sc, si, photon, (uint32_t)(9 + layer / 4), 0, u);
+    double uk = u[layer % 4];
+    double s2 = orc_kick_variance(sc, layer);
+    /* K = the smallest k with P(K <= k) > u */
+    double p = exp(-s2), cum = p;
+    int K = 0;
+    note_margin(margin, uk - cum);
+    while (!(uk < cum) && K < 8) {
+        ++K;
+        p *= s2 / K;
+        cum += p;
+        note_margin(margin, uk - cum);
+    }
+    *kx = 0.0;
+    *ky = 0.0;
+    double A0 = kick_A(x, x->kick_kappa_crit);
+    double dA = A0 - kick_A(x, x->kick_kappa_max);
+    double k0 = TWO_PI / x->kick_L0;
+    for (int j = 0; j < K; ++j) {
+        double w[4];
+        draw(sc, si, photon, (uint32_t)(8 * layer + j), 3, w);
+        /* invert the wavenumber CDF (A(kappa_crit) - A(kappa)) / dA = w0 */
+        double A = A0 - w[0] * dA;
+        double kappa = sqrt(pow(A, -6.0 / 5.0) - k0 * k0);
+        double th = sc->lambda_ref * kappa / TWO_PI;
+        *kx += th * cos(TWO_PI * w[1]);
+        *ky += th * sin(TWO_PI * w[1]);
+    }
+    return K;
+}
+
+int orc_second_kick(const orc_scene* sc, int32_t src, uint64_t photon, int layer, double* kx,
+                    double* ky) {
+    double m = 1e300;
+    return second_kick(sc, src, photon, layer, kx, ky, &m);
+}
+
 /* Spider (section 2.4.1: rectangular volumes; section 2.4.2: edge diffraction after Freniere et
  * al.).  Vane k is the box u in [r_in, r_out], |v| <= w/2, z in [z_lo, z_hi] in the frame of the
  * unit vectors u = (cos a_k, sin a_k, 0), v = (-sin a_k, cos a_k, 0), a_k = a_0 + 2 pi k / vanes.
@@ -742,6 +814,12 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
                 screen_lookup(sc, i, s, xs, ys, &ax, &ay);
                 gx += ax;
                 gy += ay;
+            }
+            if (sc->physics & ORC_SECOND_KICK) {
+                double kx, ky;
+                second_kick(sc, si, photon, i, &kx, &ky, &margin);
+                gx += kx;
+                gy += ky;
             }
             n[0] += scale * gx;
             n[1] += scale * gy;

@@ -24,7 +24,7 @@ enum { ORC_MIRROR = 0, ORC_REFRACT = 1, ORC_DETECTOR = 2 };
 enum { ORC_VACUUM = 0, ORC_GLASS = 1, ORC_SILICON = 2 };
 enum { ORC_ATMOSPHERE = 1, ORC_COATINGS = 2, ORC_SILICON_PHYS = 4, ORC_DIFFUSION = 8,
        ORC_AEROSOL = 16, ORC_DISPERSION = 32, ORC_DOME = 64, ORC_HALO = 128,
-       ORC_SPIDER = 2048, ORC_DEAD_LAYER = 4096 };
+       ORC_SPIDER = 2048, ORC_DEAD_LAYER = 4096, ORC_SECOND_KICK = 8192 };
 enum {
     ORC_DETECTED = 0, ORC_OFF_CHIP = 1, ORC_VIGNETTED = 2, ORC_ABSORBED = 3, ORC_MISSED = 4,
     ORC_NONCONV = 5, ORC_TIR = 6, ORC_ESCAPED = 7, ORC_OBSCURED = 8,
@@ -59,6 +59,9 @@ typedef struct {
     double dead;                       /* field-free layer at the silicon entrance surface   */
     int32_t vanes, pad;                /* spider: vanes at vane_angle + 2 pi k / vanes       */
     double vane_angle, vane_width, vane_r_in, vane_r_out, vane_z_lo, vane_z_hi;
+    /* hybrid atmosphere: second kick of the modes above kappa_crit (up to kappa_max) */
+    double kick_r0, kick_L0, kick_kappa_crit, kick_kappa_max;
+    double kick_fraction[ORC_MAX_LAYERS];
 } orc_extra;
 
 typedef struct {
@@ -137,6 +140,12 @@ void   orc_screen_gradient(const orc_scene* sc, int layer, int scale, double x, 
                            double* gx, double* gy);
 int    orc_gamma(uint32_t seed, int32_t src, uint64_t photon, double shape, double* out);
 double orc_air_refractivity(double lambda_m, double pressure, double temperature, double water);
+/* Second kick of one layer: phase variance of its high-frequency modes, and the kick (angle at
+ * the reference wavelength) photon `photon` receives at layer `layer`; returns the number of
+ * scatterings. */
+double orc_kick_variance(const orc_scene* sc, int layer);
+int    orc_second_kick(const orc_scene* sc, int32_t src, uint64_t photon, int layer,
+                       double* kx, double* ky);
 int    orc_halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, double x_max,
                        double* x_out);
 #endif

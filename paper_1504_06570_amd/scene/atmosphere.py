@@ -86,7 +86,10 @@ def opd_screen(rng: np.random.Generator, n: int, pixel: float, r0: float, L0: fl
 
 def make_atmosphere(seed: int, n: int = 2048, pixels=(1.0, 0.1, 0.01), r0: float = 0.15,
                     L0: float = 30.0, heights=LAYER_HEIGHTS, fractions=J_FRACTIONS,
-                    speeds=None, lambda_ref: float = 500e-9) -> Atmosphere:
+                    speeds=None, lambda_ref: float = 500e-9, kappa_cut=None) -> Atmosphere:
+    """kappa_cut: keep only the modes below this wavenumber (rad/m) -- the low-frequency screens
+    of the hybrid two-kick atmosphere (section 2.3.2), whose higher modes act through the second
+    kick instead.  The random draws are the same as without the cut."""
     rng = np.random.default_rng(seed)
     L = len(heights)
     if speeds is None:
@@ -94,6 +97,8 @@ def make_atmosphere(seed: int, n: int = 2048, pixels=(1.0, 0.1, 0.01), r0: float
     direction = rng.uniform(0.0, 2.0 * np.pi, L)
     wind = np.stack([speeds * np.cos(direction), speeds * np.sin(direction)], axis=1)
     bands = scale_bands(pixels, n)
+    if kappa_cut is not None:
+        bands = [(lo, min(hi, kappa_cut)) for lo, hi in bands]
     opd = np.empty((L, len(pixels), n, n), dtype=np.float32)
     for i in range(L):
         r0_i = fractions[i] ** (-3.0 / 5.0) * r0

@@ -89,6 +89,20 @@ def telescope(scale: float = 1.0) -> Scene:
                  physics=PHYS_COATINGS | PHYS_SILICON | PHYS_DIFFUSION, seed=2)
 
 
+def hybrid(scale: float = 1.0, screen_n: int = 2048, scene_seed: int = 3) -> Scene:
+    """``full`` with the hybrid two-kick atmosphere (section 2.3.2): the same screens limited to
+    wavenumbers below kappa_crit = 2 pi / (1.5 r0), the modes above it applied as the per-layer
+    second kick."""
+    from .physics import PHYS_SECOND_KICK, Extras
+    s = full(scale, screen_n, scene_seed)
+    x = Extras()
+    s.atmosphere = make_atmosphere(scene_seed, n=screen_n, kappa_cut=x.kick_kappa_crit)
+    s.physics = PHYS_ALL | PHYS_SECOND_KICK
+    s.extras = x
+    s.name = "hybrid"
+    return s
+
+
 def full(scale: float = 1.0, screen_n: int = 2048, scene_seed: int = 3) -> Scene:
     rng = np.random.default_rng(scene_seed)
     # uniform in the 1.75 deg disc
@@ -143,4 +157,5 @@ def gradients(scale: float = 1.0, screen_n: int = 2048, scene_seed: int = 5) -> 
                  physics=PHYS_ALL, seed=5, pupil_margin=0.3)
 
 
-CONFIGS = dict(tiny=tiny, telescope=telescope, full=full, batched=batched, gradients=gradients)
+CONFIGS = dict(tiny=tiny, telescope=telescope, full=full, batched=batched, gradients=gradients,
+               hybrid=hybrid)

@@ -3,13 +3,18 @@
 Defaults: aerosol tau0 = 0.02, Gamma = -1.28 and the micro-roughness halo (f, n, r0) =
 (0.135, 3.5, 0.1 deg) are the paper's values (sections 2.3.2 and 2.4.2).  The rest are synthetic
 site and hardware values: 30 deg zenith angle, a 2.7 km site (520 mmHg, 8 mmHg water, 12 C),
-dome seeing of 0.1 arcsec per axis, a halo truncated at 1 deg, a 50 nm field-free layer, and a
-four-vane spider holding the secondary of the three-mirror telescope.
+dome seeing of 0.1 arcsec per axis, a halo truncated at 1 deg, a 50 nm field-free layer, a
+four-vane spider holding the secondary of the three-mirror telescope, and the second kick of the
+hybrid atmosphere for the synthetic screens (r0 = 0.15 m, L0 = 30 m, the paper's split
+kappa_crit = 2 pi / (1.5 r0)).
 """
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, replace
+from dataclasses import dataclass, field, replace
+from typing import Tuple
+
+from .atmosphere import J_FRACTIONS
 
 # Flag bits of the extra physics (the same bits as the library's PHX_F_* flags).
 PHYS_AEROSOL = 1 << 4
@@ -18,8 +23,10 @@ PHYS_DOME = 1 << 6
 PHYS_HALO = 1 << 7
 PHYS_SPIDER = 1 << 11
 PHYS_DEAD_LAYER = 1 << 12
+PHYS_SECOND_KICK = 1 << 13
 PHYS_EXTRA = (PHYS_AEROSOL | PHYS_DISPERSION | PHYS_DOME | PHYS_HALO | PHYS_SPIDER |
               PHYS_DEAD_LAYER)
+MAX_LAYERS = 8
 
 ARCSEC = math.radians(1.0 / 3600.0)
 
@@ -47,6 +54,15 @@ class Extras:
     vane_r_out: float = 4.4
     vane_z_lo: float = 6.45
     vane_z_hi: float = 6.95
+    # hybrid atmosphere (second kick): the screens' r0 and L0, the split wavenumber
+    # 2 pi / (1.5 r0) of the paper, the finest screen's Nyquist wavenumber (1 cm pixels) and
+    # each layer's share of the turbulence integral
+    kick_r0: float = 0.15
+    kick_L0: float = 30.0
+    kick_kappa_crit: float = 2.0 * math.pi / (1.5 * 0.15)
+    kick_kappa_max: float = math.pi / 0.01
+    kick_fraction: Tuple[float, ...] = field(
+        default_factory=lambda: tuple(J_FRACTIONS) + (0.0,) * (MAX_LAYERS - len(J_FRACTIONS)))
 
     def replace(self, **kw) -> "Extras":
         return replace(self, **kw)
