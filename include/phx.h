@@ -89,6 +89,8 @@ enum {
     PHX_F_HALO = 1u << 7,       /* micro-roughness halo (section 2.4.2)                    */
     PHX_F_SPIDER = 1u << 11,    /* spider shadow and edge diffraction (2.4.1-2.4.2)        */
     PHX_F_DEAD_LAYER = 1u << 12,/* field-free dead layer (section 2.4.2; needs SILICON)    */
+    PHX_F_SECOND_KICK = 1u << 13,/* hybrid atmosphere: second kick per layer (2.3.2; needs
+                                   ATMOSPHERE; the pre-roll then keeps every pupil sample)   */
     PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
                                    worst-case transmission of any coated surface (section 3.2,
                                    dynamic transmission optimisation), pupil samples whose
@@ -178,7 +180,16 @@ typedef struct {
  *    mid-height, by lambda / (4 pi max(d, lambda)) across the nearest vane (sign from its random
  *    word), d = the closest distance between the ray and a long edge of a vane.
  *  - Dead layer (section 2.4.2): an electron converted less than dead_layer below the surface the
- *    light enters is removed (PHX_DEAD). */
+ *    light enters is removed (PHX_DEAD).
+ *  - Second kick (section 2.3.2, hybrid two-kick atmosphere): the screens carry the modes below
+ *    kick_kappa_crit (rad/m); at layer i the modes above it deflect the photon by a draw from
+ *    their long-exposure PSF, the Fourier transform of exp(-D(rho)/2): K ~ Poisson(s2_i)
+ *    scatterings (at most 8), each lambda_ref kappa / (2 pi) toward a uniform azimuth with kappa
+ *    from the phase spectrum 0.033 (2 pi) / 0.423 r0_i^(-5/3) (kappa^2 + (2 pi / L0)^2)^(-11/6)
+ *    on [kappa_crit, kappa_max], r0_i = kick_fraction[i]^(-3/5) kick_r0 (at lambda_ref), s2_i its
+ *    integral; the sum is added to the layer's refractive kick and scaled with it by
+ *    (lambda / lambda_ref)^(-1/5).  Random numbers: block 9 + i/4 word i%4 (count), stream 3
+ *    block 8 i + j (scattering j: wavenumber, azimuth). */
 typedef struct {
     double zenith_angle, zenith_pa;
     double aerosol_tau0, aerosol_gamma;
@@ -190,6 +201,8 @@ typedef struct {
     int32_t spider_vanes, pad;
     double spider_angle, spider_width, spider_r_inner, spider_r_outer;
     double spider_z_low, spider_z_high;
+    double kick_r0, kick_L0, kick_kappa_crit, kick_kappa_max;
+    double kick_fraction[PHX_MAX_LAYERS];
 } phx_physics;
 
 /* Per-photon record written for sampled photons (PHX_F_EVENTS). */
@@ -296,7 +309,9 @@ phx_status phx_load_sources(phx_ctx ctx, const phx_source* src_host, int32_t n_s
  * temperature > -273.15, lambda0 > 0.16 um, dome_sigma >= 0, 0 <= halo_fraction <= 1,
  * 2 < halo_index <= 6, 0 < halo_r0, 0 < halo_max < pi/2, dead_layer >= 0, 0 <= spider_vanes <= 8
  * and (with vanes) width > 0, r_inner < r_outer, z_low < z_high <= the prescription's start
- * plane (load the prescription first).  Errors: PHX_ERR_INVALID, PHX_ERR_STATE. */
+ * plane (load the prescription first), kick_r0 > 0, kick_L0 > 0,
+ * 0 < kick_kappa_crit < kick_kappa_max, 0 <= kick_fraction[i] with a phase variance of at most 2
+ * per layer.  Errors: PHX_ERR_INVALID, PHX_ERR_STATE. */
 phx_status phx_load_physics(phx_ctx ctx, const phx_physics* physics_host);
 
 /* Trace photons: for every source s in [src_begin, src_end), photons photon_begin ..

@@ -604,8 +604,35 @@ phx_status phx_load_physics(phx_ctx c, const phx_physics* x) {
             !(x->spider_z_high <= c->presc.z_start))
             return fail(c, PHX_ERR_INVALID, "bad spider geometry");
     }
-    phx::DevPhysics& X = c->host.ph;
-    X = phx::DevPhysics{};
+    {
+        const double g[] = {x->kick_r0, x->kick_L0, x->kick_kappa_crit, x->kick_kappa_max};
+        if (!finite_all(g, 4) || !finite_all(x->kick_fraction, PHX_MAX_LAYERS) ||
+            !(x->kick_r0 > 0.0) || !(x->kick_L0 > 0.0) || !(x->kick_kappa_crit > 0.0) ||
+            !(x->kick_kappa_crit < x->kick_kappa_max))
+            return fail(c, PHX_ERR_INVALID, "bad second-kick parameters");
+        for (int i = 0; i < PHX_MAX_LAYERS; ++i)
+            if (!(x->kick_fraction[i] >= 0.0))
+                return fail(c, PHX_ERR_INVALID, "negative second-kick fraction %d", i);
+    }
+    phx::DevPhysics X{};   // assigned to the parameter block only once every check passed
+    {
+        // phase variance of each layer's modes in [kappa_crit, kappa_max]: 2 pi int Phi kappa
+        const double k0 = 2.0 * M_PI / x->kick_L0;
+        const double A0 = std::pow(x->kick_kappa_crit * x->kick_kappa_crit + k0 * k0, -5.0 / 6.0);
+        const double A1 = std::pow(x->kick_kappa_max * x->kick_kappa_max + k0 * k0, -5.0 / 6.0);
+        X.kick_A0 = A0;
+        X.kick_dA = A0 - A1;
+        X.kick_k02 = k0 * k0;
+        for (int i = 0; i < PHX_MAX_LAYERS; ++i) {
+            const double cphi = 0.033 * (2.0 * M_PI) / 0.423 * x->kick_fraction[i] *
+                                std::pow(x->kick_r0, -5.0 / 3.0);
+            X.kick_s2[i] = (2.0 * M_PI) * cphi * 0.6 * (A0 - A1);
+            X.kick_p0[i] = std::exp(-X.kick_s2[i]);
+            if (!(X.kick_s2[i] <= 2.0))
+                return fail(c, PHX_ERR_INVALID, "second-kick phase variance %g of layer %d above 2",
+                            X.kick_s2[i], i);
+        }
+    }
     X.airmass = 1.0 / std::cos(x->zenith_angle);
     X.tau0 = x->aerosol_tau0;
     X.gamma = x->aerosol_gamma;
@@ -642,6 +669,7 @@ phx_status phx_load_physics(phx_ctx c, const phx_physics* x) {
     X.vane_z0 = x->spider_z_low;
     X.vane_z1 = x->spider_z_high;
     X.vane_zm = 0.5 * (x->spider_z_low + x->spider_z_high);
+    c->host.ph = X;
     c->have_phys = true;
     c->dirty = true;
     return PHX_OK;
@@ -838,7 +866,7 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
 namespace {
 
 constexpr uint32_t kExtraFlags = PHX_F_AEROSOL | PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO |
-                                 PHX_F_SPIDER | PHX_F_DEAD_LAYER;
+                                 PHX_F_SPIDER | PHX_F_DEAD_LAYER | PHX_F_SECOND_KICK;
 
 // Radii of the pupil annulus outside which a photon cannot reach the primary's clear aperture:
 // the aperture widened by a bound on the atmospheric displacement at the primary.  Each layer i
@@ -850,9 +878,10 @@ constexpr uint32_t kExtraFlags = PHX_F_AEROSOL | PHX_F_DISPERSION | PHX_F_DOME |
 void set_cull_radii(phx_ctx c, const phx_trace_args* a, phx::Launch& L) {
     L.cull_r2_lo = -1.0;
     L.cull_r2_hi = INFINITY;
-    // kicks at the telescope entrance (unbounded normal dome kick, halo, spider diffraction) move
-    // the landing point on the primary without a useful bound
-    if (a->flags & (PHX_F_DOME | PHX_F_HALO | PHX_F_SPIDER)) return;
+    // kicks at the telescope entrance (unbounded normal dome kick, halo, spider diffraction) and
+    // the second kick (up to 8 scatterings per layer, each up to lambda_ref kappa_max / 2 pi)
+    // move the landing point on the primary without a useful bound
+    if (a->flags & (PHX_F_DOME | PHX_F_HALO | PHX_F_SPIDER | PHX_F_SECOND_KICK)) return;
     const phx::DevSurface& s0 = c->host.surf[0];
     if (s0.moved || c->presc.n_surfaces < 2) return;
     double D = 1e-6;

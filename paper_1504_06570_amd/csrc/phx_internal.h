@@ -49,6 +49,10 @@ struct DevPhysics {
     int32_t vanes, pad;
     double vane_c[8], vane_s[8];     // unit vector of each vane
     double vane_hw, vane_r0, vane_r1, vane_z0, vane_z1, vane_zm, vane_w;
+    // second kick: per-layer phase variance above kappa_crit and exp(-variance); the wavenumber
+    // CDF through A(kappa) = (kappa^2 + kappa0^2)^(-5/6): A0 = A(kappa_crit), dA = A0 - A(kappa_max)
+    double kick_s2[PHX_MAX_LAYERS], kick_p0[PHX_MAX_LAYERS];
+    double kick_A0, kick_dA, kick_k02;
 };
 
 // Everything the trace kernel reads that does not change between launches with the same loads.
@@ -178,7 +182,7 @@ struct LaunchConfig {
 constexpr int kTileIters = 8;
 // Flags that select the sky and optics kernels carrying the per-photon physics beyond the core
 // path (the other instantiations hold none of its code).
-constexpr uint32_t kFrontExtra = PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO;
+constexpr uint32_t kFrontExtra = PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO | PHX_F_SECOND_KICK;
 constexpr uint32_t kBackExtra = PHX_F_AEROSOL | PHX_F_SPIDER;
 constexpr int kThreads = 256;   // workgroup size of every trace kernel
 

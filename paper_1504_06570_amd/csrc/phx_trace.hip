@@ -456,6 +456,39 @@ __device__ __forceinline__ double3 entrance_kicks(const DevParams& P, uint32_t f
     return n;
 }
 
+// Second kick of the hybrid atmosphere at layer i (section 2.3.2): the long-exposure PSF of the
+// layer's modes above kappa_crit, exp(-D/2) in the pupil, is the compound Poisson law of
+// K ~ Poisson(s2_i) scatterings (count word wk; K = the smallest k whose cumulative probability
+// exceeds the uniform, at most 8), each a deflection lambda_ref kappa / (2 pi) toward a uniform
+// azimuth with kappa from the phase spectrum on [kappa_crit, kappa_max] by inverting
+// (A(kappa_crit) - A(kappa)) / dA, A = (kappa^2 + kappa0^2)^(-5/6) (stream 3, block 8 i + j:
+// wavenumber x, azimuth y).  Adds the deflection to (gx, gy).
+__device__ __forceinline__ void second_kick(const DevParams& P, const Rng& rng, int i,
+                                            uint32_t wk, double& gx, double& gy) {
+    const DevPhysics& X = P.ph;
+    const double uk = u01(wk);
+    double p = X.kick_p0[i], cum = p;
+    if (uk < cum) return;
+    const double s2 = X.kick_s2[i];
+    int K = 0;
+    while (!(uk < cum) && K < 8) {
+        ++K;
+        p *= s2 / K;
+        cum += p;
+    }
+#pragma unroll 1
+    for (int j = 0; j < K; ++j) {
+        const uint4 w = rng.block((uint32_t)(8 * i + j), 3);
+        const double A = X.kick_A0 - u01(w.x) * X.kick_dA;
+        const double kappa = sqrt(exp(-1.2 * log(A)) - X.kick_k02);
+        const double th = P.lambda_ref * kappa / (2.0 * kPi);
+        double sa, ca;
+        sincospi(2.0 * u01(w.y), &sa, &ca);
+        gx += th * ca;
+        gy += th * sa;
+    }
+}
+
 // Aerosol extinction (section 2.3.2) and the spider (sections 2.4.1-2.4.2) at the telescope
 // entrance.  status 0: the photon lives (a ray that passes the spider is moved to the vanes'
 // mid-height and turned); PHX_EXTINCT with p the start-plane point; PHX_OBSCURED with p the first
@@ -618,6 +651,12 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
     if ((L.flags & PHX_F_ATMOSPHERE) && P.n_layers > 0) {
         const double kick = exp(-0.2 * log(lam / P.lambda_ref));
         const int64_t N = P.screen_n;
+        const bool second = EXTRA && (L.flags & PHX_F_SECOND_KICK);
+        uint4 kw0 = make_uint4(0, 0, 0, 0), kw1 = make_uint4(0, 0, 0, 0);
+        if (second) {
+            kw0 = rng.block(9);
+            if (P.n_layers > 4) kw1 = rng.block(10);
+        }
 #pragma unroll 1
         for (int i = P.n_layers - 1; i >= 0; --i) {
             const double h = P.height[i];
@@ -636,6 +675,7 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
                 gx += ax;
                 gy += ay;
             }
+            if (second) second_kick(P, rng, i, word_of(i < 4 ? kw0 : kw1, i & 3), gx, gy);
             n[0] += kick * gx;
             n[1] += kick * gy;
             const double inv = rsq_fast(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);

@@ -25,7 +25,7 @@ MOMENT_WORDS, MOMENT_Q_LOG2 = 12, 44
 F_ATMOSPHERE, F_COATINGS, F_SILICON, F_DIFFUSION = 1, 2, 4, 8
 F_CULL, F_EVENTS, F_MOMENTS = 1 << 8, 1 << 9, 1 << 10
 F_AEROSOL, F_DISPERSION, F_DOME, F_HALO = 1 << 4, 1 << 5, 1 << 6, 1 << 7
-F_SPIDER, F_DEAD_LAYER = 1 << 11, 1 << 12
+F_SPIDER, F_DEAD_LAYER, F_SECOND_KICK = 1 << 11, 1 << 12, 1 << 13
 STATUS = ["DETECTED", "OFF_CHIP", "VIGNETTED", "ABSORBED", "MISSED", "NONCONV", "TIR", "ESCAPED",
           "OBSCURED", "CULLED", "EXTINCT", "DEAD"]
 (DETECTED, OFF_CHIP, VIGNETTED, ABSORBED, MISSED, NONCONV, TIR, ESCAPED, OBSCURED, CULLED,
@@ -78,7 +78,9 @@ class Physics(C.Structure):
                 ("dead_layer", C.c_double), ("spider_vanes", C.c_int32), ("pad", C.c_int32),
                 ("spider_angle", C.c_double), ("spider_width", C.c_double),
                 ("spider_r_inner", C.c_double), ("spider_r_outer", C.c_double),
-                ("spider_z_low", C.c_double), ("spider_z_high", C.c_double)]
+                ("spider_z_low", C.c_double), ("spider_z_high", C.c_double),
+                ("kick_r0", C.c_double), ("kick_L0", C.c_double), ("kick_kappa_crit", C.c_double),
+                ("kick_kappa_max", C.c_double), ("kick_fraction", C.c_double * MAX_LAYERS)]
 
 
 def physics_struct(x) -> Physics:
@@ -93,6 +95,10 @@ def physics_struct(x) -> Physics:
     P.spider_vanes, P.spider_angle, P.spider_width = x.vanes, x.vane_angle, x.vane_width
     P.spider_r_inner, P.spider_r_outer = x.vane_r_in, x.vane_r_out
     P.spider_z_low, P.spider_z_high = x.vane_z_lo, x.vane_z_hi
+    P.kick_r0, P.kick_L0 = x.kick_r0, x.kick_L0
+    P.kick_kappa_crit, P.kick_kappa_max = x.kick_kappa_crit, x.kick_kappa_max
+    for i, f in enumerate(x.kick_fraction[:MAX_LAYERS]):
+        P.kick_fraction[i] = f
     return P
 
 

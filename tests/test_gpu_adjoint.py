@@ -117,6 +117,21 @@ def test_full_stack_with_extra_physics_matches_oracle(phx):
     assert n > 100
 
 
+def test_hybrid_atmosphere_matches_oracle(phx):
+    """The hybrid two-kick atmosphere in front of the perturbed optics: the second kick does not
+    depend on the perturbation, so the Jacobians agree with the oracle's central differences."""
+    from paper_1504_06570_amd.scene import physics as X
+    from paper_1504_06570_amd.scene.atmosphere import make_atmosphere
+    s = C.gradients(scale=1e-4, screen_n=128)
+    s.extras = X.tma_extras()
+    s.atmosphere = make_atmosphere(5, n=128, kappa_cut=s.extras.kick_kappa_crit)
+    s.physics = int(s.physics) | X.PHYS_SECOND_KICK
+    rng = np.random.default_rng(24)
+    s.perturbation = rng.uniform(-1, 1, C.N_PERTURB) * RANGE
+    n = compare_with_oracle(phx, s, 3000, sources=[0, 12, 24])
+    assert n > 100
+
+
 def test_vjp_equals_sum_of_jacobians(phx):
     """The reduced gradient equals sum_i xbar_i J_x,i + ybar_i J_y,i assembled on the host from
     the per-photon Jacobians (seeds, decode and fixed-order reductions)."""

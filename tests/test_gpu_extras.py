@@ -135,3 +135,43 @@ def test_physics_flags_need_parameters(phx):
     tr.load_physics(X.paraboloid_extras())
     tr.trace(flags=phx.F_HALO)
     tr.close()
+
+
+def test_second_kick_on_a_flat_screen(phx):
+    """The second kick alone (one layer with a flat screen, r0 = 5 cm: phase variance 1.04 above
+    kappa_crit, so 1 - exp(-1.04) of the photons scatter; 320-1080 nm so the
+    (lambda / lambda_ref)^(-1/5) scaling varies): photon by photon and pixel by pixel equal to the
+    oracle."""
+    from paper_1504_06570_amd.scene.atmosphere import uniform_gradient_atmosphere
+    s = C.tiny(scale=0.2)
+    s.sources.lam_lo[:] = 320e-9
+    s.sources.lam_hi[:] = 1080e-9
+    s.atmosphere = uniform_gradient_atmosphere(0.0, 0.0, n=64, pixels=(1.0,), heights=(0.0,))
+    s.physics = C.PHYS_ATMOSPHERE | X.PHYS_SECOND_KICK
+    s.extras = X.paraboloid_extras().replace(kick_r0=0.05, kick_fraction=(1.0,) + (0.0,) * 7)
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev)
+    assert rep["boundary_frac"] < 1e-4
+    assert parity.images_agree(gimg, oimg, gev, oev)
+    off = np.hypot(gev["xe"], gev["ye"])
+    p = 1.0 - math.exp(-O.Oracle(s).kick_variance(0))
+    n = len(gev)
+    assert abs((off > 1e-12).sum() - n * p) < 5 * math.sqrt(n * p * (1 - p))
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_hybrid_atmosphere_full_stack(phx, cull):
+    """The hybrid two-kick atmosphere (seven layers of screens below kappa_crit plus the per-layer
+    second kick) through the telescope, coatings, silicon and diffusion, with and without the
+    pre-roll: photon-by-photon and pixel parity."""
+    s = C.hybrid(scale=2e-4, screen_n=256)
+    flags = int(s.physics) | (phx.F_CULL if cull else 0)
+    gev, gimg, oev, oimg, st = run_both(phx, s, flags=flags)
+    if cull:
+        keep = gev["status"] != phx.CULLED
+        gev = gev[keep]
+        oev = oev[np.isin(oev["photon"], gev["photon"])]
+    rep = parity.compare(gev, oev)
+    assert rep["boundary_frac"] < 1e-4
+    assert rep["detected"] > 500
+    assert parity.images_agree(gimg, oimg, gev, oev)
