@@ -291,6 +291,70 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
     }
 
 
+def hybrid_leg(steps, n_ph, core_ms):
+    """The headline star through the hybrid two-kick atmosphere: the same seven layers with their
+    screens limited to wavenumbers below kappa_crit = 2 pi / (1.5 r0) and the higher modes applied
+    as the per-layer second kick (pre-roll on; its geometric cull is off with the kick)."""
+    import torch
+    from paper_1504_06570_amd import phx
+    from paper_1504_06570_amd.scene import configs as C
+    t0 = time.perf_counter()
+    scene = C.hybrid()
+    scene.sources.n_photons[:] = n_ph
+    tr = phx.Tracer(scene)
+    setup = time.perf_counter() - t0
+    flags = int(scene.physics) | phx.F_CULL
+    img = tr.new_image()
+    stats = tr.new_stats()
+    tr.trace(img, flags=flags)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    tr.set_timing(True)
+    e0.record(stream)
+    for _ in range(steps):
+        tr.trace(img, flags=flags, stats=stats)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kt = tr.get_timing()
+    tr.set_timing(False)
+    ms = e0.elapsed_time(e1) / steps
+    st = stats.cpu().numpy()
+    tab = phx.stats_table(st) / steps
+    tr.set_launch_config(pipeline=0)
+    tr.set_timing(True)
+    tr.trace(tr.new_image(), flags=flags)
+    torch.cuda.synchronize()
+    kti = tr.get_timing()
+    tr.set_timing(False)
+    ci = max(kti["chunks"], 1.0)
+    traced = float(st[phx.STAT_TRACED]) / steps
+    atm = scene.atmosphere
+    f_ms = kti["front"] / ci
+    f_gbs = traced * front_bytes_per_photon(atm.n_layers, atm.n_scales) / ci / (f_ms * 1e-3) * 1e-9
+    tr.close()
+    print(f"# hybrid atmosphere {ms:.2f} ms/step ({ms / core_ms:.2f}x core), setup {setup:.1f}s",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": "the headline star through the hybrid two-kick atmosphere (screens below "
+                    "kappa_crit = 2 pi / (1.5 r0), second kick per layer; phase variance above "
+                    "kappa_crit 0.167 summed over layers)",
+        "photons_per_step": n_ph,
+        "ms_per_step": ms,
+        "value": n_ph / (ms * 1e-3),
+        "cost_vs_core": ms / core_ms,
+        "traced_per_step": traced,
+        "detected_per_step": float(tab[phx.DETECTED].sum()),
+        "stage_ms_per_step": {k: kt[k] / steps for k in ("generate", "front", "back")},
+        "stage_ms_single_stream": {k: kti[k] for k in ("generate", "front", "back")},
+        "front_kernel_single_stream": {"bound": "hbm", "achieved": f_gbs, "peak": PEAK_HBM_GBS,
+                                       "unit": "GB/s", "frac": f_gbs / PEAK_HBM_GBS,
+                                       "launch_ms": f_ms},
+        "back_kernel_single_stream_ms": kti["back"] / ci,
+    }
+
+
 def copy_probe():
     """A plain 1 GiB device copy, for calibrating the HBM byte counters."""
     import torch
@@ -318,7 +382,8 @@ def main():
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the leg with the per-photon physics beyond the core path")
+                    help="skip the legs with the per-photon physics beyond the core path and the "
+                         "hybrid atmosphere")
     ap.add_argument("--only", choices=("batched", "gradient"), default=None,
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
@@ -432,6 +497,8 @@ def main():
 
     if not args.no_extras:
         extra["extra_physics"] = extras_leg(tr, scene, flags, max(args.steps, 1), n_ph, ms)
+        tr.close()
+        extra["hybrid_atmosphere"] = hybrid_leg(max(args.steps, 1), n_ph, ms)
 
     cpu = None
     if not args.skip_cpu:
