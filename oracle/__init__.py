@@ -56,7 +56,10 @@ class Extra(C.Structure):
                 ("vane_r_in", C.c_double), ("vane_r_out", C.c_double), ("vane_z_lo", C.c_double),
                 ("vane_z_hi", C.c_double), ("kick_r0", C.c_double), ("kick_L0", C.c_double),
                 ("kick_kappa_crit", C.c_double), ("kick_kappa_max", C.c_double),
-                ("kick_fraction", C.c_double * MAX_LAYERS)]
+                ("kick_fraction", C.c_double * MAX_LAYERS), ("si_voltage", C.c_double),
+                ("si_n_bulk", C.c_double), ("si_n_back", C.c_double), ("si_s_back", C.c_double),
+                ("si_n_front", C.c_double), ("si_s_front", C.c_double),
+                ("si_z_collect", C.c_double)]
 
 
 class Scene(C.Structure):
@@ -146,6 +149,12 @@ def lib():
             L.orc_second_kick.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_int,
                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
             L.orc_second_kick.restype = C.c_int
+            L.orc_field.argtypes = [C.POINTER(Scene), C.c_double]
+            L.orc_field.restype = C.c_double
+            L.orc_mobility.argtypes = [C.c_double, C.c_double]
+            L.orc_mobility.restype = C.c_double
+            L.orc_field_sigma.argtypes = [C.POINTER(Scene), C.c_double]
+            L.orc_field_sigma.restype = C.c_double
             L.orc_jacobian.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_uint64,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32)]
@@ -359,6 +368,12 @@ class Oracle:
         st = lib().orc_intersect(C.byref(self.sc), k, qa, da, C.byref(l), C.byref(it))
         return st, l.value, it.value
 
+    def field(self, z):
+        return lib().orc_field(C.byref(self.sc), z)
+
+    def field_sigma(self, depth):
+        return lib().orc_field_sigma(C.byref(self.sc), depth)
+
     def kick_variance(self, layer):
         return lib().orc_kick_variance(C.byref(self.sc), layer)
 
@@ -384,6 +399,11 @@ class Oracle:
 def air_refractivity(lam, pressure, temperature, water):
     """n - 1 of air (the Filippenko formula); lam in metres, pressures in mmHg, T in deg C."""
     return lib().orc_air_refractivity(lam, pressure, temperature, water)
+
+
+def mobility(E, T):
+    """Electron mobility (m^2/Vs) at field E (V/m) and temperature T (K)."""
+    return lib().orc_mobility(E, T)
 
 
 def halo_sample(seed, src, photon, n, x_max):

@@ -484,6 +484,67 @@ static void renormalise(double n[3]) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Field model of the charge diffusion (section 2.4.3).                                        */
+#define Q_E 1.602176634e-19      /* C */
+#define K_B_J 1.380649e-23       /* J/K */
+#define EPS0 8.8541878128e-12    /* F/m */
+#define EPS_SI 11.7              /* relative permittivity of silicon (the paper gives none) */
+
+/* E_z(z) = V / t_Si + q / (eps0 eps_Si) int_{t_Si}^{z} n_d(z') dz' with
+ * n_d(z) = n_bulk + n_b exp(-(t_Si - z)/s_b) + n_f exp(-z/s_f), z the height above the front
+ * (collecting) surface; the integral written out in closed form.  Pinned against quadrature of
+ * n_d and the uniform-field and uniform-doping closed forms of the diffusion width. */
+double orc_field(const orc_scene* sc, double z) {
+    const orc_extra* x = &sc->ex;
+    double t = sc->t_si;
+    double integral = x->si_n_bulk * (z - t);
+    if (x->si_s_back > 0.0)
+        integral += x->si_n_back * x->si_s_back * (exp(-(t - z) / x->si_s_back) - 1.0);
+    if (x->si_s_front > 0.0)
+        integral += x->si_n_front * x->si_s_front * (exp(-t / x->si_s_front) - exp(-z / x->si_s_front));
+    return x->si_voltage / t + Q_E / (EPS0 * EPS_SI) * integral;
+}
+
+/* Electron mobility with velocity saturation (section 2.4.3): v_m = 1.53e9 T^-0.87 cm/s,
+ * E_c = 1.01 T^1.55 V/cm, beta = 2.57e-2 T^0.66, mu = (v_m / E_c) / (1 + (E/E_c)^beta)^(1/beta)
+ * (E in V/cm, mu in cm^2/Vs, returned in m^2/Vs).  Reading: the printed outer exponent beta is
+ * 1/beta, the form whose drift velocity mu E tends to v_m at high field (pinned: the low-field
+ * mobility and the saturation velocity of electrons in silicon at 300 K). */
+double orc_mobility(double E, double T) {
+    double vm = 1.53e9 * pow(T, -0.87);
+    double Ec = 1.01 * pow(T, 1.55);
+    double beta = 2.57e-2 * pow(T, 0.66);
+    double Ecm = fabs(E) * 1e-2;
+    double mu = (vm / Ec) / pow(1.0 + pow(Ecm / Ec, beta), 1.0 / beta);
+    return mu * 1e-4;
+}
+
+/* Diffusion width of an electron converted at depth d below the entrance (back) surface of a
+ * back-illuminated device, i.e. at height z = t_Si - d above the front surface (section 2.4.3):
+ * sigma = sqrt(2 D t_c), D = mu(E(z), T) k T / q at the conversion height, collection time
+ * t_c = int_{z_c}^{z} dz' / |mu(E(z'), T) E(z')| to the collection height z_c.  Reading: D is taken
+ * at the conversion height, as the paper writes it; an electron converted at or below z_c is not
+ * spread.  The integral: composite Simpson rule with 8192 panels. */
+double orc_field_sigma(const orc_scene* sc, double depth) {
+    const orc_extra* x = &sc->ex;
+    double T = sc->temp_k;
+    double z = sc->t_si - depth, zc = x->si_z_collect;
+    if (!(z > zc)) return 0.0;
+    const int n = 8192;
+    double h = (z - zc) / n, sum = 0.0;
+    for (int i = 0; i <= n; ++i) {
+        double zi = zc + h * i;
+        double E = orc_field(sc, zi);
+        double f = 1.0 / fabs(orc_mobility(E, T) * E);
+        double w = (i == 0 || i == n) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+        sum += w * f;
+    }
+    double tc = sum * h / 3.0;
+    double D = orc_mobility(orc_field(sc, z), T) * K_B_J * T / Q_E;
+    return sqrt(2.0 * D * tc);
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Per-photon physics beyond the core path.                                                    */
 
 /* Refractivity n - 1 of air (section 2.3.2, the Filippenko formula): lambda in metres (the
@@ -995,7 +1056,9 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
                      * (section 2.4.3 simplified: sigma = sigma_max (t_Si - depth)/t_Si) */
                     double ud[4];
                     draw(sc, si, photon, 6, 0, ud);
-                    double sigma = sc->sigma_max * (sc->t_si - depth) / sc->t_si;
+                    double sigma = (sc->physics & ORC_FIELD_DIFFUSION)
+                                       ? orc_field_sigma(sc, depth)
+                                       : sc->sigma_max * (sc->t_si - depth) / sc->t_si;
                     double rad = sqrt(-2.0 * log(ud[0]));
                     xc += sigma * rad * cos(TWO_PI * ud[1]);
                     yc += sigma * rad * sin(TWO_PI * ud[1]);

@@ -24,7 +24,8 @@ enum { ORC_MIRROR = 0, ORC_REFRACT = 1, ORC_DETECTOR = 2 };
 enum { ORC_VACUUM = 0, ORC_GLASS = 1, ORC_SILICON = 2 };
 enum { ORC_ATMOSPHERE = 1, ORC_COATINGS = 2, ORC_SILICON_PHYS = 4, ORC_DIFFUSION = 8,
        ORC_AEROSOL = 16, ORC_DISPERSION = 32, ORC_DOME = 64, ORC_HALO = 128,
-       ORC_SPIDER = 2048, ORC_DEAD_LAYER = 4096, ORC_SECOND_KICK = 8192 };
+       ORC_SPIDER = 2048, ORC_DEAD_LAYER = 4096, ORC_SECOND_KICK = 8192,
+       ORC_FIELD_DIFFUSION = 16384 };
 enum {
     ORC_DETECTED = 0, ORC_OFF_CHIP = 1, ORC_VIGNETTED = 2, ORC_ABSORBED = 3, ORC_MISSED = 4,
     ORC_NONCONV = 5, ORC_TIR = 6, ORC_ESCAPED = 7, ORC_OBSCURED = 8,
@@ -62,6 +63,9 @@ typedef struct {
     /* hybrid atmosphere: second kick of the modes above kappa_crit (up to kappa_max) */
     double kick_r0, kick_L0, kick_kappa_crit, kick_kappa_max;
     double kick_fraction[ORC_MAX_LAYERS];
+    /* silicon field model of the diffusion: overdepletion voltage, doping (bulk, back-surface and
+     * front-surface exponentials, m^-3 and m), collection height above the front surface */
+    double si_voltage, si_n_bulk, si_n_back, si_s_back, si_n_front, si_s_front, si_z_collect;
 } orc_extra;
 
 typedef struct {
@@ -146,6 +150,12 @@ double orc_air_refractivity(double lambda_m, double pressure, double temperature
 double orc_kick_variance(const orc_scene* sc, int layer);
 int    orc_second_kick(const orc_scene* sc, int32_t src, uint64_t photon, int layer,
                        double* kx, double* ky);
+/* Field model of the charge diffusion: E_z (V/m) at height z above the front surface, electron
+ * mobility (m^2/Vs) at field E (V/m) and temperature T, and the diffusion sigma (m) of an
+ * electron converted at `depth` below the entrance (back) surface. */
+double orc_field(const orc_scene* sc, double z);
+double orc_mobility(double E, double T);
+double orc_field_sigma(const orc_scene* sc, double depth);
 int    orc_halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, double x_max,
                        double* x_out);
 #endif

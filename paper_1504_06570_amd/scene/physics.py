@@ -24,6 +24,7 @@ PHYS_HALO = 1 << 7
 PHYS_SPIDER = 1 << 11
 PHYS_DEAD_LAYER = 1 << 12
 PHYS_SECOND_KICK = 1 << 13
+PHYS_FIELD_DIFFUSION = 1 << 14
 PHYS_EXTRA = (PHYS_AEROSOL | PHYS_DISPERSION | PHYS_DOME | PHYS_HALO | PHYS_SPIDER |
               PHYS_DEAD_LAYER)
 MAX_LAYERS = 8
@@ -63,6 +64,17 @@ class Extras:
     kick_kappa_max: float = math.pi / 0.01
     kick_fraction: Tuple[float, ...] = field(
         default_factory=lambda: tuple(J_FRACTIONS) + (0.0,) * (MAX_LAYERS - len(J_FRACTIONS)))
+
+    # field model of the diffusion (100 um device at 173 K): 40 V overdepletion, 5e11 cm^-3 bulk
+    # doping, 5e13 cm^-3 surface layers 0.5 um deep (the field stays above 2.4e5 V/m), collection
+    # 2 um above the front surface
+    si_voltage: float = 40.0
+    si_n_bulk: float = 5e17
+    si_n_back: float = 5e19
+    si_s_back: float = 0.5e-6
+    si_n_front: float = 5e19
+    si_s_front: float = 0.5e-6
+    si_z_collect: float = 2e-6
 
     def replace(self, **kw) -> "Extras":
         return replace(self, **kw)

@@ -350,3 +350,95 @@ def test_second_kick_moves_the_image_by_the_kick():
     p = math.exp(-o.kick_variance(0))
     n = conv.sum()
     assert abs(zero - n * p) < 5 * math.sqrt(n * p * (1 - p))
+
+
+# ---------------------------------------------------------------------------------------------
+# Field model of the charge diffusion (section 2.4.3)
+# ---------------------------------------------------------------------------------------------
+KT_Q = 1.380649e-23 / 1.602176634e-19      # V/K
+EPS = 8.8541878128e-12 * 11.7
+
+
+def _field_scene(**kw):
+    s = H.flat_detector_scene(n_photons=2000, lam=350e-9,
+                              physics=C.PHYS_SILICON | C.PHYS_DIFFUSION | X.PHYS_FIELD_DIFFUSION)
+    s.extras = X.Extras(vanes=0).replace(**kw)
+    return s
+
+
+def test_mobility_matches_silicon_electron_data():
+    """The velocity-saturation mobility at 300 K: low-field electron mobility of silicon
+    1400-1600 cm^2/Vs and a saturated drift velocity of about 1e7 cm/s (textbook values); the
+    drift velocity rises monotonically with the field (the reading of the printed exponent)."""
+    mu0 = O.mobility(1.0, 300.0) * 1e4
+    assert 1400.0 < mu0 < 1600.0
+    v = [O.mobility(E, 300.0) * E for E in (1e3, 1e5, 1e6, 1e7, 1e8)]
+    assert np.all(np.diff(v) > 0)
+    assert 0.95e5 < O.mobility(1e9, 300.0) * 1e9 < 1.1e5
+    # colder silicon: higher low-field mobility
+    assert O.mobility(1.0, 173.0) > 2 * O.mobility(1.0, 300.0)
+
+
+def test_field_is_the_doping_integral():
+    """E_z(z) = V / t + q / (eps0 eps_Si) int_t^z n_d: the closed form against quadrature of the
+    doping profile (bulk + back and front exponentials)."""
+    from scipy import integrate
+    s = _field_scene()
+    o = O.Oracle(s)
+    x, t = s.extras, s.prescription.silicon.thickness
+    nd = lambda z: (x.si_n_bulk + x.si_n_back * math.exp(-(t - z) / x.si_s_back) +
+                    x.si_n_front * math.exp(-z / x.si_s_front))
+    for z in (0.0, 0.3e-6, 2e-6, 30e-6, 99e-6, t):
+        q = integrate.quad(nd, t, z, points=[0.5e-6, t - 0.5e-6] if 0 < z < t else None,
+                           limit=200, epsabs=0, epsrel=1e-12)[0]
+        want = x.si_voltage / t + 1.602176634e-19 / EPS * q
+        assert abs(o.field(z) - want) < 1e-9 * abs(want), (z, o.field(z), want)
+
+
+@pytest.mark.parametrize("depth", [0.0, 20e-6, 60e-6, 95e-6])
+def test_field_sigma_uniform_field_closed_form(depth):
+    """Undoped silicon: E = V / t everywhere, the mobility cancels and
+    sigma^2 = 2 kT (z - z_c) / (q E) (the familiar diffusion width of a drift over z - z_c)."""
+    s = _field_scene(si_n_bulk=0.0, si_n_back=0.0, si_n_front=0.0)
+    o = O.Oracle(s)
+    t, T = s.prescription.silicon.thickness, s.prescription.silicon.temperature
+    x = s.extras
+    z = t - depth
+    want = math.sqrt(2 * KT_Q * T * (z - x.si_z_collect) / (x.si_voltage / t))
+    assert abs(o.field_sigma(depth) - want) < 1e-9 * want
+
+
+@pytest.mark.parametrize("depth", [0.0, 40e-6, 90e-6])
+def test_field_sigma_uniform_doping_low_field(depth):
+    """Uniform doping at low field (400 K, 1 V over 100 um: E / E_c < 1e-2, so the mobility is its
+    low-field value to 0.2 %): E is linear, E(z) = E0 + a (z - t), and
+    sigma^2 = (2 kT / (q a)) ln(E(z) / E(z_c)) (within 0.5 %)."""
+    t = 100e-6
+    a = 5e3 / t
+    n = a * EPS / 1.602176634e-19
+    s = _field_scene(si_voltage=1.0, si_n_bulk=n, si_n_back=0.0, si_n_front=0.0)
+    s.prescription = s.prescription.replace(
+        silicon=s.prescription.silicon.__class__(thickness=t, temperature=400.0, sigma_max=4e-6))
+    o = O.Oracle(s)
+    x = s.extras
+    z = t - depth
+    E = lambda zz: 1.0 / t + a * (zz - t)
+    want = math.sqrt(2 * KT_Q * 400.0 / a * math.log(E(z) / E(x.si_z_collect)))
+    assert abs(o.field_sigma(depth) / want - 1.0) < 5e-3, (o.field_sigma(depth), want)
+
+
+def test_field_diffusion_in_the_trace():
+    """Blue light converts within nanometres of the entrance: the electron's offset from the landing
+    point divided by the field model's sigma at that depth is N(0, 1) (the sigma primitive pinned
+    above supplies sigma)."""
+    s = _field_scene()
+    s.sources.n_photons[:] = 8000
+    o = O.Oracle(s)
+    ev = o.trace_sources(threads=8)
+    conv = ev["status"] <= O.OFF_CHIP
+    sig = o.field_sigma(0.0)
+    assert sig > 1e-6
+    dx = (ev["xe"] - ev["x"])[conv] / sig
+    dy = (ev["ye"] - ev["y"])[conv] / sig
+    assert stats.kstest(dx, "norm").pvalue > 1e-3
+    assert stats.kstest(dy, "norm").pvalue > 1e-3
