@@ -91,6 +91,8 @@ enum {
     PHX_F_DEAD_LAYER = 1u << 12,/* field-free dead layer (section 2.4.2; needs SILICON)    */
     PHX_F_SECOND_KICK = 1u << 13,/* hybrid atmosphere: second kick per layer (2.3.2; needs
                                    ATMOSPHERE; the pre-roll then keeps every pupil sample)   */
+    PHX_F_FIELD_DIFFUSION = 1u << 14,/* diffusion width from the silicon field model (2.4.3;
+                                   with DIFFUSION, in place of sigma_max x drift fraction)   */
     PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
                                    worst-case transmission of any coated surface (section 3.2,
                                    dynamic transmission optimisation), pupil samples whose
@@ -189,7 +191,17 @@ typedef struct {
  *    on [kappa_crit, kappa_max], r0_i = kick_fraction[i]^(-3/5) kick_r0 (at lambda_ref), s2_i its
  *    integral; the sum is added to the layer's refractive kick and scaled with it by
  *    (lambda / lambda_ref)^(-1/5).  Random numbers: block 9 + i/4 word i%4 (count), stream 3
- *    block 8 i + j (scattering j: wavenumber, azimuth). */
+ *    block 8 i + j (scattering j: wavenumber, azimuth).
+ *  - Field diffusion (section 2.4.3): an electron converted at height z above the front
+ *    (collecting) surface of the back-illuminated device spreads with sigma = sqrt(2 D t_c),
+ *    D = mu(E(z), T) k T / q, t_c = int_{z_collect}^{z} dz' / |mu E|, with
+ *    E_z(z) = si_voltage / t_Si + q / (eps0 11.7) int_{t_Si}^{z} n_d, n_d = si_n_bulk +
+ *    si_n_back exp(-(t_Si - z)/si_s_back) + si_n_front exp(-z/si_s_front) (m^-3, m) and the
+ *    velocity-saturation mobility mu = (v_m/E_c) / (1 + (E/E_c)^beta)^(1/beta), v_m = 1.53e9
+ *    T^-0.87 cm/s, E_c = 1.01 T^1.55 V/cm, beta = 2.57e-2 T^0.66; no spread at or below
+ *    z_collect.  The library tabulates sigma^2 against depth (131073 points) when the
+ *    parameters are loaded (and again when a prescription is loaded after them); a trace with
+ *    PHX_F_FIELD_DIFFUSION fails with PHX_ERR_INVALID if E_z is not positive across the device. */
 typedef struct {
     double zenith_angle, zenith_pa;
     double aerosol_tau0, aerosol_gamma;
@@ -203,6 +215,7 @@ typedef struct {
     double spider_z_low, spider_z_high;
     double kick_r0, kick_L0, kick_kappa_crit, kick_kappa_max;
     double kick_fraction[PHX_MAX_LAYERS];
+    double si_voltage, si_n_bulk, si_n_back, si_s_back, si_n_front, si_s_front, si_z_collect;
 } phx_physics;
 
 /* Per-photon record written for sampled photons (PHX_F_EVENTS). */
@@ -311,7 +324,8 @@ phx_status phx_load_sources(phx_ctx ctx, const phx_source* src_host, int32_t n_s
  * and (with vanes) width > 0, r_inner < r_outer, z_low < z_high <= the prescription's start
  * plane (load the prescription first), kick_r0 > 0, kick_L0 > 0,
  * 0 < kick_kappa_crit < kick_kappa_max, 0 <= kick_fraction[i] with a phase variance of at most 2
- * per layer.  Errors: PHX_ERR_INVALID, PHX_ERR_STATE. */
+ * per layer, si_voltage > 0, doping densities >= 0 with positive depths, 0 <= si_z_collect < t_Si.
+ * Errors: PHX_ERR_INVALID, PHX_ERR_STATE, PHX_ERR_NOMEM, PHX_ERR_HIP. */
 phx_status phx_load_physics(phx_ctx ctx, const phx_physics* physics_host);
 
 /* Trace photons: for every source s in [src_begin, src_end), photons photon_begin ..

@@ -22,6 +22,10 @@ struct phx_ctx_s {
     std::string err;
     bool have_presc = false, have_src = false, have_coat = false, have_screens = false;
     bool have_phys = false;
+    phx_physics phys{};                  // last loaded physics parameters (re-derived on a new
+                                         // prescription)
+    bool field_ok = false;               // E_z > 0 across the device (field diffusion usable)
+    double* d_sig2 = nullptr;            // sigma^2 against depth [kSig2Cells + 1]
     phx_prescription presc{};
     double theta[PHX_N_THETA] = {0};
     DevParams host{};          // host image of the device parameter block
@@ -409,6 +413,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_coat);
     free_dev(c->d_coat_thr);
     free_dev(c->d_esc_thr);
+    free_dev(c->d_sig2);
     free_dev(c->d_grad);
     free_dev(c->d_src);
     free_dev(c->d_cdf);
@@ -506,7 +511,12 @@ phx_status phx_load_prescription(phx_ctx c, const phx_prescription* p) {
     c->have_presc = true;
     build_cull_order(c);
     c->dirty = true;
-    return build_escape_table(c);
+    const phx_status st = build_escape_table(c);
+    if (st != PHX_OK || !c->have_phys) return st;
+    // the physics parameters' derived tables depend on the silicon and the start plane
+    const phx_physics keep = c->phys;
+    c->have_phys = false;
+    return phx_load_physics(c, &keep);
 }
 
 phx_status phx_set_perturbation(phx_ctx c, const double* theta, int32_t n) {
@@ -614,6 +624,15 @@ phx_status phx_load_physics(phx_ctx c, const phx_physics* x) {
             if (!(x->kick_fraction[i] >= 0.0))
                 return fail(c, PHX_ERR_INVALID, "negative second-kick fraction %d", i);
     }
+    {
+        const double g[] = {x->si_voltage, x->si_n_bulk, x->si_n_back, x->si_s_back,
+                            x->si_n_front, x->si_s_front, x->si_z_collect};
+        if (!finite_all(g, 7) || !(x->si_voltage > 0.0) || !(x->si_n_bulk >= 0.0) ||
+            !(x->si_n_back >= 0.0) || !(x->si_n_front >= 0.0) || !(x->si_s_back > 0.0) ||
+            !(x->si_s_front > 0.0) || !(x->si_z_collect >= 0.0) ||
+            !(x->si_z_collect < c->presc.si_thickness))
+            return fail(c, PHX_ERR_INVALID, "bad silicon field parameters");
+    }
     phx::DevPhysics X{};   // assigned to the parameter block only once every check passed
     {
         // phase variance of each layer's modes in [kappa_crit, kappa_max]: 2 pi int Phi kappa
@@ -669,7 +688,69 @@ phx_status phx_load_physics(phx_ctx c, const phx_physics* x) {
     X.vane_z0 = x->spider_z_low;
     X.vane_z1 = x->spider_z_high;
     X.vane_zm = 0.5 * (x->spider_z_low + x->spider_z_high);
+    // field diffusion: sigma^2 against depth, the collection time accumulated from the
+    // collection height upward by 4-point Gauss-Legendre per table cell
+    std::vector<double> sig2(phx::kSig2Cells + 1, 0.0);
+    bool ok = true;
+    {
+        const double t = c->presc.si_thickness, T = c->presc.si_temperature, zc = x->si_z_collect;
+        const double qe = 1.602176634e-19, kT_q = 1.380649e-23 * T / qe;
+        const double k_eps = qe / (8.8541878128e-12 * 11.7);
+        auto field = [&](double z) {
+            return x->si_voltage / t +
+                   k_eps * (x->si_n_bulk * (z - t) +
+                            x->si_n_back * x->si_s_back * (std::exp((z - t) / x->si_s_back) - 1.0) +
+                            x->si_n_front * x->si_s_front *
+                                (std::exp(-t / x->si_s_front) - std::exp(-z / x->si_s_front)));
+        };
+        const double vm = 1.53e9 * std::pow(T, -0.87), Ec = 1.01 * std::pow(T, 1.55);
+        const double beta = 2.57e-2 * std::pow(T, 0.66);
+        auto mobility = [&](double E) {   // m^2/Vs at |E| V/m
+            const double r = std::fabs(E) * 1e-2 / Ec;
+            return 1e-4 * (vm / Ec) / std::pow(1.0 + std::pow(r, beta), 1.0 / beta);
+        };
+        const double gx[4] = {-0.8611363115940526, -0.3399810435848563, 0.3399810435848563,
+                              0.8611363115940526};
+        const double gw[4] = {0.3478548451374538, 0.6521451548625461, 0.6521451548625461,
+                              0.3478548451374538};
+        const int N = phx::kSig2Cells;
+        const double dmax = t - zc, h = dmax / N;
+        double tc = 0.0;   // collection time from height zc
+        for (int k = N; k >= 0; --k) {
+            const double z = t - h * k;   // height of table entry k (depth h k)
+            if (k < N) {
+                const double mid = z - 0.5 * h;   // the cell between heights z - h and z
+                double cell = 0.0;
+                for (int i = 0; i < 4; ++i) {
+                    const double zi = mid + 0.5 * h * gx[i];
+                    const double E = field(zi);
+                    if (!(E > 0.0)) ok = false;
+                    cell += gw[i] / (mobility(E) * E);
+                }
+                tc += 0.5 * h * cell;
+            }
+            const double E = field(z);
+            if (!(E > 0.0)) ok = false;
+            sig2[k] = 2.0 * mobility(E) * kT_q * tc;
+        }
+        X.n_sig2 = N;
+        X.sig2_dmax = dmax;
+        X.sig2_inv_step = N / dmax;
+    }
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    if (!c->d_sig2) {
+        const hipError_t e = hipMalloc((void**)&c->d_sig2, sig2.size() * sizeof(double));
+        if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "sigma table: %s", hipGetErrorString(e));
+    }
+    {
+        const hipError_t e = hipMemcpy(c->d_sig2, sig2.data(), sig2.size() * sizeof(double),
+                                       hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(sigma table)");
+    }
+    X.sig2 = c->d_sig2;
     c->host.ph = X;
+    c->phys = *x;
+    c->field_ok = ok;
     c->have_phys = true;
     c->dirty = true;
     return PHX_OK;
@@ -866,7 +947,8 @@ phx_status phx_load_sources(phx_ctx c, const phx_source* src, int32_t n_src, con
 namespace {
 
 constexpr uint32_t kExtraFlags = PHX_F_AEROSOL | PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO |
-                                 PHX_F_SPIDER | PHX_F_DEAD_LAYER | PHX_F_SECOND_KICK;
+                                 PHX_F_SPIDER | PHX_F_DEAD_LAYER | PHX_F_SECOND_KICK |
+                                 PHX_F_FIELD_DIFFUSION;
 
 // Radii of the pupil annulus outside which a photon cannot reach the primary's clear aperture:
 // the aperture widened by a bound on the atmospheric displacement at the primary.  Each layer i
@@ -928,6 +1010,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         return fail(c, PHX_ERR_STATE, "PHX_F_ATMOSPHERE without loaded screens");
     if ((a->flags & kExtraFlags) && !c->have_phys)
         return fail(c, PHX_ERR_STATE, "per-photon physics flags without phx_load_physics");
+    if ((a->flags & PHX_F_FIELD_DIFFUSION) && !c->field_ok)
+        return fail(c, PHX_ERR_INVALID, "silicon field model: E_z not positive across the device");
     if (a->flags & PHX_F_COATINGS)
         for (int k = 0; k < c->presc.n_surfaces; ++k) {
             const int co = c->presc.surf[k].coating;

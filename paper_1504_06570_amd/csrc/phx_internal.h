@@ -53,7 +53,12 @@ struct DevPhysics {
     // CDF through A(kappa) = (kappa^2 + kappa0^2)^(-5/6): A0 = A(kappa_crit), dA = A0 - A(kappa_max)
     double kick_s2[PHX_MAX_LAYERS], kick_p0[PHX_MAX_LAYERS];
     double kick_A0, kick_dA, kick_k02;
+    // field diffusion: sigma^2 at depths k dmax / n_sig2 below the entrance, k = 0..n_sig2
+    const double* sig2;
+    double sig2_inv_step, sig2_dmax;
+    int32_t n_sig2, sig2_pad;
 };
+constexpr int kSig2Cells = 131072;   // cells of 0.75 nm over 98 um: sigma within 2e-14 m
 
 // Everything the trace kernel reads that does not change between launches with the same loads.
 struct DevParams {

@@ -699,6 +699,23 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
     f.lam = lam;
 }
 
+// Field model of the diffusion width (section 2.4.3): sigma^2 interpolated linearly in the
+// library's table against depth below the entrance surface (zero beyond the collection height);
+// `slope` = d sigma / d depth of the interpolant.
+__device__ __forceinline__ double field_sigma(const DevParams& P, double depth, double& slope) {
+    const DevPhysics& X = P.ph;
+    slope = 0.0;
+    if (!(depth < X.sig2_dmax)) return 0.0;
+    const double f = depth * X.sig2_inv_step;
+    const int k = min((int)f, X.n_sig2 - 1);
+    const double a = f - k;
+    const double s2 = (1.0 - a) * X.sig2[k] + a * X.sig2[k + 1];
+    if (!(s2 > 0.0)) return 0.0;
+    const double sigma = sqrt(s2);
+    slope = (X.sig2[k + 1] - X.sig2[k]) * X.sig2_inv_step / (2.0 * sigma);
+    return sigma;
+}
+
 // Silicon (sections 2.4.2-2.4.3): conversion after a path of mean free path x Exp(1) along the
 // refracted direction d; escape if deeper than the silicon; Gaussian diffusion with sigma
 // proportional to the drift distance to the collecting surface.  With PHX_F_DEAD_LAYER an
@@ -718,7 +735,10 @@ __device__ __noinline__ int sensor_stage(const DevParams& P, const Launch& L, co
         yc += d[1] * L_conv;
         if (L.flags & PHX_F_DIFFUSION) {
             const uint4 wd = rng.block(6);
-            const double sigma = P.sigma_max * (P.t_si - depth) / P.t_si;
+            double slope;
+            const double sigma = (L.flags & PHX_F_FIELD_DIFFUSION)
+                                     ? field_sigma(P, depth, slope)
+                                     : P.sigma_max * (P.t_si - depth) / P.t_si;
             const double rad = sqrt(-2.0 * log(u01(wd.x)));
             double sa, ca;
             sincospi(2.0 * u01(wd.y), &sa, &ca);
@@ -1880,7 +1900,10 @@ __device__ void adjoint_sweep(const DevParams& P, const Launch& L, const Rng& rn
                     sincospi(2.0 * u01(wd.y), &sa, &ca);
                     ca *= rad;
                     sa *= rad;
-                    kz = -P.sigma_max * Lc * (d1[2] >= 0.0 ? 1.0 : -1.0) / P.t_si;
+                    // d sigma / d d1z through the depth Lc |d1z|
+                    double slope = -P.sigma_max / P.t_si;
+                    if (L.flags & PHX_F_FIELD_DIFFUSION) field_sigma(P, Lc * fabs(d1[2]), slope);
+                    kz = slope * Lc * (d1[2] >= 0.0 ? 1.0 : -1.0);
                 }
             }
 #pragma unroll

@@ -25,7 +25,7 @@ MOMENT_WORDS, MOMENT_Q_LOG2 = 12, 44
 F_ATMOSPHERE, F_COATINGS, F_SILICON, F_DIFFUSION = 1, 2, 4, 8
 F_CULL, F_EVENTS, F_MOMENTS = 1 << 8, 1 << 9, 1 << 10
 F_AEROSOL, F_DISPERSION, F_DOME, F_HALO = 1 << 4, 1 << 5, 1 << 6, 1 << 7
-F_SPIDER, F_DEAD_LAYER, F_SECOND_KICK = 1 << 11, 1 << 12, 1 << 13
+F_SPIDER, F_DEAD_LAYER, F_SECOND_KICK, F_FIELD_DIFFUSION = 1 << 11, 1 << 12, 1 << 13, 1 << 14
 STATUS = ["DETECTED", "OFF_CHIP", "VIGNETTED", "ABSORBED", "MISSED", "NONCONV", "TIR", "ESCAPED",
           "OBSCURED", "CULLED", "EXTINCT", "DEAD"]
 (DETECTED, OFF_CHIP, VIGNETTED, ABSORBED, MISSED, NONCONV, TIR, ESCAPED, OBSCURED, CULLED,
@@ -80,7 +80,10 @@ class Physics(C.Structure):
                 ("spider_r_inner", C.c_double), ("spider_r_outer", C.c_double),
                 ("spider_z_low", C.c_double), ("spider_z_high", C.c_double),
                 ("kick_r0", C.c_double), ("kick_L0", C.c_double), ("kick_kappa_crit", C.c_double),
-                ("kick_kappa_max", C.c_double), ("kick_fraction", C.c_double * MAX_LAYERS)]
+                ("kick_kappa_max", C.c_double), ("kick_fraction", C.c_double * MAX_LAYERS),
+                ("si_voltage", C.c_double), ("si_n_bulk", C.c_double), ("si_n_back", C.c_double),
+                ("si_s_back", C.c_double), ("si_n_front", C.c_double), ("si_s_front", C.c_double),
+                ("si_z_collect", C.c_double)]
 
 
 def physics_struct(x) -> Physics:
@@ -99,6 +102,9 @@ def physics_struct(x) -> Physics:
     P.kick_kappa_crit, P.kick_kappa_max = x.kick_kappa_crit, x.kick_kappa_max
     for i, f in enumerate(x.kick_fraction[:MAX_LAYERS]):
         P.kick_fraction[i] = f
+    for name in ("si_voltage", "si_n_bulk", "si_n_back", "si_s_back", "si_n_front", "si_s_front",
+                 "si_z_collect"):
+        setattr(P, name, getattr(x, name))
     return P
 
 

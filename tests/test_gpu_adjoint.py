@@ -132,6 +132,21 @@ def test_hybrid_atmosphere_matches_oracle(phx):
     assert n > 100
 
 
+def test_field_diffusion_matches_oracle(phx):
+    """With the field model of the diffusion the electron offset depends on the depth through the
+    sigma table; the Jacobians (which carry d sigma / d depth through the refracted direction)
+    agree with the oracle's central differences."""
+    from paper_1504_06570_amd.scene import physics as X
+    s = C.telescope(scale=1e-4)
+    s.physics = int(s.physics) | X.PHYS_FIELD_DIFFUSION
+    s.extras = X.tma_extras()
+    rng = np.random.default_rng(25)
+    s.perturbation = rng.uniform(-1, 1, C.N_PERTURB) * RANGE
+    # the oracle integrates each photon's collection time in every finite-difference trace
+    n = compare_with_oracle(phx, s, 800, sources=[0, 220, 440])
+    assert n > 50
+
+
 def test_vjp_equals_sum_of_jacobians(phx):
     """The reduced gradient equals sum_i xbar_i J_x,i + ybar_i J_y,i assembled on the host from
     the per-photon Jacobians (seeds, decode and fixed-order reductions)."""

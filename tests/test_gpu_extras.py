@@ -47,9 +47,9 @@ def test_each_effect_on_the_paraboloid(phx, flag, kw):
     s.sources.lam_lo[:] = 320e-9
     s.sources.lam_hi[:] = 1080e-9
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-4
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     if flag == X.PHYS_AEROSOL:
         assert (gev["status"] == phx.EXTINCT).mean() > 0.1
     if flag == X.PHYS_SPIDER:
@@ -63,10 +63,10 @@ def test_dead_layer_on_the_flat_detector(phx):
                               physics=C.PHYS_SILICON | C.PHYS_DIFFUSION | X.PHYS_DEAD_LAYER)
     s.extras = X.Extras(dead=100e-9, vanes=0)   # no spider above this detector's start plane
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-4
     assert (gev["status"] == phx.DEAD).mean() > 0.1
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
 
 
 def _full_extras(scale=2e-4, screen_n=256):
@@ -92,10 +92,10 @@ def test_full_stack_with_every_effect(phx, cull):
         keep = ~culled
         gev = gev[keep]
         oev = oev[np.isin(oev["photon"], gev["photon"])]
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-4
     assert rep["detected"] > 500
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     for status in (phx.EXTINCT, phx.DEAD, phx.OBSCURED):
         assert (oev["status"] == status).any()
 
@@ -115,9 +115,9 @@ def test_batched_graph_with_every_effect(phx):
     assert torch.equal(a, b) and torch.equal(b, c)
     tr.close()
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-4
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     assert np.array_equal(gimg, a.cpu().numpy().view(np.uint32))
 
 
@@ -150,9 +150,9 @@ def test_second_kick_on_a_flat_screen(phx):
     s.physics = C.PHYS_ATMOSPHERE | X.PHYS_SECOND_KICK
     s.extras = X.paraboloid_extras().replace(kick_r0=0.05, kick_fraction=(1.0,) + (0.0,) * 7)
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-4
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     off = np.hypot(gev["xe"], gev["ye"])
     p = 1.0 - math.exp(-O.Oracle(s).kick_variance(0))
     n = len(gev)
@@ -171,7 +171,48 @@ def test_hybrid_atmosphere_full_stack(phx, cull):
         keep = gev["status"] != phx.CULLED
         gev = gev[keep]
         oev = oev[np.isin(oev["photon"], gev["photon"])]
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-4
     assert rep["detected"] > 500
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
+
+
+@pytest.mark.parametrize("lam", [350e-9, 800e-9])
+def test_field_diffusion_on_the_flat_detector(phx, lam):
+    """The silicon field model of the diffusion (section 2.4.3) at normal incidence: blue light
+    converts at the entrance, 800 nm light throughout the device (every depth of the library's
+    sigma table is used); electron positions equal the oracle's, whose sigma integrates the
+    collection time per photon."""
+    s = H.flat_detector_scene(n_photons=20000, lam=lam, physics=C.PHYS_SILICON |
+                              C.PHYS_DIFFUSION | X.PHYS_FIELD_DIFFUSION)
+    s.extras = X.Extras(vanes=0)
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
+    assert rep["boundary_frac"] < 1e-4
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
+    conv = gev["status"] <= phx.OFF_CHIP
+    assert np.hypot(gev["xe"] - gev["x"], gev["ye"] - gev["y"])[conv].mean() > 1e-6
+
+
+def test_field_diffusion_full_stack(phx):
+    """Field diffusion under the full stack (atmosphere, telescope, coatings, silicon)."""
+    s = C.full(scale=2e-4, screen_n=256)
+    s.physics = C.PHYS_ALL | X.PHYS_FIELD_DIFFUSION
+    s.extras = X.tma_extras()
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
+    assert rep["boundary_frac"] < 1e-4
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
+
+
+def test_field_diffusion_refuses_an_undepleted_device(phx):
+    """A doping profile whose field reverses inside the device is refused at trace time."""
+    s = H.flat_detector_scene(n_photons=100, lam=500e-9, physics=C.PHYS_SILICON |
+                              C.PHYS_DIFFUSION | X.PHYS_FIELD_DIFFUSION)
+    s.extras = X.Extras(vanes=0, si_voltage=5.0)
+    tr = phx.Tracer(s)
+    with pytest.raises(phx.PhxError):
+        tr.trace()
+    tr.load_physics(X.Extras(vanes=0))
+    tr.trace()
+    tr.close()

@@ -43,7 +43,7 @@ def test_tiny_paraboloid_focus(phx):
     (32, 32), binned counts equal the transmitted photons, photon by photon equal to the oracle."""
     s = C.tiny()
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary"] == 0
     assert np.max(np.hypot(gev["x"], gev["y"])) < 1e-12
     assert gimg[32, 32] == len(gev) == gimg.sum() == 100000
@@ -56,9 +56,9 @@ def test_telescope_parity(phx):
     """Generated three-mirror telescope + camera, coatings, silicon, diffusion, 441 sources."""
     s = C.telescope(scale=0.02)
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-5
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     assert gimg.sum() == (gev["status"] == phx.DETECTED).sum()
 
 
@@ -81,19 +81,19 @@ def test_full_atmosphere_parity_small_screens(phx):
     """Seven frozen-flow layers (256^2 screens at three scales) + the telescope."""
     s = C.full(scale=2e-4, screen_n=256)
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-5
     assert rep["detected"] > 1000
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
 
 
 def test_sersic_and_blackbody_parity(phx):
     """Extended Sersic sources and tabulated blackbody SEDs through the full stack."""
     s = C.batched(scale=2e-3, screen_n=128, n_src=200)
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-5
-    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
 
 
 def test_perturbed_optics_parity(phx):
@@ -102,7 +102,7 @@ def test_perturbed_optics_parity(phx):
     rng = np.random.default_rng(3)
     s.perturbation = rng.uniform(-1, 1, C.N_PERTURB) * C.PERTURB_RANGE
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
     assert rep["boundary_frac"] < 1e-5
 
 
