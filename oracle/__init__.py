@@ -155,6 +155,11 @@ def lib():
             L.orc_mobility.restype = C.c_double
             L.orc_field_sigma.argtypes = [C.POINTER(Scene), C.c_double]
             L.orc_field_sigma.restype = C.c_double
+            L.orc_bleed.argtypes = [C.c_void_p, C.POINTER(C.c_uint32), C.c_int32, C.c_int32]
+            L.orc_readout.argtypes = [C.c_void_p, C.POINTER(C.c_uint32), C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_uint16), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                      C.POINTER(C.c_uint32)]
             L.orc_jacobian.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_uint64,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32)]
@@ -399,6 +404,68 @@ class Oracle:
 def air_refractivity(lam, pressure, temperature, water):
     """n - 1 of air (the Filippenko formula); lam in metres, pressures in mmHg, T in deg C."""
     return lib().orc_air_refractivity(lam, pressure, temperature, water)
+
+
+MAX_AMPS = 32
+
+
+class ReadoutParams(C.Structure):
+    _fields_ = [("seed", C.c_uint32), ("amp_nx", C.c_int32), ("amp_ny", C.c_int32),
+                ("over_x", C.c_int32), ("over_y", C.c_int32), ("pad", C.c_int32),
+                ("full_well", C.c_double), ("exposure", C.c_double), ("dark_rate", C.c_double),
+                ("hot_fraction", C.c_double), ("dead_fraction", C.c_double),
+                ("hot_column_fraction", C.c_double), ("cte_parallel", C.c_double),
+                ("cte_serial", C.c_double), ("nonlinearity", C.c_double),
+                ("gain", C.c_double * MAX_AMPS), ("bias", C.c_double * MAX_AMPS),
+                ("read_noise", C.c_double * MAX_AMPS), ("bit_sigma", C.c_double * 16)]
+
+
+def readout_params(rp) -> ReadoutParams:
+    """ctypes struct from a scene.readout.Readout description."""
+    P = ReadoutParams()
+    for name, _ in ReadoutParams._fields_:
+        if name == "pad":
+            continue
+        v = getattr(rp, name)
+        if name in ("gain", "bias", "read_noise", "bit_sigma"):
+            for i, x in enumerate(v):
+                getattr(P, name)[i] = x
+        else:
+            setattr(P, name, v)
+    return P
+
+
+def bleed(rp, image):
+    """Saturation and bleeding of a uint32 [ny, nx] image (a copy is returned)."""
+    img = np.ascontiguousarray(image, np.uint32).copy()
+    ny, nx = img.shape
+    P = readout_params(rp)
+    assert lib().orc_bleed(C.byref(P), img.ctypes.data_as(C.POINTER(C.c_uint32)), nx, ny) == 0
+    return img
+
+
+def readout(rp, image):
+    """The readout chain of a uint32 [ny, nx] electron image: returns (adu [amp, sh + over_y,
+    sw + over_x] uint16, margin, after-defects image, after-parallel slots, after-serial slots)."""
+    img = np.ascontiguousarray(image, np.uint32)
+    ny, nx = img.shape
+    na = rp.amp_nx * rp.amp_ny
+    sw, sh = nx // rp.amp_nx, ny // rp.amp_ny
+    ph, pw = sh + rp.over_y, sw + rp.over_x
+    out = np.zeros((na, ph, pw), np.uint16)
+    margin = np.zeros((na, ph, pw), np.float64)
+    work = np.zeros_like(img)
+    par = np.zeros((na, ph, sw), np.uint32)
+    ser = np.zeros((na, ph, pw), np.uint32)
+    P = readout_params(rp)
+    u32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_uint32))
+    rc = lib().orc_readout(C.byref(P), u32(img), nx, ny,
+                           out.ctypes.data_as(C.POINTER(C.c_uint16)),
+                           margin.ctypes.data_as(C.POINTER(C.c_double)), u32(work), u32(par),
+                           u32(ser))
+    if rc != 0:
+        raise ValueError("oracle readout: bad geometry")
+    return out, margin, work, par, ser
 
 
 def mobility(E, T):

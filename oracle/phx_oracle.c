@@ -28,7 +28,9 @@
  * air refractivity against standard-air values and its pressure, temperature and water laws;
  * dispersion image shift; aerosol survival exp(-tau sec z); dome-seeing normal law; halo radius
  * against the incomplete-beta CDF; spider shadow area and the lambda / (4 pi d) kick; dead-layer
- * fraction 1 - exp(-alpha t).
+ * fraction 1 - exp(-alpha t); second kick against exp(-D/2); field diffusion closed forms;
+ * readout chain: bleeding conservation and spread, defect and dark statistics, negative-binomial
+ * transfer trails, segment geometry, the ideal digitiser, non-linearity, read noise, bit errors.
  */
 #include "phx_oracle.h"
 
@@ -1153,5 +1155,223 @@ int orc_jacobian(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t coun
         }
         frozen[i] = 1;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Readout chain of a sensor image (section 2.4.3 saturation and bleeding; section 2.5
+ * electronic readout).  Random numbers: Philox keyed (seed, stage) with counter (index low,
+ * index high, draw block, 0): stage 1 defects and dark current per pixel, stage 2 hot-column
+ * ends per pixel, stage 3 parallel transfers per pixel, stage 4 serial transfers per packet,
+ * stage 5 read noise and bit errors per output value.                                          */
+
+static void readout_draw(uint32_t seed, uint32_t stage, uint64_t idx, uint32_t block,
+                         double u[4]) {
+    uint32_t ctr[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), block, 0u};
+    uint32_t key[2] = {seed, stage};
+    uint32_t w[4];
+    orc_philox(ctr, key, w);
+    for (int i = 0; i < 4; ++i) u[i] = orc_u01(w[i]);
+}
+
+/* Saturation and bleeding (section 2.4.3): a pixel holds at most w electrons; the excess moves
+ * along its row to the closest pixel below full well, never past the implant at the middle of the
+ * row; once the half-row is full the rest is removed.  Readings: the pixels of a half-row are
+ * treated in index order, each one's excess placed in the closest unfilled pixels in turn (a tie
+ * goes toward the row's end, away from the implant); a pixel filled by bleeding does not bleed
+ * again.  Pinned: conservation min(total, n w) per half-row, the symmetric spread of one
+ * saturated pixel, no pixel above w. */
+int orc_bleed(const orc_readout_params* rp, uint32_t* image, int32_t nx, int32_t ny) {
+    const uint64_t w = (uint64_t)rp->full_well;
+    for (int32_t j = 0; j < ny; ++j) {
+        uint32_t* row = image + (size_t)j * nx;
+        for (int half = 0; half < 2; ++half) {
+            int32_t a = half == 0 ? 0 : nx / 2, b = half == 0 ? nx / 2 : nx;   /* [a, b) */
+            for (int32_t p = a; p < b; ++p) {
+                if (row[p] <= w) continue;
+                uint64_t excess = row[p] - w;
+                row[p] = (uint32_t)w;
+                int32_t L = p - 1, R = p + 1;
+                while (excess > 0) {
+                    while (L >= a && row[L] >= w) --L;
+                    while (R < b && row[R] >= w) ++R;
+                    int has_l = L >= a, has_r = R < b;
+                    if (!has_l && !has_r) break;   /* half-row full: the rest is removed */
+                    int32_t t;
+                    if (has_l && has_r) {
+                        int32_t dl = p - L, dr = R - p;
+                        if (dl != dr) t = dl < dr ? L : R;
+                        else t = half == 0 ? L : R;   /* toward the row's end */
+                    } else {
+                        t = has_l ? L : R;
+                    }
+                    uint64_t room = w - row[t];
+                    uint64_t put = excess < room ? excess : room;
+                    row[t] += (uint32_t)put;
+                    excess -= put;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/* Delay of one electron in a transfer chain of m transfers with charge transfer efficiency cte
+ * (section 2.5): every transfer succeeds with probability cte, a failure leaves the electron in
+ * the packet behind, which is read one slot later; the slot delay is the number of failures
+ * before m successes, a negative binomial law, drawn by inversion of u (at most 64). */
+static int transfer_delay(double u, int64_t m, double eps) {
+    double p = pow(1.0 - eps, (double)m), cum = p;
+    int f = 0;
+    while (!(u < cum) && f < 64) {
+        ++f;
+        p *= (double)(m + f - 1) / f * eps;
+        cum += p;
+    }
+    return f;
+}
+
+/* Segment geometry: segment (ax, ay) covers columns [ax sw, (ax+1) sw) and rows [ay sh, (ay+1) sh);
+ * its serial register lies along the device edge (below row 0 for ay = 0, above row ny - 1 for
+ * ay = 1) and its amplifier at the segment's low-column end.  Parallel index r = rows from the
+ * register, serial index c = columns from the amplifier. */
+static void seg_coords(const orc_readout_params* rp, int32_t nx, int32_t ny, int32_t x, int32_t y,
+                       int* amp, int32_t* r, int32_t* c) {
+    int32_t sw = nx / rp->amp_nx, sh = ny / rp->amp_ny;
+    int32_t ax = x / sw, ay = y / sh;
+    *amp = ay * rp->amp_nx + ax;
+    *c = x - ax * sw;
+    *r = ay == 0 ? y : (ny - 1 - y);
+}
+
+/* The readout chain after bleeding (section 2.5): (1) dark current, a normal number of electrons
+ * with mean and variance rate x exposure, rounded and floored at zero (reading: the paper's
+ * "Gaussian error" read as the Poisson-like width sqrt(mean)); hot pixels set to w; dead pixels
+ * emptied (after the dark current); hot columns: a fraction of pixels are column ends, and the end
+ * and every pixel behind it in the readout chain (farther from the register) are set to w.
+ * (2) Parallel transfers: an electron at parallel index r takes r + 1 transfers and lands in slot
+ * r + delay; slots at or beyond sh + over_y are lost.  (3) Serial transfers of every slot of the
+ * register: an electron at serial index c lands in slot c + delay of c + 1 transfers; beyond
+ * sw + over_x lost.  (4) Read noise (a normal of sigma read_noise electrons, reading: the paper's
+ * "mean equal to the read noise" is its width), then ADU = e / (G (1 + N e / W)) + B clamped to
+ * [0, 65535], then each bit i = floor(ADU / 2^i + sigma_i g_i) mod 2, ADU = sum bit_i 2^i.
+ * Pinned: defect and dark statistics, the negative-binomial trail of one pixel, charge
+ * conservation, the ideal digitiser floor(e / G + B), the non-linearity closed form, read-noise
+ * variance, bit-error independence. */
+int orc_readout(const orc_readout_params* rp, const uint32_t* image, int32_t nx, int32_t ny,
+                uint16_t* out, double* margin, uint32_t* work, uint32_t* par, uint32_t* ser) {
+    if (rp->amp_nx < 1 || rp->amp_ny < 1 || rp->amp_ny > 2 || nx % rp->amp_nx || ny % rp->amp_ny ||
+        rp->amp_nx * rp->amp_ny > ORC_MAX_AMPS)
+        return -1;
+    const int32_t sw = nx / rp->amp_nx, sh = ny / rp->amp_ny;
+    const int32_t ph = sh + rp->over_y, pw = sw + rp->over_x;
+    const int n_amp = rp->amp_nx * rp->amp_ny;
+    const double w = rp->full_well;
+    size_t n = (size_t)nx * ny;
+    /* (1) bleeding, dark current, defects */
+    memcpy(work, image, n * sizeof(uint32_t));
+    orc_bleed(rp, work, nx, ny);
+    double mu = rp->dark_rate * rp->exposure;
+    for (int32_t y = 0; y < ny; ++y)
+        for (int32_t x = 0; x < nx; ++x) {
+            uint64_t i = (uint64_t)y * nx + x;
+            double u[4];
+            readout_draw(rp->seed, 1, i, 0, u);
+            uint64_t e = work[i];
+            if (mu > 0.0) {
+                double g = sqrt(-2.0 * log(u[2])) * cos(TWO_PI * u[3]);
+                double d = floor(mu + sqrt(mu) * g + 0.5);
+                if (d > 0.0) e += (uint64_t)d;
+            }
+            if (u[0] < rp->hot_fraction) e = (uint64_t)w;
+            else if (u[0] < rp->hot_fraction + rp->dead_fraction) e = 0;
+            work[i] = (uint32_t)(e > 0xffffffffull ? 0xffffffffull : e);
+        }
+    if (rp->hot_column_fraction > 0.0) {
+        for (int32_t x = 0; x < nx; ++x)
+            for (int half = 0; half < rp->amp_ny; ++half) {
+                /* walk the column segment away from its register */
+                int hot = 0;
+                for (int32_t r = 0; r < sh; ++r) {
+                    int32_t y = half == 0 ? r : ny - 1 - r;
+                    uint64_t i = (uint64_t)y * nx + x;
+                    double u[4];
+                    readout_draw(rp->seed, 2, i, 0, u);
+                    if (u[0] < rp->hot_column_fraction) hot = 1;
+                    if (hot) work[i] = (uint32_t)w;
+                }
+            }
+    }
+    /* (2) parallel transfers */
+    memset(par, 0, (size_t)n_amp * ph * sw * sizeof(uint32_t));
+    double ep = 1.0 - rp->cte_parallel, es = 1.0 - rp->cte_serial;
+    for (int32_t y = 0; y < ny; ++y)
+        for (int32_t x = 0; x < nx; ++x) {
+            uint64_t i = (uint64_t)y * nx + x;
+            int amp;
+            int32_t r, c;
+            seg_coords(rp, nx, ny, x, y, &amp, &r, &c);
+            uint32_t* col = par + (size_t)amp * ph * sw + c;
+            uint32_t ne = work[i];
+            double u[4];
+            for (uint32_t e = 0; e < ne; ++e) {
+                if ((e & 3) == 0) readout_draw(rp->seed, 3, i, e >> 2, u);
+                int64_t s = r + (ep > 0.0 ? transfer_delay(u[e & 3], r + 1, ep) : 0);
+                if (s < ph) col[(size_t)s * sw] += 1;
+            }
+        }
+    /* (3) serial transfers */
+    memset(ser, 0, (size_t)n_amp * ph * pw * sizeof(uint32_t));
+    for (int amp = 0; amp < n_amp; ++amp)
+        for (int32_t s = 0; s < ph; ++s)
+            for (int32_t c = 0; c < sw; ++c) {
+                uint64_t i = ((uint64_t)amp * ph + s) * sw + c;
+                uint32_t ne = par[i];
+                uint32_t* row = ser + ((size_t)amp * ph + s) * pw;
+                double u[4];
+                for (uint32_t e = 0; e < ne; ++e) {
+                    if ((e & 3) == 0) readout_draw(rp->seed, 4, i, e >> 2, u);
+                    int64_t t = c + (es > 0.0 ? transfer_delay(u[e & 3], c + 1, es) : 0);
+                    if (t < pw) row[t] += 1;
+                }
+            }
+    /* (4) read noise and digitisation */
+    int any_bit = 0;
+    for (int b = 0; b < 16; ++b) any_bit |= rp->bit_sigma[b] > 0.0;
+    for (int amp = 0; amp < n_amp; ++amp)
+        for (int32_t s = 0; s < ph; ++s)
+            for (int32_t c = 0; c < pw; ++c) {
+                uint64_t i = ((uint64_t)amp * ph + s) * pw + c;
+                double u[4];
+                readout_draw(rp->seed, 5, i, 0, u);
+                double e = (double)ser[i];
+                e += rp->read_noise[amp] * sqrt(-2.0 * log(u[0])) * cos(TWO_PI * u[1]);
+                double adu = e / (rp->gain[amp] * (1.0 + rp->nonlinearity * e / w)) + rp->bias[amp];
+                if (adu < 0.0) adu = 0.0;
+                if (adu > 65535.0) adu = 65535.0;
+                double m = 1e300;
+                uint32_t val = 0;
+                double gb[16] = {0};
+                if (any_bit)
+                    for (int k = 0; k < 4; ++k) {
+                        double v[4];
+                        readout_draw(rp->seed, 5, i, 1 + k, v);
+                        double r0 = sqrt(-2.0 * log(v[0])), r1 = sqrt(-2.0 * log(v[2]));
+                        gb[4 * k + 0] = r0 * cos(TWO_PI * v[1]);
+                        gb[4 * k + 1] = r0 * sin(TWO_PI * v[1]);
+                        gb[4 * k + 2] = r1 * cos(TWO_PI * v[3]);
+                        gb[4 * k + 3] = r1 * sin(TWO_PI * v[3]);
+                    }
+                for (int b = 0; b < 16; ++b) {
+                    double a = adu / (double)(1u << b) + rp->bit_sigma[b] * gb[b];
+                    double f = floor(a);
+                    double dist = a - f < 1.0 - (a - f) ? a - f : 1.0 - (a - f);
+                    if (dist < m) m = dist;
+                    int64_t k = (int64_t)f;
+                    if (((k % 2) + 2) % 2) val |= 1u << b;
+                }
+                out[i] = (uint16_t)val;
+                if (margin) margin[i] = m;
+            }
     return 0;
 }

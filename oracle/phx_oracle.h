@@ -156,6 +156,24 @@ int    orc_second_kick(const orc_scene* sc, int32_t src, uint64_t photon, int la
 double orc_field(const orc_scene* sc, double z);
 double orc_mobility(double E, double T);
 double orc_field_sigma(const orc_scene* sc, double depth);
+/* Readout chain of a sensor image (sections 2.4.3 saturation and bleeding, 2.5 electronic
+ * readout).  Segments: amp_nx x amp_ny amplifiers (amp_ny 1 or 2); out [amp][sh + over_y]
+ * [sw + over_x] in readout order; margin (may be NULL) per output value: the smallest distance
+ * of a floor() argument of the digitisation from an integer. */
+#define ORC_MAX_AMPS 32
+typedef struct {
+    uint32_t seed;
+    int32_t amp_nx, amp_ny, over_x, over_y, pad;
+    double full_well, exposure, dark_rate;
+    double hot_fraction, dead_fraction, hot_column_fraction;
+    double cte_parallel, cte_serial, nonlinearity;
+    double gain[ORC_MAX_AMPS], bias[ORC_MAX_AMPS], read_noise[ORC_MAX_AMPS];
+    double bit_sigma[16];
+} orc_readout_params;
+int    orc_bleed(const orc_readout_params* rp, uint32_t* image, int32_t nx, int32_t ny);
+int    orc_readout(const orc_readout_params* rp, const uint32_t* image, int32_t nx, int32_t ny,
+                   uint16_t* out, double* margin, uint32_t* stage_work, uint32_t* stage_par,
+                   uint32_t* stage_ser);
 int    orc_halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, double x_max,
                        double* x_out);
 #endif
