@@ -328,6 +328,54 @@ phx_status phx_load_sources(phx_ctx ctx, const phx_source* src_host, int32_t n_s
  * Errors: PHX_ERR_INVALID, PHX_ERR_STATE, PHX_ERR_NOMEM, PHX_ERR_HIP. */
 phx_status phx_load_physics(phx_ctx ctx, const phx_physics* physics_host);
 
+/* Sensor readout chain (section 2.4.3 saturation and bleeding; section 2.5 electronic readout),
+ * applied to an image of electrons (for instance the trace's image).  Segments: amp_nx x amp_ny
+ * amplifiers (amp_ny 1 or 2, at most PHX_MAX_AMPS, nx % amp_nx == ny % amp_ny == 0); segment
+ * (ax, ay) covers columns [ax sw, (ax+1) sw) and rows [ay sh, (ay+1) sh), sw = nx / amp_nx,
+ * sh = ny / amp_ny; its serial register lies along the device edge (below row 0 for ay = 0, above
+ * row ny - 1 for ay = 1) and its amplifier at the segment's low-column end; a pixel's parallel
+ * index r counts rows from the register, its serial index c columns from the amplifier.
+ * Steps, in order:
+ *  1. bleeding: each half-row (split at column nx / 2, the implant) holds at most full_well per
+ *     pixel; treating its pixels in index order, a pixel's excess goes to the closest pixels
+ *     below full well (a tie toward the row's end), the rest is removed once the half-row is full;
+ *  2. dark current: + max(0, round(mu + sqrt(mu) g)), mu = dark_rate x exposure; hot pixels set
+ *     to full_well, dead pixels emptied (Philox key (seed, 1), counter (pixel, 0): word 0 selects,
+ *     words 2, 3 the normal); hot columns: a pixel is a hot-column end with probability
+ *     hot_column_fraction (key (seed, 2) word 0) and it and every pixel behind it (larger r in its
+ *     segment column) are set to full_well;
+ *  3. parallel transfers: each electron of a pixel at parallel index r is read in slot
+ *     r + F, F the failures before r + 1 successes at probability cte_parallel (negative binomial,
+ *     drawn by inversion, at most 64; electron e uses key (seed, 3), counter (pixel, e / 4) word
+ *     e % 4); slots >= sh + over_y are lost;
+ *  4. serial transfers of every slot row likewise with c + 1 transfers at cte_serial (key
+ *     (seed, 4), counter (packet index in the [amp][sh + over_y][sw] layout, e / 4));
+ *  5. digitisation per output value: e + read_noise[amp] g (key (seed, 5), counter (index, 0));
+ *     ADU = e / (gain (1 + nonlinearity e / full_well)) + bias, clamped to [0, 65535]; bit i =
+ *     floor(ADU / 2^i + bit_sigma[i] g_i) mod 2 (g_i from counters (index, 1..4)); the output is
+ *     sum bit_i 2^i.
+ * electrons_dev: [ny][nx] uint32 (device; read only).  adu_dev: [amp][sh + over_y][sw + over_x]
+ * uint16 (device; adu_capacity elements at least).  work_dev [ny][nx], parallel_dev
+ * [amp][sh + over_y][sw] and serial_dev [amp][sh + over_y][sw + over_x] (uint32, device) receive
+ * the electrons after steps 2, 3 and 4 when not NULL; otherwise context-owned buffers are used
+ * (allocated or grown on first use: that call may synchronise the device).  Enqueued on
+ * `stream`.  Errors: PHX_ERR_INVALID, PHX_ERR_CAPACITY, PHX_ERR_NOMEM, PHX_ERR_HIP. */
+#define PHX_MAX_AMPS 32
+typedef struct {
+    uint32_t seed;
+    int32_t amp_nx, amp_ny, over_x, over_y, pad;
+    double full_well, exposure, dark_rate;
+    double hot_fraction, dead_fraction, hot_column_fraction;
+    double cte_parallel, cte_serial, nonlinearity;
+    double gain[PHX_MAX_AMPS], bias[PHX_MAX_AMPS], read_noise[PHX_MAX_AMPS];
+    double bit_sigma[16];
+} phx_readout_params;
+
+phx_status phx_readout(phx_ctx ctx, const phx_readout_params* params_host,
+                       const uint32_t* electrons_dev, int32_t nx, int32_t ny, uint16_t* adu_dev,
+                       uint64_t adu_capacity, uint32_t* work_dev, uint32_t* parallel_dev,
+                       uint32_t* serial_dev, void* stream);
+
 /* Trace photons: for every source s in [src_begin, src_end), photons photon_begin ..
  * photon_begin + count - 1, each keyed by Philox4x32-10 (key = (seed, s), counter = (photon
  * index, block, stream)), so any photon's history is reproducible independently of the launch.

@@ -26,6 +26,9 @@ struct phx_ctx_s {
                                          // prescription)
     bool field_ok = false;               // E_z > 0 across the device (field diffusion usable)
     double* d_sig2 = nullptr;            // sigma^2 against depth [kSig2Cells + 1]
+    // readout chain scratch (phx_readout without caller buffers)
+    uint32_t* d_ro[3] = {nullptr, nullptr, nullptr};   // work, parallel slots, serial slots
+    uint64_t ro_cap[3] = {0, 0, 0};
     phx_prescription presc{};
     double theta[PHX_N_THETA] = {0};
     DevParams host{};          // host image of the device parameter block
@@ -414,6 +417,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_coat_thr);
     free_dev(c->d_esc_thr);
     free_dev(c->d_sig2);
+    for (int k = 0; k < 3; ++k) free_dev(c->d_ro[k]);
     free_dev(c->d_grad);
     free_dev(c->d_src);
     free_dev(c->d_cdf);
@@ -1492,6 +1496,75 @@ phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     phx_set_launch_config(c, &cur);
     c->autotune_ms = cur_ms;
     if (best) *best = cur;
+    return PHX_OK;
+}
+
+phx_status phx_readout(phx_ctx c, const phx_readout_params* p, const uint32_t* in, int32_t nx,
+                       int32_t ny, uint16_t* adu, uint64_t adu_capacity, uint32_t* work,
+                       uint32_t* par, uint32_t* ser, void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!p || !in || !adu) return fail(c, PHX_ERR_INVALID, "null readout argument");
+    if (nx < 2 || ny < 1 || (nx & 1)) return fail(c, PHX_ERR_INVALID, "bad image size %d x %d", nx, ny);
+    if (p->amp_nx < 1 || p->amp_ny < 1 || p->amp_ny > 2 || p->amp_nx * p->amp_ny > PHX_MAX_AMPS ||
+        nx % p->amp_nx || ny % p->amp_ny || p->over_x < 0 || p->over_y < 0 ||
+        p->over_x > 65536 || p->over_y > 65536)
+        return fail(c, PHX_ERR_INVALID, "bad amplifier layout");
+    const int n_amp = p->amp_nx * p->amp_ny;
+    const double v[] = {p->full_well, p->exposure, p->dark_rate, p->hot_fraction,
+                        p->dead_fraction, p->hot_column_fraction, p->cte_parallel,
+                        p->cte_serial, p->nonlinearity};
+    if (!finite_all(v, 9) || !finite_all(p->gain, n_amp) || !finite_all(p->bias, n_amp) ||
+        !finite_all(p->read_noise, n_amp) || !finite_all(p->bit_sigma, 16))
+        return fail(c, PHX_ERR_INVALID, "non-finite readout parameter");
+    if (!(p->full_well >= 1.0 && p->full_well <= 4e9) || !(p->exposure >= 0.0) ||
+        !(p->dark_rate >= 0.0) || !(p->hot_fraction >= 0.0) || !(p->dead_fraction >= 0.0) ||
+        !(p->hot_fraction + p->dead_fraction <= 1.0) || !(p->hot_column_fraction >= 0.0) ||
+        !(p->hot_column_fraction <= 1.0) || !(p->cte_parallel > 0.0 && p->cte_parallel <= 1.0) ||
+        !(p->cte_serial > 0.0 && p->cte_serial <= 1.0) || !(p->nonlinearity >= 0.0))
+        return fail(c, PHX_ERR_INVALID, "readout parameter out of range");
+    for (int a = 0; a < n_amp; ++a)
+        if (!(p->gain[a] > 0.0) || !(p->read_noise[a] >= 0.0))
+            return fail(c, PHX_ERR_INVALID, "amplifier %d: gain must be > 0, read noise >= 0", a);
+    for (int b = 0; b < 16; ++b)
+        if (!(p->bit_sigma[b] >= 0.0)) return fail(c, PHX_ERR_INVALID, "negative bit_sigma");
+    const uint64_t sw = (uint64_t)(nx / p->amp_nx), sh = (uint64_t)(ny / p->amp_ny);
+    const uint64_t ph = sh + p->over_y, pw = sw + p->over_x;
+    const uint64_t need[3] = {(uint64_t)nx * ny, n_amp * ph * sw, n_amp * ph * pw};
+    if (adu_capacity < need[2])
+        return fail(c, PHX_ERR_CAPACITY, "adu capacity %llu < %llu",
+                    (unsigned long long)adu_capacity, (unsigned long long)need[2]);
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t* bufs[3] = {work, par, ser};
+    for (int k = 0; k < 3; ++k) {
+        if (bufs[k]) continue;
+        if (c->ro_cap[k] < need[k]) {
+            if (c->d_ro[k]) {
+                const hipError_t e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+                free_dev(c->d_ro[k]);
+                c->ro_cap[k] = 0;
+            }
+            const hipError_t e = hipMalloc((void**)&c->d_ro[k], need[k] * sizeof(uint32_t));
+            if (e != hipSuccess) {
+                c->d_ro[k] = nullptr;
+                return fail(c, PHX_ERR_NOMEM, "readout scratch: %s", hipGetErrorString(e));
+            }
+            c->ro_cap[k] = need[k];
+        }
+        bufs[k] = c->d_ro[k];
+    }
+    phx::ReadoutJob J;
+    J.p = *p;
+    J.in = in;
+    J.nx = nx;
+    J.ny = ny;
+    J.work = bufs[0];
+    J.par = bufs[1];
+    J.ser = bufs[2];
+    J.out = adu;
+    const hipError_t e = phx::launch_readout(J, st);
+    if (e != hipSuccess) return hip_fail(c, e, "readout launch");
     return PHX_OK;
 }
 

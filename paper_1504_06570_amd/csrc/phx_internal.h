@@ -220,6 +220,19 @@ struct Adjoint {
 hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
                           const LaunchConfig& cfg, const Adjoint& A, double* colsum, double* grad,
                           hipStream_t stream, const Pipe& pipe, const Timing& T);
+// One readout of a sensor image (phx_readout): parameters, the input electrons and the
+// buffers of each step (device pointers).
+struct ReadoutJob {
+    phx_readout_params p;
+    const uint32_t* in;
+    int32_t nx, ny;
+    uint32_t* work;     // [ny][nx] after bleeding, dark current and defects
+    uint32_t* par;      // [amp][sh + over_y][sw] after the parallel transfers
+    uint32_t* ser;      // [amp][sh + over_y][sw + over_x] after the serial transfers
+    uint16_t* out;      // [amp][sh + over_y][sw + over_x] ADU
+};
+hipError_t launch_readout(const ReadoutJob& J, hipStream_t stream);
+
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, unsigned int* gmax, hipStream_t stream);
 

@@ -108,6 +108,35 @@ def physics_struct(x) -> Physics:
     return P
 
 
+MAX_AMPS = 32
+
+
+class ReadoutParams(C.Structure):
+    _fields_ = [("seed", C.c_uint32), ("amp_nx", C.c_int32), ("amp_ny", C.c_int32),
+                ("over_x", C.c_int32), ("over_y", C.c_int32), ("pad", C.c_int32),
+                ("full_well", C.c_double), ("exposure", C.c_double), ("dark_rate", C.c_double),
+                ("hot_fraction", C.c_double), ("dead_fraction", C.c_double),
+                ("hot_column_fraction", C.c_double), ("cte_parallel", C.c_double),
+                ("cte_serial", C.c_double), ("nonlinearity", C.c_double),
+                ("gain", C.c_double * MAX_AMPS), ("bias", C.c_double * MAX_AMPS),
+                ("read_noise", C.c_double * MAX_AMPS), ("bit_sigma", C.c_double * 16)]
+
+
+def readout_struct(rp) -> ReadoutParams:
+    """phx_readout_params from a scene readout description (paper_1504_06570_amd.scene.readout)."""
+    P = ReadoutParams()
+    for name, _ in ReadoutParams._fields_:
+        if name == "pad":
+            continue
+        v = getattr(rp, name)
+        if name in ("gain", "bias", "read_noise", "bit_sigma"):
+            for i, x in enumerate(v):
+                getattr(P, name)[i] = x
+        else:
+            setattr(P, name, v)
+    return P
+
+
 class TraceArgs(C.Structure):
     _fields_ = [("seed", C.c_uint32), ("flags", C.c_uint32), ("src_begin", C.c_int32),
                 ("src_end", C.c_int32), ("photon_begin", C.c_uint64), ("photon_count", C.c_uint64),
@@ -158,6 +187,9 @@ def lib():
                                        C.c_void_p, C.c_int32, C.c_int32]
         L.phx_trace.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
         L.phx_load_physics.argtypes = [C.c_void_p, C.POINTER(Physics)]
+        L.phx_readout.argtypes = [C.c_void_p, C.POINTER(ReadoutParams), C.c_void_p, C.c_int32,
+                                  C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]
         L.phx_set_timing.argtypes = [C.c_void_p, C.c_int32]
         L.phx_get_timing.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32]
         L.phx_set_launch_config.argtypes = [C.c_void_p, C.POINTER(LaunchConfig)]
@@ -170,7 +202,8 @@ def lib():
         for f in ("phx_create", "phx_load_prescription", "phx_set_perturbation",
                   "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace",
                   "phx_set_timing", "phx_get_timing", "phx_set_launch_config",
-                  "phx_get_launch_config", "phx_trace_batched", "phx_autotune", "phx_adjoint"):
+                  "phx_get_launch_config", "phx_trace_batched", "phx_autotune", "phx_adjoint",
+                  "phx_load_physics", "phx_readout"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -418,6 +451,29 @@ class Tracer:
         out = (C.c_double * 4)()
         self._check(self.L.phx_get_timing(self.ctx, out, 4))
         return dict(generate=out[0], front=out[1], back=out[2], chunks=out[3])
+
+    def readout(self, image, params, stages=False, stream=None):
+        """Readout chain of an electron image (int32/uint32 tensor [ny, nx] on the device):
+        returns the uint16 ADU tensor [amp, sh + over_y, sw + over_x] (as int16 storage; view it
+        as uint16 on the host), and with stages=True also the electrons after defects, after the
+        parallel and after the serial transfers."""
+        import torch
+        assert image.is_contiguous() and image.dtype == torch.int32
+        ny, nx = image.shape
+        na = params.amp_nx * params.amp_ny
+        sw, sh = nx // params.amp_nx, ny // params.amp_ny
+        ph, pw = sh + params.over_y, sw + params.over_x
+        out = torch.zeros((na, ph, pw), dtype=torch.int16, device=image.device)
+        bufs = [None, None, None]
+        if stages:
+            bufs = [torch.zeros((ny, nx), dtype=torch.int32, device=image.device),
+                    torch.zeros((na, ph, sw), dtype=torch.int32, device=image.device),
+                    torch.zeros((na, ph, pw), dtype=torch.int32, device=image.device)]
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        self._check(self.L.phx_readout(self.ctx, C.byref(readout_struct(params)), image.data_ptr(),
+                                       nx, ny, out.data_ptr(), out.numel(), ptr(bufs[0]),
+                                       ptr(bufs[1]), ptr(bufs[2]), _stream_handle(stream)))
+        return (out, *bufs) if stages else out
 
     def new_stats(self):
         import torch

@@ -40,10 +40,10 @@ def test_struct_sizes_match_header_layout():
 #include <stdio.h>
 #include "phx.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phx_surface),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phx_surface),
          sizeof(phx_prescription), sizeof(phx_atmosphere), sizeof(phx_source), sizeof(phx_event),
          sizeof(phx_trace_args), offsetof(phx_trace_args, image_dev), sizeof(phx_launch_config),
-         sizeof(phx_physics), offsetof(phx_physics, spider_angle));
+         sizeof(phx_physics), offsetof(phx_physics, spider_angle), sizeof(phx_readout_params));
   return 0;
 }
 """
@@ -56,7 +56,7 @@ int main(void) {
     want = [ctypes.sizeof(P.Surface), ctypes.sizeof(P.Prescription), ctypes.sizeof(P.Atmosphere),
             ctypes.sizeof(P.Source), P.EVENT_DTYPE.itemsize, ctypes.sizeof(P.TraceArgs),
             P.TraceArgs.image_dev.offset, ctypes.sizeof(P.LaunchConfig),
-            ctypes.sizeof(P.Physics), P.Physics.spider_angle.offset]
+            ctypes.sizeof(P.Physics), P.Physics.spider_angle.offset, ctypes.sizeof(P.ReadoutParams)]
     assert got == want
 
 

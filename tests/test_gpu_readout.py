@@ -1,0 +1,114 @@
+"""GPU readout chain (phx_readout, through the C ABI) against the CPU oracle: the electrons after
+bleeding and defects, after the parallel and after the serial transfers bit for bit, and the
+digitised ADU value for value (values whose digitiser floors sit within 1e-9 of an integer in the
+oracle may differ by the rounding of the two implementations)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1504_06570_amd.scene import configs as C
+from paper_1504_06570_amd.scene.readout import Readout
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def phx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_06570_amd import phx as P
+    return P
+
+
+def _image(ny=256, nx=256, seed=0):
+    rng = np.random.default_rng(seed)
+    img = rng.poisson(40.0, (ny, nx)).astype(np.uint32)
+    # bright spots that saturate and bleed, one near the implant
+    for (fy, fx, n) in ((0.16, 0.12, 900000), (0.78, 0.5 - 1.0 / nx, 2500000),
+                        (0.47, 0.78, 150000), (0.04, 0.98, 99999)):
+        img[int(fy * ny), int(fx * nx)] = n
+    return img
+
+
+def run_both(P, img, rp):
+    import torch
+    tr = P.Tracer(C.tiny(scale=1e-4))
+    dev = torch.from_numpy(img.view(np.int32)).cuda()
+    out, work, par, ser = tr.readout(dev, rp, stages=True)
+    torch.cuda.synchronize()
+    g = [t.cpu().numpy() for t in (out, work, par, ser)]
+    tr.close()
+    o_out, margin, o_work, o_par, o_ser = O.readout(rp, img)
+    return g, (o_out, margin, o_work, o_par, o_ser)
+
+
+def check(g, o):
+    g_out, g_work, g_par, g_ser = g
+    o_out, margin, o_work, o_par, o_ser = o
+    assert np.array_equal(g_work.view(np.uint32), o_work)
+    assert np.array_equal(g_par.view(np.uint32), o_par)
+    assert np.array_equal(g_ser.view(np.uint32), o_ser)
+    ga = g_out.view(np.uint16)
+    diff = ga != o_out
+    assert not (diff & (margin >= 1e-9)).any(), np.argwhere(diff & (margin >= 1e-9))[:5]
+    return int(diff.sum())
+
+
+@pytest.mark.parametrize("layout", [(4, 2, 8, 6), (1, 1, 0, 0), (8, 2, 3, 5)])
+def test_readout_parity(phx, layout):
+    """Bleeding, dark current, hot/dead pixels, hot columns, transfer trails (inefficiencies raised
+    to 1e-4 / 5e-5 so that many electrons are delayed), read noise, non-linearity and bit errors
+    on a 256 x 256 image with saturating spots, for several amplifier layouts."""
+    ax, ay, ox, oy = layout
+    rp = Readout(amp_nx=ax, amp_ny=ay, over_x=ox, over_y=oy, hot_fraction=2e-3,
+                 dead_fraction=2e-3, hot_column_fraction=2e-4, cte_parallel=1 - 1e-4,
+                 cte_serial=1 - 5e-5, dark_rate=1.0)
+    g, o = run_both(phx, _image(), rp)
+    assert check(g, o) <= 2
+    # the spots bled: a full well plateau around each
+    assert (o[2] == rp.full_well).sum() > 30
+
+
+def test_readout_of_a_traced_image(phx):
+    """The trace's image of the telescope field read out on the device equals the oracle's readout
+    of the same image."""
+    import torch
+    s = C.telescope(scale=0.02)
+    tr = phx.Tracer(s)
+    img, _, _, _ = tr.trace()
+    rp = Readout(seed=7)
+    out, work, par, ser = tr.readout(img, rp, stages=True)
+    torch.cuda.synchronize()
+    host = img.cpu().numpy().view(np.uint32)
+    g = [t.cpu().numpy() for t in (out, work, par, ser)]
+    tr.close()
+    o = O.readout(rp, host)
+    assert host.sum() > 0
+    assert check(g, o) <= 2
+
+
+def test_readout_repeats_and_scratch_buffers(phx):
+    """Two calls give the same ADU, with caller buffers or the context's scratch."""
+    import torch
+    img = torch.from_numpy(_image(128, 128, seed=3).view(np.int32)).cuda()
+    rp = Readout(amp_nx=2, amp_ny=2, cte_parallel=1 - 1e-4)
+    tr = phx.Tracer(C.tiny(scale=1e-4))
+    a = tr.readout(img, rp)
+    b = tr.readout(img, rp)
+    c, _, _, _ = tr.readout(img, rp, stages=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    tr.close()
+
+
+def test_readout_error_paths(phx):
+    """Bad layouts and parameters are refused before any launch."""
+    import torch
+    img = torch.zeros((64, 64), dtype=torch.int32, device="cuda")
+    tr = phx.Tracer(C.tiny(scale=1e-4))
+    for bad in (dict(amp_nx=3), dict(amp_ny=3), dict(cte_parallel=0.0), dict(gain=(0.0,) * 32),
+                dict(hot_fraction=0.7, dead_fraction=0.7), dict(full_well=0.0)):
+        with pytest.raises(phx.PhxError):
+            tr.readout(img, Readout(amp_nx=2, amp_ny=2).replace(**bad))
+    tr.close()
