@@ -355,6 +355,55 @@ def hybrid_leg(steps, n_ph, core_ms):
     }
 
 
+READOUT_BYTES_PER_PIXEL = 46   # zero both slot buffers (8), bleed copy (8), defects (8),
+                               # parallel read + add (8), serial read + add (8), digitise (6)
+
+
+def readout_leg(tr, img, steps):
+    """The readout chain (bleeding, dark current, defects, per-electron parallel and serial
+    transfers, digitisation) of one step's 4096^2 image of the headline star on 16 amplifiers."""
+    import torch
+    from paper_1504_06570_amd.scene.readout import Readout
+    rp = Readout()
+    out = tr.readout(img, rp)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        out = tr.readout(img, rp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ny, nx = img.shape
+    electrons = float(img.double().sum().item())
+    # electrons each transfer stage draws a delay for (after bleeding, dark current and defects:
+    # hot pixels and hot columns at full well dominate)
+    _, work, par, _ = tr.readout(img, rp, stages=True)
+    torch.cuda.synchronize()
+    moved = float(work.view(torch.int32).double().sum().item() +
+                  par.view(torch.int32).double().sum().item())
+    del work, par
+    gbs = READOUT_BYTES_PER_PIXEL * nx * ny / (ms * 1e-3) * 1e-9
+    print(f"# readout {ms:.3f} ms ({electrons:.3e} electrons in, {moved:.3e} transferred)",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": "readout chain of one step's 4096^2 image of the headline star (16 amplifiers "
+                    "8 x 2, 10 overscan rows and columns, full well 1e5, CTE 0.999995 / 0.999998)",
+        "pixels": nx * ny,
+        "electrons": electrons,
+        "ms_per_readout": ms,
+        "pixels_per_s": nx * ny / (ms * 1e-3),
+        "electrons_per_s": electrons / (ms * 1e-3),
+        "transfer_electron_draws": moved,
+        "transfer_draws_per_s": moved / (ms * 1e-3),
+        "hbm_algorithmic": {"bytes_per_pixel": READOUT_BYTES_PER_PIXEL, "achieved": gbs,
+                            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS},
+        "adu_shape": list(out.shape),
+    }
+
+
 def copy_probe():
     """A plain 1 GiB device copy, for calibrating the HBM byte counters."""
     import torch
@@ -496,6 +545,10 @@ def main():
         extra["ms_per_step_without_preroll"] = nc_ms
 
     if not args.no_extras:
+        one = tr.new_image()
+        tr.trace(one, flags=flags)
+        extra["readout"] = readout_leg(tr, one, max(args.steps, 1))
+        del one
         extra["extra_physics"] = extras_leg(tr, scene, flags, max(args.steps, 1), n_ph, ms)
         tr.close()
         extra["hybrid_atmosphere"] = hybrid_leg(max(args.steps, 1), n_ph, ms)

@@ -27,8 +27,9 @@ struct phx_ctx_s {
     bool field_ok = false;               // E_z > 0 across the device (field diffusion usable)
     double* d_sig2 = nullptr;            // sigma^2 against depth [kSig2Cells + 1]
     // readout chain scratch (phx_readout without caller buffers)
-    uint32_t* d_ro[3] = {nullptr, nullptr, nullptr};   // work, parallel slots, serial slots
-    uint64_t ro_cap[3] = {0, 0, 0};
+    // work, parallel slots, serial slots, heavy-packet list (+ its counter)
+    uint32_t* d_ro[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t ro_cap[4] = {0, 0, 0, 0};
     phx_prescription presc{};
     double theta[PHX_N_THETA] = {0};
     DevParams host{};          // host image of the device parameter block
@@ -417,7 +418,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_coat_thr);
     free_dev(c->d_esc_thr);
     free_dev(c->d_sig2);
-    for (int k = 0; k < 3; ++k) free_dev(c->d_ro[k]);
+    for (int k = 0; k < 4; ++k) free_dev(c->d_ro[k]);
     free_dev(c->d_grad);
     free_dev(c->d_src);
     free_dev(c->d_cdf);
@@ -1529,14 +1530,15 @@ phx_status phx_readout(phx_ctx c, const phx_readout_params* p, const uint32_t* i
         if (!(p->bit_sigma[b] >= 0.0)) return fail(c, PHX_ERR_INVALID, "negative bit_sigma");
     const uint64_t sw = (uint64_t)(nx / p->amp_nx), sh = (uint64_t)(ny / p->amp_ny);
     const uint64_t ph = sh + p->over_y, pw = sw + p->over_x;
-    const uint64_t need[3] = {(uint64_t)nx * ny, n_amp * ph * sw, n_amp * ph * pw};
+    const uint64_t need[4] = {(uint64_t)nx * ny, n_amp * ph * sw, n_amp * ph * pw,
+                              std::max((uint64_t)nx * ny, n_amp * ph * sw) + 1};
     if (adu_capacity < need[2])
         return fail(c, PHX_ERR_CAPACITY, "adu capacity %llu < %llu",
                     (unsigned long long)adu_capacity, (unsigned long long)need[2]);
     if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
     hipStream_t st = (hipStream_t)stream;
-    uint32_t* bufs[3] = {work, par, ser};
-    for (int k = 0; k < 3; ++k) {
+    uint32_t* bufs[4] = {work, par, ser, nullptr};
+    for (int k = 0; k < 4; ++k) {
         if (bufs[k]) continue;
         if (c->ro_cap[k] < need[k]) {
             if (c->d_ro[k]) {
@@ -1563,6 +1565,8 @@ phx_status phx_readout(phx_ctx c, const phx_readout_params* p, const uint32_t* i
     J.par = bufs[1];
     J.ser = bufs[2];
     J.out = adu;
+    J.heavy_count = bufs[3];
+    J.heavy = bufs[3] + 1;
     const hipError_t e = phx::launch_readout(J, st);
     if (e != hipSuccess) return hip_fail(c, e, "readout launch");
     return PHX_OK;

@@ -230,6 +230,9 @@ struct ReadoutJob {
     uint32_t* par;      // [amp][sh + over_y][sw] after the parallel transfers
     uint32_t* ser;      // [amp][sh + over_y][sw + over_x] after the serial transfers
     uint16_t* out;      // [amp][sh + over_y][sw + over_x] ADU
+    uint32_t* heavy;    // packets with many electrons, handled one workgroup each
+                        // [max(ny nx, amp (sh + over_y) sw)]
+    uint32_t* heavy_count;
 };
 hipError_t launch_readout(const ReadoutJob& J, hipStream_t stream);
 

@@ -32,26 +32,10 @@ __device__ __forceinline__ uint32_t ro_word(const uint4& w, int k) {
 // Step 1: one wavefront per half-row copies it (coalesced) into the work image; if a pixel exceeds
 // the full well, lane 0 then bleeds the half-row: pixels in index order, each excess to the
 // closest pixels below full well (ties toward the row's end), the rest removed once it is full.
-__global__ __launch_bounds__(kRoBlock) void ro_bleed(const ReadoutJob J) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint64_t h = (uint64_t)blockIdx.x * (kRoBlock / 64) + wave;
-    if (h >= 2ull * (uint64_t)J.ny) return;
-    const int64_t j = (int64_t)(h >> 1);
-    const int half = (int)(h & 1);
-    const int64_t a = half ? J.nx / 2 : 0, b = half ? J.nx : J.nx / 2;
-    const uint64_t w = (uint64_t)J.p.full_well;
-    const uint32_t* src = J.in + j * J.nx;
-    uint32_t* row = J.work + j * J.nx;
-    bool sat = false;
-    for (int64_t x = a + lane; x < b; x += 64) {
-        const uint32_t v = src[x];
-        row[x] = v;
-        sat |= v > w;
-    }
-    if (__ballot(sat) == 0) return;
-    __threadfence();
-    __builtin_amdgcn_wave_barrier();
-    if (lane != 0) return;
+// With `lds` the half-row is also staged in LDS (kRoBlock / 64 half-rows of nx / 2 words per
+// workgroup), lane 0 bleeds it there and the wavefront writes it back.
+__device__ __forceinline__ void bleed_half_row(uint32_t* row, int64_t a, int64_t b, int half,
+                                               uint64_t w) {
     for (int64_t p = a; p < b; ++p) {
         if (row[p] <= w) continue;
         uint64_t excess = row[p] - w;
@@ -74,6 +58,40 @@ __global__ __launch_bounds__(kRoBlock) void ro_bleed(const ReadoutJob J) {
             row[t] += (uint32_t)put;
             excess -= put;
         }
+    }
+}
+
+__global__ __launch_bounds__(kRoBlock) void ro_bleed(const ReadoutJob J, int lds) {
+    extern __shared__ uint32_t s_half[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t h = (uint64_t)blockIdx.x * (kRoBlock / 64) + wave;
+    if (h >= 2ull * (uint64_t)J.ny) return;
+    const int64_t j = (int64_t)(h >> 1);
+    const int half = (int)(h & 1);
+    const int64_t a = half ? J.nx / 2 : 0, b = half ? J.nx : J.nx / 2;
+    const uint64_t w = (uint64_t)J.p.full_well;
+    const uint32_t* src = J.in + j * J.nx;
+    uint32_t* row = J.work + j * J.nx;
+    uint32_t* buf = s_half + (int64_t)wave * (J.nx / 2) - a;   // buf[a .. b)
+    bool sat = false;
+    for (int64_t x = a + lane; x < b; x += 64) {
+        const uint32_t v = src[x];
+        row[x] = v;
+        if (lds) buf[x] = v;
+        sat |= v > w;
+    }
+    if (__ballot(sat) == 0) return;
+    if (lds) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) bleed_half_row(buf, a, b, half, w);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t x = a + lane; x < b; x += 64) row[x] = buf[x];
+    } else {
+        __threadfence();
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) bleed_half_row(row, a, b, half, w);
     }
 }
 
@@ -100,21 +118,34 @@ __global__ __launch_bounds__(kRoBlock) void ro_defects(const ReadoutJob J) {
     }
 }
 
-// Step 2, hot columns: one thread per segment column walks away from its register; from the first
-// hot-column end on, every pixel is set to the full well.
+// Step 2, hot columns: one wavefront per segment column draws the end flags of 64 rows at a
+// time, walking away from the register; from the first end on, every pixel is set to the full
+// well.
 __global__ __launch_bounds__(kRoBlock) void ro_hot_columns(const ReadoutJob J) {
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const uint64_t t = (uint64_t)blockIdx.x * (kRoBlock / 64) + (threadIdx.x >> 6);
     if (t >= (uint64_t)J.nx * J.p.amp_ny) return;
     const int64_t x = (int64_t)(t % J.nx);
     const int half = (int)(t / J.nx);
     const int64_t sh = J.ny / J.p.amp_ny;
     const uint32_t w = (uint32_t)J.p.full_well;
-    bool hot = false;
-    for (int64_t r = 0; r < sh; ++r) {
+    int64_t first = sh;
+    for (int64_t r0 = 0; r0 < sh; r0 += 64) {
+        const int64_t r = r0 + lane;
+        bool end = false;
+        if (r < sh) {
+            const int64_t y = half == 0 ? r : J.ny - 1 - r;
+            end = u01(ro_draw(J.p.seed, 2, (uint64_t)y * J.nx + x, 0).x) < J.p.hot_column_fraction;
+        }
+        const uint64_t mask = __ballot(end);
+        if (mask) {
+            first = r0 + __ffsll((unsigned long long)mask) - 1;
+            break;
+        }
+    }
+    for (int64_t r = first + lane; r < sh; r += 64) {
         const int64_t y = half == 0 ? r : J.ny - 1 - r;
-        const uint64_t i = (uint64_t)y * J.nx + x;
-        if (!hot) hot = u01(ro_draw(J.p.seed, 2, i, 0).x) < J.p.hot_column_fraction;
-        if (hot) J.work[i] = w;
+        J.work[(uint64_t)y * J.nx + x] = w;
     }
 }
 
@@ -138,55 +169,120 @@ __device__ __forceinline__ int ro_delay(double u, int64_t m, double eps, double 
 }
 
 // Steps 3 and 4: the electrons of one packet at transfer index m - 1 (m transfers), each drawn
-// a delay; kept electrons are added to slot m - 1 at once, delayed ones one by one (rare).
-__device__ __forceinline__ void ro_transfer(uint32_t ne, int64_t idx, int64_t m, double eps,
-                                            uint32_t seed, uint32_t stage, uint32_t* dst,
-                                            int64_t stride, int64_t n_slots) {
-    if (ne == 0) return;
-    if (!(eps > 0.0)) {
-        atomicAdd(dst + (m - 1) * stride, ne);
-        return;
-    }
-    const double p0 = pow(1.0 - eps, (double)m);
-    uint32_t kept = 0;
-    uint4 r = make_uint4(0, 0, 0, 0);
-    for (uint32_t e = 0; e < ne; ++e) {
-        if ((e & 3) == 0) r = ro_draw(seed, stage, (uint64_t)idx, e >> 2);
-        const double u = u01(ro_word(r, (int)(e & 3)));
-        if (u < p0) {
-            ++kept;
-            continue;
+// a delay; electron e reads word e % 4 of draw block e / 4.  Blocks b0, b0 + db, ... are handled
+// here; the kept electrons and those delayed by one slot are counted (the caller adds them to
+// slots m - 1 and m), longer delays are added one by one (rare).
+struct Kept {
+    uint32_t k0, k1;
+};
+__device__ __forceinline__ Kept ro_transfer(uint32_t ne, uint64_t idx, int64_t m, double eps,
+                                            double p0, uint32_t seed, uint32_t stage,
+                                            uint32_t* dst, int64_t stride, int64_t n_slots,
+                                            uint32_t b0, uint32_t db) {
+    uint32_t kept = 0, one = 0;
+    // the first two cumulative probabilities of the delay, as the inversion forms them
+    const double cum1 = p0 + p0 * ((double)m / 1 * eps);
+    const uint32_t nb = (ne + 3) >> 2;
+    for (uint32_t b = b0; b < nb; b += db) {
+        const uint4 r = ro_draw(seed, stage, idx, b);
+        const uint32_t left = ne - 4 * b;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool live = (uint32_t)q < left;
+            const double u = u01(ro_word(r, q));
+            kept += live && u < p0;
+            one += live && !(u < p0) && u < cum1;
+            if (live && !(u < cum1)) {   // a delay of two slots or more: rare
+                const int64_t s = m - 1 + ro_delay(u, m, eps, p0);
+                if (s < n_slots) atomicAdd(dst + s * stride, 1u);
+            }
         }
-        const int64_t s = m - 1 + ro_delay(u, m, eps, p0);
-        if (s < n_slots) atomicAdd(dst + s * stride, 1u);
     }
-    if (kept) atomicAdd(dst + (m - 1) * stride, kept);
+    return Kept{kept, one};
 }
 
-__global__ __launch_bounds__(kRoBlock) void ro_parallel(const ReadoutJob J) {
-    const uint64_t n = (uint64_t)J.nx * J.ny;
-    const int64_t sw = J.nx / J.p.amp_nx, sh = J.ny / J.p.amp_ny, ph = sh + J.p.over_y;
-    const double eps = 1.0 - J.p.cte_parallel;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+// A packet with more electrons than this is handed to a whole wavefront (the heavy list).
+constexpr uint32_t kHeavy = 1024;
+
+// Where packet i of a transfer stage sits: its electrons, transfer count m, destination column
+// or row and slot stride / count.
+struct Packet {
+    uint32_t ne;
+    int64_t m;
+    uint32_t* dst;
+    int64_t stride, n_slots;
+};
+
+template <int STAGE>
+__device__ __forceinline__ Packet packet_of(const ReadoutJob& J, uint64_t i) {
+    const int64_t sw = J.nx / J.p.amp_nx, sh = J.ny / J.p.amp_ny;
+    const int64_t ph = sh + J.p.over_y, pw = sw + J.p.over_x;
+    Packet k;
+    if (STAGE == 3) {
         const int64_t y = (int64_t)(i / J.nx), x = (int64_t)(i % J.nx);
         const int64_t ax = x / sw, ay = y / sh;
         const int64_t amp = ay * J.p.amp_nx + ax, c = x - ax * sw;
         const int64_t r = ay == 0 ? y : J.ny - 1 - y;
-        ro_transfer(J.work[i], (int64_t)i, r + 1, eps, J.p.seed, 3, J.par + amp * ph * sw + c, sw,
-                    ph);
+        k = Packet{J.work[i], r + 1, J.par + amp * ph * sw + c, sw, ph};
+    } else {
+        const int64_t c = (int64_t)(i % sw), rowi = (int64_t)(i / sw);   // rowi = amp ph + s
+        k = Packet{J.par[i], c + 1, J.ser + rowi * pw, 1, pw};
+    }
+    return k;
+}
+
+// One thread per packet; packets above kHeavy electrons are appended to the heavy list instead.
+template <int STAGE>
+__global__ __launch_bounds__(kRoBlock) void ro_transfer_light(const ReadoutJob J, uint64_t n,
+                                                              double eps) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const Packet k = packet_of<STAGE>(J, i);
+        if (k.ne == 0) continue;
+        if (!(eps > 0.0)) {
+            atomicAdd(k.dst + (k.m - 1) * k.stride, k.ne);
+            continue;
+        }
+        if (k.ne > kHeavy) {
+            J.heavy[atomicAdd(J.heavy_count, 1u)] = (uint32_t)i;
+            continue;
+        }
+        const double p0 = pow(1.0 - eps, (double)k.m);
+        const Kept kk = ro_transfer(k.ne, i, k.m, eps, p0, J.p.seed, STAGE, k.dst, k.stride,
+                                    k.n_slots, 0, 1);
+        if (kk.k0) atomicAdd(k.dst + (k.m - 1) * k.stride, kk.k0);
+        if (kk.k1 && k.m < k.n_slots) atomicAdd(k.dst + k.m * k.stride, kk.k1);
     }
 }
 
-__global__ __launch_bounds__(kRoBlock) void ro_serial(const ReadoutJob J) {
-    const int64_t sw = J.nx / J.p.amp_nx, sh = J.ny / J.p.amp_ny;
-    const int64_t ph = sh + J.p.over_y, pw = sw + J.p.over_x;
-    const uint64_t n = (uint64_t)J.p.amp_nx * J.p.amp_ny * ph * sw;
-    const double eps = 1.0 - J.p.cte_serial;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const int64_t c = (int64_t)(i % sw), rowi = (int64_t)(i / sw);   // rowi = amp ph + s
-        ro_transfer(J.par[i], (int64_t)i, c + 1, eps, J.p.seed, 4, J.ser + rowi * pw, 1, pw);
+// kSplit wavefronts per heavy packet: wavefront `sub` takes the draw blocks sub * 64 + lane +
+// j * kSplit * 64, and each sums its kept electrons (a few hundred saturated pixels would
+// otherwise leave most SIMDs with one long dependent chain each).
+constexpr uint32_t kSplit = 4;
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kRoBlock) void ro_transfer_heavy(const ReadoutJob J, double eps) {
+    const uint64_t n = (uint64_t)*J.heavy_count * kSplit;
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (kRoBlock / 64);
+    for (uint64_t t = (uint64_t)blockIdx.x * (kRoBlock / 64) + (threadIdx.x >> 6); t < n;
+         t += waves) {
+        const uint64_t i = J.heavy[t / kSplit];
+        const uint32_t sub = (uint32_t)(t % kSplit);
+        const Packet k = packet_of<STAGE>(J, i);
+        const double p0 = pow(1.0 - eps, (double)k.m);
+        const Kept kk = ro_transfer(k.ne, i, k.m, eps, p0, J.p.seed, STAGE, k.dst, k.stride,
+                                    k.n_slots, sub * 64u + (uint32_t)lane, 64u * kSplit);
+        const uint32_t k0 = wave_sum(kk.k0), k1 = wave_sum(kk.k1);
+        if (lane == 0) {
+            if (k0) atomicAdd(k.dst + (k.m - 1) * k.stride, k0);
+            if (k1 && k.m < k.n_slots) atomicAdd(k.dst + k.m * k.stride, k1);
+        }
     }
 }
 
@@ -208,7 +304,10 @@ __global__ __launch_bounds__(kRoBlock) void ro_digitise(const ReadoutJob J, int 
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
             double g[4] = {0.0, 0.0, 0.0, 0.0};
-            if (any_bit) {
+            // a block whose four widths are zero contributes nothing (0 x g): not drawn
+            const bool need = J.p.bit_sigma[4 * k] > 0.0 || J.p.bit_sigma[4 * k + 1] > 0.0 ||
+                              J.p.bit_sigma[4 * k + 2] > 0.0 || J.p.bit_sigma[4 * k + 3] > 0.0;
+            if (any_bit && need) {
                 const uint4 v = ro_draw(J.p.seed, 5, i, 1 + k);
                 const double r0 = sqrt(-2.0 * log(u01(v.x))), r1 = sqrt(-2.0 * log(u01(v.z)));
                 g[0] = r0 * cos(kTwoPi * u01(v.y));
@@ -244,15 +343,27 @@ hipError_t launch_readout(const ReadoutJob& J, hipStream_t s) {
     int any_bit = 0;
     for (int b = 0; b < 16; ++b) any_bit |= J.p.bit_sigma[b] > 0.0;
     const uint64_t half_rows = 2ull * (uint64_t)J.ny;
-    hipLaunchKernelGGL(ro_bleed, dim3((unsigned)((half_rows + 3) / 4)), dim3(kRoBlock), 0, s, J);
+    const size_t lds_bytes = (size_t)(kRoBlock / 64) * (J.nx / 2) * sizeof(uint32_t);
+    const int lds = lds_bytes <= 64 * 1024 ? 1 : 0;
+    hipLaunchKernelGGL(ro_bleed, dim3((unsigned)((half_rows + 3) / 4)), dim3(kRoBlock),
+                       lds ? lds_bytes : 0, s, J, lds);
     hipLaunchKernelGGL(ro_defects, dim3(grid_for(npix)), dim3(kRoBlock), 0, s, J);
     if (J.p.hot_column_fraction > 0.0)
-        hipLaunchKernelGGL(ro_hot_columns, dim3(grid_for((uint64_t)J.nx * J.p.amp_ny)),
+        hipLaunchKernelGGL(ro_hot_columns,
+                           dim3((unsigned)(((uint64_t)J.nx * J.p.amp_ny + 3) / 4)),
                            dim3(kRoBlock), 0, s, J);
+    const double ep = 1.0 - J.p.cte_parallel, es = 1.0 - J.p.cte_serial;
+    const unsigned heavy_grid = 2048;
     hipLaunchKernelGGL(ro_zero, dim3(grid_for(n_par)), dim3(kRoBlock), 0, s, J.par, n_par);
-    hipLaunchKernelGGL(ro_parallel, dim3(grid_for(npix)), dim3(kRoBlock), 0, s, J);
+    hipLaunchKernelGGL(ro_zero, dim3(1), dim3(kRoBlock), 0, s, J.heavy_count, (uint64_t)1);
+    hipLaunchKernelGGL(ro_transfer_light<3>, dim3(grid_for(npix)), dim3(kRoBlock), 0, s, J, npix,
+                       ep);
+    hipLaunchKernelGGL(ro_transfer_heavy<3>, dim3(heavy_grid), dim3(kRoBlock), 0, s, J, ep);
     hipLaunchKernelGGL(ro_zero, dim3(grid_for(n_ser)), dim3(kRoBlock), 0, s, J.ser, n_ser);
-    hipLaunchKernelGGL(ro_serial, dim3(grid_for(n_par)), dim3(kRoBlock), 0, s, J);
+    hipLaunchKernelGGL(ro_zero, dim3(1), dim3(kRoBlock), 0, s, J.heavy_count, (uint64_t)1);
+    hipLaunchKernelGGL(ro_transfer_light<4>, dim3(grid_for(n_par)), dim3(kRoBlock), 0, s, J, n_par,
+                       es);
+    hipLaunchKernelGGL(ro_transfer_heavy<4>, dim3(heavy_grid), dim3(kRoBlock), 0, s, J, es);
     hipLaunchKernelGGL(ro_digitise, dim3(grid_for(n_ser)), dim3(kRoBlock), 0, s, J, any_bit);
     return hipGetLastError();
 }
