@@ -74,7 +74,7 @@ class Scene(C.Structure):
         ("theta", C.c_double * N_THETA), ("pivot", (C.c_double * 3) * 3), ("zernike_r", C.c_double),
         ("n_coat", C.c_int32), ("n_s", C.c_int32), ("n_lam", C.c_int32), ("pad0", C.c_int32),
         ("s_max", C.c_double), ("lam0", C.c_double), ("dlam", C.c_double),
-        ("coat", C.POINTER(C.c_float)),
+        ("coat", C.POINTER(C.c_float)), ("coat_r", C.POINTER(C.c_float)),
         ("n_layers", C.c_int32), ("n_scales", C.c_int32), ("screen_n", C.c_int32), ("pad1", C.c_int32),
         ("height", C.c_double * MAX_LAYERS), ("wind", (C.c_double * 2) * MAX_LAYERS),
         ("pix", C.c_double * MAX_SCALES), ("lambda_ref", C.c_double), ("opd", C.POINTER(C.c_float)),
@@ -217,6 +217,11 @@ class Oracle:
             sc.n_coat, sc.n_s, sc.n_lam = ct.shape
             sc.s_max, sc.lam0, sc.dlam = coat_mod.S_MAX, coat_mod.LAM0, coat_mod.DLAM
             sc.coat = ct.ctypes.data_as(C.POINTER(C.c_float))
+            if getattr(scene, "reflectance", None) is not None:
+                rt = np.ascontiguousarray(scene.reflectance, np.float32)
+                assert rt.shape == ct.shape
+                self._keep.append(rt)
+                sc.coat_r = rt.ctypes.data_as(C.POINTER(C.c_float))
         atm = scene.atmosphere
         if atm is not None:
             opd = np.ascontiguousarray(atm.opd, np.float32)

@@ -273,8 +273,21 @@ int orc_intersect(const orc_scene* sc, int k, const double q[3], const double d[
 /* ------------------------------------------------------------------------------------------ */
 /* Coatings (section 2.4.2): transmission probability against incidence angle and wavelength,
  * bilinear on the uniform (s = sin^2 theta, lambda) grid of the input table, clamped at its edges. */
+static double coating_table(const orc_scene* sc, const float* table, int coat, double s,
+                            double lambda_m);
 double orc_coating(const orc_scene* sc, int coat, double s, double lambda_m) {
-    const float* t = sc->coat + (size_t)coat * sc->n_s * sc->n_lam;
+    return coating_table(sc, sc->coat, coat, s, lambda_m);
+}
+
+/* Reflection probability of a coating (section 2.4.2: the four-column description carries
+ * reflection and transmission), on the transmission tables' grid. */
+static double coating_reflect(const orc_scene* sc, int coat, double s, double lambda_m) {
+    return sc->coat_r ? coating_table(sc, sc->coat_r, coat, s, lambda_m) : 0.0;
+}
+
+static double coating_table(const orc_scene* sc, const float* table, int coat, double s,
+                            double lambda_m) {
+    const float* t = table + (size_t)coat * sc->n_s * sc->n_lam;
     double fs = s / (sc->s_max / (double)(sc->n_s - 1));
     double fl = (lambda_m - sc->lam0) / sc->dlam;
     if (fs < 0.0) fs = 0.0;
@@ -776,6 +789,93 @@ static void set_event(orc_event* ev, int status, int surface, const double p[3])
 }
 
 
+#define GHOST_MAX 16
+
+/* The surface a ray meets first (ghost mode, section 2.4.2): the smallest intersection distance
+ * l > 1e-9 m among all surfaces other than `from` whose intersection converges; -1 if none. */
+static int nearest_surface(const orc_scene* sc, const double p[3], const double n[3], int from,
+                           double* margin) {
+    double best = INFINITY, second = INFINITY;
+    int bk = -1;
+    for (int j = 0; j < sc->n_surf; ++j) {
+        if (j == from) continue;
+        double q[3], d[3], l;
+        int it;
+        to_local(sc, j, p, n, q, d);
+        if (orc_intersect(sc, j, q, d, &l, &it) != 0 || !(l > 1e-9)) continue;
+        if (l < best) { second = best; best = l; bk = j; }
+        else if (l < second) second = l;
+    }
+    if (bk >= 0 && second < INFINITY) note_margin(margin, (second - best) / best);
+    return bk;
+}
+
+/* The detector (sections 2.4.2-2.4.3): conversion after the mean free path x Exp(1) along the
+ * refracted direction d, escape, the dead layer, diffusion and the pixel. */
+static void land(const orc_scene* sc, int32_t si, uint64_t photon, int k, const double q[3],
+                 const double d[3], double lam, const double u1[4], double* margin_p,
+                 orc_event* ev, uint32_t* image) {
+    const orc_extra* ex = &sc->ex;
+    double margin = *margin_p;
+    ev->x = q[0]; ev->y = q[1]; ev->z = q[2];
+    double xc = q[0], yc = q[1];
+    if (sc->physics & ORC_SILICON_PHYS) {
+        /* conversion length = mean free path x Exp(1) (section 2.4.2) */
+        double alpha = orc_rajkanan(lam, sc->temp_k) * 100.0; /* m^-1 */
+        double L = alpha > 0.0 ? -log(u1[2]) / alpha : INFINITY;
+        double depth = L * fabs(d[2]);
+        note_margin(&margin, (depth - sc->t_si) / sc->t_si);
+        if (!(depth <= sc->t_si)) {
+            set_event(ev, ORC_ESCAPED, k, q);
+            ev->margin = margin;
+            return;
+        }
+        if (sc->physics & ORC_DEAD_LAYER) {
+            /* field-free dead layer (section 2.4.2): electrons converted within `dead` of the
+             * surface the light enters are removed.  Reading: the paper's "back surface" of a
+             * back-illuminated device is the illuminated one. */
+            note_margin(&margin, (depth - ex->dead) / sc->t_si);
+            if (depth < ex->dead) {
+                set_event(ev, ORC_DEAD, k, q);
+                ev->margin = margin;
+                return;
+            }
+        }
+        xc = q[0] + d[0] * L;
+        yc = q[1] + d[1] * L;
+        if (sc->physics & ORC_DIFFUSION) {
+            /* Gaussian diffusion with sigma proportional to the drift distance (section 2.4.3
+             * simplified: sigma = sigma_max (t_Si - depth)/t_Si), or the field model */
+            double ud[4];
+            draw(sc, si, photon, 6, 0, ud);
+            double sigma = (sc->physics & ORC_FIELD_DIFFUSION)
+                               ? orc_field_sigma(sc, depth)
+                               : sc->sigma_max * (sc->t_si - depth) / sc->t_si;
+            double rad = sqrt(-2.0 * log(ud[0]));
+            xc += sigma * rad * cos(TWO_PI * ud[1]);
+            yc += sigma * rad * sin(TWO_PI * ud[1]);
+        }
+    }
+    ev->xe = xc;
+    ev->ye = yc;
+    /* pixel quantisation (section 2.4.3, last step) */
+    double fx = (xc - sc->chip_x0) / sc->pixel, fy = (yc - sc->chip_y0) / sc->pixel;
+    double ix = floor(fx), iy = floor(fy);
+    note_margin(&margin, fx - ix);
+    note_margin(&margin, 1.0 - (fx - ix));
+    note_margin(&margin, fy - iy);
+    note_margin(&margin, 1.0 - (fy - iy));
+    ev->status = ORC_OFF_CHIP;
+    ev->surface = k;
+    if (ix >= 0.0 && ix < (double)sc->nx && iy >= 0.0 && iy < (double)sc->ny) {
+        ev->status = ORC_DETECTED;
+        ev->pix_i = (int32_t)ix;
+        ev->pix_j = (int32_t)iy;
+        if (image) image[(size_t)ev->pix_j * sc->nx + ev->pix_i] += 1u;
+    }
+    ev->margin = margin;
+}
+
 static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t* image,
                       orc_event* ev) {
     const orc_source* src = &sc->src[si];
@@ -958,10 +1058,39 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         }
     }
 
+    /* The surfaces in travel order (section 2.4.2).  With ghosts, a photon reflected by a filter
+     * or anti-reflection coating propagates backwards (section 2.4.2): from then on the next
+     * surface is the nearest one ahead along the ray among all the others (the paper loops
+     * through all surfaces by their intersection distance), at most GHOST_MAX interactions. */
     double n_cur = 1.0;
+    int medium = ORC_VACUUM;
     double ucoat[4];
     int coat_block = -1;
-    for (int k = 0; k < sc->n_surf; ++k) {
+    int ghost = 0, from = -1, inter = 0, next = 0;
+    for (;;) {
+        int k;
+        if (!ghost) {
+            if (next >= sc->n_surf) {
+                /* ran out of surfaces without a detector */
+                set_event(ev, ORC_MISSED, sc->n_surf, p);
+                ev->margin = margin;
+                return;
+            }
+            k = next;
+        } else {
+            if (inter >= GHOST_MAX) {
+                set_event(ev, ORC_MISSED, from, p);
+                ev->margin = margin;
+                return;
+            }
+            k = nearest_surface(sc, p, n, from, &margin);
+            if (k < 0) {   /* leaves the optics */
+                set_event(ev, ORC_MISSED, from, p);
+                ev->margin = margin;
+                return;
+            }
+            ++inter;
+        }
         const orc_surface* s = &sc->surf[k];
         double q[3], d[3];
         to_local(sc, k, p, n, q, d);
@@ -993,27 +1122,50 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         double dn = d[0] * N[0] + d[1] * N[1] + d[2] * N[2];
         if (dn > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; dn = -dn; }
         double cosi = -dn;
-        /* coating roulette (section 2.4.2): survive with probability T(angle, lambda) */
+        int is_det = (s->kind == ORC_DETECTOR);
+        int reflect = s->kind == ORC_MIRROR;
+        /* coating roulette (section 2.4.2): transmitted with probability T(angle, lambda) (for a
+         * mirror: reflected); with ghosts a filter or anti-reflection coating reflects with
+         * probability R; otherwise the photon is absorbed.  Sequential passage: the surface's own
+         * word (block 2 + k/4); in ghost mode stream 4, block = interaction number. */
         if ((sc->physics & ORC_COATINGS) && s->coating >= 0) {
-            int blk = 2 + k / 4;
-            if (blk != coat_block) { draw(sc, si, photon, (uint32_t)blk, 0, ucoat); coat_block = blk; }
-            double uk = ucoat[k % 4];
+            double uk;
+            if (!ghost) {
+                int blk = 2 + k / 4;
+                if (blk != coat_block) { draw(sc, si, photon, (uint32_t)blk, 0, ucoat); coat_block = blk; }
+                uk = ucoat[k % 4];
+            } else {
+                double ug[4];
+                draw(sc, si, photon, (uint32_t)(inter - 1), 4, ug);
+                uk = ug[0];
+            }
             double T = orc_coating(sc, s->coating, 1.0 - cosi * cosi, lam);
             note_margin(&margin, uk - T);
             if (!(uk < T)) {
-                set_event(ev, ORC_ABSORBED, k, q);
-                ev->margin = margin;
-                return;
+                double R = 0.0;
+                if ((sc->physics & ORC_GHOSTS) && s->kind != ORC_MIRROR) {
+                    R = coating_reflect(sc, s->coating, 1.0 - cosi * cosi, lam);
+                    note_margin(&margin, uk - (T + R));
+                }
+                if (!(uk < T + R)) {
+                    set_event(ev, ORC_ABSORBED, k, q);
+                    ev->margin = margin;
+                    return;
+                }
+                reflect = 1;      /* a ghost: reflected by a refracting surface's coating */
+                ghost = 1;
             }
         }
-        int is_det = (s->kind == ORC_DETECTOR);
-        if (s->kind == ORC_MIRROR) {
+        if (reflect) {
             /* reflection across the normal (section 2.4.2) */
             for (int i = 0; i < 3; ++i) d[i] = d[i] - 2.0 * dn * N[i];
         } else if (!is_det || (sc->physics & ORC_SILICON_PHYS)) {
-            /* refraction by the vector form of Snell's law (section 2.4.2), indices from the
-             * Sellmeier / silicon formulas (section 2.4.1); vacuum elsewhere */
-            double n2 = medium_index(sc, s->medium, lam);
+            /* refraction by the vector form of Snell's law (section 2.4.2) into the medium on the
+             * other side of the surface (in travel order the surface's own medium), indices from
+             * the Sellmeier / silicon formulas (section 2.4.1); vacuum elsewhere */
+            int after = s->medium, before = k > 0 ? sc->surf[k - 1].medium : ORC_VACUUM;
+            int m2 = medium == after ? before : after;
+            double n2 = medium_index(sc, m2, lam);
             double mu = n_cur / n2;
             double kk = 1.0 - mu * mu * (1.0 - cosi * cosi);
             note_margin(&margin, kk);
@@ -1025,72 +1177,16 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
             double f = mu * cosi - sqrt(kk);
             for (int i = 0; i < 3; ++i) d[i] = mu * d[i] + f * N[i];
             n_cur = n2;
+            medium = m2;
         }
-        if (is_det) {
-            ev->x = q[0]; ev->y = q[1]; ev->z = q[2];
-            double xc = q[0], yc = q[1];
-            if (sc->physics & ORC_SILICON_PHYS) {
-                /* conversion length = mean free path x Exp(1) (section 2.4.2) */
-                double alpha = orc_rajkanan(lam, sc->temp_k) * 100.0; /* m^-1 */
-                double L = alpha > 0.0 ? -log(u1[2]) / alpha : INFINITY;
-                double depth = L * fabs(d[2]);
-                note_margin(&margin, (depth - sc->t_si) / sc->t_si);
-                if (!(depth <= sc->t_si)) {
-                    set_event(ev, ORC_ESCAPED, k, q);
-                    ev->margin = margin;
-                    return;
-                }
-                if (sc->physics & ORC_DEAD_LAYER) {
-                    /* field-free dead layer (section 2.4.2): electrons converted within `dead`
-                     * of the surface the light enters are removed.  Reading: the paper's "back
-                     * surface" of a back-illuminated device is the illuminated one. */
-                    note_margin(&margin, (depth - ex->dead) / sc->t_si);
-                    if (depth < ex->dead) {
-                        set_event(ev, ORC_DEAD, k, q);
-                        ev->margin = margin;
-                        return;
-                    }
-                }
-                xc = q[0] + d[0] * L;
-                yc = q[1] + d[1] * L;
-                if (sc->physics & ORC_DIFFUSION) {
-                    /* Gaussian diffusion with sigma proportional to the drift distance
-                     * (section 2.4.3 simplified: sigma = sigma_max (t_Si - depth)/t_Si) */
-                    double ud[4];
-                    draw(sc, si, photon, 6, 0, ud);
-                    double sigma = (sc->physics & ORC_FIELD_DIFFUSION)
-                                       ? orc_field_sigma(sc, depth)
-                                       : sc->sigma_max * (sc->t_si - depth) / sc->t_si;
-                    double rad = sqrt(-2.0 * log(ud[0]));
-                    xc += sigma * rad * cos(TWO_PI * ud[1]);
-                    yc += sigma * rad * sin(TWO_PI * ud[1]);
-                }
-            }
-            ev->xe = xc;
-            ev->ye = yc;
-            /* pixel quantisation (section 2.4.3, last step) */
-            double fx = (xc - sc->chip_x0) / sc->pixel, fy = (yc - sc->chip_y0) / sc->pixel;
-            double ix = floor(fx), iy = floor(fy);
-            note_margin(&margin, fx - ix);
-            note_margin(&margin, 1.0 - (fx - ix));
-            note_margin(&margin, fy - iy);
-            note_margin(&margin, 1.0 - (fy - iy));
-            ev->status = ORC_OFF_CHIP;
-            ev->surface = k;
-            if (ix >= 0.0 && ix < (double)sc->nx && iy >= 0.0 && iy < (double)sc->ny) {
-                ev->status = ORC_DETECTED;
-                ev->pix_i = (int32_t)ix;
-                ev->pix_j = (int32_t)iy;
-                if (image) image[(size_t)ev->pix_j * sc->nx + ev->pix_i] += 1u;
-            }
-            ev->margin = margin;
+        if (is_det && !reflect) {
+            land(sc, si, photon, k, q, d, lam, u1, &margin, ev, image);
             return;
         }
         to_global(sc, k, q, d, p, n);
+        from = k;
+        next = k + 1;
     }
-    /* ran out of surfaces without a detector */
-    set_event(ev, ORC_MISSED, sc->n_surf, p);
-    ev->margin = margin;
 }
 
 int orc_trace(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count, uint32_t* image,

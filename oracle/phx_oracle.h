@@ -25,7 +25,7 @@ enum { ORC_VACUUM = 0, ORC_GLASS = 1, ORC_SILICON = 2 };
 enum { ORC_ATMOSPHERE = 1, ORC_COATINGS = 2, ORC_SILICON_PHYS = 4, ORC_DIFFUSION = 8,
        ORC_AEROSOL = 16, ORC_DISPERSION = 32, ORC_DOME = 64, ORC_HALO = 128,
        ORC_SPIDER = 2048, ORC_DEAD_LAYER = 4096, ORC_SECOND_KICK = 8192,
-       ORC_FIELD_DIFFUSION = 16384 };
+       ORC_FIELD_DIFFUSION = 16384, ORC_GHOSTS = 32768 };
 enum {
     ORC_DETECTED = 0, ORC_OFF_CHIP = 1, ORC_VIGNETTED = 2, ORC_ABSORBED = 3, ORC_MISSED = 4,
     ORC_NONCONV = 5, ORC_TIR = 6, ORC_ESCAPED = 7, ORC_OBSCURED = 8,
@@ -86,6 +86,7 @@ typedef struct {
     int32_t n_coat, n_s, n_lam, pad0;
     double s_max, lam0, dlam;
     const float* coat;
+    const float* coat_r;   /* reflectance on the same grid (ghosts); may be NULL */
     /* atmosphere */
     int32_t n_layers, n_scales, screen_n, pad1;
     double height[ORC_MAX_LAYERS];

@@ -61,3 +61,18 @@ def standard_tables() -> np.ndarray:
 
 
 ROLES = {"mirror": MIRROR, "ar": AR, "filter": FILTER, "detector": DETECTOR_AR}
+
+# Share of the photons not transmitted that a coating reflects (ghosts); the rest is absorbed.
+# Mirrors: their table is already the reflection probability (no ghost branch).
+REFLECT_SHARE = {MIRROR: 0.0, AR: 0.9, FILTER: 0.95, DETECTOR_AR: 0.85}
+
+
+def standard_reflectance(tables=None) -> np.ndarray:
+    """Reflection probabilities R[coating][k_s][k_lambda] for the ghost branch (section 2.4.2: the
+    coating description carries reflection and transmission): a fixed share of 1 - T (interference
+    filters reflect what they do not pass; anti-reflection coatings reflect most of their small
+    loss), float32 on the transmission grid, R <= 1 - T."""
+    t = standard_tables() if tables is None else np.asarray(tables, np.float32)
+    share = np.array([REFLECT_SHARE[c] for c in range(t.shape[0])], np.float32)
+    r = share[:, None, None] * (1.0 - t.astype(np.float64))
+    return np.clip(r, 0.0, 1.0 - t).astype(np.float32)

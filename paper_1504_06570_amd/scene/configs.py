@@ -62,6 +62,7 @@ class Scene:
     perturbation: np.ndarray = field(default_factory=lambda: np.zeros(N_PERTURB))
     meta: dict = field(default_factory=dict)
     extras: Optional[Extras] = None               # parameters of the PHYS_EXTRA bits
+    reflectance: Optional[np.ndarray] = None      # float32 like coatings: ghost reflection
 
 
 def _coated_tma(chip_center=(0.0, 0.0)):

@@ -25,6 +25,7 @@ PHYS_SPIDER = 1 << 11
 PHYS_DEAD_LAYER = 1 << 12
 PHYS_SECOND_KICK = 1 << 13
 PHYS_FIELD_DIFFUSION = 1 << 14
+PHYS_GHOSTS = 1 << 15
 PHYS_EXTRA = (PHYS_AEROSOL | PHYS_DISPERSION | PHYS_DOME | PHYS_HALO | PHYS_SPIDER |
               PHYS_DEAD_LAYER)
 MAX_LAYERS = 8

@@ -442,3 +442,65 @@ def test_field_diffusion_in_the_trace():
     dy = (ev["ye"] - ev["y"])[conv] / sig
     assert stats.kstest(dx, "norm").pvalue > 1e-3
     assert stats.kstest(dy, "norm").pvalue > 1e-3
+
+
+# ---------------------------------------------------------------------------------------------
+# Ghost reflections (section 2.4.2: filter and anti-reflection coatings reflect backwards)
+# ---------------------------------------------------------------------------------------------
+def _plate_scene(T, R, n_photons, sin_theta):
+    """A collimated beam at angle theta through a 1 cm glass plate (two flat coated surfaces with
+    constant T and R) onto an uncoated flat detector 19 cm below it."""
+    from paper_1504_06570_amd.scene import optics as Op
+    from paper_1504_06570_amd.scene.sources import point_sources
+    top = Op.Surface("P1", Op.REFRACT, 0.20, r_out=0.6, medium=Op.GLASS, coating=0)
+    bot = Op.Surface("P2", Op.REFRACT, 0.19, r_out=0.6, medium=Op.VACUUM, coating=0)
+    det = Op.Surface("DET", Op.DETECTOR, 0.0, r_out=5.0, medium=Op.SILICON)
+    chip = Op.Chip(0.0, 0.0, pixel=1e-3, nx=2000, ny=2000)
+    p = Op.Prescription("plate", [top, bot, det], chip, pupil_r_in=0.0, pupil_r_out=0.1,
+                        z_start=1.0, obscuration_z=0.5, obscuration_r=0.0)
+    src = point_sources([sin_theta], [0.0], n_photons, 600e-9, 600e-9)
+    tab = np.full((1, 61, 801), T, np.float32)
+    s = C.Scene("plate", p, src, tab, physics=C.PHYS_COATINGS | X.PHYS_GHOSTS, seed=17)
+    s.reflectance = np.full_like(tab, R)
+    return s
+
+
+def test_ghosts_of_a_plate_are_displaced_by_the_round_trip():
+    """Through a coated plate the photons that reach the detector landed directly (k = 0) or after
+    k double reflections inside the plate: each lands D0 + k Delta from its pupil point with
+    Delta = 2 t tan(theta') (theta' the refracted angle, Snell with the Sellmeier index) and
+    D0 = t tan(theta') + h tan(theta), and the k-th ghost carries the share T^2 R^(2k) of the
+    photons (binomial, 5 sigma)."""
+    T, R, N, st = 0.6, 0.35, 40000, 0.1
+    s = _plate_scene(T, R, N, st)
+    o = O.Oracle(s)
+    ev = o.trace_sources(threads=8)
+    n = o.sellmeier(600e-9)
+    sp = st / n
+    t, h = 0.01, 0.19
+    tan_t = st / math.sqrt(1 - st * st)
+    tan_p = sp / math.sqrt(1 - sp * sp)
+    D0 = t * tan_p + h * tan_t
+    Delta = 2 * t * tan_p
+    land = ev["status"] == O.DETECTED
+    dx = (ev["x"] - ev["px"])[land]
+    k = np.rint((dx - D0) / Delta)
+    assert np.all(np.abs(dx - D0 - k * Delta) < 1e-9)
+    assert np.all(np.abs(ev["y"] - ev["py"])[land] < 1e-9)
+    for j in range(3):
+        p = T * T * R ** (2 * j)
+        c = (k == j).sum()
+        assert abs(c - N * p) < 5 * math.sqrt(N * p * (1 - p)), (j, c, N * p)
+    # photons reflected at the top from outside, or escaping upward after a reflection, leave the
+    # optics (MISSED); the first-surface reflection alone is the share R
+    assert (ev["status"] == O.MISSED).sum() > N * R * 0.9
+
+
+def test_without_reflectance_ghost_mode_equals_the_sequential_trace():
+    """R = 0: no photon is reflected, and the trace equals the one without the ghost flag."""
+    s = _plate_scene(0.8, 0.0, 5000, 0.1)
+    a = O.Oracle(s).trace_sources()
+    s.physics = C.PHYS_COATINGS
+    b = O.Oracle(s).trace_sources()
+    assert np.array_equal(a["status"], b["status"])
+    assert np.array_equal(a["x"], b["x"])
