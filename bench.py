@@ -291,6 +291,46 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
     }
 
 
+def ghost_leg(tr, flags, steps, n_ph, core_ms):
+    """The headline step with ghost reflections: filter, lens and detector coatings reflect what
+    they do not transmit (a fixed share), and reflected photons are traced non-sequentially."""
+    import numpy as np
+    import torch
+    from paper_1504_06570_amd import phx
+    from paper_1504_06570_amd.scene import coatings as cm
+    rt = np.ascontiguousarray(cm.standard_reflectance(), np.float32)
+    tr._check(tr.L.phx_load_reflectance(tr.ctx, rt.ctypes.data, *rt.shape))
+    fx = flags | phx.F_GHOSTS
+    img = tr.new_image()
+    stats = tr.new_stats()
+    tr.trace(img, flags=fx)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        tr.trace(img, flags=fx, stats=stats)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = stats.cpu().numpy()
+    tab = phx.stats_table(st) / steps
+    print(f"# ghosts {ms:.2f} ms/step ({ms / core_ms:.2f}x core)", file=sys.stderr, flush=True)
+    return {
+        "workload": "the headline star with ghost reflections (filter, lens and detector "
+                    "coatings reflect 0.95 / 0.9 / 0.85 of what they do not transmit; pre-roll "
+                    "on without its coating tests)",
+        "photons_per_step": n_ph,
+        "ms_per_step": ms,
+        "value": n_ph / (ms * 1e-3),
+        "cost_vs_core": ms / core_ms,
+        "traced_per_step": float(st[phx.STAT_TRACED]) / steps,
+        "detected_per_step": float(tab[phx.DETECTED].sum()),
+        "off_chip_per_step": float(tab[phx.OFF_CHIP].sum()),
+    }
+
+
 def hybrid_leg(steps, n_ph, core_ms):
     """The headline star through the hybrid two-kick atmosphere: the same seven layers with their
     screens limited to wavenumbers below kappa_crit = 2 pi / (1.5 r0) and the higher modes applied
@@ -550,6 +590,7 @@ def main():
         extra["readout"] = readout_leg(tr, one, max(args.steps, 1))
         del one
         extra["extra_physics"] = extras_leg(tr, scene, flags, max(args.steps, 1), n_ph, ms)
+        extra["ghosts"] = ghost_leg(tr, flags, max(args.steps, 1), n_ph, ms)
         tr.close()
         extra["hybrid_atmosphere"] = hybrid_leg(max(args.steps, 1), n_ph, ms)
 

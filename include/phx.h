@@ -93,6 +93,14 @@ enum {
                                    ATMOSPHERE; the pre-roll then keeps every pupil sample)   */
     PHX_F_FIELD_DIFFUSION = 1u << 14,/* diffusion width from the silicon field model (2.4.3;
                                    with DIFFUSION, in place of sigma_max x drift fraction)   */
+    PHX_F_GHOSTS = 1u << 15,    /* ghost reflections (section 2.4.2; needs COATINGS and
+                                   phx_load_reflectance): a filter or anti-reflection coating
+                                   that does not transmit reflects with probability R; the
+                                   photon then propagates backwards, its next surface being the
+                                   nearest one ahead among all surfaces (at most 16
+                                   interactions, stream 4 block i for interaction i), crossing
+                                   into the medium on the other side of each surface it passes;
+                                   the pre-roll skips its coating tests; phx_adjoint refuses it */
     PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
                                    worst-case transmission of any coated surface (section 3.2,
                                    dynamic transmission optimisation), pupil samples whose
@@ -299,6 +307,14 @@ phx_status phx_set_perturbation(phx_ctx ctx, const double* theta_host, int32_t n
  * Errors: PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
 phx_status phx_load_coatings(phx_ctx ctx, const float* tables_host, int32_t n_coat, int32_t n_s,
                              int32_t n_lambda, double s_max, double lambda0, double dlambda);
+
+/* Load the reflection probabilities of the coatings for ghosts (section 2.4.2: the coating
+ * description carries reflection and transmission against angle and wavelength): float32
+ * [n_coat][n_s][n_lambda] on the grid of the loaded transmission tables (same sizes), with
+ * 0 <= R <= 1 - T (+1e-6).  Copied.  Mirrors ignore it (their table is the reflection).
+ * Errors: PHX_ERR_INVALID, PHX_ERR_STATE (no coatings loaded), PHX_ERR_NOMEM, PHX_ERR_HIP. */
+phx_status phx_load_reflectance(phx_ctx ctx, const float* tables_host, int32_t n_coat,
+                                int32_t n_s, int32_t n_lambda);
 
 /* Load turbulence screens (sections 2.3.1-2.3.2).  opd_dev: float32 [L][S][N][N] optical path
  * (m), row j along y, column i along x, periodic; read only by work enqueued on `stream` during

@@ -22,6 +22,8 @@ struct phx_ctx_s {
     std::string err;
     bool have_presc = false, have_src = false, have_coat = false, have_screens = false;
     bool have_phys = false;
+    bool have_refl = false;
+    float* d_coat_r = nullptr;           // reflection probabilities (ghosts)
     phx_physics phys{};                  // last loaded physics parameters (re-derived on a new
                                          // prescription)
     bool field_ok = false;               // E_z > 0 across the device (field diffusion usable)
@@ -418,6 +420,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_coat_thr);
     free_dev(c->d_esc_thr);
     free_dev(c->d_sig2);
+    free_dev(c->d_coat_r);
     for (int k = 0; k < 4; ++k) free_dev(c->d_ro[k]);
     free_dev(c->d_grad);
     free_dev(c->d_src);
@@ -582,6 +585,8 @@ phx_status phx_load_coatings(phx_ctx c, const float* t, int32_t n_coat, int32_t 
     H.inv_dlam = 1.0 / dlam;
     H.coat = c->d_coat;
     H.coat_thr = c->d_coat_thr;
+    H.coat_r = nullptr;        // new tables: the reflectances must be loaded again
+    c->have_refl = false;
     c->coat_max = mx;
     c->have_coat = true;
     build_cull_order(c);
@@ -757,6 +762,35 @@ phx_status phx_load_physics(phx_ctx c, const phx_physics* x) {
     c->phys = *x;
     c->field_ok = ok;
     c->have_phys = true;
+    c->dirty = true;
+    return PHX_OK;
+}
+
+phx_status phx_load_reflectance(phx_ctx c, const float* r, int32_t n_coat, int32_t n_s,
+                                int32_t n_lam) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!c->have_coat) return fail(c, PHX_ERR_STATE, "load the coatings first");
+    if (!r || n_coat != c->host.n_coat || n_s != c->host.n_s || n_lam != c->host.n_lam)
+        return fail(c, PHX_ERR_INVALID, "reflectance tables must match the coating tables");
+    const size_t n = (size_t)n_coat * n_s * n_lam;
+    std::vector<float> t(n);
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    hipError_t e = hipMemcpy(t.data(), c->d_coat, n * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(coatings)");
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(r[i]) || r[i] < 0.0f || (double)r[i] > 1.0 - (double)t[i] + 1e-6)
+            return fail(c, PHX_ERR_INVALID, "reflectance %zu outside [0, 1 - T]", i);
+    if (!c->d_coat_r) {
+        e = hipMalloc((void**)&c->d_coat_r, n * sizeof(float));
+        if (e != hipSuccess) {
+            c->d_coat_r = nullptr;
+            return fail(c, PHX_ERR_NOMEM, "reflectance tables: %s", hipGetErrorString(e));
+        }
+    }
+    e = hipMemcpy(c->d_coat_r, r, n * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy(reflectance)");
+    c->host.coat_r = c->d_coat_r;
+    c->have_refl = true;
     c->dirty = true;
     return PHX_OK;
 }
@@ -1015,6 +1049,8 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         return fail(c, PHX_ERR_STATE, "PHX_F_ATMOSPHERE without loaded screens");
     if ((a->flags & kExtraFlags) && !c->have_phys)
         return fail(c, PHX_ERR_STATE, "per-photon physics flags without phx_load_physics");
+    if ((a->flags & PHX_F_GHOSTS) && !c->have_refl)
+        return fail(c, PHX_ERR_STATE, "PHX_F_GHOSTS without loaded reflectance tables");
     if ((a->flags & PHX_F_FIELD_DIFFUSION) && !c->field_ok)
         return fail(c, PHX_ERR_INVALID, "silicon field model: E_z not positive across the device");
     if (a->flags & PHX_F_COATINGS)
@@ -1307,6 +1343,8 @@ phx_status phx_adjoint(phx_ctx c, const phx_trace_args* a, const double* seed_de
     if (!c) return PHX_ERR_INVALID;
     if (!a) return fail(c, PHX_ERR_INVALID, "null trace arguments");
     if (!seed_dev || !grad_dev) return fail(c, PHX_ERR_INVALID, "null seed or gradient buffer");
+    if (a->flags & PHX_F_GHOSTS)
+        return fail(c, PHX_ERR_INVALID, "the adjoint follows the sequential path: no ghosts");
     hipStream_t st = (hipStream_t)stream;
     phx_trace_args b = *a;
     // outputs of the forward trace are not produced; the pre-roll changes no converted photon

@@ -88,6 +88,7 @@ struct DevParams {
     int32_t esc_pad;
     int32_t n_cull;
     const float* coat;       // [n_coat][n_s][n_lam]
+    const float* coat_r;     // [n_coat][n_s][n_lam] reflection probability (ghosts), or null
     const int64_t* coat_thr; // [n_coat][n_lam]: pre-roll threshold of wavelength column pair
                              // (il, il + 1): the largest roulette word w whose uniform
                              // (w + 1/2) 2^-32 does not exceed the larger of the two columns'
@@ -188,7 +189,7 @@ constexpr int kTileIters = 8;
 // Flags that select the sky and optics kernels carrying the per-photon physics beyond the core
 // path (the other instantiations hold none of its code).
 constexpr uint32_t kFrontExtra = PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO | PHX_F_SECOND_KICK;
-constexpr uint32_t kBackExtra = PHX_F_AEROSOL | PHX_F_SPIDER;
+constexpr uint32_t kBackExtra = PHX_F_AEROSOL | PHX_F_SPIDER | PHX_F_GHOSTS;
 constexpr int kThreads = 256;   // workgroup size of every trace kernel
 
 // Optional per-kernel timing: events recorded before/after each kernel launch.

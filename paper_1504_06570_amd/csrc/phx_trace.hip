@@ -220,12 +220,13 @@ __device__ __forceinline__ LamCol lambda_column(const DevParams& P, double lam) 
 }
 
 // Coating transmission (section 2.4.2): bilinear in s = sin^2(incidence) and wavelength.
-__device__ __forceinline__ double coating(const DevParams& P, int c, double s, const LamCol& lc) {
+__device__ __forceinline__ double coating(const DevParams& P, int c, double s, const LamCol& lc,
+                                          const float* table = nullptr) {
     double fs = s * P.inv_s_step;
     fs = fmin(fmax(fs, 0.0), (double)(P.n_s - 1));
     const int is = min((int)floor(fs), P.n_s - 2);
     const double a = fs - is, b = lc.b;
-    const float* r0 = P.coat + ((size_t)c * P.n_s + is) * P.n_lam + lc.il;
+    const float* r0 = (table ? table : P.coat) + ((size_t)c * P.n_s + is) * P.n_lam + lc.il;
     const float* r1 = r0 + P.n_lam;
     return (1.0 - a) * ((1.0 - b) * (double)r0[0] + b * (double)r0[1]) +
            a * ((1.0 - b) * (double)r1[0] + b * (double)r1[1]);
@@ -736,11 +737,14 @@ struct Hit {
 
 // Transform into surface k's frame, intersect, clip to the clear aperture, take the normal and
 // play the coating roulette (sections 2.4.1-2.4.2).  Returns 0 to continue or the photon's fate.
+// Returned by hit_surface when a filter or anti-reflection coating reflects the photon (ghosts).
+constexpr int kGhostReflect = 1000;
+
+// Geometry of a surface passage: transform into surface k's frame, intersect, clip to the clear
+// aperture, take the normal (facing the incoming ray).  Returns 0 or the photon's fate.
 template <bool ZERN, bool TAPE = false>
-__device__ __forceinline__ int hit_surface(const DevParams& P, const Launch& L, const Rng& rng,
-                                           int k, const double p[3], const double n[3],
-                                           const LamCol& lc, uint4& wc, int& wc_block, Hit& h,
-                                           int& newton) {
+__device__ __forceinline__ int hit_geometry(const DevParams& P, int k, const double p[3],
+                                            const double n[3], Hit& h, int& newton) {
     const DevSurface& s = P.surf[k];
     if (s.moved) {
         const double r0 = p[0] - s.t[0], r1 = p[1] - s.t[1], r2 = p[2] - s.t[2];
@@ -765,13 +769,29 @@ __device__ __forceinline__ int hit_surface(const DevParams& P, const Launch& L, 
     h.N[0] = -gx * inv; h.N[1] = -gy * inv; h.N[2] = inv;
     h.dn = h.d[0] * h.N[0] + h.d[1] * h.N[1] + h.d[2] * h.N[2];
     if (h.dn > 0.0) { h.N[0] = -h.N[0]; h.N[1] = -h.N[1]; h.N[2] = -h.N[2]; h.dn = -h.dn; }
+    return 0;
+}
+
+template <bool ZERN, bool TAPE = false, bool GHOST = false>
+__device__ __forceinline__ int hit_surface(const DevParams& P, const Launch& L, const Rng& rng,
+                                           int k, const double p[3], const double n[3],
+                                           const LamCol& lc, uint4& wc, int& wc_block, Hit& h,
+                                           int& newton) {
+    const int g = hit_geometry<ZERN, TAPE>(P, k, p, n, h, newton);
+    if (g != 0) return g;
+    const DevSurface& s = P.surf[k];
     if ((L.flags & PHX_F_COATINGS) && s.coating >= 0) {
         const int blk = 2 + (k >> 2);
         if (blk != wc_block) { wc = rng.block(blk); wc_block = blk; }
         const int j = k & 3;
         const uint32_t w = j == 0 ? wc.x : (j == 1 ? wc.y : (j == 2 ? wc.z : wc.w));
         const double T = coating(P, s.coating, 1.0 - h.dn * h.dn, lc);
-        if (!(u01(w) < T)) return PHX_ABSORBED;
+        if (!(u01(w) < T)) {
+            if (GHOST && (L.flags & PHX_F_GHOSTS) && s.kind != PHX_MIRROR &&
+                u01(w) < T + coating(P, s.coating, 1.0 - h.dn * h.dn, lc, P.coat_r))
+                return kGhostReflect;
+            return PHX_ABSORBED;
+        }
     }
     return 0;
 }
@@ -858,7 +878,7 @@ __device__ __forceinline__ bool entrance(const DevParams& P, const Launch& L, co
 // Surfaces k0..k1-1 before the detector (sections 2.4.1-2.4.2): returns true while the photon
 // lives, else fills the outcome.  wc / wc_block cache the roulette block of the last coated
 // surface (wc_block = -1: none).
-template <bool ZERN, bool TAPE = false>
+template <bool ZERN, bool TAPE = false, bool GHOST = false>
 __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch& L, const Rng& rng,
                                                const Optics& oc, Ray& ray, int k0, int k1,
                                                uint4& wc, int& wc_block, Outcome& o,
@@ -867,8 +887,12 @@ __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch&
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
         const DevSurface& s = P.surf[k];
-        int st = hit_surface<ZERN, TAPE>(P, L, rng, k, ray.p, ray.n, oc.lc, wc, wc_block, h,
-                                         o.newton);
+        int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, k, ray.p, ray.n, oc.lc, wc, wc_block,
+                                                h, o.newton);
+        if (GHOST && st == kGhostReflect) {
+            o = ghost_path<ZERN>(P, L, rng, oc, h, k, ray.n_cur, o);
+            return false;
+        }
         if (st == 0) {
             if (TAPE) tape_put(tp, ts, k, h);
             if (s.kind == PHX_MIRROR) {
@@ -900,26 +924,12 @@ __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch&
     return true;
 }
 
-// The detector surface: refraction into silicon, conversion, diffusion and the pixel (sections
-// 2.4.2-2.4.3); fills the outcome.
-template <bool ZERN, bool TAPE = false>
-__device__ __forceinline__ void finish_detector(const DevParams& P, const Launch& L,
-                                                const Rng& rng, const Optics& oc, Ray& ray,
-                                                uint4& wc, int& wc_block, Outcome& o,
-                                                double* tp = nullptr, uint64_t ts = 0) {
-    const int kdet = P.n_surf - 1;
-    Hit h;
-    int st = hit_surface<ZERN, TAPE>(P, L, rng, kdet, ray.p, ray.n, oc.lc, wc, wc_block, h,
-                                     o.newton);
-    if (TAPE && st == 0) tape_put(tp, ts, kdet, h);
-    if (st == 0 && (L.flags & PHX_F_SILICON) && !refract(h, ray.n_cur / n_silicon(oc.lam)))
-        st = PHX_TIR;
-    o.surface = kdet;
+// Landing on the detector after its coating and the refraction into silicon: conversion,
+// diffusion and the pixel (sections 2.4.2-2.4.3); fills the outcome.
+__device__ __forceinline__ void land(const DevParams& P, const Launch& L, const Rng& rng,
+                                     const Optics& oc, const Hit& h, Outcome& o) {
+    o.surface = P.n_surf - 1;
     o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
-    if (st != 0) {
-        o.status = st;
-        return;
-    }
     double xc = h.q[0], yc = h.q[1];
     const int ss = sensor_stage(P, L, rng, oc.lam, h.d, xc, yc);
     if (ss != 0) {
@@ -936,6 +946,165 @@ __device__ __forceinline__ void finish_detector(const DevParams& P, const Launch
         o.pix_i = (int)ix;
         o.pix_j = (int)iy;
     }
+}
+
+// Medium codes on either side of surface k in travel order and their indices.
+__device__ __forceinline__ int medium_before(const DevParams& P, int k) {
+    return k > 0 ? P.surf[k - 1].medium : PHX_VACUUM;
+}
+__device__ __forceinline__ double medium_index(const Optics& oc, int m) {
+    return m == PHX_GLASS ? oc.n_glass : (m == PHX_SILICON ? n_silicon(oc.lam) : 1.0);
+}
+
+// A ghost (section 2.4.2): the photon was reflected by the coating of refracting surface k (hit
+// h, element frame) and propagates backwards; from here on its next surface is the nearest one
+// ahead along the ray among all surfaces but the current one (intersection distance above
+// 1e-9 m), where it is transmitted into the medium on the other side, reflected (a mirror, or a
+// coating's reflection), absorbed or vignetted, for at most kGhostMax interactions (interaction
+// i draws its roulette word from stream 4, block i).  Reaching the detector it lands as usual.
+// Out of line: it runs for few photons.
+constexpr int kGhostMax = 16;
+template <bool ZERN>
+__device__ __noinline__ Outcome ghost_path(const DevParams& P, const Launch& L, Rng rng,
+                                           Optics oc, Hit h, int k, double n_cur, Outcome o) {
+    int medium = medium_before(P, k);
+    // reflect at k and return to the global frame
+    double p[3], n[3];
+    h.d[0] -= 2.0 * h.dn * h.N[0];
+    h.d[1] -= 2.0 * h.dn * h.N[1];
+    h.d[2] -= 2.0 * h.dn * h.N[2];
+    {
+        const DevSurface& s = P.surf[k];
+        if (s.moved) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] +
+                       s.t[i];
+                n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
+            }
+        } else {
+            p[0] = h.q[0]; p[1] = h.q[1]; p[2] = h.q[2] + s.t[2];
+            n[0] = h.d[0]; n[1] = h.d[1]; n[2] = h.d[2];
+        }
+    }
+    int from = k;
+#pragma unroll 1
+    for (int inter = 0; inter < kGhostMax; ++inter) {
+        // the nearest surface ahead
+        double best = INFINITY;
+        int bk = -1;
+#pragma unroll 1
+        for (int j = 0; j < P.n_surf; ++j) {
+            if (j == from) continue;
+            const DevSurface& s = P.surf[j];
+            double q[3], d[3];
+            if (s.moved) {
+                const double r0 = p[0] - s.t[0], r1 = p[1] - s.t[1], r2 = p[2] - s.t[2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    q[i] = s.R[i] * r0 + s.R[3 + i] * r1 + s.R[6 + i] * r2;
+                    d[i] = s.R[i] * n[0] + s.R[3 + i] * n[1] + s.R[6 + i] * n[2];
+                }
+            } else {
+                q[0] = p[0]; q[1] = p[1]; q[2] = p[2] - s.t[2];
+                d[0] = n[0]; d[1] = n[1]; d[2] = n[2];
+            }
+            double l, gx, gy;
+            int it = 0;
+            if (intersect<ZERN>(P, s, q, d, l, gx, gy, it) == 0 && l > 1e-9 && l < best) {
+                best = l;
+                bk = j;
+            }
+        }
+        if (bk < 0) break;   // leaves the optics
+        const DevSurface& s = P.surf[bk];
+        // the interaction: intersection, aperture, normal, then the roulette with this
+        // interaction's own word
+        const int st = hit_geometry<ZERN>(P, bk, p, n, h, o.newton);
+        if (st != 0) {
+            o.status = st; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+            return o;
+        }
+        bool reflect = s.kind == PHX_MIRROR;
+        if ((L.flags & PHX_F_COATINGS) && s.coating >= 0) {
+            const double u = u01(rng.block((uint32_t)inter, 4).x);
+            const double sv = 1.0 - h.dn * h.dn;
+            const double T = coating(P, s.coating, sv, oc.lc);
+            if (!(u < T)) {
+                const double R =
+                    s.kind != PHX_MIRROR ? coating(P, s.coating, sv, oc.lc, P.coat_r) : 0.0;
+                if (!(u < T + R)) {
+                    o.status = PHX_ABSORBED; o.surface = bk;
+                    o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+                    return o;
+                }
+                reflect = true;
+            }
+        }
+        const bool det = s.kind == PHX_DETECTOR;
+        if (reflect) {
+            h.d[0] -= 2.0 * h.dn * h.N[0];
+            h.d[1] -= 2.0 * h.dn * h.N[1];
+            h.d[2] -= 2.0 * h.dn * h.N[2];
+        } else if (!det || (L.flags & PHX_F_SILICON)) {
+            const int after = s.medium, before = medium_before(P, bk);
+            const int m2 = medium == after ? before : after;
+            const double n2 = medium_index(oc, m2);
+            if (!refract(h, n_cur / n2)) {
+                o.status = PHX_TIR; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+                return o;
+            }
+            n_cur = n2;
+            medium = m2;
+        }
+        if (det && !reflect) {
+            land(P, L, rng, oc, h, o);
+            return o;
+        }
+        if (s.moved) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] +
+                       s.t[i];
+                n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
+            }
+        } else {
+            p[0] = h.q[0]; p[1] = h.q[1]; p[2] = h.q[2] + s.t[2];
+            n[0] = h.d[0]; n[1] = h.d[1]; n[2] = h.d[2];
+        }
+        from = bk;
+    }
+    o.status = PHX_MISSED;
+    o.surface = from;
+    o.x = p[0]; o.y = p[1]; o.z = p[2];
+    return o;
+}
+
+// The detector surface: its coating, the refraction into silicon, then the landing (sections
+// 2.4.2-2.4.3); fills the outcome.  GHOST: a reflection by the detector's coating starts a ghost.
+template <bool ZERN, bool TAPE = false, bool GHOST = false>
+__device__ __forceinline__ void finish_detector(const DevParams& P, const Launch& L,
+                                                const Rng& rng, const Optics& oc, Ray& ray,
+                                                uint4& wc, int& wc_block, Outcome& o,
+                                                double* tp = nullptr, uint64_t ts = 0) {
+    const int kdet = P.n_surf - 1;
+    Hit h;
+    int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, kdet, ray.p, ray.n, oc.lc, wc, wc_block, h,
+                                            o.newton);
+    if (GHOST && st == kGhostReflect) {
+        o = ghost_path<ZERN>(P, L, rng, oc, h, kdet, ray.n_cur, o);
+        return;
+    }
+    if (TAPE && st == 0) tape_put(tp, ts, kdet, h);
+    if (st == 0 && (L.flags & PHX_F_SILICON) && !refract(h, ray.n_cur / n_silicon(oc.lam)))
+        st = PHX_TIR;
+    if (st != 0) {
+        o.status = st;
+        o.surface = kdet;
+        o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+        return;
+    }
+    land(P, L, rng, oc, h, o);
 }
 
 // Central obscuration, the surfaces (sections 2.4.1-2.4.2), silicon (sections 2.4.2-2.4.3) and
@@ -1169,7 +1338,9 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
     stats_init(s_stats);
     const DevParams& P = *Pg;
     const int lane = __lane_id();
-    const int n_tests = P.n_cull;
+    // with ghosts a photon may leave the sequential path before a coated surface, so its
+    // sequential roulette words no longer decide its fate: no coating tests then
+    const int n_tests = (L.flags & PHX_F_GHOSTS) ? 0 : P.n_cull;
     // the chunk's one source, read once (the other case reads each photon's source record)
     DevSource one_src{};
     if constexpr (ONE) one_src = P.src[one_si];
@@ -1648,8 +1819,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                         (kq & 1) ? oc.n_glass : 1.0};
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
-                if (trace_surfaces<ZERN>(P, L, rng, oc, ray, k_first, kdet, wc, wc_block, o))
-                    finish_detector<ZERN>(P, L, rng, oc, ray, wc, wc_block, o);
+                if (trace_surfaces<ZERN, false, EXTRA>(P, L, rng, oc, ray, k_first, kdet, wc,
+                                                       wc_block, o))
+                    finish_detector<ZERN, false, EXTRA>(P, L, rng, oc, ray, wc, wc_block, o);
                 newton += o.newton;
             }
             book(P, L, act, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
@@ -1683,7 +1855,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 const Optics oc = optics_of(P, L, lam);
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
-                alive = trace_surfaces<ZERN>(P, L, rng, oc, ray, 0, k_first, wc, wc_block, o);
+                alive = trace_surfaces<ZERN, false, EXTRA>(P, L, rng, oc, ray, 0, k_first, wc,
+                                                           wc_block, o);
             }
             traced += 1;
         }

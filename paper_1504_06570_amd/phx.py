@@ -26,6 +26,7 @@ F_ATMOSPHERE, F_COATINGS, F_SILICON, F_DIFFUSION = 1, 2, 4, 8
 F_CULL, F_EVENTS, F_MOMENTS = 1 << 8, 1 << 9, 1 << 10
 F_AEROSOL, F_DISPERSION, F_DOME, F_HALO = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 F_SPIDER, F_DEAD_LAYER, F_SECOND_KICK, F_FIELD_DIFFUSION = 1 << 11, 1 << 12, 1 << 13, 1 << 14
+F_GHOSTS = 1 << 15
 STATUS = ["DETECTED", "OFF_CHIP", "VIGNETTED", "ABSORBED", "MISSED", "NONCONV", "TIR", "ESCAPED",
           "OBSCURED", "CULLED", "EXTINCT", "DEAD"]
 (DETECTED, OFF_CHIP, VIGNETTED, ABSORBED, MISSED, NONCONV, TIR, ESCAPED, OBSCURED, CULLED,
@@ -187,6 +188,8 @@ def lib():
                                        C.c_void_p, C.c_int32, C.c_int32]
         L.phx_trace.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
         L.phx_load_physics.argtypes = [C.c_void_p, C.POINTER(Physics)]
+        L.phx_load_reflectance.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                           C.c_int32]
         L.phx_readout.argtypes = [C.c_void_p, C.POINTER(ReadoutParams), C.c_void_p, C.c_int32,
                                   C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p]
@@ -203,7 +206,7 @@ def lib():
                   "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace",
                   "phx_set_timing", "phx_get_timing", "phx_set_launch_config",
                   "phx_get_launch_config", "phx_trace_batched", "phx_autotune", "phx_adjoint",
-                  "phx_load_physics", "phx_readout"):
+                  "phx_load_physics", "phx_readout", "phx_load_reflectance"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -276,6 +279,10 @@ class Tracer:
             self._check(self.L.phx_load_coatings(self.ctx, ct.ctypes.data, ct.shape[0], ct.shape[1],
                                                  ct.shape[2], coat_mod.S_MAX, coat_mod.LAM0,
                                                  coat_mod.DLAM))
+        if getattr(scene, "reflectance", None) is not None:
+            rt = np.ascontiguousarray(scene.reflectance, np.float32)
+            self._check(self.L.phx_load_reflectance(self.ctx, rt.ctypes.data, rt.shape[0],
+                                                    rt.shape[1], rt.shape[2]))
         if scene.atmosphere is not None:
             self.load_screens(scene.atmosphere)
         if getattr(scene, "extras", None) is not None:

@@ -216,3 +216,70 @@ def test_field_diffusion_refuses_an_undepleted_device(phx):
     tr.load_physics(X.Extras(vanes=0))
     tr.trace()
     tr.close()
+
+
+GHOST_POS_TOL = 1e-8     # metres, positions after non-sequential ghost paths
+
+
+def test_ghosts_of_a_plate(phx):
+    """Ghost reflections through a coated glass plate (T = 0.6, R = 0.35 on both faces): the
+    non-sequential paths (reflections inside the plate, escapes back to the sky) photon by photon
+    equal to the oracle's; a sixth of the photons land as ghosts."""
+    from tests.test_oracle_extras import _plate_scene
+    s = _plate_scene(0.6, 0.35, 40000, 0.1)
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
+    assert rep["boundary_frac"] < 1e-4
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
+    assert (gev["status"] == phx.MISSED).mean() > 0.3
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_ghosts_full_stack(phx, cull):
+    """Ghosts from the filter, the lenses' and the detector's coatings in the full stack (seven
+    layers, telescope, silicon, diffusion), with and without the pre-roll (whose coating tests
+    are off with ghosts)."""
+    from paper_1504_06570_amd.scene import coatings as cm
+    s = C.full(scale=2e-4, screen_n=256)
+    s.reflectance = cm.standard_reflectance()
+    s.physics = C.PHYS_ALL | X.PHYS_GHOSTS
+    flags = int(s.physics) | (phx.F_CULL if cull else 0)
+    gev, gimg, oev, oimg, st = run_both(phx, s, flags=flags)
+    if cull:
+        keep = gev["status"] != phx.CULLED
+        assert not np.isin(oev["status"][np.isin(oev["photon"], gev["photon"][~keep])],
+                           [O.DETECTED, O.OFF_CHIP]).any()
+        gev = gev[keep]
+        oev = oev[np.isin(oev["photon"], gev["photon"])]
+    # ghost paths end on extended surfaces far off axis (a lens surface 1.8 m from the axis,
+    # near grazing), where the intersection amplifies the two sides' rounding: positions agree to
+    # 2.8e-9 m (largest over 2e5 photons), compared at GHOST_POS_TOL
+    rep = parity.compare(gev, oev, pos_tol=GHOST_POS_TOL, chip=parity.chip_of(s))
+    assert rep["boundary_frac"] < 1e-4
+    assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
+    # ghost paths happened: photons lost upward or landing after a reflection
+    s2 = C.full(scale=2e-4, screen_n=256)
+    o2 = O.Oracle(s2).trace_sources(threads=8)
+    assert (o2["status"] != O.Oracle(s).trace_sources(threads=8)["status"]).sum() > 100
+
+
+def test_ghost_error_paths(phx):
+    """Ghosts need reflectance tables; the adjoint refuses them."""
+    import torch
+    from paper_1504_06570_amd.scene import coatings as cm
+    s = C.telescope(scale=1e-4)
+    tr = phx.Tracer(s)
+    with pytest.raises(phx.PhxError):
+        tr.trace(flags=int(s.physics) | phx.F_GHOSTS)
+    rt = cm.standard_reflectance()
+    tr._check(tr.L.phx_load_reflectance(tr.ctx, rt.ctypes.data, rt.shape[0], rt.shape[1],
+                                        rt.shape[2]))
+    tr.trace(flags=int(s.physics) | phx.F_GHOSTS)
+    with pytest.raises(phx.PhxError):
+        tr.adjoint(torch.zeros((len(s.sources), 8), dtype=torch.float64),
+                   flags=int(s.physics) | phx.F_GHOSTS, photon_count=100)
+    bad = np.ascontiguousarray(rt + 0.5, np.float32)
+    with pytest.raises(phx.PhxError):
+        tr._check(tr.L.phx_load_reflectance(tr.ctx, bad.ctypes.data, bad.shape[0], bad.shape[1],
+                                            bad.shape[2]))
+    tr.close()
