@@ -1760,7 +1760,8 @@ __device__ __forceinline__ void book(const DevParams& P, const Launch& L, bool a
 constexpr int kWin = 32;                  // LDS pixel window of the optics kernel
 constexpr int kQueue = 128;               // queued photons per wavefront (64 + 63 carried)
 constexpr int kWaves = kBlock / 64;
-template <bool ZERN, bool EXTRA>
+// EXTRA: aerosol and the spider at the entrance; GHOST: the ghost branch of the roulette.
+template <bool ZERN, bool EXTRA, bool GHOST>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void back_kernel(
         const DevParams* __restrict__ Pg, const Launch L, uint64_t begin,
         const uint32_t* __restrict__ surv, const unsigned int* __restrict__ count, uint64_t n_all,
@@ -1819,9 +1820,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                         (kq & 1) ? oc.n_glass : 1.0};
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
-                if (trace_surfaces<ZERN, false, EXTRA>(P, L, rng, oc, ray, k_first, kdet, wc,
+                if (trace_surfaces<ZERN, false, GHOST>(P, L, rng, oc, ray, k_first, kdet, wc,
                                                        wc_block, o))
-                    finish_detector<ZERN, false, EXTRA>(P, L, rng, oc, ray, wc, wc_block, o);
+                    finish_detector<ZERN, false, GHOST>(P, L, rng, oc, ray, wc, wc_block, o);
                 newton += o.newton;
             }
             book(P, L, act, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
@@ -1855,7 +1856,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 const Optics oc = optics_of(P, L, lam);
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
-                alive = trace_surfaces<ZERN, false, EXTRA>(P, L, rng, oc, ray, 0, k_first, wc,
+                alive = trace_surfaces<ZERN, false, GHOST>(P, L, rng, oc, ray, 0, k_first, wc,
                                                            wc_block, o);
             }
             traced += 1;
@@ -2523,9 +2524,14 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
         const dim3 bg((unsigned)(want < bcap ? want : bcap));
         unsigned long long* bt = cfg.dynamic ? W.tiles + 2 * c + 1 : nullptr;
         S.mark(2, 0, bs);
-        const bool extra = (L.flags & kBackExtra) != 0;
-        const auto bk = L.any_zernike ? (extra ? back_kernel<true, true> : back_kernel<true, false>)
-                                      : (extra ? back_kernel<false, true> : back_kernel<false, false>);
+        const bool extra = (L.flags & kBackExtra) != 0, ghost = (L.flags & PHX_F_GHOSTS) != 0;
+        const auto bk =
+            L.any_zernike
+                ? (ghost ? back_kernel<true, true, true>
+                         : (extra ? back_kernel<true, true, false> : back_kernel<true, false, false>))
+                : (ghost ? back_kernel<false, true, true>
+                         : (extra ? back_kernel<false, true, false>
+                                  : back_kernel<false, false, false>));
         hipLaunchKernelGGL(bk, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin, S.surv(c), S.cnt(c),
                            sp.len, (const double*)S.state_buf(c), W.chunk, bt);
         S.mark(2, 1, bs);
