@@ -100,7 +100,8 @@ enum {
                                    nearest one ahead among all surfaces (at most 16
                                    interactions, stream 4 block i for interaction i), crossing
                                    into the medium on the other side of each surface it passes;
-                                   the pre-roll skips its coating tests; phx_adjoint refuses it */
+                                   the pre-roll tests only the coated surfaces ahead of the
+                                   first coated refracting one; phx_adjoint refuses it */
     PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
                                    worst-case transmission of any coated surface (section 3.2,
                                    dynamic transmission optimisation), pupil samples whose

@@ -348,7 +348,14 @@ int64_t word_threshold(double r) {
 void build_cull_order(phx_ctx c) {
     DevParams& H = c->host;
     H.n_cull = 0;
+    H.ghost_cull_limit = 0;
     if (!c->have_presc || !c->have_coat) return;
+    H.ghost_cull_limit = c->presc.n_surfaces;
+    for (int k = 0; k < c->presc.n_surfaces; ++k)
+        if (c->presc.surf[k].kind != PHX_MIRROR && c->presc.surf[k].coating >= 0) {
+            H.ghost_cull_limit = k;
+            break;
+        }
     std::vector<std::pair<double, int>> v;
     for (int k = 0; k < c->presc.n_surfaces; ++k) {
         const int co = c->presc.surf[k].coating;

@@ -87,6 +87,8 @@ struct DevParams {
     int32_t esc_col0;          // first column whose esc_thr is not 0 (n_lam when none)
     int32_t esc_pad;
     int32_t n_cull;
+    int32_t ghost_cull_limit;  // first coated refracting surface (n_surf if none): with ghosts the
+                               // pre-roll tests only coated surfaces ahead of it
     const float* coat;       // [n_coat][n_s][n_lam]
     const float* coat_r;     // [n_coat][n_s][n_lam] reflection probability (ghosts), or null
     const int64_t* coat_thr; // [n_coat][n_lam]: pre-roll threshold of wavelength column pair

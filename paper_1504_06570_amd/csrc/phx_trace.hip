@@ -321,21 +321,27 @@ __device__ __forceinline__ uint32_t word_of(const uint4& w, int m) {
     return m == 0 ? w.x : (m == 1 ? w.y : (m == 2 ? w.z : w.w));
 }
 
-// The first (most selective) test, at wavelength column il.
-__device__ __forceinline__ bool preroll_first(const DevParams& P, const Rng& rng, int il) {
+// The first (most selective) test, at wavelength column il; only surfaces below k_lim are
+// tested (with ghosts: the coated surfaces every photon passes sequentially).
+template <bool GHOST>
+__device__ __forceinline__ bool preroll_first(const DevParams& P, const Rng& rng, int il,
+                                              int k_lim) {
     const int k = P.cull_order[0];
+    if (GHOST && k >= k_lim) return false;
     const uint32_t wk = word_of(rng.block(2 + (k >> 2)), k & 3);
     return (int64_t)wk > P.coat_thr[(size_t)P.surf[k].coating * P.n_lam + il];
 }
 
 // Tests 1..n_tests-1 in order, stopping at the first that culls; a roulette block is drawn when
 // the next test's surface needs a different one.
+template <bool GHOST>
 __device__ __forceinline__ bool preroll_rest(const DevParams& P, const Rng& rng, int il,
-                                             int n_tests) {
+                                             int n_tests, int k_lim) {
     int blk = -1;
     uint4 w = make_uint4(0, 0, 0, 0);
     for (int j = 1; j < n_tests; ++j) {
         const int k = P.cull_order[j];
+        if (GHOST && k >= k_lim) continue;
         if (2 + (k >> 2) != blk) {
             blk = 2 + (k >> 2);
             w = rng.block(blk);
@@ -1323,7 +1329,7 @@ __device__ __forceinline__ void culled_event(const Launch& L, uint64_t g, int si
 
 // ONE: every photon of the chunk belongs to source one_si, whose first photon has flattened
 // index `first` (the source index and the Philox key are then uniform over the workgroup).
-template <bool ONE>
+template <bool ONE, bool GHOST>
 __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __restrict__ Pg,
                                                           const Launch L, uint64_t begin,
                                                           uint64_t len, int one_si,
@@ -1338,9 +1344,11 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
     stats_init(s_stats);
     const DevParams& P = *Pg;
     const int lane = __lane_id();
-    // with ghosts a photon may leave the sequential path before a coated surface, so its
-    // sequential roulette words no longer decide its fate: no coating tests then
-    const int n_tests = (L.flags & PHX_F_GHOSTS) ? 0 : P.n_cull;
+    // with ghosts a photon may leave the sequential path at a coated refracting surface, after
+    // which the sequential roulette words no longer decide its fate: only the coated surfaces
+    // ahead of the first coated refracting one (the mirrors) are tested then
+    const int n_tests = P.n_cull;
+    const int k_lim = GHOST ? P.ghost_cull_limit : PHX_MAX_SURF;
     // the chunk's one source, read once (the other case reads each photon's source record)
     DevSource one_src{};
     if constexpr (ONE) one_src = P.src[one_si];
@@ -1380,7 +1388,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 const double rp2 = u01(wr) * (ro * ro - ri * ri) + ri * ri;
                 const int il = lambda_column(P, lam).il;
                 culled = rp2 < L.cull_r2_lo || rp2 > L.cull_r2_hi ||
-                         (n_tests > 0 && preroll_first(P, rng, il));
+                         (n_tests > 0 && preroll_first<GHOST>(P, rng, il, k_lim));
                 pass = !culled;
                 if (culled) culled_event(L, g, si, idx, lam);
                 // time bucket of a survivor (the time stamp is t_e u01(wt))
@@ -1417,7 +1425,7 @@ __global__ __launch_bounds__(kBlock) void generate_kernel(const DevParams* __res
                 }
                 const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
                 const int il = (int)((entry >> 18) & 0x1fffu);
-                culled = preroll_rest(P, rng, il, n_tests);
+                culled = preroll_rest<GHOST>(P, rng, il, n_tests, k_lim);
                 const uint32_t et = P.esc_thr && il >= P.esc_col0 ? P.esc_thr[il] : 0u;
                 bool later = false;
                 if (!culled && et && (L.flags & PHX_F_SILICON)) {
@@ -2370,12 +2378,16 @@ static void launch_preroll(const DevParams* dparams, const Launch& L, const Work
     const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
     const dim3 gg((unsigned)(want < cap ? want : cap));
     uint8_t* key = sort ? W.key : (uint8_t*)nullptr;
-    if (sp.src >= 0)
-        hipLaunchKernelGGL(generate_kernel<true>, gg, dim3(kBlock), 0, stream, dparams, L,
-                           sp.begin, sp.len, L.src_begin + sp.src, sp.first, W.bits, key);
-    else
-        hipLaunchKernelGGL(generate_kernel<false>, gg, dim3(kBlock), 0, stream, dparams, L,
-                           sp.begin, sp.len, 0, (uint64_t)0, W.bits, key);
+    const bool ghost = (L.flags & PHX_F_GHOSTS) != 0;
+    if (sp.src >= 0) {
+        const auto gk = ghost ? generate_kernel<true, true> : generate_kernel<true, false>;
+        hipLaunchKernelGGL(gk, gg, dim3(kBlock), 0, stream, dparams, L, sp.begin, sp.len,
+                           L.src_begin + sp.src, sp.first, W.bits, key);
+    } else {
+        const auto gk = ghost ? generate_kernel<false, true> : generate_kernel<false, false>;
+        hipLaunchKernelGGL(gk, gg, dim3(kBlock), 0, stream, dparams, L, sp.begin, sp.len, 0,
+                           (uint64_t)0, W.bits, key);
+    }
     const uint64_t n_words = (sp.len + 63) / 64;
     const unsigned nb = (unsigned)((n_words + kCompactWords - 1) / kCompactWords);
     if (sort) {
