@@ -72,22 +72,22 @@ __global__ __launch_bounds__(kRoBlock) void ro_bleed(const ReadoutJob J, int lds
     const uint64_t w = (uint64_t)J.p.full_well;
     const uint32_t* src = J.in + j * J.nx;
     uint32_t* row = J.work + j * J.nx;
-    uint32_t* buf = s_half + (int64_t)wave * (J.nx / 2) - a;   // buf[a .. b)
+    uint32_t* buf = s_half + (int64_t)wave * (J.nx / 2);   // buf[x - a] holds pixel x
     bool sat = false;
     for (int64_t x = a + lane; x < b; x += 64) {
         const uint32_t v = src[x];
         row[x] = v;
-        if (lds) buf[x] = v;
+        if (lds) buf[x - a] = v;
         sat |= v > w;
     }
     if (__ballot(sat) == 0) return;
     if (lds) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) bleed_half_row(buf, a, b, half, w);
+        if (lane == 0) bleed_half_row(buf, 0, b - a, half, w);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        for (int64_t x = a + lane; x < b; x += 64) row[x] = buf[x];
+        for (int64_t x = a + lane; x < b; x += 64) row[x] = buf[x - a];
     } else {
         __threadfence();
         __builtin_amdgcn_wave_barrier();

@@ -884,6 +884,11 @@ __device__ __forceinline__ bool entrance(const DevParams& P, const Launch& L, co
 // Surfaces k0..k1-1 before the detector (sections 2.4.1-2.4.2): returns true while the photon
 // lives, else fills the outcome.  wc / wc_block cache the roulette block of the last coated
 // surface (wc_block = -1: none).
+// The ghost branch (defined with the detector landing below).
+template <bool ZERN>
+__device__ __noinline__ Outcome ghost_path(const DevParams& P, const Launch& L, Rng rng,
+                                           Optics oc, Hit h, int k, double n_cur, Outcome o);
+
 template <bool ZERN, bool TAPE = false, bool GHOST = false>
 __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch& L, const Rng& rng,
                                                const Optics& oc, Ray& ray, int k0, int k1,
