@@ -375,8 +375,9 @@ phx_status phx_load_physics(phx_ctx ctx, const phx_physics* physics_host);
  * uint16 (device; adu_capacity elements at least).  work_dev [ny][nx], parallel_dev
  * [amp][sh + over_y][sw] and serial_dev [amp][sh + over_y][sw + over_x] (uint32, device) receive
  * the electrons after steps 2, 3 and 4 when not NULL; otherwise context-owned buffers are used
- * (allocated or grown on first use: that call may synchronise the device).  Enqueued on
- * `stream`.  Errors: PHX_ERR_INVALID, PHX_ERR_CAPACITY, PHX_ERR_NOMEM, PHX_ERR_HIP. */
+ * (allocated or grown on first use: that call may synchronise the device).  Limits (the transfer
+ * stages draw one delay per electron): 1 <= full_well <= 1e7, dark_rate x exposure <= 1e6.
+ * Enqueued on `stream`.  Errors: PHX_ERR_INVALID, PHX_ERR_CAPACITY, PHX_ERR_NOMEM, PHX_ERR_HIP. */
 #define PHX_MAX_AMPS 32
 typedef struct {
     uint32_t seed;

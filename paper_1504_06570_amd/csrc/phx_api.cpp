@@ -1562,8 +1562,10 @@ phx_status phx_readout(phx_ctx c, const phx_readout_params* p, const uint32_t* i
     if (!finite_all(v, 9) || !finite_all(p->gain, n_amp) || !finite_all(p->bias, n_amp) ||
         !finite_all(p->read_noise, n_amp) || !finite_all(p->bit_sigma, 16))
         return fail(c, PHX_ERR_INVALID, "non-finite readout parameter");
-    if (!(p->full_well >= 1.0 && p->full_well <= 4e9) || !(p->exposure >= 0.0) ||
-        !(p->dark_rate >= 0.0) || !(p->hot_fraction >= 0.0) || !(p->dead_fraction >= 0.0) ||
+    // the transfer stages draw one delay per electron: bound the electrons per pixel (a full
+    // well of 1e7 is far above real devices)
+    if (!(p->full_well >= 1.0 && p->full_well <= 1e7) || !(p->exposure >= 0.0) ||
+        !(p->dark_rate >= 0.0) || !(p->dark_rate * p->exposure <= 1e6) || !(p->hot_fraction >= 0.0) || !(p->dead_fraction >= 0.0) ||
         !(p->hot_fraction + p->dead_fraction <= 1.0) || !(p->hot_column_fraction >= 0.0) ||
         !(p->hot_column_fraction <= 1.0) || !(p->cte_parallel > 0.0 && p->cte_parallel <= 1.0) ||
         !(p->cte_serial > 0.0 && p->cte_serial <= 1.0) || !(p->nonlinearity >= 0.0))

@@ -108,7 +108,8 @@ def test_readout_error_paths(phx):
     img = torch.zeros((64, 64), dtype=torch.int32, device="cuda")
     tr = phx.Tracer(C.tiny(scale=1e-4))
     for bad in (dict(amp_nx=3), dict(amp_ny=3), dict(cte_parallel=0.0), dict(gain=(0.0,) * 32),
-                dict(hot_fraction=0.7, dead_fraction=0.7), dict(full_well=0.0)):
+                dict(hot_fraction=0.7, dead_fraction=0.7), dict(full_well=0.0),
+                dict(full_well=2e7), dict(dark_rate=1e5, exposure=15.0)):
         with pytest.raises(phx.PhxError):
             tr.readout(img, Readout(amp_nx=2, amp_ny=2).replace(**bad))
     tr.close()
