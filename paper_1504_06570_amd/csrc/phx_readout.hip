@@ -168,6 +168,12 @@ __device__ __forceinline__ int ro_delay(double u, int64_t m, double eps, double 
     return f;
 }
 
+// Number of 32-bit words w with u01(w) < c: ceil(c 2^32 - 1/2) clamped to [0, 2^32].
+__device__ __forceinline__ uint64_t word_bound(double c) {
+    const double x = ceil(c * 4294967296.0 - 0.5);
+    return x <= 0.0 ? 0ull : (x >= 4294967296.0 ? 4294967296ull : (uint64_t)x);
+}
+
 // Steps 3 and 4: the electrons of one packet at transfer index m - 1 (m transfers), each drawn
 // a delay; electron e reads word e % 4 of draw block e / 4.  Blocks b0, b0 + db, ... are handled
 // here; the kept electrons and those delayed by one slot are counted (the caller adds them to
@@ -180,8 +186,11 @@ __device__ __forceinline__ Kept ro_transfer(uint32_t ne, uint64_t idx, int64_t m
                                             uint32_t* dst, int64_t stride, int64_t n_slots,
                                             uint32_t b0, uint32_t db) {
     uint32_t kept = 0, one = 0;
-    // the first two cumulative probabilities of the delay, as the inversion forms them
+    // the first two cumulative probabilities of the delay, as the inversion forms them, and the
+    // word thresholds they imply: u01(w) = (w + 1/2) 2^-32 < c exactly when w < ceil(c 2^32 - 1/2)
+    // (every step exact in double), so the decisions are integer compares
     const double cum1 = p0 + p0 * ((double)m / 1 * eps);
+    const uint64_t t0 = word_bound(p0), t1 = word_bound(cum1);
     const uint32_t nb = (ne + 3) >> 2;
     for (uint32_t b = b0; b < nb; b += db) {
         const uint4 r = ro_draw(seed, stage, idx, b);
@@ -189,11 +198,11 @@ __device__ __forceinline__ Kept ro_transfer(uint32_t ne, uint64_t idx, int64_t m
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const bool live = (uint32_t)q < left;
-            const double u = u01(ro_word(r, q));
-            kept += live && u < p0;
-            one += live && !(u < p0) && u < cum1;
-            if (live && !(u < cum1)) {   // a delay of two slots or more: rare
-                const int64_t s = m - 1 + ro_delay(u, m, eps, p0);
+            const uint64_t w = ro_word(r, q);
+            kept += live && w < t0;
+            one += live && w >= t0 && w < t1;
+            if (live && w >= t1) {   // a delay of two slots or more: rare
+                const int64_t s = m - 1 + ro_delay(u01((uint32_t)w), m, eps, p0);
                 if (s < n_slots) atomicAdd(dst + s * stride, 1u);
             }
         }
@@ -318,7 +327,8 @@ __global__ __launch_bounds__(kRoBlock) void ro_digitise(const ReadoutJob J, int 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int bit = 4 * k + q;
-                const double a = adu / (double)(1u << bit) + J.p.bit_sigma[bit] * g[q];
+                // ldexp by -bit equals the division by 2^bit exactly
+                const double a = ldexp(adu, -bit) + J.p.bit_sigma[bit] * g[q];
                 const int64_t f = (int64_t)floor(a);
                 if (((f % 2) + 2) % 2) val |= 1u << bit;
             }
