@@ -58,6 +58,8 @@ struct phx_ctx_s {
     uint64_t counts_cap = 0;
     double* d_state = nullptr;           // start-plane state of one chunk [7][ws_chunk]
     uint64_t ws_chunk = 0;
+    double* d_ghost_q = nullptr;         // ghost queues of the optics kernel, one per wavefront
+    uint64_t ghost_waves = 0;
     // kernel timing (phx_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -439,6 +441,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_survivors);
     free_dev(c->d_counts);
     free_dev(c->d_state);
+    free_dev(c->d_ghost_q);
     free_dev(c->d_tiles);
     free_dev(c->d_tape);
     free_dev(c->d_partial);
@@ -1245,6 +1248,24 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
                        (unsigned long long*)c->d_tiles, (unsigned long long*)c->d_bits,
                        c->d_bsum, c->d_key, c->d_hist, c->plan.data(), (uint64_t)c->plan.size(),
                        2};
+    if (a->flags & PHX_F_GHOSTS) {
+        // one queue per wavefront of the largest optics grid of this launch shape; grows only
+        const uint64_t waves = (uint64_t)c->n_cu * c->cfg.back_per_cu * (phx::kThreads / 64);
+        if (waves > c->ghost_waves) {
+            hipError_t e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+            free_dev(c->d_ghost_q);
+            c->ghost_waves = 0;
+            c->graphs_clear();
+            e = hipMalloc((void**)&c->d_ghost_q,
+                          waves * phx::kGhostQ * phx::kGhostFields * sizeof(double));
+            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "ghost queues: %s",
+                                             hipGetErrorString(e));
+            c->ghost_waves = waves;
+        }
+        W.ghost_q = c->d_ghost_q;
+        W.ghost_waves = c->ghost_waves;
+    }
     if (c->cfg.pipeline) {
         if (!c->aux_stream) {
             hipError_t e = hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking);
@@ -1310,9 +1331,10 @@ phx_status phx_trace_batched(phx_ctx c, const phx_trace_args* a, void* stream) {
     // fields are appended one by one)
     std::string key((const char*)&L, sizeof(L));
     auto put = [&key](const void* p, size_t n) { key.append((const char*)p, n); };
-    const void* ptrs[] = {W.survivors, W.counts, W.state, W.tiles, W.bits, W.bsum, W.key, W.hist};
+    const void* ptrs[] = {W.survivors, W.counts, W.state, W.tiles, W.bits, W.bsum, W.key, W.hist,
+                          W.ghost_q};
     put(ptrs, sizeof(ptrs));
-    const uint64_t sizes[] = {W.n_chunks, W.chunk, W.n_plan, (uint64_t)W.buffers};
+    const uint64_t sizes[] = {W.n_chunks, W.chunk, W.n_plan, (uint64_t)W.buffers, W.ghost_waves};
     put(sizes, sizeof(sizes));
     put(W.plan, W.n_plan * sizeof(phx::ChunkSpan));
     put(&c->cfg, sizeof(c->cfg));

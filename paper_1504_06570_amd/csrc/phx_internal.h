@@ -164,7 +164,13 @@ struct Workspace {
     const ChunkSpan* plan;     // host array: the launch's chunks in order
     uint64_t n_plan;
     int buffers;               // survivors and states hold this many chunks (1 or 2)
+    double* ghost_q = nullptr; // [ghost_waves][kGhostFields][kGhostQ] queues of the optics
+    uint64_t ghost_waves = 0;  // kernel with ghosts, one per wavefront of its grid
 };
+// Ghost starts queued per wavefront of the optics kernel with ghosts (64 taken at a time, up to
+// 63 carried and up to 64 added per pass), and the 8-byte fields of one entry.
+constexpr int kGhostQ = 128;
+constexpr int kGhostFields = 15;
 
 // Second stream and events for pipelining chunks (aux null: everything on the caller's stream).
 struct Pipe {

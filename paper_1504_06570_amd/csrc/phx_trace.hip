@@ -889,11 +889,75 @@ template <bool ZERN>
 __device__ __noinline__ Outcome ghost_path(const DevParams& P, const Launch& L, Rng rng,
                                            Optics oc, Hit h, int k, double n_cur, Outcome o);
 
+// A ghost branch met in the surface loop, kept for later: the hit at the reflecting surface k
+// (k = -1: none) and the refractive index of the medium the photon travelled in.  A caller that
+// passes one runs ghost_path itself once every lane of the wavefront has left the loop, so that
+// branches started at different surfaces run together instead of one after another.
+struct GhostStart {
+    Hit h;
+    int k;
+    double n_cur;
+};
+
+// Per-wavefront queue of ghost starts in device memory (optics kernel with ghosts): kGhostQ
+// entries of kGhostFields 8-byte fields (sizes in the internal header), field-major (field f of
+// entry e at f * kGhostQ + e):
+// the hit (q, d, N, dn, l), the index of the medium, the wavelength, (surface << 32 | Newton
+// steps so far) and the photon's position in the survivor list.
+__device__ __forceinline__ void ghost_put(double* q, int e, const GhostStart& gs, double lam,
+                                          uint32_t r, int newton) {
+    double* f = q + e;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f[(0 + i) * kGhostQ] = gs.h.q[i];
+        f[(3 + i) * kGhostQ] = gs.h.d[i];
+        f[(6 + i) * kGhostQ] = gs.h.N[i];
+    }
+    f[9 * kGhostQ] = gs.h.dn;
+    f[10 * kGhostQ] = gs.h.l;
+    f[11 * kGhostQ] = gs.n_cur;
+    f[12 * kGhostQ] = lam;
+    f[13 * kGhostQ] = __longlong_as_double((long long)(((uint64_t)(uint32_t)gs.k << 32) |
+                                                       (uint32_t)newton));
+    f[14 * kGhostQ] = __longlong_as_double((long long)r);
+}
+__device__ __forceinline__ void ghost_get(const double* q, int e, GhostStart& gs, double& lam,
+                                          uint32_t& r, int& newton) {
+    const double* f = q + e;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        gs.h.q[i] = f[(0 + i) * kGhostQ];
+        gs.h.d[i] = f[(3 + i) * kGhostQ];
+        gs.h.N[i] = f[(6 + i) * kGhostQ];
+    }
+    gs.h.dn = f[9 * kGhostQ];
+    gs.h.l = f[10 * kGhostQ];
+    gs.n_cur = f[11 * kGhostQ];
+    lam = f[12 * kGhostQ];
+    const uint64_t kn = (uint64_t)__double_as_longlong(f[13 * kGhostQ]);
+    gs.k = (int)(kn >> 32);
+    newton = (int)(uint32_t)kn;
+    r = (uint32_t)__double_as_longlong(f[14 * kGhostQ]);
+}
+// Appends the lanes holding a ghost start (gs.k >= 0) to the queue of gn entries; returns the
+// new count.  Every lane of the wavefront must call it; the stores are complete on return, so
+// that any lane of the wavefront may read the entries afterwards.
+__device__ __forceinline__ int ghost_push(double* q, int gn, const GhostStart& gs,
+                                          const Outcome& o, uint32_t r) {
+    const bool pend = gs.k >= 0;
+    const uint64_t pm = __ballot(pend);
+    if (pend) ghost_put(q, gn + __popcll(pm & ((1ull << __lane_id()) - 1ull)), gs, o.lam, r,
+                        o.newton);
+    __threadfence_block();
+    return gn + __popcll(pm);
+}
+
 template <bool ZERN, bool TAPE = false, bool GHOST = false>
 __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch& L, const Rng& rng,
                                                const Optics& oc, Ray& ray, int k0, int k1,
                                                uint4& wc, int& wc_block, Outcome& o,
-                                               double* tp = nullptr, uint64_t ts = 0) {
+                                               double* tp = nullptr, uint64_t ts = 0,
+                                               GhostStart* gs = nullptr) {
     Hit h;
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
@@ -901,7 +965,11 @@ __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch&
         int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, k, ray.p, ray.n, oc.lc, wc, wc_block,
                                                 h, o.newton);
         if (GHOST && st == kGhostReflect) {
-            o = ghost_path<ZERN>(P, L, rng, oc, h, k, ray.n_cur, o);
+            if (gs) {
+                gs->h = h; gs->k = k; gs->n_cur = ray.n_cur;
+            } else {
+                o = ghost_path<ZERN>(P, L, rng, oc, h, k, ray.n_cur, o);
+            }
             return false;
         }
         if (st == 0) {
@@ -1097,13 +1165,18 @@ template <bool ZERN, bool TAPE = false, bool GHOST = false>
 __device__ __forceinline__ void finish_detector(const DevParams& P, const Launch& L,
                                                 const Rng& rng, const Optics& oc, Ray& ray,
                                                 uint4& wc, int& wc_block, Outcome& o,
-                                                double* tp = nullptr, uint64_t ts = 0) {
+                                                double* tp = nullptr, uint64_t ts = 0,
+                                                GhostStart* gs = nullptr) {
     const int kdet = P.n_surf - 1;
     Hit h;
     int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, kdet, ray.p, ray.n, oc.lc, wc, wc_block, h,
                                             o.newton);
     if (GHOST && st == kGhostReflect) {
-        o = ghost_path<ZERN>(P, L, rng, oc, h, kdet, ray.n_cur, o);
+        if (gs) {
+            gs->h = h; gs->k = kdet; gs->n_cur = ray.n_cur;
+        } else {
+            o = ghost_path<ZERN>(P, L, rng, oc, h, kdet, ray.n_cur, o);
+        }
         return;
     }
     if (TAPE && st == 0) tape_put(tp, ts, kdet, h);
@@ -1778,7 +1851,8 @@ template <bool ZERN, bool EXTRA, bool GHOST>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void back_kernel(
         const DevParams* __restrict__ Pg, const Launch L, uint64_t begin,
         const uint32_t* __restrict__ surv, const unsigned int* __restrict__ count, uint64_t n_all,
-        const double* __restrict__ st, uint64_t st_stride, unsigned long long* unit_ctr) {
+        const double* __restrict__ st, uint64_t st_stride, unsigned long long* unit_ctr,
+        double* __restrict__ ghost_q) {
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
     __shared__ uint32_t s_win[kWin * kWin];
     __shared__ int s_org;   // window origin: (i0 << 16) | j0, or -1 before the first detection
@@ -1808,8 +1882,40 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     const int k_first = kdet < 1 ? kdet : 1;   // surfaces of the first pass: [0, k_first)
     int qn = 0;                                // queued photons (wavefront-uniform)
     uint32_t newton = 0, traced = 0;
+    // GHOST: photons reflected into a ghost branch wait in the wavefront's queue until 64 are
+    // there (or the work has run out) and then take the branch together
+    double* gq = GHOST ? ghost_q + ((size_t)blockIdx.x * kWaves + wave) * (kGhostQ * kGhostFields)
+                       : nullptr;
+    int gn = 0;                                // queued ghost starts (wavefront-uniform)
     for (;;) {
         const bool more = unit < n_units;
+        if (GHOST && (gn >= 64 || (!more && qn == 0 && gn > 0))) {
+            const int take = gn < 64 ? gn : 64;
+            const bool act = lane < take;
+            Outcome o;
+            outcome_init(o, 0.0);
+            uint64_t g = 0, idx = 0;
+            int si = 0;
+            if (act) {
+                GhostStart gs;
+                double lam;
+                uint32_t r;
+                int nw;
+                ghost_get(gq, gn - take + lane, gs, lam, r, nw);
+                g = begin + (surv ? (uint64_t)surv[r] : (uint64_t)r);
+                decode(L, g, si, idx);
+                const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                outcome_init(o, lam);
+                o.newton = nw;
+                const Optics oc = optics_of(P, L, lam);
+                o = ghost_path<ZERN>(P, L, rng, oc, gs.h, gs.k, gs.n_cur, o);
+                newton += o.newton;
+            }
+            book(P, L, act, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
+            gn -= take;
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
         if (qn >= 64 || (!more && qn > 0)) {
             // second pass: up to 64 queued photons through the remaining surfaces
             const int take = qn < 64 ? qn : 64;
@@ -1818,9 +1924,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             outcome_init(o, 0.0);
             uint64_t g = 0, idx = 0;
             int si = 0;
+            uint32_t r = 0;
+            GhostStart gs;
+            gs.k = -1;
             if (act) {
                 const int e = qn - take + lane;
-                const uint32_t r = qr[e];
+                r = qr[e];
                 const int32_t kq = qk[e];
                 g = begin + (surv ? (uint64_t)surv[r] : (uint64_t)r);
                 decode(L, g, si, idx);
@@ -1833,12 +1942,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                         (kq & 1) ? oc.n_glass : 1.0};
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
+                GhostStart* gp = GHOST ? &gs : nullptr;
                 if (trace_surfaces<ZERN, false, GHOST>(P, L, rng, oc, ray, k_first, kdet, wc,
-                                                       wc_block, o))
-                    finish_detector<ZERN, false, GHOST>(P, L, rng, oc, ray, wc, wc_block, o);
-                newton += o.newton;
+                                                       wc_block, o, nullptr, 0, gp))
+                    finish_detector<ZERN, false, GHOST>(P, L, rng, oc, ray, wc, wc_block, o,
+                                                        nullptr, 0, gp);
             }
-            book(P, L, act, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
+            const bool fin = act && !(GHOST && gs.k >= 0);
+            if (GHOST) gn = ghost_push(gq, gn, gs, o, r);
+            if (fin) newton += o.newton;
+            book(P, L, fin, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
             qn -= take;
             __builtin_amdgcn_wave_barrier();
             continue;
@@ -1853,6 +1966,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         uint64_t g = 0, idx = 0;
         int si = 0;
         Ray ray{{0.0, 0.0, 0.0}, {0.0, 0.0, 1.0}, 1.0};
+        GhostStart gs;
+        gs.k = -1;
         if (valid) {
             g = begin + (surv ? (uint64_t)surv[r] : r);
             decode(L, g, si, idx);
@@ -1870,10 +1985,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
                 alive = trace_surfaces<ZERN, false, GHOST>(P, L, rng, oc, ray, 0, k_first, wc,
-                                                           wc_block, o);
+                                                           wc_block, o, nullptr, 0,
+                                                           GHOST ? &gs : nullptr);
             }
             traced += 1;
         }
+        if (GHOST) gn = ghost_push(gq, gn, gs, o, (uint32_t)r);
         const uint64_t am = __ballot(alive);
         if (alive) {
             const int e = qn + __popcll(am & ((1ull << lane) - 1ull));
@@ -1884,7 +2001,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             qk[e] = (o.newton << 1) | (ray.n_cur != 1.0 ? 1 : 0);
         }
         qn += __popcll(am);
-        const bool done = valid && !alive;
+        const bool done = valid && !alive && !(GHOST && gs.k >= 0);
         if (done) newton += o.newton;
         book(P, L, done, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
         if (unit_ctr) {
@@ -2530,6 +2647,10 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
     if (L.total == 0) return hipSuccess;
     const Stages S{dparams, L, W, n_cu, cfg, stream, pipe, T};
     if (!S.valid()) return hipErrorInvalidValue;
+    // every wavefront of the optics grid needs its own ghost queue
+    if ((L.flags & PHX_F_GHOSTS) &&
+        (!W.ghost_q || W.ghost_waves < (uint64_t)n_cu * cfg.back_per_cu * kWaves))
+        return hipErrorInvalidValue;
     const uint64_t n_chunks = W.n_plan;
     if (cfg.dynamic)
         hipLaunchKernelGGL(fill_u32, dim3((unsigned)((4 * n_chunks + 255) / 256)), dim3(256), 0,
@@ -2550,7 +2671,8 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
                          : (extra ? back_kernel<false, true, false>
                                   : back_kernel<false, false, false>));
         hipLaunchKernelGGL(bk, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin, S.surv(c), S.cnt(c),
-                           sp.len, (const double*)S.state_buf(c), W.chunk, bt);
+                           sp.len, (const double*)S.state_buf(c), W.chunk, bt,
+                           ghost ? W.ghost_q : nullptr);
         S.mark(2, 1, bs);
     });
     return hipGetLastError();
