@@ -264,6 +264,35 @@ def test_ghosts_full_stack(phx, cull):
     assert (o2["status"] != O.Oracle(s).trace_sources(threads=8)["status"]).sum() > 100
 
 
+def test_ghost_queue_under_launch_shapes(phx):
+    """Ghost starts wait in per-wavefront queues of the optics kernel: the same ghost trace under
+    three launch shapes -- one optics workgroup per compute unit on the dynamic schedule (each
+    wavefront carries queued starts through many passes), then twelve (the queues grow), then the
+    default -- gives identical images, statistics and event records."""
+    import torch
+    from paper_1504_06570_amd.scene import coatings as cm
+    s = C.full(scale=2e-4, screen_n=256)
+    s.reflectance = cm.standard_reflectance()
+    s.physics = C.PHYS_ALL | X.PHYS_GHOSTS
+    tr = phx.Tracer(s)
+    shapes = (dict(back_blocks_per_cu=1, dynamic_tiles=1),
+              dict(back_blocks_per_cu=12, dynamic_tiles=0), tr.launch_config())
+    runs = []
+    for kw in shapes:
+        tr.set_launch_config(**kw)
+        img, st, _, evb = tr.trace(stats=tr.new_stats(), event_stride=1, flags=int(s.physics))
+        torch.cuda.synchronize()
+        runs.append((img.cpu().numpy(), st.cpu().numpy(), phx.events_to_numpy(evb)))
+    tr.close()
+    img0, st0, ev0 = runs[0]
+    assert img0.sum() > 0
+    for img, st, ev in runs[1:]:
+        assert np.array_equal(img, img0)
+        assert np.array_equal(st, st0)
+        for name in ev0.dtype.names:
+            assert np.array_equal(ev[name], ev0[name], equal_nan=ev0[name].dtype.kind == "f"), name
+
+
 def test_ghost_error_paths(phx):
     """Ghosts need reflectance tables; the adjoint refuses them."""
     import torch
