@@ -167,9 +167,9 @@ struct Workspace {
     double* ghost_q = nullptr; // [ghost_waves][kGhostFields][kGhostQ] queues of the optics
     uint64_t ghost_waves = 0;  // kernel with ghosts, one per wavefront of its grid
 };
-// Ghost starts queued per wavefront of the optics kernel with ghosts (64 taken at a time, up to
-// 63 carried and up to 64 added per pass), and the 8-byte fields of one entry.
-constexpr int kGhostQ = 128;
+// Ghost starts queued per wavefront of the optics kernel with ghosts (drained once more than
+// kGhostQ - 64 wait; a pass adds up to 64), and the 8-byte fields of one entry.
+constexpr int kGhostQ = 512;
 constexpr int kGhostFields = 15;
 
 // Second stream and events for pipelining chunks (aux null: everything on the caller's stream).

@@ -884,15 +884,10 @@ __device__ __forceinline__ bool entrance(const DevParams& P, const Launch& L, co
 // Surfaces k0..k1-1 before the detector (sections 2.4.1-2.4.2): returns true while the photon
 // lives, else fills the outcome.  wc / wc_block cache the roulette block of the last coated
 // surface (wc_block = -1: none).
-// The ghost branch (defined with the detector landing below).
-template <bool ZERN>
-__device__ __noinline__ Outcome ghost_path(const DevParams& P, const Launch& L, Rng rng,
-                                           Optics oc, Hit h, int k, double n_cur, Outcome o);
-
 // A ghost branch met in the surface loop, kept for later: the hit at the reflecting surface k
-// (k = -1: none) and the refractive index of the medium the photon travelled in.  A caller that
-// passes one runs ghost_path itself once every lane of the wavefront has left the loop, so that
-// branches started at different surfaces run together instead of one after another.
+// (k = -1: none) and the refractive index of the medium the photon travelled in.  The optics
+// kernel queues it and runs the branch once a wavefront's worth is waiting, so that branches
+// started at different surfaces, or by different photons, run together.
 struct GhostStart {
     Hit h;
     int k;
@@ -964,12 +959,8 @@ __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch&
         const DevSurface& s = P.surf[k];
         int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, k, ray.p, ray.n, oc.lc, wc, wc_block,
                                                 h, o.newton);
-        if (GHOST && st == kGhostReflect) {
-            if (gs) {
-                gs->h = h; gs->k = k; gs->n_cur = ray.n_cur;
-            } else {
-                o = ghost_path<ZERN>(P, L, rng, oc, h, k, ray.n_cur, o);
-            }
+        if (GHOST && st == kGhostReflect) {   // GHOST callers pass gs
+            gs->h = h; gs->k = k; gs->n_cur = ray.n_cur;
             return false;
         }
         if (st == 0) {
@@ -1041,52 +1032,61 @@ __device__ __forceinline__ double medium_index(const Optics& oc, int m) {
 // 1e-9 m), where it is transmitted into the medium on the other side, reflected (a mirror, or a
 // coating's reflection), absorbed or vignetted, for at most kGhostMax interactions (interaction
 // i draws its roulette word from stream 4, block i).  Reaching the detector it lands as usual.
-// Out of line: it runs for few photons.
+// ghost_begin sets up the branch, ghost_step performs one interaction.
 constexpr int kGhostMax = 16;
-template <bool ZERN>
-__device__ __noinline__ Outcome ghost_path(const DevParams& P, const Launch& L, Rng rng,
-                                           Optics oc, Hit h, int k, double n_cur, Outcome o) {
-    int medium = medium_before(P, k);
+struct GhostRay {
+    double p[3], n[3];   // global frame
+    double n_cur;        // index of the medium the photon travels in
+    int medium, from, inter;
+};
+
+__device__ __forceinline__ void ghost_begin(const DevParams& P, Hit h, int k, double n_cur,
+                                            GhostRay& gr) {
+    gr.medium = medium_before(P, k);
+    gr.n_cur = n_cur;
+    gr.from = k;
+    gr.inter = 0;
     // reflect at k and return to the global frame
-    double p[3], n[3];
     h.d[0] -= 2.0 * h.dn * h.N[0];
     h.d[1] -= 2.0 * h.dn * h.N[1];
     h.d[2] -= 2.0 * h.dn * h.N[2];
-    {
-        const DevSurface& s = P.surf[k];
-        if (s.moved) {
+    const DevSurface& s = P.surf[k];
+    if (s.moved) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] +
-                       s.t[i];
-                n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
-            }
-        } else {
-            p[0] = h.q[0]; p[1] = h.q[1]; p[2] = h.q[2] + s.t[2];
-            n[0] = h.d[0]; n[1] = h.d[1]; n[2] = h.d[2];
+        for (int i = 0; i < 3; ++i) {
+            gr.p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] +
+                      s.t[i];
+            gr.n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
         }
+    } else {
+        gr.p[0] = h.q[0]; gr.p[1] = h.q[1]; gr.p[2] = h.q[2] + s.t[2];
+        gr.n[0] = h.d[0]; gr.n[1] = h.d[1]; gr.n[2] = h.d[2];
     }
-    int from = k;
-#pragma unroll 1
-    for (int inter = 0; inter < kGhostMax; ++inter) {
-        // the nearest surface ahead
-        double best = INFINITY;
-        int bk = -1;
+}
+
+// One interaction of a ghost branch; true when the photon's fate is settled (o filled).
+template <bool ZERN>
+__device__ __forceinline__ bool ghost_step(const DevParams& P, const Launch& L, const Rng& rng,
+                                        const Optics& oc, GhostRay& gr, Outcome& o) {
+    // the nearest surface ahead
+    double best = INFINITY;
+    int bk = -1;
+    if (gr.inter < kGhostMax) {
 #pragma unroll 1
         for (int j = 0; j < P.n_surf; ++j) {
-            if (j == from) continue;
+            if (j == gr.from) continue;
             const DevSurface& s = P.surf[j];
             double q[3], d[3];
             if (s.moved) {
-                const double r0 = p[0] - s.t[0], r1 = p[1] - s.t[1], r2 = p[2] - s.t[2];
+                const double r0 = gr.p[0] - s.t[0], r1 = gr.p[1] - s.t[1], r2 = gr.p[2] - s.t[2];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     q[i] = s.R[i] * r0 + s.R[3 + i] * r1 + s.R[6 + i] * r2;
-                    d[i] = s.R[i] * n[0] + s.R[3 + i] * n[1] + s.R[6 + i] * n[2];
+                    d[i] = s.R[i] * gr.n[0] + s.R[3 + i] * gr.n[1] + s.R[6 + i] * gr.n[2];
                 }
             } else {
-                q[0] = p[0]; q[1] = p[1]; q[2] = p[2] - s.t[2];
-                d[0] = n[0]; d[1] = n[1]; d[2] = n[2];
+                q[0] = gr.p[0]; q[1] = gr.p[1]; q[2] = gr.p[2] - s.t[2];
+                d[0] = gr.n[0]; d[1] = gr.n[1]; d[2] = gr.n[2];
             }
             double l, gx, gy;
             int it = 0;
@@ -1095,68 +1095,71 @@ __device__ __noinline__ Outcome ghost_path(const DevParams& P, const Launch& L, 
                 bk = j;
             }
         }
-        if (bk < 0) break;   // leaves the optics
-        const DevSurface& s = P.surf[bk];
-        // the interaction: intersection, aperture, normal, then the roulette with this
-        // interaction's own word
-        const int st = hit_geometry<ZERN>(P, bk, p, n, h, o.newton);
-        if (st != 0) {
-            o.status = st; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
-            return o;
-        }
-        bool reflect = s.kind == PHX_MIRROR;
-        if ((L.flags & PHX_F_COATINGS) && s.coating >= 0) {
-            const double u = u01(rng.block((uint32_t)inter, 4).x);
-            const double sv = 1.0 - h.dn * h.dn;
-            const double T = coating(P, s.coating, sv, oc.lc);
-            if (!(u < T)) {
-                const double R =
-                    s.kind != PHX_MIRROR ? coating(P, s.coating, sv, oc.lc, P.coat_r) : 0.0;
-                if (!(u < T + R)) {
-                    o.status = PHX_ABSORBED; o.surface = bk;
-                    o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
-                    return o;
-                }
-                reflect = true;
-            }
-        }
-        const bool det = s.kind == PHX_DETECTOR;
-        if (reflect) {
-            h.d[0] -= 2.0 * h.dn * h.N[0];
-            h.d[1] -= 2.0 * h.dn * h.N[1];
-            h.d[2] -= 2.0 * h.dn * h.N[2];
-        } else if (!det || (L.flags & PHX_F_SILICON)) {
-            const int after = s.medium, before = medium_before(P, bk);
-            const int m2 = medium == after ? before : after;
-            const double n2 = medium_index(oc, m2);
-            if (!refract(h, n_cur / n2)) {
-                o.status = PHX_TIR; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
-                return o;
-            }
-            n_cur = n2;
-            medium = m2;
-        }
-        if (det && !reflect) {
-            land(P, L, rng, oc, h, o);
-            return o;
-        }
-        if (s.moved) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] +
-                       s.t[i];
-                n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
-            }
-        } else {
-            p[0] = h.q[0]; p[1] = h.q[1]; p[2] = h.q[2] + s.t[2];
-            n[0] = h.d[0]; n[1] = h.d[1]; n[2] = h.d[2];
-        }
-        from = bk;
     }
-    o.status = PHX_MISSED;
-    o.surface = from;
-    o.x = p[0]; o.y = p[1]; o.z = p[2];
-    return o;
+    if (bk < 0) {   // leaves the optics, or the interaction limit is reached
+        o.status = PHX_MISSED;
+        o.surface = gr.from;
+        o.x = gr.p[0]; o.y = gr.p[1]; o.z = gr.p[2];
+        return true;
+    }
+    const DevSurface& s = P.surf[bk];
+    // the interaction: intersection, aperture, normal, then the roulette with this interaction's
+    // own word
+    Hit h;
+    const int st = hit_geometry<ZERN>(P, bk, gr.p, gr.n, h, o.newton);
+    if (st != 0) {
+        o.status = st; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+        return true;
+    }
+    bool reflect = s.kind == PHX_MIRROR;
+    if ((L.flags & PHX_F_COATINGS) && s.coating >= 0) {
+        const double u = u01(rng.block((uint32_t)gr.inter, 4).x);
+        const double sv = 1.0 - h.dn * h.dn;
+        const double T = coating(P, s.coating, sv, oc.lc);
+        if (!(u < T)) {
+            const double R = s.kind != PHX_MIRROR ? coating(P, s.coating, sv, oc.lc, P.coat_r) : 0.0;
+            if (!(u < T + R)) {
+                o.status = PHX_ABSORBED; o.surface = bk;
+                o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+                return true;
+            }
+            reflect = true;
+        }
+    }
+    const bool det = s.kind == PHX_DETECTOR;
+    if (reflect) {
+        h.d[0] -= 2.0 * h.dn * h.N[0];
+        h.d[1] -= 2.0 * h.dn * h.N[1];
+        h.d[2] -= 2.0 * h.dn * h.N[2];
+    } else if (!det || (L.flags & PHX_F_SILICON)) {
+        const int after = s.medium, before = medium_before(P, bk);
+        const int m2 = gr.medium == after ? before : after;
+        const double n2 = medium_index(oc, m2);
+        if (!refract(h, gr.n_cur / n2)) {
+            o.status = PHX_TIR; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+            return true;
+        }
+        gr.n_cur = n2;
+        gr.medium = m2;
+    }
+    if (det && !reflect) {
+        land(P, L, rng, oc, h, o);
+        return true;
+    }
+    if (s.moved) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            gr.p[i] = s.R[3 * i] * h.q[0] + s.R[3 * i + 1] * h.q[1] + s.R[3 * i + 2] * h.q[2] +
+                      s.t[i];
+            gr.n[i] = s.R[3 * i] * h.d[0] + s.R[3 * i + 1] * h.d[1] + s.R[3 * i + 2] * h.d[2];
+        }
+    } else {
+        gr.p[0] = h.q[0]; gr.p[1] = h.q[1]; gr.p[2] = h.q[2] + s.t[2];
+        gr.n[0] = h.d[0]; gr.n[1] = h.d[1]; gr.n[2] = h.d[2];
+    }
+    gr.from = bk;
+    gr.inter += 1;
+    return false;
 }
 
 // The detector surface: its coating, the refraction into silicon, then the landing (sections
@@ -1171,12 +1174,8 @@ __device__ __forceinline__ void finish_detector(const DevParams& P, const Launch
     Hit h;
     int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, kdet, ray.p, ray.n, oc.lc, wc, wc_block, h,
                                             o.newton);
-    if (GHOST && st == kGhostReflect) {
-        if (gs) {
-            gs->h = h; gs->k = kdet; gs->n_cur = ray.n_cur;
-        } else {
-            o = ghost_path<ZERN>(P, L, rng, oc, h, kdet, ray.n_cur, o);
-        }
+    if (GHOST && st == kGhostReflect) {   // GHOST callers pass gs
+        gs->h = h; gs->k = kdet; gs->n_cur = ray.n_cur;
         return;
     }
     if (TAPE && st == 0) tape_put(tp, ts, kdet, h);
@@ -1882,37 +1881,54 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     const int k_first = kdet < 1 ? kdet : 1;   // surfaces of the first pass: [0, k_first)
     int qn = 0;                                // queued photons (wavefront-uniform)
     uint32_t newton = 0, traced = 0;
-    // GHOST: photons reflected into a ghost branch wait in the wavefront's queue until 64 are
-    // there (or the work has run out) and then take the branch together
+    // GHOST: photons reflected into a ghost branch wait in the wavefront's queue until more than
+    // kGhostQ - 64 are there (or the work has run out); the queue is then drained with every lane
+    // busy
     double* gq = GHOST ? ghost_q + ((size_t)blockIdx.x * kWaves + wave) * (kGhostQ * kGhostFields)
                        : nullptr;
     int gn = 0;                                // queued ghost starts (wavefront-uniform)
     for (;;) {
         const bool more = unit < n_units;
-        if (GHOST && (gn >= 64 || (!more && qn == 0 && gn > 0))) {
-            const int take = gn < 64 ? gn : 64;
-            const bool act = lane < take;
+        if (GHOST && (gn > kGhostQ - 64 || (!more && qn == 0 && gn > 0))) {
+            // drain the ghost queue one interaction at a time: a lane whose photon is settled
+            // takes the next queued start, so that the lanes stay busy until the queue is empty
+            bool busy = false;
+            GhostRay gr;
             Outcome o;
             outcome_init(o, 0.0);
+            Optics oc{0.0, 1.0, LamCol{0, 0.0}};
+            Rng rng{0u, 0u, 0u, 0u};
             uint64_t g = 0, idx = 0;
             int si = 0;
-            if (act) {
-                GhostStart gs;
-                double lam;
-                uint32_t r;
-                int nw;
-                ghost_get(gq, gn - take + lane, gs, lam, r, nw);
-                g = begin + (surv ? (uint64_t)surv[r] : (uint64_t)r);
-                decode(L, g, si, idx);
-                const Rng rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
-                outcome_init(o, lam);
-                o.newton = nw;
-                const Optics oc = optics_of(P, L, lam);
-                o = ghost_path<ZERN>(P, L, rng, oc, gs.h, gs.k, gs.n_cur, o);
-                newton += o.newton;
+            for (;;) {
+                const uint64_t idle = __ballot(!busy);
+                const int take = min(__popcll(idle), gn);
+                const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+                if (!busy && rank < take) {
+                    GhostStart gs;
+                    double lam;
+                    uint32_t r;
+                    int nw;
+                    ghost_get(gq, gn - take + rank, gs, lam, r, nw);
+                    g = begin + (surv ? (uint64_t)surv[r] : (uint64_t)r);
+                    decode(L, g, si, idx);
+                    rng = Rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                    outcome_init(o, lam);
+                    o.newton = nw;
+                    oc = optics_of(P, L, lam);
+                    ghost_begin(P, gs.h, gs.k, gs.n_cur, gr);
+                    busy = true;
+                }
+                gn -= take;
+                if (__ballot(busy) == 0) break;
+                bool fin = false;
+                if (busy) fin = ghost_step<ZERN>(P, L, rng, oc, gr, o);
+                if (fin) {
+                    newton += o.newton;
+                    busy = false;
+                }
+                book(P, L, fin, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
             }
-            book(P, L, act, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
-            gn -= take;
             __builtin_amdgcn_wave_barrier();
             continue;
         }
