@@ -706,9 +706,10 @@ __device__ __forceinline__ double field_sigma(const DevParams& P, double depth, 
 // proportional to the drift distance to the collecting surface.  With PHX_F_DEAD_LAYER an
 // electron converted less than `dead` below the entrance surface is removed (section 2.4.2
 // field-free layer).  Moves (xc, yc) from the landing point to the electron position; returns 0,
-// PHX_ESCAPED or PHX_DEAD.  Kept out of line: it runs once per photon and inlining it raises the
-// register count of the whole optics loop.
-__device__ __noinline__ int sensor_stage(const DevParams& P, const Launch& L, const Rng& rng,
+// PHX_ESCAPED or PHX_DEAD.  Inlined: it raises the optics kernel's spills (20 -> 65 words), but a
+// call would give the kernel a stack frame and register saves around it, which cost more
+// (headline step 49.9 -> 48.5 ms inlined).
+__device__ __forceinline__ int sensor_stage(const DevParams& P, const Launch& L, const Rng& rng,
                                          double lam, const double* d, double& xc, double& yc) {
     if (L.flags & PHX_F_SILICON) {
         const double alpha = absorption(P, lam);
