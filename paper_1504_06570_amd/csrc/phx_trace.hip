@@ -660,7 +660,12 @@ __device__ void photon_front(const DevParams& P, const Launch& L, int si, uint64
                 gx += ax;
                 gy += ay;
             }
-            if (second) second_kick(P, rng, i, word_of(i < 4 ? kw0 : kw1, i & 3), gx, gy);
+            if (second) {
+                // select by value: a select between the two blocks' addresses would keep them in
+                // scratch memory
+                const uint4 kw = i < 4 ? kw0 : kw1;
+                second_kick(P, rng, i, word_of(kw, i & 3), gx, gy);
+            }
             n[0] += kick * gx;
             n[1] += kick * gy;
             const double inv = rsq_fast(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
