@@ -1,12 +1,26 @@
-"""GPU-vs-oracle comparison helpers (used by the gpu-marked tests and the smoke check)."""
+"""GPU-vs-oracle comparison helpers (used by the gpu-marked tests and the smoke check).
+
+The rule (per-photon parity of a Monte Carlo sample path driven by the same random numbers):
+  * a *boundary photon* is one whose smallest decision margin in the oracle -- distance of its
+    electron position to a pixel edge in pixels, |u - T| of a roulette, the relative distance to
+    an aperture edge, to the silicon thickness or to total internal reflection, a rejection
+    sampler's acceptance test -- is below BOUNDARY_MARGIN; a rounding-level difference between
+    the two implementations may flip one of its decisions;
+  * every other photon has the same status and deciding surface on both sides, its last position
+    (and, when converted, its electron position) within the position bar, and when detected the
+    same pixel;
+  * boundary photons are fewer than 1e-5 of the photons (asserted by the tests);
+  * images agree after each side's boundary photons are taken out of its own image.
+BOUNDARY_MARGIN = 1e-7 is 1e-12 m at the 10 um pixels of the telescope's chip; the measured
+worst position deviation of a converted photon is below 1e-13 m, so no detected photon away from
+the boundary band can change pixel.
+"""
 from __future__ import annotations
 
 import numpy as np
 
 import oracle as O
 
-# A photon whose decision margin (oracle) is below this is a boundary photon: a rounding-level
-# difference between the two implementations may flip one of its decisions.
 BOUNDARY_MARGIN = 1e-7
 POS_TOL = 1e-9          # metres: landing and electron positions
 
@@ -22,50 +36,67 @@ def match(gpu_ev: np.ndarray, orc_ev: np.ndarray):
 
 
 def chip_of(scene):
-    """(x0, y0, pixel) of a scene's chip, for the pixel-edge rule of compare / images_agree."""
+    """(x0, y0, pixel) of a scene's chip (kept for callers that report pixel geometry)."""
     c = scene.prescription.chip
     return (c.x0, c.y0, c.pixel)
 
 
-def near_pixel_edge(ev, chip, pos_tol=POS_TOL):
-    """Photons whose electron position lies within pos_tol of a pixel edge: positions agree only to
-    pos_tol, so their pixel index is not unique."""
-    if chip is None:
-        return np.zeros(len(ev), bool)
-    x0, y0, p = chip
-    fx = (ev["xe"] - x0) / p
-    fy = (ev["ye"] - y0) / p
-    dx = np.abs(fx - np.round(fx)) * p
-    dy = np.abs(fy - np.round(fy)) * p
-    return (dx < pos_tol) | (dy < pos_tol)
+def deviations(g, o):
+    """Per photon the largest coordinate difference of the last position and, for converted
+    photons, of the electron position (metres); NaN where statuses or surfaces differ."""
+    d = np.maximum.reduce([np.abs(g[f] - o[f]) for f in ("x", "y", "z")])
+    conv = o["status"] <= O.OFF_CHIP
+    de = np.maximum(np.abs(g["xe"] - o["xe"]), np.abs(g["ye"] - o["ye"]))
+    d = np.where(conv, np.maximum(d, de), d)
+    same = (g["status"] == o["status"]) & (g["surface"] == o["surface"])
+    return np.where(same, d, np.nan)
+
+
+def group_worst(g, o, d, mask):
+    """Worst deviation per (status, deciding surface) over the photons in mask, with the photon
+    that carries it: {"STATUS@surface": (worst, n, source, photon)}."""
+    out = {}
+    st, sf = o["status"][mask], o["surface"][mask]
+    dm, src, ph = d[mask], o["source"][mask], o["photon"][mask]
+    for key in sorted(set(zip(st.tolist(), sf.tolist()))):
+        m = (st == key[0]) & (sf == key[1])
+        i = int(np.argmax(dm[m]))
+        out[f"{O.STATUS[key[0]]}@{key[1]}"] = (float(dm[m][i]), int(m.sum()), int(src[m][i]),
+                                               int(ph[m][i]))
+    return out
 
 
 def compare(gpu_ev, orc_ev, pos_tol=POS_TOL, chip=None):
-    """Returns a report dict; raises AssertionError on a parity failure.  With the chip geometry,
-    detected photons within pos_tol of a pixel edge (oracle position) are compared by position
-    only."""
+    """Returns a report dict; raises AssertionError on a parity failure (see the module
+    docstring).  `chip` is accepted for older callers and not used: pixel edges are part of the
+    oracle's decision margin."""
     g, o = match(gpu_ev, orc_ev)
     boundary = o["margin"] < BOUNDARY_MARGIN
-    same = g["status"] == o["status"]
-    same &= g["surface"] == o["surface"]
+    same = (g["status"] == o["status"]) & (g["surface"] == o["surface"])
     bad = ~same & ~boundary
     assert not bad.any(), (
         f"{bad.sum()} non-boundary status mismatches; first: gpu {g[bad][:3]} oracle {o[bad][:3]}")
     ok = same & ~boundary
-    dx = np.abs(g["x"] - o["x"])[ok]
-    dy = np.abs(g["y"] - o["y"])[ok]
+    d = deviations(g, o)
+    groups = group_worst(g, o, d, ok)
+    worst = max([0.0] + [v[0] for v in groups.values()])
     conv = ok & (o["status"] <= O.OFF_CHIP)
-    dxe = np.abs(g["xe"] - o["xe"])[conv]
-    dye = np.abs(g["ye"] - o["ye"])[conv]
-    worst = max([0.0] + [float(a.max()) for a in (dx, dy, dxe, dye) if a.size])
-    assert worst <= pos_tol, f"position mismatch {worst:.3e} m > {pos_tol:.1e} m"
-    det = conv & (o["status"] == O.DETECTED) & ~near_pixel_edge(o, chip, pos_tol)
-    assert np.array_equal(g["pix_i"][det], o["pix_i"][det])
-    assert np.array_equal(g["pix_j"][det], o["pix_j"][det])
+    worst_conv = float(d[conv].max()) if conv.any() else 0.0
+    if worst > pos_tol:
+        k = max(groups, key=lambda kk: groups[kk][0])
+        raise AssertionError(f"position mismatch {worst:.3e} m > {pos_tol:.1e} m at {k} "
+                             f"(source {groups[k][2]}, photon {groups[k][3]})")
+    det = ok & (o["status"] == O.DETECTED)
+    flips = det & ((g["pix_i"] != o["pix_i"]) | (g["pix_j"] != o["pix_j"]))
+    assert not flips.any(), (f"{flips.sum()} non-boundary detected photons in different pixels; "
+                             f"first: gpu {g[flips][:2]} oracle {o[flips][:2]}")
     lam = np.abs(g["lam"] - o["lam"]).max() if len(g) else 0.0
-    return dict(n=len(g), boundary=int(boundary.sum()), boundary_frac=float(boundary.mean()) if len(g) else 0.0,
-                status_mismatch_boundary=int((~same).sum()), worst_pos=worst, worst_lam=float(lam),
-                detected=int((o["status"] == O.DETECTED).sum()))
+    return dict(n=len(g), boundary=int(boundary.sum()),
+                boundary_frac=float(boundary.mean()) if len(g) else 0.0,
+                status_mismatch_boundary=int((~same).sum()), worst_pos=worst,
+                worst_converted=worst_conv, worst_lam=float(lam),
+                detected=int((o["status"] == O.DETECTED).sum()),
+                groups={k: v[0] for k, v in groups.items()})
 
 
 def image_without_boundary(img: np.ndarray, ev: np.ndarray) -> np.ndarray:
@@ -78,9 +109,9 @@ def image_without_boundary(img: np.ndarray, ev: np.ndarray) -> np.ndarray:
 
 def images_agree(gpu_img, orc_img, gpu_ev, orc_ev, chip=None):
     """Per-pixel counts equal after removing the boundary photons' contributions from each side
-    (each side's own decision for those photons)."""
+    (each side's own decision for those photons).  `chip` is not used (see compare)."""
     g, o = match(gpu_ev, orc_ev)
-    boundary = (o["margin"] < BOUNDARY_MARGIN) | near_pixel_edge(o, chip)
+    boundary = o["margin"] < BOUNDARY_MARGIN
     gi = gpu_img.astype(np.int64).copy()
     oi = orc_img.astype(np.int64).copy()
     gb = g[boundary & (g["status"] == O.DETECTED)]

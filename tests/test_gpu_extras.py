@@ -49,12 +49,25 @@ def test_each_effect_on_the_paraboloid(phx, flag, kw):
     s.sources.lam_hi[:] = 1080e-9
     gev, gimg, oev, oimg, st = run_both(phx, s)
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     if flag == X.PHYS_AEROSOL:
         assert (gev["status"] == phx.EXTINCT).mean() > 0.1
     if flag == X.PHYS_SPIDER:
         assert (gev["status"] == phx.OBSCURED).mean() > 0.01
+
+
+def test_spider_with_rays_crossing_two_vanes(phx):
+    """Inclined light under a spider of wide, tall vanes (the oracle pin's scene): many rays
+    cross two vanes; the GPU stops each at the same first entry along the ray, and the edge
+    kicks of the rays that pass agree photon by photon."""
+    from tests.test_oracle_extras import inclined_spider_scene
+    s = inclined_spider_scene(200000)
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    rep = parity.compare(gev, oev)
+    assert rep["boundary_frac"] < 1e-5
+    assert parity.images_agree(gimg, oimg, gev, oev)
+    assert (gev["status"] == phx.OBSCURED).mean() > 0.3
 
 
 def test_dead_layer_on_the_flat_detector(phx):
@@ -65,7 +78,7 @@ def test_dead_layer_on_the_flat_detector(phx):
     s.extras = X.Extras(dead=100e-9, vanes=0)   # no spider above this detector's start plane
     gev, gimg, oev, oimg, st = run_both(phx, s)
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert (gev["status"] == phx.DEAD).mean() > 0.1
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
 
@@ -94,7 +107,7 @@ def test_full_stack_with_every_effect(phx, cull):
         gev = gev[keep]
         oev = oev[np.isin(oev["photon"], gev["photon"])]
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert rep["detected"] > 500
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     for status in (phx.EXTINCT, phx.DEAD, phx.OBSCURED):
@@ -117,7 +130,7 @@ def test_batched_graph_with_every_effect(phx):
     tr.close()
     gev, gimg, oev, oimg, st = run_both(phx, s)
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     assert np.array_equal(gimg, a.cpu().numpy().view(np.uint32))
 
@@ -142,9 +155,9 @@ def test_second_kick_on_a_flat_screen(phx):
     """The second kick alone (one layer with a flat screen, r0 = 5 cm: phase variance 1.04 above
     kappa_crit, so 1 - exp(-1.04) of the photons scatter; 320-1080 nm so the
     (lambda / lambda_ref)^(-1/5) scaling varies): photon by photon and pixel by pixel equal to the
-    oracle."""
+    oracle.  2e5 photons, so that one boundary photon is within the 1e-5 bar."""
     from paper_1504_06570_amd.scene.atmosphere import uniform_gradient_atmosphere
-    s = C.tiny(scale=0.2)
+    s = C.tiny(scale=2.0)
     s.sources.lam_lo[:] = 320e-9
     s.sources.lam_hi[:] = 1080e-9
     s.atmosphere = uniform_gradient_atmosphere(0.0, 0.0, n=64, pixels=(1.0,), heights=(0.0,))
@@ -152,7 +165,7 @@ def test_second_kick_on_a_flat_screen(phx):
     s.extras = X.paraboloid_extras().replace(kick_r0=0.05, kick_fraction=(1.0,) + (0.0,) * 7)
     gev, gimg, oev, oimg, st = run_both(phx, s)
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     off = np.hypot(gev["xe"], gev["ye"])
     p = 1.0 - math.exp(-O.Oracle(s).kick_variance(0))
@@ -173,7 +186,7 @@ def test_hybrid_atmosphere_full_stack(phx, cull):
         gev = gev[keep]
         oev = oev[np.isin(oev["photon"], gev["photon"])]
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert rep["detected"] > 500
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
 
@@ -189,7 +202,7 @@ def test_field_diffusion_on_the_flat_detector(phx, lam):
     s.extras = X.Extras(vanes=0)
     gev, gimg, oev, oimg, st = run_both(phx, s)
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     conv = gev["status"] <= phx.OFF_CHIP
     assert np.hypot(gev["xe"] - gev["x"], gev["ye"] - gev["y"])[conv].mean() > 1e-6
@@ -202,7 +215,7 @@ def test_field_diffusion_full_stack(phx):
     s.extras = X.tma_extras()
     gev, gimg, oev, oimg, st = run_both(phx, s)
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
 
 
@@ -219,9 +232,6 @@ def test_field_diffusion_refuses_an_undepleted_device(phx):
     tr.close()
 
 
-GHOST_POS_TOL = 1e-8     # metres, positions after non-sequential ghost paths
-
-
 def test_ghosts_of_a_plate(phx):
     """Ghost reflections through a coated glass plate (T = 0.6, R = 0.35 on both faces): the
     non-sequential paths (reflections inside the plate, escapes back to the sky) photon by photon
@@ -230,7 +240,7 @@ def test_ghosts_of_a_plate(phx):
     s = _plate_scene(0.6, 0.35, 40000, 0.1)
     gev, gimg, oev, oimg, st = run_both(phx, s)
     rep = parity.compare(gev, oev, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     assert (gev["status"] == phx.MISSED).mean() > 0.3
 
@@ -252,11 +262,8 @@ def test_ghosts_full_stack(phx, cull):
                            [O.DETECTED, O.OFF_CHIP]).any()
         gev = gev[keep]
         oev = oev[np.isin(oev["photon"], gev["photon"])]
-    # ghost paths end on extended surfaces far off axis (a lens surface 1.8 m from the axis,
-    # near grazing), where the intersection amplifies the two sides' rounding: positions agree to
-    # 2.8e-9 m (largest over 2e5 photons), compared at GHOST_POS_TOL
-    rep = parity.compare(gev, oev, pos_tol=GHOST_POS_TOL, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     # ghost paths happened: photons lost upward or landing after a reflection
     s2 = C.full(scale=2e-4, screen_n=256)
@@ -318,8 +325,7 @@ def test_ghost_error_paths(phx):
 def test_batched_graph_with_hybrid_ghosts_and_field_diffusion(phx):
     """The captured-graph batched trace with the hybrid atmosphere's second kick, ghost
     reflections, the field model of the diffusion and every per-photon effect at once equals the
-    eager trace on every replay, and photon by photon the oracle (positions after ghost paths at
-    the ghost tolerance)."""
+    eager trace on every replay, and photon by photon the oracle."""
     import torch
     from paper_1504_06570_amd.scene import coatings as cm
     from paper_1504_06570_amd.scene.atmosphere import make_atmosphere
@@ -339,7 +345,7 @@ def test_batched_graph_with_hybrid_ghosts_and_field_diffusion(phx):
     assert all(torch.equal(a, b) for b in imgs)
     tr.close()
     gev, gimg, oev, oimg, st = run_both(phx, s)
-    rep = parity.compare(gev, oev, pos_tol=GHOST_POS_TOL, chip=parity.chip_of(s))
-    assert rep["boundary_frac"] < 1e-4
+    rep = parity.compare(gev, oev, chip=parity.chip_of(s))
+    assert rep["boundary_frac"] < 1e-5
     assert parity.images_agree(gimg, oimg, gev, oev, chip=parity.chip_of(s))
     assert np.array_equal(gimg, a.cpu().numpy().view(np.uint32))

@@ -244,6 +244,84 @@ def test_spider_edge_diffraction_kick_is_lambda_over_4_pi_d():
     assert abs(plus - 0.5) < 5 * math.sqrt(0.25 / far.sum())
 
 
+def inclined_spider_scene(n_photons=20000, incline=0.4):
+    """A flat detector (z = 0, start plane z = 1 m) under a four-vane spider of wide, tall vanes
+    (w = 5 cm, r <= 0.6 m, 0.2 <= z <= 0.9 m) lit by a source inclined along the diagonal
+    (direction cosines (incline, incline)): a ray passing near the centre crosses two vanes, one
+    along x and one along y."""
+    s = H.flat_detector_scene(n_photons=n_photons, xi=incline, eta=incline, physics=X.PHYS_SPIDER)
+    s.extras = X.Extras(vanes=4, vane_angle=0.0, vane_width=0.05, vane_r_in=0.0, vane_r_out=0.6,
+                        vane_z_lo=0.2, vane_z_hi=0.9)
+    return s
+
+
+def _first_vane_entry(p, n, x):
+    """First point along p + t n (t >= 0) inside a vane box, by marching in steps of 1 mm and
+    bisecting the step where the point enters a box (point-in-box tests only); returns that t,
+    the vanes holding the point just after it, and every vane the ray passes through."""
+    def inside(t):
+        q = p + t * n
+        hits = []
+        for k in range(x.vanes):
+            a = x.vane_angle + 2 * math.pi * k / x.vanes
+            u = q[0] * math.cos(a) + q[1] * math.sin(a)
+            v = -q[0] * math.sin(a) + q[1] * math.cos(a)
+            if (x.vane_r_in <= u <= x.vane_r_out and abs(v) <= 0.5 * x.vane_width and
+                    x.vane_z_lo <= q[2] <= x.vane_z_hi):
+                hits.append(k)
+        return hits
+    t_end = (x.vane_z_lo - p[2]) / n[2] + 1e-9
+    ts = np.arange(0.0, t_end + 1e-3, 1e-3)
+    first, entered, crossed = None, [], set()
+    for i, t in enumerate(ts):
+        h = inside(t)
+        crossed.update(h)
+        if h and first is None:
+            lo, hi = (ts[i - 1] if i else 0.0), t
+            if i == 0:
+                first = 0.0
+            else:
+                for _ in range(60):
+                    mid = 0.5 * (lo + hi)
+                    if inside(mid):
+                        hi = mid
+                    else:
+                        lo = mid
+                first = hi
+            entered = inside(first + 1e-9)
+    return first, entered, crossed
+
+
+def test_spider_event_is_the_first_vane_entry_along_the_ray():
+    """A ray that crosses two vanes is stopped where it first enters a vane along its path (the
+    reading of the spider volumes, section 2.4.1): the event point equals the first point of the
+    ray inside any vane box, found by marching and bisection with point-in-box tests; the cases
+    include rays whose first vane has the larger index, and entries through the top face and
+    through the side faces."""
+    s = inclined_spider_scene(20000)
+    ev = O.Oracle(s).trace_sources(threads=8)
+    x = s.extras
+    nx = ny = 0.4
+    n = np.array([nx, ny, -math.sqrt(1.0 - nx * nx - ny * ny)])
+    z0 = s.prescription.z_start
+    sh = np.nonzero(ev["status"] == O.OBSCURED)[0]
+    assert len(sh) > 500
+    two, later_lower, side = 0, 0, 0
+    for i in sh[:400]:
+        # the pupil sample lies on the flat detector (z = 0); the ray starts on the start plane
+        p = np.array([ev["px"][i], ev["py"][i], 0.0]) + n * z0 / n[2]
+        t, entered, crossed = _first_vane_entry(p, n, x)
+        assert t is not None and entered
+        want = p + t * n
+        got = np.array([ev["x"][i], ev["y"][i], ev["z"][i]])
+        assert np.abs(got - want).max() < 1e-9, (i, got, want)
+        if len(crossed) > 1:
+            two += 1
+            later_lower += min(entered) > min(crossed)
+        side += abs(want[2] - x.vane_z_hi) > 1e-9
+    assert two > 20 and later_lower > 5 and side > 20, (two, later_lower, side)
+
+
 # ---------------------------------------------------------------------------------------------
 # Field-free dead layer (section 2.4.2)
 # ---------------------------------------------------------------------------------------------

@@ -1,5 +1,6 @@
-"""The GPU-vs-oracle comparison rules themselves (no GPU): a photon closer to a pixel edge than the
-position tolerance may land in either pixel; any other pixel difference is a failure."""
+"""The GPU-vs-oracle comparison rules themselves (no GPU): only photons inside the oracle's
+decision-margin band may change pixel or status, they count as boundary photons, and every other
+difference is a failure."""
 import numpy as np
 import pytest
 
@@ -7,38 +8,62 @@ import oracle as O
 from tests import parity
 
 
-def _events(xe, pix_i, status=O.DETECTED):
+def _events(xe, pix_i, status=O.DETECTED, margin=1.0, surface=1):
     ev = np.zeros(len(xe), O.EVENT_DTYPE)
     ev["photon"] = np.arange(len(xe))
     ev["status"] = status
-    ev["surface"] = 1
+    ev["surface"] = surface
     ev["xe"] = xe
     ev["x"] = xe
     ev["ye"] = ev["y"] = 0.5e-5     # mid-pixel in y
     ev["pix_i"] = pix_i
-    ev["margin"] = 1.0
+    ev["margin"] = margin
     return ev
 
 
-def test_pixel_flip_within_the_position_tolerance_is_allowed_only_with_the_chip():
-    chip = (0.0, 0.0, 1e-5)
-    o = _events([1e-5 + 2e-10, 2.5e-5], [1, 2])
-    g = _events([1e-5 - 1e-10, 2.5e-5], [0, 2])
+def test_pixel_flip_is_allowed_only_for_a_boundary_photon():
+    # photon 0 sits 2e-12 m (2e-7 px) from the edge between pixels 0 and 1: not a boundary photon
+    o = _events([1e-5 + 2e-12, 2.5e-5], [1, 2])
+    g = _events([1e-5 - 1e-12, 2.5e-5], [0, 2])
     with pytest.raises(AssertionError):
         parity.compare(g, o)
-    rep = parity.compare(g, o, chip=chip)
-    assert rep["n"] == 2
     img_o = np.zeros((1, 4), np.uint32)
     img_g = np.zeros((1, 4), np.uint32)
     img_o[0, [1, 2]] += 1
     img_g[0, [0, 2]] += 1
     assert not parity.images_agree(img_g, img_o, g, o)
-    assert parity.images_agree(img_g, img_o, g, o, chip=chip)
+    # the same photon with an oracle margin below the band is a boundary photon
+    o["margin"][0] = 0.5 * parity.BOUNDARY_MARGIN
+    rep = parity.compare(g, o)
+    assert rep["boundary"] == 1 and rep["boundary_frac"] == 0.5
+    assert parity.images_agree(img_g, img_o, g, o)
 
 
-def test_pixel_flip_beyond_the_position_tolerance_fails():
-    chip = (0.0, 0.0, 1e-5)
-    o = _events([1e-5 + 5e-9], [1])
-    g = _events([1e-5 + 5e-9], [0])
+def test_position_beyond_the_bar_fails_and_names_the_photon():
+    o = _events([1e-5 + 5e-6], [1])
+    g = _events([1e-5 + 5e-6 + 2e-9], [1])
+    with pytest.raises(AssertionError, match=r"DETECTED@1 \(source 0, photon 0\)"):
+        parity.compare(g, o)
+
+
+def test_status_mismatch_fails_outside_the_band():
+    o = _events([5e-6, 15e-6], [0, 1])
+    g = _events([5e-6, 15e-6], [0, 1])
+    g["status"][1] = O.ABSORBED
     with pytest.raises(AssertionError):
-        parity.compare(g, o, chip=chip)
+        parity.compare(g, o)
+    o["margin"][1] = 0.0
+    assert parity.compare(g, o)["status_mismatch_boundary"] == 1
+
+
+def test_report_groups_worst_by_status_and_surface():
+    o = np.concatenate([_events([5e-6, 15e-6], [0, 1]),
+                        _events([25e-6], [2], status=O.ABSORBED, surface=3)])
+    o["photon"] = np.arange(3)
+    g = o.copy()
+    g["x"][2] += 3e-13
+    g["xe"][1] += 1e-14
+    rep = parity.compare(g, o)
+    assert rep["groups"]["ABSORBED@3"] == pytest.approx(3e-13, rel=1e-3)
+    assert rep["groups"]["DETECTED@1"] == pytest.approx(1e-14, rel=1e-2)
+    assert rep["worst_converted"] == pytest.approx(1e-14, rel=1e-2)
