@@ -400,6 +400,21 @@ phx_status phx_readout(phx_ctx ctx, const phx_readout_params* params_host,
  * Enqueued on `stream`.  Errors: PHX_ERR_INVALID, PHX_ERR_STATE, PHX_ERR_CAPACITY, PHX_ERR_HIP. */
 phx_status phx_trace(phx_ctx ctx, const phx_trace_args* args, void* stream);
 
+/* The same trace as phx_trace for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): phx_trace_noalloc calls
+ * no hipMalloc or hipFree and creates no stream or event.  Its workspace is a file-scope device
+ * array of 40 MiB per GPU (held until the process ends), whose address the library looks up
+ * once per device when a context is created; the caller still passes the image, statistics,
+ * moments and event buffers.  Photons, results and error behaviour are those of phx_trace with
+ * the same arguments (the launch is cut into chunks of at most 2^19 photons, run on `stream`
+ * alone).  Limits: at most 65536 sources and 16384 chunks (about 8.6e9 photons); PHX_F_GHOSTS
+ * is refused (PHX_ERR_INVALID: ghost queues need context memory); beyond a limit
+ * PHX_ERR_CAPACITY, nothing enqueued.  Every call on one GPU shares that GPU's workspace, so
+ * calls that overlap on one GPU (two streams, two threads or two contexts) race: serialise them.
+ * The parameter block is uploaded on `stream` when a load changed it (that call synchronises
+ * `stream`). */
+phx_status phx_trace_noalloc(phx_ctx ctx, const phx_trace_args* args, void* stream);
+
 /* Launch shape of phx_trace / phx_trace_batched / phx_adjoint.  chunk_log2: photons per chunk =
  * 2^chunk_log2 (16..27; the context keeps survivor lists and 56-byte states for two chunks);
  * *_blocks_per_cu: workgroups of 256 lanes per compute unit for the pre-roll, sky+atmosphere and

@@ -91,7 +91,8 @@ struct phx_ctx_s {
     unsigned int* d_bsum = nullptr;
     uint8_t* d_key = nullptr;
     unsigned int* d_hist = nullptr;
-    std::vector<phx::ChunkSpan> plan;
+    std::vector<phx::ChunkSpan> plan;   // reserved for kNoAllocMaxChunks chunks at creation
+    void* scratch = nullptr;            // device address of this GPU's no-allocation workspace
     double sed_lo = 0.0;                    // lowest SED bin edge (m)
     std::vector<double> grad_max;           // [layer][scale] largest gradient norm of a screen
     void graphs_clear() {
@@ -412,9 +413,20 @@ phx_status phx_create(int32_t device, phx_ctx* out) {
         if (e == hipSuccess) c->n_cu = prop.multiProcessorCount;
     }
     if (e == hipSuccess) e = hipMalloc((void**)&c->dparams, sizeof(DevParams));
+    // the device address of this GPU's phx_trace_noalloc workspace (looked up once per device,
+    // with the device current)
+    if (e == hipSuccess) e = phx::scratch_address(device, &c->scratch);
     if (e != hipSuccess) {
+        free_dev(c->dparams);
         delete c;
         return PHX_ERR_HIP;
+    }
+    try {
+        c->plan.reserve(phx::kNoAllocMaxChunks);
+    } catch (...) {
+        free_dev(c->dparams);
+        delete c;
+        return PHX_ERR_NOMEM;
     }
     *out = c;
     return PHX_OK;
@@ -1048,10 +1060,9 @@ void set_cull_radii(phx_ctx c, const phx_trace_args* a, phx::Launch& L) {
     L.cull_r2_hi = hi * hi;
 }
 
-// Validation, uploads and workspace for a trace; fills the launch description.  May synchronise
-// `st` (new prefix table, growing workspace, changed parameter block).
-phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Launch& L,
-                   phx::Workspace& W, bool need_image = true) {
+// Validation and the launch description (no device allocation, no upload): the sources, the
+// photon total and the event capacity.  The prefix table is not set here.
+phx_status validate_launch(phx_ctx c, const phx_trace_args* a, phx::Launch& L, bool need_image) {
     if (!a) return fail(c, PHX_ERR_INVALID, "null trace arguments");
     if (!c->have_presc || !c->have_src)
         return fail(c, PHX_ERR_STATE, "load a prescription and sources first");
@@ -1108,19 +1119,86 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
             return fail(c, PHX_ERR_INVALID, "photon total overflows");
         L.total = a->photon_count * (uint64_t)L.n_src;
     } else {
-        std::vector<uint64_t> pre(L.n_src + 1, 0);
+        uint64_t total = 0;
         for (int s = 0; s < L.n_src; ++s) {
             const uint64_t n = c->src[a->src_begin + s].n_photons;
-            if (pre[s] > UINT64_MAX - n) return fail(c, PHX_ERR_INVALID, "photon total overflows");
-            pre[s + 1] = pre[s] + n;
+            if (total > UINT64_MAX - n) return fail(c, PHX_ERR_INVALID, "photon total overflows");
+            total += n;
         }
-        L.total = pre[L.n_src];
+        L.total = total;
+    }
+    if (a->photon_begin > UINT64_MAX - (L.total ? L.total : 0))
+        return fail(c, PHX_ERR_INVALID, "photon index overflows");
+    if (need_image && (a->flags & PHX_F_EVENTS)) {
+        if (!a->events_dev || a->event_stride == 0)
+            return fail(c, PHX_ERR_INVALID, "PHX_F_EVENTS needs events_dev and event_stride > 0");
+        const uint64_t need = (L.total + a->event_stride - 1) / a->event_stride;
+        if (need > a->event_capacity)
+            return fail(c, PHX_ERR_CAPACITY, "events need %llu slots, capacity %llu",
+                        (unsigned long long)need, (unsigned long long)a->event_capacity);
+    }
+    return PHX_OK;
+}
+
+// Blocks of 2^shift photons for the source guide: about four per source.
+uint32_t guide_shift_of(uint64_t total, int n_src) {
+    uint32_t shift = 0;
+    while (shift < 40 && (total >> (shift + 1)) >= 4 * (uint64_t)n_src) ++shift;
+    return shift;
+}
+
+// Chunk plan.  With the atmosphere every chunk has its survivors sorted by time (screen
+// locality; a chunk of many sources keeps their order within a time bucket); traces of big
+// sources are cut at source boundaries, traces of many small sources and adjoints evenly (the
+// adjoint's optics kernel is the heavy stage and wants few, full chunks).  Returns the number of
+// chunks; fills c->plan only if that is at most max_chunks.
+uint64_t make_plan(phx_ctx c, const phx_trace_args* a, const phx::Launch& L, uint64_t chunk,
+                   bool need_image, uint64_t max_chunks) {
+    const bool atm = (a->flags & PHX_F_ATMOSPHERE) != 0;
+    const bool per_source = need_image && atm && L.n_src > 1 &&
+                            L.total / (uint64_t)L.n_src >= chunk / 8;
+    uint64_t n = 0;
+    if (per_source) {
+        for (int s = 0; s < L.n_src; ++s) {
+            const uint64_t n_s = L.uniform_count ? L.uniform_count
+                                                 : c->src[a->src_begin + s].n_photons;
+            n += (n_s + chunk - 1) / chunk;
+        }
+    } else {
+        n = (L.total + chunk - 1) / chunk;
+    }
+    if (n > max_chunks) return n;
+    c->plan.clear();
+    if (per_source) {
+        uint64_t start = 0;
+        for (int s = 0; s < L.n_src; ++s) {
+            const uint64_t n_s = L.uniform_count ? L.uniform_count
+                                                 : c->src[a->src_begin + s].n_photons;
+            for (uint64_t o = 0; o < n_s; o += chunk)
+                c->plan.push_back({start + o, std::min(chunk, n_s - o), start, 1, s});
+            start += n_s;
+        }
+    } else {
+        for (uint64_t b = 0; b < L.total; b += chunk)
+            c->plan.push_back({b, std::min(chunk, L.total - b), 0, atm ? 1 : 0,
+                               L.n_src == 1 ? 0 : -1});
+    }
+    return n;
+}
+
+// Validation, uploads and workspace for a trace; fills the launch description.  May synchronise
+// `st` (new prefix table, growing workspace, changed parameter block).
+phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Launch& L,
+                   phx::Workspace& W, bool need_image = true) {
+    phx_status r = validate_launch(c, a, L, need_image);
+    if (r != PHX_OK) return r;
+    if (a->photon_count == 0) {
+        std::vector<uint64_t> pre(L.n_src + 1, 0);
+        for (int s = 0; s < L.n_src; ++s) pre[s + 1] = pre[s] + c->src[a->src_begin + s].n_photons;
         const bool same = c->prefix_valid && c->prefix_begin == a->src_begin &&
                           c->prefix_end == a->src_end && c->prefix_version == c->src_version;
         if (!same) {
-            // source guide: blocks of 2^shift photons, about four per source
-            uint32_t shift = 0;
-            while (shift < 40 && (L.total >> (shift + 1)) >= 4 * (uint64_t)L.n_src) ++shift;
+            const uint32_t shift = guide_shift_of(L.total, L.n_src);
             const uint64_t nb = L.total ? ((L.total - 1) >> shift) + 1 : 1;
             std::vector<int32_t> guide(nb + 1);
             int s = 0;
@@ -1170,16 +1248,6 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         L.src_guide = c->d_src_guide;
         L.guide_shift = c->guide_shift;
     }
-    if (a->photon_begin > UINT64_MAX - (L.total ? L.total : 0))
-        return fail(c, PHX_ERR_INVALID, "photon index overflows");
-    if (need_image && (a->flags & PHX_F_EVENTS)) {
-        if (!a->events_dev || a->event_stride == 0)
-            return fail(c, PHX_ERR_INVALID, "PHX_F_EVENTS needs events_dev and event_stride > 0");
-        const uint64_t need = (L.total + a->event_stride - 1) / a->event_stride;
-        if (need > a->event_capacity)
-            return fail(c, PHX_ERR_CAPACITY, "events need %llu slots, capacity %llu",
-                        (unsigned long long)need, (unsigned long long)a->event_capacity);
-    }
     // Workspace: chunk = min(2^chunk_log2, total rounded up to a power of two); grows only
     const uint64_t max_chunk = 1ull << c->chunk_log2;
     uint64_t chunk = 1024;
@@ -1209,29 +1277,7 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         c->ws_chunk = chunk;
     }
     chunk = std::min<uint64_t>(c->ws_chunk, max_chunk);
-    // Chunk plan.  With the atmosphere every chunk has its survivors sorted by time (screen
-    // locality; a chunk of many sources keeps their order within a time bucket); traces of big
-    // sources are cut at source boundaries, traces of many small sources and adjoints evenly.
-    c->plan.clear();
-    const bool atm = (a->flags & PHX_F_ATMOSPHERE) != 0;
-    // (the adjoint cuts evenly: its optics kernel is the heavy stage and wants few, full chunks)
-    const bool per_source = need_image && atm && L.n_src > 1 &&
-                            L.total / (uint64_t)L.n_src >= chunk / 8;
-    if (per_source) {
-        uint64_t start = 0;
-        for (int s = 0; s < L.n_src; ++s) {
-            const uint64_t n_s = L.uniform_count ? L.uniform_count
-                                                 : c->src[a->src_begin + s].n_photons;
-            for (uint64_t o = 0; o < n_s; o += chunk)
-                c->plan.push_back({start + o, std::min(chunk, n_s - o), start, 1, s});
-            start += n_s;
-        }
-    } else {
-        for (uint64_t b = 0; b < L.total; b += chunk)
-            c->plan.push_back({b, std::min(chunk, L.total - b), 0, atm ? 1 : 0,
-                               L.n_src == 1 ? 0 : -1});
-    }
-    const uint64_t n_chunks = c->plan.size();
+    const uint64_t n_chunks = make_plan(c, a, L, chunk, need_image, UINT64_MAX);
     if (n_chunks > c->counts_cap) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
@@ -1317,6 +1363,61 @@ phx_status phx_trace(phx_ctx c, const phx_trace_args* a, void* stream) {
     phx_status r = prepare(c, a, st, L, W);
     if (r != PHX_OK) return r;
     return enqueue(c, L, W, st, true);
+}
+
+phx_status phx_trace_noalloc(phx_ctx c, const phx_trace_args* a, void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    phx::Launch L;
+    phx_status r = validate_launch(c, a, L, true);
+    if (r != PHX_OK) return r;
+    if (a->flags & PHX_F_GHOSTS)
+        return fail(c, PHX_ERR_INVALID,
+                    "phx_trace_noalloc does not trace ghosts (their queues need context memory)");
+    if (L.n_src > phx::kNoAllocMaxSources)
+        return fail(c, PHX_ERR_CAPACITY, "phx_trace_noalloc traces at most %d sources, not %d",
+                    phx::kNoAllocMaxSources, L.n_src);
+    if (!c->scratch) return fail(c, PHX_ERR_STATE, "no scratch address for this device");
+    if (L.total == 0) return upload_params(c, st);
+    uint64_t chunk = 1024;
+    const uint64_t max_chunk = 1ull << std::min(c->chunk_log2, phx::kNoAllocChunkLog2);
+    while (chunk < L.total && chunk < max_chunk) chunk <<= 1;
+    const uint64_t n_chunks = make_plan(c, a, L, chunk, true, phx::kNoAllocMaxChunks);
+    if (n_chunks > phx::kNoAllocMaxChunks)
+        return fail(c, PHX_ERR_CAPACITY,
+                    "phx_trace_noalloc handles at most %llu chunks of %llu photons, not %llu",
+                    (unsigned long long)phx::kNoAllocMaxChunks, (unsigned long long)chunk,
+                    (unsigned long long)n_chunks);
+    constexpr phx::ScratchLayout S = phx::scratch_layout();
+    unsigned char* base = (unsigned char*)c->scratch;
+    if (a->photon_count == 0 && L.n_src > 1) {
+        // prefix table and source guide of this launch, built on the device in the scratch
+        const uint32_t shift = guide_shift_of(L.total, L.n_src);
+        const uint64_t nb = ((L.total - 1) >> shift) + 1;
+        if (nb + 1 > phx::kNoAllocGuideMax)
+            return fail(c, PHX_ERR_CAPACITY, "source guide of %llu blocks",
+                        (unsigned long long)nb);
+        L.prefix = (const uint64_t*)(base + S.prefix);
+        L.src_guide = (const int32_t*)(base + S.guide);
+        L.guide_shift = shift;
+        const hipError_t e = phx::launch_prefix(c->d_src, a->src_begin, L.n_src,
+                                                (uint64_t*)(base + S.prefix),
+                                                (int32_t*)(base + S.guide), nb, shift, st);
+        if (e != hipSuccess) return hip_fail(c, e, "prefix kernels");
+    }
+    const phx::Workspace W{(uint32_t*)(base + S.survivors), (unsigned int*)(base + S.counts),
+                           phx::kNoAllocMaxChunks, (double*)(base + S.state), chunk,
+                           (unsigned long long*)(base + S.tiles),
+                           (unsigned long long*)(base + S.bits), (unsigned int*)(base + S.bsum),
+                           (uint8_t*)(base + S.key), (unsigned int*)(base + S.hist),
+                           c->plan.data(), (uint64_t)c->plan.size(), 1};
+    r = upload_params(c, st);
+    if (r != PHX_OK) return r;
+    // every stage on the caller's stream, one buffer set, no timing events
+    const hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, c->cfg, st, phx::Pipe{},
+                                           phx::Timing{});
+    if (e != hipSuccess) return hip_fail(c, e, "trace kernel launch");
+    return PHX_OK;
 }
 
 phx_status phx_trace_batched(phx_ctx c, const phx_trace_args* a, void* stream) {

@@ -167,6 +167,47 @@ struct Workspace {
     double* ghost_q = nullptr; // [ghost_waves][kGhostFields][kGhostQ] queues of the optics
     uint64_t ghost_waves = 0;  // kernel with ghosts, one per wavefront of its grid
 };
+// Workspace of phx_trace_noalloc: a file-scope device array of kScratchBytes on each GPU (its
+// address is looked up once per device when a context is created), carved into the buffers of
+// one chunk of at most 2^kNoAllocChunkLog2 photons (one buffer set: no pipeline), the per-chunk
+// counters of at most kNoAllocMaxChunks chunks, and the prefix table and source guide of at
+// most kNoAllocMaxSources sources (built on the device).  Offsets in bytes, each 256-aligned.
+constexpr int kNoAllocChunkLog2 = 19;
+constexpr uint64_t kNoAllocMaxChunks = 16384;
+constexpr int kNoAllocMaxSources = 65536;
+constexpr uint64_t kNoAllocGuideMax = 8ull * kNoAllocMaxSources + 2;   // guide blocks + 1
+constexpr uint64_t kScratchBytes = 40ull << 20;
+struct ScratchLayout {
+    uint64_t survivors, state, bits, bsum, key, hist, counts, tiles, prefix, guide, end;
+};
+constexpr uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+constexpr ScratchLayout scratch_layout() {
+    const uint64_t chunk = 1ull << kNoAllocChunkLog2;
+    const uint64_t groups = ((chunk + 63) / 64 + 4095) / 4096;
+    ScratchLayout s{};
+    s.survivors = 0;
+    s.state = align256(s.survivors + chunk * 4);
+    s.bits = align256(s.state + 7 * chunk * 8);
+    s.bsum = align256(s.bits + (chunk + 63) / 64 * 8);
+    s.key = align256(s.bsum + groups * 4);
+    s.hist = align256(s.key + chunk);
+    s.counts = align256(s.hist + 2 * groups * 64 * 4);
+    s.tiles = align256(s.counts + kNoAllocMaxChunks * 4);
+    s.prefix = align256(s.tiles + 2 * kNoAllocMaxChunks * 8);
+    s.guide = align256(s.prefix + (kNoAllocMaxSources + 1) * 8);
+    s.end = align256(s.guide + kNoAllocGuideMax * 4);
+    return s;
+}
+static_assert(scratch_layout().end <= kScratchBytes, "no-allocation workspace exceeds the scratch");
+// Device address of this GPU's scratch array (the calling thread's current device must be
+// `device`); looked up once per device and cached.
+hipError_t scratch_address(int device, void** out);
+// Exclusive prefix of the photon counts of sources [src_begin, src_begin + n_src) into
+// prefix[0 .. n_src] and the photon-block guide (Launch::src_guide) guide[0 .. n_blocks] for
+// blocks of 2^shift photons, computed on the device from the source table.
+hipError_t launch_prefix(const DevSource* src, int src_begin, int n_src, uint64_t* prefix,
+                         int32_t* guide, uint64_t n_blocks, uint32_t shift, hipStream_t stream);
+
 // Ghost starts queued per wavefront of the optics kernel with ghosts (drained once more than
 // kGhostQ - 64 wait; a pass adds up to 64), and the 8-byte fields of one entry.
 constexpr int kGhostQ = 512;

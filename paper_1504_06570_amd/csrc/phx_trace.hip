@@ -15,6 +15,8 @@
 // Stream 1, block t: trial t of the Gamma sampler used by Sersic sources.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "phx_internal.h"
 #include "phx_rng.h"
 
@@ -2740,6 +2742,88 @@ hipError_t launch_adjoint(const DevParams* dparams, const Launch& L, const Works
     hipLaunchKernelGGL(adjoint_columns, dim3(kAdj), dim3(256), 0, stream, A.partial, rows, colsum);
     hipLaunchKernelGGL(adjoint_finish, dim3(1), dim3(64), 0, stream, dparams,
                        (const double*)colsum, grad);
+    return hipGetLastError();
+}
+
+// Workspace of the entry point without allocation (phx_trace_noalloc), one per GPU for the life
+// of the process.  Host code never passes this name to a kernel: it is a host-side stand-in for
+// the symbol, and scratch_address gives the device address to use instead.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** out) {
+    static std::mutex mu;
+    static void* addr[64] = {};
+    if (!out || device < 0 || device >= 64) return hipErrorInvalidValue;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+namespace {
+// Exclusive prefix of the sources' photon counts: each of 256 lanes sums a contiguous slice, a
+// workgroup scan of the slice sums gives each slice its start, and the lane writes its slice.
+__global__ __launch_bounds__(256) void prefix_kernel(const DevSource* __restrict__ src,
+                                                     int src_begin, int n_src,
+                                                     uint64_t* __restrict__ prefix) {
+    __shared__ uint64_t s_sum[256];
+    const int t = threadIdx.x;
+    const int per = (n_src + 255) / 256;
+    const int a = min(n_src, t * per), b = min(n_src, a + per);
+    uint64_t sum = 0;
+    for (int i = a; i < b; ++i) sum += src[src_begin + i].n_photons;
+    s_sum[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint64_t v = t >= o ? s_sum[t - o] : 0;
+        __syncthreads();
+        s_sum[t] += v;
+        __syncthreads();
+    }
+    uint64_t run = t ? s_sum[t - 1] : 0;
+    for (int i = a; i < b; ++i) {
+        prefix[i] = run;
+        run += src[src_begin + i].n_photons;
+    }
+    if (t == 255) prefix[n_src] = s_sum[255];
+}
+
+// guide[b] = the source holding flattened photon b << shift: the number of j in [1, n_src) with
+// prefix[j] <= b << shift (the prefix does not decrease); guide[n_blocks] = n_src - 1.
+__global__ __launch_bounds__(256) void guide_kernel(const uint64_t* __restrict__ prefix,
+                                                    int n_src, int32_t* __restrict__ guide,
+                                                    uint64_t n_blocks, uint32_t shift) {
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > n_blocks) return;
+    if (b == n_blocks) {
+        guide[b] = n_src - 1;
+        return;
+    }
+    const uint64_t g = b << shift;
+    int lo = 1, hi = n_src;   // first j in [1, n_src) with prefix[j] > g, else n_src
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid + 1; else hi = mid;
+    }
+    guide[b] = lo - 1;
+}
+}  // namespace
+
+hipError_t launch_prefix(const DevSource* src, int src_begin, int n_src, uint64_t* prefix,
+                         int32_t* guide, uint64_t n_blocks, uint32_t shift, hipStream_t stream) {
+    if (!src || !prefix || !guide || n_src < 1 || src_begin < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(prefix_kernel, dim3(1), dim3(256), 0, stream, src, src_begin, n_src, prefix);
+    hipLaunchKernelGGL(guide_kernel, dim3((unsigned)((n_blocks + 1 + 255) / 256)), dim3(256), 0,
+                       stream, (const uint64_t*)prefix, n_src, guide, n_blocks, shift);
     return hipGetLastError();
 }
 

@@ -198,6 +198,7 @@ def lib():
         L.phx_set_launch_config.argtypes = [C.c_void_p, C.POINTER(LaunchConfig)]
         L.phx_get_launch_config.argtypes = [C.c_void_p, C.POINTER(LaunchConfig)]
         L.phx_trace_batched.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
+        L.phx_trace_noalloc.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
         L.phx_autotune.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p,
                                    C.POINTER(LaunchConfig)]
         L.phx_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p, C.c_void_p,
@@ -206,7 +207,8 @@ def lib():
                   "phx_load_coatings", "phx_load_screens", "phx_load_sources", "phx_trace",
                   "phx_set_timing", "phx_get_timing", "phx_set_launch_config",
                   "phx_get_launch_config", "phx_trace_batched", "phx_autotune", "phx_adjoint",
-                  "phx_load_physics", "phx_readout", "phx_load_reflectance"):
+                  "phx_load_physics", "phx_readout", "phx_load_reflectance",
+                  "phx_trace_noalloc"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -385,13 +387,15 @@ class Tracer:
 
     def trace(self, image=None, *, flags=None, seed=None, src_begin=0, src_end=None,
               photon_begin=0, photon_count=0, stats=None, moments=None, event_stride=0,
-              events=None, stream=None, exposure=None, batched=False):
+              events=None, stream=None, exposure=None, batched=False, noalloc=False):
         """Enqueue one trace of sources [src_begin, src_end).  `batched` replays a captured graph
-        of the whole launch (phx_trace_batched).  Returns (image, stats, moments, events)
-        tensors (events as raw bytes)."""
+        of the whole launch (phx_trace_batched); `noalloc` calls phx_trace_noalloc (the workspace
+        in the library's static device array).  Returns (image, stats, moments, events) tensors
+        (events as raw bytes)."""
         a, image, events = self._args(image, flags, seed, src_begin, src_end, photon_begin,
                                       photon_count, stats, moments, event_stride, events, exposure)
-        fn = self.L.phx_trace_batched if batched else self.L.phx_trace
+        fn = (self.L.phx_trace_batched if batched else
+              self.L.phx_trace_noalloc if noalloc else self.L.phx_trace)
         self._check(fn(self.ctx, C.byref(a), _stream_handle(stream)))
         return image, stats, moments, events
 
