@@ -187,10 +187,8 @@ def gradient_leg(steps):
     m = tr.new_moments()
     tr.trace(img, flags=flags, moments=m)
     torch.cuda.synchronize()
-    mom = phx.moments(m)
-    gout = np.random.default_rng(6).standard_normal((len(mom), 5))
-    seeds = torch.from_numpy(phx.adjoint_seeds(mom, gout)).cuda()
-    grad = tr.adjoint(seeds, flags=flags)
+    dmom = torch.from_numpy(np.random.default_rng(6).standard_normal((len(scene.sources), 5)))
+    grad = tr.adjoint_moments(m, dmom, flags=flags)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -203,7 +201,7 @@ def gradient_leg(steps):
     tr.set_timing(True)
     e0.record(stream)
     for _ in range(steps):
-        tr.adjoint(seeds, flags=flags, grad=grad)
+        tr.adjoint_moments(m, dmom, flags=flags, grad=grad)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_a = e0.elapsed_time(e1) / steps

@@ -319,7 +319,9 @@ phx_status phx_load_reflectance(phx_ctx ctx, const float* tables_host, int32_t n
 
 /* Load turbulence screens (sections 2.3.1-2.3.2).  opd_dev: float32 [L][S][N][N] optical path
  * (m), row j along y, column i along x, periodic; read only by work enqueued on `stream` during
- * this call.  The context derives and owns the gradient screens (centred differences).
+ * this call.  The context derives and owns the gradient screens (centred differences).  A screen
+ * holding a NaN or infinite value is refused with PHX_ERR_INVALID, and the context then has no
+ * usable screens (PHX_F_ATMOSPHERE fails with PHX_ERR_STATE until a good load).
  * Errors: PHX_ERR_INVALID, PHX_ERR_NOMEM, PHX_ERR_HIP. */
 phx_status phx_load_screens(phx_ctx ctx, const phx_atmosphere* atm_host, const float* opd_dev,
                             int64_t n_floats, void* stream);
@@ -472,6 +474,38 @@ phx_status phx_autotune(phx_ctx ctx, const phx_trace_args* sample, void* stream,
 phx_status phx_adjoint(phx_ctx ctx, const phx_trace_args* args, const double* seed_dev,
                        double* grad_dev, double* jac_dev, uint64_t jac_stride,
                        uint64_t jac_capacity, void* stream);
+
+/* Per-source moments of the converted photons (paper section 3.1 outputs: per-source counts and
+ * centroids; the moments of section 4 read as unweighted moments of the electron positions):
+ * from the moment words of a trace with PHX_F_MOMENTS, moments_dev [n_src][PHX_MOMENT_WORDS]
+ * (device), writes out_dev [n_src][6] (device doubles) = (n, mean x, mean y, Ixx, Iyy, Ixy),
+ * mean x = SX / n, Ixx = (n SXX - SX^2) / n^2, Ixy = (n SXY - SX SY) / n^2 over the quantised
+ * sums, each evaluated in exact integer arithmetic and rounded once to the nearest double (ties
+ * to even); a source with n = 0 gets a zero row.  Enqueued on `stream`.  Errors:
+ * PHX_ERR_INVALID (null buffer with n_src > 0, n_src < 0), PHX_ERR_HIP. */
+phx_status phx_moments(phx_ctx ctx, const uint64_t* moments_dev, int32_t n_src, double* out_dev,
+                       void* stream);
+
+/* Adjoint of a loss of the per-source moments (the gradient of section 2.4.1's perturbation
+ * parameters, as phx_adjoint): moments_dev is the forward trace's moment-word buffer
+ * [n_sources][PHX_MOMENT_WORDS] (device; the rows of sources [src_begin, src_end) are read) and
+ * dmom_dev [src_end - src_begin][5] (device doubles) the loss gradient with respect to
+ * (mean x, mean y, Ixx, Iyy, Ixy) of each source.  The library forms the cotangent coefficients
+ * of phx_adjoint on the device -- g = (dL/dmx, dL/dmy, 2 dL/dIxx, 2 dL/dIyy, dL/dIxy) / n and the
+ * means from the words (zero for a source without converted photons) -- into a context-owned
+ * buffer (grown on first use: that call may synchronise `stream`) and runs phx_adjoint with
+ * them.  Other arguments, results and errors as phx_adjoint. */
+phx_status phx_adjoint_moments(phx_ctx ctx, const phx_trace_args* args,
+                               const uint64_t* moments_dev, const double* dmom_dev,
+                               double* grad_dev, double* jac_dev, uint64_t jac_stride,
+                               uint64_t jac_capacity, void* stream);
+
+/* Copy a trace image (section 2.4.3 pixel counts) to host memory: image_dev [ny][nx] uint32
+ * (device) into image_host (host, n = nx ny of the loaded prescription elements), enqueued on
+ * `stream`, which is then synchronised.  Errors: PHX_ERR_STATE (no prescription),
+ * PHX_ERR_INVALID (null pointer, n not nx ny), PHX_ERR_HIP. */
+phx_status phx_read_image(phx_ctx ctx, const uint32_t* image_dev, uint32_t* image_host, int64_t n,
+                          void* stream);
 
 /* Kernel timing for profiling.  While on, phx_trace brackets each kernel it launches with HIP
  * events on the trace stream; phx_get_timing waits for them and returns the accumulated

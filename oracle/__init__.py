@@ -110,6 +110,8 @@ def lib():
             L.orc_release.argtypes = [C.POINTER(Scene)]
             L.orc_trace.argtypes = [C.POINTER(Scene), C.c_int32, C.c_uint64, C.c_uint64,
                                     C.c_void_p, C.c_void_p]
+            L.orc_trace_list.argtypes = [C.POINTER(Scene), C.c_int32, C.c_void_p, C.c_uint64,
+                                         C.c_void_p, C.c_void_p]
             L.orc_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                      C.POINTER(C.c_uint32)]
             L.orc_u01.argtypes = [C.c_uint32]
@@ -289,6 +291,31 @@ class Oracle:
                              ev.ctypes.data if ev is not None else None)
         if rc != 0:
             raise ValueError("oracle trace failed")
+        return ev
+
+    def trace_list(self, src: int, photons, threads: int = 1):
+        """Events of the given photon indices of one source (a sample of a launch), in order;
+        split over `threads` Python threads (the C call releases the GIL)."""
+        ph = np.ascontiguousarray(photons, np.uint64)
+        ev = np.zeros(len(ph), EVENT_DTYPE)
+        parts = np.array_split(np.arange(len(ph)), max(1, threads))
+
+        def run(idx):
+            if len(idx) == 0:
+                return
+            a, b = int(idx[0]), int(idx[-1]) + 1
+            rc = lib().orc_trace_list(C.byref(self.sc), int(src), ph[a:b].ctypes.data, b - a,
+                                      None, ev[a:b].ctypes.data)
+            if rc != 0:
+                raise ValueError("oracle trace failed")
+        if threads <= 1:
+            run(parts[0])
+        else:
+            ths = [threading.Thread(target=run, args=(p,)) for p in parts]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
         return ev
 
     def trace_sources(self, counts=None, begin=0, image=None, events=True, threads=1):

@@ -1200,6 +1200,15 @@ int orc_trace(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count, 
     return 0;
 }
 
+/* The photons photon[0 .. count) of source src, one by one (a sample of a launch). */
+int orc_trace_list(const orc_scene* sc, int32_t src, const uint64_t* photon, uint64_t count,
+                   uint32_t* image, orc_event* events) {
+    if (src < 0 || src >= sc->n_src || (count && !photon)) return -1;
+    orc_event tmp;
+    for (uint64_t i = 0; i < count; ++i) trace_one(sc, src, photon[i], image, events ? &events[i] : &tmp);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Derivative of each photon's electron position (xe, ye) with respect to the 22 perturbation
  * parameters.  The paper has no derivative; this is the plain limit definition of one: central

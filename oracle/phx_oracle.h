@@ -125,6 +125,10 @@ void orc_release(orc_scene* sc);
 /* Trace photons [begin, begin+count) of source `src`; events may be NULL; image may be NULL. */
 int  orc_trace(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count,
                uint32_t* image, orc_event* events);
+/* Photons photon[0 .. count) of source src (any indices, in the given order); events[i] for
+ * photon[i].  Returns 0, or -1 for a bad source or a null list. */
+int  orc_trace_list(const orc_scene* sc, int32_t src, const uint64_t* photon, uint64_t count,
+                    uint32_t* image, orc_event* events);
 /* d(xe, ye)/d(theta) of photons [begin, begin+count) by Richardson-extrapolated central
  * differences with frozen decisions; jac [count][2][22], frozen [count]. */
 int  orc_jacobian(const orc_scene* sc, int32_t src, uint64_t begin, uint64_t count,

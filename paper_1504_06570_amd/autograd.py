@@ -9,8 +9,6 @@ decisions held fixed (a fixed-seed estimator).  Both passes run in the library's
 """
 from __future__ import annotations
 
-from . import phx as P
-
 
 def _function():
     import torch
@@ -26,18 +24,17 @@ def _function():
             words = tracer.new_moments()
             image = tracer.new_image()
             tracer.trace(image, moments=words, **kw)
-            mom = P.moments(words)[src_begin:src_end]
-            ctx.tracer, ctx.kw, ctx.mom, ctx.theta = tracer, dict(kw), mom, th
+            mom = tracer.moments(words)[src_begin:src_end, 1:]
+            ctx.tracer, ctx.kw, ctx.words, ctx.theta = tracer, dict(kw), words, th
             ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
-            return torch.from_numpy(mom[:, 1:].copy()).to(theta.device)
+            return mom.to(theta.device)
 
         @staticmethod
         def backward(ctx, gout):
             tr = ctx.tracer
             tr.set_perturbation(ctx.theta)
-            seeds = P.adjoint_seeds(ctx.mom, gout.detach().to("cpu", torch.float64).numpy())
             kw = {k: v for k, v in ctx.kw.items() if k not in ("stats", "event_stride", "events")}
-            grad = tr.adjoint(torch.from_numpy(seeds), **kw)
+            grad = tr.adjoint_moments(ctx.words, gout.detach(), **kw)
             return grad.to(ctx.theta_device, ctx.theta_dtype), None, None
 
     return _PsfMoments

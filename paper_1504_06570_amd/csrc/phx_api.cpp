@@ -87,6 +87,8 @@ struct phx_ctx_s {
     double* d_partial = nullptr;
     uint64_t rows_cap = 0;
     double* d_colsum = nullptr;
+    double* d_seed = nullptr;            // cotangent coefficients of phx_adjoint_moments
+    uint64_t seed_cap = 0;
     uint64_t* d_bits = nullptr;
     unsigned int* d_bsum = nullptr;
     uint8_t* d_key = nullptr;
@@ -458,6 +460,7 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_tape);
     free_dev(c->d_partial);
     free_dev(c->d_colsum);
+    free_dev(c->d_seed);
     free_dev(c->d_bits);
     free_dev(c->d_bsum);
     free_dev(c->d_key);
@@ -869,7 +872,15 @@ phx_status phx_load_screens(phx_ctx c, const phx_atmosphere* a, const float* opd
     for (int i = 0; i < planes; ++i) {
         float f;
         std::memcpy(&f, &gm[i], sizeof(f));
-        c->grad_max[i] = std::isfinite(f) ? (double)f : INFINITY;
+        if (!std::isfinite(f)) {
+            // the gradient screens now hold this load's values: no screens are usable
+            c->have_screens = false;
+            c->grad_max.clear();
+            return fail(c, PHX_ERR_INVALID,
+                        "screen plane %d (layer %d, scale %d) holds a NaN or infinite value", i,
+                        i / a->n_scales, i % a->n_scales);
+        }
+        c->grad_max[i] = (double)f;
     }
     DevParams& H = c->host;
     H.n_layers = a->n_layers;
@@ -1539,6 +1550,65 @@ phx_status phx_adjoint(phx_ctx c, const phx_trace_args* a, const double* seed_de
     hipError_t e = phx::launch_adjoint(c->dparams, L, W, c->n_cu, c->cfg, A, c->d_colsum, grad_dev,
                                        st, pipe_of(c), T);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint kernel launch");
+    return PHX_OK;
+}
+
+phx_status phx_adjoint_moments(phx_ctx c, const phx_trace_args* a, const uint64_t* moments_dev,
+                               const double* dmom_dev, double* grad_dev, double* jac_dev,
+                               uint64_t jac_stride, uint64_t jac_capacity, void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!a) return fail(c, PHX_ERR_INVALID, "null trace arguments");
+    if (!moments_dev || !dmom_dev)
+        return fail(c, PHX_ERR_INVALID, "null moment words or moment gradient");
+    const int n_src_all = (int)c->src.size();
+    if (a->src_begin < 0 || a->src_end > n_src_all || a->src_begin >= a->src_end)
+        return fail(c, PHX_ERR_INVALID, "source range [%d, %d) outside [0, %d)", a->src_begin,
+                    a->src_end, n_src_all);
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t n = (uint64_t)(a->src_end - a->src_begin);
+    if (n > c->seed_cap) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        free_dev(c->d_seed);
+        c->seed_cap = 0;
+        e = hipMalloc((void**)&c->d_seed, n * 8 * sizeof(double));
+        if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "adjoint seeds");
+        c->seed_cap = n;
+    }
+    hipError_t e = phx::launch_seeds((const unsigned long long*)moments_dev +
+                                         (size_t)a->src_begin * PHX_MOMENT_WORDS,
+                                     (int)n, dmom_dev, c->d_seed, st);
+    if (e != hipSuccess) return hip_fail(c, e, "seed kernel launch");
+    return phx_adjoint(c, a, c->d_seed, grad_dev, jac_dev, jac_stride, jac_capacity, stream);
+}
+
+phx_status phx_moments(phx_ctx c, const uint64_t* moments_dev, int32_t n_src, double* out_dev,
+                       void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    if (n_src < 0 || (n_src > 0 && (!moments_dev || !out_dev)))
+        return fail(c, PHX_ERR_INVALID, "null buffer or negative source count");
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    const hipError_t e = phx::launch_moments((const unsigned long long*)moments_dev, n_src,
+                                             out_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "moments kernel launch");
+    return PHX_OK;
+}
+
+phx_status phx_read_image(phx_ctx c, const uint32_t* image_dev, uint32_t* image_host, int64_t n,
+                          void* stream) {
+    if (!c) return PHX_ERR_INVALID;
+    if (!c->have_presc) return fail(c, PHX_ERR_STATE, "load a prescription first");
+    const int64_t npix = (int64_t)c->presc.nx * c->presc.ny;
+    if (!image_dev || !image_host || n != npix)
+        return fail(c, PHX_ERR_INVALID, "null image or n = %lld, not nx ny = %lld", (long long)n,
+                    (long long)npix);
+    if (set_device(c) != PHX_OK) return PHX_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(image_host, image_dev, (size_t)n * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(c, e, "image copy");
     return PHX_OK;
 }
 

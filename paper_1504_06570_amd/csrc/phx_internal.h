@@ -286,6 +286,15 @@ struct ReadoutJob {
 };
 hipError_t launch_readout(const ReadoutJob& J, hipStream_t stream);
 
+// Per-source (n, mean x, mean y, Ixx, Iyy, Ixy) from moment words [n_src][PHX_MOMENT_WORDS]
+// into out [n_src][6], each rounded once from exact integer arithmetic (phx_moments).
+hipError_t launch_moments(const unsigned long long* words, int n_src, double* out,
+                          hipStream_t stream);
+// The adjoint's cotangent coefficients [n_src][8] from the moment words and a loss gradient
+// dmom [n_src][5] with respect to (mean x, mean y, Ixx, Iyy, Ixy).
+hipError_t launch_seeds(const unsigned long long* words, int n_src, const double* dmom,
+                        double* seed, hipStream_t stream);
+
 hipError_t launch_gradients(const float* opd, float4* grad, int n_layers, int n_scales, int n,
                             const double* pixel, unsigned int* gmax, hipStream_t stream);
 

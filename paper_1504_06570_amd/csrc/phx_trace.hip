@@ -2503,7 +2503,10 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
         grad[2 * id + 1] = make_float4(g01.x, g01.y, g11.x, g11.y);
     }
     if (!gmax) return;
-    float m = live ? sqrtf(g00.x * g00.x + g00.y * g00.y) : 0.0f;
+    // a non-finite gradient (from a NaN or infinite optical path) records an infinite maximum
+    // (fmaxf would drop a NaN), which the host refuses
+    const bool finite = isfinite(g00.x) && isfinite(g00.y);
+    float m = live ? (finite ? sqrtf(g00.x * g00.x + g00.y * g00.y) : INFINITY) : 0.0f;
     const int p0 = __shfl((int)plane, 0);
     if (__ballot((int)plane != p0) == 0) {   // the whole wavefront is on one screen
 #pragma unroll

@@ -199,6 +199,11 @@ def lib():
         L.phx_get_launch_config.argtypes = [C.c_void_p, C.POINTER(LaunchConfig)]
         L.phx_trace_batched.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
         L.phx_trace_noalloc.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p]
+        L.phx_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.phx_adjoint_moments.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                          C.c_uint64, C.c_void_p]
+        L.phx_read_image.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.phx_autotune.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p,
                                    C.POINTER(LaunchConfig)]
         L.phx_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p, C.c_void_p,
@@ -208,7 +213,8 @@ def lib():
                   "phx_set_timing", "phx_get_timing", "phx_set_launch_config",
                   "phx_get_launch_config", "phx_trace_batched", "phx_autotune", "phx_adjoint",
                   "phx_load_physics", "phx_readout", "phx_load_reflectance",
-                  "phx_trace_noalloc"):
+                  "phx_trace_noalloc", "phx_moments", "phx_adjoint_moments",
+                  "phx_read_image"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -403,7 +409,8 @@ class Tracer:
                 photon_count=0, jac_stride=0, grad=None, stream=None):
         """Gradient of sum_i (xbar_i x_i + ybar_i y_i) over converted photons with respect to the
         22 perturbation parameters (phx_adjoint).  seeds: float64 device tensor [n, 8] for the
-        sources [src_begin, src_end) (see adjoint_seeds).  With jac_stride > 0 also returns the
+        sources [src_begin, src_end) (the coefficients of phx_adjoint; adjoint_moments forms them
+        from the moment words).  With jac_stride > 0 also returns the
         per-photon Jacobians [slots, 2, 22] of every jac_stride-th photon of the launch."""
         import torch
         src_end = self.n_sources if src_end is None else src_end
@@ -427,6 +434,56 @@ class Tracer:
         self._check(self.L.phx_adjoint(self.ctx, C.byref(a), seeds.data_ptr(), grad.data_ptr(), jp,
                                        int(jac_stride), int(cap), _stream_handle(stream)))
         return (grad, jac) if jac_stride else grad
+
+    def adjoint_moments(self, words, dmom, *, flags=None, seed=None, src_begin=0, src_end=None,
+                        photon_begin=0, photon_count=0, jac_stride=0, grad=None, stream=None):
+        """Gradient of a loss of the per-source moments with respect to the 22 perturbation
+        parameters (phx_adjoint_moments): words are the forward trace's moment words (device
+        tensor [n_sources, MOMENT_WORDS]), dmom the loss gradient [src_end - src_begin, 5] with
+        respect to (mean x, mean y, Ixx, Iyy, Ixy).  Returns grad (and the per-photon Jacobians
+        with jac_stride > 0, as adjoint)."""
+        import torch
+        src_end = self.n_sources if src_end is None else src_end
+        dmom = dmom.to(device=self.device, dtype=torch.float64).contiguous()
+        if dmom.shape != (src_end - src_begin, 5):
+            raise PhxError(f"dmom must be [{src_end - src_begin}, 5], got {tuple(dmom.shape)}")
+        if words.shape != (self.n_sources, MOMENT_WORDS) or not words.is_contiguous():
+            raise PhxError("words must be the contiguous [n_sources, MOMENT_WORDS] trace buffer")
+        a, _, _ = self._args(None, flags, seed, src_begin, src_end, photon_begin, photon_count,
+                             None, None, 0, None, None, adjoint_only=True)
+        if grad is None:
+            grad = torch.zeros(N_THETA, dtype=torch.float64, device=self.device)
+        jac, jp, cap = None, None, 0
+        if jac_stride:
+            total = (photon_count * (src_end - src_begin) if photon_count else
+                     int(self.scene.sources.n_photons[src_begin:src_end].sum()))
+            cap = (total + jac_stride - 1) // jac_stride
+            jac = torch.zeros((cap, 2, N_THETA), dtype=torch.float64, device=self.device)
+            jp = jac.data_ptr()
+        self._check(self.L.phx_adjoint_moments(self.ctx, C.byref(a), words.data_ptr(),
+                                               dmom.data_ptr(), grad.data_ptr(), jp,
+                                               int(jac_stride), int(cap), _stream_handle(stream)))
+        return (grad, jac) if jac_stride else grad
+
+    def moments(self, words, stream=None):
+        """Per-source (n, mean x, mean y, Ixx, Iyy, Ixy) of moment words (device tensor
+        [n, MOMENT_WORDS]) as a device float64 tensor [n, 6] (phx_moments)."""
+        import torch
+        assert words.is_contiguous() and words.shape[-1] == MOMENT_WORDS
+        n = words.shape[0]
+        out = torch.empty((n, 6), dtype=torch.float64, device=self.device)
+        self._check(self.L.phx_moments(self.ctx, words.data_ptr(), n, out.data_ptr(),
+                                       _stream_handle(stream)))
+        return out
+
+    def read_image(self, image, stream=None) -> np.ndarray:
+        """Host copy of a trace image (phx_read_image) as uint32 [ny, nx]."""
+        p = self.scene.prescription
+        out = np.empty((p.chip.ny, p.chip.nx), np.uint32)
+        assert image.is_contiguous()
+        self._check(self.L.phx_read_image(self.ctx, image.data_ptr(), out.ctypes.data, out.size,
+                                          _stream_handle(stream)))
+        return out
 
     def launch_config(self) -> dict:
         cfg = LaunchConfig()
@@ -509,58 +566,6 @@ def moment_sums(words):
             v = (int(row[3 + 2 * i]) << 64) | int(row[2 + 2 * i])
             vals.append(v - (1 << 128) if v >> 127 else v)
         out.append(tuple(vals))
-    return out
-
-
-def moments_from_sums(sums) -> np.ndarray:
-    """Per source (n, mean x, mean y, Ixx, Iyy, Ixy) in metres and square metres, the central
-    second moments (1/n) sum (x - mean)^2 etc.  Evaluated exactly in rational arithmetic from
-    the integer sums and rounded once, so no cancellation is lost; n = 0 gives a zero row."""
-    from fractions import Fraction
-    q = 1 << MOMENT_Q_LOG2
-    out = np.zeros((len(sums), 6))
-    for i, (n, sx, sy, sxx, syy, sxy) in enumerate(sums):
-        if n == 0:
-            continue
-        out[i] = (n, float(Fraction(sx, n * q)), float(Fraction(sy, n * q)),
-                  float(Fraction(n * sxx - sx * sx, n * n * q * q)),
-                  float(Fraction(n * syy - sy * sy, n * n * q * q)),
-                  float(Fraction(n * sxy - sx * sy, n * n * q * q)))
-    return out
-
-
-def moments(words) -> np.ndarray:
-    """Moment words -> per source (n, mean x, mean y, Ixx, Iyy, Ixy)."""
-    return moments_from_sums(moment_sums(words))
-
-
-def quantised_sums(xe, ye):
-    """The exact integer sums the library accumulates, for positions given on the host."""
-    q = float(1 << MOMENT_Q_LOG2)
-    X = [int(v) for v in np.rint(np.asarray(xe, np.float64) * q)]
-    Y = [int(v) for v in np.rint(np.asarray(ye, np.float64) * q)]
-    return (len(X), sum(X), sum(Y), sum(a * a for a in X), sum(b * b for b in Y),
-            sum(a * b for a, b in zip(X, Y)))
-
-
-def adjoint_seeds(mom, gout) -> np.ndarray:
-    """Per-source cotangent coefficients for phx_adjoint from the forward moments
-    mom [n, 6] = (n, mean x, mean y, Ixx, Iyy, Ixy) and the loss gradient gout [n, 5] with
-    respect to (mean x, mean y, Ixx, Iyy, Ixy): d mean/d x_i = 1/n, d Ixx/d x_i = 2 (x_i - mean)/n,
-    d Ixy/d x_i = (y_i - mean y)/n.  Sources without converted photons get zero rows."""
-    mom = np.asarray(mom, np.float64)
-    g = np.asarray(gout, np.float64)
-    out = np.zeros((len(mom), 8))
-    n = mom[:, 0]
-    ok = n > 0
-    inv = np.where(ok, 1.0 / np.where(ok, n, 1.0), 0.0)
-    out[:, 0] = g[:, 0] * inv
-    out[:, 1] = g[:, 1] * inv
-    out[:, 2] = 2.0 * g[:, 2] * inv
-    out[:, 3] = 2.0 * g[:, 3] * inv
-    out[:, 4] = g[:, 4] * inv
-    out[:, 5] = mom[:, 1]
-    out[:, 6] = mom[:, 2]
     return out
 
 

@@ -114,3 +114,35 @@ def noll_zernike(j, u, v):
         return np.sqrt(n + 1) * R
     ang = np.cos(ma * phi) if m > 0 else np.sin(ma * phi)
     return np.sqrt(2 * (n + 1)) * R * ang
+
+
+def newton_cycle_scene(n_photons=2000):
+    """A surface on which Newton's iteration never converges, for the NONCONV outcome.  Newton on
+    G(t) = t^3 - 2t + 2 has the superattracting two-cycle t = 0 <-> 1.  A paraboloid (kappa = -1,
+    curvature c) with an r^3 term a3, met by a ray in its x-z plane of slope dz/dx = -1 through
+    (x0, 0, z0) of its frame, has f = z - S = z0 - x0 + u - (c/2) u^2 - a3 |u|^3 along the ray
+    (u = x, here u < 0); choosing f = K G((u - a)/b) with a = 2^(1/3) b puts the conic root where
+    the iteration starts (t = 0).  A flat vacuum window at z = 0 holds a tiny pupil on the axis;
+    the surface is decentred by -x0 (group 1) so the light crosses its frame at x0."""
+    import math
+    b, m, x0 = -0.1, -1.0, -1.0
+    a = 2 ** (1 / 3) * b
+    K = m * b / (3 * 2 ** (2 / 3) - 2)
+    c = 6 * K * a / b ** 3
+    a3 = K / b ** 3
+    z0 = 2 * K - K * a ** 3 / b ** 3 + 2 * K * a / b + x0 * m
+    V = -z0
+    win = Op.Surface("WIN", Op.REFRACT, 0.0, 0.0, 0.0, (0.0,) * 8, 0.0, 10.0, Op.VACUUM)
+    mir = Op.Surface("NC", Op.MIRROR, V, c, -1.0, (a3,) + (0.0,) * 7, 0.0, 10.0, Op.VACUUM, -1, 1)
+    det = Op.Surface("DET", Op.DETECTOR, 5.0, 0.0, 0.0, (0.0,) * 8, 0.0, 100.0, Op.SILICON)
+    chip = Op.Chip(0.0, 0.0, 1e-3, 100, 100)
+    p = Op.Prescription("newton_cycle", [win, mir, det], chip, pupil_r_in=0.0, pupil_r_out=1e-9,
+                        z_start=1.0, obscuration_z=0.0, obscuration_r=0.0,
+                        group_pivot=((0, 0, 0), (0.0, 0.0, V), (0, 0, 0)))
+    src = point_sources([math.sqrt(0.5)], [0.0], n_photons, 500e-9, 500e-9)
+    s = C.Scene("newton_cycle", p, src, physics=0, seed=21)
+    th = np.zeros(C.N_PERTURB)
+    th[0] = -x0
+    s.perturbation = th
+    s.meta = dict(a=a, b=b, x0=x0, z0=z0)
+    return s

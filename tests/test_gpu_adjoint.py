@@ -7,6 +7,7 @@ import pytest
 
 import oracle as O
 from paper_1504_06570_amd.scene import configs as C
+from tests import moments_ref as R
 from tests import helpers as H
 
 pytestmark = pytest.mark.gpu
@@ -158,12 +159,15 @@ def test_vjp_equals_sum_of_jacobians(phx):
     ns = len(s.sources)
     m = tr.new_moments()
     _, _, _, ev = tr.trace(moments=m, photon_count=n, event_stride=1)
-    mom = phx.moments(m)
+    mom = tr.moments(m).cpu().numpy()
     gout = np.random.default_rng(24).standard_normal((ns, 5))
-    seeds = phx.adjoint_seeds(mom, gout)
+    seeds = R.adjoint_seeds(mom, gout)
     g, jac = tr.adjoint(torch.from_numpy(seeds), photon_count=n, jac_stride=1)
     g2 = tr.adjoint(torch.from_numpy(seeds), photon_count=n)
+    # the library's own cotangent coefficients from the words and dL/d(moments)
+    g3 = tr.adjoint_moments(m, torch.from_numpy(gout), photon_count=n)
     torch.cuda.synchronize()
+    assert torch.equal(g3, g2)
     e = phx.events_to_numpy(ev)
     j = jac.cpu().numpy()
     conv = e["status"] <= phx.OFF_CHIP
@@ -199,8 +203,8 @@ def moments_on(P, e, sel, ns):
     sums = []
     for si in range(ns):
         k = sel & (e["source"] == si)
-        sums.append(P.quantised_sums(e["xe"][k], e["ye"][k]))
-    return P.moments_from_sums(sums)
+        sums.append(R.quantised_sums(e["xe"][k], e["ye"][k]))
+    return R.moments_from_sums(sums)
 
 
 def test_central_differences_on_frozen_set(phx):
@@ -276,9 +280,10 @@ def test_autograd_function_backward(phx):
     tr.set_perturbation(theta.detach().numpy())
     m = tr.new_moments()
     tr.trace(moments=m, photon_count=3000)
-    mom = phx.moments(m)
+    torch.cuda.synchronize()
+    mom = R.moments_from_sums(phx.moment_sums(m))
     assert np.array_equal(out.detach().cpu().numpy(), mom[:, 1:])
-    g = tr.adjoint(torch.from_numpy(phx.adjoint_seeds(mom, w.numpy())), photon_count=3000)
+    g = tr.adjoint(torch.from_numpy(R.adjoint_seeds(mom, w.numpy())), photon_count=3000)
     torch.cuda.synchronize()
     assert torch.equal(theta.grad, g.cpu())
     tr.close()

@@ -1,0 +1,57 @@
+"""The benchmark's own workload against the oracle: the full configuration (one star, seven
+frozen-flow layers of 2048^2 screens at 1 m / 10 cm / 1 cm, the telescope with coatings, silicon,
+diffusion, the 4096^2 chip), the default launch shape the benchmark settles on (chunks of 2^26
+photons, the two-stream pipeline, 16 / 64 / 3 workgroups per compute unit), the pre-roll on, three
+chunks of photons.  Every 1000th photon of the launch is recorded and traced by the oracle alone,
+by its index; they must agree photon by photon and pixel by pixel."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1504_06570_amd.scene import configs as C
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def phx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_06570_amd import phx as P
+    return P
+
+
+def test_headline_configuration_sampled_against_the_oracle(phx):
+    import torch
+    s = C.full()
+    tr = phx.Tracer(s)
+    cfg = tr.launch_config()
+    assert cfg["chunk_log2"] == 26 and cfg["pipeline"] == 1
+    n, stride = 3 << 26, 1000
+    flags = int(s.physics) | phx.F_CULL
+    stats = tr.new_stats()
+    img, _, _, evb = tr.trace(flags=flags, stats=stats, photon_count=n, event_stride=stride)
+    torch.cuda.synchronize()
+    g = phx.events_to_numpy(evb).copy()
+    gimg = img.cpu().numpy().view(np.uint32)
+    st = stats.cpu().numpy()
+    tr.close()
+    assert len(g) == (n + stride - 1) // stride
+    assert np.array_equal(g["photon"], np.arange(0, n, stride, dtype=np.uint64))
+    tab = phx.stats_table(st)
+    assert int(gimg.sum()) == int(tab[phx.DETECTED].sum()) > 0
+    o = O.Oracle(s).trace_list(0, g["photon"], threads=16)
+    # culled photons are ones the oracle does not convert
+    culled = g["status"] == phx.CULLED
+    assert 0.5 < culled.mean() < 0.99
+    assert not np.isin(o["status"][culled], [O.DETECTED, O.OFF_CHIP]).any()
+    rep = parity.compare(g[~culled], o[~culled])
+    print("headline sample:", {k: v for k, v in rep.items() if k != "groups"})
+    print("worst deviation per status@surface:", rep["groups"])
+    assert rep["boundary_frac"] < 1e-5
+    assert rep["detected"] > 1000
+    # every sampled detected photon is counted in its pixel of the launch's image
+    det = (g["status"] == phx.DETECTED) & ~culled
+    assert np.all(gimg[g["pix_j"][det], g["pix_i"][det]] > 0)

@@ -7,6 +7,7 @@ from paper_1504_06570_amd.scene import configs as C
 from paper_1504_06570_amd.scene import optics as Op
 from paper_1504_06570_amd.scene.sources import blackbody_table, sersic_bn
 from tests import helpers as H
+from tests import moments_ref as R
 from tests import parity
 
 pytestmark = pytest.mark.gpu
@@ -174,7 +175,7 @@ def test_moments_equal_sums_over_events(phx):
     assert conv.sum() > 1000
     for si in range(len(s.sources)):
         sel = conv & (e["source"] == si)
-        assert got[si] == phx.quantised_sums(e["xe"][sel], e["ye"][sel]), si
+        assert got[si] == R.quantised_sums(e["xe"][sel], e["ye"][sel]), si
     tr.close()
 
 
@@ -243,3 +244,36 @@ def test_photon_index_crossing_32_bits(phx):
     rep = parity.compare(g[~culled], o[~culled])
     assert rep["boundary_frac"] < 1e-5
     assert not np.isin(o["status"][culled], [phx.DETECTED, phx.OFF_CHIP]).any()
+
+
+def test_newton_cycle_is_nonconv(phx):
+    """A surface on which Newton's iteration cycles (tests/helpers.newton_cycle_scene): every
+    photon is counted as NONCONV at that surface, photon by photon equal to the oracle, with
+    nothing binned."""
+    s = H.newton_cycle_scene(20000)
+    gev, gimg, oev, oimg, st = run_both(phx, s)
+    assert np.all(gev["status"] == phx.NONCONV) and np.all(gev["surface"] == 1)
+    rep = parity.compare(gev, oev)
+    assert rep["boundary"] == 0
+    tab = phx.stats_table(st)
+    assert tab[phx.NONCONV, 2] == 20000 and tab.sum() == 20000
+    assert gimg.sum() == 0
+
+
+def test_non_finite_screens_are_refused(phx):
+    """A screen holding a NaN or an infinity is refused at load (PHX_ERR_INVALID), after which the
+    atmosphere cannot be traced (PHX_ERR_STATE) until good screens are loaded."""
+    import copy
+    s = C.full(scale=1e-6, screen_n=64)
+    tr = phx.Tracer(s)
+    for bad in (np.nan, np.inf, -np.inf):
+        atm = copy.deepcopy(s.atmosphere)
+        atm.opd = np.array(atm.opd, np.float32)
+        atm.opd[3, 2, 10, 20] = bad
+        with pytest.raises(phx.PhxError, match="NaN or infinite"):
+            tr.load_screens(atm)
+        with pytest.raises(phx.PhxError, match="without loaded screens"):
+            tr.trace()
+    tr.load_screens(s.atmosphere)
+    img, _, _, _ = tr.trace()
+    tr.close()

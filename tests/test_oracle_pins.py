@@ -604,3 +604,29 @@ def test_detected_fraction_matches_effective_area_integral():
 
 def orc_alpha(lam, temp):
     return O.lib().orc_rajkanan(lam, temp)
+
+
+def test_newton_cycle_is_counted_as_nonconv():
+    """Newton's iteration on a surface built so that it enters the superattracting two-cycle of
+    t^3 - 2t + 2 (tests/helpers.newton_cycle_scene) never converges: after the 16 steps every
+    photon is NONCONV at that surface, the event holds the ray's start point in the surface's
+    frame, and the iterates alternate between the cycle's two points (checked on the surface
+    equation directly)."""
+    import math
+    s = H.newton_cycle_scene(2000)
+    o = O.Oracle(s)
+    ev = o.trace_sources()
+    assert np.all(ev["status"] == O.NONCONV) and np.all(ev["surface"] == 1)
+    x0, z0 = s.meta["x0"], s.meta["z0"]
+    assert np.abs(ev["x"] - x0).max() < 1e-8 and np.abs(ev["z"] - z0).max() < 1e-8
+    st, _, it = o.intersect(1, [x0, 0.0, z0], [math.sqrt(0.5), 0.0, -math.sqrt(0.5)])
+    assert st == O.NONCONV and it == 16
+    # Newton on f(u) = z(u) - S(u) along the ray from the cycle's first point returns to it
+    surf = s.prescription.surfaces[1]
+    c, a3 = surf.curvature, surf.alpha[0]
+    f = lambda u: z0 + (u - x0) * -1.0 - (0.5 * c * u * u + a3 * abs(u) ** 3)
+    fp = lambda u: -1.0 - (c * u + 3 * a3 * u * abs(u))
+    u = s.meta["a"]
+    u1 = u - f(u) / fp(u)
+    u2 = u1 - f(u1) / fp(u1)
+    assert abs(u1 - (s.meta["a"] + s.meta["b"])) < 1e-12 and abs(u2 - u) < 1e-12
