@@ -16,6 +16,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -25,29 +27,61 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1504_06570_amd", "csrc", "phx_trace.hip")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "trace_kernel_full_1e9_pmc.json")
 
-# Algorithmic FP64 operation counts of the trace stages (add/sub/mul/div/sqrt/transcendental = 1,
-# fused multiply-add = 2), counted from the algorithm as written ("Roofline").
-# Algorithmic bytes of the sky+atmosphere stage per traced photon: per layer and scale one
-# bilinear footprint of four (g_x, g_y) float pairs, plus the 7-double start-plane state written.
-FLOPS_SURFACE = 80           # transform, conic root, clip, normal, coating, reflect/refract
-FLOPS_NEWTON = 70            # one Newton step: point, sag + gradient with asphere terms
-FLOPS_SILICON = 65           # index, absorption, conversion, diffusion, pixel
+PEAK_INT32_TOPS = 78.6    # 32-bit integer VALU lane operations: 256 CU x 4 SIMD x 32 lanes x 2.4 GHz
+OP_COUNTS = os.path.join(ROOT, "profiles", "oracle_op_counts_full.json")
+FP64_FIELDS = ("add", "mul", "div", "sqrt", "trans")
+# Implementation traffic of the sky stage (not the method's): the 7-double start-plane state each
+# traced photon hands to the optics stage.
 STATE_BYTES = 7 * 8
+# Integer operations of one Philox4x32-10 block: ten rounds of two 32x32 -> 64-bit products, two
+# three-way XORs (four XORs) and two key additions.
+PHILOX_INT_OPS = 10 * 8
+# The pre-roll's algorithmic work per generated photon, a lower bound: the block holding its
+# wavelength and pupil radius and the block holding the first (most selective) roulette word.
+PREROLL_BLOCKS = 2
 
 
-def front_bytes_per_photon(n_layers, n_scales):
-    return n_layers * n_scales * 4 * 8 + STATE_BYTES
+def op_counts():
+    """The oracle counting build's mean operations per photon by outcome (committed table)."""
+    try:
+        return json.load(open(OP_COUNTS))
+    except (OSError, ValueError):
+        return None
 
 
-def back_flops(stats, n_surf):
-    """FP64 operations of the optics + silicon stage for this launch's traced photons."""
-    import numpy as np
+def front_bytes_per_photon(n_layers, n_scales, counts=None):
+    """Algorithmic bytes per traced photon of the sky stage: the screen footprints the method
+    gathers (from the counting build when its table is there: 7 layers x 3 scales x 32 B)."""
+    if counts is not None:
+        return counts["by_outcome"]["all"]["sky"]["gather_bytes"]
+    return n_layers * n_scales * 4 * 8
+
+
+def back_flops(stats, counts):
+    """FP64 operations of the optics + sensor stage for this launch's traced photons: each
+    outcome group's count in the launch statistics times its mean count in the oracle's counting
+    build (a group absent from the counted sample takes the mean of its status)."""
     from paper_1504_06570_amd import phx
-    tab = phx.stats_table(stats).astype(np.float64)
-    decided_at = tab.sum(axis=0)
-    reach = sum(decided_at[k + 1:].sum() for k in range(n_surf))
-    silicon = tab[[phx.DETECTED, phx.OFF_CHIP, phx.ESCAPED, phx.DEAD], n_surf].sum()
-    return reach * FLOPS_SURFACE + float(stats[phx.STAT_NEWTON]) * FLOPS_NEWTON + silicon * FLOPS_SILICON
+    tab = phx.stats_table(stats)
+    by = counts["by_outcome"]
+
+    def ops(rec):
+        return sum(rec["optics"][f] + rec["sensor"][f] for f in FP64_FIELDS)
+    total = 0.0
+    for st in range(phx.N_STATUS):
+        if st == phx.CULLED:
+            continue
+        for col in range(tab.shape[1]):
+            n = float(tab[st, col])
+            if n == 0:
+                continue
+            key = f"{phx.STATUS[st]}@{col - 1}"
+            if key in by:
+                total += n * ops(by[key])
+            else:
+                same = [v for k, v in by.items() if k.split("@")[0] == phx.STATUS[st]]
+                total += n * (np.mean([ops(v) for v in same]) if same else ops(by["all"]))
+    return total
 
 
 def kernel_hash():
@@ -69,8 +103,19 @@ def traffic_from_profiles(n_launch_photons, kernel):
     return d.get("hbm_bytes_per_launch", {}).get(kernel)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, n_photons, threads):
-    import numpy as np
+    """The oracle on the host: photons [0, n_photons) of the headline star, full physics, no
+    pre-roll (the oracle traces every photon to its fate), split over `threads` threads."""
     import oracle as O
     orc = O.Oracle(scene)
     img = np.zeros(orc.image_shape, np.uint32)
@@ -453,6 +498,35 @@ def copy_probe():
     print(json.dumps({"copy_bytes_each_way": a.numel() * 4}))
 
 
+def gather_probe(footprints_mib=(64, 256, 1024, 2816), rows_per_launch=1 << 22, reps=20):
+    """Random 32-byte gathers (the size of one screen footprint record) over buffers of several
+    sizes: rows gathered per second, the memory system's rate for the sky stage's access pattern
+    (a reference for its roofline).  Uses torch's row gather, which also writes the gathered rows
+    contiguously (32 B per row, coalesced); prints one JSON line."""
+    import torch
+    out = []
+    g = torch.Generator(device="cuda").manual_seed(7)
+    for mib in footprints_mib:
+        n_rows = mib * (1 << 20) // 32
+        src = torch.ones((n_rows, 8), dtype=torch.float32, device="cuda")
+        idx = torch.randint(0, n_rows, (rows_per_launch,), device="cuda", generator=g)
+        dst = torch.empty((rows_per_launch, 8), dtype=torch.float32, device="cuda")
+        torch.index_select(src, 0, idx, out=dst)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.index_select(src, 0, idx, out=dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out.append({"footprint_mib": mib, "rows": rows_per_launch, "ms": ms,
+                    "rows_per_s": rows_per_launch / (ms * 1e-3),
+                    "useful_GBps": rows_per_launch * 32 / (ms * 1e-3) * 1e-9})
+        del src, idx, dst
+    print(json.dumps({"gather_probe": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -464,6 +538,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="random 32-byte gathers over buffers of 64 MiB - 2.75 GiB (reference "
+                         "rate of the sky stage's access pattern)")
     ap.add_argument("--no-compare", action="store_true", help="skip the run without the pre-roll")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-source batched leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint leg")
@@ -480,6 +557,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.gather_probe:
+        gather_probe()
         return
     if args.only:
         leg = batched_leg if args.only == "batched" else gradient_leg
@@ -534,17 +614,37 @@ def main():
     traced = float(st[phx.STAT_TRACED])
     chunks = max(kt["chunks"], 1.0)
     atm = scene.atmosphere
-    # per-launch (one chunk's kernel) figures of each stage
+    counts = op_counts()
+    if counts is None:
+        raise SystemExit(f"bench.py: {OP_COUNTS} is missing (python -m oracle.count_ops)")
+    # per-launch (one chunk's kernel) figures of each stage: algorithmic work from the oracle's
+    # counting build (sky: screen bytes gathered; optics + sensor: FP64 operations by outcome)
+    # and, for the pre-roll, its first two Philox blocks per generated photon
     kinds = {
+        "generate": dict(ms=kt["generate"] / chunks, bound="alu", unit="Tops/s", peak=PEAK_INT32_TOPS,
+                         work=n_ph * args.steps * PREROLL_BLOCKS * PHILOX_INT_OPS / chunks,
+                         scale=1e-12),
         "front": dict(ms=kt["front"] / chunks, bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS,
-                      work=traced * front_bytes_per_photon(atm.n_layers, atm.n_scales) / chunks,
+                      work=traced * front_bytes_per_photon(atm.n_layers, atm.n_scales, counts) / chunks,
                       scale=1e-9),
         "back": dict(ms=kt["back"] / chunks, bound="alu", unit="TFLOP/s", peak=PEAK_FP64_TFLOPS,
-                     work=back_flops(st, n_surf) / chunks, scale=1e-12),
+                     work=back_flops(st, counts) / chunks, scale=1e-12),
     }
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
     d = kinds[dom]
     achieved = d["work"] / (d["ms"] * 1e-3) * d["scale"]
+    pipelined = {}
+    for k, v in kinds.items():
+        a_k = v["work"] / (v["ms"] * 1e-3) * v["scale"]
+        pipelined[f"{k}_kernel"] = {"bound": v["bound"], "achieved": a_k, "peak": v["peak"],
+                                    "unit": v["unit"], "frac": a_k / v["peak"],
+                                    "launch_ms": v["ms"], "work_per_launch": v["work"]}
+    implementation = {
+        "front_state_write_bytes_per_launch": traced * STATE_BYTES / chunks,
+        "note": "the sky stage also writes the 7-double start-plane state of each traced photon "
+                "for the optics stage; that traffic comes from splitting the trace into kernels "
+                "and is not in the algorithmic bytes",
+    }
     stage_ms = {k: kt[k] / args.steps for k in ("generate", "front", "back")}
     extra = {}
     # The timed steps overlap each chunk's optics stage with the next chunk's sky stage, so the
@@ -565,7 +665,9 @@ def main():
         a_k = v["work"] / (ms_k * 1e-3) * v["scale"]
         iso[f"{k}_kernel"] = {"bound": v["bound"], "achieved": a_k, "peak": v["peak"],
                               "unit": v["unit"], "frac": a_k / v["peak"], "launch_ms": ms_k}
+    extra["roofline_pipelined"] = pipelined
     extra["roofline_single_stream"] = iso
+    extra["implementation_traffic"] = implementation
     extra["stage_ms_single_stream"] = {k: kti[k] for k in ("generate", "front", "back")}
     if not args.no_cull and not args.no_compare:
         # the same step without the pre-roll (every photon traced until its fate)
@@ -594,13 +696,23 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
+        # all cores of the host's share for one GPU (16 on the GPU machines), then one core
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         n_cpu = int(args.cpu_sample)
         rate, dt = cpu_baseline(scene, n_cpu, threads)
+        n_one = max(int(n_cpu // 16), 1)
+        rate1, dt1 = cpu_baseline(scene, n_one, 1)
         cpu = {"value": rate, "unit": "photons/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {n_cpu:.0e} photons of the same star, full physics, no pre-roll, "
-                         f"{dt:.1f} s on {threads} host threads"}
-        print(f"# cpu oracle {rate:.3e} photons/s ({dt:.1f}s)", file=sys.stderr, flush=True)
+               "sample": f"first {n_cpu:.0e} photons of the headline star, full physics, no "
+                         f"pre-roll (every photon traced to its fate), {dt:.1f} s on {threads} "
+                         f"host threads; one core: first {n_one:.0e} photons, {dt1:.1f} s",
+               "one_core_value": rate1, "cpu_model": cpu_model(),
+               "host_cpus": os.cpu_count()}
+        nc = extra.get("value_without_preroll")
+        if nc:
+            cpu["gpu_over_oracle_equal_work"] = nc / rate
+        print(f"# cpu oracle {rate:.3e} photons/s ({dt:.1f}s, {threads} threads), one core "
+              f"{rate1:.3e} photons/s ({dt1:.1f}s)", file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batched:
@@ -622,6 +734,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
+        "precision": "FP64 arithmetic throughout; screen gradients and coating tables are stored "
+                     "as FP32 and widened on use; hardware reciprocal and reciprocal-square-root "
+                     "estimates refined to about 1 ulp in the continuous geometry",
         "data": "synthetic",
         "config": {
             "workload": "full single-source trace: 1 star, 1e9 photons/step, 7 frozen-flow von "

@@ -38,6 +38,24 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Hooks of the counting build (count.cpp includes this file with every double replaced by a
+ * type that counts its arithmetic): the trace stage being counted, a pause around arithmetic that
+ * is not the method's (decision margins, per-device constants), Philox blocks and screen bytes
+ * read.  Empty in the oracle itself. */
+#ifndef ORC_STAGE
+#define ORC_STAGE(s)
+#define ORC_COUNT_PAUSE()
+#define ORC_COUNT_RESUME()
+#define ORC_COUNT_PHILOX()
+#define ORC_COUNT_GATHER(bytes)
+#endif
+#define NOTE_MARGIN(m, v)        \
+    do {                         \
+        ORC_COUNT_PAUSE();       \
+        note_margin((m), (v));   \
+        ORC_COUNT_RESUME();      \
+    } while (0)
+
 #define TWO_PI 6.283185307179586476925286766559
 #define HC_EV_M 1.2398419843320026e-6 /* h c / e (eV m), SI-exact constants */
 #define K_B_EV 8.617333262e-5         /* Boltzmann constant (eV/K) */
@@ -51,6 +69,7 @@
  * M0 = 0xD2511F53, M1 = 0xCD9E8D57 and the key bumped by the Weyl constants
  * (0x9E3779B9, 0xBB67AE85) between rounds. */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    ORC_COUNT_PHILOX();
     uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
     uint32_t k0 = key[0], k1 = key[1];
     for (int round = 0; round < 10; ++round) {
@@ -111,23 +130,30 @@ double orc_rajkanan(double lambda_m, double T) {
     const double C[2] = {5.5, 4.0};
     const double A[2] = {3.231e2, 7.237e3};
     const double Ad = 1.052e6;
-    double e = HC_EV_M / lambda_m;
+    /* constants of the device temperature (not counted per photon by the counting build) */
+    ORC_COUNT_PAUSE();
     double shift = beta * T * T / (T + gam);
-    double alpha = 0.0;
+    double absorb[2], emit[2], eg[2], CA[2][2];
     for (int i = 0; i < 2; ++i) {
-        double absorb = exp(ep[i] / (K_B_EV * T)) - 1.0;
-        double emit = 1.0 - exp(-ep[i] / (K_B_EV * T));
-        for (int j = 0; j < 2; ++j) {
-            double eg = eg0[j] - shift;
-            double a = e - eg + ep[i];
-            double b = e - eg - ep[i];
-            double term = 0.0;
-            if (a > 0.0) term += a * a / absorb;
-            if (b > 0.0) term += b * b / emit;
-            alpha += C[i] * A[j] * term;
-        }
+        absorb[i] = exp(ep[i] / (K_B_EV * T)) - 1.0;
+        emit[i] = 1.0 - exp(-ep[i] / (K_B_EV * T));
+        eg[i] = eg0[i] - shift;
+        for (int j = 0; j < 2; ++j) CA[i][j] = C[i] * A[j];
     }
     double egd = egd0 - shift;
+    ORC_COUNT_RESUME();
+    double e = HC_EV_M / lambda_m;
+    double alpha = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        for (int j = 0; j < 2; ++j) {
+            double a = e - eg[j] + ep[i];
+            double b = e - eg[j] - ep[i];
+            double term = 0.0;
+            if (a > 0.0) term += a * a / absorb[i];
+            if (b > 0.0) term += b * b / emit[i];
+            alpha += CA[i][j] * term;
+        }
+    }
     if (e > egd) alpha += Ad * sqrt(e - egd);
     return alpha;
 }
@@ -336,6 +362,7 @@ static void screen_lookup(const orc_scene* sc, int l, int s, double xs, double y
                           double* gy) {
     int64_t N = sc->screen_n;
     const float* g = sc->grad + ((size_t)l * sc->n_scales + s) * N * N * 2;
+    ORC_COUNT_GATHER(32);   /* the four corners' (g_x, g_y) float pairs */
     double fx = floor(xs), fy = floor(ys);
     double a = xs - fx, b = ys - fy;
     int64_t i0 = wrap((int64_t)fx, N), j0 = wrap((int64_t)fy, N);
@@ -466,16 +493,16 @@ static int gamma_sample(uint32_t seed, int32_t src, uint64_t photon, double shap
         draw(&tmp, src, photon, t, 1, u);
         double x = sqrt(-2.0 * log(u[0])) * cos(TWO_PI * u[1]);
         double v = 1.0 + cc * x;
-        note_margin(margin, v);
+        NOTE_MARGIN(margin, v);
         if (v <= 0.0) continue;
         v = v * v * v;
         double x2 = x * x;
         double t1 = 1.0 - 0.0331 * x2 * x2;
-        note_margin(margin, u[2] - t1);
+        NOTE_MARGIN(margin, u[2] - t1);
         int accept = u[2] < t1;
         if (!accept) {
             double t2 = 0.5 * x2 + dd * (1.0 - v + log(v));
-            note_margin(margin, log(u[2]) - t2);
+            NOTE_MARGIN(margin, log(u[2]) - t2);
             accept = log(u[2]) < t2;
         }
         if (accept) {
@@ -604,7 +631,7 @@ static int halo_sample(uint32_t seed, int32_t src, uint64_t photon, double n, do
         /* (1 + x^2)^e = 1 - v Fq */
         double x = sqrt(pow(1.0 - v * Fq, 1.0 / e) - 1.0);
         double ratio = pow(1.0 + x * x, 0.5 * n) / (1.0 + pow(x, n));
-        note_margin(margin, u - ratio / M);
+        NOTE_MARGIN(margin, u - ratio / M);
         if (u < ratio / M) {
             *x_out = x;
             return (int)t;
@@ -658,12 +685,12 @@ static int second_kick(const orc_scene* sc, int32_t si, uint64_t photon, int lay
     /* K = the smallest k with P(K <= k) > u */
     double p = exp(-s2), cum = p;
     int K = 0;
-    note_margin(margin, uk - cum);
+    NOTE_MARGIN(margin, uk - cum);
     while (!(uk < cum) && K < 8) {
         ++K;
         p *= s2 / K;
         cum += p;
-        note_margin(margin, uk - cum);
+        NOTE_MARGIN(margin, uk - cum);
     }
     *kx = 0.0;
     *ky = 0.0;
@@ -731,7 +758,7 @@ static int spider(const orc_scene* sc, double p[3], double n[3], double lam, dou
         }
         if (inside && t0 <= t1 && t1 >= 0.0) {
             if (t0 < 0.0) t0 = 0.0;
-            note_margin(margin, (t1 - t0) / (fabs(t0) + fabs(t1)));
+            NOTE_MARGIN(margin, (t1 - t0) / (fabs(t0) + fabs(t1)));
             if (t0 < t_hit) t_hit = t0;
             continue;
         }
@@ -762,9 +789,9 @@ static int spider(const orc_scene* sc, double p[3], double n[3], double lam, dou
     if (best_k < 0) return 0;
     for (int k = 0; k < x->vanes; ++k)
         if (k != best_k && dk[k] < second) second = dk[k];
-    note_margin(margin, best / x->vane_width);
-    if (second < INFINITY) note_margin(margin, (second - best) / best);
-    note_margin(margin, u_sign - 0.5);
+    NOTE_MARGIN(margin, best / x->vane_width);
+    if (second < INFINITY) NOTE_MARGIN(margin, (second - best) / best);
+    NOTE_MARGIN(margin, u_sign - 0.5);
     double zm = 0.5 * (x->vane_z_lo + x->vane_z_hi);
     double l = (zm - p[2]) / n[2];
     p[0] += n[0] * l;
@@ -806,7 +833,7 @@ static int nearest_surface(const orc_scene* sc, const double p[3], const double 
         if (l < best) { second = best; best = l; bk = j; }
         else if (l < second) second = l;
     }
-    if (bk >= 0 && second < INFINITY) note_margin(margin, (second - best) / best);
+    if (bk >= 0 && second < INFINITY) NOTE_MARGIN(margin, (second - best) / best);
     return bk;
 }
 
@@ -817,6 +844,7 @@ static void land(const orc_scene* sc, int32_t si, uint64_t photon, int k, const 
                  orc_event* ev, uint32_t* image) {
     const orc_extra* ex = &sc->ex;
     double margin = *margin_p;
+    ORC_STAGE(2);   /* sensor: silicon, diffusion, pixel */
     ev->x = q[0]; ev->y = q[1]; ev->z = q[2];
     double xc = q[0], yc = q[1];
     if (sc->physics & ORC_SILICON_PHYS) {
@@ -824,7 +852,7 @@ static void land(const orc_scene* sc, int32_t si, uint64_t photon, int k, const 
         double alpha = orc_rajkanan(lam, sc->temp_k) * 100.0; /* m^-1 */
         double L = alpha > 0.0 ? -log(u1[2]) / alpha : INFINITY;
         double depth = L * fabs(d[2]);
-        note_margin(&margin, (depth - sc->t_si) / sc->t_si);
+        NOTE_MARGIN(&margin, (depth - sc->t_si) / sc->t_si);
         if (!(depth <= sc->t_si)) {
             set_event(ev, ORC_ESCAPED, k, q);
             ev->margin = margin;
@@ -834,7 +862,7 @@ static void land(const orc_scene* sc, int32_t si, uint64_t photon, int k, const 
             /* field-free dead layer (section 2.4.2): electrons converted within `dead` of the
              * surface the light enters are removed.  Reading: the paper's "back surface" of a
              * back-illuminated device is the illuminated one. */
-            note_margin(&margin, (depth - ex->dead) / sc->t_si);
+            NOTE_MARGIN(&margin, (depth - ex->dead) / sc->t_si);
             if (depth < ex->dead) {
                 set_event(ev, ORC_DEAD, k, q);
                 ev->margin = margin;
@@ -861,10 +889,10 @@ static void land(const orc_scene* sc, int32_t si, uint64_t photon, int k, const 
     /* pixel quantisation (section 2.4.3, last step) */
     double fx = (xc - sc->chip_x0) / sc->pixel, fy = (yc - sc->chip_y0) / sc->pixel;
     double ix = floor(fx), iy = floor(fy);
-    note_margin(&margin, fx - ix);
-    note_margin(&margin, 1.0 - (fx - ix));
-    note_margin(&margin, fy - iy);
-    note_margin(&margin, 1.0 - (fy - iy));
+    NOTE_MARGIN(&margin, fx - ix);
+    NOTE_MARGIN(&margin, 1.0 - (fx - ix));
+    NOTE_MARGIN(&margin, fy - iy);
+    NOTE_MARGIN(&margin, 1.0 - (fy - iy));
     ev->status = ORC_OFF_CHIP;
     ev->surface = k;
     if (ix >= 0.0 && ix < (double)sc->nx && iy >= 0.0 && iy < (double)sc->ny) {
@@ -881,6 +909,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
     const orc_source* src = &sc->src[si];
     double margin = 1e300;
     double u0[4], u1[4];
+    ORC_STAGE(0);   /* sky: source, atmosphere, start plane */
     draw(sc, si, photon, 0, 0, u0);
     draw(sc, si, photon, 1, 0, u1);
     memset(ev, 0, sizeof(*ev));
@@ -915,8 +944,8 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         const double* cdf = sc->sed_cdf + (size_t)src->sed * (sc->sed_k + 1);
         int k = 0;
         while (k < sc->sed_k - 1 && !(cdf[k + 1] > u0[3])) ++k;
-        note_margin(&margin, u0[3] - cdf[k]);
-        note_margin(&margin, u0[3] - cdf[k + 1]);
+        NOTE_MARGIN(&margin, u0[3] - cdf[k]);
+        NOTE_MARGIN(&margin, u0[3] - cdf[k + 1]);
         lam = sc->sed_edges[k] + u1[0] * (sc->sed_edges[k + 1] - sc->sed_edges[k]);
     }
     lam = lam * (1.0 + src->redshift);
@@ -996,6 +1025,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         p[1] += n[1] * l;
         p[2] = sc->z_start;
     }
+    ORC_STAGE(1);   /* optics: entrance effects, obscuration, surfaces */
     double u7[4] = {0.5, 0.5, 0.5, 0.5};
     if (sc->physics & (ORC_AEROSOL | ORC_HALO | ORC_SPIDER)) draw(sc, si, photon, 7, 0, u7);
     if (sc->physics & ORC_AEROSOL) {
@@ -1004,7 +1034,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
          * Reading: the printed destruction probability exp(-tau) is the survival probability. */
         double tau = ex->tau0 * pow(lam / 500e-9, ex->gamma) / cos(ex->zenith);
         double keep = exp(-tau);
-        note_margin(&margin, u7[0] - keep);
+        NOTE_MARGIN(&margin, u7[0] - keep);
         if (!(u7[0] < keep)) {
             set_event(ev, ORC_EXTINCT, -1, p);
             ev->margin = margin;
@@ -1024,7 +1054,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
     if (sc->physics & ORC_HALO) {
         /* Micro-roughness halo (section 2.4.2): with probability f, a kick of angle r0 x
          * (halo_sample) toward a uniform azimuth, at the start of the telescope. */
-        note_margin(&margin, u7[1] - ex->halo_f);
+        NOTE_MARGIN(&margin, u7[1] - ex->halo_f);
         if (u7[1] < ex->halo_f) {
             double xh;
             if (halo_sample(sc->seed, si, photon, ex->halo_n, ex->halo_max / ex->halo_r0, &xh,
@@ -1049,7 +1079,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         double l = (sc->obsc_z - p[2]) / n[2];
         double x = p[0] + n[0] * l, y = p[1] + n[1] * l;
         double rr = sqrt(x * x + y * y);
-        note_margin(&margin, (rr - sc->obsc_r) / sc->obsc_r);
+        NOTE_MARGIN(&margin, (rr - sc->obsc_r) / sc->obsc_r);
         if (rr < sc->obsc_r) {
             double q[3] = {x, y, sc->obsc_z};
             set_event(ev, ORC_OBSCURED, -1, q);
@@ -1064,6 +1094,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
      * through all surfaces by their intersection distance), at most GHOST_MAX interactions. */
     double n_cur = 1.0;
     int medium = ORC_VACUUM;
+    double n_index[3] = {1.0, -1.0, -1.0};   /* vacuum, glass, silicon: formed on first use */
     double ucoat[4];
     int coat_block = -1;
     int ghost = 0, from = -1, inter = 0, next = 0;
@@ -1107,8 +1138,8 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         q[0] += d[0] * l; q[1] += d[1] * l; q[2] += d[2] * l;
         /* clear aperture (paper Table 1: outer and inner radii) */
         double rq = sqrt(q[0] * q[0] + q[1] * q[1]);
-        if (s->r_in > 0.0) note_margin(&margin, (rq - s->r_in) / s->r_in);
-        note_margin(&margin, (rq - s->r_out) / s->r_out);
+        if (s->r_in > 0.0) NOTE_MARGIN(&margin, (rq - s->r_in) / s->r_in);
+        NOTE_MARGIN(&margin, (rq - s->r_out) / s->r_out);
         if (rq < s->r_in || rq > s->r_out) {
             set_event(ev, ORC_VIGNETTED, k, q);
             ev->margin = margin;
@@ -1140,12 +1171,12 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
                 uk = ug[0];
             }
             double T = orc_coating(sc, s->coating, 1.0 - cosi * cosi, lam);
-            note_margin(&margin, uk - T);
+            NOTE_MARGIN(&margin, uk - T);
             if (!(uk < T)) {
                 double R = 0.0;
                 if ((sc->physics & ORC_GHOSTS) && s->kind != ORC_MIRROR) {
                     R = coating_reflect(sc, s->coating, 1.0 - cosi * cosi, lam);
-                    note_margin(&margin, uk - (T + R));
+                    NOTE_MARGIN(&margin, uk - (T + R));
                 }
                 if (!(uk < T + R)) {
                     set_event(ev, ORC_ABSORBED, k, q);
@@ -1165,10 +1196,12 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
              * the Sellmeier / silicon formulas (section 2.4.1); vacuum elsewhere */
             int after = s->medium, before = k > 0 ? sc->surf[k - 1].medium : ORC_VACUUM;
             int m2 = medium == after ? before : after;
-            double n2 = medium_index(sc, m2, lam);
+            /* each index once per photon (it depends on the wavelength only) */
+            if (n_index[m2] < 0.0) n_index[m2] = medium_index(sc, m2, lam);
+            double n2 = n_index[m2];
             double mu = n_cur / n2;
             double kk = 1.0 - mu * mu * (1.0 - cosi * cosi);
-            note_margin(&margin, kk);
+            NOTE_MARGIN(&margin, kk);
             if (kk < 0.0) {
                 set_event(ev, ORC_TIR, k, q);
                 ev->margin = margin;

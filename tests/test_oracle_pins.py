@@ -630,3 +630,29 @@ def test_newton_cycle_is_counted_as_nonconv():
     u1 = u - f(u) / fp(u)
     u2 = u1 - f(u1) / fp(u1)
     assert abs(u1 - (s.meta["a"] + s.meta["b"])) < 1e-12 and abs(u2 - u) < 1e-12
+
+
+def test_counting_build_traces_the_same_photons_and_counts_structure():
+    """The oracle's counting build (oracle/count.cpp: the oracle's source with a counting double)
+    gives the oracle's events bit for bit; its counts have the structure the method fixes: 7 x 3
+    screen footprints of 32 bytes per photon with the atmosphere and none without, two Philox
+    blocks in the sky stage of a flat-spectrum point source (pupil / time / wavelength and the
+    conversion word), no optics work for a photon stopped at the central obscuration, and more
+    for a detected photon than for one vignetted at the primary."""
+    from oracle import count_ops as K
+    K.build()
+    for scene, layers in ((C.full(scale=2e-5, screen_n=128), 7 * 3), (C.telescope(scale=1e-4), 0)):
+        ph = np.arange(int(scene.sources.n_photons[0]), dtype=np.uint64)
+        ev, cnt = K.count(scene, ph, threads=4)
+        ref = O.Oracle(scene).trace_list(0, ph)
+        for f in ev.dtype.names:
+            assert np.array_equal(ev[f], ref[f], equal_nan=True), f
+        sky = cnt[:, 0]
+        assert np.all(sky[:, K.FIELDS.index("gather_bytes")] == 32 * layers)
+        assert np.all(sky[:, K.FIELDS.index("philox")] == 2)
+        tb = K.table(ev, cnt)
+        ops = lambda k: sum(tb[k]["optics"][f] for f in ("add", "mul", "div", "sqrt"))
+        if "OBSCURED@-1" in tb:
+            assert ops("OBSCURED@-1") < 20
+        if "VIGNETTED@0" in tb and "DETECTED@11" in tb:
+            assert ops("DETECTED@11") > 5 * ops("VIGNETTED@0")
