@@ -422,9 +422,10 @@ phx_status phx_trace_noalloc(phx_ctx ctx, const phx_trace_args* args, void* stre
  * *_blocks_per_cu: workgroups of 256 lanes per compute unit for the pre-roll, sky+atmosphere and
  * optics kernels (1..64); dynamic_tiles: 0 = static grid-stride, 1 = the sky kernel claims tiles of
  * 2048 photons and each optics wavefront units of 64 from device counters; pipeline: 1 = each
- * chunk's pre-roll and optics stages run on a context-owned second stream, overlapping the sky
- * stage of the chunk between them (ordered by events; the caller's stream waits for the last
- * optics stage), 0 = everything on the caller's stream.  Launches captured by phx_trace_batched always run on the capturing stream.
+ * chunk's pre-roll bitmap and optics stages run on a context-owned second stream, overlapping
+ * the survivor compaction and sky stage of the next chunk on the caller's stream (ordered by
+ * events; the caller's stream waits for the last optics stage), 0 = everything on the caller's
+ * stream.  Launches captured by phx_trace_batched always run on the capturing stream.
  * Defaults: 26, 16, 64, 3, 0, 1. */
 typedef struct {
     int32_t chunk_log2;

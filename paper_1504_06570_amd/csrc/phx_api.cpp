@@ -1276,12 +1276,13 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
         c->graphs_clear();
         e = hipMalloc((void**)&c->d_survivors, 2 * chunk * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, 2 * 7 * chunk * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc((void**)&c->d_bits, (chunk + 63) / 64 * sizeof(uint64_t));
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&c->d_bits, 2 * ((chunk + 63) / 64) * sizeof(uint64_t));
         if (e == hipSuccess)
             e = hipMalloc((void**)&c->d_bsum, phx::compact_groups(chunk) * sizeof(unsigned int));
-        if (e == hipSuccess) e = hipMalloc((void**)&c->d_key, chunk);
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_key, 2 * chunk);
         if (e == hipSuccess)
-            e = hipMalloc((void**)&c->d_hist, 2 * phx::compact_groups(chunk) *
+            e = hipMalloc((void**)&c->d_hist, (2 * phx::bucket_groups(chunk) + 1) *
                                                   phx::kTimeBucketsMax * sizeof(unsigned int));
         if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "trace workspace: %s",
                                          hipGetErrorString(e));

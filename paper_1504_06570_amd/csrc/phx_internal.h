@@ -8,6 +8,7 @@
 namespace phx {
 
 constexpr int kNZern = 12;  // Noll Z4..Z15
+constexpr int kThreads = 256;   // workgroup size of every trace kernel
 constexpr int kSedGuide = 1024;   // guide entries per SED for the wavelength search
 constexpr int kNZernPoly = 15;  // monomials u^a v^b, a + b <= 4
 
@@ -157,13 +158,15 @@ struct Workspace {
     double* state;             // [buffers][7][chunk]
     uint64_t chunk;
     unsigned long long* tiles; // [n_chunks][2] tile counters of the dynamic schedule
-    unsigned long long* bits;  // [chunk / 64] survivor bitmap
+    unsigned long long* bits;  // [buffers][chunk / 64] survivor bitmap
     unsigned int* bsum;        // [compact_groups(chunk)] survivors per compaction workgroup
-    uint8_t* key;              // [chunk] time bucket of each survivor
-    unsigned int* hist;        // [compact_groups(chunk)][kTimeBucketsMax] survivors per bucket
+    uint8_t* key;              // [buffers][chunk] time bucket of each survivor
+    unsigned int* hist;        // [2 bucket_groups(chunk) + 1][kTimeBucketsMax]: survivors per
+                               // bucket and workgroup, their prefixes over workgroups, totals
     const ChunkSpan* plan;     // host array: the launch's chunks in order
     uint64_t n_plan;
-    int buffers;               // survivors and states hold this many chunks (1 or 2)
+    int buffers;               // bitmaps, keys, survivors and states hold this many chunks
+                               // (1 or 2)
     double* ghost_q = nullptr; // [ghost_waves][kGhostFields][kGhostQ] queues of the optics
     uint64_t ghost_waves = 0;  // kernel with ghosts, one per wavefront of its grid
 };
@@ -183,7 +186,8 @@ struct ScratchLayout {
 constexpr uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 constexpr ScratchLayout scratch_layout() {
     const uint64_t chunk = 1ull << kNoAllocChunkLog2;
-    const uint64_t groups = ((chunk + 63) / 64 + 4095) / 4096;
+    const uint64_t groups = ((chunk + 63) / 64 + 4095) / 4096;            // compaction
+    const uint64_t bgroups = ((chunk + 63) / 64 + 1023) / 1024;           // time-bucket sort
     ScratchLayout s{};
     s.survivors = 0;
     s.state = align256(s.survivors + chunk * 4);
@@ -191,7 +195,7 @@ constexpr ScratchLayout scratch_layout() {
     s.bsum = align256(s.bits + (chunk + 63) / 64 * 8);
     s.key = align256(s.bsum + groups * 4);
     s.hist = align256(s.key + chunk);
-    s.counts = align256(s.hist + 2 * groups * 64 * 4);
+    s.counts = align256(s.hist + (2 * bgroups + 1) * 64 * 4);
     s.tiles = align256(s.counts + kNoAllocMaxChunks * 4);
     s.prefix = align256(s.tiles + 2 * kNoAllocMaxChunks * 8);
     s.guide = align256(s.prefix + (kNoAllocMaxSources + 1) * 8);
@@ -223,6 +227,11 @@ constexpr int kTimeBucketsMax = 64;
 // Workgroups of the ordered compaction for a chunk of n photons (64 photons per bitmap word,
 // 4096 words per workgroup).
 inline uint64_t compact_groups(uint64_t n) { return ((n + 63) / 64 + 4095) / 4096; }
+// Workgroups of the time-bucket sort for a chunk of n photons (1024 bitmap words each).
+constexpr int kBucketWordsPerThread = 4;
+inline uint64_t bucket_groups(uint64_t n) {
+    return ((n + 63) / 64 + kThreads * kBucketWordsPerThread - 1) / (kThreads * kBucketWordsPerThread);
+}
 
 // Launch shape (tunable): workgroups per compute unit of each stage, and the schedule of the
 // sky and optics stages (static grid-stride, or tiles of kTileIters x 256 photons taken from a
@@ -239,7 +248,6 @@ constexpr int kTileIters = 8;
 // path (the other instantiations hold none of its code).
 constexpr uint32_t kFrontExtra = PHX_F_DISPERSION | PHX_F_DOME | PHX_F_HALO | PHX_F_SECOND_KICK;
 constexpr uint32_t kBackExtra = PHX_F_AEROSOL | PHX_F_SPIDER | PHX_F_GHOSTS;
-constexpr int kThreads = 256;   // workgroup size of every trace kernel
 
 // Optional per-kernel timing: events recorded before/after each kernel launch.
 struct Timing {

@@ -1656,7 +1656,29 @@ __global__ __launch_bounds__(kBlock) void compact_scatter(const unsigned long lo
 // Time-bucketed compaction (with the atmosphere): a stable counting sort of the survivors by
 // time bucket, so that photons traced together see the same wind-shifted stretch of every phase
 // screen and share its cache lines.  Within a bucket survivors keep photon order; the result is
-// the same on every run.
+// the same on every run.  Each workgroup takes kBucketWords bitmap words; a word's 64 bucket
+// bytes are read with four 16-byte loads before its set bits are visited (in photon order).
+constexpr uint64_t kBucketWords = (uint64_t)kBlock * kBucketWordsPerThread;
+
+template <class F>
+__device__ __forceinline__ void for_each_survivor(unsigned long long m, const uint8_t* key_word,
+                                                  F f) {
+    if (!m) return;
+    const uint4* kp = reinterpret_cast<const uint4*>(key_word);
+    const uint4 k0 = kp[0], k1 = kp[1], k2 = kp[2], k3 = kp[3];
+    const uint32_t kw[16] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w,
+                             k2.x, k2.y, k2.z, k2.w, k3.x, k3.y, k3.z, k3.w};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        uint32_t mj = (uint32_t)(m >> (4 * j)) & 0xfu;
+        while (mj) {
+            const int b = __ffs(mj) - 1;
+            f(4 * j + b, (int)((kw[j] >> (8 * b)) & 0xffu));
+            mj &= mj - 1;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void bucket_count(const unsigned long long* __restrict__ bits,
                                                        const uint8_t* __restrict__ key,
                                                        uint64_t n_words,
@@ -1664,93 +1686,94 @@ __global__ __launch_bounds__(kBlock) void bucket_count(const unsigned long long*
     __shared__ unsigned int s_h[kTimeBuckets];
     if (threadIdx.x < kTimeBuckets) s_h[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWords;
-    for (int i = 0; i < kWordsPerThread; ++i) {
+    const uint64_t w0 = (uint64_t)blockIdx.x * kBucketWords;
+    for (int i = 0; i < kBucketWordsPerThread; ++i) {
         const uint64_t w = w0 + (uint64_t)i * kBlock + threadIdx.x;
         if (w >= n_words) continue;
-        unsigned long long m = bits[w];
-        while (m) {
-            const int bit = __ffsll(m) - 1;
-            atomicAdd(&s_h[key[w * 64 + bit]], 1u);
-            m &= m - 1;
-        }
+        for_each_survivor(bits[w], key + w * 64, [&](int, int b) { atomicAdd(&s_h[b], 1u); });
     }
     __syncthreads();
     if (threadIdx.x < kTimeBuckets) hist[(uint64_t)blockIdx.x * kTimeBuckets + threadIdx.x] = s_h[threadIdx.x];
 }
 
-// Each workgroup first derives where its survivors of every bucket start: the survivors of all
-// earlier buckets, plus those of its bucket in earlier workgroups (from the per-workgroup
-// histograms); the last workgroup stores the total in *count.
+// Per bucket, the exclusive prefix of its survivors over the sort's workgroups (pre[g][b]) and
+// its total (tot[b]): one workgroup per bucket.
+__global__ __launch_bounds__(kBlock) void bucket_scan(const unsigned int* __restrict__ hist,
+                                                      unsigned int n_groups,
+                                                      unsigned int* __restrict__ pre,
+                                                      unsigned int* __restrict__ tot) {
+    __shared__ unsigned int s_scan[kBlock];
+    const int b = blockIdx.x, t = threadIdx.x;
+    unsigned int carry = 0;
+    for (unsigned int g0 = 0; g0 < n_groups; g0 += kBlock) {
+        const unsigned int g = g0 + t;
+        const unsigned int v = g < n_groups ? hist[(uint64_t)g * kTimeBuckets + b] : 0u;
+        s_scan[t] = v;
+        __syncthreads();
+        for (int d = 1; d < kBlock; d <<= 1) {
+            const unsigned int x = t >= d ? s_scan[t - d] : 0u;
+            __syncthreads();
+            s_scan[t] += x;
+            __syncthreads();
+        }
+        if (g < n_groups) pre[(uint64_t)g * kTimeBuckets + b] = carry + s_scan[t] - v;
+        carry += s_scan[kBlock - 1];
+        __syncthreads();
+    }
+    if (t == 0) tot[b] = carry;
+}
+
+// Each workgroup's survivors of bucket b start after the survivors of all earlier buckets and
+// those of bucket b in earlier workgroups; the last workgroup stores the total in *count.
 __global__ __launch_bounds__(kBlock) void bucket_scatter(const unsigned long long* __restrict__ bits,
                                                          const uint8_t* __restrict__ key,
                                                          uint64_t n_words,
-                                                         const unsigned int* __restrict__ hist,
+                                                         const unsigned int* __restrict__ pre,
+                                                         const unsigned int* __restrict__ tot,
                                                          uint32_t* __restrict__ surv,
                                                          unsigned int* __restrict__ count) {
-    __shared__ unsigned int s_c[kTimeBuckets][kBlock];   // per bucket, per thread: count, then slot
-    __shared__ unsigned int s_tot[kBlock / kTimeBuckets][kTimeBuckets];
-    __shared__ unsigned int s_pre[kBlock / kTimeBuckets][kTimeBuckets];
+    // per bucket, per thread: count, then slot (a thread holds at most 4 x 64 survivors)
+    __shared__ uint16_t s_c[kTimeBuckets][kBlock];
     __shared__ unsigned int s_off[kTimeBuckets];
+    static_assert(kBucketWordsPerThread * 64 < 65536, "per-thread counts fit 16 bits");
     const int t = threadIdx.x;
-    {
-        constexpr int kParts = kBlock / kTimeBuckets;
-        const int b = t % kTimeBuckets, part = t / kTimeBuckets;
-        unsigned int tot = 0, pre = 0;
-        for (unsigned int g = part; g < gridDim.x; g += kParts) {
-            const unsigned int v = hist[(uint64_t)g * kTimeBuckets + b];
-            tot += v;
-            if (g < blockIdx.x) pre += v;
+    if (t < kTimeBuckets) {
+        unsigned int base = 0, all = 0;
+        for (int c = 0; c < kTimeBuckets; ++c) {
+            const unsigned int tc = tot[c];
+            if (c < t) base += tc;
+            all += tc;
         }
-        s_tot[part][b] = tot;
-        s_pre[part][b] = pre;
-        __syncthreads();
-        if (t < kTimeBuckets) {
-            unsigned int base = 0, mine = 0, all = 0;
-            for (int c = 0; c < kTimeBuckets; ++c) {
-                unsigned int tc = 0;
-                for (int q = 0; q < kParts; ++q) tc += s_tot[q][c];
-                if (c < t) base += tc;
-                all += tc;
-            }
-            for (int q = 0; q < kParts; ++q) mine += s_pre[q][t];
-            s_off[t] = base + mine;
-            if (blockIdx.x == gridDim.x - 1 && t == 0) *count = all;
-        }
-        __syncthreads();
+        s_off[t] = base + pre[(uint64_t)blockIdx.x * kTimeBuckets + t];
+        if (blockIdx.x == gridDim.x - 1 && t == 0) *count = all;
     }
+    __syncthreads();
     for (int b = 0; b < kTimeBuckets; ++b) s_c[b][t] = 0;
-    const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWords + (uint64_t)t * kWordsPerThread;
-    for (int i = 0; i < kWordsPerThread; ++i) {
+    const uint64_t w0 = (uint64_t)blockIdx.x * kBucketWords + (uint64_t)t * kBucketWordsPerThread;
+    for (int i = 0; i < kBucketWordsPerThread; ++i) {
         if (w0 + i >= n_words) break;
-        unsigned long long m = bits[w0 + i];
-        while (m) {
-            const int bit = __ffsll(m) - 1;
-            s_c[key[(w0 + i) * 64 + bit]][t] += 1;
-            m &= m - 1;
-        }
+        for_each_survivor(bits[w0 + i], key + (w0 + i) * 64,
+                          [&](int, int b) { s_c[b][t] += 1; });
     }
     __syncthreads();
     if (t < kTimeBuckets) {   // exclusive scan of bucket t over the threads, in thread order
         unsigned int run = 0;
         for (int u = 0; u < kBlock; ++u) {
             const unsigned int v = s_c[t][u];
-            s_c[t][u] = run;
+            s_c[t][u] = (uint16_t)run;   // a thread's slot within its workgroup's bucket run
             run += v;
         }
     }
     __syncthreads();
+    // slots within the workgroup's run of a bucket: below 4 x 64 x 256 = 65536
     const unsigned int* o = s_off;
-    for (int i = 0; i < kWordsPerThread; ++i) {
+    for (int i = 0; i < kBucketWordsPerThread; ++i) {
         if (w0 + i >= n_words) break;
-        unsigned long long m = bits[w0 + i];
-        while (m) {
-            const int bit = __ffsll(m) - 1;
-            const int b = key[(w0 + i) * 64 + bit];
-            surv[o[b] + s_c[b][t]] = (uint32_t)((w0 + i) * 64 + bit);
+        const uint64_t base = (w0 + i) * 64;
+        for_each_survivor(bits[w0 + i], key + base, [&](int bit, int b) {
+            surv[o[b] + s_c[b][t]] = (uint32_t)(base + bit);
             s_c[b][t] += 1;
-            m &= m - 1;
-        }
+        });
     }
 }
 
@@ -2519,51 +2542,62 @@ __global__ void gradient_kernel(const float* __restrict__ opd, float4* __restric
 
 }  // namespace
 
-// Pre-roll of one chunk: survivor bitmap, then the survivor list (in photon order, or sorted by
-// time bucket) and its count.
-static void launch_preroll(const DevParams* dparams, const Launch& L, const Workspace& W, int n_cu,
-                           const LaunchConfig& cfg, const ChunkSpan& sp, uint64_t c,
-                           uint32_t* surv, hipStream_t stream) {
-    const bool sort = sp.sort && W.key && W.hist;
+// Pre-roll of one chunk, first half: the survivor bitmap `bits` (and each survivor's time bucket
+// in `key` when the chunk's survivors are sorted by time).
+static void preroll_generate(const DevParams* dparams, const Launch& L, int n_cu,
+                             const LaunchConfig& cfg, const ChunkSpan& sp,
+                             unsigned long long* bits, uint8_t* key, hipStream_t stream) {
     const uint64_t want = (sp.len + kGenRange - 1) / kGenRange;
     const uint64_t cap = (uint64_t)n_cu * cfg.generate_per_cu;
     const dim3 gg((unsigned)(want < cap ? want : cap));
-    uint8_t* key = sort ? W.key : (uint8_t*)nullptr;
     const bool ghost = (L.flags & PHX_F_GHOSTS) != 0;
     if (sp.src >= 0) {
         const auto gk = ghost ? generate_kernel<true, true> : generate_kernel<true, false>;
         hipLaunchKernelGGL(gk, gg, dim3(kBlock), 0, stream, dparams, L, sp.begin, sp.len,
-                           L.src_begin + sp.src, sp.first, W.bits, key);
+                           L.src_begin + sp.src, sp.first, bits, key);
     } else {
         const auto gk = ghost ? generate_kernel<false, true> : generate_kernel<false, false>;
         hipLaunchKernelGGL(gk, gg, dim3(kBlock), 0, stream, dparams, L, sp.begin, sp.len, 0,
-                           (uint64_t)0, W.bits, key);
+                           (uint64_t)0, bits, key);
     }
-    const uint64_t n_words = (sp.len + 63) / 64;
-    const unsigned nb = (unsigned)((n_words + kCompactWords - 1) / kCompactWords);
-    if (sort) {
-        hipLaunchKernelGGL(bucket_count, dim3(nb), dim3(kBlock), 0, stream,
-                           (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words, W.hist);
-        hipLaunchKernelGGL(bucket_scatter, dim3(nb), dim3(kBlock), 0, stream,
-                           (const unsigned long long*)W.bits, (const uint8_t*)W.key, n_words,
-                           (const unsigned int*)W.hist, surv, W.counts + c);
-        return;
-    }
-    hipLaunchKernelGGL(compact_count, dim3(nb), dim3(kBlock), 0, stream,
-                       (const unsigned long long*)W.bits, n_words, W.bsum);
-    hipLaunchKernelGGL(compact_scatter, dim3(nb), dim3(kBlock), 0, stream,
-                       (const unsigned long long*)W.bits, n_words, (const unsigned int*)W.bsum,
-                       surv, W.counts + c);
 }
 
-// Chunks are pipelined over two streams when the pipe gives a second one: the bandwidth-bound
-// sky stage runs on `stream` and the arithmetic-bound pre-roll and optics stage on pipe.aux, in
-// the order pre-roll(0), pre-roll(1), optics(0), pre-roll(2), optics(1), ..., so the two kinds
-// of work share the compute units.  Survivor lists and states alternate between two buffers;
-// events order the hand-offs (pre-roll -> sky -> optics, and state reuse), the host issues every
-// event record before the waits on it, and the caller's stream waits for the last optics stage
-// before returning work to it.  Without a second stream each chunk's stages run in order on
-// `stream`.
+// Second half: the survivor list (in photon order, or sorted by time bucket when key is given)
+// and its count.
+static void preroll_compact(const Workspace& W, const ChunkSpan& sp, uint64_t c,
+                            const unsigned long long* bits, const uint8_t* key, uint32_t* surv,
+                            hipStream_t stream) {
+    const uint64_t n_words = (sp.len + 63) / 64;
+    if (key) {
+        const unsigned nbb = (unsigned)((n_words + kBucketWords - 1) / kBucketWords);
+        // hist: [nbb][buckets] counts, then [nbb][buckets] prefixes, then [buckets] totals
+        unsigned int* pre = W.hist + (uint64_t)nbb * kTimeBuckets;
+        unsigned int* tot = pre + (uint64_t)nbb * kTimeBuckets;
+        hipLaunchKernelGGL(bucket_count, dim3(nbb), dim3(kBlock), 0, stream, bits, key, n_words,
+                           W.hist);
+        hipLaunchKernelGGL(bucket_scan, dim3(kTimeBuckets), dim3(kBlock), 0, stream,
+                           (const unsigned int*)W.hist, nbb, pre, tot);
+        hipLaunchKernelGGL(bucket_scatter, dim3(nbb), dim3(kBlock), 0, stream, bits, key, n_words,
+                           (const unsigned int*)pre, (const unsigned int*)tot, surv, W.counts + c);
+        return;
+    }
+    const unsigned nb = (unsigned)((n_words + kCompactWords - 1) / kCompactWords);
+    hipLaunchKernelGGL(compact_count, dim3(nb), dim3(kBlock), 0, stream, bits, n_words, W.bsum);
+    hipLaunchKernelGGL(compact_scatter, dim3(nb), dim3(kBlock), 0, stream, bits, n_words,
+                       (const unsigned int*)W.bsum, surv, W.counts + c);
+}
+
+// Chunks are pipelined over two streams when the pipe gives a second one: the arithmetic-bound
+// pre-roll bitmap and optics stage run on pipe.aux, in the order pre-roll(0), pre-roll(1),
+// optics(0), pre-roll(2), optics(1), ..., and the survivor compaction and the bandwidth-bound
+// sky stage on `stream`, so the two kinds of work share the compute units and neither stream
+// carries much more than the other.  Bitmaps, time keys, survivor lists and states alternate
+// between two buffers; events order the hand-offs (bitmap -> compaction and sky -> optics, and
+// buffer reuse: a chunk's compaction waits for the optics stage two chunks back, and its bitmap
+// is rewritten only by the pre-roll issued after the optics stage that follows the sky stage
+// that read it), the host issues every event record before the waits on it, and the caller's
+// stream waits for the last optics stage before returning work to it.  Without a second stream
+// each chunk's stages run in order on `stream`.
 namespace {
 struct Stages {
     const DevParams* dparams;
@@ -2584,25 +2618,38 @@ struct Stages {
     hipStream_t arith() const { return piped() ? pipe.aux : stream; }
     uint32_t* surv_buf(uint64_t c) const { return W.survivors + (piped() ? c % 2 : 0) * W.chunk; }
     double* state_buf(uint64_t c) const { return W.state + (piped() ? c % 2 : 0) * 7 * W.chunk; }
+    unsigned long long* bits_buf(uint64_t c) const {
+        return W.bits + (piped() ? c % 2 : 0) * ((W.chunk + 63) / 64);
+    }
+    // time keys of chunk c, or null when its survivors keep photon order
+    uint8_t* key_buf(uint64_t c) const {
+        return (W.plan[c].sort && W.key && W.hist) ? W.key + (piped() ? c % 2 : 0) * W.chunk
+                                                   : nullptr;
+    }
     const uint32_t* surv(uint64_t c) const { return preroll() ? surv_buf(c) : nullptr; }
     const unsigned int* cnt(uint64_t c) const { return preroll() ? W.counts + c : nullptr; }
 
-    // pre-roll of chunk c (survivor list and count)
+    // pre-roll bitmap of chunk c
     void pre(uint64_t c) const {
         const hipStream_t s = arith();
         if (preroll()) {
             mark(0, 0, s);
-            launch_preroll(dparams, L, W, n_cu, cfg, W.plan[c], c, surv_buf(c), s);
+            preroll_generate(dparams, L, n_cu, cfg, W.plan[c], bits_buf(c), key_buf(c), s);
             mark(0, 1, s);
         }
         if (piped()) (void)hipEventRecord(ev(0, c), s);
     }
-    // sky stage of chunk c on `stream`
+    // survivor compaction and sky stage of chunk c on `stream`
     void sky(uint64_t c, unsigned long long* ft) const {
         const ChunkSpan& sp = W.plan[c];
         if (piped()) {
             (void)hipStreamWaitEvent(stream, ev(0, c), 0);
             if (c >= 2) (void)hipStreamWaitEvent(stream, ev(2, c - 2), 0);
+        }
+        if (preroll()) {
+            mark(0, 0, stream);
+            preroll_compact(W, sp, c, bits_buf(c), key_buf(c), surv_buf(c), stream);
+            mark(0, 1, stream);
         }
         const uint64_t want = (sp.len + kBlock - 1) / kBlock;
         const uint64_t fcap = (uint64_t)n_cu * cfg.front_per_cu;
