@@ -83,8 +83,8 @@ enum {
     /* Per-photon physics beyond the core path; each needs phx_load_physics.  With PHX_F_DOME,
        PHX_F_HALO or PHX_F_SPIDER the pre-roll keeps every pupil sample (the kicks at the
        telescope entrance have no bound on the displacement at the primary). */
-    PHX_F_AEROSOL = 1u << 4,    /* aerosol extinction (section 2.3.2)                      */
-    PHX_F_DISPERSION = 1u << 5, /* atmospheric dispersion (section 2.3.2)                  */
+    PHX_F_AEROSOL = 1u << 4,    /* aerosol extinction (section 2.3.3)                      */
+    PHX_F_DISPERSION = 1u << 5, /* atmospheric dispersion (section 2.3.3)                  */
     PHX_F_DOME = 1u << 6,       /* dome seeing (section 2.4.2)                             */
     PHX_F_HALO = 1u << 7,       /* micro-roughness halo (section 2.4.2)                    */
     PHX_F_SPIDER = 1u << 11,    /* spider shadow and edge diffraction (2.4.1-2.4.2)        */
@@ -173,9 +173,9 @@ typedef struct {
  * metres, all in the global frame of the prescription.  Random numbers: Philox block 7 (aerosol,
  * halo selection, halo azimuth, spider sign), block 8 (dome-seeing normal pair), stream 2 block t
  * (halo rejection trial t).
- *  - Aerosol (section 2.3.2): a photon survives with probability exp(-tau sec z),
+ *  - Aerosol (section 2.3.3): a photon survives with probability exp(-tau sec z),
  *    tau = tau0 (lambda / 500 nm)^gamma; else PHX_EXTINCT at the start plane.
- *  - Dispersion (section 2.3.2): the source direction moves by (R(lambda) - R(lambda0)) along
+ *  - Dispersion (section 2.3.3): the source direction moves by (R(lambda) - R(lambda0)) along
  *    (cos zenith_pa, sin zenith_pa) in (n_x, n_y), R = (n_air - 1) tan z with the Filippenko
  *    index of air at pressure, water-vapour pressure (mmHg) and temperature (deg C), the water
  *    term taken as a product with W.

@@ -589,7 +589,7 @@ double orc_field_sigma(const orc_scene* sc, double depth) {
 /* ------------------------------------------------------------------------------------------ */
 /* Per-photon physics beyond the core path.                                                    */
 
-/* Refractivity n - 1 of air (section 2.3.2, the Filippenko formula): lambda in metres (the
+/* Refractivity n - 1 of air (section 2.3.3, the Filippenko formula): lambda in metres (the
  * formula takes micrometres), pressure P and water-vapour pressure W in mmHg, temperature T in
  * deg C.  Reading: the printed water term ends in a division by W, which would make the term grow
  * without bound in dry air; it is taken as a product with W (humid air is less refractive).
@@ -952,7 +952,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
     ev->lambda = lam;
     const orc_extra* ex = &sc->ex;
     if (sc->physics & ORC_DISPERSION) {
-        /* Atmospheric dispersion (section 2.3.2): refraction (n_air - 1) tan z toward the zenith,
+        /* Atmospheric dispersion (section 2.3.3): refraction (n_air - 1) tan z toward the zenith,
          * less that of the reference wavelength lam0, applied to (n_x, n_y) like the Sersic
          * offset.  Reading: plane-parallel refraction R = (n - 1) tan z. */
         double dR = (orc_air_refractivity(lam, ex->pressure, ex->temperature, ex->water) -
@@ -1029,7 +1029,7 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
     double u7[4] = {0.5, 0.5, 0.5, 0.5};
     if (sc->physics & (ORC_AEROSOL | ORC_HALO | ORC_SPIDER)) draw(sc, si, photon, 7, 0, u7);
     if (sc->physics & ORC_AEROSOL) {
-        /* Aerosol opacity (section 2.3.2): tau = tau0 (lambda / 500 nm)^gamma at the zenith, times
+        /* Aerosol opacity (section 2.3.3): tau = tau0 (lambda / 500 nm)^gamma at the zenith, times
          * the airmass sec z along the path; the photon survives with probability exp(-tau).
          * Reading: the printed destruction probability exp(-tau) is the survival probability. */
         double tau = ex->tau0 * pow(lam / 500e-9, ex->gamma) / cos(ex->zenith);

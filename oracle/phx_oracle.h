@@ -47,7 +47,7 @@ typedef struct {
     uint64_t n_photons;
 } orc_source;
 
-/* Per-photon physics beyond the core path (sections 2.3.2, 2.4.1, 2.4.2); angles in radians,
+/* Per-photon physics beyond the core path (sections 2.3.2, 2.3.3, 2.4.1, 2.4.2); angles in radians,
  * lengths in metres.  Each part is used only when its physics bit is set. */
 typedef struct {
     double zenith, zenith_pa;          /* zenith angle; refraction moves (n_x, n_y) along

@@ -382,7 +382,7 @@ __device__ __forceinline__ double3 unit3(double3 v) {
     return make_double3(v.x * inv, v.y * inv, v.z * inv);
 }
 
-// Atmospheric dispersion (section 2.3.2): the direction moves by R(lambda) - R(lambda0) along the
+// Atmospheric dispersion (section 2.3.3): the direction moves by R(lambda) - R(lambda0) along the
 // zenith direction in (n_x, n_y), R = (n_air - 1) tan z, n_air from the Filippenko formula with
 // its pressure-temperature and water factors precomputed; the difference of the dry brackets and
 // of the water terms is taken before scaling, so no 1 + 3e-4 is formed.
@@ -478,7 +478,7 @@ __device__ __forceinline__ void second_kick(const DevParams& P, const Rng& rng, 
     }
 }
 
-// Aerosol extinction (section 2.3.2) and the spider (sections 2.4.1-2.4.2) at the telescope
+// Aerosol extinction (section 2.3.3) and the spider (sections 2.4.1-2.4.2) at the telescope
 // entrance.  status 0: the photon lives (a ray that passes the spider is moved to the vanes'
 // mid-height and turned); PHX_EXTINCT with p the start-plane point; PHX_OBSCURED with p the first
 // point along the ray inside a vane.

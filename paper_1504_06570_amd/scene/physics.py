@@ -1,7 +1,7 @@
 """Parameters of the per-photon physics beyond the core path (setup inputs only).
 
 Defaults: aerosol tau0 = 0.02, Gamma = -1.28 and the micro-roughness halo (f, n, r0) =
-(0.135, 3.5, 0.1 deg) are the paper's values (sections 2.3.2 and 2.4.2).  The rest are synthetic
+(0.135, 3.5, 0.1 deg) are the paper's values (sections 2.3.3 and 2.4.2).  The rest are synthetic
 site and hardware values: 30 deg zenith angle, a 2.7 km site (520 mmHg, 8 mmHg water, 12 C),
 dome seeing of 0.1 arcsec per axis, a halo truncated at 1 deg, a 50 nm field-free layer, a
 four-vane spider holding the secondary of the three-mirror telescope, and the second kick of the

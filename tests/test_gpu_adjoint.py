@@ -260,8 +260,17 @@ def test_central_differences_on_frozen_set(phx):
         adj[si, 3] = 2 * (dy[:, None] * Jy).sum(0) / N
         adj[si, 4] = ((dy[:, None] * Jx) + (dx[:, None] * Jy)).sum(0) / N
     a, b = adj * RANGE, fd * RANGE
-    scale = np.abs(b).max(axis=2, keepdims=True)
-    assert np.all(np.abs(a - b) <= 1e-4 * scale), np.abs(a - b).max() / scale.min()
+    # each entry to 1e-4 of itself, above a floor of 1e-6 of its row's largest entry (the central
+    # differences' truncation error, O(h^2) relative, and the rounding of the GPU positions over
+    # 2h are far below it; entries that vanish by symmetry meet the floor)
+    row = np.abs(b).max(axis=2, keepdims=True)
+    err = np.abs(a - b)
+    bound = 1e-4 * np.abs(b) + 1e-6 * row
+    worst = (err / bound).max()
+    print(f"adjoint vs central differences: worst error / bound {worst:.3f}, "
+          f"worst relative error of entries above 1e-3 of their row "
+          f"{(err / np.abs(b))[np.abs(b) > 1e-3 * row].max():.2e}")
+    assert np.all(err <= bound), worst
     tr.close()
 
 

@@ -32,7 +32,7 @@ def _block(scene, src, photons, block, stream=0):
 
 
 # ---------------------------------------------------------------------------------------------
-# Air index of the dispersion (section 2.3.2)
+# Air index of the dispersion (section 2.3.3)
 # ---------------------------------------------------------------------------------------------
 def test_air_refractivity_standard_air_values():
     """Dry air at 15 C and 760 mmHg has n - 1 = 2.77e-4 at the sodium D line (and the formula's
@@ -91,7 +91,7 @@ def test_dispersion_moves_the_image_along_the_zenith_direction():
 
 
 # ---------------------------------------------------------------------------------------------
-# Aerosol extinction (section 2.3.2)
+# Aerosol extinction (section 2.3.3)
 # ---------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("lam", [500e-9, 1000e-9])
 def test_aerosol_survival_is_exp_minus_tau_airmass(lam):
