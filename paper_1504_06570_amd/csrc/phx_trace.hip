@@ -175,6 +175,14 @@ __device__ __forceinline__ bool sag(const DevParams& P, const DevSurface& s, dou
 template <bool ZERN>
 __device__ int intersect(const DevParams& P, const DevSurface& s, const double q[3],
                          const double d[3], double& l, double& gx, double& gy, int& iters) {
+    if (s.c == 0.0 && s.asphere == 0 && !(ZERN && s.zernike)) {
+        // a plane (the conic root below with c = 0: l = q_z / -d_z), slope zero
+        if (d[2] == 0.0) return PHX_MISSED;
+        l = -q[2] * rcp_fast(d[2]);
+        gx = 0.0;
+        gy = 0.0;
+        return 0;
+    }
     const double A = s.c * (d[0] * d[0] + d[1] * d[1] + s.kappa1 * d[2] * d[2]);
     const double B = s.c * (q[0] * d[0] + q[1] * d[1] + s.kappa1 * q[2] * d[2]) - d[2];
     const double C = s.c * (q[0] * q[0] + q[1] * q[1] + s.kappa1 * q[2] * q[2]) - 2.0 * q[2];
@@ -781,8 +789,12 @@ __device__ __forceinline__ int hit_geometry(const DevParams& P, int k, const dou
     h.q[0] += h.d[0] * l; h.q[1] += h.d[1] * l; h.q[2] += h.d[2] * l;
     const double rq2 = h.q[0] * h.q[0] + h.q[1] * h.q[1];
     if (rq2 < s.r_in2 || rq2 > s.r_out2) return PHX_VIGNETTED;
-    const double inv = rsq_fast(gx * gx + gy * gy + 1.0);
-    h.N[0] = -gx * inv; h.N[1] = -gy * inv; h.N[2] = inv;
+    if (s.c == 0.0 && s.asphere == 0 && !(ZERN && s.zernike)) {
+        h.N[0] = 0.0; h.N[1] = 0.0; h.N[2] = 1.0;   // a plane
+    } else {
+        const double inv = rsq_fast(gx * gx + gy * gy + 1.0);
+        h.N[0] = -gx * inv; h.N[1] = -gy * inv; h.N[2] = inv;
+    }
     h.dn = h.d[0] * h.N[0] + h.d[1] * h.N[1] + h.d[2] * h.N[2];
     if (h.dn > 0.0) { h.N[0] = -h.N[0]; h.N[1] = -h.N[1]; h.N[2] = -h.N[2]; h.dn = -h.dn; }
     return 0;
