@@ -265,7 +265,7 @@ def gradient_leg(steps):
         "adjoint_forward_ratio": ms_a / ms_f,
         "forward_photons_per_s": total / (ms_f * 1e-3),
         "adjoint_photons_per_s": total / (ms_a * 1e-3),
-        "adjoint_stage_ms": {k: kt[k] / steps for k in ("generate", "front", "back")},
+        "adjoint_stage_ms": {k: kt[k] / steps for k in ("generate", "compact", "front", "back")},
     }
 
 
@@ -325,8 +325,8 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
         "extinct_per_step": float(tab[phx.EXTINCT].sum()),
         "dead_per_step": float(tab[phx.DEAD].sum()),
         "obscured_per_step": float(tab[phx.OBSCURED].sum()),
-        "stage_ms_per_step": {k: kt[k] / steps for k in ("generate", "front", "back")},
-        "stage_ms_single_stream": {k: kti[k] for k in ("generate", "front", "back")},
+        "stage_ms_per_step": {k: kt[k] / steps for k in ("generate", "compact", "front", "back")},
+        "stage_ms_single_stream": {k: kti[k] for k in ("generate", "compact", "front", "back")},
         "front_kernel_single_stream": {"bound": "hbm", "achieved": f_gbs, "peak": PEAK_HBM_GBS,
                                        "unit": "GB/s", "frac": f_gbs / PEAK_HBM_GBS,
                                        "launch_ms": f_ms},
@@ -429,8 +429,8 @@ def hybrid_leg(steps, n_ph, core_ms):
         "cost_vs_core": ms / core_ms,
         "traced_per_step": traced,
         "detected_per_step": float(tab[phx.DETECTED].sum()),
-        "stage_ms_per_step": {k: kt[k] / steps for k in ("generate", "front", "back")},
-        "stage_ms_single_stream": {k: kti[k] for k in ("generate", "front", "back")},
+        "stage_ms_per_step": {k: kt[k] / steps for k in ("generate", "compact", "front", "back")},
+        "stage_ms_single_stream": {k: kti[k] for k in ("generate", "compact", "front", "back")},
         "front_kernel_single_stream": {"bound": "hbm", "achieved": f_gbs, "peak": PEAK_HBM_GBS,
                                        "unit": "GB/s", "frac": f_gbs / PEAK_HBM_GBS,
                                        "launch_ms": f_ms},
@@ -645,7 +645,7 @@ def main():
                 "for the optics stage; that traffic comes from splitting the trace into kernels "
                 "and is not in the algorithmic bytes",
     }
-    stage_ms = {k: kt[k] / args.steps for k in ("generate", "front", "back")}
+    stage_ms = {k: kt[k] / args.steps for k in ("generate", "compact", "front", "back")}
     extra = {}
     # The timed steps overlap each chunk's optics stage with the next chunk's sky stage, so the
     # per-launch durations above include time shared with the other kernel.  One more step with
@@ -668,7 +668,7 @@ def main():
     extra["roofline_pipelined"] = pipelined
     extra["roofline_single_stream"] = iso
     extra["implementation_traffic"] = implementation
-    extra["stage_ms_single_stream"] = {k: kti[k] for k in ("generate", "front", "back")}
+    extra["stage_ms_single_stream"] = {k: kti[k] for k in ("generate", "compact", "front", "back")}
     if not args.no_cull and not args.no_compare:
         # the same step without the pre-roll (every photon traced until its fate)
         nc_img = tr.new_image()

@@ -511,9 +511,10 @@ phx_status phx_read_image(phx_ctx ctx, const uint32_t* image_dev, uint32_t* imag
 /* Kernel timing for profiling.  While on, phx_trace brackets each kernel it launches with HIP
  * events on the trace stream; phx_get_timing waits for them and returns the accumulated
  * milliseconds per kernel kind since timing was switched on:
- *   out[0] pre-roll (generate)   out[1] sky + atmosphere (front)   out[2] optics + silicon (back)
- *   out[3] number of chunks launched.
- * n is the capacity of out (at most 4 values are written).  Switching on resets the totals.
+ *   out[0] pre-roll bitmap (generate)   out[1] sky + atmosphere (front)
+ *   out[2] optics + silicon (back)      out[3] number of chunks launched
+ *   out[4] pre-roll survivor compaction (ordered or by time bucket).
+ * n is the capacity of out (at most 5 values are written).  Switching on resets the totals.
  * Errors: PHX_ERR_INVALID, PHX_ERR_HIP. */
 phx_status phx_set_timing(phx_ctx ctx, int32_t on);
 phx_status phx_get_timing(phx_ctx ctx, double* out_host, int32_t n);

@@ -65,8 +65,8 @@ struct phx_ctx_s {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_pairs;   // kind, (start, stop)
     size_t ev_used = 0;
-    long pending_start[3] = {-1, -1, -1};
-    double timing_ms[3] = {0, 0, 0};
+    long pending_start[4] = {-1, -1, -1, -1};
+    double timing_ms[4] = {0, 0, 0, 0};   // pre-roll bitmap, sky, optics, compaction
     double timing_chunks = 0;
     // launch shape, prefix-table cache, captured graphs (phx_trace_batched)
     phx::LaunchConfig cfg;
@@ -1818,7 +1818,7 @@ phx_status phx_set_timing(phx_ctx c, int32_t on) {
     c->timing = on != 0;
     c->ev_pairs.clear();
     c->ev_used = 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         c->pending_start[k] = -1;
         c->timing_ms[k] = 0.0;
     }
@@ -1839,8 +1839,9 @@ phx_status phx_get_timing(phx_ctx c, double* out, int32_t n) {
     }
     c->ev_pairs.clear();
     c->ev_used = 0;
-    const double v[4] = {c->timing_ms[0], c->timing_ms[1], c->timing_ms[2], c->timing_chunks};
-    for (int i = 0; i < n && i < 4; ++i) out[i] = v[i];
+    const double v[5] = {c->timing_ms[0], c->timing_ms[1], c->timing_ms[2], c->timing_chunks,
+                         c->timing_ms[3]};
+    for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
     return PHX_OK;
 }
 

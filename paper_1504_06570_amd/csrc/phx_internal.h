@@ -252,7 +252,8 @@ constexpr uint32_t kBackExtra = PHX_F_AEROSOL | PHX_F_SPIDER | PHX_F_GHOSTS;
 // Optional per-kernel timing: events recorded before/after each kernel launch.
 struct Timing {
     bool on = false;
-    // event pairs per kernel kind (0 generate, 1 front, 2 back), appended per chunk
+    // event pairs per kernel kind (0 generate, 1 front, 2 back, 3 survivor compaction),
+    // appended per chunk
     void (*record)(void* self, int kind, int edge, hipStream_t stream) = nullptr;
     void* self = nullptr;
 };

@@ -515,10 +515,10 @@ class Tracer:
 
     def get_timing(self):
         """Accumulated kernel milliseconds since timing was switched on:
-        dict(generate, front, back, chunks)."""
-        out = (C.c_double * 4)()
-        self._check(self.L.phx_get_timing(self.ctx, out, 4))
-        return dict(generate=out[0], front=out[1], back=out[2], chunks=out[3])
+        dict(generate, front, back, chunks, compact)."""
+        out = (C.c_double * 5)()
+        self._check(self.L.phx_get_timing(self.ctx, out, 5))
+        return dict(generate=out[0], front=out[1], back=out[2], chunks=out[3], compact=out[4])
 
     def readout(self, image, params, stages=False, stream=None):
         """Readout chain of an electron image (int32/uint32 tensor [ny, nx] on the device):
