@@ -100,7 +100,11 @@ def traffic_from_profiles(n_launch_photons, kernel):
         return None
     if d.get("kernel_hash") != kernel_hash() or d.get("photons") != n_launch_photons:
         return None
-    return d.get("hbm_bytes_per_launch", {}).get(kernel)
+    # keys carry the template arguments of the instantiation (`front_kernel<false, false>`); the
+    # headline command launches one instantiation of each kernel
+    hbm = d.get("hbm_bytes_per_launch", {})
+    keys = [k for k in hbm if k == kernel or k.startswith(kernel + "<")]
+    return hbm[keys[0]] if len(keys) == 1 else None
 
 
 def cpu_model():
@@ -527,6 +531,102 @@ def gather_probe(footprints_mib=(64, 256, 1024, 2816), rows_per_launch=1 << 22, 
     print(json.dumps({"gather_probe": out}), flush=True)
 
 
+_KERNEL_NAME = None
+
+
+def kernel_short_name(name):
+    """`back_kernel<false, false, false>` from a demangled rocprofv3 kernel name."""
+    import re
+    global _KERNEL_NAME
+    if _KERNEL_NAME is None:
+        _KERNEL_NAME = re.compile(r"([A-Za-z_]\w*(?:<[^()]*>)?)\(")
+    m = _KERNEL_NAME.search(name)
+    return m.group(1) if m else name[:48]
+
+
+def summarize_stats(csv_path):
+    """Table of a rocprofv3 `--stats` kernel summary (its *_kernel_stats.csv): calls, average and
+    total duration per kernel, in milliseconds."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    agg = {}
+    for r in rows:
+        k = kernel_short_name(r["Name"])
+        a = agg.setdefault(k, [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"]) * 1e-6
+    tot = sum(a[1] for a in agg.values()) or 1.0
+    lines = [f"{'kernel':40s} {'calls':>7s} {'avg_ms':>9s} {'total_ms':>10s} {'pct':>6s}"]
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{k[:40]:40s} {n:7d} {t / n:9.4f} {t:10.2f} {100 * t / tot:6.2f}")
+    return "\n".join(lines)
+
+
+def _counter_rows(d):
+    """{(kernel, counter): [values per dispatch]} of a rocprofv3 `--pmc` run's directory."""
+    import csv
+    import glob
+    out = {}
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        for r in csv.DictReader(open(f)):
+            k = kernel_short_name(r.get("Kernel_Name") or r.get("Kernel-Name") or "")
+            out.setdefault((k, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(dirs, copy_dirs, photons, json_out):
+    """Per-dispatch means of the counters of several rocprofv3 `--pmc` runs of the headline command,
+    and the HBM bytes per launch from FETCH_SIZE and WRITE_SIZE scaled by what the same counters
+    read for a plain device copy of known size (the two `--copy-probe` runs).  Writes the JSON that
+    the benchmark's `traffic` field reads (keyed to the kernel source's hash) and returns a
+    table."""
+    rows = {}
+    for d in dirs:
+        for key, v in _counter_rows(d).items():
+            rows.setdefault(key, []).extend(v)
+    copy = {}
+    for d in copy_dirs:
+        for key, v in _counter_rows(d).items():
+            copy.setdefault(key, []).extend(v)
+    copy_bytes = float(1 << 30)
+    # the copy is the dispatch that fetches the most; its write counter is read on the same kernel
+    fk = max((k for k in copy if k[1] == "FETCH_SIZE"), key=lambda k: max(copy[k]))
+    fetch_kib = max(copy[fk])
+    write_kib = max(copy.get((fk[0], "WRITE_SIZE"), [0.0]))
+    fetch_factor = copy_bytes / 1024 / fetch_kib
+    write_factor = copy_bytes / 1024 / write_kib if write_kib else None
+    kernels = sorted({k for k, _ in rows})
+    mean = {k: {c: float(np.mean(v)) for (kk, c), v in rows.items() if kk == k} for k in kernels}
+    calls = {k: max(len(v) for (kk, _), v in rows.items() if kk == k) for k in kernels}
+    hbm = {}
+    for k, m in mean.items():
+        if "FETCH_SIZE" in m and "WRITE_SIZE" in m and write_factor:
+            hbm[k] = (m["FETCH_SIZE"] * fetch_factor + m["WRITE_SIZE"] * write_factor) * 1024
+    rec = {
+        "kernel_hash": kernel_hash(),
+        "photons": int(photons),
+        "calibration": {"copy_bytes_each_way": copy_bytes, "copy_kernel": fk[0],
+                        "copy_fetch_kib": fetch_kib, "copy_write_kib": write_kib,
+                        "fetch_factor": fetch_factor, "write_factor": write_factor},
+        "hbm_bytes_per_launch": hbm,
+        "counters_per_dispatch": mean,
+        "dispatches": calls,
+    }
+    with open(json_out, "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = [f"# copy calibration: {fk[0]} reads {fetch_kib:.0f} KiB FETCH_SIZE and writes "
+             f"{write_kib:.0f} KiB WRITE_SIZE for 1 GiB each way -> fetch factor "
+             f"{fetch_factor:.3f}, write factor {write_factor:.3f}", ""]
+    for k in sorted(kernels, key=lambda k: -hbm.get(k, 0.0)):
+        if not any(t in k for t in ("_kernel", "bucket_", "compact_")):
+            continue
+        lines.append(f"{k}   dispatches {calls[k]}" +
+                     (f"   HBM bytes per launch {hbm[k]:.4e}" if k in hbm else ""))
+        for c in sorted(mean[k]):
+            lines.append(f"    {c:28s} {mean[k][c]:.4e}")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -550,7 +650,29 @@ def main():
                          "hybrid atmosphere")
     ap.add_argument("--only", choices=("batched", "gradient"), default=None,
                     help="run one secondary leg alone and print its record (for profiling)")
+    ap.add_argument("--launch", default=None, metavar="G,F,B",
+                    help="fixed launch shape (pre-roll, sky and optics workgroups per compute "
+                         "unit) in place of the autotuner, so that a profile holds only the "
+                         "timed launches")
+    ap.add_argument("--no-single-stream", action="store_true",
+                    help="skip the step with both stages on one stream")
+    ap.add_argument("--summarize-stats", default=None, metavar="CSV",
+                    help="print the table of a rocprofv3 --stats kernel summary and exit")
+    ap.add_argument("--summarize-pmc", nargs="+", default=None, metavar="DIR",
+                    help="rocprofv3 --pmc output directories of the headline command: print "
+                         "per-dispatch counter means, write the HBM traffic summary and exit")
+    ap.add_argument("--copy-dirs", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="with --summarize-pmc: the two --copy-probe counter runs")
+    ap.add_argument("--pmc-json", default=PMC_SUMMARY)
     args = ap.parse_args()
+    if args.summarize_stats:
+        print(summarize_stats(args.summarize_stats))
+        return
+    if args.summarize_pmc:
+        if not args.copy_dirs:
+            raise SystemExit("bench.py: --summarize-pmc needs --copy-dirs")
+        print(summarize_pmc(args.summarize_pmc, args.copy_dirs, args.photons, args.pmc_json))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
@@ -583,7 +705,11 @@ def main():
     img = tr.new_image()
     stats = tr.new_stats()
     t_tune = time.perf_counter()
-    if args.no_autotune:
+    if args.launch:
+        g, f, b = (int(x) for x in args.launch.split(","))
+        tr.set_launch_config(generate_blocks_per_cu=g, front_blocks_per_cu=f, back_blocks_per_cu=b)
+        tuned = tr.launch_config()
+    elif args.no_autotune:
         tuned = tr.launch_config()
     else:
         tuned = tr.autotune(flags=flags)   # eager launches pipelined over two streams
@@ -650,25 +776,27 @@ def main():
     # The timed steps overlap each chunk's optics stage with the next chunk's sky stage, so the
     # per-launch durations above include time shared with the other kernel.  One more step with
     # the stages on a single stream gives each kernel's duration alone.
-    tr.set_launch_config(pipeline=0)
-    iso_stats = tr.new_stats()
-    tr.set_timing(True)
-    tr.trace(tr.new_image(), flags=flags, stats=iso_stats)
-    torch.cuda.synchronize()
-    kti = tr.get_timing()
-    tr.set_timing(False)
-    tr.set_launch_config(pipeline=1)
-    ci = max(kti["chunks"], 1.0)
-    iso = {}
-    for k, v in kinds.items():
-        ms_k = kti[k] / ci
-        a_k = v["work"] / (ms_k * 1e-3) * v["scale"]
-        iso[f"{k}_kernel"] = {"bound": v["bound"], "achieved": a_k, "peak": v["peak"],
-                              "unit": v["unit"], "frac": a_k / v["peak"], "launch_ms": ms_k}
     extra["roofline_pipelined"] = pipelined
-    extra["roofline_single_stream"] = iso
     extra["implementation_traffic"] = implementation
-    extra["stage_ms_single_stream"] = {k: kti[k] for k in ("generate", "compact", "front", "back")}
+    if not args.no_single_stream:
+        tr.set_launch_config(pipeline=0)
+        iso_stats = tr.new_stats()
+        tr.set_timing(True)
+        tr.trace(tr.new_image(), flags=flags, stats=iso_stats)
+        torch.cuda.synchronize()
+        kti = tr.get_timing()
+        tr.set_timing(False)
+        tr.set_launch_config(pipeline=1)
+        ci = max(kti["chunks"], 1.0)
+        iso = {}
+        for k, v in kinds.items():
+            ms_k = kti[k] / ci
+            a_k = v["work"] / (ms_k * 1e-3) * v["scale"]
+            iso[f"{k}_kernel"] = {"bound": v["bound"], "achieved": a_k, "peak": v["peak"],
+                                  "unit": v["unit"], "frac": a_k / v["peak"], "launch_ms": ms_k}
+        extra["roofline_single_stream"] = iso
+        extra["stage_ms_single_stream"] = {k: kti[k] for k in ("generate", "compact", "front",
+                                                               "back")}
     if not args.no_cull and not args.no_compare:
         # the same step without the pre-roll (every photon traced until its fate)
         nc_img = tr.new_image()
