@@ -502,33 +502,53 @@ def copy_probe():
     print(json.dumps({"copy_bytes_each_way": a.numel() * 4}))
 
 
-def gather_probe(footprints_mib=(64, 256, 1024, 2816), rows_per_launch=1 << 22, reps=20):
-    """Random 32-byte gathers (the size of one screen footprint record) over buffers of several
-    sizes: rows gathered per second, the memory system's rate for the sky stage's access pattern
-    (a reference for its roofline).  Uses torch's row gather, which also writes the gathered rows
-    contiguously (32 B per row, coalesced); prints one JSON line."""
+def gather_probe(footprints_mib=(4, 64, 256, 940, 2816), threads=1 << 24, reps=10):
+    """Random gathers of 32-byte records (one screen-cell record of the sky stage) over tables of
+    several sizes, by the probe kernel of libphx_probe.so: each thread makes 7 dependent rounds
+    of 1 or 3 independent gathers (the sky stage's 7 layers, one or all 3 screen scales in
+    flight).  940 MiB is the footprint of the seven finest screens, 2816 MiB that of all 21
+    screens of the headline workload.  Prints one JSON line: records per second and the rate in
+    128-byte lines (the L2 line each missing record brings in)."""
+    import ctypes as C
     import torch
-    out = []
-    g = torch.Generator(device="cuda").manual_seed(7)
+    from paper_1504_06570_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        raise SystemExit(f"bench.py: {B.PROBE_LIB} is not built (python -c 'import "
+                         "__graft_entry__ as g; g.build()')")
+    lib = C.CDLL(B.PROBE_LIB)
+    lib.probe_gather.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_int,
+                                 C.c_int, C.c_uint32, C.c_void_p]
+    lib.probe_gather.restype = C.c_int
+    stream = torch.cuda.current_stream()
+    out = torch.empty(threads, dtype=torch.int32, device="cuda")
+    rows = []
     for mib in footprints_mib:
-        n_rows = mib * (1 << 20) // 32
-        src = torch.ones((n_rows, 8), dtype=torch.float32, device="cuda")
-        idx = torch.randint(0, n_rows, (rows_per_launch,), device="cuda", generator=g)
-        dst = torch.empty((rows_per_launch, 8), dtype=torch.float32, device="cuda")
-        torch.index_select(src, 0, idx, out=dst)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            torch.index_select(src, 0, idx, out=dst)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out.append({"footprint_mib": mib, "rows": rows_per_launch, "ms": ms,
-                    "rows_per_s": rows_per_launch / (ms * 1e-3),
-                    "useful_GBps": rows_per_launch * 32 / (ms * 1e-3) * 1e-9})
-        del src, idx, dst
-    print(json.dumps({"gather_probe": out}), flush=True)
+        n_rec = mib * (1 << 20) // 32
+        table = torch.zeros(n_rec * 8, dtype=torch.int32, device="cuda")
+        for width in (1, 3):
+            def run(seed):
+                rc = lib.probe_gather(table.data_ptr(), n_rec, out.data_ptr(), threads, 7, width,
+                                      seed, C.c_void_p(stream.cuda_stream))
+                if rc != 0:
+                    raise SystemExit(f"bench.py: probe_gather returned {rc}")
+            run(1)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for r in range(reps):
+                run(2 + r)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            recs = threads * 7 * width
+            rows.append({"footprint_mib": mib, "in_flight_per_thread": width, "records": recs,
+                         "ms": ms, "records_per_s": recs / (ms * 1e-3),
+                         "record_GBps": recs * 32 / (ms * 1e-3) * 1e-9,
+                         "line_GBps": recs * 128 / (ms * 1e-3) * 1e-9})
+            print(f"# gather {mib} MiB x{width}: {rows[-1]['records_per_s']:.3e} records/s",
+                  file=sys.stderr, flush=True)
+        del table
+    print(json.dumps({"gather_probe": rows}), flush=True)
 
 
 _KERNEL_NAME = None
@@ -639,8 +659,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--gather-probe", action="store_true",
-                    help="random 32-byte gathers over buffers of 64 MiB - 2.75 GiB (reference "
-                         "rate of the sky stage's access pattern)")
+                    help="random 32-byte record gathers over tables of 4 MiB - 2.75 GiB (the "
+                         "memory system's rate for the sky stage's access pattern)")
     ap.add_argument("--no-compare", action="store_true", help="skip the run without the pre-roll")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-source batched leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint leg")

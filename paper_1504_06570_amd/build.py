@@ -1,4 +1,4 @@
-"""Build the HIP library libphx.so for gfx950 (in-tree)."""
+"""Build the HIP library libphx.so for gfx950 (in-tree), and the benchmark's probe library."""
 from __future__ import annotations
 
 import os
@@ -15,14 +15,24 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+# the benchmark's memory-system probe, a library of its own (not part of the trace)
+PROBE_LIB = os.path.join(HERE, "libphx_probe.so")
+PROBE_SOURCES = ["probe_gather.hip"]
+
+
+def _link(lib, sources, verbose):
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = lib + ".tmp"
     cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    _link(LIB, SOURCES, verbose)
+    _link(PROBE_LIB, PROBE_SOURCES, verbose)
     return LIB
 
 

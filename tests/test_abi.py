@@ -71,3 +71,20 @@ def test_create_without_gpu_is_an_error():
     assert P.lib().phx_last_error(None) == b"null context"
     assert P.lib().phx_trace_batched(None, None, None) == -1
     assert P.lib().phx_autotune(None, None, None, None) == -1
+
+
+def test_probe_library_exports_and_checks_arguments():
+    """The benchmark's gather probe (a library of its own) loads on the CPU, and refuses invalid
+    arguments before it touches a device."""
+    from paper_1504_06570_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        pytest.skip("probe library not built")
+    L = ctypes.CDLL(B.PROBE_LIB)
+    f = L.probe_gather
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                  ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    assert f(None, 16, None, 1, 7, 1, 0, None) == -1        # null table and output
+    assert f(16, 16, 16, 1, 7, 5, 0, None) == -1            # more than four gathers in flight
+    assert f(24, 16, 16, 1, 7, 1, 0, None) == -1            # table not 16-byte aligned
+    assert f(16, 1 << 33, 16, 1, 7, 1, 0, None) == -1       # more records than 32-bit indices
