@@ -426,7 +426,7 @@ phx_status phx_trace_noalloc(phx_ctx ctx, const phx_trace_args* args, void* stre
  * the survivor compaction and sky stage of the next chunk on the caller's stream (ordered by
  * events; the caller's stream waits for the last optics stage), 0 = everything on the caller's
  * stream.  Launches captured by phx_trace_batched always run on the capturing stream.
- * Defaults: 26, 16, 64, 3, 0, 1. */
+ * Defaults: 26, 16, 48, 2, 0, 1 (the shape the autotuner settles on for one star of 1e9 photons). */
 typedef struct {
     int32_t chunk_log2;
     int32_t generate_blocks_per_cu, front_blocks_per_cu, back_blocks_per_cu;

@@ -238,8 +238,8 @@ inline uint64_t bucket_groups(uint64_t n) {
 // device counter).
 struct LaunchConfig {
     int generate_per_cu = 16;
-    int front_per_cu = 64;
-    int back_per_cu = 3;
+    int front_per_cu = 48;
+    int back_per_cu = 2;
     int dynamic = 0;
     int pipeline = 1;
 };

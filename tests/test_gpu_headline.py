@@ -1,7 +1,8 @@
 """The benchmark's own workload against the oracle: the full configuration (one star, seven
 frozen-flow layers of 2048^2 screens at 1 m / 10 cm / 1 cm, the telescope with coatings, silicon,
 diffusion, the 4096^2 chip), the default launch shape the benchmark settles on (chunks of 2^26
-photons, the two-stream pipeline, 16 / 64 / 3 workgroups per compute unit), the pre-roll on, three
+photons, the two-stream pipeline, 16 / 48 / 2 workgroups per compute unit, the shape the autotuner
+settles on), the pre-roll on, three
 chunks of photons.  Every 1000th photon of the launch is recorded and traced by the oracle alone,
 by its index; they must agree photon by photon and pixel by pixel."""
 import numpy as np
@@ -29,6 +30,8 @@ def test_headline_configuration_sampled_against_the_oracle(phx):
     tr = phx.Tracer(s)
     cfg = tr.launch_config()
     assert cfg["chunk_log2"] == 26 and cfg["pipeline"] == 1
+    assert (cfg["generate_blocks_per_cu"], cfg["front_blocks_per_cu"],
+            cfg["back_blocks_per_cu"]) == (16, 48, 2)
     n, stride = 3 << 26, 1000
     flags = int(s.physics) | phx.F_CULL
     stats = tr.new_stats()
