@@ -58,8 +58,9 @@ struct phx_ctx_s {
     uint64_t counts_cap = 0;
     double* d_state = nullptr;           // start-plane state of one chunk [7][ws_chunk]
     uint64_t ws_chunk = 0;
-    double* d_ghost_q = nullptr;         // ghost queues of the optics kernel, one per wavefront
-    uint64_t ghost_waves = 0;
+    double* d_ghost = nullptr;           // ghost list of a chunk (with ghosts) and its counters
+    uint64_t ghost_cap = 0;
+    unsigned long long* d_ghost_ctr = nullptr;
     // kernel timing (phx_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -455,7 +456,8 @@ void phx_destroy(phx_ctx c) {
     free_dev(c->d_survivors);
     free_dev(c->d_counts);
     free_dev(c->d_state);
-    free_dev(c->d_ghost_q);
+    free_dev(c->d_ghost);
+    free_dev(c->d_ghost_ctr);
     free_dev(c->d_tiles);
     free_dev(c->d_tape);
     free_dev(c->d_partial);
@@ -1307,22 +1309,24 @@ phx_status prepare(phx_ctx c, const phx_trace_args* a, hipStream_t st, phx::Laun
                        c->d_bsum, c->d_key, c->d_hist, c->plan.data(), (uint64_t)c->plan.size(),
                        2};
     if (a->flags & PHX_F_GHOSTS) {
-        // one queue per wavefront of the largest optics grid of this launch shape; grows only
-        const uint64_t waves = (uint64_t)c->n_cu * c->cfg.back_per_cu * (phx::kThreads / 64);
-        if (waves > c->ghost_waves) {
+        // every traced photon of a chunk may leave one ghost start: a list of chunk entries
+        // (14 doubles each; 7.5 GB for chunks of 2^26 photons); grows only
+        if (chunk > c->ghost_cap || !c->d_ghost_ctr) {
             hipError_t e = hipStreamSynchronize(st);
             if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-            free_dev(c->d_ghost_q);
-            c->ghost_waves = 0;
+            free_dev(c->d_ghost);
+            c->ghost_cap = 0;
             c->graphs_clear();
-            e = hipMalloc((void**)&c->d_ghost_q,
-                          waves * phx::kGhostQ * phx::kGhostFields * sizeof(double));
-            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "ghost queues: %s",
+            e = hipMalloc((void**)&c->d_ghost, chunk * phx::kGhostFields * sizeof(double));
+            if (e == hipSuccess && !c->d_ghost_ctr)
+                e = hipMalloc((void**)&c->d_ghost_ctr, 2 * sizeof(unsigned long long));
+            if (e != hipSuccess) return fail(c, PHX_ERR_NOMEM, "ghost list: %s",
                                              hipGetErrorString(e));
-            c->ghost_waves = waves;
+            c->ghost_cap = chunk;
         }
-        W.ghost_q = c->d_ghost_q;
-        W.ghost_waves = c->ghost_waves;
+        W.ghost_list = c->d_ghost;
+        W.ghost_cap = c->ghost_cap;
+        W.ghost_ctr = c->d_ghost_ctr;
     }
     if (c->cfg.pipeline) {
         if (!c->aux_stream) {
@@ -1385,7 +1389,7 @@ phx_status phx_trace_noalloc(phx_ctx c, const phx_trace_args* a, void* stream) {
     if (r != PHX_OK) return r;
     if (a->flags & PHX_F_GHOSTS)
         return fail(c, PHX_ERR_INVALID,
-                    "phx_trace_noalloc does not trace ghosts (their queues need context memory)");
+                    "phx_trace_noalloc does not trace ghosts (their list needs context memory)");
     if (L.n_src > phx::kNoAllocMaxSources)
         return fail(c, PHX_ERR_CAPACITY, "phx_trace_noalloc traces at most %d sources, not %d",
                     phx::kNoAllocMaxSources, L.n_src);
@@ -1445,9 +1449,9 @@ phx_status phx_trace_batched(phx_ctx c, const phx_trace_args* a, void* stream) {
     std::string key((const char*)&L, sizeof(L));
     auto put = [&key](const void* p, size_t n) { key.append((const char*)p, n); };
     const void* ptrs[] = {W.survivors, W.counts, W.state, W.tiles, W.bits, W.bsum, W.key, W.hist,
-                          W.ghost_q};
+                          W.ghost_list, W.ghost_ctr};
     put(ptrs, sizeof(ptrs));
-    const uint64_t sizes[] = {W.n_chunks, W.chunk, W.n_plan, (uint64_t)W.buffers, W.ghost_waves};
+    const uint64_t sizes[] = {W.n_chunks, W.chunk, W.n_plan, (uint64_t)W.buffers, W.ghost_cap};
     put(sizes, sizeof(sizes));
     put(W.plan, W.n_plan * sizeof(phx::ChunkSpan));
     put(&c->cfg, sizeof(c->cfg));

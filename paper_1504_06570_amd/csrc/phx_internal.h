@@ -167,8 +167,9 @@ struct Workspace {
     uint64_t n_plan;
     int buffers;               // bitmaps, keys, survivors and states hold this many chunks
                                // (1 or 2)
-    double* ghost_q = nullptr; // [ghost_waves][kGhostFields][kGhostQ] queues of the optics
-    uint64_t ghost_waves = 0;  // kernel with ghosts, one per wavefront of its grid
+    double* ghost_list = nullptr;          // [kGhostFields][ghost_cap] ghost starts of a chunk
+    uint64_t ghost_cap = 0;                 // (with ghosts: at least chunk entries)
+    unsigned long long* ghost_ctr = nullptr; // [2] entries listed, entries claimed
 };
 // Workspace of phx_trace_noalloc: a file-scope device array of kScratchBytes on each GPU (its
 // address is looked up once per device when a context is created), carved into the buffers of
@@ -212,10 +213,8 @@ hipError_t scratch_address(int device, void** out);
 hipError_t launch_prefix(const DevSource* src, int src_begin, int n_src, uint64_t* prefix,
                          int32_t* guide, uint64_t n_blocks, uint32_t shift, hipStream_t stream);
 
-// Ghost starts queued per wavefront of the optics kernel with ghosts (drained once more than
-// kGhostQ - 64 wait; a pass adds up to 64), and the 8-byte fields of one entry.
-constexpr int kGhostQ = 512;
-constexpr int kGhostFields = 15;
+// 8-byte fields of one entry of the ghost list (the optics kernel's ghost starts of a chunk).
+constexpr int kGhostFields = 14;
 
 // Second stream and events for pipelining chunks (aux null: everything on the caller's stream).
 struct Pipe {

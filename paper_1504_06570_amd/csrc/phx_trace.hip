@@ -908,65 +908,77 @@ __device__ __forceinline__ bool entrance(const DevParams& P, const Launch& L, co
 // surface (wc_block = -1: none).
 // A ghost branch met in the surface loop, kept for later: the hit at the reflecting surface k
 // (k = -1: none) and the refractive index of the medium the photon travelled in.  The optics
-// kernel queues it and runs the branch once a wavefront's worth is waiting, so that branches
-// started at different surfaces, or by different photons, run together.
+// kernel appends it to the chunk's ghost list; a second pass of the kernel runs the branches,
+// started at different surfaces or by different photons, together.
 struct GhostStart {
     Hit h;
     int k;
     double n_cur;
 };
 
-// Per-wavefront queue of ghost starts in device memory (optics kernel with ghosts): kGhostQ
-// entries of kGhostFields 8-byte fields (sizes in the internal header), field-major (field f of
-// entry e at f * kGhostQ + e):
-// the hit (q, d, N, dn, l), the index of the medium, the wavelength, (surface << 32 | Newton
-// steps so far) and the photon's position in the survivor list.
-__device__ __forceinline__ void ghost_put(double* q, int e, const GhostStart& gs, double lam,
-                                          uint32_t r, int newton) {
-    double* f = q + e;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        f[(0 + i) * kGhostQ] = gs.h.q[i];
-        f[(3 + i) * kGhostQ] = gs.h.d[i];
-        f[(6 + i) * kGhostQ] = gs.h.N[i];
-    }
-    f[9 * kGhostQ] = gs.h.dn;
-    f[10 * kGhostQ] = gs.h.l;
-    f[11 * kGhostQ] = gs.n_cur;
-    f[12 * kGhostQ] = lam;
-    f[13 * kGhostQ] = __longlong_as_double((long long)(((uint64_t)(uint32_t)gs.k << 32) |
-                                                       (uint32_t)newton));
-    f[14 * kGhostQ] = __longlong_as_double((long long)r);
-}
-__device__ __forceinline__ void ghost_get(const double* q, int e, GhostStart& gs, double& lam,
-                                          uint32_t& r, int& newton) {
+// The chunk's list of ghost starts in device memory: cap entries of kGhostFields 8-byte fields,
+// field-major (field f of entry e at f * cap + e): the hit (q, d, N, dn), the index of the
+// medium, the wavelength, (surface << 32 | Newton steps so far) and the photon's position in the
+// survivor list.  ghost_get reads one entry.
+__device__ __forceinline__ void ghost_get(const double* q, uint64_t cap, uint64_t e, GhostStart& gs,
+                                          double& lam, uint32_t& r, int& newton) {
     const double* f = q + e;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        gs.h.q[i] = f[(0 + i) * kGhostQ];
-        gs.h.d[i] = f[(3 + i) * kGhostQ];
-        gs.h.N[i] = f[(6 + i) * kGhostQ];
+        gs.h.q[i] = f[(0 + i) * cap];
+        gs.h.d[i] = f[(3 + i) * cap];
+        gs.h.N[i] = f[(6 + i) * cap];
     }
-    gs.h.dn = f[9 * kGhostQ];
-    gs.h.l = f[10 * kGhostQ];
-    gs.n_cur = f[11 * kGhostQ];
-    lam = f[12 * kGhostQ];
-    const uint64_t kn = (uint64_t)__double_as_longlong(f[13 * kGhostQ]);
+    gs.h.dn = f[9 * cap];
+    gs.h.l = 0.0;   // not used by the branch
+    gs.n_cur = f[10 * cap];
+    lam = f[11 * cap];
+    const uint64_t kn = (uint64_t)__double_as_longlong(f[12 * cap]);
     gs.k = (int)(kn >> 32);
     newton = (int)(uint32_t)kn;
-    r = (uint32_t)__double_as_longlong(f[14 * kGhostQ]);
+    r = (uint32_t)__double_as_longlong(f[13 * cap]);
 }
-// Appends the lanes holding a ghost start (gs.k >= 0) to the queue of gn entries; returns the
-// new count.  Every lane of the wavefront must call it; the stores are complete on return, so
-// that any lane of the wavefront may read the entries afterwards.
-__device__ __forceinline__ int ghost_push(double* q, int gn, const GhostStart& gs,
-                                          const Outcome& o, uint32_t r) {
+// Where the sequential pass leaves a lane's ghost start: the hit's fields are written to the
+// lane's column of the wavefront's LDS staging area at the reflecting surface (field i at
+// f[i * 64]), so that no register carries them out of the surface loop, and k records the
+// surface (-1: none).
+constexpr int kGhostStage = 11;   // q, d, N, dn, index of the medium
+struct GhostSink {
+    double* f;
+    int k;
+};
+__device__ __forceinline__ void ghost_stage(GhostSink* gs, const Hit& h, int k, double n_cur) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        gs->f[(0 + i) * 64] = h.q[i];
+        gs->f[(3 + i) * 64] = h.d[i];
+        gs->f[(6 + i) * 64] = h.N[i];
+    }
+    gs->f[9 * 64] = h.dn;
+    gs->f[10 * 64] = n_cur;
+    gs->k = k;
+}
+// Appends the lanes holding a ghost start (gs.k >= 0) to the list (ctr[0] counts the entries;
+// an entry beyond cap, which the list's size rules out, is not written).  Every lane of the
+// wavefront must call it.
+__device__ __forceinline__ void ghost_append(double* q, uint64_t cap, unsigned long long* ctr,
+                                             const GhostSink& gs, const Outcome& o, uint32_t r) {
     const bool pend = gs.k >= 0;
     const uint64_t pm = __ballot(pend);
-    if (pend) ghost_put(q, gn + __popcll(pm & ((1ull << __lane_id()) - 1ull)), gs, o.lam, r,
-                        o.newton);
-    __threadfence_block();
-    return gn + __popcll(pm);
+    if (!pm) return;
+    unsigned long long base = 0;
+    if (__lane_id() == 0) base = atomicAdd(&ctr[0], (unsigned long long)__popcll(pm));
+    base = __shfl(base, 0);
+    const uint64_t e = base + __popcll(pm & ((1ull << __lane_id()) - 1ull));
+    if (pend && e < cap) {
+        double* f = q + e;
+#pragma unroll
+        for (int i = 0; i < kGhostStage; ++i) f[i * cap] = gs.f[i * 64];
+        f[11 * cap] = o.lam;
+        f[12 * cap] = __longlong_as_double((long long)(((uint64_t)(uint32_t)gs.k << 32) |
+                                                       (uint32_t)o.newton));
+        f[13 * cap] = __longlong_as_double((long long)r);
+    }
 }
 
 template <bool ZERN, bool TAPE = false, bool GHOST = false>
@@ -974,7 +986,7 @@ __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch&
                                                const Optics& oc, Ray& ray, int k0, int k1,
                                                uint4& wc, int& wc_block, Outcome& o,
                                                double* tp = nullptr, uint64_t ts = 0,
-                                               GhostStart* gs = nullptr) {
+                                               GhostSink* gs = nullptr) {
     Hit h;
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
@@ -982,7 +994,7 @@ __device__ __forceinline__ bool trace_surfaces(const DevParams& P, const Launch&
         int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, k, ray.p, ray.n, oc.lc, wc, wc_block,
                                                 h, o.newton);
         if (GHOST && st == kGhostReflect) {   // GHOST callers pass gs
-            gs->h = h; gs->k = k; gs->n_cur = ray.n_cur;
+            ghost_stage(gs, h, k, ray.n_cur);
             return false;
         }
         if (st == 0) {
@@ -1090,9 +1102,13 @@ __device__ __forceinline__ void ghost_begin(const DevParams& P, Hit h, int k, do
 template <bool ZERN>
 __device__ __forceinline__ bool ghost_step(const DevParams& P, const Launch& L, const Rng& rng,
                                         const Optics& oc, GhostRay& gr, Outcome& o) {
-    // the nearest surface ahead
+    // the nearest surface ahead; the search keeps the best candidate's frame coordinates, path
+    // length, slope and Newton steps, so that its hit is finished without intersecting again
     double best = INFINITY;
     int bk = -1;
+    Hit h;
+    double bgx = 0.0, bgy = 0.0;
+    int bit = 0;
     if (gr.inter < kGhostMax) {
 #pragma unroll 1
         for (int j = 0; j < P.n_surf; ++j) {
@@ -1115,6 +1131,11 @@ __device__ __forceinline__ bool ghost_step(const DevParams& P, const Launch& L, 
             if (intersect<ZERN>(P, s, q, d, l, gx, gy, it) == 0 && l > 1e-9 && l < best) {
                 best = l;
                 bk = j;
+                h.q[0] = q[0]; h.q[1] = q[1]; h.q[2] = q[2];
+                h.d[0] = d[0]; h.d[1] = d[1]; h.d[2] = d[2];
+                bgx = gx;
+                bgy = gy;
+                bit = it;
             }
         }
     }
@@ -1125,13 +1146,24 @@ __device__ __forceinline__ bool ghost_step(const DevParams& P, const Launch& L, 
         return true;
     }
     const DevSurface& s = P.surf[bk];
-    // the interaction: intersection, aperture, normal, then the roulette with this interaction's
-    // own word
-    Hit h;
-    const int st = hit_geometry<ZERN>(P, bk, gr.p, gr.n, h, o.newton);
-    if (st != 0) {
-        o.status = st; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
-        return true;
+    // the interaction: the hit point, aperture and normal (as the sequential passage takes
+    // them), then the roulette with this interaction's own word
+    o.newton += bit;
+    h.q[0] += h.d[0] * best; h.q[1] += h.d[1] * best; h.q[2] += h.d[2] * best;
+    {
+        const double rq2 = h.q[0] * h.q[0] + h.q[1] * h.q[1];
+        if (rq2 < s.r_in2 || rq2 > s.r_out2) {
+            o.status = PHX_VIGNETTED; o.surface = bk; o.x = h.q[0]; o.y = h.q[1]; o.z = h.q[2];
+            return true;
+        }
+        if (s.c == 0.0 && s.asphere == 0 && !(ZERN && s.zernike)) {
+            h.N[0] = 0.0; h.N[1] = 0.0; h.N[2] = 1.0;   // a plane
+        } else {
+            const double inv = rsq_fast(bgx * bgx + bgy * bgy + 1.0);
+            h.N[0] = -bgx * inv; h.N[1] = -bgy * inv; h.N[2] = inv;
+        }
+        h.dn = h.d[0] * h.N[0] + h.d[1] * h.N[1] + h.d[2] * h.N[2];
+        if (h.dn > 0.0) { h.N[0] = -h.N[0]; h.N[1] = -h.N[1]; h.N[2] = -h.N[2]; h.dn = -h.dn; }
     }
     bool reflect = s.kind == PHX_MIRROR;
     if ((L.flags & PHX_F_COATINGS) && s.coating >= 0) {
@@ -1191,13 +1223,13 @@ __device__ __forceinline__ void finish_detector(const DevParams& P, const Launch
                                                 const Rng& rng, const Optics& oc, Ray& ray,
                                                 uint4& wc, int& wc_block, Outcome& o,
                                                 double* tp = nullptr, uint64_t ts = 0,
-                                                GhostStart* gs = nullptr) {
+                                                GhostSink* gs = nullptr) {
     const int kdet = P.n_surf - 1;
     Hit h;
     int st = hit_surface<ZERN, TAPE, GHOST>(P, L, rng, kdet, ray.p, ray.n, oc.lc, wc, wc_block, h,
                                             o.newton);
     if (GHOST && st == kGhostReflect) {   // GHOST callers pass gs
-        gs->h = h; gs->k = kdet; gs->n_cur = ray.n_cur;
+        ghost_stage(gs, h, kdet, ray.n_cur);
         return;
     }
     if (TAPE && st == 0) tape_put(tp, ts, kdet, h);
@@ -1890,16 +1922,23 @@ __device__ __forceinline__ void book(const DevParams& P, const Launch& L, bool a
 constexpr int kWin = 32;                  // LDS pixel window of the optics kernel
 constexpr int kQueue = 128;               // queued photons per wavefront (64 + 63 carried)
 constexpr int kWaves = kBlock / 64;
-// EXTRA: aerosol and the spider at the entrance; GHOST: the ghost branch of the roulette.
+// EXTRA: aerosol and the spider at the entrance.  GH, the ghost branch of the roulette (with
+// ghosts the kernel runs twice per chunk): 0 none; 1 the sequential pass, which appends the
+// photons a coating reflects to the chunk's ghost list (ghost_list, cap entries, ghost_ctr[0]
+// their number) instead of booking them; 2 the branches of the listed photons, claimed 64 at a
+// time through ghost_ctr[1], with every lane refilled from the claimed entries as its photon is
+// settled.  Keeping the branches out of the sequential pass keeps its registers those of the
+// kernel without ghosts.
 // Register budget for three waves per SIMD (168 VGPRs): alone the kernel runs about 7 % slower
 // than with four (128 VGPRs and more spills), but beside the sky stage the whole step is faster,
 // the launch then placing fewer of its workgroups on a compute unit.
-template <bool ZERN, bool EXTRA, bool GHOST>
+template <bool ZERN, bool EXTRA, int GH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void back_kernel(
         const DevParams* __restrict__ Pg, const Launch L, uint64_t begin,
         const uint32_t* __restrict__ surv, const unsigned int* __restrict__ count, uint64_t n_all,
         const double* __restrict__ st, uint64_t st_stride, unsigned long long* unit_ctr,
-        double* __restrict__ ghost_q) {
+        double* __restrict__ ghost_list, uint64_t ghost_cap, unsigned long long* ghost_ctr) {
+    constexpr bool GHOST = GH == 1;
     __shared__ uint32_t s_stats[PHX_STATS_LEN];
     __shared__ uint32_t s_win[kWin * kWin];
     __shared__ int s_org;   // window origin: (i0 << 16) | j0, or -1 before the first detection
@@ -1907,6 +1946,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     __shared__ double s_q[kWaves][7][kQueue];   // p, n (global frame) and wavelength
     __shared__ uint32_t s_qr[kWaves][kQueue];   // position in the survivor list
     __shared__ int32_t s_qk[kWaves][kQueue];    // Newton steps so far << 1 | travelling in glass
+    // GH == 1: each wavefront's staging area of ghost starts (kGhostStage fields x 64 lanes)
+    __shared__ double s_gs[GH == 1 ? kWaves * kGhostStage * 64 : 1];
     for (int i = threadIdx.x; i < kWin * kWin; i += blockDim.x) s_win[i] = 0;
     if (threadIdx.x == 0) s_org = -1;
     moment_cache_init(&s_mc);
@@ -1929,57 +1970,63 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     const int k_first = kdet < 1 ? kdet : 1;   // surfaces of the first pass: [0, k_first)
     int qn = 0;                                // queued photons (wavefront-uniform)
     uint32_t newton = 0, traced = 0;
-    // GHOST: photons reflected into a ghost branch wait in the wavefront's queue until more than
-    // kGhostQ - 64 are there (or the work has run out); the queue is then drained with every lane
-    // busy
-    double* gq = GHOST ? ghost_q + ((size_t)blockIdx.x * kWaves + wave) * (kGhostQ * kGhostFields)
-                       : nullptr;
-    int gn = 0;                                // queued ghost starts (wavefront-uniform)
-    for (;;) {
-        const bool more = unit < n_units;
-        if (GHOST && (gn > kGhostQ - 64 || (!more && qn == 0 && gn > 0))) {
-            // drain the ghost queue one interaction at a time: a lane whose photon is settled
-            // takes the next queued start, so that the lanes stay busy until the queue is empty
-            bool busy = false;
-            GhostRay gr;
-            Outcome o;
-            outcome_init(o, 0.0);
-            Optics oc{0.0, 1.0, LamCol{0, 0.0}};
-            Rng rng{0u, 0u, 0u, 0u};
-            uint64_t g = 0, idx = 0;
-            int si = 0;
-            for (;;) {
-                const uint64_t idle = __ballot(!busy);
-                const int take = min(__popcll(idle), gn);
-                const int rank = __popcll(idle & ((1ull << lane) - 1ull));
-                if (!busy && rank < take) {
-                    GhostStart gs;
-                    double lam;
-                    uint32_t r;
-                    int nw;
-                    ghost_get(gq, gn - take + rank, gs, lam, r, nw);
-                    g = begin + (surv ? (uint64_t)surv[r] : (uint64_t)r);
-                    decode(L, g, si, idx);
-                    rng = Rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
-                    outcome_init(o, lam);
-                    o.newton = nw;
-                    oc = optics_of(P, L, lam);
-                    ghost_begin(P, gs.h, gs.k, gs.n_cur, gr);
-                    busy = true;
-                }
-                gn -= take;
-                if (__ballot(busy) == 0) break;
-                bool fin = false;
-                if (busy) fin = ghost_step<ZERN>(P, L, rng, oc, gr, o);
-                if (fin) {
-                    newton += o.newton;
-                    busy = false;
-                }
-                book(P, L, fin, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
+    if (GH == 2) {
+        // the branches: the wavefront claims 64 listed starts at a time; a lane whose photon is
+        // settled takes the next claimed start, so that the lanes stay busy until the list is
+        // exhausted
+        const uint64_t total = min((uint64_t)ghost_ctr[0], ghost_cap);
+        uint64_t wbase = 0, wend = 0;   // the wavefront's claimed, not yet started entries
+        bool claims = true;
+        bool busy = false;
+        GhostRay gr;
+        Outcome o;
+        outcome_init(o, 0.0);
+        Optics oc{0.0, 1.0, LamCol{0, 0.0}};
+        Rng rng{0u, 0u, 0u, 0u};
+        uint64_t g = 0, idx = 0;
+        int si = 0;
+        for (;;) {
+            const uint64_t idle = __ballot(!busy);
+            if (claims && idle && wbase == wend) {
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(&ghost_ctr[1], 64ull);
+                b = __shfl(b, 0);
+                wbase = b < total ? b : total;
+                wend = b + 64 < total ? b + 64 : total;
+                claims = wbase < wend;
             }
-            __builtin_amdgcn_wave_barrier();
-            continue;
+            const uint64_t avail = wend - wbase;
+            const int take = (int)min((uint64_t)__popcll(idle), avail);
+            const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+            if (!busy && rank < take) {
+                GhostStart gs;
+                double lam;
+                uint32_t r;
+                int nw;
+                ghost_get(ghost_list, ghost_cap, wbase + rank, gs, lam, r, nw);
+                g = begin + (surv ? (uint64_t)surv[r] : (uint64_t)r);
+                decode(L, g, si, idx);
+                rng = Rng{L.seed, (uint32_t)si, (uint32_t)idx, (uint32_t)(idx >> 32)};
+                outcome_init(o, lam);
+                o.newton = nw;
+                oc = optics_of(P, L, lam);
+                ghost_begin(P, gs.h, gs.k, gs.n_cur, gr);
+                busy = true;
+            }
+            wbase += take;
+            if (__ballot(busy) == 0) break;
+            bool fin = false;
+            if (busy) fin = ghost_step<ZERN>(P, L, rng, oc, gr, o);
+            if (fin) {
+                newton += o.newton;
+                busy = false;
+            }
+            book(P, L, fin, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
         }
+    }
+    for (;;) {
+        if (GH == 2) break;
+        const bool more = unit < n_units;
         if (qn >= 64 || (!more && qn > 0)) {
             // second pass: up to 64 queued photons through the remaining surfaces
             const int take = qn < 64 ? qn : 64;
@@ -1989,8 +2036,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             uint64_t g = 0, idx = 0;
             int si = 0;
             uint32_t r = 0;
-            GhostStart gs;
-            gs.k = -1;
+            GhostSink gs{s_gs + (GH == 1 ? wave * kGhostStage * 64 + lane : 0), -1};
             if (act) {
                 const int e = qn - take + lane;
                 r = qr[e];
@@ -2006,14 +2052,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                         (kq & 1) ? oc.n_glass : 1.0};
                 uint4 wc = make_uint4(0, 0, 0, 0);
                 int wc_block = -1;
-                GhostStart* gp = GHOST ? &gs : nullptr;
+                GhostSink* gp = GHOST ? &gs : nullptr;
                 if (trace_surfaces<ZERN, false, GHOST>(P, L, rng, oc, ray, k_first, kdet, wc,
                                                        wc_block, o, nullptr, 0, gp))
                     finish_detector<ZERN, false, GHOST>(P, L, rng, oc, ray, wc, wc_block, o,
                                                         nullptr, 0, gp);
             }
             const bool fin = act && !(GHOST && gs.k >= 0);
-            if (GHOST) gn = ghost_push(gq, gn, gs, o, r);
+            if (GHOST) ghost_append(ghost_list, ghost_cap, ghost_ctr, gs, o, r);
             if (fin) newton += o.newton;
             book(P, L, fin, g, si, idx, o, s_stats, s_win, kWin, &s_org, &s_mc);
             qn -= take;
@@ -2030,8 +2076,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         uint64_t g = 0, idx = 0;
         int si = 0;
         Ray ray{{0.0, 0.0, 0.0}, {0.0, 0.0, 1.0}, 1.0};
-        GhostStart gs;
-        gs.k = -1;
+        GhostSink gs{s_gs + (GH == 1 ? wave * kGhostStage * 64 + lane : 0), -1};
         if (valid) {
             g = begin + (surv ? (uint64_t)surv[r] : r);
             decode(L, g, si, idx);
@@ -2054,7 +2099,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             }
             traced += 1;
         }
-        if (GHOST) gn = ghost_push(gq, gn, gs, o, (uint32_t)r);
+        if (GHOST) ghost_append(ghost_list, ghost_cap, ghost_ctr, gs, o, (uint32_t)r);
         const uint64_t am = __ballot(alive);
         if (alive) {
             const int e = qn + __popcll(am & ((1ull << lane) - 1ull));
@@ -2738,9 +2783,8 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
     if (L.total == 0) return hipSuccess;
     const Stages S{dparams, L, W, n_cu, cfg, stream, pipe, T};
     if (!S.valid()) return hipErrorInvalidValue;
-    // every wavefront of the optics grid needs its own ghost queue
-    if ((L.flags & PHX_F_GHOSTS) &&
-        (!W.ghost_q || W.ghost_waves < (uint64_t)n_cu * cfg.back_per_cu * kWaves))
+    // with ghosts every chunk's traced photons may each leave one ghost start in the list
+    if ((L.flags & PHX_F_GHOSTS) && (!W.ghost_list || !W.ghost_ctr || W.ghost_cap < W.chunk))
         return hipErrorInvalidValue;
     const uint64_t n_chunks = W.n_plan;
     if (cfg.dynamic)
@@ -2754,16 +2798,29 @@ hipError_t launch_trace(const DevParams* dparams, const Launch& L, const Workspa
         unsigned long long* bt = cfg.dynamic ? W.tiles + 2 * c + 1 : nullptr;
         S.mark(2, 0, bs);
         const bool extra = (L.flags & kBackExtra) != 0, ghost = (L.flags & PHX_F_GHOSTS) != 0;
-        const auto bk =
-            L.any_zernike
-                ? (ghost ? back_kernel<true, true, true>
-                         : (extra ? back_kernel<true, true, false> : back_kernel<true, false, false>))
-                : (ghost ? back_kernel<false, true, true>
-                         : (extra ? back_kernel<false, true, false>
-                                  : back_kernel<false, false, false>));
-        hipLaunchKernelGGL(bk, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin, S.surv(c), S.cnt(c),
-                           sp.len, (const double*)S.state_buf(c), W.chunk, bt,
-                           ghost ? W.ghost_q : nullptr);
+        if (ghost) {
+            // the sequential pass lists the chunk's ghost starts, the second pass runs them (the
+            // list is reused by the next chunk, whose optics stage follows on this stream)
+            hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, bs, (unsigned int*)W.ghost_ctr, 4,
+                               0u);
+            const auto k1 = L.any_zernike ? back_kernel<true, true, 1> : back_kernel<false, true, 1>;
+            const auto k2 = L.any_zernike ? back_kernel<true, true, 2> : back_kernel<false, true, 2>;
+            hipLaunchKernelGGL(k1, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin, S.surv(c),
+                               S.cnt(c), sp.len, (const double*)S.state_buf(c), W.chunk, bt,
+                               W.ghost_list, W.ghost_cap, W.ghost_ctr);
+            hipLaunchKernelGGL(k2, dim3((unsigned)bcap), dim3(kBlock), 0, bs, dparams, L,
+                               sp.begin, S.surv(c), S.cnt(c), sp.len,
+                               (const double*)S.state_buf(c), W.chunk,
+                               (unsigned long long*)nullptr, W.ghost_list, W.ghost_cap,
+                               W.ghost_ctr);
+        } else {
+            const auto bk = L.any_zernike
+                                    ? (extra ? back_kernel<true, true, 0> : back_kernel<true, false, 0>)
+                                    : (extra ? back_kernel<false, true, 0> : back_kernel<false, false, 0>);
+            hipLaunchKernelGGL(bk, bg, dim3(kBlock), 0, bs, dparams, L, sp.begin, S.surv(c),
+                               S.cnt(c), sp.len, (const double*)S.state_buf(c), W.chunk, bt,
+                               (double*)nullptr, (uint64_t)0, (unsigned long long*)nullptr);
+        }
         S.mark(2, 1, bs);
     });
     return hipGetLastError();

@@ -272,10 +272,11 @@ def test_ghosts_full_stack(phx, cull):
 
 
 def test_ghost_queue_under_launch_shapes(phx):
-    """Ghost starts wait in per-wavefront queues of the optics kernel: the same ghost trace under
-    three launch shapes -- one optics workgroup per compute unit on the dynamic schedule (each
-    wavefront carries queued starts through many passes), then twelve (the queues grow), then the
-    default -- gives identical images, statistics and event records."""
+    """Ghost starts are listed by the optics kernel's sequential pass and run by its second pass,
+    whose wavefronts claim them 64 at a time: the same ghost trace under three launch shapes --
+    one optics workgroup per compute unit on the dynamic schedule (few wavefronts, each running
+    many claims), then twelve, then the default -- gives identical images, statistics and event
+    records."""
     import torch
     from paper_1504_06570_amd.scene import coatings as cm
     s = C.full(scale=2e-4, screen_n=256)
