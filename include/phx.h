@@ -101,7 +101,9 @@ enum {
                                    interactions, stream 4 block i for interaction i), crossing
                                    into the medium on the other side of each surface it passes;
                                    the pre-roll tests only the coated surfaces ahead of the
-                                   first coated refracting one; phx_adjoint refuses it */
+                                   first coated refracting one; the context then holds a list of
+                                   112 bytes per photon of a chunk (7.5 GB for chunks of 2^26);
+                                   phx_adjoint and phx_trace_noalloc refuse it */
     PHX_F_CULL = 1u << 8,       /* pre-roll: skip photons whose roulette draws exceed the
                                    worst-case transmission of any coated surface (section 3.2,
                                    dynamic transmission optimisation), pupil samples whose
@@ -410,7 +412,7 @@ phx_status phx_trace(phx_ctx ctx, const phx_trace_args* args, void* stream);
  * moments and event buffers.  Photons, results and error behaviour are those of phx_trace with
  * the same arguments (the launch is cut into chunks of at most 2^19 photons, run on `stream`
  * alone).  Limits: at most 65536 sources and 16384 chunks (about 8.6e9 photons); PHX_F_GHOSTS
- * is refused (PHX_ERR_INVALID: ghost queues need context memory); beyond a limit
+ * is refused (PHX_ERR_INVALID: the ghost list needs context memory); beyond a limit
  * PHX_ERR_CAPACITY, nothing enqueued.  Every call on one GPU shares that GPU's workspace, so
  * calls that overlap on one GPU (two streams, two threads or two contexts) race: serialise them.
  * The parameter block is uploaded on `stream` when a load changed it (that call synchronises
