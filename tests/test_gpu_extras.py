@@ -273,18 +273,20 @@ def test_ghosts_full_stack(phx, cull):
 
 def test_ghost_queue_under_launch_shapes(phx):
     """Ghost starts are listed by the optics kernel's sequential pass and run by its second pass,
-    whose wavefronts claim them 64 at a time: the same ghost trace under three launch shapes --
+    whose wavefronts claim them 64 at a time: the same ghost trace under four launch shapes --
     one optics workgroup per compute unit on the dynamic schedule (few wavefronts, each running
-    many claims), then twelve, then the default -- gives identical images, statistics and event
-    records."""
+    many claims), twelve, chunks of 2^16 photons (the list and its counters reused chunk after
+    chunk), then the default -- gives identical images, statistics and event records."""
     import torch
     from paper_1504_06570_amd.scene import coatings as cm
     s = C.full(scale=2e-4, screen_n=256)
     s.reflectance = cm.standard_reflectance()
     s.physics = C.PHYS_ALL | X.PHYS_GHOSTS
     tr = phx.Tracer(s)
+    default = tr.launch_config()
     shapes = (dict(back_blocks_per_cu=1, dynamic_tiles=1),
-              dict(back_blocks_per_cu=12, dynamic_tiles=0), tr.launch_config())
+              dict(back_blocks_per_cu=12, dynamic_tiles=0),
+              dict(default, chunk_log2=16), default)
     runs = []
     for kw in shapes:
         tr.set_launch_config(**kw)
