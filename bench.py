@@ -57,17 +57,18 @@ def front_bytes_per_photon(n_layers, n_scales, counts=None):
     return n_layers * n_scales * 4 * 8
 
 
-def back_flops(stats, counts):
-    """FP64 operations of the optics + sensor stage for this launch's traced photons: each
-    outcome group's count in the launch statistics times its mean count in the oracle's counting
-    build (a group absent from the counted sample takes the mean of its status)."""
+def back_ops_by_class(stats, counts):
+    """FP64 operations of the optics + sensor stage for this launch's traced photons, per class
+    (add/sub, mul, div, sqrt, transcendental): each outcome group's count in the launch statistics
+    times its mean count in the oracle's counting build (a group absent from the counted sample
+    takes the mean of its status)."""
     from paper_1504_06570_amd import phx
     tab = phx.stats_table(stats)
     by = counts["by_outcome"]
 
-    def ops(rec):
-        return sum(rec["optics"][f] + rec["sensor"][f] for f in FP64_FIELDS)
-    total = 0.0
+    def ops(rec, f):
+        return rec["optics"][f] + rec["sensor"][f]
+    total = {f: 0.0 for f in FP64_FIELDS}
     for st in range(phx.N_STATUS):
         if st == phx.CULLED:
             continue
@@ -76,12 +77,70 @@ def back_flops(stats, counts):
             if n == 0:
                 continue
             key = f"{phx.STATUS[st]}@{col - 1}"
-            if key in by:
-                total += n * ops(by[key])
-            else:
-                same = [v for k, v in by.items() if k.split("@")[0] == phx.STATUS[st]]
-                total += n * (np.mean([ops(v) for v in same]) if same else ops(by["all"]))
+            same = [v for k, v in by.items() if k.split("@")[0] == phx.STATUS[st]]
+            for f in FP64_FIELDS:
+                if key in by:
+                    total[f] += n * ops(by[key], f)
+                else:
+                    total[f] += n * (np.mean([ops(v, f) for v in same]) if same
+                                     else ops(by["all"], f))
     return total
+
+
+def back_flops(stats, counts):
+    """FP64 operations of the optics + sensor stage (every class counted as one operation)."""
+    return sum(back_ops_by_class(stats, counts).values())
+
+
+# FP64 operation classes of the op-rate probe (probe_fp64's kind codes)
+OP_KINDS = {"fma": (0, 4000), "div": (1, 1000), "sqrt": (2, 1000), "exp": (3, 400),
+            "log": (4, 200), "sin": (5, 200), "div_refined": (6, 2000),
+            "sqrt_refined": (7, 2000)}
+
+
+def fp64_op_rates(threads=1 << 22, reps=3):
+    """Operations per second of each FP64 class as compiled for this GPU (probe_fp64 of
+    libphx_probe.so: 8 independent chains per thread, so the issue rate is measured, not the
+    latency); None when the probe library is not built."""
+    import ctypes as C
+    import torch
+    from paper_1504_06570_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        return None
+    lib = C.CDLL(B.PROBE_LIB)
+    lib.probe_fp64.argtypes = [C.c_int, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p]
+    lib.probe_fp64.restype = C.c_int
+    out = torch.empty(threads, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    rates = {}
+    for name, (kind, iters) in OP_KINDS.items():
+        def run():
+            rc = lib.probe_fp64(kind, out.data_ptr(), threads, iters, C.c_void_p(stream.cuda_stream))
+            if rc != 0:
+                raise SystemExit(f"bench.py: probe_fp64 returned {rc}")
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rates[name] = threads * iters * 8 / (ms * 1e-3)
+    return rates
+
+
+def per_class_seconds(ops, rates):
+    """Time of FP64 operations by class at the measured rates: additions and multiplications
+    paired into fused multiply-adds, divisions and square roots at the rates of the refined
+    hardware estimates (the faster forms, so the bound is the stricter one), transcendentals at
+    the harmonic mean of exp, log and sin."""
+    trans = 3.0 / (1.0 / rates["exp"] + 1.0 / rates["log"] + 1.0 / rates["sin"])
+    div = max(rates["div"], rates["div_refined"])
+    sqrt = max(rates["sqrt"], rates["sqrt_refined"])
+    return ((ops["add"] + ops["mul"]) / (2.0 * rates["fma"]) + ops["div"] / div +
+            ops["sqrt"] / sqrt + ops["trans"] / trans)
 
 
 def kernel_hash():
@@ -658,6 +717,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--op-probe", action="store_true",
+                    help="issue rates of the FP64 operation classes (fma, div, sqrt, exp, log, sin)")
     ap.add_argument("--gather-probe", action="store_true",
                     help="random 32-byte record gathers over tables of 4 MiB - 2.75 GiB (the "
                          "memory system's rate for the sky stage's access pattern)")
@@ -702,6 +763,9 @@ def main():
         return
     if args.gather_probe:
         gather_probe()
+        return
+    if args.op_probe:
+        print(json.dumps({"fp64_op_rates": fp64_op_rates()}), flush=True)
         return
     if args.only:
         leg = batched_leg if args.only == "batched" else gradient_leg
@@ -817,6 +881,33 @@ def main():
         extra["roofline_single_stream"] = iso
         extra["stage_ms_single_stream"] = {k: kti[k] for k in ("generate", "compact", "front",
                                                                "back")}
+    # The optics kernel against the FP64 classes' own measured rates (division, square root and
+    # transcendentals are sequences of several instructions, not one), and the whole step against
+    # the sum of its stages' times at their peaks (the counted work over the measured per-class
+    # rates, the screen bytes over the HBM peak, the Philox operations over the integer peak).
+    rates = fp64_op_rates()
+    if rates is not None:
+        ops = {f: v / chunks for f, v in back_ops_by_class(st, counts).items()}
+        t_back = per_class_seconds(ops, rates)
+        for tab_ in (extra.get("roofline_pipelined"), extra.get("roofline_single_stream")):
+            if tab_ and "back_kernel" in tab_:
+                tab_["back_kernel"]["frac_per_class"] = t_back / (tab_["back_kernel"]["launch_ms"]
+                                                                  * 1e-3)
+        t_sky = kinds["front"]["work"] / (PEAK_HBM_GBS * 1e9)
+        t_pre = kinds["generate"]["work"] / (PEAK_INT32_TOPS * 1e12)
+        per_step = chunks / args.steps * 1e3   # launches per step, seconds -> ms
+        t_sum = (t_sky + t_back + t_pre) * per_step
+        extra["fp64_op_rates"] = {k: v for k, v in rates.items()}
+        extra["fp64_ops_per_launch"] = ops
+        extra["step_roofline"] = {
+            "sky_ms": t_sky * per_step, "optics_ms": t_back * per_step,
+            "preroll_ms": t_pre * per_step, "sum_ms": t_sum, "measured_ms": ms,
+            "frac": t_sum / ms,
+            "frac_max": max(t_sky, t_back, t_pre) * per_step / ms,
+            "note": "each stage's counted work at its peak, summed over the step, over the "
+                    "measured step time (frac); the stages run concurrently on different units, "
+                    "so the largest stage alone over the step time (frac_max) is the tighter "
+                    "bound"}
     if not args.no_cull and not args.no_compare:
         # the same step without the pre-roll (every photon traced until its fate)
         nc_img = tr.new_image()

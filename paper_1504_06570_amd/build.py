@@ -17,7 +17,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 # the benchmark's memory-system probe, a library of its own (not part of the trace)
 PROBE_LIB = os.path.join(HERE, "libphx_probe.so")
-PROBE_SOURCES = ["probe_gather.hip"]
+PROBE_SOURCES = ["probe.hip"]
 
 
 def _link(lib, sources, verbose):

@@ -88,3 +88,17 @@ def test_probe_library_exports_and_checks_arguments():
     assert f(16, 16, 16, 1, 7, 5, 0, None) == -1            # more than four gathers in flight
     assert f(24, 16, 16, 1, 7, 1, 0, None) == -1            # table not 16-byte aligned
     assert f(16, 1 << 33, 16, 1, 7, 1, 0, None) == -1       # more records than 32-bit indices
+
+
+def test_probe_library_op_rate_entry_checks_arguments():
+    """The FP64 op-rate probe refuses invalid arguments before it touches a device."""
+    from paper_1504_06570_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        pytest.skip("probe library not built")
+    f = ctypes.CDLL(B.PROBE_LIB).probe_fp64
+    f.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    assert f(0, None, 16, 10, None) == -1      # null output
+    assert f(8, 16, 16, 10, None) == -1        # unknown class
+    assert f(0, 16, 0, 10, None) == -1         # no threads
+    assert f(0, 16, 16, 0, None) == -1         # no steps
