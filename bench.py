@@ -5,7 +5,8 @@ Karman layers (2048^2 screens at 1 m / 10 cm / 1 cm), the generated three-mirror
 camera with coatings, 100 um silicon with diffusion, a 4096^2 chip centred on the star.  Inputs
 are synthetic and resident on the GPU before timing; the image accumulates across steps.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the trace runs on one GPU (photons shard by
+key across GPUs with one image sum, which is not implemented).
 """
 from __future__ import annotations
 
@@ -755,8 +756,8 @@ def main():
         print(summarize_pmc(args.summarize_pmc, args.copy_dirs, args.photons, args.pmc_json))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: the trace runs on one GPU only (asked for --gpus {args.gpus}); sharding "
+              "photons over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
