@@ -246,6 +246,51 @@ def test_photon_index_crossing_32_bits(phx):
     assert not np.isin(o["status"][culled], [phx.DETECTED, phx.OFF_CHIP]).any()
 
 
+def _parity_with_cull(phx, gev, oev):
+    g, o = parity.match(gev, oev)
+    culled = g["status"] == phx.CULLED
+    assert not np.isin(o["status"][culled], [phx.DETECTED, phx.OFF_CHIP]).any()
+    rep = parity.compare(g[~culled], o[~culled])
+    assert rep["boundary_frac"] < 1e-5
+    return g, o, culled
+
+
+def test_ragged_counts_and_a_single_photon(phx):
+    """Photon counts that fill no bitmap word, wavefront or workgroup evenly, at an odd first
+    index: 100003 photons from index 17, and one photon alone, with the pre-roll and the
+    atmosphere on; GPU and oracle agree photon by photon and the image counts the detected."""
+    s = C.full(scale=2e-4, screen_n=128)
+    flags = int(s.physics) | phx.F_CULL
+    for count, begin in ((100003, 17), (1, 12345)):
+        gev, gimg, oev, oimg, _ = run_both(phx, s, flags=flags, photon_count=count,
+                                           photon_begin=begin)
+        assert len(gev) == count and gev["photon"].min() == begin
+        assert gev["photon"].max() == begin + count - 1
+        g, o, culled = _parity_with_cull(phx, gev, oev)
+        assert int(gimg.sum()) == int((g["status"] == phx.DETECTED).sum())
+
+
+def test_last_chunk_of_one_photon(phx):
+    """Chunks of 2^16 photons and a launch of 2^16 + 1: the second chunk holds one photon and
+    runs through the two-stream pipeline like the first; GPU and oracle agree photon by photon."""
+    import torch
+    s = C.full(scale=2e-4, screen_n=128)
+    flags = int(s.physics) | phx.F_CULL
+    n = (1 << 16) + 1
+    tr = phx.Tracer(s)
+    tr.set_launch_config(chunk_log2=16, pipeline=1)
+    stats = tr.new_stats()
+    img, stats, _, evb = tr.trace(stats=stats, event_stride=1, flags=flags, photon_count=n)
+    torch.cuda.synchronize()
+    gev = phx.events_to_numpy(evb)
+    gimg = img.cpu().numpy().view(np.uint32)
+    tr.close()
+    oev = O.Oracle(s).trace_sources(counts=np.full(len(s.sources), n), threads=8)
+    assert len(gev) == n
+    g, o, culled = _parity_with_cull(phx, gev, oev)
+    assert int(gimg.sum()) == int((g["status"] == phx.DETECTED).sum())
+
+
 def test_newton_cycle_is_nonconv(phx):
     """A surface on which Newton's iteration cycles (tests/helpers.newton_cycle_scene): every
     photon is counted as NONCONV at that surface, photon by photon equal to the oracle, with
