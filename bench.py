@@ -132,6 +132,35 @@ def fp64_op_rates(threads=1 << 22, reps=3):
     return rates
 
 
+def philox_rate(threads=1 << 22, iters=64, reps=3):
+    """Philox4x32-10 blocks per second as the trace kernels compute them (probe_philox of
+    libphx_probe.so); None when the probe library is not built."""
+    import ctypes as C
+    import torch
+    from paper_1504_06570_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        return None
+    lib = C.CDLL(B.PROBE_LIB)
+    lib.probe_philox.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_void_p]
+    lib.probe_philox.restype = C.c_int
+    out = torch.empty(threads, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run():
+        rc = lib.probe_philox(out.data_ptr(), threads, iters, C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise SystemExit(f"bench.py: probe_philox returned {rc}")
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return threads * iters * 8 / (e0.elapsed_time(e1) / reps * 1e-3)
+
+
 def per_class_seconds(ops, rates):
     """Time of FP64 operations by class at the measured rates: additions and multiplications
     paired into fused multiply-adds, divisions and square roots at the rates of the refined
@@ -719,7 +748,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--op-probe", action="store_true",
-                    help="issue rates of the FP64 operation classes (fma, div, sqrt, exp, log, sin)")
+                    help="issue rates of the FP64 operation classes (fma, div, sqrt, exp, log, "
+                         "sin) and of Philox blocks")
     ap.add_argument("--gather-probe", action="store_true",
                     help="random 32-byte record gathers over tables of 4 MiB - 2.75 GiB (the "
                          "memory system's rate for the sky stage's access pattern)")
@@ -766,7 +796,8 @@ def main():
         gather_probe()
         return
     if args.op_probe:
-        print(json.dumps({"fp64_op_rates": fp64_op_rates()}), flush=True)
+        print(json.dumps({"fp64_op_rates": fp64_op_rates(), "philox_blocks_per_s": philox_rate()}),
+              flush=True)
         return
     if args.only:
         leg = batched_leg if args.only == "batched" else gradient_leg
@@ -896,6 +927,15 @@ def main():
                                                                   * 1e-3)
         t_sky = kinds["front"]["work"] / (PEAK_HBM_GBS * 1e9)
         t_pre = kinds["generate"]["work"] / (PEAK_INT32_TOPS * 1e12)
+        # the pre-roll's blocks at the measured Philox block rate
+        blocks_rate = philox_rate()
+        if blocks_rate:
+            t_pre = kinds["generate"]["work"] / PHILOX_INT_OPS / blocks_rate
+            for tab_ in (extra.get("roofline_pipelined"), extra.get("roofline_single_stream")):
+                if tab_ and "generate_kernel" in tab_:
+                    tab_["generate_kernel"]["frac_per_class"] = t_pre / (
+                        tab_["generate_kernel"]["launch_ms"] * 1e-3)
+            extra["philox_blocks_per_s"] = blocks_rate
         per_step = chunks / args.steps * 1e3   # launches per step, seconds -> ms
         t_sum = (t_sky + t_back + t_pre) * per_step
         extra["fp64_op_rates"] = {k: v for k, v in rates.items()}

@@ -10,6 +10,8 @@
 
 #include <cstdint>
 
+#include "phx_rng.h"
+
 namespace {
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
@@ -72,9 +74,10 @@ extern "C" __attribute__((visibility("default"))) int probe_gather(
 
 // probe_fp64: the issue rate of one class of FP64 operation as hipcc compiles it for this GPU --
 // fused multiply-add, IEEE division and square root, exp, log, sin, and the refined reciprocal
-// and square root of the trace kernels -- the classes the oracle's counting build tallies.  Every thread runs kChains independent dependency chains for `iters`
-// steps (enough chains in flight that the rate, not the latency, is measured); each step maps a
-// value in [1/2, 2] back into that range.  One result word per thread keeps the work alive.
+// and square root of the trace kernels -- the classes the oracle's counting build tallies.
+// Every thread runs kChains independent dependency chains for `iters` steps (enough chains in
+// flight that the rate, not the latency, is measured); each step maps a value in [1/2, 2] back
+// into that range.  One result word per thread keeps the work alive.
 namespace {
 constexpr int kChains = 8;
 
@@ -144,5 +147,40 @@ extern "C" __attribute__((visibility("default"))) int probe_fp64(int kind, doubl
     case 6: hipLaunchKernelGGL(op_kernel<6>, g, b, 0, stream, out, n_threads, iters); break;
     default: hipLaunchKernelGGL(op_kernel<7>, g, b, 0, stream, out, n_threads, iters); break;
     }
+    return (int)hipGetLastError();
+}
+
+// probe_philox: the rate of Philox4x32-10 blocks as the trace kernels compute them (the pre-roll's
+// unit of work).  Every thread computes `iters` blocks of kChains independent counters; the
+// words are folded into one word per thread.
+namespace {
+__global__ __launch_bounds__(256) void philox_kernel(uint32_t* __restrict__ out,
+                                                     uint64_t n_threads, int iters) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_threads) return;
+    uint32_t acc = 0;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) {
+            const uint4 w = phx::philox(make_uint4((uint32_t)i, (uint32_t)(i >> 32),
+                                                   (uint32_t)(it * kChains + k), acc & 1u),
+                                        0x1234567u, (uint32_t)k);
+            acc ^= w.x ^ w.y ^ w.z ^ w.w;
+        }
+    }
+    out[i] = acc;
+}
+}  // namespace
+
+// out: n_threads words; the blocks computed are n_threads x iters x 8.  Returns 0, -1 for an
+// invalid argument, or the HIP error code of the launch.
+extern "C" __attribute__((visibility("default"))) int probe_philox(uint32_t* out,
+                                                                   uint64_t n_threads, int iters,
+                                                                   hipStream_t stream) {
+    if (!out || n_threads == 0 || iters < 1) return -1;
+    const uint64_t blocks = (n_threads + 255) / 256;
+    if (blocks > 0x7fffffffull) return -1;
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, out,
+                       n_threads, iters);
     return (int)hipGetLastError();
 }

@@ -102,3 +102,16 @@ def test_probe_library_op_rate_entry_checks_arguments():
     assert f(8, 16, 16, 10, None) == -1        # unknown class
     assert f(0, 16, 0, 10, None) == -1         # no threads
     assert f(0, 16, 16, 0, None) == -1         # no steps
+
+
+def test_probe_library_philox_entry_checks_arguments():
+    """The Philox block-rate probe refuses invalid arguments before it touches a device."""
+    from paper_1504_06570_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        pytest.skip("probe library not built")
+    f = ctypes.CDLL(B.PROBE_LIB).probe_philox
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    assert f(None, 16, 10, None) == -1         # null output
+    assert f(16, 0, 10, None) == -1            # no threads
+    assert f(16, 16, 0, None) == -1            # no blocks
