@@ -234,9 +234,7 @@ def batched_leg(steps, per_source_steps=1, variant_slope=-1.1):
     counts = scene.sources.n_photons.astype(np.int64)
     total = int(counts.sum())
     t0 = time.perf_counter()
-    tr.set_launch_config(pipeline=0)   # tune the graph-replayed launch
-    best = tr.autotune(flags=flags)
-    tr.set_launch_config(pipeline=1)   # per-source launches below run eagerly
+    best = tr.autotune(flags=flags, batched=True)   # graph replays, two streams captured
     t_tune = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

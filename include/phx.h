@@ -427,7 +427,7 @@ phx_status phx_trace_noalloc(phx_ctx ctx, const phx_trace_args* args, void* stre
  * chunk's pre-roll bitmap and optics stages run on a context-owned second stream, overlapping
  * the survivor compaction and sky stage of the next chunk on the caller's stream (ordered by
  * events; the caller's stream waits for the last optics stage), 0 = everything on the caller's
- * stream.  Launches captured by phx_trace_batched always run on the capturing stream.
+ * stream.  Graphs captured by phx_trace_batched follow the same setting.
  * Defaults: 26, 16, 48, 2, 0, 1 (the shape the autotuner settles on for one star of 1e9 photons). */
 typedef struct {
     int32_t chunk_log2;
@@ -450,11 +450,16 @@ phx_status phx_trace_batched(phx_ctx ctx, const phx_trace_args* args, void* stre
 /* Autotuner: times `sample` for candidate launch shapes (coordinate descent over optics, sky and
  * pre-roll workgroups per CU, the schedule and the chunk size; the pipeline setting is kept and
  * selects what is timed: eager phx_trace launches when it is 1, phx_trace_batched graph replays
- * when it is 0), writing into context-owned scratch outputs (the sample's output pointers are
- * ignored), sets the fastest shape on the context and returns it in *best_host (may be NULL).
- * Synchronises `stream`.  Errors as phx_trace, plus PHX_ERR_NOMEM. */
+ * on one stream when it is 0), writing into context-owned scratch outputs (the sample's output
+ * pointers are ignored), sets the fastest shape on the context and returns it in *best_host (may
+ * be NULL).  Synchronises `stream`.  Errors as phx_trace, plus PHX_ERR_NOMEM. */
 phx_status phx_autotune(phx_ctx ctx, const phx_trace_args* sample, void* stream,
                         phx_launch_config* best_host);
+
+/* The same for phx_trace_batched graph replays in the context's pipeline setting (with the
+ * pipeline on, the captured graph holds both streams' stages and their hand-offs). */
+phx_status phx_autotune_batched(phx_ctx ctx, const phx_trace_args* sample, void* stream,
+                                phx_launch_config* best_host);
 
 /* Adjoint trace: the gradient of a weighted sum of per-source moments with respect to the
  * PHX_N_THETA perturbation parameters (section 2.4.1 misalignments: group 1 and group 2 shift

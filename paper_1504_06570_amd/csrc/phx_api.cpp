@@ -1353,16 +1353,17 @@ phx::Pipe pipe_of(phx_ctx c) {
     return p;
 }
 
-// Eager launches (timed) may pipeline chunks over the context's streams; a launch being captured
-// into a graph stays on the capturing stream.
+// Launches pipeline chunks over the context's two streams when the launch shape says so; in a
+// launch being captured into a graph the second stream joins the capture through the pipeline's
+// fork event and rejoins it through the final wait, so the hand-off events become graph edges.
+// Only eager launches are timed.
 phx_status enqueue(phx_ctx c, const phx::Launch& L, const phx::Workspace& W, hipStream_t st,
                    bool eager) {
     phx::Timing T;
     T.on = eager && c->timing;
     T.record = timing_record;
     T.self = c;
-    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, c->cfg, st,
-                                     eager ? pipe_of(c) : phx::Pipe{}, T);
+    hipError_t e = phx::launch_trace(c->dparams, L, W, c->n_cu, c->cfg, st, pipe_of(c), T);
     if (e != hipSuccess) return hip_fail(c, e, "trace kernel launch");
     return PHX_OK;
 }
@@ -1647,8 +1648,10 @@ phx_status phx_get_launch_config(phx_ctx c, phx_launch_config* cfg) {
     return PHX_OK;
 }
 
-phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
-                        phx_launch_config* best) {
+namespace {
+// graph: time phx_trace_batched graph replays, else eager phx_trace launches
+phx_status autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
+                    phx_launch_config* best, bool graph) {
     if (!c) return PHX_ERR_INVALID;
     if (!sample) return fail(c, PHX_ERR_INVALID, "null sample");
     if (!c->have_presc) return fail(c, PHX_ERR_STATE, "load a prescription first");
@@ -1681,9 +1684,9 @@ phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     phx_launch_config cur;
     phx_get_launch_config(c, &cur);
     phx_status status = PHX_OK;
-    // the path the shape is for: eager launches pipelined over two streams, or graph replays
+    // the path the shape is for: eager launches or graph replays
     auto launch = [&]() -> phx_status {
-        return c->cfg.pipeline ? phx_trace(c, &a, st) : phx_trace_batched(c, &a, st);
+        return graph ? phx_trace_batched(c, &a, st) : phx_trace(c, &a, st);
     };
     auto measure = [&](const phx_launch_config& k, float& ms_out) -> phx_status {
         phx_status r = phx_set_launch_config(c, &k);
@@ -1706,12 +1709,14 @@ phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     };
     float cur_ms = 0.0f;
     status = measure(cur, cur_ms);
-    // coordinate descent, one pass per knob
+    // coordinate descent: two passes over the knobs (the best optics and sky widths depend on
+    // the chunk size and on each other)
     const int backs[] = {2, 3, 4, 6, 8, 12};
     const int fronts[] = {8, 16, 24, 32, 48, 64};
     const int gens[] = {2, 4, 8, 16};
     const int chunks[] = {24, 25, 26};
-    for (int knob = 0; knob < 5 && status == PHX_OK; ++knob) {
+    for (int step = 0; step < 10 && status == PHX_OK; ++step) {
+        const int knob = step % 5;
         std::vector<phx_launch_config> cand;
         if (knob == 0) for (int v : backs) { auto k = cur; k.back_blocks_per_cu = v; cand.push_back(k); }
         if (knob == 1) for (int v : fronts) { auto k = cur; k.front_blocks_per_cu = v; cand.push_back(k); }
@@ -1741,6 +1746,17 @@ phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     c->autotune_ms = cur_ms;
     if (best) *best = cur;
     return PHX_OK;
+}
+}  // namespace
+
+phx_status phx_autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
+                        phx_launch_config* best) {
+    return autotune(c, sample, stream, best, c && !c->cfg.pipeline);
+}
+
+phx_status phx_autotune_batched(phx_ctx c, const phx_trace_args* sample, void* stream,
+                                phx_launch_config* best) {
+    return autotune(c, sample, stream, best, true);
 }
 
 phx_status phx_readout(phx_ctx c, const phx_readout_params* p, const uint32_t* in, int32_t nx,

@@ -206,6 +206,8 @@ def lib():
         L.phx_read_image.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.phx_autotune.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p,
                                    C.POINTER(LaunchConfig)]
+        L.phx_autotune_batched.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p,
+                                           C.POINTER(LaunchConfig)]
         L.phx_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceArgs), C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p]
         for f in ("phx_create", "phx_load_prescription", "phx_set_perturbation",
@@ -214,7 +216,7 @@ def lib():
                   "phx_get_launch_config", "phx_trace_batched", "phx_autotune", "phx_adjoint",
                   "phx_load_physics", "phx_readout", "phx_load_reflectance",
                   "phx_trace_noalloc", "phx_moments", "phx_adjoint_moments",
-                  "phx_read_image"):
+                  "phx_read_image", "phx_autotune_batched"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -501,13 +503,15 @@ class Tracer:
         self._check(self.L.phx_set_launch_config(self.ctx, C.byref(cfg)))
 
     def autotune(self, *, flags=None, seed=None, src_begin=0, src_end=None, photon_count=0,
-                 stream=None) -> dict:
+                 stream=None, batched=False) -> dict:
         """Pick the launch shape that traces this sample fastest (the sample's outputs go to
-        scratch buffers) and keep it; returns the chosen configuration."""
+        scratch buffers) and keep it; returns the chosen configuration.  batched: time graph
+        replays (phx_autotune_batched) in the current pipeline setting."""
         a, _, _ = self._args(self.new_image(), flags, seed, src_begin, src_end, 0, photon_count,
                              None, None, 0, None, None)
         cfg = LaunchConfig()
-        self._check(self.L.phx_autotune(self.ctx, C.byref(a), _stream_handle(stream), C.byref(cfg)))
+        f = self.L.phx_autotune_batched if batched else self.L.phx_autotune
+        self._check(f(self.ctx, C.byref(a), _stream_handle(stream), C.byref(cfg)))
         return cfg.as_dict()
 
     def set_timing(self, on: bool):

@@ -108,6 +108,15 @@ def test_autotune_picks_a_valid_shape_and_keeps_results(phx, scene):
     img, _, _, _ = tr.trace(flags=flags, batched=True)
     torch.cuda.synchronize()
     assert torch.equal(img, ref)
+    # graph replays tuned with the pipeline on: the captured graph holds both streams
+    tr.set_launch_config(pipeline=1)
+    best = tr.autotune(flags=flags, batched=True)
+    assert best == tr.launch_config() and best["pipeline"] == 1
+    for _ in range(3):   # replays with eager work between them, each equal to the eager trace
+        img, _, _, _ = tr.trace(flags=flags, batched=True)
+        eager, _, _, _ = tr.trace(flags=flags)
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref) and torch.equal(eager, ref)
     tr.close()
 
 
