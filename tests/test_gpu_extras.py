@@ -303,6 +303,28 @@ def test_ghost_queue_under_launch_shapes(phx):
             assert np.array_equal(ev[name], ev0[name], equal_nan=ev0[name].dtype.kind == "f"), name
 
 
+def test_batched_graph_with_ghosts(phx):
+    """Ghosts in a captured graph: with chunks of 2^16 photons the graph holds, per chunk, the
+    list's counter reset and both optics passes on the pipeline's second stream; replays with
+    eager work between them equal the eager trace's image and statistics."""
+    import torch
+    from paper_1504_06570_amd.scene import coatings as cm
+    s = C.full(scale=2e-4, screen_n=256)
+    s.reflectance = cm.standard_reflectance()
+    s.physics = C.PHYS_ALL | X.PHYS_GHOSTS
+    tr = phx.Tracer(s)
+    tr.set_launch_config(chunk_log2=16, pipeline=1)
+    ref, st_ref, _, _ = tr.trace(stats=tr.new_stats(), flags=int(s.physics))
+    torch.cuda.synchronize()
+    assert int(ref.sum()) > 0
+    for _ in range(3):
+        img, st, _, _ = tr.trace(stats=tr.new_stats(), flags=int(s.physics), batched=True)
+        eager, _, _, _ = tr.trace(flags=int(s.physics))
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref) and torch.equal(st, st_ref) and torch.equal(eager, ref)
+    tr.close()
+
+
 def test_ghost_error_paths(phx):
     """Ghosts need reflectance tables; the adjoint refuses them."""
     import torch
