@@ -291,6 +291,32 @@ def test_last_chunk_of_one_photon(phx):
     assert int(gimg.sum()) == int((g["status"] == phx.DETECTED).sum())
 
 
+def test_largest_chunk_and_the_top_of_the_index_range(phx):
+    """The largest launch shape's chunk (2^27 photons, two buffers of it pipelined) with a ragged
+    second chunk, every 9973rd photon recorded and traced by the oracle alone; and photon indices
+    just below 2^64 (the end of the 64-bit counter).  GPU and oracle agree photon by photon."""
+    import torch
+    s = C.full(scale=2e-4, screen_n=256)
+    flags = int(s.physics) | phx.F_CULL
+    tr = phx.Tracer(s)
+    tr.set_launch_config(chunk_log2=27, pipeline=1)
+    n, stride = (1 << 27) + 4097, 9973
+    img, _, _, evb = tr.trace(flags=flags, photon_count=n, event_stride=stride)
+    torch.cuda.synchronize()
+    g = phx.events_to_numpy(evb).copy()
+    tr.close()
+    assert len(g) == (n + stride - 1) // stride
+    assert np.array_equal(g["photon"], np.arange(0, n, stride, dtype=np.uint64))
+    o = O.Oracle(s).trace_list(0, g["photon"], threads=8)
+    _parity_with_cull(phx, g, o)
+    assert int(img.sum()) > 0
+    # the last 4000 photons below 2^64
+    begin = (1 << 64) - 4001
+    gev, gimg, oev, oimg, _ = run_both(phx, s, flags=flags, photon_count=4000, photon_begin=begin)
+    assert int(gev["photon"].max()) == (1 << 64) - 2
+    _parity_with_cull(phx, gev, oev)
+
+
 def test_newton_cycle_is_nonconv(phx):
     """A surface on which Newton's iteration cycles (tests/helpers.newton_cycle_scene): every
     photon is counted as NONCONV at that surface, photon by photon equal to the oracle, with
