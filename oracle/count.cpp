@@ -5,7 +5,9 @@
 // optics: entrance effects, obscuration, surfaces; sensor: silicon, diffusion, pixel), with the
 // Philox blocks drawn and the screen bytes read.  The oracle marks its stages and pauses the
 // count around arithmetic that is not the method's (decision margins kept for the tests,
-// per-device constants).  Counting conventions: an addition, subtraction or multiplication is one
+// per-scene and per-device constants) and around the wavelength's position on the coating grid,
+// which depends on the photon alone (its one subtraction and division per photon are left out
+// rather than counted at every coated surface).  Counting conventions: an addition, subtraction or multiplication is one
 // operation each (the oracle forms no fused multiply-adds: it is built without contraction);
 // a division, a square root and a transcendental function (exp, log, sin, cos, tan, atan, pow
 // with a non-integer exponent) one each in their own class; pow with a small integer exponent
