@@ -96,7 +96,9 @@ def compare(gpu_ev, orc_ev, pos_tol=POS_TOL, chip=None):
                 status_mismatch_boundary=int((~same).sum()), worst_pos=worst,
                 worst_converted=worst_conv, worst_lam=float(lam),
                 detected=int((o["status"] == O.DETECTED).sum()),
-                groups={k: v[0] for k, v in groups.items()})
+                groups={k: v[0] for k, v in groups.items()},
+                worst_photon=(max(groups, key=lambda kk: groups[kk][0]),) + groups[
+                    max(groups, key=lambda kk: groups[kk][0])][2:] if groups else None)
 
 
 def image_without_boundary(img: np.ndarray, ev: np.ndarray) -> np.ndarray:

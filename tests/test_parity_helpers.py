@@ -67,3 +67,5 @@ def test_report_groups_worst_by_status_and_surface():
     assert rep["groups"]["ABSORBED@3"] == pytest.approx(3e-13, rel=1e-3)
     assert rep["groups"]["DETECTED@1"] == pytest.approx(1e-14, rel=1e-2)
     assert rep["worst_converted"] == pytest.approx(1e-14, rel=1e-2)
+    # the photon that carries the largest deviation is named
+    assert rep["worst_photon"] == ("ABSORBED@3", int(o["source"][2]), 2)
