@@ -974,7 +974,7 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
-        # all cores of the host's share for one GPU (16 on the GPU machines), then one core
+        # the host cores that serve one GPU (at most 16 threads), then one core
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         n_cpu = int(args.cpu_sample)
         rate, dt = cpu_baseline(scene, n_cpu, threads)
