@@ -447,8 +447,9 @@ phx_status phx_get_launch_config(phx_ctx ctx, phx_launch_config* cfg_host);
  * and captures on a context-owned stream; later calls only launch the graph.  Errors as phx_trace. */
 phx_status phx_trace_batched(phx_ctx ctx, const phx_trace_args* args, void* stream);
 
-/* Autotuner: times `sample` for candidate launch shapes (coordinate descent over optics, sky and
- * pre-roll workgroups per CU, the schedule and the chunk size; the pipeline setting is kept and
+/* Autotuner: times `sample` for candidate launch shapes (coordinate descent over the chunk size,
+ * the schedule and the optics, sky and pre-roll workgroups per CU, in that order, up to three
+ * passes; each shape's time is the best of three runs; the pipeline setting is kept and
  * selects what is timed: eager phx_trace launches when it is 1, phx_trace_batched graph replays
  * on one stream when it is 0), writing into context-owned scratch outputs (the sample's output
  * pointers are ignored), sets the fastest shape on the context and returns it in *best_host (may

@@ -1694,7 +1694,7 @@ phx_status autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
         r = launch();   // warm-up (prepares, and captures a graph)
         if (r != PHX_OK) return r;
         float best_ms = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 3; ++rep) {
             (void)hipEventRecord(e0, st);
             r = launch();
             if (r != PHX_OK) return r;
@@ -1709,30 +1709,35 @@ phx_status autotune(phx_ctx c, const phx_trace_args* sample, void* stream,
     };
     float cur_ms = 0.0f;
     status = measure(cur, cur_ms);
-    // coordinate descent: two passes over the knobs (the best optics and sky widths depend on
-    // the chunk size and on each other)
+    // coordinate descent over the knobs, the chunk size and the schedule first (they set how
+    // many chunks overlap and how the work is split, which the best optics and sky widths then
+    // depend on); up to three passes, ending after a pass that changes nothing
     const int backs[] = {2, 3, 4, 6, 8, 12};
     const int fronts[] = {8, 16, 24, 32, 48, 64};
     const int gens[] = {2, 4, 8, 16};
     const int chunks[] = {24, 25, 26};
-    for (int step = 0; step < 10 && status == PHX_OK; ++step) {
-        const int knob = step % 5;
-        std::vector<phx_launch_config> cand;
-        if (knob == 0) for (int v : backs) { auto k = cur; k.back_blocks_per_cu = v; cand.push_back(k); }
-        if (knob == 1) for (int v : fronts) { auto k = cur; k.front_blocks_per_cu = v; cand.push_back(k); }
-        if (knob == 2) for (int v : gens) { auto k = cur; k.generate_blocks_per_cu = v; cand.push_back(k); }
-        if (knob == 3) for (int v = 0; v < 2; ++v) { auto k = cur; k.dynamic_tiles = v; cand.push_back(k); }
-        if (knob == 4) for (int v : chunks) { auto k = cur; k.chunk_log2 = v; cand.push_back(k); }
-        for (const auto& k : cand) {
-            if (std::memcmp(&k, &cur, sizeof(k)) == 0) continue;
-            float ms = 0.0f;
-            status = measure(k, ms);
-            if (status != PHX_OK) break;
-            if (ms < cur_ms) {
-                cur_ms = ms;
-                cur = k;
+    for (int pass = 0; pass < 3 && status == PHX_OK; ++pass) {
+        bool changed = false;
+        for (int knob = 0; knob < 5 && status == PHX_OK; ++knob) {
+            std::vector<phx_launch_config> cand;
+            if (knob == 0) for (int v : chunks) { auto k = cur; k.chunk_log2 = v; cand.push_back(k); }
+            if (knob == 1) for (int v = 0; v < 2; ++v) { auto k = cur; k.dynamic_tiles = v; cand.push_back(k); }
+            if (knob == 2) for (int v : backs) { auto k = cur; k.back_blocks_per_cu = v; cand.push_back(k); }
+            if (knob == 3) for (int v : fronts) { auto k = cur; k.front_blocks_per_cu = v; cand.push_back(k); }
+            if (knob == 4) for (int v : gens) { auto k = cur; k.generate_blocks_per_cu = v; cand.push_back(k); }
+            for (const auto& k : cand) {
+                if (std::memcmp(&k, &cur, sizeof(k)) == 0) continue;
+                float ms = 0.0f;
+                status = measure(k, ms);
+                if (status != PHX_OK) break;
+                if (ms < cur_ms) {
+                    cur_ms = ms;
+                    cur = k;
+                    changed = true;
+                }
             }
         }
+        if (!changed) break;
     }
     (void)hipStreamSynchronize(st);
     (void)hipEventDestroy(e0);
