@@ -56,6 +56,13 @@
         ORC_COUNT_RESUME();      \
     } while (0)
 
+/* The tests' boundary band: a photon with a decision margin below ORC_MARGIN_UNIT is one whose
+ * decision a rounding-level difference between two implementations may change.  Margins are
+ * absolute or relative differences from the decision's threshold, except the SED bin choice,
+ * whose distance ORC_SED_MARGIN_ABS is scaled to ORC_MARGIN_UNIT (see trace_one). */
+#define ORC_MARGIN_UNIT 1e-7
+#define ORC_SED_MARGIN_ABS 1e-12
+
 #define TWO_PI 6.283185307179586476925286766559
 #define HC_EV_M 1.2398419843320026e-6 /* h c / e (eV m), SI-exact constants */
 #define K_B_EV 8.617333262e-5         /* Boltzmann constant (eV/K) */
@@ -949,8 +956,14 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         const double* cdf = sc->sed_cdf + (size_t)src->sed * (sc->sed_k + 1);
         int k = 0;
         while (k < sc->sed_k - 1 && !(cdf[k + 1] > u0[3])) ++k;
-        NOTE_MARGIN(&margin, u0[3] - cdf[k]);
-        NOTE_MARGIN(&margin, u0[3] - cdf[k + 1]);
+        /* Margin of the bin choice, on the common scale of the other margins: any implementation
+         * compares the same uniform with a CDF summed in the same order, whose entries then
+         * agree with these to K eps (1.7e-13 for the 761 bins of a blackbody table, counting
+         * both sides), so only a uniform within ORC_SED_MARGIN_ABS of an edge can change bin;
+         * that distance is recorded as ORC_MARGIN_UNIT.  (Taken as it stands, |u - CDF[k]| below
+         * 1e-7 would hold 2e-7 K = 1.5e-4 of the photons, none of them near a change of bin.) */
+        NOTE_MARGIN(&margin, (u0[3] - cdf[k]) * (ORC_MARGIN_UNIT / ORC_SED_MARGIN_ABS));
+        NOTE_MARGIN(&margin, (u0[3] - cdf[k + 1]) * (ORC_MARGIN_UNIT / ORC_SED_MARGIN_ABS));
         lam = sc->sed_edges[k] + u1[0] * (sc->sed_edges[k + 1] - sc->sed_edges[k]);
     }
     lam = lam * (1.0 + src->redshift);

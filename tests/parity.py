@@ -4,8 +4,12 @@ The rule (per-photon parity of a Monte Carlo sample path driven by the same rand
   * a *boundary photon* is one whose smallest decision margin in the oracle -- distance of its
     electron position to a pixel edge in pixels, |u - T| of a roulette, the relative distance to
     an aperture edge, to the silicon thickness or to total internal reflection, a rejection
-    sampler's acceptance test -- is below BOUNDARY_MARGIN; a rounding-level difference between
-    the two implementations may flip one of its decisions;
+    sampler's acceptance test, the distance of an SED draw's uniform to its bin's edges -- is
+    below BOUNDARY_MARGIN; a rounding-level difference between the two implementations may flip
+    one of its decisions.  The SED bin choice compares the same uniform with CDF sums that the
+    two sides form in the same order, equal to K eps (1.7e-13 for 761 bins), so the oracle
+    records its distance scaled by 1e5: the band is 1e-12 there (taken unscaled, 1e-7 of the
+    uniform would mark 2e-7 K = 1.5e-4 of the photons of a blackbody source);
   * every other photon has the same status and deciding surface on both sides, its last position
     (and, when converted, its electron position) within the position bar, and when detected the
     same pixel;

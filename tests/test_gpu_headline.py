@@ -4,7 +4,8 @@ diffusion, the 4096^2 chip), the default launch shape the benchmark settles on (
 photons, the two-stream pipeline, 16 / 48 / 2 workgroups per compute unit, the shape the autotuner
 settles on), the pre-roll on, three chunks of photons; then the same star with the extra
 per-photon physics, through the hybrid two-kick atmosphere, and with ghost reflections, as the
-benchmark runs them.  Every 50th photon of the launch (4e6 photons) is recorded and traced by the
+benchmark runs them; and the many-source workload (1e4 sources, 9.5e7 photons), every photon of
+it.  Every 50th photon of the launch (4e6 photons) is recorded and traced by the
 oracle alone, by its index; they must agree photon by photon and pixel by pixel.  Boundary photons
 (an oracle decision margin below the parity module's bar) are counted against the whole sample,
 the culled photons included: the pre-roll's decisions are exact integer comparisons, and a culled
@@ -107,3 +108,62 @@ def test_next_rows_at_full_size_sampled_against_the_oracle(phx, kind):
     if kind == "extras":
         for status in (phx.EXTINCT, phx.DEAD, phx.OBSCURED):
             assert (o["status"][~culled] == status).any()
+
+
+def test_batched_catalogue_every_photon_against_the_oracle(phx):
+    """The benchmark's many-source workload at full size -- 1e4 stars and Sersic galaxies with
+    blackbody SEDs and power-law photon counts (9.5e7 photons), seven layers of 2048^2 screens, the
+    telescope, coatings, silicon and diffusion -- as one graph-replayed batched launch in the
+    default launch shape with the pre-roll on.  Every photon's record equals the oracle's (the
+    oracle traced source block by source block), boundary photons are fewer than 1e-5 of all, and
+    the image equals the oracle's after each side's boundary photons are taken out of its own."""
+    import torch
+    s = C.batched()
+    tr = phx.Tracer(s)
+    flags = int(s.physics) | phx.F_CULL
+    stats = tr.new_stats()
+    img, _, _, evb = tr.trace(flags=flags, stats=stats, event_stride=1, batched=True)
+    torch.cuda.synchronize()
+    g_all = phx.events_to_numpy(evb).copy()
+    gimg = img.cpu().numpy().view(np.uint32).astype(np.int64)
+    tab = phx.stats_table(stats.cpu().numpy())
+    del evb, img
+    tr.close()
+    torch.cuda.empty_cache()
+    counts = s.sources.n_photons.astype(np.int64)
+    total = int(counts.sum())
+    assert len(g_all) == total
+    assert int(gimg.sum()) == int(tab[phx.DETECTED].sum()) > 0
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    orc = O.Oracle(s)
+    oimg = np.zeros(orc.image_shape, np.uint32)
+    adj_g = np.zeros(gimg.shape, np.int64)
+    adj_o = np.zeros(gimg.shape, np.int64)
+    boundary = detected = n_culled = 0
+    worst = worst_conv = 0.0
+    for blk in np.array_split(np.arange(len(counts)), 20):
+        cb = np.zeros(len(counts), np.uint64)
+        cb[blk] = counts[blk]
+        o = orc.trace_sources(counts=cb, image=oimg, threads=16)
+        g = g_all[starts[blk[0]]:starts[blk[-1] + 1]]
+        assert len(g) == len(o)
+        culled = g["status"] == phx.CULLED
+        assert not np.isin(o["status"][culled], [O.DETECTED, O.OFF_CHIP]).any()
+        rep = parity.compare(g[~culled], o[~culled])
+        boundary += rep["boundary"]
+        detected += rep["detected"]
+        n_culled += int(culled.sum())
+        worst = max(worst, rep["worst_pos"])
+        worst_conv = max(worst_conv, rep["worst_converted"])
+        gm, om = parity.match(g[~culled], o[~culled])
+        b = om["margin"] < parity.BOUNDARY_MARGIN
+        gb = gm[b & (gm["status"] == O.DETECTED)]
+        ob = om[b & (om["status"] == O.DETECTED)]
+        np.add.at(adj_g, (gb["pix_j"], gb["pix_i"]), 1)
+        np.add.at(adj_o, (ob["pix_j"], ob["pix_i"]), 1)
+        del o, g, gm, om
+    print(f"batched catalogue: {total} photons, {n_culled} culled, {detected} detected, "
+          f"{boundary} boundary ({boundary / total:.2e}), worst deviation {worst:.2e} m "
+          f"(converted {worst_conv:.2e} m)")
+    assert boundary / total < 1e-5
+    assert np.array_equal(gimg - adj_g, oimg.astype(np.int64) - adj_o)

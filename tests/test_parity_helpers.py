@@ -69,3 +69,40 @@ def test_report_groups_worst_by_status_and_surface():
     assert rep["worst_converted"] == pytest.approx(1e-14, rel=1e-2)
     # the photon that carries the largest deviation is named
     assert rep["worst_photon"] == ("ABSORBED@3", int(o["source"][2]), 2)
+
+
+def _sed_scene(c):
+    """The tiny paraboloid scene with one star whose two-bin SED puts the CDF edge at c."""
+    from paper_1504_06570_amd.scene import configs as C
+    from paper_1504_06570_amd.scene.sources import SEDTable
+    s = C.tiny(scale=1e-4)
+    lo, mid, hi = 500e-9, 600e-9, 700e-9
+    a0 = (mid - lo) * (0.5 * (lo + mid))
+    a1 = (hi - mid) * (0.5 * (mid + hi))
+    f1 = a0 * (1.0 - c) / (c * a1)
+    s.sed = SEDTable(np.array([lo, mid, hi]), np.array([[1.0, f1]]))
+    s.sources.sed[:] = 0
+    # the CDF edge as the oracle forms it (the same operations in the same order)
+    c1 = 0.0 + 1.0 * (mid - lo) * (0.5 * (lo + mid))
+    c2 = c1 + f1 * (hi - mid) * (0.5 * (mid + hi))
+    return s, c1 / c2
+
+
+def test_sed_bin_margin_is_scaled_to_its_rounding_band():
+    """The SED bin choice compares the same uniform with CDF sums that two implementations agree
+    on to K eps (K bins), so its boundary band is 1e-12 of the uniform, recorded on the common
+    scale: a photon whose wavelength uniform lies 5e-13 from the bin edge is a boundary photon,
+    one 5e-12 away is not (its recorded margin is 5e-7 or another decision's smaller one)."""
+    photon = 12345
+    w = O.philox([photon & 0xFFFFFFFF, photon >> 32, 0, 0], [1, 0])
+    u = (w[3] + 0.5) * 2.0 ** -32
+    for dist, boundary in ((5e-13, True), (5e-12, False)):
+        s, edge = _sed_scene(u + dist)
+        assert abs(edge - (u + dist)) < 1e-15
+        ev = O.Oracle(s).trace(0, photon, 1)
+        m = float(ev["margin"][0])
+        assert (m < parity.BOUNDARY_MARGIN) == boundary, (dist, m)
+        if boundary:
+            assert m == pytest.approx(abs(u - edge) * 1e5, rel=1e-3)
+        else:
+            assert m <= abs(u - edge) * 1e5 * (1 + 1e-9)
