@@ -93,7 +93,7 @@ EVENT_DTYPE = np.dtype([("photon", np.uint64), ("source", np.int32), ("status", 
                         ("newton", np.int32), ("x", np.float64), ("y", np.float64),
                         ("z", np.float64), ("xe", np.float64), ("ye", np.float64),
                         ("lam", np.float64), ("margin", np.float64), ("t", np.float64),
-                        ("px", np.float64), ("py", np.float64)])
+                        ("px", np.float64), ("py", np.float64), ("cond", np.float64)])
 
 _lib = None
 _lock = threading.Lock()

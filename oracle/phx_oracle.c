@@ -742,7 +742,7 @@ int orc_second_kick(const orc_scene* sc, int32_t src, uint64_t photon, int layer
  * edge).  Pinned: the shadowed fraction of a vertical beam against the vanes' exact area inside
  * the annulus; the focal-plane offset against lambda / (4 pi d) for vertical rays. */
 static int spider(const orc_scene* sc, double p[3], double n[3], double lam, double u_sign,
-                  double q[3], double* margin) {
+                  double q[3], double* margin, double* cond) {
     const orc_extra* x = &sc->ex;
     double hw = 0.5 * x->vane_width;
     double best = INFINITY, second = INFINITY, dk[8], t_hit = INFINITY;
@@ -811,6 +811,11 @@ static int spider(const orc_scene* sc, double p[3], double n[3], double lam, dou
     p[2] = zm;
     double a = x->vane_angle + TWO_PI * best_k / x->vanes;
     double delta = lam / (2.0 * TWO_PI * (best > lam ? best : lam));
+    /* conditioning of the rest of the path: a difference dd in the edge distance turns the ray by
+     * delta / d x dd (zero where d is floored at lambda) */
+    ORC_COUNT_PAUSE();
+    *cond = best > lam ? delta / best : 0.0;
+    ORC_COUNT_RESUME();
     if (!(u_sign < 0.5)) delta = -delta;
     n[0] += delta * -sin(a);
     n[1] += delta * cos(a);
@@ -1085,12 +1090,13 @@ static void trace_one(const orc_scene* sc, int32_t si, uint64_t photon, uint32_t
         }
     }
     if ((sc->physics & ORC_SPIDER) && ex->vanes > 0) {
-        double q[3];
-        if (spider(sc, p, n, lam, u7[3], q, &margin)) {
+        double q[3], cond = 0.0;
+        if (spider(sc, p, n, lam, u7[3], q, &margin, &cond)) {
             set_event(ev, ORC_OBSCURED, -1, q);
             ev->margin = margin;
             return;
         }
+        ev->cond = cond;
     }
     /* Central obscuration (shadow of the secondary; section 2.4.1 obscuring structure). */
     if (sc->obsc_r > 0.0) {

@@ -118,6 +118,8 @@ typedef struct {
     double lambda;
     double margin;        /* smallest normalised distance of any decision from its threshold */
     double t, px, py;     /* time stamp and pupil sample */
+    double cond;          /* conditioning of the path after the spider: the turn per metre of
+                           * edge distance of its edge diffraction (rad/m), 0 without one */
 } orc_event;
 
 int  orc_prepare(orc_scene* sc);

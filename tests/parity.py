@@ -11,8 +11,9 @@ The rule (per-photon parity of a Monte Carlo sample path driven by the same rand
     records its distance scaled by 1e5: the band is 1e-12 there (taken unscaled, 1e-7 of the
     uniform would mark 2e-7 K = 1.5e-4 of the photons of a blackbody source);
   * every other photon has the same status and deciding surface on both sides, its last position
-    (and, when converted, its electron position) within the position bar, and when detected the
-    same pixel;
+    (and, when converted, its electron position) within the position bar (POS_TOL, wider for a
+    photon that the spider's edge diffraction makes sensitive to rounding: position_bar), and
+    when detected the same pixel;
   * boundary photons are fewer than 1e-5 of the photons (asserted by the tests);
   * images agree after each side's boundary photons are taken out of its own image.
 BOUNDARY_MARGIN = 1e-7 is 1e-12 m at the 10 um pixels of the telescope's chip; the measured
@@ -27,6 +28,19 @@ import oracle as O
 
 BOUNDARY_MARGIN = 1e-7
 POS_TOL = 1e-9          # metres: landing and electron positions
+# A photon whose spider edge diffraction turns it by delta / d per metre of edge distance d
+# (oracle event field `cond`) carries a position difference at the vanes, at rounding level, into
+# its final position amplified by cond x the path after the spider.  Its position bar is
+# UPSTREAM_EPS x SPIDER_PATH x cond when that exceeds POS_TOL: UPSTREAM_EPS is ten times the
+# largest difference measured at the vanes (2.6e-14 m), SPIDER_PATH bounds the telescope's path
+# from the spider to the detector.  Its status, surface and pixel must still be equal.
+UPSTREAM_EPS = 1e-13    # metres
+SPIDER_PATH = 30.0      # metres
+
+
+def position_bar(orc_ev, pos_tol=POS_TOL):
+    """Per-photon position bar: pos_tol, or wider for a photon conditioned by the spider."""
+    return np.maximum(pos_tol, UPSTREAM_EPS * SPIDER_PATH * orc_ev["cond"])
 
 
 def match(gpu_ev: np.ndarray, orc_ev: np.ndarray):
@@ -86,10 +100,13 @@ def compare(gpu_ev, orc_ev, pos_tol=POS_TOL, chip=None):
     worst = max([0.0] + [v[0] for v in groups.values()])
     conv = ok & (o["status"] <= O.OFF_CHIP)
     worst_conv = float(d[conv].max()) if conv.any() else 0.0
-    if worst > pos_tol:
-        k = max(groups, key=lambda kk: groups[kk][0])
-        raise AssertionError(f"position mismatch {worst:.3e} m > {pos_tol:.1e} m at {k} "
-                             f"(source {groups[k][2]}, photon {groups[k][3]})")
+    bar = position_bar(o, pos_tol)
+    over = ok & (d > bar)
+    if over.any():
+        i = int(np.argmax(np.where(over, d / bar, 0.0)))
+        raise AssertionError(f"position mismatch {d[i]:.3e} m > {bar[i]:.1e} m at "
+                             f"{O.STATUS[o['status'][i]]}@{o['surface'][i]} (source "
+                             f"{o['source'][i]}, photon {o['photon'][i]})")
     det = ok & (o["status"] == O.DETECTED)
     flips = det & ((g["pix_i"] != o["pix_i"]) | (g["pix_j"] != o["pix_j"]))
     assert not flips.any(), (f"{flips.sum()} non-boundary detected photons in different pixels; "
@@ -99,6 +116,7 @@ def compare(gpu_ev, orc_ev, pos_tol=POS_TOL, chip=None):
                 boundary_frac=float(boundary.mean()) if len(g) else 0.0,
                 status_mismatch_boundary=int((~same).sum()), worst_pos=worst,
                 worst_converted=worst_conv, worst_lam=float(lam),
+                widened=int((ok & (bar > pos_tol)).sum()),
                 detected=int((o["status"] == O.DETECTED).sum()),
                 groups={k: v[0] for k, v in groups.items()},
                 worst_photon=(max(groups, key=lambda kk: groups[kk][0]),) + groups[

@@ -242,6 +242,36 @@ def test_spider_edge_diffraction_kick_is_lambda_over_4_pi_d():
     assert np.all(np.abs(cross) < 1e-2 * want)
     plus = (main > 0).mean()
     assert abs(plus - 0.5) < 5 * math.sqrt(0.25 / far.sum())
+    # the recorded conditioning is the turn per metre of edge distance, d/dd [lambda / (4 pi d)]
+    assert np.allclose(ev["cond"][far], lam / (4 * math.pi * d[far] ** 2), rtol=1e-6)
+
+
+def test_spider_conditioning_widens_only_its_photons_position_bar():
+    """The parity bar: a photon conditioned by the spider (cond in rad/m) may differ from the
+    oracle by UPSTREAM_EPS x SPIDER_PATH x cond when that exceeds 1e-9 m, every other photon by
+    1e-9 m; status and pixel stay exact for both."""
+    from tests import parity
+    o = np.zeros(3, O.EVENT_DTYPE)
+    o["photon"] = np.arange(3)
+    o["status"] = O.DETECTED
+    o["surface"] = 1
+    o["margin"] = 1.0
+    o["xe"] = 5e-6
+    o["cond"] = [0.0, 2000.0, 10.0]
+    bar = parity.position_bar(o)
+    assert bar[0] == parity.POS_TOL and bar[2] == parity.POS_TOL
+    assert bar[1] == pytest.approx(parity.UPSTREAM_EPS * parity.SPIDER_PATH * 2000.0)
+    g = o.copy()
+    g["xe"][1] += 5e-9          # within the photon's widened bar (6e-9 m)
+    rep = parity.compare(g, o)
+    assert rep["widened"] == 1 and rep["worst_pos"] == pytest.approx(5e-9, rel=1e-6)
+    g["xe"][2] += 5e-9          # the same difference on an unconditioned photon fails
+    with pytest.raises(AssertionError):
+        parity.compare(g, o)
+    g = o.copy()
+    g["pix_i"][1] += 1          # a conditioned photon in another pixel fails
+    with pytest.raises(AssertionError):
+        parity.compare(g, o)
 
 
 def inclined_spider_scene(n_photons=20000, incline=0.4):
