@@ -369,6 +369,10 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
     from paper_1504_06570_amd.scene import physics as X
     tr.load_physics(X.tma_extras())
     fx = flags | X.PHYS_EXTRA
+    base_cfg = tr.launch_config()
+    t0 = time.perf_counter()
+    tuned = tr.autotune(flags=fx)   # the leg's own launch shape; the tracer's is restored after
+    t_tune = time.perf_counter() - t0
     img = tr.new_image()
     stats = tr.new_stats()
     tr.trace(img, flags=fx)
@@ -395,14 +399,14 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
     torch.cuda.synchronize()
     kti = tr.get_timing()
     tr.set_timing(False)
-    tr.set_launch_config(pipeline=1)
+    tr.set_launch_config(**base_cfg)
     ci = max(kti["chunks"], 1.0)
     atm = scene.atmosphere
     f_ms = kti["front"] / ci
     f_bytes = traced * front_bytes_per_photon(atm.n_layers, atm.n_scales) / ci
     f_gbs = f_bytes / (f_ms * 1e-3) * 1e-9
-    print(f"# extra physics {ms:.2f} ms/step ({ms / core_ms:.2f}x core), kernels {kt}",
-          file=sys.stderr, flush=True)
+    print(f"# extra physics {ms:.2f} ms/step ({ms / core_ms:.2f}x core), tuned {tuned} in "
+          f"{t_tune:.1f}s, kernels {kt}", file=sys.stderr, flush=True)
     return {
         "workload": "the headline star with aerosol extinction, dispersion, dome seeing, the "
                     "micro-roughness halo, a four-vane spider and a 50 nm dead layer on "
@@ -422,6 +426,8 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
                                        "unit": "GB/s", "frac": f_gbs / PEAK_HBM_GBS,
                                        "launch_ms": f_ms},
         "back_kernel_single_stream_ms": kti["back"] / ci,
+        "launch_config": tuned,
+        "autotune_s": t_tune,
     }
 
 
@@ -435,6 +441,12 @@ def ghost_leg(tr, flags, steps, n_ph, core_ms):
     rt = np.ascontiguousarray(cm.standard_reflectance(), np.float32)
     tr._check(tr.L.phx_load_reflectance(tr.ctx, rt.ctypes.data, *rt.shape))
     fx = flags | phx.F_GHOSTS
+    # the ghost trace's own launch shape, tuned on a quarter of the step (four chunks); the
+    # tracer's shape is restored afterwards
+    base_cfg = tr.launch_config()
+    t0 = time.perf_counter()
+    tuned = tr.autotune(flags=fx, photon_count=1 << 28)
+    t_tune = time.perf_counter() - t0
     img = tr.new_image()
     stats = tr.new_stats()
     tr.trace(img, flags=fx)
@@ -450,7 +462,9 @@ def ghost_leg(tr, flags, steps, n_ph, core_ms):
     ms = e0.elapsed_time(e1) / steps
     st = stats.cpu().numpy()
     tab = phx.stats_table(st) / steps
-    print(f"# ghosts {ms:.2f} ms/step ({ms / core_ms:.2f}x core)", file=sys.stderr, flush=True)
+    tr.set_launch_config(**base_cfg)
+    print(f"# ghosts {ms:.2f} ms/step ({ms / core_ms:.2f}x core), tuned {tuned} in {t_tune:.1f}s",
+          file=sys.stderr, flush=True)
     return {
         "workload": "the headline star with ghost reflections (filter, lens and detector "
                     "coatings reflect 0.95 / 0.9 / 0.85 of what they do not transmit; pre-roll "
@@ -462,6 +476,8 @@ def ghost_leg(tr, flags, steps, n_ph, core_ms):
         "traced_per_step": float(st[phx.STAT_TRACED]) / steps,
         "detected_per_step": float(tab[phx.DETECTED].sum()),
         "off_chip_per_step": float(tab[phx.OFF_CHIP].sum()),
+        "launch_config": tuned,
+        "autotune_s": t_tune,
     }
 
 
@@ -478,6 +494,9 @@ def hybrid_leg(steps, n_ph, core_ms):
     tr = phx.Tracer(scene)
     setup = time.perf_counter() - t0
     flags = int(scene.physics) | phx.F_CULL
+    t0 = time.perf_counter()
+    tuned = tr.autotune(flags=flags)   # the leg's own launch shape
+    t_tune = time.perf_counter() - t0
     img = tr.new_image()
     stats = tr.new_stats()
     tr.trace(img, flags=flags)
@@ -508,8 +527,8 @@ def hybrid_leg(steps, n_ph, core_ms):
     f_ms = kti["front"] / ci
     f_gbs = traced * front_bytes_per_photon(atm.n_layers, atm.n_scales) / ci / (f_ms * 1e-3) * 1e-9
     tr.close()
-    print(f"# hybrid atmosphere {ms:.2f} ms/step ({ms / core_ms:.2f}x core), setup {setup:.1f}s",
-          file=sys.stderr, flush=True)
+    print(f"# hybrid atmosphere {ms:.2f} ms/step ({ms / core_ms:.2f}x core), setup {setup:.1f}s, "
+          f"tuned {tuned} in {t_tune:.1f}s", file=sys.stderr, flush=True)
     return {
         "workload": "the headline star through the hybrid two-kick atmosphere (screens below "
                     "kappa_crit = 2 pi / (1.5 r0), second kick per layer; phase variance above "
@@ -526,6 +545,8 @@ def hybrid_leg(steps, n_ph, core_ms):
                                        "unit": "GB/s", "frac": f_gbs / PEAK_HBM_GBS,
                                        "launch_ms": f_ms},
         "back_kernel_single_stream_ms": kti["back"] / ci,
+        "launch_config": tuned,
+        "autotune_s": t_tune,
     }
 
 
