@@ -360,7 +360,7 @@ def gradient_leg(steps):
     }
 
 
-def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
+def extras_leg(tr, scene, flags, steps, n_ph, core_ms, tune=True):
     """The headline step with aerosol extinction, dispersion, dome seeing, the micro-roughness
     halo, the spider and the dead layer switched on (their kernels' EXTRA instantiations): time
     per step, its cost against the core step, and each kernel's duration on a single stream."""
@@ -371,7 +371,8 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
     fx = flags | X.PHYS_EXTRA
     base_cfg = tr.launch_config()
     t0 = time.perf_counter()
-    tuned = tr.autotune(flags=fx)   # the leg's own launch shape; the tracer's is restored after
+    # the leg's own launch shape (unless the command fixes it); the tracer's is restored after
+    tuned = tr.autotune(flags=fx) if tune else base_cfg
     t_tune = time.perf_counter() - t0
     img = tr.new_image()
     stats = tr.new_stats()
@@ -431,7 +432,7 @@ def extras_leg(tr, scene, flags, steps, n_ph, core_ms):
     }
 
 
-def ghost_leg(tr, flags, steps, n_ph, core_ms):
+def ghost_leg(tr, flags, steps, n_ph, core_ms, tune=True):
     """The headline step with ghost reflections: filter, lens and detector coatings reflect what
     they do not transmit (a fixed share), and reflected photons are traced non-sequentially."""
     import numpy as np
@@ -441,11 +442,11 @@ def ghost_leg(tr, flags, steps, n_ph, core_ms):
     rt = np.ascontiguousarray(cm.standard_reflectance(), np.float32)
     tr._check(tr.L.phx_load_reflectance(tr.ctx, rt.ctypes.data, *rt.shape))
     fx = flags | phx.F_GHOSTS
-    # the ghost trace's own launch shape, tuned on a quarter of the step (four chunks); the
-    # tracer's shape is restored afterwards
+    # the ghost trace's own launch shape, tuned on a quarter of the step (four chunks) unless the
+    # command fixes it; the tracer's shape is restored afterwards
     base_cfg = tr.launch_config()
     t0 = time.perf_counter()
-    tuned = tr.autotune(flags=fx, photon_count=1 << 28)
+    tuned = tr.autotune(flags=fx, photon_count=1 << 28) if tune else base_cfg
     t_tune = time.perf_counter() - t0
     img = tr.new_image()
     stats = tr.new_stats()
@@ -481,7 +482,7 @@ def ghost_leg(tr, flags, steps, n_ph, core_ms):
     }
 
 
-def hybrid_leg(steps, n_ph, core_ms):
+def hybrid_leg(steps, n_ph, core_ms, launch=None):
     """The headline star through the hybrid two-kick atmosphere: the same seven layers with their
     screens limited to wavenumbers below kappa_crit = 2 pi / (1.5 r0) and the higher modes applied
     as the per-layer second kick (pre-roll on; its geometric cull is off with the kick)."""
@@ -495,7 +496,11 @@ def hybrid_leg(steps, n_ph, core_ms):
     setup = time.perf_counter() - t0
     flags = int(scene.physics) | phx.F_CULL
     t0 = time.perf_counter()
-    tuned = tr.autotune(flags=flags)   # the leg's own launch shape
+    if launch is None:
+        tuned = tr.autotune(flags=flags)   # the leg's own launch shape
+    else:
+        tr.set_launch_config(**launch)     # the shape the command fixes
+        tuned = tr.launch_config()
     t_tune = time.perf_counter() - t0
     img = tr.new_image()
     stats = tr.new_stats()
@@ -988,10 +993,13 @@ def main():
         tr.trace(one, flags=flags)
         extra["readout"] = readout_leg(tr, one, max(args.steps, 1))
         del one
-        extra["extra_physics"] = extras_leg(tr, scene, flags, max(args.steps, 1), n_ph, ms)
-        extra["ghosts"] = ghost_leg(tr, flags, max(args.steps, 1), n_ph, ms)
+        fixed = bool(args.launch or args.no_autotune)   # the command fixes the launch shape
+        extra["extra_physics"] = extras_leg(tr, scene, flags, max(args.steps, 1), n_ph, ms,
+                                            tune=not fixed)
+        extra["ghosts"] = ghost_leg(tr, flags, max(args.steps, 1), n_ph, ms, tune=not fixed)
+        shape = tr.launch_config() if fixed else None
         tr.close()
-        extra["hybrid_atmosphere"] = hybrid_leg(max(args.steps, 1), n_ph, ms)
+        extra["hybrid_atmosphere"] = hybrid_leg(max(args.steps, 1), n_ph, ms, launch=shape)
 
     cpu = None
     if not args.skip_cpu:
