@@ -464,8 +464,9 @@ def ghost_leg(tr, flags, steps, n_ph, core_ms, tune=True):
     st = stats.cpu().numpy()
     tab = phx.stats_table(st) / steps
     tr.set_launch_config(**base_cfg)
-    print(f"# ghosts {ms:.2f} ms/step ({ms / core_ms:.2f}x core), tuned {tuned} in {t_tune:.1f}s",
-          file=sys.stderr, flush=True)
+    rel = f" ({ms / core_ms:.2f}x core)" if core_ms else ""
+    print(f"# ghosts {ms:.2f} ms/step{rel}, tuned {tuned} in {t_tune:.1f}s", file=sys.stderr,
+          flush=True)
     return {
         "workload": "the headline star with ghost reflections (filter, lens and detector "
                     "coatings reflect 0.95 / 0.9 / 0.85 of what they do not transmit; pre-roll "
@@ -473,13 +474,42 @@ def ghost_leg(tr, flags, steps, n_ph, core_ms, tune=True):
         "photons_per_step": n_ph,
         "ms_per_step": ms,
         "value": n_ph / (ms * 1e-3),
-        "cost_vs_core": ms / core_ms,
+        "cost_vs_core": ms / core_ms if core_ms else None,
         "traced_per_step": float(st[phx.STAT_TRACED]) / steps,
         "detected_per_step": float(tab[phx.DETECTED].sum()),
         "off_chip_per_step": float(tab[phx.OFF_CHIP].sum()),
         "launch_config": tuned,
         "autotune_s": t_tune,
     }
+
+
+def launch_shape(text):
+    """--launch G,F,B[,C]: pre-roll, sky and optics workgroups per compute unit, and optionally
+    the chunk size's log2."""
+    v = [int(x) for x in text.split(",")]
+    if len(v) not in (3, 4):
+        raise SystemExit("bench.py: --launch takes G,F,B or G,F,B,C")
+    shape = dict(generate_blocks_per_cu=v[0], front_blocks_per_cu=v[1], back_blocks_per_cu=v[2])
+    if len(v) == 4:
+        shape["chunk_log2"] = v[3]
+    return shape
+
+
+def ghosts_only(args):
+    """The ghost leg alone on the headline star (for profiling it): the launch shape from
+    --launch, else the leg's own tuning."""
+    from paper_1504_06570_amd import phx
+    from paper_1504_06570_amd.scene import configs as C
+    n_ph = int(args.photons)
+    scene = C.full()
+    scene.sources.n_photons[:] = n_ph
+    tr = phx.Tracer(scene)
+    if args.launch:
+        tr.set_launch_config(**launch_shape(args.launch))
+    out = ghost_leg(tr, int(scene.physics) | phx.F_CULL, max(args.steps, 1), n_ph, None,
+                    tune=not (args.launch or args.no_autotune))
+    tr.close()
+    return out
 
 
 def hybrid_leg(steps, n_ph, core_ms, launch=None):
@@ -784,12 +814,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the legs with the per-photon physics beyond the core path and the "
                          "hybrid atmosphere")
-    ap.add_argument("--only", choices=("batched", "gradient"), default=None,
+    ap.add_argument("--only", choices=("batched", "gradient", "ghosts"), default=None,
                     help="run one secondary leg alone and print its record (for profiling)")
-    ap.add_argument("--launch", default=None, metavar="G,F,B",
+    ap.add_argument("--launch", default=None, metavar="G,F,B[,C]",
                     help="fixed launch shape (pre-roll, sky and optics workgroups per compute "
-                         "unit) in place of the autotuner, so that a profile holds only the "
-                         "timed launches")
+                         "unit, optionally the chunk size's log2) in place of the autotuner, so "
+                         "that a profile holds only the timed launches")
     ap.add_argument("--no-single-stream", action="store_true",
                     help="skip the step with both stages on one stream")
     ap.add_argument("--summarize-stats", default=None, metavar="CSV",
@@ -823,6 +853,9 @@ def main():
         print(json.dumps({"fp64_op_rates": fp64_op_rates(), "philox_blocks_per_s": philox_rate()}),
               flush=True)
         return
+    if args.only == "ghosts":
+        print(json.dumps(ghosts_only(args)), flush=True)
+        return
     if args.only:
         leg = batched_leg if args.only == "batched" else gradient_leg
         print(json.dumps(leg(max(args.steps, 1))), flush=True)
@@ -846,8 +879,7 @@ def main():
     stats = tr.new_stats()
     t_tune = time.perf_counter()
     if args.launch:
-        g, f, b = (int(x) for x in args.launch.split(","))
-        tr.set_launch_config(generate_blocks_per_cu=g, front_blocks_per_cu=f, back_blocks_per_cu=b)
+        tr.set_launch_config(**launch_shape(args.launch))
         tuned = tr.launch_config()
     elif args.no_autotune:
         tuned = tr.launch_config()
