@@ -106,3 +106,15 @@ def test_sed_bin_margin_is_scaled_to_its_rounding_band():
             assert m == pytest.approx(abs(u - edge) * 1e5, rel=1e-3)
         else:
             assert m <= abs(u - edge) * 1e5 * (1 + 1e-9)
+
+
+def test_spider_path_bounds_the_telescope_path_after_the_vanes():
+    """The lever in the spider's position bar bounds the axial path from the top of the vanes to
+    the detector through M1, M2, M3 and the camera, with 10 % for the rays' inclination."""
+    from paper_1504_06570_amd.scene import configs as C
+    from paper_1504_06570_amd.scene import physics as X
+    surf = {s.name: s.z for s in C.full().prescription.surfaces}
+    top = X.tma_extras().vane_z_hi
+    path = (top - surf["M1"]) + abs(surf["M2"] - surf["M1"]) + abs(surf["M2"] - surf["M3"]) + \
+        abs(surf["DET"] - surf["M3"])
+    assert 1.1 * path < parity.SPIDER_PATH
