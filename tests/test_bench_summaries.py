@@ -69,3 +69,15 @@ def test_per_class_seconds_prices_each_class():
     ops = {"add": 1e12, "mul": 1e12, "div": 2e11, "sqrt": 1e11, "trans": 1e10}
     # (add + mul) / (2 fma) + div / faster div + sqrt / faster sqrt + trans / harmonic mean
     assert abs(bench.per_class_seconds(ops, rates) - (1.0 + 1.0 + 1.0 + 1.0)) < 1e-12
+
+
+def test_launch_shape_parses_widths_and_an_optional_chunk_size():
+    import pytest
+    assert bench.launch_shape("16,48,2") == dict(generate_blocks_per_cu=16, front_blocks_per_cu=48,
+                                                 back_blocks_per_cu=2)
+    assert bench.launch_shape("16,64,3,24") == dict(generate_blocks_per_cu=16,
+                                                    front_blocks_per_cu=64,
+                                                    back_blocks_per_cu=3, chunk_log2=24)
+    for bad in ("16,48", "1,2,3,4,5"):
+        with pytest.raises(SystemExit):
+            bench.launch_shape(bad)
