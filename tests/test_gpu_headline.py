@@ -167,3 +167,45 @@ def test_batched_catalogue_every_photon_against_the_oracle(phx):
           f"(converted {worst_conv:.2e} m)")
     assert boundary / total < 1e-5
     assert np.array_equal(gimg - adj_g, oimg.astype(np.int64) - adj_o)
+
+
+def test_gradient_configuration_forward_sampled_against_the_oracle(phx):
+    """The forward trace of the benchmark's gradient workload at full size: 25 stars on a 5 x 5
+    grid over the field, 1e7 photons each, seven layers of 2048^2 screens, the telescope with its
+    22 perturbation parameters set as the benchmark sets them (decenters, tilts and pistons of M2
+    and the camera, Zernike terms of M1), coatings, silicon and diffusion, pre-roll on.  Every 50th
+    photon of the launch equals the oracle's (traced with the same perturbation), boundary photons
+    counted against the sample."""
+    import torch
+    s = C.gradients()
+    theta = np.random.default_rng(5).uniform(-1, 1, C.N_PERTURB) * C.PERTURB_RANGE
+    tr = phx.Tracer(s)
+    tr.set_perturbation(theta)
+    flags = int(s.physics) | phx.F_CULL
+    stats = tr.new_stats()
+    img, _, _, evb = tr.trace(flags=flags, stats=stats, event_stride=STRIDE)
+    torch.cuda.synchronize()
+    g = phx.events_to_numpy(evb).copy()
+    gimg = img.cpu().numpy().view(np.uint32)
+    tab = phx.stats_table(stats.cpu().numpy())
+    tr.close()
+    counts = s.sources.n_photons.astype(np.int64)
+    total = int(counts.sum())
+    assert len(g) == (total + STRIDE - 1) // STRIDE
+    assert int(gimg.sum()) == int(tab[phx.DETECTED].sum()) > 0
+    orc = O.Oracle(s, theta=theta)
+    o = np.zeros(len(g), O.EVENT_DTYPE)
+    for src in np.unique(g["source"]):
+        m = g["source"] == src
+        o[m] = orc.trace_list(int(src), g["photon"][m], threads=16)
+    culled = g["status"] == phx.CULLED
+    assert culled.any()
+    assert not np.isin(o["status"][culled], [O.DETECTED, O.OFF_CHIP]).any()
+    rep = parity.compare(g[~culled], o[~culled])
+    frac = rep["boundary"] / len(g)
+    print(f"gradient workload sample: {len(g)} photons, {int(culled.sum())} culled, boundary "
+          f"fraction of the sample {frac:.2e};", {k: v for k, v in rep.items() if k != "groups"})
+    assert frac < 1e-5
+    assert rep["detected"] > 10000
+    det = (g["status"] == phx.DETECTED) & ~culled
+    assert np.all(gimg[g["pix_j"][det], g["pix_i"][det]] > 0)
