@@ -104,6 +104,15 @@ def test_full_stack_matches_oracle(phx):
     assert n > 100
 
 
+def test_benchmark_gradient_scene_matches_oracle(phx):
+    """The benchmark's gradient workload itself (seven layers of 2048^2 screens, the perturbation
+    the benchmark sets): the first 3000 photons of three of its 25 stars."""
+    s = C.gradients()
+    s.perturbation = np.random.default_rng(5).uniform(-1, 1, C.N_PERTURB) * RANGE
+    n = compare_with_oracle(phx, s, 3000, sources=[0, 12, 24])
+    assert n > 100
+
+
 def test_full_stack_with_extra_physics_matches_oracle(phx):
     """Dispersion, dome seeing, the halo, the spider, aerosol extinction and the dead layer on top
     of the full stack: none depends on the perturbation, so the photons' Jacobians still agree
